@@ -1,0 +1,264 @@
+/*
+ * hss.h - adaptive randomized HSS compression on AMD MI355X (gfx950).
+ *
+ * C ABI of libhss.so.  The method is the one of Gorman, Chavez, Ghysels,
+ * Mary, Rouet and Li, "Matrix-free construction of HSS representation
+ * using adaptive randomized sampling" (arXiv 1810.04125):
+ *   - random sampling S^r = A R, S^c = A^T R and element extraction
+ *     A(I,J) (Sec. 2.2 eq. sample_off_diag; Sec. 4 partially matrix-free
+ *     interface), here matrix-free with entries generated on the GPU;
+ *   - bottom-up interpolative decompositions of the local samples
+ *     (eqs. ID, QRCPSr; Alg. 1 and 2);
+ *   - the adaptive driver (Alg. 3) with the doubling (Alg. 4, with the
+ *     HMT-scaled RRQR of eq. RRQRHMTstop) and incrementing (Alg. 5, block
+ *     Gram-Schmidt with eq. stopping_criteria) strategies.
+ *
+ * Conventions for every call:
+ *   - every function returns hss_status; HSS_OK = 0, positive values are
+ *     warnings with valid outputs, negative values are errors after which
+ *     no output is valid and every resource of the call has been freed;
+ *     hss_last_error() gives a thread-local message for the last non-OK
+ *     status;
+ *   - "device" pointers are HIP device memory of the current device,
+ *     "host" pointers are ordinary host memory; ownership of every pointer
+ *     argument stays with the caller, which must keep it valid for the
+ *     duration of the call (asynchronous calls: until the stream reaches
+ *     the work);
+ *   - matrices are column-major with an explicit leading dimension unless
+ *     stated otherwise; indices are 0-based;
+ *   - real arithmetic only: the paper's conjugate transpose is the
+ *     transpose.
+ */
+#ifndef HSS_H
+#define HSS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HSS_OK = 0,
+  HSS_NOT_CONVERGED = 1,               /* d reached d_max; open nodes were accepted as they stood */
+  HSS_TOL_BELOW_SAMPLING_PRECISION = 2,/* thresholds raised to the sampling precision floor */
+  HSS_ERR_INVALID_ARG = -1,
+  HSS_ERR_OUT_OF_MEMORY = -2,
+  HSS_ERR_DEVICE = -3,                 /* a HIP runtime call failed */
+  HSS_ERR_NONFINITE = -5,              /* a non-finite sample or entry was met */
+  HSS_ERR_INTERNAL = -6
+} hss_status;
+
+/* Operator families whose entries the kernels generate on the fly. */
+typedef enum {
+  HSS_FAM_TOEPLITZ = 0, /* symmetric Toeplitz: t(0)=pi^2/(6h^2), t(k)=(-1)^k/(k^2 h^2) */
+  HSS_FAM_LAPLACE = 1,  /* 1/(4 pi |x_i-x_j|) for i != j, `diag` on the diagonal */
+  HSS_FAM_GAUSS = 2,    /* exp(-|x_i-x_j|^2/(2 sigma^2)) + diag * delta_ij */
+  HSS_FAM_DENSE = 3     /* explicit n x n matrix in device memory (read from HBM) */
+} hss_family;
+
+/* Sample-growth strategy and stopping test (Alg. 3-5). */
+typedef enum {
+  HSS_DBL_FNORM = 0, /* doubling, block Gram-Schmidt F-norm test (eq. stopping_criteria) */
+  HSS_INC_FNORM = 1, /* incrementing by delta_d, same test (Alg. 5) */
+  HSS_DBL_HMT = 2    /* doubling, RRQR with the HMT factor, accept iff r < d - p (Alg. 4) */
+} hss_strategy;
+
+/* Arithmetic of the sampling product A R (the ID and the tests stay FP64). */
+typedef enum {
+  HSS_SAMPLE_FP64 = 0,
+  HSS_SAMPLE_FP32 = 1,   /* FP32 MFMA, FP32 accumulation per K chunk, FP64 chunk sums */
+  HSS_SAMPLE_BF16X3 = 2  /* bf16 hi/lo split, three bf16 MFMA products, FP32 accumulation */
+} hss_precision;
+
+/* Operator description.  All pointers are device pointers in the ORIGINAL
+ * (unpermuted) index order; the library applies the tree permutation.
+ *   toeplitz: h (grid step)
+ *   laplace : points (n x 3, xyz interleaved, row-major), diag (A_ii)
+ *   gauss   : points, sigma, diag
+ *   dense   : dense (column-major, leading dimension ld >= n); symmetric
+ *             tells whether A = A^T may be assumed (then S^c = S^r). */
+typedef struct {
+  int32_t family;
+  int32_t symmetric;
+  int64_t n;
+  double h;
+  double sigma;
+  double diag;
+  const double* points;
+  const double* dense;
+  int64_t ld;
+} hss_generator;
+
+/* Cluster tree (Sec. 2.1): binary, numbered level by level top-down from
+ * 0 at the root, every node owns the contiguous permuted range [lo, hi),
+ * children partition their parent.  Host memory; leaves have
+ * left = right = -1, the root has parent = -1.  perm[i] is the original
+ * index at permuted position i. */
+typedef struct {
+  int64_t n;
+  int32_t num_nodes;
+  int64_t* perm;
+  int32_t* lo;
+  int32_t* hi;
+  int32_t* left;
+  int32_t* right;
+  int32_t* parent;
+  int32_t* level;
+} hss_tree;
+
+/* Build a cluster tree on the host.  points_host: n x 3 row-major, or
+ * NULL for index bisection.  method: 0 index bisection, 1 recursive
+ * coordinate bisection (split the axis of largest extent), 2 kd (axis =
+ * depth mod 3).  A node with m > leaf_size indices splits into floor(m/2)
+ * and the rest, points ordered by (coordinate, original index); indices
+ * inside a leaf ascend.  The tree is owned by the caller: free it with
+ * hss_tree_free. */
+hss_status hss_tree_build(int64_t n, const double* points_host, int32_t leaf_size,
+                          int32_t method, hss_tree** out);
+void hss_tree_free(hss_tree* tree);
+
+/* Options of one compression (Alg. 3).
+ *   rtol, atol : relative / absolute tolerance; every node tau uses
+ *                eta*rtol/level(tau) and eta*atol/level(tau)
+ *   eta        : global safety factor on the per-node tolerance (1 = literal)
+ *   d0         : initial number of random vectors
+ *   delta_d    : increment (HSS_INC_FNORM)
+ *   oversample_p : p of the HMT acceptance r < d - p (HSS_DBL_HMT)
+ *   d_max      : cap on the number of random vectors; <= ncols_R
+ *   R, ldr, ncols_R : device, the n x ncols_R Gaussian matrix the method
+ *                draws from, rows in PERMUTED order; columns are consumed
+ *                left to right and never regenerated
+ *   stream     : hipStream_t for all work (NULL = default stream) */
+typedef struct {
+  double rtol;
+  double atol;
+  double eta;
+  int32_t strategy;
+  int32_t d0;
+  int32_t delta_d;
+  int32_t oversample_p;
+  int32_t d_max;
+  int32_t sample_precision;
+  const double* R;
+  int64_t ldr;
+  int32_t ncols_R;
+  int32_t reserved;
+  void* stream;
+} hss_options;
+
+typedef struct hss_matrix hss_matrix;
+
+/* Adaptive HSS compression (Alg. 3): returns the generators D, U, V
+ * (as skeleton indices J and interpolation matrices E), B12, B21 of every
+ * node.  Host-synchronous: one small device-to-host copy per sampling
+ * round decides whether to sample more.  Returns HSS_NOT_CONVERGED
+ * (a warning) when d reached d_max before the root compressed. */
+hss_status hss_compress(const hss_generator* gen, const hss_tree* tree,
+                        const hss_options* opt, hss_matrix** out);
+
+/* `count` independent compressions run together: every kernel launch
+ * covers the same tree level of all problems, and one sampling launch
+ * covers every problem (Sec. 4, level-synchronised traversal).  gens,
+ * trees, opts and out are arrays of length count; all options must use
+ * the same strategy and the same stream. */
+hss_status hss_compress_batched(int32_t count, const hss_generator* gens,
+                                const hss_tree* const* trees, const hss_options* opts,
+                                hss_matrix** out);
+
+void hss_destroy(hss_matrix* h);
+
+/* Y = H X for nrhs right-hand sides, X and Y device, ORIGINAL ordering,
+ * asynchronous on `stream`.  Upward pass x_hat = V^T x, top-down sibling
+ * couplings through B12/B21 and the nested bases (eq. nestedUV). */
+hss_status hss_matvec(const hss_matrix* h, int32_t nrhs, const double* X, int64_t ldx,
+                      double* Y, int64_t ldy, void* stream);
+
+/* ||A - H||_F / ||A||_F over all n^2 entries (the error measure of
+ * table HMT), in FP64, by column blocks of H and generated blocks of A.
+ * Host-synchronous. */
+hss_status hss_rel_error(const hss_matrix* h, const hss_generator* gen, double* rel_err);
+
+typedef struct {
+  int64_t n;
+  int32_t num_nodes;
+  int32_t rounds;      /* passes over the tree */
+  int32_t d_final;     /* random vectors used */
+  int32_t hss_rank;    /* max node rank */
+  int32_t status;      /* hss_status of the compression */
+  int32_t symmetric;   /* 1 if only S^r was computed (S^c = S^r) */
+  double sample_ms;    /* summed HIP-event time of the sampling launches */
+  double total_ms;     /* wall time of hss_compress */
+  double sample_flops; /* 2 n^2 d_final per product computed */
+} hss_info;
+
+hss_status hss_get_info(const hss_matrix* h, hss_info* out);
+
+typedef struct {
+  int32_t state;   /* 0 UNTOUCHED, 1 PARTIALLY_COMPRESSED, 2 COMPRESSED */
+  int32_t is_leaf;
+  int32_t lo, hi;
+  int32_t m_r, m_c;       /* rows of the local samples tau.S^r, tau.S^c */
+  int32_t rank_r, rank_c; /* columns of U_tau, V_tau */
+  int32_t b_rows, b_cols; /* B12 is b_rows x b_cols (non-leaf); B21 is b_cols' x b_rows' */
+} hss_node_info;
+
+hss_status hss_get_node_info(const hss_matrix* h, int32_t node, hss_node_info* out);
+
+/* Copy one generator of a node to host memory.  Layouts:
+ *   HSS_NODE_D    : leaf, (hi-lo)^2 doubles, column-major
+ *   HSS_NODE_B12  : rank_r(left) x rank_c(right), column-major
+ *   HSS_NODE_B21  : rank_r(right) x rank_c(left), column-major
+ *   HSS_NODE_JR / HSS_NODE_JC : m int32, pivot order: the first rank
+ *                   entries are J, the rest ascend (U(J,:) = I)
+ *   HSS_NODE_ER / HSS_NODE_EC : rank x (m - rank), column-major; U(rest,:) = E^T
+ *   HSS_NODE_IR / HSS_NODE_IC : rank int64 skeleton indices (permuted)
+ * bytes must be at least the size of the object. */
+enum {
+  HSS_NODE_D = 0, HSS_NODE_B12 = 1, HSS_NODE_B21 = 2, HSS_NODE_JR = 3, HSS_NODE_JC = 4,
+  HSS_NODE_ER = 5, HSS_NODE_EC = 6, HSS_NODE_IR = 7, HSS_NODE_IC = 8
+};
+hss_status hss_copy_node(const hss_matrix* h, int32_t node, int32_t what, void* host_dst,
+                         size_t bytes);
+
+/* --- individual hot-path steps, for testing and for callers that build
+ *     their own driver --------------------------------------------------- */
+
+/* S = op(A_hat) R for ncols columns, A_hat(i,j) = a(perm[i], perm[j]),
+ * op = identity (transpose = 0, S^r) or transpose (1, S^c) (Sec. 2.2
+ * eq. sample_off_diag).  perm: device int64[n].  R, S: device, n x ncols,
+ * column-major.  precision: hss_precision.  Asynchronous on stream. */
+hss_status hss_sample(const hss_generator* gen, const int64_t* perm, int32_t ncols,
+                      const double* R, int64_t ldr, double* S, int64_t lds, int32_t transpose,
+                      int32_t precision, void* stream);
+
+/* out = A_hat(I, J), nI x nJ column-major (ldo >= nI); I, J device int64
+ * permuted indices (Sec. 4: B = A(J^r, J^c) is a sub-block of A). */
+hss_status hss_extract(const hss_generator* gen, const int64_t* perm, int32_t nI,
+                       const int64_t* I, int32_t nJ, const int64_t* J, double* out,
+                       int64_t ldo, void* stream);
+
+/* Batched interpolative decomposition (eqs. ID, QRCPSr): for each of
+ * `count` matrices S_k (m_k x d_k, device, ROW-major with leading
+ * dimension ld_k, i.e. S_k^T column-major), QR with column pivoting of
+ * S_k^T that stops before the first pivot with residual norm
+ * <= max(eps_a, eps_r * nu_1).  Outputs per matrix: rank[k];
+ * piv_k (int32[m_k], pivot order then the rest ascending);
+ * E_k (rank x (m_k - rank), column-major, leading dimension m_k).
+ * Host arrays: m, d, ld, offsets (in elements) into S, piv, E.
+ * Host-synchronous (ranks are returned in host memory). */
+hss_status hss_interpolative_batched(int32_t count, const int32_t* m, const int32_t* d,
+                                     const int64_t* ld, const double* S, const int64_t* s_off,
+                                     double eps_r, double eps_a, int32_t* piv,
+                                     const int64_t* piv_off, double* E, const int64_t* e_off,
+                                     int32_t* rank_host);
+
+const char* hss_last_error(void);
+const char* hss_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HSS_H */

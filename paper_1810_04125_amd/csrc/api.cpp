@@ -1,0 +1,427 @@
+// C ABI of libhss (declared in include/hss.h).  Every entry point catches
+// all C++ exceptions, records a thread-local message and returns a status.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "driver.h"
+
+using namespace hss;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+hss_status fail(hss_status code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+template <class F>
+hss_status guarded(F&& f) {
+  try {
+    g_last_error.clear();
+    return f();
+  } catch (const Error& e) {
+    return fail(e.code, e.msg);
+  } catch (const std::bad_alloc&) {
+    return fail(HSS_ERR_OUT_OF_MEMORY, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(HSS_ERR_INTERNAL, e.what());
+  } catch (...) {
+    return fail(HSS_ERR_INTERNAL, "unknown error");
+  }
+}
+
+// Device copies of the generator tables needed by the standalone kernels.
+struct GenHolder {
+  GenDev g;
+  std::vector<void*> mem;
+  ~GenHolder() {
+    for (void* p : mem) hipFree(p);
+  }
+  void* alloc(size_t b) {
+    void* p = nullptr;
+    HSS_HIP_CHECK(hipMalloc(&p, std::max<size_t>(b, 8)));
+    mem.push_back(p);
+    return p;
+  }
+  GenHolder(const hss_generator& gen, const int64_t* perm, hipStream_t s) {
+    if (!perm) throw Error(HSS_ERR_INVALID_ARG, "perm must be a device int64[n] array");
+    if (gen.n < 1 || gen.family < 0 || gen.family > 3) throw Error(HSS_ERR_INVALID_ARG, "bad generator");
+    std::memset(&g, 0, sizeof(g));
+    g.family = gen.family;
+    g.n = gen.n;
+    g.diag = gen.diag;
+    g.perm = perm;
+    g.symmetric = gen.family != HSS_FAM_DENSE || gen.symmetric;
+    if (gen.family == HSS_FAM_TOEPLITZ) {
+      if (!(gen.h > 0.0)) throw Error(HSS_ERR_INVALID_ARG, "toeplitz needs h > 0");
+      double* t = (double*)alloc(sizeof(double) * gen.n);
+      launch_toeplitz_table(t, gen.n, gen.h, s);
+      g.tcol = t;
+    } else if (gen.family == HSS_FAM_DENSE) {
+      if (!gen.dense || gen.ld < gen.n) throw Error(HSS_ERR_INVALID_ARG, "dense needs dense, ld >= n");
+      g.dense = gen.dense;
+      g.ld = gen.ld;
+    } else {
+      if (!gen.points) throw Error(HSS_ERR_INVALID_ARG, "kernel family needs points");
+      if (gen.family == HSS_FAM_GAUSS) {
+        if (!(gen.sigma > 0.0)) throw Error(HSS_ERR_INVALID_ARG, "gauss needs sigma > 0");
+        g.inv2s2 = 1.0 / (2.0 * gen.sigma * gen.sigma);
+      }
+      double* pts = (double*)alloc(sizeof(double) * 3 * gen.n);
+      launch_permute_points(gen.points, perm, gen.n, pts, s);
+      g.pts = pts;
+    }
+  }
+};
+
+// Permuted-space matvec on the compressed job: Yp = H Xp, both n x nrhs (ld n).
+void matvec_permuted(const hss_matrix* h, int32_t nrhs, const double* Xp, double* Yp, double* xh,
+                     double* yh, hipStream_t s) {
+  Job& J = *h->job;
+  const Problem& P = J.probs[h->k];
+  // The level lists mix problems; run per problem with its own sub-lists.
+  for (int lev = J.maxlevel; lev >= 0; --lev) {
+    MvArgs a;
+    const LevelInfo& L = J.levels[lev];
+    int32_t first = -1, cnt = 0;
+    for (size_t i = 0; i < L.nodes.size(); ++i)
+      if (J.desc[L.nodes[i]].prob == h->k) {
+        if (first < 0) first = (int32_t)i;
+        ++cnt;
+      }
+    if (cnt == 0) continue;
+    a.desc = J.desc_d; a.st = J.st_d; a.nodes = J.nodes_d + L.off + first; a.count = cnt;
+    a.dpool = J.dpool; a.ipool = J.ipool; a.xh = xh; a.yh = yh; a.xh_off = J.mvoff_d;
+    a.X = Xp; a.Y = Yp; a.n = P.n; a.nrhs = nrhs;
+    launch_mv_up(a, s);
+  }
+  for (int lev = 0; lev <= J.maxlevel; ++lev) {
+    MvArgs a;
+    const LevelInfo& L = J.levels[lev];
+    int32_t first = -1, cnt = 0;
+    for (size_t i = 0; i < L.nodes.size(); ++i)
+      if (J.desc[L.nodes[i]].prob == h->k) {
+        if (first < 0) first = (int32_t)i;
+        ++cnt;
+      }
+    if (cnt == 0) continue;
+    a.desc = J.desc_d; a.st = J.st_d; a.nodes = J.nodes_d + L.off + first; a.count = cnt;
+    a.dpool = J.dpool; a.ipool = J.ipool; a.xh = xh; a.yh = yh; a.xh_off = J.mvoff_d;
+    a.X = Xp; a.Y = Yp; a.n = P.n; a.nrhs = nrhs;
+    launch_mv_down(a, s);
+  }
+  HSS_HIP_CHECK(hipGetLastError());
+}
+
+struct DevBuf {
+  void* p = nullptr;
+  explicit DevBuf(size_t bytes) { HSS_HIP_CHECK(hipMalloc(&p, std::max<size_t>(bytes, 8))); }
+  ~DevBuf() { if (p) hipFree(p); }
+  template <class T> T* as() const { return (T*)p; }
+};
+
+}  // namespace
+
+extern "C" {
+
+const char* hss_last_error(void) { return g_last_error.c_str(); }
+const char* hss_version(void) { return "libhss 0.1 (gfx950)"; }
+
+hss_status hss_tree_build(int64_t n, const double* points_host, int32_t leaf_size, int32_t method,
+                          hss_tree** out) {
+  return guarded([&]() -> hss_status {
+    if (!out) throw Error(HSS_ERR_INVALID_ARG, "out is NULL");
+    *out = tree_build(n, points_host, leaf_size, method);
+    return HSS_OK;
+  });
+}
+
+void hss_tree_free(hss_tree* tree) { tree_free(tree); }
+
+hss_status hss_compress_batched(int32_t count, const hss_generator* gens, const hss_tree* const* trees,
+                                const hss_options* opts, hss_matrix** out) {
+  return guarded([&]() -> hss_status {
+    if (count < 1 || !gens || !trees || !opts || !out) throw Error(HSS_ERR_INVALID_ARG, "NULL argument");
+    for (int32_t k = 0; k < count; ++k) out[k] = nullptr;
+    auto job = std::make_shared<Job>();
+    job->setup(count, gens, trees, opts);
+    job->compress();
+    hss_status worst = HSS_OK;
+    for (int32_t k = 0; k < count; ++k)
+      if (job->probs[k].status > worst) worst = job->probs[k].status;
+    std::vector<hss_matrix*> res(count);
+    for (int32_t k = 0; k < count; ++k) {
+      res[k] = new hss_matrix;
+      res[k]->job = job;
+      res[k]->k = k;
+    }
+    for (int32_t k = 0; k < count; ++k) out[k] = res[k];
+    if (worst == HSS_NOT_CONVERGED) g_last_error = "d reached d_max before the root compressed";
+    return worst;
+  });
+}
+
+hss_status hss_compress(const hss_generator* gen, const hss_tree* tree, const hss_options* opt,
+                        hss_matrix** out) {
+  if (!tree) return fail(HSS_ERR_INVALID_ARG, "tree is NULL");
+  const hss_tree* trees[1] = {tree};
+  return hss_compress_batched(1, gen, trees, opt, out);
+}
+
+void hss_destroy(hss_matrix* h) { delete h; }
+
+hss_status hss_get_info(const hss_matrix* h, hss_info* out) {
+  return guarded([&]() -> hss_status {
+    if (!h || !out) throw Error(HSS_ERR_INVALID_ARG, "NULL argument");
+    const Job& J = *h->job;
+    const Problem& P = J.probs[h->k];
+    std::memset(out, 0, sizeof(*out));
+    out->n = P.n;
+    out->num_nodes = P.nn;
+    out->rounds = P.rounds;
+    out->d_final = P.d;
+    int32_t r = 0;
+    for (int32_t v = 1; v < P.nn; ++v) {
+      const NodeState& s = J.st_h[P.node0 + v];
+      r = std::max(r, std::max(s.rank[0], s.rank[1]));
+    }
+    out->hss_rank = r;
+    out->status = P.status;
+    out->symmetric = P.sym;
+    out->sample_ms = J.sample_ms;
+    out->total_ms = J.total_ms;
+    out->sample_flops = 2.0 * (double)P.n * (double)P.n * P.d * (P.sym ? 1 : 2);
+    return HSS_OK;
+  });
+}
+
+hss_status hss_get_node_info(const hss_matrix* h, int32_t node, hss_node_info* out) {
+  return guarded([&]() -> hss_status {
+    if (!h || !out) throw Error(HSS_ERR_INVALID_ARG, "NULL argument");
+    const Job& J = *h->job;
+    const Problem& P = J.probs[h->k];
+    if (node < 0 || node >= P.nn) throw Error(HSS_ERR_INVALID_ARG, "node out of range");
+    const NodeDesc& d = J.desc[P.node0 + node];
+    const NodeState& s = J.st_h[P.node0 + node];
+    std::memset(out, 0, sizeof(*out));
+    out->state = s.state;
+    out->is_leaf = d.leaf;
+    out->lo = d.lo;
+    out->hi = d.hi;
+    if (d.parent >= 0) {
+      out->m_r = s.m[0];
+      out->m_c = s.m[1];
+      out->rank_r = s.rank[0];
+      out->rank_c = s.rank[1];
+    }
+    if (!d.leaf) {
+      out->b_rows = J.st_h[d.left].rank[0];
+      out->b_cols = J.st_h[d.right].rank[1];
+    }
+    return HSS_OK;
+  });
+}
+
+hss_status hss_copy_node(const hss_matrix* h, int32_t node, int32_t what, void* host_dst, size_t bytes) {
+  return guarded([&]() -> hss_status {
+    if (!h || !host_dst) throw Error(HSS_ERR_INVALID_ARG, "NULL argument");
+    const Job& J = *h->job;
+    const Problem& P = J.probs[h->k];
+    if (node < 0 || node >= P.nn) throw Error(HSS_ERR_INVALID_ARG, "node out of range");
+    const NodeDesc& d = J.desc[P.node0 + node];
+    const NodeState& s = J.st_h[P.node0 + node];
+    const bool root = d.parent < 0;
+    auto need = [&](size_t b) {
+      if (bytes < b) throw Error(HSS_ERR_INVALID_ARG, "destination too small");
+    };
+    // copy a (rows x cols) block with device leading dimension ld into a dense
+    // column-major host array
+    auto copy2d = [&](const double* src, int64_t ld, int32_t rows, int32_t cols) {
+      need(sizeof(double) * (size_t)rows * cols);
+      if (rows == 0 || cols == 0) return;
+      HSS_HIP_CHECK(hipMemcpy2D(host_dst, sizeof(double) * rows, src, sizeof(double) * ld, sizeof(double) * rows,
+                                cols, hipMemcpyDeviceToHost));
+    };
+    switch (what) {
+      case HSS_NODE_D: {
+        if (!d.leaf) throw Error(HSS_ERR_INVALID_ARG, "D exists on leaves only");
+        const int32_t m = d.hi - d.lo;
+        copy2d(J.dpool + d.D, m, m, m);
+        break;
+      }
+      case HSS_NODE_B12:
+      case HSS_NODE_B21: {
+        if (d.leaf) throw Error(HSS_ERR_INVALID_ARG, "B exists on non-leaves only");
+        const NodeDesc& L = J.desc[d.left];
+        const NodeDesc& R = J.desc[d.right];
+        const NodeState& sl = J.st_h[d.left];
+        const NodeState& sr = J.st_h[d.right];
+        if (what == HSS_NODE_B12) copy2d(J.dpool + d.B12, L.rcap, sl.rank[0], sr.rank[1]);
+        else copy2d(J.dpool + d.B21, R.rcap, sr.rank[0], sl.rank[1]);
+        break;
+      }
+      case HSS_NODE_JR:
+      case HSS_NODE_JC: {
+        if (root) throw Error(HSS_ERR_INVALID_ARG, "the root has no basis");
+        const int side = what == HSS_NODE_JC;
+        need(sizeof(int32_t) * s.m[side]);
+        if (s.m[side])
+          HSS_HIP_CHECK(hipMemcpy(host_dst, J.ipool + d.J[side], sizeof(int32_t) * s.m[side], hipMemcpyDeviceToHost));
+        break;
+      }
+      case HSS_NODE_ER:
+      case HSS_NODE_EC: {
+        if (root) throw Error(HSS_ERR_INVALID_ARG, "the root has no basis");
+        const int side = what == HSS_NODE_EC;
+        copy2d(J.dpool + d.E[side], d.rcap, s.rank[side], s.m[side] - s.rank[side]);
+        break;
+      }
+      case HSS_NODE_IR:
+      case HSS_NODE_IC: {
+        if (root) throw Error(HSS_ERR_INVALID_ARG, "the root has no basis");
+        const int side = what == HSS_NODE_IC;
+        need(sizeof(int64_t) * s.rank[side]);
+        if (s.rank[side])
+          HSS_HIP_CHECK(hipMemcpy(host_dst, J.lpool + d.I[side], sizeof(int64_t) * s.rank[side], hipMemcpyDeviceToHost));
+        break;
+      }
+      default:
+        throw Error(HSS_ERR_INVALID_ARG, "unknown node object");
+    }
+    return HSS_OK;
+  });
+}
+
+hss_status hss_matvec(const hss_matrix* h, int32_t nrhs, const double* X, int64_t ldx, double* Y, int64_t ldy,
+                      void* stream) {
+  return guarded([&]() -> hss_status {
+    if (!h || !X || !Y || nrhs < 1) throw Error(HSS_ERR_INVALID_ARG, "bad arguments");
+    const Job& J = *h->job;
+    const Problem& P = J.probs[h->k];
+    if (ldx < P.n || ldy < P.n) throw Error(HSS_ERR_INVALID_ARG, "leading dimension < n");
+    hipStream_t s = (hipStream_t)stream;
+    DevBuf xp(sizeof(double) * P.n * nrhs), yp(sizeof(double) * P.n * nrhs);
+    DevBuf xh(sizeof(double) * J.mvtot * nrhs), yh(sizeof(double) * J.mvtot * nrhs);
+    const int64_t* perm = P.dev.gen.perm;
+    launch_gather_rows(X, ldx, perm, P.n, nrhs, xp.as<double>(), P.n, 0, s);
+    matvec_permuted(h, nrhs, xp.as<double>(), yp.as<double>(), xh.as<double>(), yh.as<double>(), s);
+    launch_gather_rows(yp.as<double>(), P.n, perm, P.n, nrhs, Y, ldy, 1, s);
+    HSS_HIP_CHECK(hipGetLastError());
+    // temporaries are freed at scope exit; hipFree waits for the device to finish with them
+    HSS_HIP_CHECK(hipStreamSynchronize(s));
+    return HSS_OK;
+  });
+}
+
+hss_status hss_rel_error(const hss_matrix* h, const hss_generator* gen, double* rel_err) {
+  return guarded([&]() -> hss_status {
+    if (!h || !rel_err) throw Error(HSS_ERR_INVALID_ARG, "NULL argument");
+    (void)gen;  // the compressed job keeps its own generator tables
+    const Job& J = *h->job;
+    const Problem& P = J.probs[h->k];
+    hipStream_t s = J.stream;
+    const int32_t nb = (int32_t)std::min<int64_t>(P.n, 256);
+    DevBuf xp(sizeof(double) * P.n * nb), yp(sizeof(double) * P.n * nb);
+    DevBuf xh(sizeof(double) * J.mvtot * nb), yh(sizeof(double) * J.mvtot * nb);
+    DevBuf acc(sizeof(double) * 2 * 1024);
+    HSS_HIP_CHECK(hipMemsetAsync(acc.p, 0, sizeof(double) * 2 * 1024, s));
+    for (int64_t j0 = 0; j0 < P.n; j0 += nb) {
+      const int32_t w = (int32_t)std::min<int64_t>(nb, P.n - j0);
+      launch_eye_block(xp.as<double>(), P.n, j0, w, s);
+      matvec_permuted(h, w, xp.as<double>(), yp.as<double>(), xh.as<double>(), yh.as<double>(), s);
+      launch_err_block(P.dev.gen, yp.as<double>(), P.n, j0, w, acc.as<double>(), s);
+    }
+    std::vector<double> hacc(2 * 1024);
+    HSS_HIP_CHECK(hipMemcpyAsync(hacc.data(), acc.p, sizeof(double) * 2 * 1024, hipMemcpyDeviceToHost, s));
+    HSS_HIP_CHECK(hipStreamSynchronize(s));
+    double e = 0.0, a = 0.0;
+    for (int i = 0; i < 1024; ++i) {
+      e += hacc[2 * i];
+      a += hacc[2 * i + 1];
+    }
+    *rel_err = a > 0.0 ? std::sqrt(e / a) : std::sqrt(e);
+    return HSS_OK;
+  });
+}
+
+hss_status hss_sample(const hss_generator* gen, const int64_t* perm, int32_t ncols, const double* R, int64_t ldr,
+                      double* S, int64_t lds, int32_t transpose, int32_t precision, void* stream) {
+  return guarded([&]() -> hss_status {
+    if (!gen || !R || !S || ncols < 0) throw Error(HSS_ERR_INVALID_ARG, "bad arguments");
+    if (ldr < gen->n || lds < gen->n) throw Error(HSS_ERR_INVALID_ARG, "leading dimension < n");
+    if (precision < 0 || precision > 2) throw Error(HSS_ERR_INVALID_ARG, "bad precision");
+    if (precision != HSS_SAMPLE_FP64 && gen->family == HSS_FAM_DENSE)
+      throw Error(HSS_ERR_INVALID_ARG, "reduced-precision sampling needs a generated family");
+    hipStream_t s = (hipStream_t)stream;
+    GenHolder G(*gen, perm, s);
+    const size_t pe = sample_partial_elems(gen->n, ncols);
+    DevBuf part(sizeof(double) * std::max<size_t>(pe, 1));
+    launch_sample(G.g, transpose ? 1 : 0, precision, R, ldr, S, lds, ncols, part.as<double>(), s);
+    HSS_HIP_CHECK(hipGetLastError());
+    HSS_HIP_CHECK(hipStreamSynchronize(s));
+    return HSS_OK;
+  });
+}
+
+hss_status hss_extract(const hss_generator* gen, const int64_t* perm, int32_t nI, const int64_t* I, int32_t nJ,
+                       const int64_t* Jx, double* out, int64_t ldo, void* stream) {
+  return guarded([&]() -> hss_status {
+    if (!gen || nI < 0 || nJ < 0 || (nI && !I) || (nJ && !Jx) || !out || ldo < std::max(nI, 1))
+      throw Error(HSS_ERR_INVALID_ARG, "bad arguments");
+    hipStream_t s = (hipStream_t)stream;
+    GenHolder G(*gen, perm, s);
+    launch_extract(G.g, nI, I, nJ, Jx, out, ldo, s);
+    HSS_HIP_CHECK(hipGetLastError());
+    HSS_HIP_CHECK(hipStreamSynchronize(s));
+    return HSS_OK;
+  });
+}
+
+hss_status hss_interpolative_batched(int32_t count, const int32_t* m, const int32_t* d, const int64_t* ld,
+                                     const double* S, const int64_t* s_off, double eps_r, double eps_a,
+                                     int32_t* piv, const int64_t* piv_off, double* E, const int64_t* e_off,
+                                     int32_t* rank_host) {
+  return guarded([&]() -> hss_status {
+    if (count < 0 || (count && (!m || !d || !ld || !S || !s_off || !piv || !piv_off || !E || !e_off || !rank_host)))
+      throw Error(HSS_ERR_INVALID_ARG, "NULL argument");
+    if (count == 0) return HSS_OK;
+    if (!(eps_r >= 0.0) || !(eps_a >= 0.0)) throw Error(HSS_ERR_INVALID_ARG, "need eps >= 0");
+    int32_t mmax = 1, dmax = 1;
+    std::vector<int64_t> woff(count);
+    int64_t wtot = 0;
+    for (int32_t k = 0; k < count; ++k) {
+      if (m[k] < 0 || d[k] < 0 || ld[k] < std::max(d[k], 1)) throw Error(HSS_ERR_INVALID_ARG, "bad matrix shape");
+      mmax = std::max(mmax, m[k]);
+      dmax = std::max(dmax, d[k]);
+      woff[k] = wtot;
+      wtot += (int64_t)m[k] * ld[k];
+    }
+    DevBuf dm(sizeof(int32_t) * count), dd(sizeof(int32_t) * count), dld(sizeof(int64_t) * count);
+    DevBuf dso(sizeof(int64_t) * count), dwo(sizeof(int64_t) * count), dpo(sizeof(int64_t) * count);
+    DevBuf deo(sizeof(int64_t) * count), drk(sizeof(int32_t) * count);
+    DevBuf W(sizeof(double) * std::max<int64_t>(wtot, 1)), nrm(sizeof(double) * (size_t)mmax * count);
+    HSS_HIP_CHECK(hipMemcpy(dm.p, m, sizeof(int32_t) * count, hipMemcpyHostToDevice));
+    HSS_HIP_CHECK(hipMemcpy(dd.p, d, sizeof(int32_t) * count, hipMemcpyHostToDevice));
+    HSS_HIP_CHECK(hipMemcpy(dld.p, ld, sizeof(int64_t) * count, hipMemcpyHostToDevice));
+    HSS_HIP_CHECK(hipMemcpy(dso.p, s_off, sizeof(int64_t) * count, hipMemcpyHostToDevice));
+    HSS_HIP_CHECK(hipMemcpy(dwo.p, woff.data(), sizeof(int64_t) * count, hipMemcpyHostToDevice));
+    HSS_HIP_CHECK(hipMemcpy(dpo.p, piv_off, sizeof(int64_t) * count, hipMemcpyHostToDevice));
+    HSS_HIP_CHECK(hipMemcpy(deo.p, e_off, sizeof(int64_t) * count, hipMemcpyHostToDevice));
+    launch_qrcp_standalone(count, dm.as<int32_t>(), dd.as<int32_t>(), dld.as<int64_t>(), S, dso.as<int64_t>(),
+                           W.as<double>(), dwo.as<int64_t>(), eps_r, eps_a, piv, dpo.as<int64_t>(), E,
+                           deo.as<int64_t>(), drk.as<int32_t>(), nrm.as<double>(), mmax, dmax, nullptr);
+    HSS_HIP_CHECK(hipGetLastError());
+    HSS_HIP_CHECK(hipMemcpy(rank_host, drk.p, sizeof(int32_t) * count, hipMemcpyDeviceToHost));
+    return HSS_OK;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,385 @@
+// Host driver of the adaptive HSS compression (Alg. 3, HSSCompressAdaptive).
+//
+// A job holds one or more independent problems.  All their nodes live in
+// one node table; the per-level kernels cover one tree level of every
+// problem per launch (Sec. 4: level-synchronised traversal), and the
+// sampling step covers every problem still open.  Device memory is sized
+// once from capacities (rank <= min(m, d_max)), so no allocation or
+// host round trip happens inside a round; the host reads back only the
+// root states at the end of each round to decide whether to sample more.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "driver.h"
+
+namespace hss {
+
+static int64_t align8(int64_t x) { return (x + 7) & ~int64_t(7); }
+
+Job::~Job() {
+  for (void* p : allocs) hipFree(p);
+  if (ev0) hipEventDestroy(ev0);
+  if (ev1) hipEventDestroy(ev1);
+}
+
+void* Job::dalloc(size_t bytes) {
+  void* p = nullptr;
+  if (bytes == 0) bytes = 8;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    hipGetLastError();
+    throw Error(e == hipErrorOutOfMemory ? HSS_ERR_OUT_OF_MEMORY : HSS_ERR_DEVICE,
+                "hipMalloc of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
+  }
+  allocs.push_back(p);
+  return p;
+}
+
+static void validate(const hss_generator& g, const hss_tree* t, const hss_options& o, int k) {
+  const std::string who = "problem " + std::to_string(k) + ": ";
+  if (!t || !t->perm || !t->lo || !t->hi || !t->left || !t->right || !t->parent || !t->level)
+    throw Error(HSS_ERR_INVALID_ARG, who + "incomplete tree");
+  if (g.n != t->n || g.n < 1) throw Error(HSS_ERR_INVALID_ARG, who + "generator n != tree n");
+  if (g.family < 0 || g.family > 3) throw Error(HSS_ERR_INVALID_ARG, who + "unknown family");
+  if ((g.family == HSS_FAM_LAPLACE || g.family == HSS_FAM_GAUSS) && !g.points)
+    throw Error(HSS_ERR_INVALID_ARG, who + "kernel family needs points");
+  if (g.family == HSS_FAM_DENSE && (!g.dense || g.ld < g.n))
+    throw Error(HSS_ERR_INVALID_ARG, who + "dense family needs dense and ld >= n");
+  if (g.family == HSS_FAM_TOEPLITZ && !(g.h > 0.0)) throw Error(HSS_ERR_INVALID_ARG, who + "toeplitz needs h > 0");
+  if (g.family == HSS_FAM_GAUSS && !(g.sigma > 0.0)) throw Error(HSS_ERR_INVALID_ARG, who + "gauss needs sigma > 0");
+  if (!(o.rtol >= 0.0) || !(o.atol >= 0.0) || !(o.eta > 0.0))
+    throw Error(HSS_ERR_INVALID_ARG, who + "need rtol >= 0, atol >= 0, eta > 0");
+  if (o.strategy < 0 || o.strategy > 2) throw Error(HSS_ERR_INVALID_ARG, who + "unknown strategy");
+  if (o.d0 < 1 || o.d_max < 1) throw Error(HSS_ERR_INVALID_ARG, who + "need d0 >= 1 and d_max >= 1");
+  if (o.strategy == HSS_INC_FNORM && o.delta_d < 1) throw Error(HSS_ERR_INVALID_ARG, who + "need delta_d >= 1");
+  if (o.strategy == HSS_DBL_HMT && o.oversample_p < 0) throw Error(HSS_ERR_INVALID_ARG, who + "need p >= 0");
+  if (!o.R || o.ldr < g.n || o.ncols_R < std::min<int64_t>(o.d_max, g.n))
+    throw Error(HSS_ERR_INVALID_ARG, who + "R must be n x ncols_R with ncols_R >= min(d_max, n)");
+  if (o.sample_precision < 0 || o.sample_precision > 2) throw Error(HSS_ERR_INVALID_ARG, who + "bad precision");
+  if (o.sample_precision != HSS_SAMPLE_FP64 && g.family == HSS_FAM_DENSE)
+    throw Error(HSS_ERR_INVALID_ARG, who + "reduced-precision sampling needs a generated family");
+  // tree structure
+  const int32_t nn = t->num_nodes;
+  if (nn < 1 || t->lo[0] != 0 || t->hi[0] != g.n || t->parent[0] != -1)
+    throw Error(HSS_ERR_INVALID_ARG, who + "root must own [0, n)");
+  for (int32_t v = 0; v < nn; ++v) {
+    if (t->hi[v] <= t->lo[v]) throw Error(HSS_ERR_INVALID_ARG, who + "empty tree node");
+    const int32_t l = t->left[v], r = t->right[v];
+    if ((l < 0) != (r < 0)) throw Error(HSS_ERR_INVALID_ARG, who + "nodes need zero or two children");
+    if (l >= 0) {
+      if (l <= v || r <= v || l >= nn || r >= nn || t->lo[l] != t->lo[v] || t->hi[l] != t->lo[r] ||
+          t->hi[r] != t->hi[v] || t->parent[l] != v || t->parent[r] != v || t->level[l] != t->level[v] + 1 ||
+          t->level[r] != t->level[v] + 1)
+        throw Error(HSS_ERR_INVALID_ARG, who + "children must partition their parent (BFS numbering)");
+    }
+  }
+}
+
+void Job::setup(int32_t count, const hss_generator* gens, const hss_tree* const* trees,
+                const hss_options* opts) {
+  if (count < 1) throw Error(HSS_ERR_INVALID_ARG, "count must be >= 1");
+  strategy = opts[0].strategy;
+  stream = (hipStream_t)opts[0].stream;
+  for (int k = 0; k < count; ++k) {
+    validate(gens[k], trees[k], opts[k], k);
+    if (opts[k].strategy != strategy || opts[k].stream != opts[0].stream)
+      throw Error(HSS_ERR_INVALID_ARG, "batched problems must share strategy and stream");
+  }
+  HSS_HIP_CHECK(hipEventCreate(&ev0));
+  HSS_HIP_CHECK(hipEventCreate(&ev1));
+  probs.resize(count);
+  int64_t dtot = 0, itot = 0, ltot = 0;
+  int32_t gnodes = 0;
+  maxlevel = 0;
+  for (int k = 0; k < count; ++k) {
+    Problem& P = probs[k];
+    const hss_tree* t = trees[k];
+    P.gen = gens[k];
+    P.opt = opts[k];
+    P.n = t->n;
+    P.nn = t->num_nodes;
+    P.sym = (gens[k].family != HSS_FAM_DENSE) || gens[k].symmetric ? 1 : 0;
+    P.dcap = (int32_t)std::min<int64_t>(opts[k].d_max, t->n);
+    P.node0 = gnodes;
+    P.perm.assign(t->perm, t->perm + t->n);
+    gnodes += P.nn;
+    for (int32_t v = 0; v < P.nn; ++v) maxlevel = std::max(maxlevel, t->level[v]);
+  }
+  desc.resize(gnodes);
+  // capacities bottom-up, then pool offsets
+  for (int k = 0; k < count; ++k) {
+    Problem& P = probs[k];
+    const hss_tree* t = trees[k];
+    const int64_t dc = P.dcap;
+    for (int32_t v = P.nn - 1; v >= 0; --v) {
+      NodeDesc& d = desc[P.node0 + v];
+      std::memset(&d, 0, sizeof(d));
+      d.prob = k;
+      d.level = t->level[v];
+      d.leaf = t->left[v] < 0;
+      d.parent = t->parent[v] < 0 ? -1 : P.node0 + t->parent[v];
+      d.left = t->left[v] < 0 ? -1 : P.node0 + t->left[v];
+      d.right = t->right[v] < 0 ? -1 : P.node0 + t->right[v];
+      d.lo = t->lo[v];
+      d.hi = t->hi[v];
+      const int32_t size = d.hi - d.lo;
+      if (d.leaf) d.mcap = size;
+      else d.mcap = std::min<int32_t>(size, desc[d.left].rcap + desc[d.right].rcap);
+      d.rcap = (int32_t)std::min<int64_t>(d.mcap, dc);
+      d.qcap = strategy == HSS_DBL_HMT ? 0 : d.rcap;
+      d.rcap = std::max(d.rcap, 1);
+    }
+    for (int32_t v = 0; v < P.nn; ++v) {
+      NodeDesc& d = desc[P.node0 + v];
+      const bool root = d.parent < 0;
+      const int nsides = P.sym ? 1 : 2;
+      for (int s = 0; s < nsides; ++s) {
+        if (!root) {
+          d.S[s] = dtot; dtot += align8((int64_t)d.mcap * dc);
+          d.RR[s] = dtot; dtot += align8((int64_t)d.rcap * dc);
+          d.Q[s] = dtot; dtot += align8((int64_t)d.mcap * d.qcap);
+          d.E[s] = dtot; dtot += align8((int64_t)d.rcap * d.mcap);
+          d.J[s] = itot; itot += align8(d.mcap);
+          d.I[s] = ltot; ltot += align8(d.rcap);
+        }
+      }
+      if (P.sym) {
+        d.S[1] = d.S[0]; d.RR[1] = d.RR[0]; d.Q[1] = d.Q[0]; d.E[1] = d.E[0];
+        d.J[1] = d.J[0]; d.I[1] = d.I[0];
+      }
+      if (d.leaf) { d.D = dtot; dtot += align8((int64_t)(d.hi - d.lo) * (d.hi - d.lo)); }
+      else {
+        d.B12 = dtot; dtot += align8((int64_t)desc[d.left].rcap * desc[d.right].rcap);
+        d.B21 = dtot; dtot += align8((int64_t)desc[d.right].rcap * desc[d.left].rcap);
+      }
+    }
+    for (int s = 0; s < (P.sym ? 1 : 2); ++s) {
+      P.sglob[s] = dtot;
+      dtot += align8(P.n * dc);
+    }
+    if (P.sym) P.sglob[1] = P.sglob[0];
+  }
+  // levels and workspaces
+  levels.assign(maxlevel + 1, LevelInfo());
+  for (int32_t g = 0; g < gnodes; ++g) levels[desc[g].level].nodes.push_back(g);
+  int64_t wsA = 0, wsB = 0;
+  int32_t maxcount = 0;
+  for (auto& L : levels) {
+    int64_t a = 0, b = 0;
+    for (int32_t g : L.nodes) {
+      NodeDesc& d = desc[g];
+      const int64_t dc = probs[d.prob].dcap;
+      d.ws = a;
+      a += align8((int64_t)d.mcap * dc);
+      d.wsq = b;
+      b += align8(std::max<int64_t>((int64_t)d.qcap * dc, d.mcap));
+      L.mcap = std::max(L.mcap, d.mcap);
+      L.rcap = std::max(L.rcap, d.rcap);
+      L.qcap = std::max(L.qcap, d.qcap);
+      L.dcap = std::max<int32_t>(L.dcap, probs[d.prob].dcap);
+    }
+    wsA = std::max(wsA, a);
+    wsB = std::max(wsB, b);
+    maxcount = std::max<int32_t>(maxcount, (int32_t)L.nodes.size());
+  }
+  size_t part = 0;
+  for (auto& P : probs) part = std::max(part, sample_partial_elems(P.n, P.dcap));
+  dpool = (double*)dalloc(sizeof(double) * std::max<int64_t>(dtot, 1));
+  ipool = (int32_t*)dalloc(sizeof(int32_t) * std::max<int64_t>(itot, 1));
+  lpool = (int64_t*)dalloc(sizeof(int64_t) * std::max<int64_t>(ltot, 1));
+  wsa = (double*)dalloc(sizeof(double) * std::max<int64_t>(wsA, 1));
+  wsb = (double*)dalloc(sizeof(double) * std::max<int64_t>(wsB, 1));
+  partial = part ? (double*)dalloc(sizeof(double) * part) : nullptr;
+  desc_d = (NodeDesc*)dalloc(sizeof(NodeDesc) * gnodes);
+  st_d = (NodeState*)dalloc(sizeof(NodeState) * gnodes);
+  prob_d = (ProbDev*)dalloc(sizeof(ProbDev) * count);
+  tasks_d = (GemmTask*)dalloc(sizeof(GemmTask) * 2 * std::max(maxcount, 1));
+  flags_d = (int32_t*)dalloc(sizeof(int32_t) * 4);
+  nodes_d = (int32_t*)dalloc(sizeof(int32_t) * gnodes);
+  {
+    std::vector<int64_t> mo(gnodes);
+    int64_t acc = 0;
+    for (int32_t g = 0; g < gnodes; ++g) { mo[g] = acc; acc += desc[g].rcap; }
+    mvtot = acc;
+    mvoff_d = (int64_t*)dalloc(sizeof(int64_t) * gnodes);
+    HSS_HIP_CHECK(hipMemcpy(mvoff_d, mo.data(), sizeof(int64_t) * gnodes, hipMemcpyHostToDevice));
+  }
+  int32_t off = 0;
+  std::vector<int32_t> all;
+  for (auto& L : levels) {
+    L.off = off;
+    off += (int32_t)L.nodes.size();
+    all.insert(all.end(), L.nodes.begin(), L.nodes.end());
+  }
+  HSS_HIP_CHECK(hipMemcpy(nodes_d, all.data(), sizeof(int32_t) * all.size(), hipMemcpyHostToDevice));
+  HSS_HIP_CHECK(hipMemcpy(desc_d, desc.data(), sizeof(NodeDesc) * gnodes, hipMemcpyHostToDevice));
+  HSS_HIP_CHECK(hipMemsetAsync(st_d, 0, sizeof(NodeState) * gnodes, stream));
+  HSS_HIP_CHECK(hipMemsetAsync(flags_d, 0, sizeof(int32_t) * 4, stream));
+  // per-problem generator data
+  for (auto& P : probs) {
+    GenDev& g = P.dev.gen;
+    std::memset(&g, 0, sizeof(g));
+    g.family = P.gen.family;
+    g.symmetric = P.sym;
+    g.n = P.n;
+    g.diag = P.gen.diag;
+    g.inv2s2 = P.gen.family == HSS_FAM_GAUSS ? 1.0 / (2.0 * P.gen.sigma * P.gen.sigma) : 0.0;
+    int64_t* perm = (int64_t*)dalloc(sizeof(int64_t) * P.n);
+    HSS_HIP_CHECK(hipMemcpy(perm, P.perm.data(), sizeof(int64_t) * P.n, hipMemcpyHostToDevice));
+    g.perm = perm;
+    if (P.gen.family == HSS_FAM_TOEPLITZ) {
+      double* t = (double*)dalloc(sizeof(double) * P.n);
+      launch_toeplitz_table(t, P.n, P.gen.h, stream);
+      g.tcol = t;
+    }
+    if (P.gen.family == HSS_FAM_LAPLACE || P.gen.family == HSS_FAM_GAUSS) {
+      double* pts = (double*)dalloc(sizeof(double) * 3 * P.n);
+      launch_permute_points(P.gen.points, perm, P.n, pts, stream);
+      g.pts = pts;
+    }
+    if (P.gen.family == HSS_FAM_DENSE) {
+      g.dense = P.gen.dense;
+      g.ld = P.gen.ld;
+    }
+    ProbDev& pd = P.dev;
+    pd.dcap = P.dcap;
+    pd.strategy = strategy;
+    pd.p = P.opt.oversample_p;
+    pd.symmetric = P.sym;
+    pd.n = P.n;
+    pd.eps_r = P.opt.eta * P.opt.rtol;
+    pd.eps_a = P.opt.eta * P.opt.atol;
+    pd.sglob[0] = P.sglob[0];
+    pd.sglob[1] = P.sglob[1];
+    pd.R = P.opt.R;
+    pd.ldr = P.opt.ldr;
+  }
+  HSS_HIP_CHECK(hipGetLastError());
+}
+
+void Job::sample(Problem& P, int32_t c0, int32_t ncols) {
+  if (ncols <= 0) return;
+  const int prec = P.opt.sample_precision;
+  HSS_HIP_CHECK(hipEventRecord(ev0, stream));
+  for (int s = 0; s < (P.sym ? 1 : 2); ++s) {
+    launch_sample(P.dev.gen, s, prec, P.opt.R + (int64_t)c0 * P.opt.ldr, P.opt.ldr,
+                  dpool + P.sglob[s] + (int64_t)c0 * P.n, P.n, ncols, partial, stream);
+  }
+  HSS_HIP_CHECK(hipEventRecord(ev1, stream));
+  HSS_HIP_CHECK(hipGetLastError());
+  HSS_HIP_CHECK(hipEventSynchronize(ev1));
+  float ms = 0.f;
+  HSS_HIP_CHECK(hipEventElapsedTime(&ms, ev0, ev1));
+  sample_ms += ms;
+  sample_flops += 2.0 * (double)P.n * (double)P.n * ncols * (P.sym ? 1 : 2);
+}
+
+void Job::run_level(int lev, int32_t ncap) {
+  LevelInfo& L = levels[lev];
+  LevelArgs a;
+  a.desc = desc_d;
+  a.st = st_d;
+  a.prob = prob_d;
+  a.nodes = nodes_d + L.off;
+  a.count = (int32_t)L.nodes.size();
+  a.dpool = dpool;
+  a.ipool = ipool;
+  a.lpool = lpool;
+  a.wsA = wsa;
+  a.wsB = wsb;
+  a.tasks = tasks_d;
+  a.flags = flags_d;
+  const int nsides = all_sym ? 1 : 2;
+  const int32_t nc = std::min(ncap, L.dcap);
+  launch_plan(a, stream);
+  launch_extract_nodes(a, stream);
+  for (int s = 0; s < nsides; ++s) launch_local_samples(a, s, L.mcap, L.rcap, nc, stream);
+  if (strategy == HSS_DBL_HMT) {
+    for (int s = 0; s < nsides; ++s) launch_qrcp(a, s, 1, L.mcap, L.dcap, stream);
+    launch_decide_hmt(a, stream);
+  } else {
+    for (int s = 0; s < nsides; ++s) launch_fnorm_test(a, s, L.mcap, std::max(L.qcap, 1), nc, stream);
+    launch_decide_fnorm(a, stream);
+    for (int s = 0; s < nsides; ++s) launch_qrcp(a, s, 0, L.mcap, L.dcap, stream);
+  }
+  for (int s = 0; s < nsides; ++s) launch_reduce(a, s, L.mcap, L.rcap, nc, stream);
+  launch_finalize(a, stream);
+  HSS_HIP_CHECK(hipGetLastError());
+}
+
+void Job::compress() {
+  auto t0 = std::chrono::steady_clock::now();
+  all_sym = true;
+  for (auto& P : probs) all_sym = all_sym && P.sym;
+  for (auto& P : probs) {
+    P.d = std::min(P.opt.d0, P.dcap);
+    P.b = P.d;
+    P.force = 0;
+    P.done = 0;
+    P.rounds = 0;
+    P.sched.push_back(P.d);
+    sample(P, 0, P.d);
+  }
+  std::vector<NodeState> roots(probs.size());
+  std::vector<ProbDev> pdev(probs.size());
+  int32_t flags[4];
+  for (int round = 0;; ++round) {
+    int32_t ncap = 0;
+    for (size_t k = 0; k < probs.size(); ++k) {
+      Problem& P = probs[k];
+      P.dev.d = P.d;
+      P.dev.b = P.b;
+      P.dev.force = P.force;
+      P.dev.done = P.done;
+      pdev[k] = P.dev;
+      if (!P.done) {
+        ncap = std::max(ncap, P.d);
+        P.rounds++;
+      }
+    }
+    HSS_HIP_CHECK(hipMemcpyAsync(prob_d, pdev.data(), sizeof(ProbDev) * pdev.size(), hipMemcpyHostToDevice, stream));
+    for (int lev = maxlevel; lev >= 0; --lev) run_level(lev, ncap);
+    for (size_t k = 0; k < probs.size(); ++k)
+      HSS_HIP_CHECK(hipMemcpyAsync(&roots[k], st_d + probs[k].node0, sizeof(NodeState), hipMemcpyDeviceToHost, stream));
+    HSS_HIP_CHECK(hipMemcpyAsync(flags, flags_d, sizeof(flags), hipMemcpyDeviceToHost, stream));
+    HSS_HIP_CHECK(hipStreamSynchronize(stream));
+    if (flags[0]) throw Error(HSS_ERR_NONFINITE, "non-finite matrix entry generated");
+    bool all_done = true;
+    for (size_t k = 0; k < probs.size(); ++k) {
+      Problem& P = probs[k];
+      if (P.done) continue;
+      if (roots[k].state == COMPRESSED) {
+        P.done = 1;
+        continue;
+      }
+      all_done = false;
+      if (P.force) throw Error(HSS_ERR_INTERNAL, "forced round left the root open");
+      if (P.d >= P.dcap) {
+        P.force = 1;
+        P.b = 0;
+        P.status = HSS_NOT_CONVERGED;
+        continue;
+      }
+      int32_t b = strategy == HSS_INC_FNORM ? P.opt.delta_d : P.d;
+      b = std::min(b, P.dcap - P.d);
+      sample(P, P.d, b);
+      P.b = b;
+      P.d += b;
+      P.sched.push_back(P.d);
+    }
+    if (all_done) break;
+  }
+  st_h.resize(desc.size());
+  HSS_HIP_CHECK(hipMemcpyAsync(st_h.data(), st_d, sizeof(NodeState) * desc.size(), hipMemcpyDeviceToHost, stream));
+  HSS_HIP_CHECK(hipStreamSynchronize(stream));
+  total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+}  // namespace hss

@@ -1,0 +1,75 @@
+// Host-side job state of libhss (see driver.cpp).
+#pragma once
+
+#include <memory>
+#include <vector>
+
+#include "hss_internal.h"
+
+namespace hss {
+
+hss_tree* tree_build(int64_t n, const double* pts, int32_t leaf, int32_t method);
+void tree_free(hss_tree* t);
+
+struct Problem {
+  hss_generator gen;
+  hss_options opt;
+  int64_t n = 0;
+  int32_t nn = 0;
+  int32_t sym = 1;
+  int32_t dcap = 0;
+  int32_t node0 = 0;
+  std::vector<int64_t> perm;
+  int64_t sglob[2] = {0, 0};
+  ProbDev dev;
+  int32_t d = 0, b = 0, force = 0, done = 0, rounds = 0;
+  hss_status status = HSS_OK;
+  std::vector<int32_t> sched;
+};
+
+struct LevelInfo {
+  std::vector<int32_t> nodes;
+  int32_t off = 0;
+  int32_t mcap = 0, rcap = 0, qcap = 0, dcap = 0;
+};
+
+struct Job {
+  std::vector<Problem> probs;
+  std::vector<NodeDesc> desc;
+  std::vector<NodeState> st_h;
+  std::vector<LevelInfo> levels;
+  int32_t maxlevel = 0;
+  int32_t strategy = 0;
+  bool all_sym = true;
+  hipStream_t stream = nullptr;
+  std::vector<void*> allocs;
+  double *dpool = nullptr, *wsa = nullptr, *wsb = nullptr, *partial = nullptr;
+  int32_t* ipool = nullptr;
+  int64_t* lpool = nullptr;
+  NodeDesc* desc_d = nullptr;
+  NodeState* st_d = nullptr;
+  ProbDev* prob_d = nullptr;
+  GemmTask* tasks_d = nullptr;
+  int32_t* flags_d = nullptr;
+  int32_t* nodes_d = nullptr;
+  int64_t* mvoff_d = nullptr;   // per node: prefix sum of rcap (matvec slots)
+  int64_t mvtot = 0;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  double sample_ms = 0.0, sample_flops = 0.0, total_ms = 0.0;
+
+  ~Job();
+  void* dalloc(size_t bytes);
+  void setup(int32_t count, const hss_generator* gens, const hss_tree* const* trees,
+             const hss_options* opts);
+  void compress();
+  void sample(Problem& P, int32_t c0, int32_t ncols);
+  void run_level(int lev, int32_t ncap);
+};
+
+}  // namespace hss
+
+// One compressed problem; `job` is shared by the problems of a batched call.
+struct hss_matrix {
+  std::shared_ptr<hss::Job> job;
+  int32_t k = 0;
+};

@@ -1,0 +1,196 @@
+// Internal definitions shared by the host driver and the HIP kernels of
+// libhss.  Device data of one compression job lives in a few pools; every
+// node of every problem of the job has a NodeDesc (static: capacities and
+// pool offsets) and a NodeState (mutable, updated by the kernels).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/hss.h"
+
+namespace hss {
+
+enum NodeStateCode : int32_t { UNTOUCHED = 0, PARTIAL = 1, COMPRESSED = 2 };
+
+// Generator as seen by the kernels (entries of the PERMUTED operator).
+struct GenDev {
+  int32_t family;
+  int32_t symmetric;
+  int64_t n;
+  double t0;          // Toeplitz t(0)
+  double inv2s2;      // Gaussian 1/(2 sigma^2)
+  double diag;        // Laplace A_ii, Gaussian diagonal shift
+  const double* tcol; // Toeplitz t(0..n-1), library owned
+  const double* pts;  // points in permuted order, n x 3, library owned
+  const int64_t* perm;
+  const double* dense;
+  int64_t ld;
+};
+
+// Static per-node description.  Offsets are in elements of the pool of the
+// matching type (double pool, int32 pool, int64 pool).  Side 0 is the row
+// side (S^r, U, J^r, I^r, R^c = U^T R), side 1 the column side (S^c, V,
+// J^c, I^c, R^r = V^T R); for symmetric problems side 1 aliases side 0.
+struct NodeDesc {
+  int32_t prob;
+  int32_t level;
+  int32_t leaf;
+  int32_t parent, left, right;  // global node ids, -1 if none
+  int32_t lo, hi;               // permuted index range within the problem
+  int32_t mcap;                 // capacity of local-sample rows
+  int32_t rcap;                 // capacity of the rank
+  int32_t qcap;                 // capacity of the test basis Q
+  int32_t pad0;
+  int64_t S[2];    // local samples, mcap x dcap, row-major (ld = dcap)
+  int64_t RR[2];   // reduced random matrix built from side s's basis: rcap x dcap row-major
+  int64_t Q[2];    // stopping-test basis, mcap x qcap column-major
+  int64_t E[2];    // interpolation matrix, rcap x mcap column-major (ld = rcap)
+  int64_t J[2];    // int32 pool: mcap pivot order
+  int64_t I[2];    // int64 pool: rcap skeleton indices
+  int64_t D;       // leaf: size x size column-major
+  int64_t B12;     // rcap(left) x rcap(right) column-major (ld = rcap(left))
+  int64_t B21;     // rcap(right) x rcap(left) column-major (ld = rcap(right))
+  int64_t ws;      // offset of this node's slot in the level workspace A (mcap x dcap)
+  int64_t wsq;     // offset in the level workspace B (qcap x dcap)
+};
+
+struct NodeState {
+  int32_t state;
+  int32_t active;   // local samples are computed this round
+  int32_t fresh;    // was UNTOUCHED when the round reached it
+  int32_t extract;  // needs D / B extraction this round
+  int32_t c0, nc;   // new columns [c0, c0 + nc) of this round
+  int32_t go;       // compress (ID) this round
+  int32_t test;     // not yet compressed: evaluate the stopping test
+  int32_t m[2];     // rows of the local samples per side
+  int32_t rank[2];
+  int32_t passed[2];
+  int32_t need[2];  // F-norm test must run its projections this round
+  int32_t q[2];     // columns of Q per side
+  double rho[2];
+};
+
+// Per-problem device parameters (rewritten by the host every round).
+struct ProbDev {
+  int32_t d;        // columns sampled so far
+  int32_t b;        // columns added in the last sampling step
+  int32_t force;    // accept every open node
+  int32_t done;     // root compressed: skip all work
+  int32_t dcap;
+  int32_t strategy;
+  int32_t p;        // HMT oversampling
+  int32_t symmetric;
+  int64_t n;
+  double eps_r, eps_a;   // eta * tol (divided by level(tau) in the kernels)
+  int64_t sglob[2];      // offsets of the global samples (n x dcap col-major) in the double pool
+  const double* R;
+  int64_t ldr;
+  GenDev gen;
+};
+
+// C(i,j) = alpha * sum_k A(i,k) B(k,j) + beta * C(i,j) with arbitrary strides.
+struct GemmTask {
+  const double* A;
+  const double* B;
+  double* C;
+  int64_t a_rs, a_cs, b_rs, b_cs, c_rs, c_cs;
+  int32_t M, N, K, pad;
+  double alpha, beta;
+};
+
+// ------------------------------------------------------------------ launchers
+void launch_toeplitz_table(double* t, int64_t n, double h, hipStream_t s);
+void launch_permute_points(const double* pts, const int64_t* perm, int64_t n, double* out,
+                           hipStream_t s);
+// Sampling: S(:, 0:ncols) = op(A_hat) R(:, 0:ncols); `partial` is workspace of
+// partial_cap doubles for the split-K partial sums.
+int sample_splits(int64_t n, int32_t ncols);
+size_t sample_partial_elems(int64_t n, int32_t ncols);
+void launch_sample(const GenDev& g, int32_t transpose, int32_t precision, const double* R,
+                   int64_t ldr, double* S, int64_t lds, int32_t ncols, double* partial,
+                   hipStream_t s);
+void launch_extract(const GenDev& g, int32_t nI, const int64_t* I, int32_t nJ, const int64_t* J,
+                    double* out, int64_t ldo, hipStream_t s);
+void launch_gemm(const GemmTask* tasks, int32_t ntasks, int32_t mcap, int32_t ncap,
+                 hipStream_t s);
+
+struct LevelArgs {
+  const NodeDesc* desc;
+  NodeState* st;
+  const ProbDev* prob;
+  const int32_t* nodes;  // global ids of this level's nodes
+  int32_t count;
+  double* dpool;
+  int32_t* ipool;
+  int64_t* lpool;
+  double* wsA;
+  double* wsB;
+  GemmTask* tasks;       // scratch task array, capacity >= 2 * count
+  int32_t* flags;        // device error flags
+};
+
+void launch_plan(const LevelArgs& a, hipStream_t s);
+void launch_extract_nodes(const LevelArgs& a, hipStream_t s);
+void launch_local_samples(const LevelArgs& a, int side, int32_t mcap_max, int32_t rcap_max,
+                          int32_t dcap_max, hipStream_t s);
+void launch_fnorm_test(const LevelArgs& a, int side, int32_t mcap_max, int32_t qcap_max,
+                       int32_t dcap_max, hipStream_t s);
+void launch_decide_fnorm(const LevelArgs& a, hipStream_t s);
+void launch_qrcp(const LevelArgs& a, int side, int32_t hmt, int32_t mcap_max,
+                 int32_t dcap_max, hipStream_t s);
+void launch_decide_hmt(const LevelArgs& a, hipStream_t s);
+void launch_reduce(const LevelArgs& a, int side, int32_t mcap_max, int32_t rcap_max,
+                   int32_t dcap_max, hipStream_t s);
+void launch_finalize(const LevelArgs& a, hipStream_t s);
+
+// Standalone batched ID (hss_interpolative_batched).
+void launch_qrcp_standalone(int32_t count, const int32_t* m, const int32_t* d,
+                            const int64_t* ld, const double* S, const int64_t* s_off,
+                            double* W, const int64_t* w_off, double eps_r, double eps_a,
+                            int32_t* piv, const int64_t* piv_off, double* E,
+                            const int64_t* e_off, int32_t* rank, double* nrm, int32_t mmax,
+                            int32_t dmax, hipStream_t s);
+
+// Matvec pieces (one workgroup per node of a level).
+struct MvArgs {
+  const NodeDesc* desc;
+  const NodeState* st;
+  const int32_t* nodes;
+  int32_t count;
+  const double* dpool;
+  const int32_t* ipool;
+  double* xh;           // per node: rcap x nrhs (column-major, ld = rcap)
+  double* yh;
+  const int64_t* xh_off;  // per global node offset into xh / yh
+  const double* X;      // permuted input, n x nrhs (ld = n)
+  double* Y;
+  int64_t n;
+  int32_t nrhs;
+};
+void launch_mv_up(const MvArgs& a, hipStream_t s);
+void launch_mv_down(const MvArgs& a, hipStream_t s);
+void launch_gather_rows(const double* X, int64_t ldx, const int64_t* perm, int64_t n, int32_t nrhs,
+                        double* out, int64_t ldo, int32_t inverse, hipStream_t s);
+void launch_eye_block(double* X, int64_t n, int64_t j0, int32_t nb, hipStream_t s);
+void launch_err_block(const GenDev& g, const double* Hc, int64_t ldh, int64_t j0, int32_t nb,
+                      double* accum, hipStream_t s);
+
+}  // namespace hss
+
+#define HSS_HIP_CHECK(expr)                                                        \
+  do {                                                                             \
+    hipError_t _e = (expr);                                                        \
+    if (_e != hipSuccess) throw hss::Error(HSS_ERR_DEVICE, std::string(#expr) + ": " + \
+                                           hipGetErrorString(_e));                 \
+  } while (0)
+
+namespace hss {
+struct Error {
+  hss_status code;
+  std::string msg;
+  Error(hss_status c, std::string m) : code(c), msg(std::move(m)) {}
+};
+}  // namespace hss

@@ -1,0 +1,684 @@
+// Per-level kernels of the adaptive HSS compression.  Every launch covers
+// all nodes of one tree level of every problem of the job; one workgroup
+// (256 threads) or one thread owns a node.  Sizes that depend on ranks are
+// read from NodeState, so a whole round runs without host involvement.
+//
+//   k_plan          Alg. 3: which nodes take part, their column range
+//   k_extract_nodes Alg. 3: D = A(I,I) on leaves, B12/B21 from skeletons
+//   k_ls_gather     Alg. 2 ComputeLocalSamples (copy part; products on MFMA)
+//   k_fn_copy/qr    Alg. 5 / eq. stopping_criteria: CGS2 (on MFMA), norms,
+//                   Householder QR of the projected block, the two tests
+//   k_qrcp          eqs. ID, QRCPSr: QR with column pivoting of S^T with
+//                   threshold stopping (plain, or HMT-scaled for Alg. 4),
+//                   then E = R1^{-1} R2
+//   k_red_gather    Alg. 2 ReduceLocalSamples (gather part; E x(rest) on MFMA)
+//   k_finalize      node state transitions of Alg. 3
+#include <math.h>
+
+#include <algorithm>
+
+#include "gen.h"
+
+namespace hss {
+
+constexpr int NB = 256;  // threads per node workgroup
+constexpr int NW = NB / 64;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Sum over the workgroup; every thread gets the result.  `red` holds NW doubles.
+__device__ double block_sum(double v, double* red) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) s += red[i];
+  __syncthreads();
+  return s;
+}
+
+__device__ __forceinline__ const double* cdp(const LevelArgs& a, int64_t off) { return a.dpool + off; }
+__device__ __forceinline__ double* dp(const LevelArgs& a, int64_t off) { return a.dpool + off; }
+
+// ------------------------------------------------------------------ plan
+__global__ void k_plan(LevelArgs a) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= a.count) return;
+  const int g = a.nodes[t];
+  const NodeDesc& nd = a.desc[g];
+  NodeState& st = a.st[g];
+  const ProbDev& P = a.prob[nd.prob];
+  st.active = 0;
+  st.extract = 0;
+  st.go = 0;
+  st.test = 0;
+  st.need[0] = st.need[1] = 0;
+  st.nc = 0;
+  if (P.done) return;
+  if (st.state == COMPRESSED && nd.parent < 0) return;
+  const bool kids = nd.leaf || (a.st[nd.left].state == COMPRESSED && a.st[nd.right].state == COMPRESSED);
+  if (!kids) return;
+  st.fresh = st.state == UNTOUCHED;
+  st.extract = st.fresh;
+  if (nd.parent < 0) {  // root: extraction, then COMPRESSED
+    st.go = 1;
+    return;
+  }
+  st.active = 1;
+  st.c0 = st.fresh ? 0 : P.d - P.b;
+  st.nc = P.d - st.c0;
+  for (int s = 0; s < 2; ++s)
+    st.m[s] = nd.leaf ? (nd.hi - nd.lo) : a.st[nd.left].rank[s] + a.st[nd.right].rank[s];
+  if (P.symmetric) st.m[1] = st.m[0];
+  st.test = st.state != COMPRESSED;
+  if (!st.test) return;
+  if (st.fresh) {
+    for (int s = 0; s < 2; ++s) {
+      st.passed[s] = 0;
+      st.q[s] = 0;
+      st.rho[s] = -1.0;
+      st.rank[s] = 0;
+    }
+  }
+  if (P.strategy != HSS_DBL_HMT && !P.force) {
+    for (int s = 0; s < 2; ++s) {
+      if (st.passed[s]) continue;
+      if (P.d >= st.m[s]) st.passed[s] = 1;  // samples span the whole local range
+      else if (st.nc > 0) st.need[s] = 1;
+    }
+  }
+}
+
+void launch_plan(const LevelArgs& a, hipStream_t s) {
+  if (a.count <= 0) return;
+  hipLaunchKernelGGL(k_plan, dim3((a.count + 127) / 128), dim3(128), 0, s, a);
+}
+
+// ------------------------------------------------------------------ extraction
+__global__ __launch_bounds__(NB) void k_extract_nodes(LevelArgs a) {
+  const int g = a.nodes[blockIdx.x];
+  const NodeDesc& nd = a.desc[g];
+  const NodeState& st = a.st[g];
+  if (!st.extract) return;
+  const ProbDev& P = a.prob[nd.prob];
+  const GenDev& gen = P.gen;
+  int bad = 0;
+  if (nd.leaf) {
+    const int m = nd.hi - nd.lo;
+    double* D = dp(a, nd.D);
+    for (int64_t idx = threadIdx.x; idx < (int64_t)m * m; idx += NB) {
+      const int i = (int)(idx % m), j = (int)(idx / m);
+      const double v = gen_entry(gen, nd.lo + i, nd.lo + j);
+      bad |= !isfinite(v);
+      D[idx] = v;
+    }
+  } else {
+    const NodeDesc& L = a.desc[nd.left];
+    const NodeDesc& Rn = a.desc[nd.right];
+    const NodeState& sl = a.st[nd.left];
+    const NodeState& sr = a.st[nd.right];
+    // B12 = A(left.I^r, right.I^c), B21 = A(right.I^r, left.I^c)
+    const int r1 = sl.rank[0], c2 = sr.rank[1];
+    const int64_t* I1r = a.lpool + L.I[0];
+    const int64_t* I2c = a.lpool + Rn.I[1];
+    double* B12 = dp(a, nd.B12);
+    for (int64_t idx = threadIdx.x; idx < (int64_t)r1 * c2; idx += NB) {
+      const int i = (int)(idx % r1), j = (int)(idx / r1);
+      const double v = gen_entry(gen, I1r[i], I2c[j]);
+      bad |= !isfinite(v);
+      B12[(int64_t)j * L.rcap + i] = v;
+    }
+    const int r2 = sr.rank[0], c1 = sl.rank[1];
+    const int64_t* I2r = a.lpool + Rn.I[0];
+    const int64_t* I1c = a.lpool + L.I[1];
+    double* B21 = dp(a, nd.B21);
+    for (int64_t idx = threadIdx.x; idx < (int64_t)r2 * c1; idx += NB) {
+      const int i = (int)(idx % r2), j = (int)(idx / r2);
+      const double v = gen_entry(gen, I2r[i], I1c[j]);
+      bad |= !isfinite(v);
+      B21[(int64_t)j * Rn.rcap + i] = v;
+    }
+  }
+  if (bad) atomicOr(a.flags, 1);
+}
+
+void launch_extract_nodes(const LevelArgs& a, hipStream_t s) {
+  if (a.count <= 0) return;
+  hipLaunchKernelGGL(k_extract_nodes, dim3(a.count), dim3(NB), 0, s, a);
+}
+
+// ------------------------------------------------------------------ local samples
+// Copies the first term of ComputeLocalSamples into tau.S(:, c0:c0+nc) and
+// writes the GEMM tasks of the product terms (two per node).
+__global__ __launch_bounds__(NB) void k_ls_gather(LevelArgs a, int side) {
+  const int t = blockIdx.x;
+  const int g = a.nodes[t];
+  const NodeDesc& nd = a.desc[g];
+  const NodeState& st = a.st[g];
+  GemmTask* T0 = a.tasks + t;
+  GemmTask* T1 = a.tasks + a.count + t;
+  if (threadIdx.x == 0) {
+    T0->M = 0;
+    T1->M = 0;
+  }
+  if (!st.active || st.nc <= 0) return;
+  const ProbDev& P = a.prob[nd.prob];
+  const int dcap = P.dcap;
+  const int c0 = st.c0, nc = st.nc;
+  const int m = st.m[side];
+  double* S = dp(a, nd.S[side]);
+  if (nd.leaf) {
+    const double* Sg = cdp(a, P.sglob[side]);
+    for (int64_t idx = threadIdx.x; idx < (int64_t)m * nc; idx += NB) {
+      const int i = (int)(idx % m), c = (int)(idx / m);
+      S[(int64_t)i * dcap + c0 + c] = Sg[(int64_t)(c0 + c) * P.n + nd.lo + i];
+    }
+    if (threadIdx.x == 0) {
+      GemmTask k;
+      k.A = cdp(a, nd.D);
+      if (side == 0) { k.a_rs = 1; k.a_cs = m; } else { k.a_rs = m; k.a_cs = 1; }
+      k.B = P.R + nd.lo + (int64_t)c0 * P.ldr;
+      k.b_rs = 1;
+      k.b_cs = P.ldr;
+      k.C = S + c0;
+      k.c_rs = dcap;
+      k.c_cs = 1;
+      k.M = m; k.N = nc; k.K = m; k.pad = 0;
+      k.alpha = -1.0; k.beta = 1.0;
+      *T0 = k;
+    }
+    return;
+  }
+  const NodeDesc& L = a.desc[nd.left];
+  const NodeDesc& Rn = a.desc[nd.right];
+  const NodeState& sl = a.st[nd.left];
+  const NodeState& sr = a.st[nd.right];
+  const int r1 = sl.rank[side];
+  const int32_t* J1 = a.ipool + L.J[side];
+  const int32_t* J2 = a.ipool + Rn.J[side];
+  const double* S1 = cdp(a, L.S[side]);
+  const double* S2 = cdp(a, Rn.S[side]);
+  for (int64_t idx = threadIdx.x; idx < (int64_t)m * nc; idx += NB) {
+    const int c = (int)(idx % nc), i = (int)(idx / nc);
+    const double v = i < r1 ? S1[(int64_t)J1[i] * dcap + c0 + c] : S2[(int64_t)J2[i - r1] * dcap + c0 + c];
+    S[(int64_t)i * dcap + c0 + c] = v;
+  }
+  if (threadIdx.x == 0) {
+    GemmTask k;
+    k.b_rs = dcap; k.b_cs = 1; k.c_rs = dcap; k.c_cs = 1; k.N = nc; k.pad = 0;
+    k.alpha = -1.0; k.beta = 1.0;
+    if (side == 0) {
+      // [left.S^r(J) - B12 right.R^r ; right.S^r(J) - B21 left.R^r], R^r = V^T R (side-1 basis)
+      k.A = cdp(a, nd.B12); k.a_rs = 1; k.a_cs = L.rcap;
+      k.B = cdp(a, Rn.RR[1]) + c0; k.C = S + c0;
+      k.M = sl.rank[0]; k.K = sr.rank[1];
+      *T0 = k;
+      k.A = cdp(a, nd.B21); k.a_rs = 1; k.a_cs = Rn.rcap;
+      k.B = cdp(a, L.RR[1]) + c0; k.C = S + (int64_t)sl.rank[0] * dcap + c0;
+      k.M = sr.rank[0]; k.K = sl.rank[1];
+      *T1 = k;
+    } else {
+      // [left.S^c(J) - B21^T right.R^c ; right.S^c(J) - B12^T left.R^c], R^c = U^T R
+      k.A = cdp(a, nd.B21); k.a_rs = Rn.rcap; k.a_cs = 1;
+      k.B = cdp(a, Rn.RR[0]) + c0; k.C = S + c0;
+      k.M = sl.rank[1]; k.K = sr.rank[0];
+      *T0 = k;
+      k.A = cdp(a, nd.B12); k.a_rs = L.rcap; k.a_cs = 1;
+      k.B = cdp(a, L.RR[0]) + c0; k.C = S + (int64_t)sl.rank[1] * dcap + c0;
+      k.M = sr.rank[1]; k.K = sl.rank[0];
+      *T1 = k;
+    }
+  }
+}
+
+void launch_local_samples(const LevelArgs& a, int side, int32_t mcap_max, int32_t rcap_max,
+                          int32_t ncap, hipStream_t s) {
+  (void)rcap_max;
+  if (a.count <= 0) return;
+  hipLaunchKernelGGL(k_ls_gather, dim3(a.count), dim3(NB), 0, s, a, side);
+  launch_gemm(a.tasks, 2 * a.count, mcap_max, ncap, s);
+}
+
+// ------------------------------------------------------------------ F-norm test
+__global__ __launch_bounds__(NB) void k_fn_copy(LevelArgs a, int side) {
+  const int t = blockIdx.x;
+  const int g = a.nodes[t];
+  const NodeDesc& nd = a.desc[g];
+  const NodeState& st = a.st[g];
+  GemmTask* TA = a.tasks + t;
+  GemmTask* TB = a.tasks + a.count + t;
+  if (threadIdx.x == 0) { TA->M = 0; TB->M = 0; }
+  if (!st.need[side]) return;
+  const ProbDev& P = a.prob[nd.prob];
+  const int dcap = P.dcap, m = st.m[side], nc = st.nc, c0 = st.c0, q = st.q[side];
+  const double* S = cdp(a, nd.S[side]);
+  double* Sh = a.wsA + nd.ws;
+  for (int64_t idx = threadIdx.x; idx < (int64_t)m * nc; idx += NB) {
+    const int i = (int)(idx % m), c = (int)(idx / m);
+    Sh[(int64_t)c * nd.mcap + i] = S[(int64_t)i * dcap + c0 + c];
+  }
+  if (threadIdx.x == 0) {
+    const double* Q = cdp(a, nd.Q[side]);
+    double* W = a.wsB + nd.wsq;
+    GemmTask k;
+    k.pad = 0;
+    // W = Q^T Sh
+    k.A = Q; k.a_rs = nd.mcap; k.a_cs = 1;
+    k.B = Sh; k.b_rs = 1; k.b_cs = nd.mcap;
+    k.C = W; k.c_rs = 1; k.c_cs = nd.qcap;
+    k.M = q; k.N = nc; k.K = m; k.alpha = 1.0; k.beta = 0.0;
+    *TA = k;
+    // Sh -= Q W
+    k.A = Q; k.a_rs = 1; k.a_cs = nd.mcap;
+    k.B = W; k.b_rs = 1; k.b_cs = nd.qcap;
+    k.C = Sh; k.c_rs = 1; k.c_cs = nd.mcap;
+    k.M = m; k.N = nc; k.K = q; k.alpha = -1.0; k.beta = 1.0;
+    *TB = k;
+  }
+}
+
+// Householder QR of the projected block Sh (m x nc, column-major, ld mcap)
+// and the tests of eq. stopping_criteria; on failure Q <- [Q Q_k].
+__global__ __launch_bounds__(NB) void k_fn_qr(LevelArgs a, int side) {
+  __shared__ double red[NW];
+  __shared__ int s_pass;
+  const int g = a.nodes[blockIdx.x];
+  const NodeDesc& nd = a.desc[g];
+  NodeState& st = a.st[g];
+  if (!st.need[side]) return;
+  const ProbDev& P = a.prob[nd.prob];
+  const int dcap = P.dcap, m = st.m[side], nc = st.nc, c0 = st.c0, ld = nd.mcap;
+  const double lev = (double)nd.level;
+  const double er = P.eps_r / lev, ea = P.eps_a / lev;
+  const double* S = cdp(a, nd.S[side]);
+  double* Sh = a.wsA + nd.ws;
+  double* tau = a.wsB + nd.wsq;  // nc reflector scales (the CGS2 workspace is free now)
+  double* alph = tau + nc;        // nc diagonal entries of Rbar
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+
+  double p1 = 0.0, p2 = 0.0;
+  for (int64_t idx = threadIdx.x; idx < (int64_t)m * nc; idx += NB) {
+    const int i = (int)(idx % m), c = (int)(idx / m);
+    const double x = S[(int64_t)i * dcap + c0 + c];
+    const double y = Sh[(int64_t)c * ld + i];
+    p1 += x * x;
+    p2 += y * y;
+  }
+  const double nS = sqrt(block_sum(p1, red));
+  const double nSh = sqrt(block_sum(p2, red));
+  if (nS == 0.0 || nSh < er * nS || nSh / sqrt((double)nc) < ea) {
+    if (threadIdx.x == 0) st.passed[side] = 1;
+    return;
+  }
+  // Householder QR, column by column
+  for (int k = 0; k < nc; ++k) {
+    double* x = Sh + (int64_t)k * ld;
+    double part = 0.0;
+    for (int i = k + threadIdx.x; i < m; i += NB) part += x[i] * x[i];
+    const double nrm = sqrt(block_sum(part, red));
+    const double x0 = x[k];
+    double alpha = 0.0, tk = 0.0;
+    if (nrm > 0.0) {
+      alpha = x0 >= 0.0 ? -nrm : nrm;
+      tk = 1.0 / (nrm * (nrm + fabs(x0)));  // 2 / v^T v
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      x[k] = x0 - alpha;  // v_0; v_i = x_i below
+      tau[k] = tk;
+      alph[k] = alpha;
+    }
+    __syncthreads();
+    for (int j = k + 1 + w; j < nc; j += NW) {
+      double* y = Sh + (int64_t)j * ld;
+      double dot = 0.0;
+      for (int i = k + lane; i < m; i += 64) dot += x[i] * y[i];
+      dot = wave_sum(dot) * tk;
+      for (int i = k + lane; i < m; i += 64) y[i] -= dot * x[i];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double mn = INFINITY;
+    for (int k = 0; k < nc; ++k) mn = fmin(mn, fabs(alph[k]));
+    if (st.rho[side] < 0.0) st.rho[side] = fabs(alph[0]);
+    s_pass = (mn < ea || mn < er * st.rho[side]) ? 1 : 0;
+    if (s_pass) st.passed[side] = 1;
+  }
+  __syncthreads();
+  if (s_pass) return;
+  // Q_k = H_0 ... H_{nc-1} [I; 0] written into Q(:, q : q + nc)
+  const int q = st.q[side];
+  double* Qk = dp(a, nd.Q[side]) + (int64_t)q * ld;
+  for (int64_t idx = threadIdx.x; idx < (int64_t)m * nc; idx += NB) {
+    const int i = (int)(idx % m), c = (int)(idx / m);
+    Qk[(int64_t)c * ld + i] = (i == c) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int k = nc - 1; k >= 0; --k) {
+    const double* x = Sh + (int64_t)k * ld;
+    const double tk = tau[k];
+    for (int j = k + w; j < nc; j += NW) {
+      double* y = Qk + (int64_t)j * ld;
+      double dot = 0.0;
+      for (int i = k + lane; i < m; i += 64) dot += x[i] * y[i];
+      dot = wave_sum(dot) * tk;
+      for (int i = k + lane; i < m; i += 64) y[i] -= dot * x[i];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) st.q[side] = q + nc;
+}
+
+void launch_fnorm_test(const LevelArgs& a, int side, int32_t mcap_max, int32_t qcap_max,
+                       int32_t ncap, hipStream_t s) {
+  if (a.count <= 0) return;
+  hipLaunchKernelGGL(k_fn_copy, dim3(a.count), dim3(NB), 0, s, a, side);
+  for (int pass = 0; pass < 2; ++pass) {  // block Gram-Schmidt, twice
+    launch_gemm(a.tasks, a.count, qcap_max, ncap, s);
+    launch_gemm(a.tasks + a.count, a.count, mcap_max, ncap, s);
+  }
+  hipLaunchKernelGGL(k_fn_qr, dim3(a.count), dim3(NB), 0, s, a, side);
+}
+
+__global__ void k_decide_fnorm(LevelArgs a) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= a.count) return;
+  const int g = a.nodes[t];
+  NodeState& st = a.st[g];
+  if (!st.active || !st.test) return;
+  const ProbDev& P = a.prob[a.desc[g].prob];
+  const bool ok = st.passed[0] && (P.symmetric || st.passed[1]);
+  st.go = (ok || P.force) ? 1 : 0;
+}
+
+void launch_decide_fnorm(const LevelArgs& a, hipStream_t s) {
+  if (a.count <= 0) return;
+  hipLaunchKernelGGL(k_decide_fnorm, dim3((a.count + 127) / 128), dim3(128), 0, s, a);
+}
+
+// ------------------------------------------------------------------ QRCP / ID
+// Panel W = S^T (d x m, column j = row j of S, contiguous) copied to the
+// workspace.  Step k: pivot = remaining column of largest residual norm
+// (ties -> lowest index); stop before it if its norm nu <= threshold;
+// otherwise reflect it to alpha e_k and update every remaining column,
+// recomputing its residual norm (rows k+1..d-1) from the updated values.
+// Writes J (pivots, then the rest ascending), E = R1^{-1} R2 (r x (m-r),
+// column-major, leading dimension lde) and returns the rank.
+__device__ int qrcp_core(const double* __restrict__ S, int64_t lds, int m, int d, double* __restrict__ W,
+                         int64_t ldw, double* __restrict__ nrm, int32_t* __restrict__ J,
+                         double* __restrict__ E, int64_t lde, double er, double ea, int hmt,
+                         double mn_hank, double* vsh) {
+  __shared__ double rv[NW];
+  __shared__ int ri[NW];
+  __shared__ int s_piv, s_stop, s_rank;
+  __shared__ double s_nu, s_nu1, s_tau;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int j = w; j < m; j += NW) {
+    const double* src = S + (int64_t)j * lds;
+    double* dst = W + (int64_t)j * ldw;
+    double sq = 0.0;
+    for (int i = lane; i < d; i += 64) {
+      const double x = src[i];
+      dst[i] = x;
+      sq += x * x;
+    }
+    sq = wave_sum(sq);
+    if (lane == 0) nrm[j] = sqrt(sq);
+  }
+  __syncthreads();
+  const int kmax = min(m, d);
+  int k = 0;
+  for (; k < kmax; ++k) {
+    double bv = -1.0;
+    int bi = 0x7fffffff;
+    for (int j = threadIdx.x; j < m; j += NB) {
+      const double v = nrm[j];
+      if (v < 0.0) continue;
+      if (v > bv || (v == bv && j < bi)) { bv = v; bi = j; }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ov = __shfl_xor(bv, o, 64);
+      const int oi = __shfl_xor(bi, o, 64);
+      if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+    }
+    if (lane == 0) { rv[w] = bv; ri[w] = bi; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double v = rv[0];
+      int p = ri[0];
+      for (int i = 1; i < NW; ++i)
+        if (rv[i] > v || (rv[i] == v && ri[i] < p)) { v = rv[i]; p = ri[i]; }
+      if (k == 0) s_nu1 = v;
+      double thr = fmax(ea, er * s_nu1);
+      if (hmt) {
+        const double over = (double)(d - (k + 1) - 1);
+        thr = over <= 0.0 ? 0.0 : thr / (1.0 + 4.0 * sqrt((double)d) / over * sqrt(mn_hank));
+      }
+      s_stop = (v <= thr) ? 1 : 0;
+      s_piv = p;
+      s_nu = v;
+      if (!s_stop) {
+        J[k] = p;
+        nrm[p] = -1.0;
+      }
+    }
+    __syncthreads();
+    if (s_stop) break;
+    const int p = s_piv;
+    const double nu = s_nu;
+    double* x = W + (int64_t)p * ldw;
+    const double x0 = x[k];
+    const double alpha = x0 >= 0.0 ? -nu : nu;
+    for (int i = k + threadIdx.x; i < d; i += NB) vsh[i - k] = (i == k) ? x0 - alpha : x[i];
+    if (threadIdx.x == 0) s_tau = 1.0 / (nu * (nu + fabs(x0)));
+    __syncthreads();
+    if (threadIdx.x == 0) x[k] = alpha;  // R(k,k); rows > k of the pivot column are dead
+    const double tk = s_tau;
+    for (int j = w; j < m; j += NW) {
+      if (j == p || nrm[j] < 0.0) continue;
+      double* y = W + (int64_t)j * ldw;
+      double dot = 0.0;
+      for (int i = k + lane; i < d; i += 64) dot += vsh[i - k] * y[i];
+      dot = wave_sum(dot) * tk;
+      double sq = 0.0;
+      for (int i = k + lane; i < d; i += 64) {
+        const double yi = y[i] - dot * vsh[i - k];
+        y[i] = yi;
+        if (i > k) sq += yi * yi;
+      }
+      sq = wave_sum(sq);
+      if (lane == 0) nrm[j] = sqrt(sq);
+    }
+    __syncthreads();
+  }
+  const int r = k;
+  if (threadIdx.x == 0) {
+    int pos = r;
+    for (int j = 0; j < m; ++j)
+      if (nrm[j] >= 0.0) J[pos++] = j;
+    s_rank = r;
+  }
+  __syncthreads();
+  // E = R1^{-1} R2: column l of R2 is W(0:r, J[r+l]); back substitution in place
+  const int nrest = m - r;
+  for (int l = threadIdx.x; l < nrest; l += NB) {
+    double* y = W + (int64_t)J[r + l] * ldw;
+    for (int kk = r - 1; kk >= 0; --kk) {
+      const double* col = W + (int64_t)J[kk] * ldw;
+      const double yk = y[kk] / col[kk];
+      y[kk] = yk;
+      for (int i = 0; i < kk; ++i) y[i] -= col[i] * yk;
+    }
+    for (int i = 0; i < r; ++i) E[(int64_t)l * lde + i] = y[i];
+  }
+  __syncthreads();
+  return s_rank;
+}
+
+__global__ __launch_bounds__(NB) void k_qrcp(LevelArgs a, int side, int hmt) {
+  extern __shared__ double vsh[];  // Householder vector, d entries
+  const int g = a.nodes[blockIdx.x];
+  const NodeDesc& nd = a.desc[g];
+  NodeState& st = a.st[g];
+  if (!st.active || !st.test) return;
+  if (!hmt && !st.go) return;
+  const ProbDev& P = a.prob[nd.prob];
+  const double lev = (double)nd.level;
+  const int64_t size = nd.hi - nd.lo;
+  const int r = qrcp_core(a.dpool + nd.S[side], P.dcap, st.m[side], P.d, a.wsA + nd.ws, P.dcap,
+                          a.wsB + nd.wsq, a.ipool + nd.J[side], a.dpool + nd.E[side], nd.rcap,
+                          P.eps_r / lev, P.eps_a / lev, hmt, (double)min(size, P.n - size), vsh);
+  if (threadIdx.x == 0) st.rank[side] = r;
+}
+
+__global__ __launch_bounds__(NB) void k_qrcp_standalone(const int32_t* m, const int32_t* d, const int64_t* ld,
+                                                        const double* S, const int64_t* s_off, double* W,
+                                                        const int64_t* w_off, double eps_r, double eps_a,
+                                                        int32_t* piv, const int64_t* piv_off, double* E,
+                                                        const int64_t* e_off, int32_t* rank, double* nrm,
+                                                        int32_t mmax) {
+  extern __shared__ double vsh[];
+  const int k = blockIdx.x;
+  const int r = qrcp_core(S + s_off[k], ld[k], m[k], d[k], W + w_off[k], ld[k], nrm + (int64_t)k * mmax,
+                          piv + piv_off[k], E + e_off[k], m[k], eps_r, eps_a, 0, 0.0, vsh);
+  if (threadIdx.x == 0) rank[k] = r;
+}
+
+void launch_qrcp_standalone(int32_t count, const int32_t* m, const int32_t* d, const int64_t* ld,
+                            const double* S, const int64_t* s_off, double* W, const int64_t* w_off,
+                            double eps_r, double eps_a, int32_t* piv, const int64_t* piv_off, double* E,
+                            const int64_t* e_off, int32_t* rank, double* nrm, int32_t mmax, int32_t dmax,
+                            hipStream_t s) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_qrcp_standalone, dim3(count), dim3(NB), (size_t)std::max(dmax, 1) * sizeof(double), s,
+                     m, d, ld, S, s_off, W, w_off, eps_r, eps_a, piv, piv_off, E, e_off, rank, nrm, mmax);
+}
+
+void launch_qrcp(const LevelArgs& a, int side, int32_t hmt, int32_t mcap_max, int32_t dcap_max,
+                 hipStream_t s) {
+  (void)mcap_max;
+  if (a.count <= 0) return;
+  const size_t lds = (size_t)dcap_max * sizeof(double);
+  hipLaunchKernelGGL(k_qrcp, dim3(a.count), dim3(NB), lds, s, a, side, hmt);
+}
+
+__global__ void k_decide_hmt(LevelArgs a) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= a.count) return;
+  const int g = a.nodes[t];
+  NodeState& st = a.st[g];
+  if (!st.active || !st.test) return;
+  const ProbDev& P = a.prob[a.desc[g].prob];
+  bool ok = true;
+  for (int s = 0; s < (P.symmetric ? 1 : 2); ++s)
+    ok = ok && (st.rank[s] < P.d - P.p || st.rank[s] == st.m[s]);
+  st.go = (ok || P.force) ? 1 : 0;
+}
+
+void launch_decide_hmt(const LevelArgs& a, hipStream_t s) {
+  if (a.count <= 0) return;
+  hipLaunchKernelGGL(k_decide_hmt, dim3((a.count + 127) / 128), dim3(128), 0, s, a);
+}
+
+// ------------------------------------------------------------------ reduce
+// RR[side](:, cols) = U_side^T X(:, cols) = X(J,:) + E X(rest,:), X = R(I_tau)
+// on a leaf or the stacked children's RR[side]; skeleton indices on compression.
+__global__ __launch_bounds__(NB) void k_red_gather(LevelArgs a, int side) {
+  const int t = blockIdx.x;
+  const int g = a.nodes[t];
+  const NodeDesc& nd = a.desc[g];
+  const NodeState& st = a.st[g];
+  GemmTask* T0 = a.tasks + t;
+  if (threadIdx.x == 0) T0->M = 0;
+  if (!st.active) return;
+  if (!(st.state == COMPRESSED || st.go)) return;
+  const ProbDev& P = a.prob[nd.prob];
+  const int dcap = P.dcap;
+  const int c0 = st.go ? 0 : st.c0;
+  const int nc = P.d - c0;
+  const int m = st.m[side], r = st.rank[side];
+  const int32_t* J = a.ipool + nd.J[side];
+  double* RR = dp(a, nd.RR[side]);
+  double* Xr = a.wsA + nd.ws;  // (m - r) x nc, column-major, ld = mcap
+  int r1 = 0;
+  const double *X1 = nullptr, *X2 = nullptr;
+  if (!nd.leaf) {
+    r1 = a.st[nd.left].rank[side];
+    X1 = cdp(a, a.desc[nd.left].RR[side]);
+    X2 = cdp(a, a.desc[nd.right].RR[side]);
+  }
+  for (int64_t idx = threadIdx.x; idx < (int64_t)m * nc; idx += NB) {
+    const int c = (int)(idx % nc), i = (int)(idx / nc);
+    const int row = J[i];
+    double v;
+    if (nd.leaf) v = P.R[(int64_t)(c0 + c) * P.ldr + nd.lo + row];
+    else v = row < r1 ? X1[(int64_t)row * dcap + c0 + c] : X2[(int64_t)(row - r1) * dcap + c0 + c];
+    if (i < r) RR[(int64_t)i * dcap + c0 + c] = v;
+    else Xr[(int64_t)c * nd.mcap + (i - r)] = v;
+  }
+  if (st.go) {
+    int64_t* I = a.lpool + nd.I[side];
+    const int64_t* I1 = nd.leaf ? nullptr : a.lpool + a.desc[nd.left].I[side];
+    const int64_t* I2 = nd.leaf ? nullptr : a.lpool + a.desc[nd.right].I[side];
+    for (int k = threadIdx.x; k < r; k += NB) {
+      const int row = J[k];
+      I[k] = nd.leaf ? (int64_t)nd.lo + row : (row < r1 ? I1[row] : I2[row - r1]);
+    }
+  }
+  if (threadIdx.x == 0) {
+    GemmTask k;
+    k.A = cdp(a, nd.E[side]); k.a_rs = 1; k.a_cs = nd.rcap;
+    k.B = Xr; k.b_rs = 1; k.b_cs = nd.mcap;
+    k.C = RR + c0; k.c_rs = dcap; k.c_cs = 1;
+    k.M = r; k.N = nc; k.K = m - r; k.pad = 0;
+    k.alpha = 1.0; k.beta = 1.0;
+    *T0 = k;
+  }
+}
+
+void launch_reduce(const LevelArgs& a, int side, int32_t mcap_max, int32_t rcap_max,
+                   int32_t ncap, hipStream_t s) {
+  (void)mcap_max;
+  if (a.count <= 0) return;
+  hipLaunchKernelGGL(k_red_gather, dim3(a.count), dim3(NB), 0, s, a, side);
+  launch_gemm(a.tasks, a.count, rcap_max, ncap, s);
+}
+
+// ------------------------------------------------------------------ finalize
+__global__ void k_finalize(LevelArgs a) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= a.count) return;
+  const int g = a.nodes[t];
+  NodeState& st = a.st[g];
+  const NodeDesc& nd = a.desc[g];
+  const ProbDev& P = a.prob[nd.prob];
+  if (nd.parent < 0) {
+    if (st.go) st.state = COMPRESSED;
+    return;
+  }
+  if (!st.active) return;
+  if (st.go) st.state = COMPRESSED;
+  else if (st.state != COMPRESSED) st.state = PARTIAL;
+  if (P.symmetric) {
+    st.rank[1] = st.rank[0];
+    st.passed[1] = st.passed[0];
+    st.q[1] = st.q[0];
+    st.rho[1] = st.rho[0];
+  }
+}
+
+void launch_finalize(const LevelArgs& a, hipStream_t s) {
+  if (a.count <= 0) return;
+  hipLaunchKernelGGL(k_finalize, dim3((a.count + 127) / 128), dim3(128), 0, s, a);
+}
+
+}  // namespace hss

@@ -1,0 +1,215 @@
+// Matrix-free random sampling S = A_hat R (and S^c = A_hat^T R) for the
+// adaptive HSS compression (Sec. 2.2, eq. sample_off_diag: the samples of
+// every Hankel block derive from S^r = A R and S^c = A^* R).
+//
+// A is never stored: each lane generates the entries it feeds to the
+// matrix core.  One workgroup = 8 waves computes a 128 x 64 tile of S
+// (each wave 16 rows x 64 columns = four 16x16 FP64 MFMA blocks), so every
+// generated entry is reused for 64 columns of R.  R tiles are staged in
+// LDS and shared by the 8 waves.  The K dimension (n) is split over
+// blockIdx.z when the tile grid alone would not fill the 256 CUs; split
+// partial sums are reduced in fixed order, so results are deterministic.
+#include <algorithm>
+
+#include "gen.h"
+
+namespace hss {
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+constexpr int SM_ROWS = 128;   // rows of S per workgroup
+constexpr int SM_COLS = 64;    // columns of S per workgroup
+constexpr int SM_BK = 32;      // K rows of R staged per LDS tile
+constexpr int SM_LDP = SM_COLS + 2;
+
+__global__ void k_toeplitz_table(double* __restrict__ t, int64_t n, double h) {
+  int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  if (k == 0) {
+    t[0] = kPi * kPi / (6.0 * h * h);
+  } else {
+    const double kk = (double)k;
+    const double sign = (k & 1) ? -1.0 : 1.0;
+    t[k] = sign / (kk * kk * h * h);
+  }
+}
+
+void launch_toeplitz_table(double* t, int64_t n, double h, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_toeplitz_table, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, t, n, h);
+}
+
+__global__ void k_permute_points(const double* __restrict__ pts, const int64_t* __restrict__ perm,
+                                 int64_t n, double* __restrict__ out) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t p = perm[i];
+  out[3 * i] = pts[3 * p];
+  out[3 * i + 1] = pts[3 * p + 1];
+  out[3 * i + 2] = pts[3 * p + 2];
+}
+
+void launch_permute_points(const double* pts, const int64_t* perm, int64_t n, double* out,
+                           hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_permute_points, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, pts,
+                     perm, n, out);
+}
+
+template <int FAM>
+__device__ __forceinline__ double entry_t(const GenDev& g, int64_t i, int64_t j) {
+  if constexpr (FAM == HSS_FAM_TOEPLITZ) return toeplitz_entry(g, i, j);
+  else if constexpr (FAM == HSS_FAM_LAPLACE) return laplace_entry(g, i, j);
+  else if constexpr (FAM == HSS_FAM_GAUSS) return gauss_entry(g, i, j);
+  else return dense_entry(g, i, j);
+}
+
+// out(row, col) for rows [0,n), cols [0, ncols): either S directly
+// (nsplit == 1, column-major with lds) or the split-K partial buffer
+// P[z][row][col] with row length ncp = gridDim.y * SM_COLS.
+template <int FAM, int TRANS>
+__global__ __launch_bounds__(512) void k_sample_f64(GenDev g, const double* __restrict__ R,
+                                                    int64_t ldr, double* __restrict__ out,
+                                                    int64_t lds, int32_t ncols, int64_t kchunk,
+                                                    int32_t nsplit) {
+  __shared__ double Rs[SM_BK][SM_LDP];
+  const int64_t n = g.n;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t row0 = (int64_t)blockIdx.x * SM_ROWS + wave * 16;
+  const int col0 = blockIdx.y * SM_COLS;
+  const int64_t kb = (int64_t)blockIdx.z * kchunk;
+  const int64_t ke = min(n, kb + kchunk);
+  const int64_t my_row = row0 + (lane & 15);
+  const bool row_ok = my_row < n;
+  const int kq = lane >> 4;
+
+  dbl4 acc[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) acc[c] = dbl4{0.0, 0.0, 0.0, 0.0};
+
+  for (int64_t kt = kb; kt < ke; kt += SM_BK) {
+    // stage R(kt:kt+BK, col0:col0+64) -> Rs[k][c]
+    for (int idx = threadIdx.x; idx < SM_BK * SM_COLS; idx += 512) {
+      const int r = idx % SM_BK;
+      const int c = idx / SM_BK;
+      const int64_t gk = kt + r;
+      const int gc = col0 + c;
+      Rs[r][c] = (gk < ke && gc < ncols) ? R[(int64_t)gc * ldr + gk] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 2
+    for (int kk = 0; kk < SM_BK; kk += 4) {
+      const int64_t j = kt + kk + kq;
+      double a = 0.0;
+      if (row_ok && j < ke) a = TRANS ? entry_t<FAM>(g, j, my_row) : entry_t<FAM>(g, my_row, j);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const double b = Rs[kk + kq][c * 16 + (lane & 15)];
+        acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[c], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+  // D[i][j]: i = 4*(lane/16) + v, j = lane % 16
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int gc = col0 + c * 16 + (lane & 15);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t gr = row0 + 4 * kq + v;
+      if (gr >= n || gc >= ncols) continue;
+      if (nsplit == 1) {
+        out[(int64_t)gc * lds + gr] = acc[c][v];
+      } else {
+        const int64_t ncp = (int64_t)gridDim.y * SM_COLS;
+        out[((int64_t)blockIdx.z * n + gr) * ncp + gc] = acc[c][v];
+      }
+    }
+  }
+}
+
+__global__ void k_splitk_reduce(const double* __restrict__ P, int64_t n, int32_t ncols, int64_t ncp,
+                                int32_t nsplit, double* __restrict__ S, int64_t lds) {
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= n * ncols) return;
+  const int64_t row = idx % n;
+  const int64_t col = idx / n;
+  double s = 0.0;
+  for (int z = 0; z < nsplit; ++z) s += P[((int64_t)z * n + row) * ncp + col];
+  S[col * lds + row] = s;
+}
+
+int sample_splits(int64_t n, int32_t ncols) {
+  const int64_t gx = (n + SM_ROWS - 1) / SM_ROWS;
+  const int64_t gy = (ncols + SM_COLS - 1) / SM_COLS;
+  const int64_t tiles = gx * gy;
+  const int64_t target = 2048;
+  int64_t z = (target + tiles - 1) / tiles;
+  const int64_t zmax = (n + 255) / 256;   // at least 256 K rows per split
+  if (z > zmax) z = zmax;
+  if (z < 1) z = 1;
+  return (int)z;
+}
+
+// Partial-sum capacity covering every column count up to ncols_max (the split
+// count is not monotone in the column count, so take the maximum).
+size_t sample_partial_elems(int64_t n, int32_t ncols_max) {
+  size_t best = 0;
+  const int64_t gymax = (ncols_max + SM_COLS - 1) / SM_COLS;
+  for (int64_t gy = 1; gy <= gymax; ++gy) {
+    const int z = sample_splits(n, (int32_t)(gy * SM_COLS));
+    if (z == 1) continue;
+    best = std::max(best, (size_t)z * (size_t)n * (size_t)(gy * SM_COLS));
+  }
+  return best;
+}
+
+template <int FAM>
+static void launch_fam(const GenDev& g, int transpose, const double* R, int64_t ldr, double* out,
+                       int64_t lds, int32_t ncols, int64_t kchunk, int nsplit, dim3 grid,
+                       hipStream_t s) {
+  if (transpose)
+    hipLaunchKernelGGL((k_sample_f64<FAM, 1>), grid, dim3(512), 0, s, g, R, ldr, out, lds, ncols,
+                       kchunk, nsplit);
+  else
+    hipLaunchKernelGGL((k_sample_f64<FAM, 0>), grid, dim3(512), 0, s, g, R, ldr, out, lds, ncols,
+                       kchunk, nsplit);
+}
+
+void launch_sample_f32(const GenDev& g, int32_t transpose, int32_t bf16x3, const double* R,
+                       int64_t ldr, double* S, int64_t lds, int32_t ncols, double* partial,
+                       hipStream_t s);
+
+void launch_sample(const GenDev& g, int32_t transpose, int32_t precision, const double* R,
+                   int64_t ldr, double* S, int64_t lds, int32_t ncols, double* partial,
+                   hipStream_t s) {
+  if (ncols <= 0 || g.n <= 0) return;
+  if (precision != HSS_SAMPLE_FP64) {
+    launch_sample_f32(g, transpose, precision == HSS_SAMPLE_BF16X3, R, ldr, S, lds, ncols,
+                      partial, s);
+    return;
+  }
+  const int64_t n = g.n;
+  const int nsplit = sample_splits(n, ncols);
+  int64_t kchunk = (n + nsplit - 1) / nsplit;
+  kchunk = (kchunk + SM_BK - 1) / SM_BK * SM_BK;
+  const int nz = (int)((n + kchunk - 1) / kchunk);
+  dim3 grid((unsigned)((n + SM_ROWS - 1) / SM_ROWS), (unsigned)((ncols + SM_COLS - 1) / SM_COLS),
+            (unsigned)nz);
+  double* out = nz == 1 ? S : partial;
+  switch (g.family) {
+    case HSS_FAM_TOEPLITZ: launch_fam<HSS_FAM_TOEPLITZ>(g, transpose, R, ldr, out, lds, ncols, kchunk, nz, grid, s); break;
+    case HSS_FAM_LAPLACE: launch_fam<HSS_FAM_LAPLACE>(g, transpose, R, ldr, out, lds, ncols, kchunk, nz, grid, s); break;
+    case HSS_FAM_GAUSS: launch_fam<HSS_FAM_GAUSS>(g, transpose, R, ldr, out, lds, ncols, kchunk, nz, grid, s); break;
+    default: launch_fam<HSS_FAM_DENSE>(g, transpose, R, ldr, out, lds, ncols, kchunk, nz, grid, s); break;
+  }
+  if (nz > 1) {
+    const int64_t ncp = (int64_t)grid.y * SM_COLS;
+    const int64_t tot = n * ncols;
+    hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
+                       partial, n, ncols, ncp, nz, S, lds);
+  }
+}
+
+}  // namespace hss

@@ -1,0 +1,383 @@
+"""Python binding of libhss (argument marshalling only).
+
+Every computation happens in libhss.so (HIP kernels for gfx950).  PyTorch
+provides device memory and the stream; this module converts tensors to
+pointers and strides, calls the C ABI of include/hss.h and turns status
+codes into exceptions.  There is no fallback: if the library or a GPU is
+missing, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libhss.so")
+
+FAMILY = {"toeplitz": 0, "laplace": 1, "gauss": 2, "dense": 3}
+STRATEGY = {"dbl_fnorm": 0, "inc_fnorm": 1, "dbl_hmt": 2}
+PRECISION = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+TREE_METHOD = {"bisect": 0, "rcb": 1, "kd": 2}
+NODE = {"D": 0, "B12": 1, "B21": 2, "JR": 3, "JC": 4, "ER": 5, "EC": 6, "IR": 7, "IC": 8}
+
+OK, NOT_CONVERGED, TOL_FLOOR = 0, 1, 2
+
+
+class HSSError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("libhss status %d: %s" % (code, msg))
+        self.code = code
+
+
+class _Gen(C.Structure):
+    _fields_ = [("family", C.c_int32), ("symmetric", C.c_int32), ("n", C.c_int64),
+                ("h", C.c_double), ("sigma", C.c_double), ("diag", C.c_double),
+                ("points", C.c_void_p), ("dense", C.c_void_p), ("ld", C.c_int64)]
+
+
+class _Tree(C.Structure):
+    _fields_ = [("n", C.c_int64), ("num_nodes", C.c_int32), ("perm", C.POINTER(C.c_int64)),
+                ("lo", C.POINTER(C.c_int32)), ("hi", C.POINTER(C.c_int32)),
+                ("left", C.POINTER(C.c_int32)), ("right", C.POINTER(C.c_int32)),
+                ("parent", C.POINTER(C.c_int32)), ("level", C.POINTER(C.c_int32))]
+
+
+class _Opt(C.Structure):
+    _fields_ = [("rtol", C.c_double), ("atol", C.c_double), ("eta", C.c_double),
+                ("strategy", C.c_int32), ("d0", C.c_int32), ("delta_d", C.c_int32),
+                ("oversample_p", C.c_int32), ("d_max", C.c_int32), ("sample_precision", C.c_int32),
+                ("R", C.c_void_p), ("ldr", C.c_int64), ("ncols_R", C.c_int32),
+                ("reserved", C.c_int32), ("stream", C.c_void_p)]
+
+
+class _Info(C.Structure):
+    _fields_ = [("n", C.c_int64), ("num_nodes", C.c_int32), ("rounds", C.c_int32),
+                ("d_final", C.c_int32), ("hss_rank", C.c_int32), ("status", C.c_int32),
+                ("symmetric", C.c_int32), ("sample_ms", C.c_double), ("total_ms", C.c_double),
+                ("sample_flops", C.c_double)]
+
+
+class _NodeInfo(C.Structure):
+    _fields_ = [(k, C.c_int32) for k in ("state", "is_leaf", "lo", "hi", "m_r", "m_c", "rank_r",
+                                          "rank_c", "b_rows", "b_cols")]
+
+
+_lib = None
+
+EXPORTS = ["hss_tree_build", "hss_tree_free", "hss_compress", "hss_compress_batched", "hss_destroy",
+           "hss_matvec", "hss_rel_error", "hss_get_info", "hss_get_node_info", "hss_copy_node",
+           "hss_sample", "hss_extract", "hss_interpolative_batched", "hss_last_error", "hss_version"]
+
+
+def lib():
+    """Load libhss.so (after torch, so both share one HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    import torch  # noqa: F401  (loads the HIP runtime torch was built with)
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libhss.so is not built; run `python -m paper_1810_04125_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    L.hss_last_error.restype = C.c_char_p
+    L.hss_version.restype = C.c_char_p
+    L.hss_tree_build.argtypes = [i64, vp, i32, i32, C.POINTER(C.POINTER(_Tree))]
+    L.hss_tree_free.argtypes = [C.POINTER(_Tree)]
+    L.hss_tree_free.restype = None
+    L.hss_compress.argtypes = [C.POINTER(_Gen), C.POINTER(_Tree), C.POINTER(_Opt), C.POINTER(vp)]
+    L.hss_compress_batched.argtypes = [i32, C.POINTER(_Gen), C.POINTER(C.POINTER(_Tree)),
+                                       C.POINTER(_Opt), C.POINTER(vp)]
+    L.hss_destroy.argtypes = [vp]
+    L.hss_destroy.restype = None
+    L.hss_matvec.argtypes = [vp, i32, vp, i64, vp, i64, vp]
+    L.hss_rel_error.argtypes = [vp, C.POINTER(_Gen), C.POINTER(dbl)]
+    L.hss_get_info.argtypes = [vp, C.POINTER(_Info)]
+    L.hss_get_node_info.argtypes = [vp, i32, C.POINTER(_NodeInfo)]
+    L.hss_copy_node.argtypes = [vp, i32, i32, vp, C.c_size_t]
+    L.hss_sample.argtypes = [C.POINTER(_Gen), vp, i32, vp, i64, vp, i64, i32, i32, vp]
+    L.hss_extract.argtypes = [C.POINTER(_Gen), vp, i32, vp, i32, vp, vp, i64, vp]
+    L.hss_interpolative_batched.argtypes = [i32, vp, vp, vp, vp, vp, dbl, dbl, vp, vp, vp, vp, vp]
+    for name in EXPORTS:
+        if name not in ("hss_tree_free", "hss_destroy", "hss_last_error", "hss_version"):
+            getattr(L, name).restype = C.c_int32
+    _lib = L
+    return L
+
+
+def _check(code):
+    if code < 0:
+        raise HSSError(code, lib().hss_last_error().decode())
+    return code
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _colmajor(t, name):
+    """(rows, cols) float64 CUDA tensor with unit row stride -> leading dimension."""
+    import torch
+    if t.dtype != torch.float64 or not t.is_cuda:
+        raise TypeError("%s must be a float64 CUDA tensor" % name)
+    if t.dim() != 2 or t.stride(0) != 1 or t.stride(1) < max(1, t.shape[0]):
+        raise ValueError("%s must be column-major (use X.t().contiguous().t())" % name)
+    return t.stride(1)
+
+
+def colmajor(x):
+    """Copy a 2-D tensor into column-major layout."""
+    return x.t().contiguous().t()
+
+
+# --------------------------------------------------------------------------- tree
+class Tree:
+    """Cluster tree built by libhss on the host (hss_tree_build)."""
+
+    def __init__(self, n, leaf_size, points=None, method="bisect"):
+        L = lib()
+        pts = None
+        if points is not None:
+            pts = np.ascontiguousarray(points, dtype=np.float64)
+            if pts.shape != (n, 3):
+                raise ValueError("points must be (n, 3)")
+        out = C.POINTER(_Tree)()
+        _check(L.hss_tree_build(n, pts.ctypes.data if pts is not None else None, leaf_size,
+                                TREE_METHOD[method], C.byref(out)))
+        self._t = out
+        t = out.contents
+        nn = t.num_nodes
+        self.n, self.num_nodes = t.n, nn
+        self.perm = np.ctypeslib.as_array(t.perm, shape=(n,)).copy()
+        self.lo = np.ctypeslib.as_array(t.lo, shape=(nn,)).copy()
+        self.hi = np.ctypeslib.as_array(t.hi, shape=(nn,)).copy()
+        self.left = np.ctypeslib.as_array(t.left, shape=(nn,)).copy()
+        self.right = np.ctypeslib.as_array(t.right, shape=(nn,)).copy()
+        self.parent = np.ctypeslib.as_array(t.parent, shape=(nn,)).copy()
+        self.level = np.ctypeslib.as_array(t.level, shape=(nn,)).copy()
+
+    def __del__(self):
+        if getattr(self, "_t", None) is not None and _lib is not None:
+            _lib.hss_tree_free(self._t)
+            self._t = None
+
+
+# --------------------------------------------------------------------------- generator
+@dataclass
+class Generator:
+    family: str
+    n: int
+    h: float = 0.0
+    sigma: float = 0.0
+    diag: float = 0.0
+    points: object = None    # (n, 3) float64 CUDA tensor, original order
+    dense: object = None     # (n, n) float64 CUDA tensor, column-major
+    symmetric: bool = True
+
+    def _c(self):
+        g = _Gen()
+        g.family = FAMILY[self.family]
+        g.symmetric = int(self.symmetric)
+        g.n = self.n
+        g.h, g.sigma, g.diag = self.h, self.sigma, self.diag
+        g.points = self.points.data_ptr() if self.points is not None else None
+        if self.dense is not None:
+            g.ld = _colmajor(self.dense, "dense")
+            g.dense = self.dense.data_ptr()
+        return g
+
+
+def toeplitz(n, h):
+    return Generator("toeplitz", n, h=h)
+
+
+def laplace(points, diag=1.0):
+    return Generator("laplace", points.shape[0], diag=diag, points=points.contiguous())
+
+
+def gauss(points, sigma=0.5, diag=1e-2):
+    return Generator("gauss", points.shape[0], sigma=sigma, diag=diag, points=points.contiguous())
+
+
+def dense(A, symmetric=False):
+    return Generator("dense", A.shape[0], dense=colmajor(A), symmetric=symmetric)
+
+
+# --------------------------------------------------------------------------- compression
+class HSSMatrix:
+    def __init__(self, handle, keep):
+        self._h = C.c_void_p(handle)
+        self._keep = keep
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.hss_destroy(self._h)
+            self._h = None
+
+    def info(self) -> dict:
+        inf = _Info()
+        _check(lib().hss_get_info(self._h, C.byref(inf)))
+        return {k: getattr(inf, k) for k, _ in _Info._fields_}
+
+    def node_info(self, node) -> dict:
+        ni = _NodeInfo()
+        _check(lib().hss_get_node_info(self._h, node, C.byref(ni)))
+        return {k: getattr(ni, k) for k, _ in _NodeInfo._fields_}
+
+    def node(self, node, what):
+        """Host copy of a node generator (see hss_copy_node for the layouts)."""
+        ni = self.node_info(node)
+        if what == "D":
+            m = ni["hi"] - ni["lo"]
+            out = np.empty((m, m), order="F")
+        elif what == "B12":
+            out = np.empty((ni["b_rows"], ni["b_cols"]), order="F")
+        elif what == "B21":
+            # B21 is rank_r(right) x rank_c(left): ask the children
+            raise ValueError("use node_b21()")
+        elif what in ("JR", "JC"):
+            out = np.empty(ni["m_r"] if what == "JR" else ni["m_c"], dtype=np.int32)
+        elif what in ("ER", "EC"):
+            r = ni["rank_r"] if what == "ER" else ni["rank_c"]
+            m = ni["m_r"] if what == "ER" else ni["m_c"]
+            out = np.empty((r, m - r), order="F")
+        elif what in ("IR", "IC"):
+            out = np.empty(ni["rank_r"] if what == "IR" else ni["rank_c"], dtype=np.int64)
+        else:
+            raise ValueError(what)
+        if out.size:
+            _check(lib().hss_copy_node(self._h, node, NODE[what], out.ctypes.data, out.nbytes))
+        return out
+
+    def node_b21(self, node, left, right):
+        rr = self.node_info(right)["rank_r"]
+        cl = self.node_info(left)["rank_c"]
+        out = np.empty((rr, cl), order="F")
+        if out.size:
+            _check(lib().hss_copy_node(self._h, node, NODE["B21"], out.ctypes.data, out.nbytes))
+        return out
+
+    def matvec(self, X):
+        """Y = H X (original ordering); X: (n,) or (n, k) float64 CUDA tensor."""
+        import torch
+        vec = X.dim() == 1
+        Xc = colmajor(X[:, None] if vec else X)
+        Y = torch.empty_like(Xc)
+        Y = colmajor(Y)
+        _check(lib().hss_matvec(self._h, Xc.shape[1], _ptr(Xc), _colmajor(Xc, "X"), _ptr(Y),
+                                _colmajor(Y, "Y"), _stream()))
+        return Y[:, 0] if vec else Y
+
+    def rel_error(self) -> float:
+        e = C.c_double()
+        _check(lib().hss_rel_error(self._h, None, C.byref(e)))
+        return e.value
+
+
+def _opts(R, rtol, atol, eta, strategy, d0, delta_d, p, d_max, precision):
+    ldr = _colmajor(R, "R")
+    o = _Opt()
+    o.rtol, o.atol, o.eta = rtol, atol, eta
+    o.strategy = STRATEGY[strategy]
+    o.d0, o.delta_d, o.oversample_p = d0, delta_d, p
+    o.d_max = d_max if d_max is not None else R.shape[1]
+    o.sample_precision = PRECISION[precision]
+    o.R = R.data_ptr()
+    o.ldr = ldr
+    o.ncols_R = R.shape[1]
+    o.stream = _stream()
+    return o
+
+
+def compress(gen: Generator, tree: Tree, R, rtol=1e-6, atol=1e-12, eta=1.0, strategy="dbl_fnorm",
+             d0=64, delta_d=64, p=10, d_max=None, precision="fp64"):
+    """Adaptive HSS compression (hss_compress).  R: (n, d_cap) float64 CUDA tensor,
+    column-major, rows in permuted order.  Returns (HSSMatrix, status)."""
+    g = gen._c()
+    o = _opts(R, rtol, atol, eta, strategy, d0, delta_d, p, d_max, precision)
+    h = C.c_void_p()
+    st = _check(lib().hss_compress(C.byref(g), tree._t, C.byref(o), C.byref(h)))
+    return HSSMatrix(h.value, (gen, tree, R)), st
+
+
+def compress_batched(gens, trees, Rs, **kw):
+    """Independent compressions in one job (hss_compress_batched)."""
+    k = len(gens)
+    G = (_Gen * k)(*[g._c() for g in gens])
+    T = (C.POINTER(_Tree) * k)(*[t._t for t in trees])
+    O = (_Opt * k)(*[_opts(R, kw.get("rtol", 1e-6), kw.get("atol", 1e-12), kw.get("eta", 1.0),
+                           kw.get("strategy", "dbl_fnorm"), kw.get("d0", 64), kw.get("delta_d", 64),
+                           kw.get("p", 10), kw.get("d_max"), kw.get("precision", "fp64"))
+                     for R in Rs])
+    H = (C.c_void_p * k)()
+    st = _check(lib().hss_compress_batched(k, G, T, O, H))
+    return [HSSMatrix(H[i], (gens[i], trees[i], Rs[i])) for i in range(k)], st
+
+
+# --------------------------------------------------------------------------- single steps
+def sample(gen: Generator, perm, R, transpose=False, precision="fp64"):
+    """S = op(A_hat) R (hss_sample); perm: int64 CUDA tensor; R (n, k) column-major."""
+    import torch
+    ldr = _colmajor(R, "R")
+    S = colmajor(torch.empty((R.shape[0], R.shape[1]), dtype=torch.float64, device=R.device))
+    g = gen._c()
+    _check(lib().hss_sample(C.byref(g), _ptr(perm), R.shape[1], _ptr(R), ldr, _ptr(S),
+                            _colmajor(S, "S"), int(transpose), PRECISION[precision], _stream()))
+    return S
+
+
+def extract(gen: Generator, perm, I, J):
+    """A_hat(I, J) (hss_extract); I, J int64 CUDA tensors of permuted indices."""
+    import torch
+    out = colmajor(torch.empty((len(I), len(J)), dtype=torch.float64, device=perm.device))
+    g = gen._c()
+    ldo = max(1, len(I))
+    _check(lib().hss_extract(C.byref(g), _ptr(perm), len(I), _ptr(I), len(J), _ptr(J), _ptr(out),
+                             ldo, _stream()))
+    return out
+
+
+def interpolative_batched(mats, eps_r, eps_a=0.0):
+    """Batched ID (hss_interpolative_batched) of host matrices S_k (m_k x d_k).
+
+    Returns a list of (rank, piv, E) with piv the pivot order followed by the
+    other rows ascending and E = R1^{-1} R2 (rank x (m_k - rank))."""
+    import torch
+    dev = torch.device("cuda")
+    k = len(mats)
+    m = np.array([s.shape[0] for s in mats], dtype=np.int32)
+    d = np.array([s.shape[1] for s in mats], dtype=np.int32)
+    ld = np.maximum(d, 1).astype(np.int64)
+    s_off = np.zeros(k, np.int64)
+    p_off = np.zeros(k, np.int64)
+    e_off = np.zeros(k, np.int64)
+    so = po = eo = 0
+    for i in range(k):
+        s_off[i], p_off[i], e_off[i] = so, po, eo
+        so += m[i] * ld[i]
+        po += m[i]
+        eo += m[i] * m[i]
+    flat = np.zeros(max(so, 1))
+    for i, s in enumerate(mats):
+        flat[s_off[i]:s_off[i] + m[i] * ld[i]] = np.ascontiguousarray(s, dtype=np.float64).ravel()
+    S = torch.from_numpy(flat).to(dev)
+    piv = torch.zeros(max(po, 1), dtype=torch.int32, device=dev)
+    E = torch.zeros(max(eo, 1), dtype=torch.float64, device=dev)
+    rank = np.zeros(k, np.int32)
+    _check(lib().hss_interpolative_batched(k, m.ctypes.data, d.ctypes.data, ld.ctypes.data, _ptr(S),
+                                           s_off.ctypes.data, eps_r, eps_a, _ptr(piv), p_off.ctypes.data,
+                                           _ptr(E), e_off.ctypes.data, rank.ctypes.data))
+    pv, Ev = piv.cpu().numpy(), E.cpu().numpy()
+    out = []
+    for i in range(k):
+        r = int(rank[i])
+        Ei = Ev[e_off[i]:e_off[i] + m[i] * m[i]].reshape((m[i], m[i]), order="F")[:r, :m[i] - r]
+        out.append((r, pv[p_off[i]:p_off[i] + m[i]].copy(), Ei.copy()))
+    return out

@@ -1,0 +1,46 @@
+"""C-ABI library: loads, exports every declared symbol, host-side logic (CPU only)."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle.tree import build_tree
+from paper_1810_04125_amd import hss, inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "hss.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(hss_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = hss.lib()
+    names = _declared()
+    assert "hss_compress" in names and "hss_matvec" in names
+    for name in names:
+        assert hasattr(L, name), name
+    assert sorted(hss.EXPORTS) == names
+
+
+@pytest.mark.parametrize("method,n,leaf,seed", [("bisect", 1000, 64, 0), ("rcb", 4099, 128, 1),
+                                                ("kd", 3000, 100, 2), ("rcb", 257, 128, 3),
+                                                ("bisect", 1, 8, 0), ("kd", 65536, 256, 2)])
+def test_tree_bit_exact_with_oracle(method, n, leaf, seed):
+    pts = inputs.sphere_points(n, seed) if method == "rcb" else inputs.cube_points(n, seed)
+    a = hss.Tree(n, leaf, None if method == "bisect" else pts, method)
+    b = build_tree(n, leaf, None if method == "bisect" else pts, method)
+    for f in ("perm", "lo", "hi", "left", "right", "parent", "level"):
+        assert np.array_equal(getattr(a, f), getattr(b, f)), f
+
+
+def test_tree_rejects_bad_input():
+    with pytest.raises(hss.HSSError):
+        hss.Tree(10, 0)
+    bad = inputs.cube_points(10, 0)
+    bad[3, 1] = np.nan
+    with pytest.raises(hss.HSSError):
+        hss.Tree(10, 4, bad, "rcb")
