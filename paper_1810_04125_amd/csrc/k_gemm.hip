@@ -68,7 +68,8 @@ __global__ __launch_bounds__(256) void k_gemm_grouped(const GemmTask* __restrict
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int64_t gi = i0 + wr + a * 16 + 4 * (lane >> 4) + v;
+        // FP64 16x16x4 result layout: row 4*v + lane/16, column lane % 16
+        const int64_t gi = i0 + wr + a * 16 + 4 * v + (lane >> 4);
         const int64_t gj = j0 + wc + b * 16 + (lane & 15);
         if (gi >= t.M || gj >= t.N) continue;
         double* c = t.C + gi * t.c_rs + gj * t.c_cs;

@@ -111,13 +111,13 @@ __global__ __launch_bounds__(512) void k_sample_f64(GenDev g, const double* __re
     }
     __syncthreads();
   }
-  // D[i][j]: i = 4*(lane/16) + v, j = lane % 16
+  // FP64 16x16x4 result layout: D[i][j] with i = 4*v + lane/16, j = lane % 16
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
     const int gc = col0 + c * 16 + (lane & 15);
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int64_t gr = row0 + 4 * kq + v;
+      const int64_t gr = row0 + 4 * v + kq;
       if (gr >= n || gc >= ncols) continue;
       if (nsplit == 1) {
         out[(int64_t)gc * lds + gr] = acc[c][v];

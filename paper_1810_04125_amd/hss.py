@@ -127,7 +127,14 @@ def _colmajor(t, name):
     import torch
     if t.dtype != torch.float64 or not t.is_cuda:
         raise TypeError("%s must be a float64 CUDA tensor" % name)
-    if t.dim() != 2 or t.stride(0) != 1 or t.stride(1) < max(1, t.shape[0]):
+    if t.dim() != 2:
+        raise ValueError("%s must be 2-D" % name)
+    rows, cols = t.shape
+    if cols <= 1:   # a single column: only the row stride matters
+        if rows > 1 and t.stride(0) != 1:
+            raise ValueError("%s must be column-major (use X.t().contiguous().t())" % name)
+        return max(1, rows)
+    if (rows > 1 and t.stride(0) != 1) or t.stride(1) < max(1, rows):
         raise ValueError("%s must be column-major (use X.t().contiguous().t())" % name)
     return t.stride(1)
 
