@@ -15,8 +15,13 @@ Readings of points the paper leaves open (the HIP path uses the same):
   * tolerances are scaled per node as eta*eps/level(tau) (Sec. 2.2 text
     after the compression-stages figure; Alg. 1 and 3); eta is a global
     safety factor, 1 = the paper's literal rule;
-  * new columns are the b most recently appended; an UNTOUCHED node uses
-    all d columns (Alg. 3 column ranges);
+  * new columns are the b most recently appended; an UNTOUCHED node
+    computes all d columns (Alg. 3 column ranges);
+  * a node that meets the stopping test for the first time, with several
+    sampled blocks already available, runs Alg. 5 over those blocks in the
+    order they were sampled (block widths = the sampling schedule) and
+    stops at the first pass, as if it had been tested since the first
+    round; an already tested node tests only the newest block;
   * the absolute F-norm test divides by sqrt(b), b = width of the new
     block (E||S||_F^2 = b ||A||_F^2, Sec. 3.4);
   * a side whose local sample has m <= d rows passes (the samples span
@@ -228,6 +233,7 @@ class _Compressor:
         self.d_max = min(d_max if d_max is not None else self.N, R.shape[1])
         self.nodes = [Node() for _ in range(tree.num_nodes)]
         self.force = False
+        self.sched = []   # d after every sampling step (the block edges)
 
     # -- global samples --------------------------------------------------
     def append_columns(self, b: int):
@@ -237,6 +243,7 @@ class _Compressor:
         self.Sr = np.hstack([self.Sr, Sr])
         self.Sc = np.hstack([self.Sc, Sc])
         self.d += b
+        self.sched.append(self.d)
 
     def eps(self, t: int):
         lev = int(self.tree.level[t])
@@ -309,9 +316,20 @@ class _Compressor:
                 nd.idr, nd.idc = idr, idc
                 return True
             return False
-        pr = fnorm_test(nd.tr, nd.Sr[:, cols], self.d, er, ea)
-        pc = fnorm_test(nd.tc, nd.Sc[:, cols], self.d, er, ea)
-        if (pr and pc) or self.force:
+        if nd.state == UNTOUCHED:
+            edges = [0] + self.sched
+            blocks = [(edges[i], edges[i + 1]) for i in range(len(self.sched))]
+        else:
+            blocks = [(self.d - len(cols), self.d)]
+        ok = []
+        for S, st in ((nd.Sr, nd.tr), (nd.Sc, nd.tc)):
+            passed = st.passed
+            for c0, c1 in blocks:
+                if passed or c1 <= c0:
+                    break
+                passed = fnorm_test(st, S[:, c0:c1], c1, er, ea)
+            ok.append(passed)
+        if all(ok) or self.force:
             nd.idr = interpolative(nd.Sr, er, ea)
             nd.idc = interpolative(nd.Sc, er, ea)
             return True
@@ -361,7 +379,6 @@ class _Compressor:
         self.append_columns(d0)
         b = d0
         rounds = 0
-        schedule = [self.d]
         root = 0
         while True:
             rounds += 1
@@ -377,8 +394,7 @@ class _Compressor:
             b = self.d if self.strategy.startswith("dbl") else self.delta_d
             b = min(b, self.d_max - self.d)
             self.append_columns(b)
-            schedule.append(self.d)
-        return HSS(self.tree, self.nodes, self.d, rounds, schedule,
+        return HSS(self.tree, self.nodes, self.d, rounds, list(self.sched),
                    not self.force, self.eta, self.strategy)
 
 

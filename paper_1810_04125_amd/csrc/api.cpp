@@ -395,30 +395,52 @@ hss_status hss_interpolative_batched(int32_t count, const int32_t* m, const int3
     if (count == 0) return HSS_OK;
     if (!(eps_r >= 0.0) || !(eps_a >= 0.0)) throw Error(HSS_ERR_INVALID_ARG, "need eps >= 0");
     int32_t mmax = 1, dmax = 1;
-    std::vector<int64_t> woff(count);
-    int64_t wtot = 0;
+    std::vector<int64_t> woff(count), soff(count);
+    int64_t wtot = 0, stot = 0;
     for (int32_t k = 0; k < count; ++k) {
       if (m[k] < 0 || d[k] < 0 || ld[k] < std::max(d[k], 1)) throw Error(HSS_ERR_INVALID_ARG, "bad matrix shape");
       mmax = std::max(mmax, m[k]);
       dmax = std::max(dmax, d[k]);
       woff[k] = wtot;
-      wtot += (int64_t)m[k] * ld[k];
+      wtot += (int64_t)std::max(m[k], 1) * ld[k];
+      soff[k] = stot;
+      stot += 16 + 2 * (int64_t)std::max(m[k], 1) + std::max(d[k], 1);
     }
-    DevBuf dm(sizeof(int32_t) * count), dd(sizeof(int32_t) * count), dld(sizeof(int64_t) * count);
-    DevBuf dso(sizeof(int64_t) * count), dwo(sizeof(int64_t) * count), dpo(sizeof(int64_t) * count);
-    DevBuf deo(sizeof(int64_t) * count), drk(sizeof(int32_t) * count);
-    DevBuf W(sizeof(double) * std::max<int64_t>(wtot, 1)), nrm(sizeof(double) * (size_t)mmax * count);
-    HSS_HIP_CHECK(hipMemcpy(dm.p, m, sizeof(int32_t) * count, hipMemcpyHostToDevice));
-    HSS_HIP_CHECK(hipMemcpy(dd.p, d, sizeof(int32_t) * count, hipMemcpyHostToDevice));
-    HSS_HIP_CHECK(hipMemcpy(dld.p, ld, sizeof(int64_t) * count, hipMemcpyHostToDevice));
-    HSS_HIP_CHECK(hipMemcpy(dso.p, s_off, sizeof(int64_t) * count, hipMemcpyHostToDevice));
-    HSS_HIP_CHECK(hipMemcpy(dwo.p, woff.data(), sizeof(int64_t) * count, hipMemcpyHostToDevice));
-    HSS_HIP_CHECK(hipMemcpy(dpo.p, piv_off, sizeof(int64_t) * count, hipMemcpyHostToDevice));
-    HSS_HIP_CHECK(hipMemcpy(deo.p, e_off, sizeof(int64_t) * count, hipMemcpyHostToDevice));
-    launch_qrcp_standalone(count, dm.as<int32_t>(), dd.as<int32_t>(), dld.as<int64_t>(), S, dso.as<int64_t>(),
-                           W.as<double>(), dwo.as<int64_t>(), eps_r, eps_a, piv, dpo.as<int64_t>(), E,
-                           deo.as<int64_t>(), drk.as<int32_t>(), nrm.as<double>(), mmax, dmax, nullptr);
-    HSS_HIP_CHECK(hipGetLastError());
+    DevBuf W(sizeof(double) * std::max<int64_t>(wtot, 1)), scr(sizeof(double) * stot);
+    DevBuf drk(sizeof(int32_t) * count), flag(sizeof(int32_t) * 4);
+    DevBuf dt(sizeof(QrcpTask) * count), gt(sizeof(GemmTask) * count);
+    std::vector<QrcpTask> tasks(count);
+    std::vector<int32_t> mc(count);
+    for (int32_t k = 0; k < count; ++k) {
+      QrcpTask& q = tasks[k];
+      std::memset(&q, 0, sizeof(q));
+      q.S = S + s_off[k];
+      q.lds = ld[k];
+      q.W = W.as<double>() + woff[k];
+      q.ldw = ld[k];
+      q.scr = scr.as<double>() + soff[k];
+      q.J = piv + piv_off[k];
+      q.E = E + e_off[k];
+      q.lde = std::max(m[k], 1);
+      q.rank_out = drk.as<int32_t>() + k;
+      q.er = eps_r;
+      q.ea = eps_a;
+      q.hmt_mn = 0.0;
+      q.m = m[k];
+      q.d = d[k];
+      q.mcap = std::max(m[k], 1);
+      q.active = 1;
+      mc[k] = q.mcap;
+    }
+    QrcpPlan plan = make_qrcp_plan(mc);
+    DevBuf ws(sizeof(int2) * plan.step.size()), wt(sizeof(int2) * plan.trsm.size());
+    HSS_HIP_CHECK(hipMemcpy(dt.p, tasks.data(), sizeof(QrcpTask) * count, hipMemcpyHostToDevice));
+    HSS_HIP_CHECK(hipMemcpy(ws.p, plan.step.data(), sizeof(int2) * plan.step.size(), hipMemcpyHostToDevice));
+    HSS_HIP_CHECK(hipMemcpy(wt.p, plan.trsm.data(), sizeof(int2) * plan.trsm.size(), hipMemcpyHostToDevice));
+    run_qrcp(dt.as<QrcpTask>(), count, ws.as<int2>(), (int32_t)plan.step.size(), wt.as<int2>(),
+             (int32_t)plan.trsm.size(), std::min(mmax, dmax), dmax, flag.as<int32_t>(), gt.as<GemmTask>(), mmax,
+             nullptr);
+    HSS_HIP_CHECK(hipStreamSynchronize(nullptr));
     HSS_HIP_CHECK(hipMemcpy(rank_host, drk.p, sizeof(int32_t) * count, hipMemcpyDeviceToHost));
     return HSS_OK;
   });

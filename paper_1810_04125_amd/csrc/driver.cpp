@@ -179,7 +179,7 @@ void Job::setup(int32_t count, const hss_generator* gens, const hss_tree* const*
       d.ws = a;
       a += align8((int64_t)d.mcap * dc);
       d.wsq = b;
-      b += align8(std::max<int64_t>((int64_t)d.qcap * dc, d.mcap));
+      b += align8(std::max<int64_t>((int64_t)d.qcap * dc, 16 + 2 * (int64_t)d.mcap + dc));
       L.mcap = std::max(L.mcap, d.mcap);
       L.rcap = std::max(L.rcap, d.rcap);
       L.qcap = std::max(L.qcap, d.qcap);
@@ -201,6 +201,18 @@ void Job::setup(int32_t count, const hss_generator* gens, const hss_tree* const*
   st_d = (NodeState*)dalloc(sizeof(NodeState) * gnodes);
   prob_d = (ProbDev*)dalloc(sizeof(ProbDev) * count);
   tasks_d = (GemmTask*)dalloc(sizeof(GemmTask) * 2 * std::max(maxcount, 1));
+  qtasks_d = (QrcpTask*)dalloc(sizeof(QrcpTask) * std::max(maxcount, 1));
+  for (auto& L : levels) {
+    std::vector<int32_t> mc;
+    for (int32_t g : L.nodes) mc.push_back(desc[g].mcap);
+    QrcpPlan qp = make_qrcp_plan(mc);
+    L.nstep = (int32_t)qp.step.size();
+    L.ntrsm = (int32_t)qp.trsm.size();
+    L.wg_step = (int2*)dalloc(sizeof(int2) * std::max<size_t>(qp.step.size(), 1));
+    L.wg_trsm = (int2*)dalloc(sizeof(int2) * std::max<size_t>(qp.trsm.size(), 1));
+    HSS_HIP_CHECK(hipMemcpy(L.wg_step, qp.step.data(), sizeof(int2) * qp.step.size(), hipMemcpyHostToDevice));
+    HSS_HIP_CHECK(hipMemcpy(L.wg_trsm, qp.trsm.data(), sizeof(int2) * qp.trsm.size(), hipMemcpyHostToDevice));
+  }
   flags_d = (int32_t*)dalloc(sizeof(int32_t) * 4);
   nodes_d = (int32_t*)dalloc(sizeof(int32_t) * gnodes);
   {
@@ -260,6 +272,8 @@ void Job::setup(int32_t count, const hss_generator* gens, const hss_tree* const*
     pd.sglob[1] = P.sglob[1];
     pd.R = P.opt.R;
     pd.ldr = P.opt.ldr;
+    P.sched_d = (int32_t*)dalloc(sizeof(int32_t) * (P.dcap + 2));
+    pd.sched = P.sched_d;
   }
   HSS_HIP_CHECK(hipGetLastError());
 }
@@ -298,16 +312,29 @@ void Job::run_level(int lev, int32_t ncap) {
   a.flags = flags_d;
   const int nsides = all_sym ? 1 : 2;
   const int32_t nc = std::min(ncap, L.dcap);
+  HSS_HIP_CHECK(hipMemsetAsync(flags_d + 1, 0, sizeof(int32_t), stream));
   launch_plan(a, stream);
   launch_extract_nodes(a, stream);
   for (int s = 0; s < nsides; ++s) launch_local_samples(a, s, L.mcap, L.rcap, nc, stream);
+  auto id_phase = [&](int hmt) {
+    for (int s = 0; s < nsides; ++s) {
+      launch_build_qrcp(a, s, hmt, qtasks_d, stream);
+      run_qrcp(qtasks_d, a.count, L.wg_step, L.nstep, L.wg_trsm, L.ntrsm, std::min(L.mcap, ncap), ncap,
+               flags_d + 2, tasks_d, L.mcap, stream);
+    }
+  };
   if (strategy == HSS_DBL_HMT) {
-    for (int s = 0; s < nsides; ++s) launch_qrcp(a, s, 1, L.mcap, L.dcap, stream);
+    id_phase(1);
     launch_decide_hmt(a, stream);
   } else {
-    for (int s = 0; s < nsides; ++s) launch_fnorm_test(a, s, L.mcap, std::max(L.qcap, 1), nc, stream);
+    int32_t nblk = 0;
+    HSS_HIP_CHECK(hipMemcpyAsync(&nblk, flags_d + 1, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+    HSS_HIP_CHECK(hipStreamSynchronize(stream));
+    for (int it = 0; it < nblk; ++it)
+      for (int s = 0; s < nsides; ++s)
+        launch_fnorm_test(a, s, it, L.mcap, std::max(L.qcap, 1), std::min(max_block, L.dcap), stream);
     launch_decide_fnorm(a, stream);
-    for (int s = 0; s < nsides; ++s) launch_qrcp(a, s, 0, L.mcap, L.dcap, stream);
+    id_phase(0);
   }
   for (int s = 0; s < nsides; ++s) launch_reduce(a, s, L.mcap, L.rcap, nc, stream);
   launch_finalize(a, stream);
@@ -332,12 +359,17 @@ void Job::compress() {
   int32_t flags[4];
   for (int round = 0;; ++round) {
     int32_t ncap = 0;
+    max_block = 0;
     for (size_t k = 0; k < probs.size(); ++k) {
       Problem& P = probs[k];
       P.dev.d = P.d;
       P.dev.b = P.b;
       P.dev.force = P.force;
       P.dev.done = P.done;
+      P.dev.nsched = (int32_t)P.sched.size();
+      HSS_HIP_CHECK(hipMemcpy(P.sched_d, P.sched.data(), sizeof(int32_t) * P.sched.size(), hipMemcpyHostToDevice));
+      for (size_t i = 0; i < P.sched.size(); ++i)
+        max_block = std::max(max_block, P.sched[i] - (i ? P.sched[i - 1] : 0));
       pdev[k] = P.dev;
       if (!P.done) {
         ncap = std::max(ncap, P.d);

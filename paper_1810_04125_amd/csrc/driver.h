@@ -25,12 +25,16 @@ struct Problem {
   int32_t d = 0, b = 0, force = 0, done = 0, rounds = 0;
   hss_status status = HSS_OK;
   std::vector<int32_t> sched;
+  int32_t* sched_d = nullptr;
 };
 
 struct LevelInfo {
   std::vector<int32_t> nodes;
   int32_t off = 0;
   int32_t mcap = 0, rcap = 0, qcap = 0, dcap = 0;
+  int2* wg_step = nullptr;   // QRCP workgroup maps (device)
+  int2* wg_trsm = nullptr;
+  int32_t nstep = 0, ntrsm = 0;
 };
 
 struct Job {
@@ -41,6 +45,7 @@ struct Job {
   int32_t maxlevel = 0;
   int32_t strategy = 0;
   bool all_sym = true;
+  int32_t max_block = 0;   // widest sampling block so far
   hipStream_t stream = nullptr;
   std::vector<void*> allocs;
   double *dpool = nullptr, *wsa = nullptr, *wsb = nullptr, *partial = nullptr;
@@ -52,6 +57,7 @@ struct Job {
   GemmTask* tasks_d = nullptr;
   int32_t* flags_d = nullptr;
   int32_t* nodes_d = nullptr;
+  QrcpTask* qtasks_d = nullptr;
   int64_t* mvoff_d = nullptr;   // per node: prefix sum of rcap (matvec slots)
   int64_t mvtot = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;

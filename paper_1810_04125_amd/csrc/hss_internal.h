@@ -8,6 +8,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "../../include/hss.h"
 
@@ -70,6 +71,10 @@ struct NodeState {
   int32_t passed[2];
   int32_t need[2];  // F-norm test must run its projections this round
   int32_t q[2];     // columns of Q per side
+  int32_t tb;       // first sampling block to test this round
+  int32_t nblk;     // number of blocks to test this round
+  int32_t run[2];   // the current test iteration runs its QR on this side
+  int32_t bc0, bnc; // columns of the block under test
   double rho[2];
 };
 
@@ -88,10 +93,14 @@ struct ProbDev {
   int64_t sglob[2];      // offsets of the global samples (n x dcap col-major) in the double pool
   const double* R;
   int64_t ldr;
+  const int32_t* sched;  // d after every sampling step (block edges), nsched entries
+  int32_t nsched;
+  int32_t pad1;
   GenDev gen;
 };
 
 // C(i,j) = alpha * sum_k A(i,k) B(k,j) + beta * C(i,j) with arbitrary strides.
+// a_cols, when set, maps column k of A to the physical column a_cols[k].
 struct GemmTask {
   const double* A;
   const double* B;
@@ -99,7 +108,38 @@ struct GemmTask {
   int64_t a_rs, a_cs, b_rs, b_cs, c_rs, c_cs;
   int32_t M, N, K, pad;
   double alpha, beta;
+  const int32_t* a_cols = nullptr;
 };
+
+// One matrix of a batched interpolative decomposition (k_qrcp.hip).
+// S: m rows of length d (row j at S + j * lds); W: panel, column j at
+// W + j * ldw; scr: 16 + 2 * mcap + min(m, d) doubles of scratch; J: m
+// int32; E: rank x (m - rank), column-major with leading dimension lde.
+struct QrcpTask {
+  const double* S;
+  int64_t lds;
+  double* W;
+  int64_t ldw;
+  double* scr;
+  int32_t* J;
+  double* E;
+  int64_t lde;
+  int32_t* rank_out;
+  double er, ea;     // stop when nu_k <= max(ea, er * nu_1) (/ HMT factor)
+  double hmt_mn;     // > 0: HMT factor with sqrt(hmt_mn); 0: plain threshold
+  int32_t m, d, mcap, active;
+};
+
+constexpr int QCPW = 16;  // panel columns owned by one workgroup
+
+struct QrcpPlan {
+  std::vector<int2> step;   // (task, first column) per workgroup of a pivot step
+  std::vector<int2> trsm;   // (task, first column of E) per workgroup of the solve
+};
+QrcpPlan make_qrcp_plan(const std::vector<int32_t>& mcaps);
+void run_qrcp(const QrcpTask* tasks, int32_t ntasks, const int2* wg_step, int32_t nstep,
+              const int2* wg_trsm, int32_t ntrsm, int32_t kmax, int32_t dmax, int32_t* flag,
+              GemmTask* gtasks, int32_t mcap_max, hipStream_t s);
 
 // ------------------------------------------------------------------ launchers
 void launch_toeplitz_table(double* t, int64_t n, double h, hipStream_t s);
@@ -136,23 +176,15 @@ void launch_plan(const LevelArgs& a, hipStream_t s);
 void launch_extract_nodes(const LevelArgs& a, hipStream_t s);
 void launch_local_samples(const LevelArgs& a, int side, int32_t mcap_max, int32_t rcap_max,
                           int32_t dcap_max, hipStream_t s);
-void launch_fnorm_test(const LevelArgs& a, int side, int32_t mcap_max, int32_t qcap_max,
-                       int32_t dcap_max, hipStream_t s);
+void launch_fnorm_test(const LevelArgs& a, int side, int32_t iter, int32_t mcap_max,
+                       int32_t qcap_max, int32_t ncap, hipStream_t s);
 void launch_decide_fnorm(const LevelArgs& a, hipStream_t s);
-void launch_qrcp(const LevelArgs& a, int side, int32_t hmt, int32_t mcap_max,
-                 int32_t dcap_max, hipStream_t s);
+void launch_build_qrcp(const LevelArgs& a, int side, int32_t hmt, QrcpTask* out, hipStream_t s);
 void launch_decide_hmt(const LevelArgs& a, hipStream_t s);
 void launch_reduce(const LevelArgs& a, int side, int32_t mcap_max, int32_t rcap_max,
                    int32_t dcap_max, hipStream_t s);
 void launch_finalize(const LevelArgs& a, hipStream_t s);
 
-// Standalone batched ID (hss_interpolative_batched).
-void launch_qrcp_standalone(int32_t count, const int32_t* m, const int32_t* d,
-                            const int64_t* ld, const double* S, const int64_t* s_off,
-                            double* W, const int64_t* w_off, double eps_r, double eps_a,
-                            int32_t* piv, const int64_t* piv_off, double* E,
-                            const int64_t* e_off, int32_t* rank, double* nrm, int32_t mmax,
-                            int32_t dmax, hipStream_t s);
 
 // Matvec pieces (one workgroup per node of a level).
 struct MvArgs {

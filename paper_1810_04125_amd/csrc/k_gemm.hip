@@ -41,7 +41,12 @@ __global__ __launch_bounds__(256) void k_gemm_grouped(const GemmTask* __restrict
       int k, i;
       if (t.a_rs <= t.a_cs) { i = idx % GT; k = idx / GT; } else { k = idx % GK; i = idx / GK; }
       const int64_t gi = i0 + i, gk = k0 + k;
-      As[k][i] = (gi < t.M && gk < t.K) ? t.A[gi * t.a_rs + gk * t.a_cs] : 0.0;
+      double av = 0.0;
+      if (gi < t.M && gk < t.K) {
+        const int64_t col = t.a_cols ? (int64_t)t.a_cols[gk] : gk;
+        av = t.A[gi * t.a_rs + col * t.a_cs];
+      }
+      As[k][i] = av;
       int kb, j;
       if (t.b_cs <= t.b_rs) { j = idx % GT; kb = idx / GT; } else { kb = idx % GK; j = idx / GK; }
       const int64_t gj = j0 + j, gkb = k0 + kb;

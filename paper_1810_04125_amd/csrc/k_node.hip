@@ -87,12 +87,13 @@ __global__ void k_plan(LevelArgs a) {
       st.rank[s] = 0;
     }
   }
-  if (P.strategy != HSS_DBL_HMT && !P.force) {
-    for (int s = 0; s < 2; ++s) {
-      if (st.passed[s]) continue;
-      if (P.d >= st.m[s]) st.passed[s] = 1;  // samples span the whole local range
-      else if (st.nc > 0) st.need[s] = 1;
-    }
+  // Alg. 5 runs over the sampling blocks not yet tested: all of them the
+  // first time a node is tested, afterwards only the newest one.
+  st.tb = st.fresh ? 0 : P.nsched - 1;
+  st.nblk = (st.fresh ? P.nsched : 1);
+  if (P.strategy != HSS_DBL_HMT && !P.force && st.nc > 0) {
+    for (int s = 0; s < 2; ++s) st.need[s] = !st.passed[s];
+    if (st.need[0] || st.need[1]) atomicMax(a.flags + 1, st.nblk);
   }
 }
 
@@ -247,17 +248,43 @@ void launch_local_samples(const LevelArgs& a, int side, int32_t mcap_max, int32_
 }
 
 // ------------------------------------------------------------------ F-norm test
-__global__ __launch_bounds__(NB) void k_fn_copy(LevelArgs a, int side) {
+// Iteration `iter` of the test tests block tb + iter of the sampling
+// schedule, columns [sched[b-1], sched[b]).  A side passes at once when the
+// samples up to that block are at least as many as its rows (they span the
+// whole local range).
+__global__ __launch_bounds__(NB) void k_fn_copy(LevelArgs a, int side, int iter) {
   const int t = blockIdx.x;
   const int g = a.nodes[t];
   const NodeDesc& nd = a.desc[g];
-  const NodeState& st = a.st[g];
+  NodeState& st = a.st[g];
   GemmTask* TA = a.tasks + t;
   GemmTask* TB = a.tasks + a.count + t;
-  if (threadIdx.x == 0) { TA->M = 0; TB->M = 0; }
-  if (!st.need[side]) return;
+  __shared__ int s_go;
+  if (threadIdx.x == 0) {
+    TA->M = 0;
+    TB->M = 0;
+    int go = 0;
+    st.run[side] = 0;
+    if (st.need[side] && !st.passed[side] && iter < st.nblk) {
+      const ProbDev& P = a.prob[nd.prob];
+      const int b = st.tb + iter;
+      const int c0 = b > 0 ? P.sched[b - 1] : 0;
+      const int c1 = P.sched[b];
+      if (c1 >= st.m[side]) {
+        st.passed[side] = 1;
+      } else if (c1 > c0) {
+        st.bc0 = c0;
+        st.bnc = c1 - c0;
+        st.run[side] = 1;
+        go = 1;
+      }
+    }
+    s_go = go;
+  }
+  __syncthreads();
+  if (!s_go) return;
   const ProbDev& P = a.prob[nd.prob];
-  const int dcap = P.dcap, m = st.m[side], nc = st.nc, c0 = st.c0, q = st.q[side];
+  const int dcap = P.dcap, m = st.m[side], nc = st.bnc, c0 = st.bc0, q = st.q[side];
   const double* S = cdp(a, nd.S[side]);
   double* Sh = a.wsA + nd.ws;
   for (int64_t idx = threadIdx.x; idx < (int64_t)m * nc; idx += NB) {
@@ -292,9 +319,9 @@ __global__ __launch_bounds__(NB) void k_fn_qr(LevelArgs a, int side) {
   const int g = a.nodes[blockIdx.x];
   const NodeDesc& nd = a.desc[g];
   NodeState& st = a.st[g];
-  if (!st.need[side]) return;
+  if (!st.run[side]) return;
   const ProbDev& P = a.prob[nd.prob];
-  const int dcap = P.dcap, m = st.m[side], nc = st.nc, c0 = st.c0, ld = nd.mcap;
+  const int dcap = P.dcap, m = st.m[side], nc = st.bnc, c0 = st.bc0, ld = nd.mcap;
   const double lev = (double)nd.level;
   const double er = P.eps_r / lev, ea = P.eps_a / lev;
   const double* S = cdp(a, nd.S[side]);
@@ -377,10 +404,10 @@ __global__ __launch_bounds__(NB) void k_fn_qr(LevelArgs a, int side) {
   if (threadIdx.x == 0) st.q[side] = q + nc;
 }
 
-void launch_fnorm_test(const LevelArgs& a, int side, int32_t mcap_max, int32_t qcap_max,
+void launch_fnorm_test(const LevelArgs& a, int side, int32_t iter, int32_t mcap_max, int32_t qcap_max,
                        int32_t ncap, hipStream_t s) {
   if (a.count <= 0) return;
-  hipLaunchKernelGGL(k_fn_copy, dim3(a.count), dim3(NB), 0, s, a, side);
+  hipLaunchKernelGGL(k_fn_copy, dim3(a.count), dim3(NB), 0, s, a, side, iter);
   for (int pass = 0; pass < 2; ++pass) {  // block Gram-Schmidt, twice
     launch_gemm(a.tasks, a.count, qcap_max, ncap, s);
     launch_gemm(a.tasks + a.count, a.count, mcap_max, ncap, s);
@@ -405,170 +432,41 @@ void launch_decide_fnorm(const LevelArgs& a, hipStream_t s) {
 }
 
 // ------------------------------------------------------------------ QRCP / ID
-// Panel W = S^T (d x m, column j = row j of S, contiguous) copied to the
-// workspace.  Step k: pivot = remaining column of largest residual norm
-// (ties -> lowest index); stop before it if its norm nu <= threshold;
-// otherwise reflect it to alpha e_k and update every remaining column,
-// recomputing its residual norm (rows k+1..d-1) from the updated values.
-// Writes J (pivots, then the rest ascending), E = R1^{-1} R2 (r x (m-r),
-// column-major, leading dimension lde) and returns the rank.
-__device__ int qrcp_core(const double* __restrict__ S, int64_t lds, int m, int d, double* __restrict__ W,
-                         int64_t ldw, double* __restrict__ nrm, int32_t* __restrict__ J,
-                         double* __restrict__ E, int64_t lde, double er, double ea, int hmt,
-                         double mn_hank, double* vsh) {
-  __shared__ double rv[NW];
-  __shared__ int ri[NW];
-  __shared__ int s_piv, s_stop, s_rank;
-  __shared__ double s_nu, s_nu1, s_tau;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  for (int j = w; j < m; j += NW) {
-    const double* src = S + (int64_t)j * lds;
-    double* dst = W + (int64_t)j * ldw;
-    double sq = 0.0;
-    for (int i = lane; i < d; i += 64) {
-      const double x = src[i];
-      dst[i] = x;
-      sq += x * x;
-    }
-    sq = wave_sum(sq);
-    if (lane == 0) nrm[j] = sqrt(sq);
-  }
-  __syncthreads();
-  const int kmax = min(m, d);
-  int k = 0;
-  for (; k < kmax; ++k) {
-    double bv = -1.0;
-    int bi = 0x7fffffff;
-    for (int j = threadIdx.x; j < m; j += NB) {
-      const double v = nrm[j];
-      if (v < 0.0) continue;
-      if (v > bv || (v == bv && j < bi)) { bv = v; bi = j; }
-    }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      const double ov = __shfl_xor(bv, o, 64);
-      const int oi = __shfl_xor(bi, o, 64);
-      if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
-    }
-    if (lane == 0) { rv[w] = bv; ri[w] = bi; }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double v = rv[0];
-      int p = ri[0];
-      for (int i = 1; i < NW; ++i)
-        if (rv[i] > v || (rv[i] == v && ri[i] < p)) { v = rv[i]; p = ri[i]; }
-      if (k == 0) s_nu1 = v;
-      double thr = fmax(ea, er * s_nu1);
-      if (hmt) {
-        const double over = (double)(d - (k + 1) - 1);
-        thr = over <= 0.0 ? 0.0 : thr / (1.0 + 4.0 * sqrt((double)d) / over * sqrt(mn_hank));
-      }
-      s_stop = (v <= thr) ? 1 : 0;
-      s_piv = p;
-      s_nu = v;
-      if (!s_stop) {
-        J[k] = p;
-        nrm[p] = -1.0;
-      }
-    }
-    __syncthreads();
-    if (s_stop) break;
-    const int p = s_piv;
-    const double nu = s_nu;
-    double* x = W + (int64_t)p * ldw;
-    const double x0 = x[k];
-    const double alpha = x0 >= 0.0 ? -nu : nu;
-    for (int i = k + threadIdx.x; i < d; i += NB) vsh[i - k] = (i == k) ? x0 - alpha : x[i];
-    if (threadIdx.x == 0) s_tau = 1.0 / (nu * (nu + fabs(x0)));
-    __syncthreads();
-    if (threadIdx.x == 0) x[k] = alpha;  // R(k,k); rows > k of the pivot column are dead
-    const double tk = s_tau;
-    for (int j = w; j < m; j += NW) {
-      if (j == p || nrm[j] < 0.0) continue;
-      double* y = W + (int64_t)j * ldw;
-      double dot = 0.0;
-      for (int i = k + lane; i < d; i += 64) dot += vsh[i - k] * y[i];
-      dot = wave_sum(dot) * tk;
-      double sq = 0.0;
-      for (int i = k + lane; i < d; i += 64) {
-        const double yi = y[i] - dot * vsh[i - k];
-        y[i] = yi;
-        if (i > k) sq += yi * yi;
-      }
-      sq = wave_sum(sq);
-      if (lane == 0) nrm[j] = sqrt(sq);
-    }
-    __syncthreads();
-  }
-  const int r = k;
-  if (threadIdx.x == 0) {
-    int pos = r;
-    for (int j = 0; j < m; ++j)
-      if (nrm[j] >= 0.0) J[pos++] = j;
-    s_rank = r;
-  }
-  __syncthreads();
-  // E = R1^{-1} R2: column l of R2 is W(0:r, J[r+l]); back substitution in place
-  const int nrest = m - r;
-  for (int l = threadIdx.x; l < nrest; l += NB) {
-    double* y = W + (int64_t)J[r + l] * ldw;
-    for (int kk = r - 1; kk >= 0; --kk) {
-      const double* col = W + (int64_t)J[kk] * ldw;
-      const double yk = y[kk] / col[kk];
-      y[kk] = yk;
-      for (int i = 0; i < kk; ++i) y[i] -= col[i] * yk;
-    }
-    for (int i = 0; i < r; ++i) E[(int64_t)l * lde + i] = y[i];
-  }
-  __syncthreads();
-  return s_rank;
-}
-
-__global__ __launch_bounds__(NB) void k_qrcp(LevelArgs a, int side, int hmt) {
-  extern __shared__ double vsh[];  // Householder vector, d entries
-  const int g = a.nodes[blockIdx.x];
+// One QrcpTask per node of the level: the node's side-`side` local sample
+// (m x d), its workspace slots and thresholds eta*eps/level(tau).  Nodes
+// that do not compress this round get active = 0.
+__global__ void k_build_qrcp(LevelArgs a, int side, int hmt, QrcpTask* __restrict__ out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= a.count) return;
+  const int g = a.nodes[t];
   const NodeDesc& nd = a.desc[g];
   NodeState& st = a.st[g];
-  if (!st.active || !st.test) return;
-  if (!hmt && !st.go) return;
   const ProbDev& P = a.prob[nd.prob];
+  QrcpTask q;
+  q.active = st.active && st.test && (hmt || st.go);
+  q.S = a.dpool + nd.S[side];
+  q.lds = P.dcap;
+  q.W = a.wsA + nd.ws;
+  q.ldw = P.dcap;
+  q.scr = a.wsB + nd.wsq;
+  q.J = a.ipool + nd.J[side];
+  q.E = a.dpool + nd.E[side];
+  q.lde = nd.rcap;
+  q.rank_out = &st.rank[side];
   const double lev = (double)nd.level;
+  q.er = P.eps_r / lev;
+  q.ea = P.eps_a / lev;
   const int64_t size = nd.hi - nd.lo;
-  const int r = qrcp_core(a.dpool + nd.S[side], P.dcap, st.m[side], P.d, a.wsA + nd.ws, P.dcap,
-                          a.wsB + nd.wsq, a.ipool + nd.J[side], a.dpool + nd.E[side], nd.rcap,
-                          P.eps_r / lev, P.eps_a / lev, hmt, (double)min(size, P.n - size), vsh);
-  if (threadIdx.x == 0) st.rank[side] = r;
+  q.hmt_mn = hmt ? (double)min(size, P.n - size) : 0.0;
+  q.m = st.m[side];
+  q.d = P.d;
+  q.mcap = nd.mcap;
+  out[t] = q;
 }
 
-__global__ __launch_bounds__(NB) void k_qrcp_standalone(const int32_t* m, const int32_t* d, const int64_t* ld,
-                                                        const double* S, const int64_t* s_off, double* W,
-                                                        const int64_t* w_off, double eps_r, double eps_a,
-                                                        int32_t* piv, const int64_t* piv_off, double* E,
-                                                        const int64_t* e_off, int32_t* rank, double* nrm,
-                                                        int32_t mmax) {
-  extern __shared__ double vsh[];
-  const int k = blockIdx.x;
-  const int r = qrcp_core(S + s_off[k], ld[k], m[k], d[k], W + w_off[k], ld[k], nrm + (int64_t)k * mmax,
-                          piv + piv_off[k], E + e_off[k], m[k], eps_r, eps_a, 0, 0.0, vsh);
-  if (threadIdx.x == 0) rank[k] = r;
-}
-
-void launch_qrcp_standalone(int32_t count, const int32_t* m, const int32_t* d, const int64_t* ld,
-                            const double* S, const int64_t* s_off, double* W, const int64_t* w_off,
-                            double eps_r, double eps_a, int32_t* piv, const int64_t* piv_off, double* E,
-                            const int64_t* e_off, int32_t* rank, double* nrm, int32_t mmax, int32_t dmax,
-                            hipStream_t s) {
-  if (count <= 0) return;
-  hipLaunchKernelGGL(k_qrcp_standalone, dim3(count), dim3(NB), (size_t)std::max(dmax, 1) * sizeof(double), s,
-                     m, d, ld, S, s_off, W, w_off, eps_r, eps_a, piv, piv_off, E, e_off, rank, nrm, mmax);
-}
-
-void launch_qrcp(const LevelArgs& a, int side, int32_t hmt, int32_t mcap_max, int32_t dcap_max,
-                 hipStream_t s) {
-  (void)mcap_max;
+void launch_build_qrcp(const LevelArgs& a, int side, int32_t hmt, QrcpTask* out, hipStream_t s) {
   if (a.count <= 0) return;
-  const size_t lds = (size_t)dcap_max * sizeof(double);
-  hipLaunchKernelGGL(k_qrcp, dim3(a.count), dim3(NB), lds, s, a, side, hmt);
+  hipLaunchKernelGGL(k_build_qrcp, dim3((a.count + 127) / 128), dim3(128), 0, s, a, side, hmt, out);
 }
 
 __global__ void k_decide_hmt(LevelArgs a) {

@@ -1,0 +1,289 @@
+// Interpolative decomposition by QR with column pivoting (Sec. 2.2,
+// eqs. ID and QRCPSr): for a local sample S (m x d), factor S^T (d x m)
+// with column pivoting, stop before the first pivot whose residual norm
+// nu_k is <= max(eps_a, eps_r nu_1) (divided by the HMT factor of
+// eq. RRQRHMTstop for the doubling strategy), and return the selected
+// rows J (pivot order, then the other rows ascending) and
+// E = R1^{-1} R2, so that S(rest,:) ~= E^T S(J,:).
+//
+// The factorization runs on many workgroups per matrix: column j of the
+// panel W = S^T (the j-th row of S, contiguous) belongs to one workgroup,
+// and every pivot step is one launch covering all matrices of a batch.
+// Each workgroup finds the pivot itself (argmax over the residual norms
+// of the previous step, ties to the lowest index), rebuilds the
+// Householder vector from the pivot column in LDS, and updates its own
+// columns, recomputing their residual norms exactly from the updated
+// values.  Norms are double-buffered between steps and the pivot column is
+// never written during a step, so workgroups of one launch never race.
+// E is then obtained by a blocked back substitution: 64 x 64 diagonal
+// blocks solved in LDS, the off-diagonal updates on the FP64 matrix cores.
+#include <algorithm>
+
+#include "hss_internal.h"
+
+namespace hss {
+
+constexpr int QB = 256;          // threads per workgroup
+constexpr int QW = QB / 64;
+constexpr int TRB = 64;          // diagonal block of the triangular solve
+
+struct QrcpCtl {
+  int32_t done;
+  int32_t rank;
+  double nu1;
+};
+
+__device__ __forceinline__ QrcpCtl* ctl_of(const QrcpTask& t) { return reinterpret_cast<QrcpCtl*>(t.scr); }
+__device__ __forceinline__ double* nrm_of(const QrcpTask& t, int k) { return t.scr + 16 + (int64_t)(k & 1) * t.mcap; }
+__device__ __forceinline__ double* rdiag_of(const QrcpTask& t) { return t.scr + 16 + 2 * (int64_t)t.mcap; }
+
+__device__ __forceinline__ double wsum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__global__ __launch_bounds__(QB) void k_qrcp_init(const QrcpTask* __restrict__ tasks, const int2* __restrict__ wg) {
+  const int2 w = wg[blockIdx.x];
+  const QrcpTask& t = tasks[w.x];
+  if (!t.active) return;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (w.y == 0 && threadIdx.x == 0) {
+    QrcpCtl* c = ctl_of(t);
+    c->done = 0;
+    c->rank = 0;
+    c->nu1 = 0.0;
+  }
+  double* nrm = nrm_of(t, 0);
+  const int jend = min(t.m, w.y + QCPW);
+  for (int j = w.y + wv; j < jend; j += QW) {
+    const double* src = t.S + (int64_t)j * t.lds;
+    double* dst = t.W + (int64_t)j * t.ldw;
+    double sq = 0.0;
+    for (int i = lane; i < t.d; i += 64) {
+      const double x = src[i];
+      dst[i] = x;
+      sq += x * x;
+    }
+    sq = wsum(sq);
+    if (lane == 0) nrm[j] = sqrt(sq);
+  }
+}
+
+__global__ __launch_bounds__(QB) void k_qrcp_step(const QrcpTask* __restrict__ tasks, const int2* __restrict__ wg,
+                                                  int k) {
+  extern __shared__ double vsh[];
+  __shared__ double rv[QW];
+  __shared__ int ri[QW];
+  const int2 w = wg[blockIdx.x];
+  const QrcpTask& t = tasks[w.x];
+  if (!t.active) return;
+  const int m = t.m, d = t.d;
+  if (k >= min(m, d)) return;
+  QrcpCtl* c = ctl_of(t);
+  if (c->done) return;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const double* nold = nrm_of(t, k);
+  double* nnew = nrm_of(t, k + 1);
+  // pivot: largest residual norm among the remaining columns, ties -> lowest index
+  double bv = -1.0;
+  int bi = 0x7fffffff;
+  for (int j = threadIdx.x; j < m; j += QB) {
+    const double v = nold[j];
+    if (v < 0.0) continue;
+    if (v > bv || (v == bv && j < bi)) { bv = v; bi = j; }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const double ov = __shfl_xor(bv, o, 64);
+    const int oi = __shfl_xor(bi, o, 64);
+    if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+  }
+  if (lane == 0) { rv[wv] = bv; ri[wv] = bi; }
+  __syncthreads();
+  double nu = rv[0];
+  int p = ri[0];
+  for (int i = 1; i < QW; ++i)
+    if (rv[i] > nu || (rv[i] == nu && ri[i] < p)) { nu = rv[i]; p = ri[i]; }
+  const double nu1 = (k == 0) ? nu : c->nu1;
+  double thr = fmax(t.ea, t.er * nu1);
+  if (t.hmt_mn > 0.0) {
+    const double over = (double)(d - (k + 1) - 1);
+    thr = over <= 0.0 ? 0.0 : thr / (1.0 + 4.0 * sqrt((double)d) / over * sqrt(t.hmt_mn));
+  }
+  const bool lead = (w.y == 0 && threadIdx.x == 0);
+  if (nu <= thr) {
+    if (lead) {
+      c->rank = k;
+      c->done = 1;
+    }
+    return;
+  }
+  const double* x = t.W + (int64_t)p * t.ldw;
+  const double x0 = x[k];
+  const double alpha = x0 >= 0.0 ? -nu : nu;
+  for (int i = k + threadIdx.x; i < d; i += QB) vsh[i - k] = (i == k) ? x0 - alpha : x[i];
+  const double tk = 1.0 / (nu * (nu + fabs(x0)));  // 2 / v^T v
+  if (lead) {
+    if (k == 0) c->nu1 = nu;
+    rdiag_of(t)[k] = alpha;
+    t.J[k] = p;
+  }
+  __syncthreads();
+  const int jend = min(m, w.y + QCPW);
+  for (int j = w.y + wv; j < jend; j += QW) {
+    if (j == p || nold[j] < 0.0) {
+      if (lane == 0) nnew[j] = -1.0;
+      continue;
+    }
+    double* y = t.W + (int64_t)j * t.ldw;
+    double dot = 0.0;
+    for (int i = k + lane; i < d; i += 64) dot += vsh[i - k] * y[i];
+    dot = wsum(dot) * tk;
+    double sq = 0.0;
+    for (int i = k + lane; i < d; i += 64) {
+      const double yi = y[i] - dot * vsh[i - k];
+      y[i] = yi;
+      if (i > k) sq += yi * yi;
+    }
+    sq = wsum(sq);
+    if (lane == 0) nnew[j] = sqrt(sq);
+  }
+}
+
+// count of matrices still factoring after step k-1 has run
+__global__ void k_qrcp_alive(const QrcpTask* __restrict__ tasks, int ntasks, int k, int32_t* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ntasks) return;
+  const QrcpTask& t = tasks[i];
+  if (!t.active) return;
+  if (k < min(t.m, t.d) && !ctl_of(t)->done) atomicAdd(out, 1);
+}
+
+// rank, the ascending rest of J, R2 copied into E, max rank of the batch
+__global__ __launch_bounds__(QB) void k_qrcp_fin(const QrcpTask* __restrict__ tasks, int32_t* maxrank) {
+  const QrcpTask& t = tasks[blockIdx.x];
+  if (!t.active) return;
+  __shared__ int s_r;
+  const int m = t.m, d = t.d;
+  const int kmax = min(m, d);
+  if (threadIdx.x == 0) {
+    const QrcpCtl* c = ctl_of(t);
+    const int r = (kmax > 0 && c->done) ? c->rank : kmax;
+    const double* nfin = nrm_of(t, r);
+    int pos = r;
+    if (m > 0 && r == 0) {
+      for (int j = 0; j < m; ++j) t.J[pos++] = j;
+    } else {
+      for (int j = 0; j < m; ++j)
+        if (nfin[j] >= 0.0) t.J[pos++] = j;
+    }
+    *t.rank_out = r;
+    atomicMax(maxrank, r);
+    s_r = r;
+  }
+  __syncthreads();
+  const int r = s_r;
+  const int nrest = m - r;
+  for (int64_t idx = threadIdx.x; idx < (int64_t)r * nrest; idx += QB) {
+    const int i = (int)(idx % r), l = (int)(idx / r);
+    t.E[(int64_t)l * t.lde + i] = t.W[(int64_t)t.J[r + l] * t.ldw + i];
+  }
+}
+
+// Diagonal block [i0, i1) of the back substitution R1 E = R2 for the
+// columns [c0, c0 + QB) of E; the workgroup with c0 == 0 also writes the
+// GEMM task of the update E(0:i0, :) -= R1(0:i0, i0:i1) E(i0:i1, :).
+__global__ __launch_bounds__(QB) void k_trsm_diag(const QrcpTask* __restrict__ tasks, const int2* __restrict__ wg,
+                                                  int ib, GemmTask* __restrict__ gt) {
+  __shared__ double T[TRB][TRB + 1];
+  const int2 w = wg[blockIdx.x];
+  const QrcpTask& t = tasks[w.x];
+  GemmTask* g = gt + w.x;
+  if (w.y == 0 && threadIdx.x == 0) g->M = 0;
+  if (!t.active) return;
+  const int r = *t.rank_out;
+  const int i0 = ib * TRB;
+  if (i0 >= r) return;
+  const int i1 = min(r, i0 + TRB);
+  const int nb = i1 - i0;
+  const int nrest = t.m - r;
+  const double* rdiag = rdiag_of(t);
+  for (int idx = threadIdx.x; idx < TRB * TRB; idx += QB) {
+    const int ii = idx % TRB, jj = idx / TRB;
+    double v = 0.0;
+    if (ii < nb && jj < nb && ii <= jj)
+      v = (ii == jj) ? rdiag[i0 + jj] : t.W[(int64_t)t.J[i0 + jj] * t.ldw + i0 + ii];
+    T[ii][jj] = v;
+  }
+  __syncthreads();
+  const int l = w.y + threadIdx.x;
+  if (l < nrest) {
+    double* e = t.E + (int64_t)l * t.lde + i0;
+    double x[TRB];
+#pragma unroll
+    for (int ii = 0; ii < TRB; ++ii) x[ii] = ii < nb ? e[ii] : 0.0;
+#pragma unroll
+    for (int jj = TRB - 1; jj >= 0; --jj) {
+      if (jj < nb) {
+        const double xj = x[jj] / T[jj][jj];
+        x[jj] = xj;
+#pragma unroll
+        for (int ii = 0; ii < jj; ++ii) x[ii] -= T[ii][jj] * xj;
+      }
+    }
+#pragma unroll
+    for (int ii = 0; ii < TRB; ++ii)
+      if (ii < nb) e[ii] = x[ii];
+  }
+  if (w.y == 0 && threadIdx.x == 0 && i0 > 0 && nrest > 0) {
+    GemmTask q;
+    q.A = t.W; q.a_rs = 1; q.a_cs = t.ldw; q.a_cols = t.J + i0;
+    q.B = t.E + i0; q.b_rs = 1; q.b_cs = t.lde;
+    q.C = t.E; q.c_rs = 1; q.c_cs = t.lde;
+    q.M = i0; q.N = nrest; q.K = nb; q.pad = 0;
+    q.alpha = -1.0; q.beta = 1.0;
+    *g = q;
+  }
+}
+
+QrcpPlan make_qrcp_plan(const std::vector<int32_t>& mcaps) {
+  QrcpPlan p;
+  for (size_t t = 0; t < mcaps.size(); ++t) {
+    const int mc = std::max(mcaps[t], 1);
+    for (int c = 0; c < mc; c += QCPW) p.step.push_back(make_int2((int)t, c));
+    for (int c = 0; c < mc; c += QB) p.trsm.push_back(make_int2((int)t, c));
+  }
+  return p;
+}
+
+void run_qrcp(const QrcpTask* tasks, int32_t ntasks, const int2* wg_step, int32_t nstep,
+              const int2* wg_trsm, int32_t ntrsm, int32_t kmax, int32_t dmax, int32_t* flag,
+              GemmTask* gtasks, int32_t mcap_max, hipStream_t s) {
+  if (ntasks <= 0) return;
+  hipLaunchKernelGGL(k_qrcp_init, dim3(nstep), dim3(QB), 0, s, tasks, wg_step);
+  const size_t lds = (size_t)std::max(dmax, 1) * sizeof(double);
+  int32_t alive = 1;
+  for (int k = 0; k < kmax; ++k) {
+    if ((k % 32) == 0) {
+      HSS_HIP_CHECK(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
+      hipLaunchKernelGGL(k_qrcp_alive, dim3((ntasks + 127) / 128), dim3(128), 0, s, tasks, ntasks, k, flag);
+      HSS_HIP_CHECK(hipMemcpyAsync(&alive, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      HSS_HIP_CHECK(hipStreamSynchronize(s));
+      if (alive == 0) break;
+    }
+    hipLaunchKernelGGL(k_qrcp_step, dim3(nstep), dim3(QB), lds, s, tasks, wg_step, k);
+  }
+  HSS_HIP_CHECK(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
+  hipLaunchKernelGGL(k_qrcp_fin, dim3(ntasks), dim3(QB), 0, s, tasks, flag);
+  int32_t rmax = 0;
+  HSS_HIP_CHECK(hipMemcpyAsync(&rmax, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HSS_HIP_CHECK(hipStreamSynchronize(s));
+  for (int ib = (rmax + TRB - 1) / TRB - 1; ib >= 0; --ib) {
+    hipLaunchKernelGGL(k_trsm_diag, dim3(ntrsm), dim3(QB), 0, s, tasks, wg_trsm, ib, gtasks);
+    if (ib > 0) launch_gemm(gtasks, ntasks, ib * TRB, mcap_max, s);
+  }
+  HSS_HIP_CHECK(hipGetLastError());
+}
+
+}  // namespace hss
