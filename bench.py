@@ -1,0 +1,215 @@
+#!/usr/bin/env python
+"""Benchmark: adaptive randomized HSS compressions per second on one MI355X.
+
+Workload (default): dense Laplace kernel A_ij = 1/(4 pi |x_i - x_j|),
+A_ii = 1, n = 32768 points uniform on the unit sphere (seed 1), ordered by
+recursive coordinate bisection with leaf size 128, entries generated on the
+fly; incrementing strategy d0 = 128, delta_d = 64; rtol = 1e-6,
+atol = 1e-12, per-node safety factor eta = 0.1; FP64 throughout.  The
+Gaussian random matrix (seed 0, n x 4096) and the points are resident in
+HBM before the timed region.  One step = one full hss_compress call
+(sampling, extraction, local samples, stopping tests, IDs, reductions).
+
+Prints one JSON line.  `roofline` covers the kernel class with the largest
+measured GPU time (HIP events around every launch of one extra profiled
+compression); `cpu_baseline` times the CPU oracle on a bounded sample of
+the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "HSS compressions/s + sampling TFLOP/s at rel err≤1e-6; learned/mixed vs FP64"
+PEAK_FP64_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
+
+# kernel class -> (HIP kernel name, bound)
+KCLASS_INFO = {
+    "SAMPLE": ("k_sample_f64", "mfma"),
+    "GEMM": ("k_gemm_grouped", "mfma"),
+    "TEST_QR": ("k_fn_qr", "hbm"),
+    "QRCP_STEP": ("k_qrcp_step", "hbm"),
+    "GATHER": ("k_ls_gather/k_red_gather/k_fn_copy", "hbm"),
+    "EXTRACT": ("k_extract_nodes", "hbm"),
+    "TRSM": ("k_trsm_diag", "hbm"),
+    "SAMPLE_REDUCE": ("k_splitk_reduce", "hbm"),
+    "QRCP_OTHER": ("k_qrcp_init/k_qrcp_fin", "hbm"),
+    "MISC": ("k_plan/k_finalize/...", "hbm"),
+}
+
+WORKLOADS = {
+    "laplace-sphere-32768": dict(family="laplace", n=32768, leaf=128, method="rcb", points_seed=1,
+                                 strategy="inc_fnorm", d0=128, delta_d=64, d_max=4096),
+    "laplace-sphere-8192": dict(family="laplace", n=8192, leaf=128, method="rcb", points_seed=1,
+                                strategy="inc_fnorm", d0=128, delta_d=64, d_max=2048),
+    "toeplitz-1024": dict(family="toeplitz", n=1024, leaf=64, method="bisect", h=0.1,
+                          strategy="dbl_fnorm", d0=64, delta_d=64, d_max=1024),
+}
+
+
+def roofline(stats):
+    name = max((k for k in stats if stats[k]["ms"] > 0), key=lambda k: stats[k]["ms"])
+    s = stats[name]
+    kern, bound = KCLASS_INFO[name]
+    sec = s["ms"] / 1e3
+    if bound == "mfma":
+        ach = s["flops"] / sec / 1e12
+        peak, unit = PEAK_FP64_TFLOPS, "TFLOP/s"
+    else:
+        ach = s["bytes"] / sec / 1e9
+        peak, unit = PEAK_HBM_GBS, "GB/s"
+    return {"bound": bound, "achieved": round(ach, 3), "peak": peak, "unit": unit,
+            "frac": round(ach / peak, 5), "traffic": None, "kernel": kern, "class": name,
+            "launches": s["launches"], "avg_launch_us": round(1e3 * s["ms"] / max(1, s["launches"]), 3),
+            "share_of_profiled_gpu_time": round(s["ms"] / sum(v["ms"] for v in stats.values()), 4)}
+
+
+def cpu_baseline(W, d_final, budget_rows=16384):
+    """The oracle's sampling of one 64-column increment on `budget_rows` of the
+    n rows, scaled to a whole compression: n / budget_rows row blocks per
+    increment, d_final / 64 increments.  Counts sampling only, so the figure
+    is an upper bound on the oracle's compressions/s."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+
+    from oracle.operators import Laplace, PermutedOperator, Toeplitz
+    from oracle.tree import build_tree
+    from paper_1810_04125_amd import inputs
+
+    n = W["n"]
+    if W["family"] == "laplace":
+        pts = inputs.sphere_points(n, W["points_seed"])
+        ot = build_tree(n, W["leaf"], pts, W["method"])
+        op = PermutedOperator(Laplace(pts), ot.perm, block=512)
+    else:
+        ot = build_tree(n, W["leaf"])
+        op = PermutedOperator(Toeplitz(n, W["h"]), ot.perm, block=512)
+    rows = min(n, budget_rows)
+    R = inputs.gaussian_matrix(n, 64, 0)
+    cols = np.arange(n)
+    t0 = time.perf_counter()
+    for i0 in range(0, rows, op.block):
+        blk = op.extract(np.arange(i0, min(rows, i0 + op.block)), cols)
+        _ = blk @ R
+    el = time.perf_counter() - t0
+    est = el * (n / rows) * (d_final / 64.0)
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    return {"value": 1.0 / est, "unit": "compressions/s", "cores": threads, "kind": "oracle",
+            "sample": ("oracle dense-block sampling of one 64-column increment on %d of %d rows "
+                       "(%.1f s), scaled by %d/%d rows and d_final/64 = %d increments; sampling "
+                       "only, so an upper bound on the oracle's rate" %
+                       (rows, n, el, n, rows, d_final // 64))}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=8)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="laplace-sphere-32768", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-profile", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1810_04125_amd import hss, inputs
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    W = WORKLOADS[args.workload]
+    n = W["n"]
+    log = lambda m: print(m, file=sys.stderr, flush=True)
+    log("bench: workload %s" % args.workload)
+    if W["family"] == "laplace":
+        pts = inputs.sphere_points(n, W["points_seed"])
+        T = hss.Tree(n, W["leaf"], pts, W["method"])
+        gen = hss.laplace(torch.from_numpy(pts).cuda())
+    else:
+        T = hss.Tree(n, W["leaf"])
+        gen = hss.toeplitz(n, W["h"])
+    Rh = inputs.gaussian_matrix(n, W["d_max"], 0)
+    R = hss.colmajor(torch.from_numpy(np.ascontiguousarray(Rh.T)).cuda().t())
+    del Rh
+    kw = dict(rtol=1e-6, atol=1e-12, eta=0.1, strategy=W["strategy"], d0=W["d0"], delta_d=W["delta_d"],
+              d_max=W["d_max"])
+
+    for i in range(args.warmup):
+        H, st = hss.compress(gen, T, R, **kw)
+        log("bench: warmup %d done" % i)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        H, st = hss.compress(gen, T, R, **kw)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    info = H.info()
+    log("bench: timed %d steps in %.3f s; info %s" % (args.steps, el, info))
+
+    # accuracy: Gaussian-probe estimate ||(A - H) W||_F / ||A W||_F (64 probes),
+    # exact ||A - H||_F / ||A||_F for n <= 8192
+    Om = hss.colmajor(torch.from_numpy(np.ascontiguousarray(inputs.gaussian_matrix(n, 64, 7).T)).cuda().t())
+    perm = torch.from_numpy(T.perm).cuda()
+    inv = torch.empty_like(perm)
+    inv[perm] = torch.arange(n, device=perm.device)
+    AO_perm = hss.sample(gen, perm, hss.colmajor(Om[perm]))       # A_hat (P Om)
+    AO = AO_perm[inv]                                            # back to original order
+    HO = H.matvec(Om)
+    est = float(torch.linalg.norm(AO - HO) / torch.linalg.norm(AO))
+    exact = H.rel_error() if n <= 8192 else None
+    err = exact if exact is not None else est
+    log("bench: rel err estimate %.3e exact %s" % (est, exact))
+
+    rl = None
+    if not args.no_profile:
+        Hp, _ = hss.compress(gen, T, R, profile=True, **kw)
+        stats = Hp.kernel_stats()
+        rl = roofline(stats)
+        samp = stats["SAMPLE"]
+        rl["sampling_kernel"] = {"kernel": "k_sample_f64", "launches": samp["launches"],
+                                 "achieved_tflops": round(samp["flops"] / (samp["ms"] / 1e3) / 1e12, 3),
+                                 "frac_of_fp64_peak": round(samp["flops"] / (samp["ms"] / 1e3) / 1e12 /
+                                                            PEAK_FP64_TFLOPS, 4),
+                                 "avg_launch_us": round(1e3 * samp["ms"] / max(1, samp["launches"]), 3)}
+        rl["profiled_gpu_ms_by_class"] = {k: round(v["ms"], 2) for k, v in stats.items()}
+        log("bench: profile %s" % json.dumps(rl))
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(W, info["d_final"])
+        log("bench: cpu baseline %s" % cpu)
+
+    value = args.steps / el
+    out = {
+        "metric": METRIC, "value": round(value, 4), "unit": "compressions/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * el / args.steps, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "leaf": W["leaf"], "tree": W["method"],
+                   "strategy": W["strategy"], "d0": W["d0"], "delta_d": W["delta_d"], "rtol": 1e-6,
+                   "atol": 1e-12, "eta": 0.1, "d_max": W["d_max"], "sampling": "fp64"},
+        "rel_err": err, "rel_err_kind": "exact" if exact is not None else "64-probe estimate",
+        "rel_err_ok": bool(err <= 1e-6),
+        "sampling_tflops": round(info["sample_flops"] / (info["sample_ms"] / 1e3) / 1e12, 3),
+        "rounds": info["rounds"], "d_final": info["d_final"], "hss_rank": info["hss_rank"],
+        "roofline": rl, "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -144,7 +144,7 @@ typedef struct {
   const double* R;
   int64_t ldr;
   int32_t ncols_R;
-  int32_t reserved;
+  int32_t profile;   /* 1: time every kernel launch with HIP events (slower; see hss_get_kernel_stats) */
   void* stream;
 } hss_options;
 
@@ -194,6 +194,32 @@ typedef struct {
 } hss_info;
 
 hss_status hss_get_info(const hss_matrix* h, hss_info* out);
+
+/* Per kernel class of the job that produced h: launches, GPU time
+ * (summed HIP-event time around each launch, only when the compression
+ * ran with options.profile = 1, else 0) and the algorithmic bytes and
+ * flops the launches had to move / perform by their definition:
+ *   SAMPLE       2 n^2 c flops, 16 n c + 24 n bytes per c sampled columns
+ *   GEMM         2 M N K flops, 8 (MK + KN + MN [+ MN if accumulating]) bytes
+ *   TEST_QR      Householder QR of the projected block (m x b): 2 m b^2 flops
+ *                (4 m b^2 when Q_k is formed), 8 m b (2 or 3) bytes
+ *   QRCP_STEP    one pivot step on the (d-k) x (m-k-1) trailing panel:
+ *                4 (d-k)(m-k-1) flops, 16 (d-k)(m-k-1) bytes
+ *   GATHER       copies of local samples / reduced random matrices: 16 bytes per entry
+ *   EXTRACT      8 bytes per generated entry
+ *   TRSM         diagonal blocks of the back substitution for E */
+enum {
+  HSS_K_SAMPLE = 0, HSS_K_SAMPLE_REDUCE = 1, HSS_K_EXTRACT = 2, HSS_K_GATHER = 3, HSS_K_GEMM = 4,
+  HSS_K_TEST_QR = 5, HSS_K_QRCP_STEP = 6, HSS_K_QRCP_OTHER = 7, HSS_K_TRSM = 8, HSS_K_MISC = 9,
+  HSS_K_COUNT = 10
+};
+typedef struct {
+  int64_t launches;
+  double ms;
+  double bytes;
+  double flops;
+} hss_kernel_stats;
+hss_status hss_get_kernel_stats(const hss_matrix* h, int32_t kclass, hss_kernel_stats* out);
 
 typedef struct {
   int32_t state;   /* 0 UNTOUCHED, 1 PARTIALLY_COMPRESSED, 2 COMPRESSED */

@@ -203,6 +203,15 @@ hss_status hss_get_info(const hss_matrix* h, hss_info* out) {
   });
 }
 
+hss_status hss_get_kernel_stats(const hss_matrix* h, int32_t kclass, hss_kernel_stats* out) {
+  return guarded([&]() -> hss_status {
+    if (!h || !out) throw Error(HSS_ERR_INVALID_ARG, "NULL argument");
+    if (kclass < 0 || kclass >= HSS_K_COUNT) throw Error(HSS_ERR_INVALID_ARG, "unknown kernel class");
+    *out = h->job->kstats[kclass];
+    return HSS_OK;
+  });
+}
+
 hss_status hss_get_node_info(const hss_matrix* h, int32_t node, hss_node_info* out) {
   return guarded([&]() -> hss_status {
     if (!h || !out) throw Error(HSS_ERR_INVALID_ARG, "NULL argument");

@@ -21,12 +21,37 @@
 
 namespace hss {
 
+thread_local Prof* g_prof = nullptr;
+
+void prof_begin(hipStream_t s) {
+  if (g_prof && g_prof->on) hipEventRecord(g_prof->e0, s);
+}
+
+void prof_end(int cls, hipStream_t s) {
+  if (!g_prof) return;
+  g_prof->launches[cls]++;
+  if (!g_prof->on) return;
+  hipEventRecord(g_prof->e1, s);
+  hipEventSynchronize(g_prof->e1);
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, g_prof->e0, g_prof->e1) == hipSuccess) g_prof->ms[cls] += ms;
+}
+
+// Makes the job's profiler current for the calling thread while alive.
+struct ProfScope {
+  Prof* saved;
+  explicit ProfScope(Prof* p) : saved(g_prof) { g_prof = p; }
+  ~ProfScope() { g_prof = saved; }
+};
+
 static int64_t align8(int64_t x) { return (x + 7) & ~int64_t(7); }
 
 Job::~Job() {
   for (void* p : allocs) hipFree(p);
   if (ev0) hipEventDestroy(ev0);
   if (ev1) hipEventDestroy(ev1);
+  if (prof.e0) hipEventDestroy(prof.e0);
+  if (prof.e1) hipEventDestroy(prof.e1);
 }
 
 void* Job::dalloc(size_t bytes) {
@@ -94,6 +119,10 @@ void Job::setup(int32_t count, const hss_generator* gens, const hss_tree* const*
   }
   HSS_HIP_CHECK(hipEventCreate(&ev0));
   HSS_HIP_CHECK(hipEventCreate(&ev1));
+  HSS_HIP_CHECK(hipEventCreate(&prof.e0));
+  HSS_HIP_CHECK(hipEventCreate(&prof.e1));
+  prof.on = false;
+  for (int k = 0; k < count; ++k) prof.on = prof.on || opts[k].profile != 0;
   probs.resize(count);
   int64_t dtot = 0, itot = 0, ltot = 0;
   int32_t gnodes = 0;
@@ -214,6 +243,8 @@ void Job::setup(int32_t count, const hss_generator* gens, const hss_tree* const*
     HSS_HIP_CHECK(hipMemcpy(L.wg_trsm, qp.trsm.data(), sizeof(int2) * qp.trsm.size(), hipMemcpyHostToDevice));
   }
   flags_d = (int32_t*)dalloc(sizeof(int32_t) * 4);
+  kcnt_d = (unsigned long long*)dalloc(sizeof(unsigned long long) * 2 * HSS_K_COUNT);
+  HSS_HIP_CHECK(hipMemset(kcnt_d, 0, sizeof(unsigned long long) * 2 * HSS_K_COUNT));
   nodes_d = (int32_t*)dalloc(sizeof(int32_t) * gnodes);
   {
     std::vector<int64_t> mo(gnodes);
@@ -284,7 +315,9 @@ void Job::sample(Problem& P, int32_t c0, int32_t ncols) {
   HSS_HIP_CHECK(hipEventRecord(ev0, stream));
   for (int s = 0; s < (P.sym ? 1 : 2); ++s) {
     launch_sample(P.dev.gen, s, prec, P.opt.R + (int64_t)c0 * P.opt.ldr, P.opt.ldr,
-                  dpool + P.sglob[s] + (int64_t)c0 * P.n, P.n, ncols, partial, stream);
+                  dpool + P.sglob[s] + (int64_t)c0 * P.n, P.n, ncols, partial, stream, kcnt_d);
+    host_flops[HSS_K_SAMPLE] += 2.0 * (double)P.n * (double)P.n * ncols;
+    host_bytes[HSS_K_SAMPLE] += 16.0 * (double)P.n * ncols + 24.0 * (double)P.n;
   }
   HSS_HIP_CHECK(hipEventRecord(ev1, stream));
   HSS_HIP_CHECK(hipGetLastError());
@@ -310,6 +343,7 @@ void Job::run_level(int lev, int32_t ncap) {
   a.wsB = wsb;
   a.tasks = tasks_d;
   a.flags = flags_d;
+  a.kcnt = kcnt_d;
   const int nsides = all_sym ? 1 : 2;
   const int32_t nc = std::min(ncap, L.dcap);
   HSS_HIP_CHECK(hipMemsetAsync(flags_d + 1, 0, sizeof(int32_t), stream));
@@ -320,7 +354,7 @@ void Job::run_level(int lev, int32_t ncap) {
     for (int s = 0; s < nsides; ++s) {
       launch_build_qrcp(a, s, hmt, qtasks_d, stream);
       run_qrcp(qtasks_d, a.count, L.wg_step, L.nstep, L.wg_trsm, L.ntrsm, std::min(L.mcap, ncap), ncap,
-               flags_d + 2, tasks_d, L.mcap, stream);
+               flags_d + 2, tasks_d, L.mcap, stream, kcnt_d);
     }
   };
   if (strategy == HSS_DBL_HMT) {
@@ -342,6 +376,7 @@ void Job::run_level(int lev, int32_t ncap) {
 }
 
 void Job::compress() {
+  ProfScope scope(&prof);
   auto t0 = std::chrono::steady_clock::now();
   all_sym = true;
   for (auto& P : probs) all_sym = all_sym && P.sym;
@@ -410,7 +445,15 @@ void Job::compress() {
   }
   st_h.resize(desc.size());
   HSS_HIP_CHECK(hipMemcpyAsync(st_h.data(), st_d, sizeof(NodeState) * desc.size(), hipMemcpyDeviceToHost, stream));
+  unsigned long long kc[2 * HSS_K_COUNT];
+  HSS_HIP_CHECK(hipMemcpyAsync(kc, kcnt_d, sizeof(kc), hipMemcpyDeviceToHost, stream));
   HSS_HIP_CHECK(hipStreamSynchronize(stream));
+  for (int c = 0; c < HSS_K_COUNT; ++c) {
+    kstats[c].launches = prof.launches[c];
+    kstats[c].ms = prof.ms[c];
+    kstats[c].bytes = (double)kc[2 * c] + host_bytes[c];
+    kstats[c].flops = (double)kc[2 * c + 1] + host_flops[c];
+  }
   total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
 

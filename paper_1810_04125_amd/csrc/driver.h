@@ -62,6 +62,10 @@ struct Job {
   int64_t mvtot = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   double sample_ms = 0.0, sample_flops = 0.0, total_ms = 0.0;
+  Prof prof;
+  unsigned long long* kcnt_d = nullptr;     // device algorithmic counters
+  hss_kernel_stats kstats[HSS_K_COUNT] = {};
+  double host_bytes[HSS_K_COUNT] = {}, host_flops[HSS_K_COUNT] = {};
 
   ~Job();
   void* dalloc(size_t bytes);

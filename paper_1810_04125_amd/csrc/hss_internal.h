@@ -139,7 +139,27 @@ struct QrcpPlan {
 QrcpPlan make_qrcp_plan(const std::vector<int32_t>& mcaps);
 void run_qrcp(const QrcpTask* tasks, int32_t ntasks, const int2* wg_step, int32_t nstep,
               const int2* wg_trsm, int32_t ntrsm, int32_t kmax, int32_t dmax, int32_t* flag,
-              GemmTask* gtasks, int32_t mcap_max, hipStream_t s);
+              GemmTask* gtasks, int32_t mcap_max, hipStream_t s, unsigned long long* kcnt = nullptr);
+
+// ------------------------------------------------------------------ profiling
+// Launch counts and (in profile mode) HIP-event time per kernel class; the
+// algorithmic bytes / flops are accumulated on the device in kcnt[2 * class
+// + {0, 1}] (unsigned 64-bit).
+struct Prof {
+  bool on = false;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  double ms[HSS_K_COUNT] = {};
+  int64_t launches[HSS_K_COUNT] = {};
+};
+extern thread_local Prof* g_prof;
+void prof_begin(hipStream_t s);
+void prof_end(int cls, hipStream_t s);
+
+__device__ __forceinline__ void kcount(unsigned long long* kc, int cls, double bytes, double flops) {
+  if (!kc) return;
+  atomicAdd(kc + 2 * cls, (unsigned long long)bytes);
+  atomicAdd(kc + 2 * cls + 1, (unsigned long long)flops);
+}
 
 // ------------------------------------------------------------------ launchers
 void launch_toeplitz_table(double* t, int64_t n, double h, hipStream_t s);
@@ -151,11 +171,11 @@ int sample_splits(int64_t n, int32_t ncols);
 size_t sample_partial_elems(int64_t n, int32_t ncols);
 void launch_sample(const GenDev& g, int32_t transpose, int32_t precision, const double* R,
                    int64_t ldr, double* S, int64_t lds, int32_t ncols, double* partial,
-                   hipStream_t s);
+                   hipStream_t s, unsigned long long* kcnt = nullptr);
 void launch_extract(const GenDev& g, int32_t nI, const int64_t* I, int32_t nJ, const int64_t* J,
                     double* out, int64_t ldo, hipStream_t s);
 void launch_gemm(const GemmTask* tasks, int32_t ntasks, int32_t mcap, int32_t ncap,
-                 hipStream_t s);
+                 hipStream_t s, unsigned long long* kcnt = nullptr);
 
 struct LevelArgs {
   const NodeDesc* desc;
@@ -170,6 +190,7 @@ struct LevelArgs {
   double* wsB;
   GemmTask* tasks;       // scratch task array, capacity >= 2 * count
   int32_t* flags;        // device error flags
+  unsigned long long* kcnt;  // algorithmic byte / flop counters
 };
 
 void launch_plan(const LevelArgs& a, hipStream_t s);

@@ -18,10 +18,15 @@ constexpr int GT = 64;   // output tile
 constexpr int GK = 16;   // K tile
 constexpr int GLD = GT + 2;
 
-__global__ __launch_bounds__(256) void k_gemm_grouped(const GemmTask* __restrict__ tasks) {
+__global__ __launch_bounds__(256) void k_gemm_grouped(const GemmTask* __restrict__ tasks,
+                                                     unsigned long long* __restrict__ kcnt) {
   const GemmTask t = tasks[blockIdx.z];
   const int tm = blockIdx.y, tn = blockIdx.x;
   if (t.M <= 0 || t.N <= 0) return;
+  if (tm == 0 && tn == 0 && threadIdx.x == 0) {
+    const double M = t.M, N = t.N, K = t.K;
+    kcount(kcnt, HSS_K_GEMM, 8.0 * (M * K + K * N + M * N * (t.beta == 0.0 ? 1.0 : 2.0)), 2.0 * M * N * K);
+  }
   if (tm * GT >= t.M || tn * GT >= t.N) return;
   __shared__ double As[GK][GLD];
   __shared__ double Bs[GK][GLD];
@@ -83,10 +88,13 @@ __global__ __launch_bounds__(256) void k_gemm_grouped(const GemmTask* __restrict
       }
 }
 
-void launch_gemm(const GemmTask* tasks, int32_t ntasks, int32_t mcap, int32_t ncap, hipStream_t s) {
+void launch_gemm(const GemmTask* tasks, int32_t ntasks, int32_t mcap, int32_t ncap, hipStream_t s,
+                 unsigned long long* kcnt) {
   if (ntasks <= 0 || mcap <= 0 || ncap <= 0) return;
   dim3 grid((unsigned)((ncap + GT - 1) / GT), (unsigned)((mcap + GT - 1) / GT), (unsigned)ntasks);
-  hipLaunchKernelGGL(k_gemm_grouped, grid, dim3(256), 0, s, tasks);
+  prof_begin(s);
+  hipLaunchKernelGGL(k_gemm_grouped, grid, dim3(256), 0, s, tasks, kcnt);
+  prof_end(HSS_K_GEMM, s);
 }
 
 }  // namespace hss

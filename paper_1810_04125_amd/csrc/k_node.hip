@@ -99,7 +99,9 @@ __global__ void k_plan(LevelArgs a) {
 
 void launch_plan(const LevelArgs& a, hipStream_t s) {
   if (a.count <= 0) return;
+  prof_begin(s);
   hipLaunchKernelGGL(k_plan, dim3((a.count + 127) / 128), dim3(128), 0, s, a);
+  prof_end(HSS_K_MISC, s);
 }
 
 // ------------------------------------------------------------------ extraction
@@ -148,11 +150,20 @@ __global__ __launch_bounds__(NB) void k_extract_nodes(LevelArgs a) {
     }
   }
   if (bad) atomicOr(a.flags, 1);
+  if (threadIdx.x == 0) {
+    double ent;
+    if (nd.leaf) ent = (double)(nd.hi - nd.lo) * (nd.hi - nd.lo);
+    else ent = (double)a.st[nd.left].rank[0] * a.st[nd.right].rank[1] +
+               (double)a.st[nd.right].rank[0] * a.st[nd.left].rank[1];
+    kcount(a.kcnt, HSS_K_EXTRACT, 8.0 * ent, 0.0);
+  }
 }
 
 void launch_extract_nodes(const LevelArgs& a, hipStream_t s) {
   if (a.count <= 0) return;
+  prof_begin(s);
   hipLaunchKernelGGL(k_extract_nodes, dim3(a.count), dim3(NB), 0, s, a);
+  prof_end(HSS_K_EXTRACT, s);
 }
 
 // ------------------------------------------------------------------ local samples
@@ -175,6 +186,7 @@ __global__ __launch_bounds__(NB) void k_ls_gather(LevelArgs a, int side) {
   const int c0 = st.c0, nc = st.nc;
   const int m = st.m[side];
   double* S = dp(a, nd.S[side]);
+  if (threadIdx.x == 0) kcount(a.kcnt, HSS_K_GATHER, 16.0 * m * nc, 0.0);
   if (nd.leaf) {
     const double* Sg = cdp(a, P.sglob[side]);
     for (int64_t idx = threadIdx.x; idx < (int64_t)m * nc; idx += NB) {
@@ -243,8 +255,10 @@ void launch_local_samples(const LevelArgs& a, int side, int32_t mcap_max, int32_
                           int32_t ncap, hipStream_t s) {
   (void)rcap_max;
   if (a.count <= 0) return;
+  prof_begin(s);
   hipLaunchKernelGGL(k_ls_gather, dim3(a.count), dim3(NB), 0, s, a, side);
-  launch_gemm(a.tasks, 2 * a.count, mcap_max, ncap, s);
+  prof_end(HSS_K_GATHER, s);
+  launch_gemm(a.tasks, 2 * a.count, mcap_max, ncap, s, a.kcnt);
 }
 
 // ------------------------------------------------------------------ F-norm test
@@ -285,6 +299,7 @@ __global__ __launch_bounds__(NB) void k_fn_copy(LevelArgs a, int side, int iter)
   if (!s_go) return;
   const ProbDev& P = a.prob[nd.prob];
   const int dcap = P.dcap, m = st.m[side], nc = st.bnc, c0 = st.bc0, q = st.q[side];
+  if (threadIdx.x == 0) kcount(a.kcnt, HSS_K_GATHER, 16.0 * m * nc, 0.0);
   const double* S = cdp(a, nd.S[side]);
   double* Sh = a.wsA + nd.ws;
   for (int64_t idx = threadIdx.x; idx < (int64_t)m * nc; idx += NB) {
@@ -341,7 +356,10 @@ __global__ __launch_bounds__(NB) void k_fn_qr(LevelArgs a, int side) {
   const double nS = sqrt(block_sum(p1, red));
   const double nSh = sqrt(block_sum(p2, red));
   if (nS == 0.0 || nSh < er * nS || nSh / sqrt((double)nc) < ea) {
-    if (threadIdx.x == 0) st.passed[side] = 1;
+    if (threadIdx.x == 0) {
+      st.passed[side] = 1;
+      kcount(a.kcnt, HSS_K_TEST_QR, 16.0 * m * nc, 4.0 * m * nc);
+    }
     return;
   }
   // Householder QR, column by column
@@ -378,6 +396,9 @@ __global__ __launch_bounds__(NB) void k_fn_qr(LevelArgs a, int side) {
     if (st.rho[side] < 0.0) st.rho[side] = fabs(alph[0]);
     s_pass = (mn < ea || mn < er * st.rho[side]) ? 1 : 0;
     if (s_pass) st.passed[side] = 1;
+    const double mm = m, b = nc;
+    kcount(a.kcnt, HSS_K_TEST_QR, 8.0 * mm * b * (s_pass ? 2.0 : 3.0),
+           (s_pass ? 2.0 : 4.0) * mm * b * b);
   }
   __syncthreads();
   if (s_pass) return;
@@ -407,12 +428,16 @@ __global__ __launch_bounds__(NB) void k_fn_qr(LevelArgs a, int side) {
 void launch_fnorm_test(const LevelArgs& a, int side, int32_t iter, int32_t mcap_max, int32_t qcap_max,
                        int32_t ncap, hipStream_t s) {
   if (a.count <= 0) return;
+  prof_begin(s);
   hipLaunchKernelGGL(k_fn_copy, dim3(a.count), dim3(NB), 0, s, a, side, iter);
+  prof_end(HSS_K_GATHER, s);
   for (int pass = 0; pass < 2; ++pass) {  // block Gram-Schmidt, twice
-    launch_gemm(a.tasks, a.count, qcap_max, ncap, s);
-    launch_gemm(a.tasks + a.count, a.count, mcap_max, ncap, s);
+    launch_gemm(a.tasks, a.count, qcap_max, ncap, s, a.kcnt);
+    launch_gemm(a.tasks + a.count, a.count, mcap_max, ncap, s, a.kcnt);
   }
+  prof_begin(s);
   hipLaunchKernelGGL(k_fn_qr, dim3(a.count), dim3(NB), 0, s, a, side);
+  prof_end(HSS_K_TEST_QR, s);
 }
 
 __global__ void k_decide_fnorm(LevelArgs a) {
@@ -428,7 +453,9 @@ __global__ void k_decide_fnorm(LevelArgs a) {
 
 void launch_decide_fnorm(const LevelArgs& a, hipStream_t s) {
   if (a.count <= 0) return;
+  prof_begin(s);
   hipLaunchKernelGGL(k_decide_fnorm, dim3((a.count + 127) / 128), dim3(128), 0, s, a);
+  prof_end(HSS_K_MISC, s);
 }
 
 // ------------------------------------------------------------------ QRCP / ID
@@ -466,7 +493,9 @@ __global__ void k_build_qrcp(LevelArgs a, int side, int hmt, QrcpTask* __restric
 
 void launch_build_qrcp(const LevelArgs& a, int side, int32_t hmt, QrcpTask* out, hipStream_t s) {
   if (a.count <= 0) return;
+  prof_begin(s);
   hipLaunchKernelGGL(k_build_qrcp, dim3((a.count + 127) / 128), dim3(128), 0, s, a, side, hmt, out);
+  prof_end(HSS_K_MISC, s);
 }
 
 __global__ void k_decide_hmt(LevelArgs a) {
@@ -484,7 +513,9 @@ __global__ void k_decide_hmt(LevelArgs a) {
 
 void launch_decide_hmt(const LevelArgs& a, hipStream_t s) {
   if (a.count <= 0) return;
+  prof_begin(s);
   hipLaunchKernelGGL(k_decide_hmt, dim3((a.count + 127) / 128), dim3(128), 0, s, a);
+  prof_end(HSS_K_MISC, s);
 }
 
 // ------------------------------------------------------------------ reduce
@@ -506,6 +537,7 @@ __global__ __launch_bounds__(NB) void k_red_gather(LevelArgs a, int side) {
   const int m = st.m[side], r = st.rank[side];
   const int32_t* J = a.ipool + nd.J[side];
   double* RR = dp(a, nd.RR[side]);
+  if (threadIdx.x == 0) kcount(a.kcnt, HSS_K_GATHER, 16.0 * m * nc, 0.0);
   double* Xr = a.wsA + nd.ws;  // (m - r) x nc, column-major, ld = mcap
   int r1 = 0;
   const double *X1 = nullptr, *X2 = nullptr;
@@ -547,8 +579,10 @@ void launch_reduce(const LevelArgs& a, int side, int32_t mcap_max, int32_t rcap_
                    int32_t ncap, hipStream_t s) {
   (void)mcap_max;
   if (a.count <= 0) return;
+  prof_begin(s);
   hipLaunchKernelGGL(k_red_gather, dim3(a.count), dim3(NB), 0, s, a, side);
-  launch_gemm(a.tasks, a.count, rcap_max, ncap, s);
+  prof_end(HSS_K_GATHER, s);
+  launch_gemm(a.tasks, a.count, rcap_max, ncap, s, a.kcnt);
 }
 
 // ------------------------------------------------------------------ finalize
@@ -576,7 +610,9 @@ __global__ void k_finalize(LevelArgs a) {
 
 void launch_finalize(const LevelArgs& a, hipStream_t s) {
   if (a.count <= 0) return;
+  prof_begin(s);
   hipLaunchKernelGGL(k_finalize, dim3((a.count + 127) / 128), dim3(128), 0, s, a);
+  prof_end(HSS_K_MISC, s);
 }
 
 }  // namespace hss

@@ -71,7 +71,7 @@ __global__ __launch_bounds__(QB) void k_qrcp_init(const QrcpTask* __restrict__ t
 }
 
 __global__ __launch_bounds__(QB) void k_qrcp_step(const QrcpTask* __restrict__ tasks, const int2* __restrict__ wg,
-                                                  int k) {
+                                                  int k, unsigned long long* __restrict__ kcnt) {
   extern __shared__ double vsh[];
   __shared__ double rv[QW];
   __shared__ int ri[QW];
@@ -128,6 +128,8 @@ __global__ __launch_bounds__(QB) void k_qrcp_step(const QrcpTask* __restrict__ t
     if (k == 0) c->nu1 = nu;
     rdiag_of(t)[k] = alpha;
     t.J[k] = p;
+    const double cells = (double)(d - k) * (double)(m - k - 1);
+    kcount(kcnt, HSS_K_QRCP_STEP, 16.0 * cells, 4.0 * cells);
   }
   __syncthreads();
   const int jend = min(m, w.y + QCPW);
@@ -195,7 +197,8 @@ __global__ __launch_bounds__(QB) void k_qrcp_fin(const QrcpTask* __restrict__ ta
 // columns [c0, c0 + QB) of E; the workgroup with c0 == 0 also writes the
 // GEMM task of the update E(0:i0, :) -= R1(0:i0, i0:i1) E(i0:i1, :).
 __global__ __launch_bounds__(QB) void k_trsm_diag(const QrcpTask* __restrict__ tasks, const int2* __restrict__ wg,
-                                                  int ib, GemmTask* __restrict__ gt) {
+                                                  int ib, GemmTask* __restrict__ gt,
+                                                  unsigned long long* __restrict__ kcnt) {
   __shared__ double T[TRB][TRB + 1];
   const int2 w = wg[blockIdx.x];
   const QrcpTask& t = tasks[w.x];
@@ -236,6 +239,7 @@ __global__ __launch_bounds__(QB) void k_trsm_diag(const QrcpTask* __restrict__ t
     for (int ii = 0; ii < TRB; ++ii)
       if (ii < nb) e[ii] = x[ii];
   }
+  if (w.y == 0 && threadIdx.x == 0) kcount(kcnt, HSS_K_TRSM, 16.0 * nb * nrest, (double)nb * nb * nrest);
   if (w.y == 0 && threadIdx.x == 0 && i0 > 0 && nrest > 0) {
     GemmTask q;
     q.A = t.W; q.a_rs = 1; q.a_cs = t.ldw; q.a_cols = t.J + i0;
@@ -259,9 +263,11 @@ QrcpPlan make_qrcp_plan(const std::vector<int32_t>& mcaps) {
 
 void run_qrcp(const QrcpTask* tasks, int32_t ntasks, const int2* wg_step, int32_t nstep,
               const int2* wg_trsm, int32_t ntrsm, int32_t kmax, int32_t dmax, int32_t* flag,
-              GemmTask* gtasks, int32_t mcap_max, hipStream_t s) {
+              GemmTask* gtasks, int32_t mcap_max, hipStream_t s, unsigned long long* kcnt) {
   if (ntasks <= 0) return;
+  prof_begin(s);
   hipLaunchKernelGGL(k_qrcp_init, dim3(nstep), dim3(QB), 0, s, tasks, wg_step);
+  prof_end(HSS_K_QRCP_OTHER, s);
   const size_t lds = (size_t)std::max(dmax, 1) * sizeof(double);
   int32_t alive = 1;
   for (int k = 0; k < kmax; ++k) {
@@ -272,16 +278,22 @@ void run_qrcp(const QrcpTask* tasks, int32_t ntasks, const int2* wg_step, int32_
       HSS_HIP_CHECK(hipStreamSynchronize(s));
       if (alive == 0) break;
     }
-    hipLaunchKernelGGL(k_qrcp_step, dim3(nstep), dim3(QB), lds, s, tasks, wg_step, k);
+    prof_begin(s);
+    hipLaunchKernelGGL(k_qrcp_step, dim3(nstep), dim3(QB), lds, s, tasks, wg_step, k, kcnt);
+    prof_end(HSS_K_QRCP_STEP, s);
   }
   HSS_HIP_CHECK(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
+  prof_begin(s);
   hipLaunchKernelGGL(k_qrcp_fin, dim3(ntasks), dim3(QB), 0, s, tasks, flag);
+  prof_end(HSS_K_QRCP_OTHER, s);
   int32_t rmax = 0;
   HSS_HIP_CHECK(hipMemcpyAsync(&rmax, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HSS_HIP_CHECK(hipStreamSynchronize(s));
   for (int ib = (rmax + TRB - 1) / TRB - 1; ib >= 0; --ib) {
-    hipLaunchKernelGGL(k_trsm_diag, dim3(ntrsm), dim3(QB), 0, s, tasks, wg_trsm, ib, gtasks);
-    if (ib > 0) launch_gemm(gtasks, ntasks, ib * TRB, mcap_max, s);
+    prof_begin(s);
+    hipLaunchKernelGGL(k_trsm_diag, dim3(ntrsm), dim3(QB), 0, s, tasks, wg_trsm, ib, gtasks, kcnt);
+    prof_end(HSS_K_TRSM, s);
+    if (ib > 0) launch_gemm(gtasks, ntasks, ib * TRB, mcap_max, s, kcnt);
   }
   HSS_HIP_CHECK(hipGetLastError());
 }

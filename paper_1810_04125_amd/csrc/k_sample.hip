@@ -183,7 +183,8 @@ void launch_sample_f32(const GenDev& g, int32_t transpose, int32_t bf16x3, const
 
 void launch_sample(const GenDev& g, int32_t transpose, int32_t precision, const double* R,
                    int64_t ldr, double* S, int64_t lds, int32_t ncols, double* partial,
-                   hipStream_t s) {
+                   hipStream_t s, unsigned long long* kcnt) {
+  (void)kcnt;
   if (ncols <= 0 || g.n <= 0) return;
   if (precision != HSS_SAMPLE_FP64) {
     launch_sample_f32(g, transpose, precision == HSS_SAMPLE_BF16X3, R, ldr, S, lds, ncols,
@@ -198,17 +199,21 @@ void launch_sample(const GenDev& g, int32_t transpose, int32_t precision, const 
   dim3 grid((unsigned)((n + SM_ROWS - 1) / SM_ROWS), (unsigned)((ncols + SM_COLS - 1) / SM_COLS),
             (unsigned)nz);
   double* out = nz == 1 ? S : partial;
+  prof_begin(s);
   switch (g.family) {
     case HSS_FAM_TOEPLITZ: launch_fam<HSS_FAM_TOEPLITZ>(g, transpose, R, ldr, out, lds, ncols, kchunk, nz, grid, s); break;
     case HSS_FAM_LAPLACE: launch_fam<HSS_FAM_LAPLACE>(g, transpose, R, ldr, out, lds, ncols, kchunk, nz, grid, s); break;
     case HSS_FAM_GAUSS: launch_fam<HSS_FAM_GAUSS>(g, transpose, R, ldr, out, lds, ncols, kchunk, nz, grid, s); break;
     default: launch_fam<HSS_FAM_DENSE>(g, transpose, R, ldr, out, lds, ncols, kchunk, nz, grid, s); break;
   }
+  prof_end(HSS_K_SAMPLE, s);
   if (nz > 1) {
     const int64_t ncp = (int64_t)grid.y * SM_COLS;
     const int64_t tot = n * ncols;
+    prof_begin(s);
     hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
                        partial, n, ncols, ncp, nz, S, lds);
+    prof_end(HSS_K_SAMPLE_REDUCE, s);
   }
 }
 

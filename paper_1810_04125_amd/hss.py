@@ -50,7 +50,7 @@ class _Opt(C.Structure):
                 ("strategy", C.c_int32), ("d0", C.c_int32), ("delta_d", C.c_int32),
                 ("oversample_p", C.c_int32), ("d_max", C.c_int32), ("sample_precision", C.c_int32),
                 ("R", C.c_void_p), ("ldr", C.c_int64), ("ncols_R", C.c_int32),
-                ("reserved", C.c_int32), ("stream", C.c_void_p)]
+                ("profile", C.c_int32), ("stream", C.c_void_p)]
 
 
 class _Info(C.Structure):
@@ -58,6 +58,14 @@ class _Info(C.Structure):
                 ("d_final", C.c_int32), ("hss_rank", C.c_int32), ("status", C.c_int32),
                 ("symmetric", C.c_int32), ("sample_ms", C.c_double), ("total_ms", C.c_double),
                 ("sample_flops", C.c_double)]
+
+
+class _KStats(C.Structure):
+    _fields_ = [("launches", C.c_int64), ("ms", C.c_double), ("bytes", C.c_double), ("flops", C.c_double)]
+
+
+KCLASS = ["SAMPLE", "SAMPLE_REDUCE", "EXTRACT", "GATHER", "GEMM", "TEST_QR", "QRCP_STEP", "QRCP_OTHER",
+          "TRSM", "MISC"]
 
 
 class _NodeInfo(C.Structure):
@@ -69,7 +77,8 @@ _lib = None
 
 EXPORTS = ["hss_tree_build", "hss_tree_free", "hss_compress", "hss_compress_batched", "hss_destroy",
            "hss_matvec", "hss_rel_error", "hss_get_info", "hss_get_node_info", "hss_copy_node",
-           "hss_sample", "hss_extract", "hss_interpolative_batched", "hss_last_error", "hss_version"]
+           "hss_sample", "hss_extract", "hss_interpolative_batched", "hss_last_error", "hss_version",
+           "hss_get_kernel_stats"]
 
 
 def lib():
@@ -96,6 +105,7 @@ def lib():
     L.hss_rel_error.argtypes = [vp, C.POINTER(_Gen), C.POINTER(dbl)]
     L.hss_get_info.argtypes = [vp, C.POINTER(_Info)]
     L.hss_get_node_info.argtypes = [vp, i32, C.POINTER(_NodeInfo)]
+    L.hss_get_kernel_stats.argtypes = [vp, i32, C.POINTER(_KStats)]
     L.hss_copy_node.argtypes = [vp, i32, i32, vp, C.c_size_t]
     L.hss_sample.argtypes = [C.POINTER(_Gen), vp, i32, vp, i64, vp, i64, i32, i32, vp]
     L.hss_extract.argtypes = [C.POINTER(_Gen), vp, i32, vp, i32, vp, vp, i64, vp]
@@ -233,6 +243,15 @@ class HSSMatrix:
         _check(lib().hss_get_info(self._h, C.byref(inf)))
         return {k: getattr(inf, k) for k, _ in _Info._fields_}
 
+    def kernel_stats(self) -> dict:
+        """{class: {launches, ms, bytes, flops}} of the compression (ms only in profile mode)."""
+        out = {}
+        for i, name in enumerate(KCLASS):
+            k = _KStats()
+            _check(lib().hss_get_kernel_stats(self._h, i, C.byref(k)))
+            out[name] = {f: getattr(k, f) for f, _ in _KStats._fields_}
+        return out
+
     def node_info(self, node) -> dict:
         ni = _NodeInfo()
         _check(lib().hss_get_node_info(self._h, node, C.byref(ni)))
@@ -288,7 +307,7 @@ class HSSMatrix:
         return e.value
 
 
-def _opts(R, rtol, atol, eta, strategy, d0, delta_d, p, d_max, precision):
+def _opts(R, rtol, atol, eta, strategy, d0, delta_d, p, d_max, precision, profile=False):
     ldr = _colmajor(R, "R")
     o = _Opt()
     o.rtol, o.atol, o.eta = rtol, atol, eta
@@ -299,16 +318,17 @@ def _opts(R, rtol, atol, eta, strategy, d0, delta_d, p, d_max, precision):
     o.R = R.data_ptr()
     o.ldr = ldr
     o.ncols_R = R.shape[1]
+    o.profile = int(bool(profile))
     o.stream = _stream()
     return o
 
 
 def compress(gen: Generator, tree: Tree, R, rtol=1e-6, atol=1e-12, eta=1.0, strategy="dbl_fnorm",
-             d0=64, delta_d=64, p=10, d_max=None, precision="fp64"):
+             d0=64, delta_d=64, p=10, d_max=None, precision="fp64", profile=False):
     """Adaptive HSS compression (hss_compress).  R: (n, d_cap) float64 CUDA tensor,
     column-major, rows in permuted order.  Returns (HSSMatrix, status)."""
     g = gen._c()
-    o = _opts(R, rtol, atol, eta, strategy, d0, delta_d, p, d_max, precision)
+    o = _opts(R, rtol, atol, eta, strategy, d0, delta_d, p, d_max, precision, profile)
     h = C.c_void_p()
     st = _check(lib().hss_compress(C.byref(g), tree._t, C.byref(o), C.byref(h)))
     return HSSMatrix(h.value, (gen, tree, R)), st
