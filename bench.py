@@ -35,7 +35,7 @@ PEAK_HBM_GBS = 8000.0
 KCLASS_INFO = {
     "SAMPLE": ("k_sample_f64", "mfma"),
     "GEMM": ("k_gemm_grouped", "mfma"),
-    "TEST_QR": ("k_fn_qr", "hbm"),
+    "TEST_QR": ("k_fn_norms/k_qrcp_step(nopivot)/k_qform_step", "hbm"),
     "QRCP_STEP": ("k_qrcp_step", "hbm"),
     "GATHER": ("k_ls_gather/k_red_gather/k_fn_copy", "hbm"),
     "EXTRACT": ("k_extract_nodes", "hbm"),

@@ -27,7 +27,8 @@ Readings of points the paper leaves open (the HIP path uses the same):
   * a side whose local sample has m <= d rows passes (the samples span
     its whole local range with probability one);
   * rho = |Rbar_11| of the first QR'd block (Alg. 5);
-  * a zero new block (||S_new||_F = 0) passes;
+  * a zero new block (||S_new||_F = 0) passes, and so does a projected
+    block whose QR has an exactly zero diagonal entry;
   * the doubling strategy grows the sample by b = d (Alg. 3 "double"),
     the HMT test accepts iff r < d - p or r = m (Alg. 4, p counted
     inside d), with min(m,n) taken from the Hankel block sizes
@@ -167,7 +168,7 @@ def fnorm_test(st: FnormSide, S_new: np.ndarray, d: int, eps_r: float, eps_a: fl
     if st.rho is None:
         st.rho = float(dg[0])
     mn = float(dg.min())
-    if mn < eps_a or mn < eps_r * st.rho:
+    if mn == 0.0 or mn < eps_a or mn < eps_r * st.rho:
         st.passed = True
         return True
     st.Q = np.hstack([Q, Qk])

@@ -208,7 +208,7 @@ void Job::setup(int32_t count, const hss_generator* gens, const hss_tree* const*
       d.ws = a;
       a += align8((int64_t)d.mcap * dc);
       d.wsq = b;
-      b += align8(std::max<int64_t>((int64_t)d.qcap * dc, 16 + 2 * (int64_t)d.mcap + dc));
+      b += align8(std::max<int64_t>((int64_t)d.qcap * dc, 16 + 2 * ((int64_t)d.mcap + dc)));
       L.mcap = std::max(L.mcap, d.mcap);
       L.rcap = std::max(L.rcap, d.rcap);
       L.qcap = std::max(L.qcap, d.qcap);
@@ -231,6 +231,7 @@ void Job::setup(int32_t count, const hss_generator* gens, const hss_tree* const*
   prob_d = (ProbDev*)dalloc(sizeof(ProbDev) * count);
   tasks_d = (GemmTask*)dalloc(sizeof(GemmTask) * 2 * std::max(maxcount, 1));
   qtasks_d = (QrcpTask*)dalloc(sizeof(QrcpTask) * std::max(maxcount, 1));
+  qform_d = (QformTask*)dalloc(sizeof(QformTask) * std::max(maxcount, 1));
   for (auto& L : levels) {
     std::vector<int32_t> mc;
     for (int32_t g : L.nodes) mc.push_back(desc[g].mcap);
@@ -364,9 +365,23 @@ void Job::run_level(int lev, int32_t ncap) {
     int32_t nblk = 0;
     HSS_HIP_CHECK(hipMemcpyAsync(&nblk, flags_d + 1, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
     HSS_HIP_CHECK(hipStreamSynchronize(stream));
-    for (int it = 0; it < nblk; ++it)
-      for (int s = 0; s < nsides; ++s)
-        launch_fnorm_test(a, s, it, L.mcap, std::max(L.qcap, 1), std::min(max_block, L.dcap), stream);
+    if (nblk > 0) {
+      const int32_t nb = std::min(max_block, L.dcap);
+      constexpr int kTestCpw = 4;
+      if (L.test_ncap != nb) {   // workgroup map: kTestCpw block columns per workgroup
+        std::vector<int32_t> caps(L.nodes.size(), nb);
+        QrcpPlan qp = make_qrcp_plan(caps, kTestCpw);
+        if (L.wg_test == nullptr || (int32_t)qp.step.size() > L.ntest)
+          L.wg_test = (int2*)dalloc(sizeof(int2) * qp.step.size());
+        HSS_HIP_CHECK(hipMemcpy(L.wg_test, qp.step.data(), sizeof(int2) * qp.step.size(), hipMemcpyHostToDevice));
+        L.ntest = (int32_t)qp.step.size();
+        L.test_ncap = nb;
+      }
+      TestScratch ts{qtasks_d, qform_d, L.wg_test, L.ntest, kTestCpw, flags_d + 3, tasks_d};
+      for (int it = 0; it < nblk; ++it)
+        for (int s = 0; s < nsides; ++s)
+          launch_fnorm_test(a, s, it, L.mcap, std::max(L.qcap, 1), nb, ts, stream);
+    }
     launch_decide_fnorm(a, stream);
     id_phase(0);
   }

@@ -35,6 +35,8 @@ struct LevelInfo {
   int2* wg_step = nullptr;   // QRCP workgroup maps (device)
   int2* wg_trsm = nullptr;
   int32_t nstep = 0, ntrsm = 0;
+  int2* wg_test = nullptr;   // stopping-test QR workgroup map for test_ncap columns
+  int32_t ntest = 0, test_ncap = 0;
 };
 
 struct Job {
@@ -58,6 +60,7 @@ struct Job {
   int32_t* flags_d = nullptr;
   int32_t* nodes_d = nullptr;
   QrcpTask* qtasks_d = nullptr;
+  QformTask* qform_d = nullptr;
   int64_t* mvoff_d = nullptr;   // per node: prefix sum of rcap (matvec slots)
   int64_t mvtot = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;

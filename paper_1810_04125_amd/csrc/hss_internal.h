@@ -75,6 +75,8 @@ struct NodeState {
   int32_t nblk;     // number of blocks to test this round
   int32_t run[2];   // the current test iteration runs its QR on this side
   int32_t bc0, bnc; // columns of the block under test
+  int32_t qrank;    // columns the QR of the projected block reached
+  int32_t pad2;
   double rho[2];
 };
 
@@ -128,18 +130,35 @@ struct QrcpTask {
   double er, ea;     // stop when nu_k <= max(ea, er * nu_1) (/ HMT factor)
   double hmt_mn;     // > 0: HMT factor with sqrt(hmt_mn); 0: plain threshold
   int32_t m, d, mcap, active;
+  int32_t nopivot;   // 1: plain Householder QR (column k is the k-th pivot)
+  int32_t kcls;      // kernel class the step counters are charged to
 };
 
-constexpr int QCPW = 16;  // panel columns owned by one workgroup
+// Explicit Q of a Householder QR done by run_qrcp in nopivot mode:
+// Q(:, 0:nc) = H_0 ... H_{nc-1} [I; 0], reflectors rebuilt from the
+// untouched panel columns W(k:m, k) and the diagonal rdiag[k].
+struct QformTask {
+  const double* W;
+  int64_t ldw;
+  const double* rdiag;
+  double* Q;
+  int64_t ldq;
+  int32_t m, nc, active, pad;
+};
+
+constexpr int QCPW = 16;  // panel columns owned by one workgroup of the ID
 
 struct QrcpPlan {
   std::vector<int2> step;   // (task, first column) per workgroup of a pivot step
   std::vector<int2> trsm;   // (task, first column of E) per workgroup of the solve
 };
-QrcpPlan make_qrcp_plan(const std::vector<int32_t>& mcaps);
+QrcpPlan make_qrcp_plan(const std::vector<int32_t>& mcaps, int cpw = QCPW);
 void run_qrcp(const QrcpTask* tasks, int32_t ntasks, const int2* wg_step, int32_t nstep,
               const int2* wg_trsm, int32_t ntrsm, int32_t kmax, int32_t dmax, int32_t* flag,
-              GemmTask* gtasks, int32_t mcap_max, hipStream_t s, unsigned long long* kcnt = nullptr);
+              GemmTask* gtasks, int32_t mcap_max, hipStream_t s, unsigned long long* kcnt = nullptr,
+              int32_t cpw = QCPW, bool solve_e = true);
+void run_qform(const QformTask* tasks, const int2* wg, int32_t nwg, int32_t cpw, int32_t ncmax,
+               hipStream_t s, unsigned long long* kcnt, int32_t mmax);
 
 // ------------------------------------------------------------------ profiling
 // Launch counts and (in profile mode) HIP-event time per kernel class; the
@@ -197,8 +216,20 @@ void launch_plan(const LevelArgs& a, hipStream_t s);
 void launch_extract_nodes(const LevelArgs& a, hipStream_t s);
 void launch_local_samples(const LevelArgs& a, int side, int32_t mcap_max, int32_t rcap_max,
                           int32_t dcap_max, hipStream_t s);
+// One iteration of the Alg. 5 test on side `side`: copy + CGS2 (GEMMs),
+// norms and the F-norm tests, Householder QR of the projected block on
+// many workgroups (run_qrcp, nopivot), the R-diagonal tests, explicit Q_k.
+struct TestScratch {
+  QrcpTask* qt;        // count entries
+  QformTask* qf;       // count entries
+  const int2* wg;      // (task, first column) pairs for cpw-column workgroups
+  int32_t nwg;
+  int32_t cpw;
+  int32_t* flag;
+  GemmTask* gt;
+};
 void launch_fnorm_test(const LevelArgs& a, int side, int32_t iter, int32_t mcap_max,
-                       int32_t qcap_max, int32_t ncap, hipStream_t s);
+                       int32_t qcap_max, int32_t ncap, const TestScratch& ts, hipStream_t s);
 void launch_decide_fnorm(const LevelArgs& a, hipStream_t s);
 void launch_build_qrcp(const LevelArgs& a, int side, int32_t hmt, QrcpTask* out, hipStream_t s);
 void launch_decide_hmt(const LevelArgs& a, hipStream_t s);

@@ -326,14 +326,16 @@ __global__ __launch_bounds__(NB) void k_fn_copy(LevelArgs a, int side, int iter)
   }
 }
 
-// Householder QR of the projected block Sh (m x nc, column-major, ld mcap)
-// and the tests of eq. stopping_criteria; on failure Q <- [Q Q_k].
-__global__ __launch_bounds__(NB) void k_fn_qr(LevelArgs a, int side) {
+// The F-norm tests of eq. stopping_criteria on the projected block Sh
+// (m x nc, column-major, ld mcap): pass if ||Sh|| < eps_r ||S_new|| or
+// ||Sh|| / sqrt(nc) < eps_a; otherwise queue the Householder QR of Sh.
+__global__ __launch_bounds__(NB) void k_fn_norms(LevelArgs a, int side, QrcpTask* __restrict__ qt) {
   __shared__ double red[NW];
-  __shared__ int s_pass;
-  const int g = a.nodes[blockIdx.x];
+  const int t = blockIdx.x;
+  const int g = a.nodes[t];
   const NodeDesc& nd = a.desc[g];
   NodeState& st = a.st[g];
+  if (threadIdx.x == 0) qt[t].active = 0;
   if (!st.run[side]) return;
   const ProbDev& P = a.prob[nd.prob];
   const int dcap = P.dcap, m = st.m[side], nc = st.bnc, c0 = st.bc0, ld = nd.mcap;
@@ -341,10 +343,6 @@ __global__ __launch_bounds__(NB) void k_fn_qr(LevelArgs a, int side) {
   const double er = P.eps_r / lev, ea = P.eps_a / lev;
   const double* S = cdp(a, nd.S[side]);
   double* Sh = a.wsA + nd.ws;
-  double* tau = a.wsB + nd.wsq;  // nc reflector scales (the CGS2 workspace is free now)
-  double* alph = tau + nc;        // nc diagonal entries of Rbar
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-
   double p1 = 0.0, p2 = 0.0;
   for (int64_t idx = threadIdx.x; idx < (int64_t)m * nc; idx += NB) {
     const int i = (int)(idx % m), c = (int)(idx / m);
@@ -355,78 +353,60 @@ __global__ __launch_bounds__(NB) void k_fn_qr(LevelArgs a, int side) {
   }
   const double nS = sqrt(block_sum(p1, red));
   const double nSh = sqrt(block_sum(p2, red));
+  if (threadIdx.x != 0) return;
+  kcount(a.kcnt, HSS_K_TEST_QR, 16.0 * m * nc, 4.0 * m * nc);
   if (nS == 0.0 || nSh < er * nS || nSh / sqrt((double)nc) < ea) {
-    if (threadIdx.x == 0) {
-      st.passed[side] = 1;
-      kcount(a.kcnt, HSS_K_TEST_QR, 16.0 * m * nc, 4.0 * m * nc);
-    }
+    st.passed[side] = 1;
+    st.run[side] = 0;
     return;
   }
-  // Householder QR, column by column
-  for (int k = 0; k < nc; ++k) {
-    double* x = Sh + (int64_t)k * ld;
-    double part = 0.0;
-    for (int i = k + threadIdx.x; i < m; i += NB) part += x[i] * x[i];
-    const double nrm = sqrt(block_sum(part, red));
-    const double x0 = x[k];
-    double alpha = 0.0, tk = 0.0;
-    if (nrm > 0.0) {
-      alpha = x0 >= 0.0 ? -nrm : nrm;
-      tk = 1.0 / (nrm * (nrm + fabs(x0)));  // 2 / v^T v
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      x[k] = x0 - alpha;  // v_0; v_i = x_i below
-      tau[k] = tk;
-      alph[k] = alpha;
-    }
-    __syncthreads();
-    for (int j = k + 1 + w; j < nc; j += NW) {
-      double* y = Sh + (int64_t)j * ld;
-      double dot = 0.0;
-      for (int i = k + lane; i < m; i += 64) dot += x[i] * y[i];
-      dot = wave_sum(dot) * tk;
-      for (int i = k + lane; i < m; i += 64) y[i] -= dot * x[i];
-    }
-    __syncthreads();
+  QrcpTask q;
+  q.S = Sh; q.lds = ld; q.W = Sh; q.ldw = ld;
+  q.scr = a.wsB + nd.wsq;
+  q.J = nullptr; q.E = nullptr; q.lde = 1;
+  q.rank_out = &st.qrank;
+  q.er = 0.0; q.ea = 0.0; q.hmt_mn = 0.0;
+  q.m = nc; q.d = m; q.mcap = nc; q.active = 1;
+  q.nopivot = 1; q.kcls = HSS_K_TEST_QR;
+  qt[t] = q;
+}
+
+// R-diagonal tests of eq. stopping_criteria after the QR of the projected
+// block: pass if min |Rbar_ii| < eps_a or < eps_r rho (rho = |Rbar_11| of the
+// first block QR'd on this side); otherwise queue Q_k for Q <- [Q Q_k].
+__global__ void k_fn_rtest(LevelArgs a, int side, QformTask* __restrict__ qf) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= a.count) return;
+  const int g = a.nodes[t];
+  const NodeDesc& nd = a.desc[g];
+  NodeState& st = a.st[g];
+  qf[t].active = 0;
+  if (!st.run[side]) return;
+  const ProbDev& P = a.prob[nd.prob];
+  const int m = st.m[side], nc = st.bnc;
+  const double lev = (double)nd.level;
+  const double er = P.eps_r / lev, ea = P.eps_a / lev;
+  const double* rdiag = a.wsB + nd.wsq + 16 + 2 * (int64_t)nc;
+  const int r = st.qrank;
+  double mn = r < nc ? 0.0 : INFINITY;
+  for (int k = 0; k < r; ++k) mn = fmin(mn, fabs(rdiag[k]));
+  if (st.rho[side] < 0.0) st.rho[side] = r > 0 ? fabs(rdiag[0]) : 0.0;
+  st.run[side] = 0;
+  if (r < nc || mn < ea || mn < er * st.rho[side]) {  // an exactly zero Rbar_ii also passes
+    st.passed[side] = 1;
+    return;
   }
-  if (threadIdx.x == 0) {
-    double mn = INFINITY;
-    for (int k = 0; k < nc; ++k) mn = fmin(mn, fabs(alph[k]));
-    if (st.rho[side] < 0.0) st.rho[side] = fabs(alph[0]);
-    s_pass = (mn < ea || mn < er * st.rho[side]) ? 1 : 0;
-    if (s_pass) st.passed[side] = 1;
-    const double mm = m, b = nc;
-    kcount(a.kcnt, HSS_K_TEST_QR, 8.0 * mm * b * (s_pass ? 2.0 : 3.0),
-           (s_pass ? 2.0 : 4.0) * mm * b * b);
-  }
-  __syncthreads();
-  if (s_pass) return;
-  // Q_k = H_0 ... H_{nc-1} [I; 0] written into Q(:, q : q + nc)
-  const int q = st.q[side];
-  double* Qk = dp(a, nd.Q[side]) + (int64_t)q * ld;
-  for (int64_t idx = threadIdx.x; idx < (int64_t)m * nc; idx += NB) {
-    const int i = (int)(idx % m), c = (int)(idx / m);
-    Qk[(int64_t)c * ld + i] = (i == c) ? 1.0 : 0.0;
-  }
-  __syncthreads();
-  for (int k = nc - 1; k >= 0; --k) {
-    const double* x = Sh + (int64_t)k * ld;
-    const double tk = tau[k];
-    for (int j = k + w; j < nc; j += NW) {
-      double* y = Qk + (int64_t)j * ld;
-      double dot = 0.0;
-      for (int i = k + lane; i < m; i += 64) dot += x[i] * y[i];
-      dot = wave_sum(dot) * tk;
-      for (int i = k + lane; i < m; i += 64) y[i] -= dot * x[i];
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) st.q[side] = q + nc;
+  QformTask f;
+  f.W = a.wsA + nd.ws; f.ldw = nd.mcap;
+  f.rdiag = rdiag;
+  f.Q = dp(a, nd.Q[side]) + (int64_t)st.q[side] * nd.mcap; f.ldq = nd.mcap;
+  f.m = m; f.nc = nc; f.active = 1; f.pad = 0;
+  qf[t] = f;
+  st.q[side] += nc;
 }
 
 void launch_fnorm_test(const LevelArgs& a, int side, int32_t iter, int32_t mcap_max, int32_t qcap_max,
-                       int32_t ncap, hipStream_t s) {
+                       int32_t ncap, const TestScratch& ts, hipStream_t s) {
   if (a.count <= 0) return;
   prof_begin(s);
   hipLaunchKernelGGL(k_fn_copy, dim3(a.count), dim3(NB), 0, s, a, side, iter);
@@ -436,8 +416,14 @@ void launch_fnorm_test(const LevelArgs& a, int side, int32_t iter, int32_t mcap_
     launch_gemm(a.tasks + a.count, a.count, mcap_max, ncap, s, a.kcnt);
   }
   prof_begin(s);
-  hipLaunchKernelGGL(k_fn_qr, dim3(a.count), dim3(NB), 0, s, a, side);
+  hipLaunchKernelGGL(k_fn_norms, dim3(a.count), dim3(NB), 0, s, a, side, ts.qt);
   prof_end(HSS_K_TEST_QR, s);
+  run_qrcp(ts.qt, a.count, ts.wg, ts.nwg, nullptr, 0, ncap, mcap_max, ts.flag, ts.gt, mcap_max, s, a.kcnt,
+           ts.cpw, false);
+  prof_begin(s);
+  hipLaunchKernelGGL(k_fn_rtest, dim3((a.count + 127) / 128), dim3(128), 0, s, a, side, ts.qf);
+  prof_end(HSS_K_TEST_QR, s);
+  run_qform(ts.qf, ts.wg, ts.nwg, ts.cpw, ncap, s, a.kcnt, mcap_max);
 }
 
 __global__ void k_decide_fnorm(LevelArgs a) {
@@ -488,6 +474,8 @@ __global__ void k_build_qrcp(LevelArgs a, int side, int hmt, QrcpTask* __restric
   q.m = st.m[side];
   q.d = P.d;
   q.mcap = nd.mcap;
+  q.nopivot = 0;
+  q.kcls = HSS_K_QRCP_STEP;
   out[t] = q;
 }
 

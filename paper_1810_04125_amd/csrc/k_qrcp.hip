@@ -43,7 +43,8 @@ __device__ __forceinline__ double wsum(double v) {
   return v;
 }
 
-__global__ __launch_bounds__(QB) void k_qrcp_init(const QrcpTask* __restrict__ tasks, const int2* __restrict__ wg) {
+__global__ __launch_bounds__(QB) void k_qrcp_init(const QrcpTask* __restrict__ tasks, const int2* __restrict__ wg,
+                                                  int cpw) {
   const int2 w = wg[blockIdx.x];
   const QrcpTask& t = tasks[w.x];
   if (!t.active) return;
@@ -55,7 +56,7 @@ __global__ __launch_bounds__(QB) void k_qrcp_init(const QrcpTask* __restrict__ t
     c->nu1 = 0.0;
   }
   double* nrm = nrm_of(t, 0);
-  const int jend = min(t.m, w.y + QCPW);
+  const int jend = min(t.m, w.y + cpw);
   for (int j = w.y + wv; j < jend; j += QW) {
     const double* src = t.S + (int64_t)j * t.lds;
     double* dst = t.W + (int64_t)j * t.ldw;
@@ -71,7 +72,7 @@ __global__ __launch_bounds__(QB) void k_qrcp_init(const QrcpTask* __restrict__ t
 }
 
 __global__ __launch_bounds__(QB) void k_qrcp_step(const QrcpTask* __restrict__ tasks, const int2* __restrict__ wg,
-                                                  int k, unsigned long long* __restrict__ kcnt) {
+                                                  int k, unsigned long long* __restrict__ kcnt, int cpw) {
   extern __shared__ double vsh[];
   __shared__ double rv[QW];
   __shared__ int ri[QW];
@@ -85,26 +86,33 @@ __global__ __launch_bounds__(QB) void k_qrcp_step(const QrcpTask* __restrict__ t
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const double* nold = nrm_of(t, k);
   double* nnew = nrm_of(t, k + 1);
-  // pivot: largest residual norm among the remaining columns, ties -> lowest index
-  double bv = -1.0;
-  int bi = 0x7fffffff;
-  for (int j = threadIdx.x; j < m; j += QB) {
-    const double v = nold[j];
-    if (v < 0.0) continue;
-    if (v > bv || (v == bv && j < bi)) { bv = v; bi = j; }
-  }
+  double nu;
+  int p;
+  if (t.nopivot) {
+    p = k;
+    nu = nold[k];
+  } else {
+    // pivot: largest residual norm among the remaining columns, ties -> lowest index
+    double bv = -1.0;
+    int bi = 0x7fffffff;
+    for (int j = threadIdx.x; j < m; j += QB) {
+      const double v = nold[j];
+      if (v < 0.0) continue;
+      if (v > bv || (v == bv && j < bi)) { bv = v; bi = j; }
+    }
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    const double ov = __shfl_xor(bv, o, 64);
-    const int oi = __shfl_xor(bi, o, 64);
-    if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ov = __shfl_xor(bv, o, 64);
+      const int oi = __shfl_xor(bi, o, 64);
+      if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+    }
+    if (lane == 0) { rv[wv] = bv; ri[wv] = bi; }
+    __syncthreads();
+    nu = rv[0];
+    p = ri[0];
+    for (int i = 1; i < QW; ++i)
+      if (rv[i] > nu || (rv[i] == nu && ri[i] < p)) { nu = rv[i]; p = ri[i]; }
   }
-  if (lane == 0) { rv[wv] = bv; ri[wv] = bi; }
-  __syncthreads();
-  double nu = rv[0];
-  int p = ri[0];
-  for (int i = 1; i < QW; ++i)
-    if (rv[i] > nu || (rv[i] == nu && ri[i] < p)) { nu = rv[i]; p = ri[i]; }
   const double nu1 = (k == 0) ? nu : c->nu1;
   double thr = fmax(t.ea, t.er * nu1);
   if (t.hmt_mn > 0.0) {
@@ -127,12 +135,12 @@ __global__ __launch_bounds__(QB) void k_qrcp_step(const QrcpTask* __restrict__ t
   if (lead) {
     if (k == 0) c->nu1 = nu;
     rdiag_of(t)[k] = alpha;
-    t.J[k] = p;
+    if (t.J) t.J[k] = p;
     const double cells = (double)(d - k) * (double)(m - k - 1);
-    kcount(kcnt, HSS_K_QRCP_STEP, 16.0 * cells, 4.0 * cells);
+    kcount(kcnt, t.kcls, 16.0 * cells, 4.0 * cells);
   }
   __syncthreads();
-  const int jend = min(m, w.y + QCPW);
+  const int jend = min(m, w.y + cpw);
   for (int j = w.y + wv; j < jend; j += QW) {
     if (j == p || nold[j] < 0.0) {
       if (lane == 0) nnew[j] = -1.0;
@@ -174,9 +182,7 @@ __global__ __launch_bounds__(QB) void k_qrcp_fin(const QrcpTask* __restrict__ ta
     const int r = (kmax > 0 && c->done) ? c->rank : kmax;
     const double* nfin = nrm_of(t, r);
     int pos = r;
-    if (m > 0 && r == 0) {
-      for (int j = 0; j < m; ++j) t.J[pos++] = j;
-    } else {
+    if (t.J) {
       for (int j = 0; j < m; ++j)
         if (nfin[j] >= 0.0) t.J[pos++] = j;
     }
@@ -187,6 +193,7 @@ __global__ __launch_bounds__(QB) void k_qrcp_fin(const QrcpTask* __restrict__ ta
   __syncthreads();
   const int r = s_r;
   const int nrest = m - r;
+  if (!t.E) return;
   for (int64_t idx = threadIdx.x; idx < (int64_t)r * nrest; idx += QB) {
     const int i = (int)(idx % r), l = (int)(idx / r);
     t.E[(int64_t)l * t.lde + i] = t.W[(int64_t)t.J[r + l] * t.ldw + i];
@@ -251,11 +258,11 @@ __global__ __launch_bounds__(QB) void k_trsm_diag(const QrcpTask* __restrict__ t
   }
 }
 
-QrcpPlan make_qrcp_plan(const std::vector<int32_t>& mcaps) {
+QrcpPlan make_qrcp_plan(const std::vector<int32_t>& mcaps, int cpw) {
   QrcpPlan p;
   for (size_t t = 0; t < mcaps.size(); ++t) {
     const int mc = std::max(mcaps[t], 1);
-    for (int c = 0; c < mc; c += QCPW) p.step.push_back(make_int2((int)t, c));
+    for (int c = 0; c < mc; c += cpw) p.step.push_back(make_int2((int)t, c));
     for (int c = 0; c < mc; c += QB) p.trsm.push_back(make_int2((int)t, c));
   }
   return p;
@@ -263,10 +270,11 @@ QrcpPlan make_qrcp_plan(const std::vector<int32_t>& mcaps) {
 
 void run_qrcp(const QrcpTask* tasks, int32_t ntasks, const int2* wg_step, int32_t nstep,
               const int2* wg_trsm, int32_t ntrsm, int32_t kmax, int32_t dmax, int32_t* flag,
-              GemmTask* gtasks, int32_t mcap_max, hipStream_t s, unsigned long long* kcnt) {
+              GemmTask* gtasks, int32_t mcap_max, hipStream_t s, unsigned long long* kcnt, int32_t cpw,
+              bool solve_e) {
   if (ntasks <= 0) return;
   prof_begin(s);
-  hipLaunchKernelGGL(k_qrcp_init, dim3(nstep), dim3(QB), 0, s, tasks, wg_step);
+  hipLaunchKernelGGL(k_qrcp_init, dim3(nstep), dim3(QB), 0, s, tasks, wg_step, cpw);
   prof_end(HSS_K_QRCP_OTHER, s);
   const size_t lds = (size_t)std::max(dmax, 1) * sizeof(double);
   int32_t alive = 1;
@@ -279,13 +287,14 @@ void run_qrcp(const QrcpTask* tasks, int32_t ntasks, const int2* wg_step, int32_
       if (alive == 0) break;
     }
     prof_begin(s);
-    hipLaunchKernelGGL(k_qrcp_step, dim3(nstep), dim3(QB), lds, s, tasks, wg_step, k, kcnt);
-    prof_end(HSS_K_QRCP_STEP, s);
+    hipLaunchKernelGGL(k_qrcp_step, dim3(nstep), dim3(QB), lds, s, tasks, wg_step, k, kcnt, cpw);
+    prof_end(solve_e ? HSS_K_QRCP_STEP : HSS_K_TEST_QR, s);
   }
   HSS_HIP_CHECK(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
   prof_begin(s);
   hipLaunchKernelGGL(k_qrcp_fin, dim3(ntasks), dim3(QB), 0, s, tasks, flag);
   prof_end(HSS_K_QRCP_OTHER, s);
+  if (!solve_e) return;
   int32_t rmax = 0;
   HSS_HIP_CHECK(hipMemcpyAsync(&rmax, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HSS_HIP_CHECK(hipStreamSynchronize(s));
@@ -296,6 +305,63 @@ void run_qrcp(const QrcpTask* tasks, int32_t ntasks, const int2* wg_step, int32_
     if (ib > 0) launch_gemm(gtasks, ntasks, ib * TRB, mcap_max, s, kcnt);
   }
   HSS_HIP_CHECK(hipGetLastError());
+}
+
+// ------------------------------------------------------------------ explicit Q
+__global__ __launch_bounds__(QB) void k_qform_init(const QformTask* __restrict__ tasks, const int2* __restrict__ wg,
+                                                   int cpw) {
+  const int2 w = wg[blockIdx.x];
+  const QformTask& t = tasks[w.x];
+  if (!t.active) return;
+  const int jend = min(t.nc, w.y + cpw);
+  for (int j = w.y; j < jend; ++j) {
+    double* q = t.Q + (int64_t)j * t.ldq;
+    for (int i = threadIdx.x; i < t.m; i += QB) q[i] = (i == j) ? 1.0 : 0.0;
+  }
+}
+
+// Q(k:m, j) -= tau_k v_k (v_k^T Q(k:m, j)) for the workgroup's columns j >= k
+__global__ __launch_bounds__(QB) void k_qform_step(const QformTask* __restrict__ tasks, const int2* __restrict__ wg,
+                                                   int cpw, int k, unsigned long long* __restrict__ kcnt) {
+  extern __shared__ double vsh[];
+  const int2 w = wg[blockIdx.x];
+  const QformTask& t = tasks[w.x];
+  if (!t.active || k >= t.nc) return;
+  const int jbeg = max(w.y, k), jend = min(t.nc, w.y + cpw);
+  if (jbeg >= jend) return;
+  const int m = t.m;
+  const double* x = t.W + (int64_t)k * t.ldw;
+  const double alpha = t.rdiag[k];
+  const double x0 = x[k];
+  const double nu = fabs(alpha);
+  if (nu == 0.0) return;
+  const double tk = 1.0 / (nu * (nu + fabs(x0)));
+  for (int i = k + threadIdx.x; i < m; i += QB) vsh[i - k] = (i == k) ? x0 - alpha : x[i];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (w.y <= k && k < w.y + cpw && threadIdx.x == 0)
+    kcount(kcnt, HSS_K_TEST_QR, 16.0 * (m - k) * (t.nc - k), 4.0 * (m - k) * (t.nc - k));
+  for (int j = jbeg + wv; j < jend; j += QW) {
+    double* y = t.Q + (int64_t)j * t.ldq;
+    double dot = 0.0;
+    for (int i = k + lane; i < m; i += 64) dot += vsh[i - k] * y[i];
+    dot = wsum(dot) * tk;
+    for (int i = k + lane; i < m; i += 64) y[i] -= dot * vsh[i - k];
+  }
+}
+
+void run_qform(const QformTask* tasks, const int2* wg, int32_t nwg, int32_t cpw, int32_t ncmax, hipStream_t s,
+               unsigned long long* kcnt, int32_t mmax) {
+  if (nwg <= 0 || ncmax <= 0) return;
+  prof_begin(s);
+  hipLaunchKernelGGL(k_qform_init, dim3(nwg), dim3(QB), 0, s, tasks, wg, cpw);
+  prof_end(HSS_K_TEST_QR, s);
+  const size_t lds = (size_t)std::max(mmax, 1) * sizeof(double);
+  for (int k = ncmax - 1; k >= 0; --k) {
+    prof_begin(s);
+    hipLaunchKernelGGL(k_qform_step, dim3(nwg), dim3(QB), lds, s, tasks, wg, cpw, k, kcnt);
+    prof_end(HSS_K_TEST_QR, s);
+  }
 }
 
 }  // namespace hss
