@@ -44,6 +44,17 @@ __device__ double block_sum(double v, double* red) {
   return s;
 }
 
+// Element loops of the per-node copy kernels are spread over gridDim.y
+// workgroups of the same node.
+#define CHUNKED_FOR(idx, total) \
+  for (int64_t idx = threadIdx.x + (int64_t)blockIdx.y * NB; idx < (total); idx += (int64_t)NB * gridDim.y)
+
+static dim3 node_grid(int count) {
+  int g = (1024 + count - 1) / count;
+  g = g < 1 ? 1 : (g > 64 ? 64 : g);
+  return dim3(count, g);
+}
+
 __device__ __forceinline__ const double* cdp(const LevelArgs& a, int64_t off) { return a.dpool + off; }
 __device__ __forceinline__ double* dp(const LevelArgs& a, int64_t off) { return a.dpool + off; }
 
@@ -116,7 +127,7 @@ __global__ __launch_bounds__(NB) void k_extract_nodes(LevelArgs a) {
   if (nd.leaf) {
     const int m = nd.hi - nd.lo;
     double* D = dp(a, nd.D);
-    for (int64_t idx = threadIdx.x; idx < (int64_t)m * m; idx += NB) {
+    CHUNKED_FOR(idx, (int64_t)m * m) {
       const int i = (int)(idx % m), j = (int)(idx / m);
       const double v = gen_entry(gen, nd.lo + i, nd.lo + j);
       bad |= !isfinite(v);
@@ -132,7 +143,7 @@ __global__ __launch_bounds__(NB) void k_extract_nodes(LevelArgs a) {
     const int64_t* I1r = a.lpool + L.I[0];
     const int64_t* I2c = a.lpool + Rn.I[1];
     double* B12 = dp(a, nd.B12);
-    for (int64_t idx = threadIdx.x; idx < (int64_t)r1 * c2; idx += NB) {
+    CHUNKED_FOR(idx, (int64_t)r1 * c2) {
       const int i = (int)(idx % r1), j = (int)(idx / r1);
       const double v = gen_entry(gen, I1r[i], I2c[j]);
       bad |= !isfinite(v);
@@ -142,7 +153,7 @@ __global__ __launch_bounds__(NB) void k_extract_nodes(LevelArgs a) {
     const int64_t* I2r = a.lpool + Rn.I[0];
     const int64_t* I1c = a.lpool + L.I[1];
     double* B21 = dp(a, nd.B21);
-    for (int64_t idx = threadIdx.x; idx < (int64_t)r2 * c1; idx += NB) {
+    CHUNKED_FOR(idx, (int64_t)r2 * c1) {
       const int i = (int)(idx % r2), j = (int)(idx / r2);
       const double v = gen_entry(gen, I2r[i], I1c[j]);
       bad |= !isfinite(v);
@@ -150,7 +161,7 @@ __global__ __launch_bounds__(NB) void k_extract_nodes(LevelArgs a) {
     }
   }
   if (bad) atomicOr(a.flags, 1);
-  if (threadIdx.x == 0) {
+  if (threadIdx.x == 0 && blockIdx.y == 0) {
     double ent;
     if (nd.leaf) ent = (double)(nd.hi - nd.lo) * (nd.hi - nd.lo);
     else ent = (double)a.st[nd.left].rank[0] * a.st[nd.right].rank[1] +
@@ -162,7 +173,7 @@ __global__ __launch_bounds__(NB) void k_extract_nodes(LevelArgs a) {
 void launch_extract_nodes(const LevelArgs& a, hipStream_t s) {
   if (a.count <= 0) return;
   prof_begin(s);
-  hipLaunchKernelGGL(k_extract_nodes, dim3(a.count), dim3(NB), 0, s, a);
+  hipLaunchKernelGGL(k_extract_nodes, node_grid(a.count), dim3(NB), 0, s, a);
   prof_end(HSS_K_EXTRACT, s);
 }
 
@@ -176,7 +187,7 @@ __global__ __launch_bounds__(NB) void k_ls_gather(LevelArgs a, int side) {
   const NodeState& st = a.st[g];
   GemmTask* T0 = a.tasks + t;
   GemmTask* T1 = a.tasks + a.count + t;
-  if (threadIdx.x == 0) {
+  if (threadIdx.x == 0 && blockIdx.y == 0) {
     T0->M = 0;
     T1->M = 0;
   }
@@ -186,14 +197,14 @@ __global__ __launch_bounds__(NB) void k_ls_gather(LevelArgs a, int side) {
   const int c0 = st.c0, nc = st.nc;
   const int m = st.m[side];
   double* S = dp(a, nd.S[side]);
-  if (threadIdx.x == 0) kcount(a.kcnt, HSS_K_GATHER, 16.0 * m * nc, 0.0);
+  if (threadIdx.x == 0 && blockIdx.y == 0) kcount(a.kcnt, HSS_K_GATHER, 16.0 * m * nc, 0.0);
   if (nd.leaf) {
     const double* Sg = cdp(a, P.sglob[side]);
-    for (int64_t idx = threadIdx.x; idx < (int64_t)m * nc; idx += NB) {
+    CHUNKED_FOR(idx, (int64_t)m * nc) {
       const int i = (int)(idx % m), c = (int)(idx / m);
       S[(int64_t)i * dcap + c0 + c] = Sg[(int64_t)(c0 + c) * P.n + nd.lo + i];
     }
-    if (threadIdx.x == 0) {
+    if (threadIdx.x == 0 && blockIdx.y == 0) {
       GemmTask k;
       k.A = cdp(a, nd.D);
       if (side == 0) { k.a_rs = 1; k.a_cs = m; } else { k.a_rs = m; k.a_cs = 1; }
@@ -218,12 +229,12 @@ __global__ __launch_bounds__(NB) void k_ls_gather(LevelArgs a, int side) {
   const int32_t* J2 = a.ipool + Rn.J[side];
   const double* S1 = cdp(a, L.S[side]);
   const double* S2 = cdp(a, Rn.S[side]);
-  for (int64_t idx = threadIdx.x; idx < (int64_t)m * nc; idx += NB) {
+  CHUNKED_FOR(idx, (int64_t)m * nc) {
     const int c = (int)(idx % nc), i = (int)(idx / nc);
     const double v = i < r1 ? S1[(int64_t)J1[i] * dcap + c0 + c] : S2[(int64_t)J2[i - r1] * dcap + c0 + c];
     S[(int64_t)i * dcap + c0 + c] = v;
   }
-  if (threadIdx.x == 0) {
+  if (threadIdx.x == 0 && blockIdx.y == 0) {
     GemmTask k;
     k.b_rs = dcap; k.b_cs = 1; k.c_rs = dcap; k.c_cs = 1; k.N = nc; k.pad = 0;
     k.alpha = -1.0; k.beta = 1.0;
@@ -256,7 +267,7 @@ void launch_local_samples(const LevelArgs& a, int side, int32_t mcap_max, int32_
   (void)rcap_max;
   if (a.count <= 0) return;
   prof_begin(s);
-  hipLaunchKernelGGL(k_ls_gather, dim3(a.count), dim3(NB), 0, s, a, side);
+  hipLaunchKernelGGL(k_ls_gather, node_grid(a.count), dim3(NB), 0, s, a, side);
   prof_end(HSS_K_GATHER, s);
   launch_gemm(a.tasks, 2 * a.count, mcap_max, ncap, s, a.kcnt);
 }
@@ -273,40 +284,45 @@ __global__ __launch_bounds__(NB) void k_fn_copy(LevelArgs a, int side, int iter)
   NodeState& st = a.st[g];
   GemmTask* TA = a.tasks + t;
   GemmTask* TB = a.tasks + a.count + t;
-  __shared__ int s_go;
-  if (threadIdx.x == 0) {
-    TA->M = 0;
-    TB->M = 0;
-    int go = 0;
-    st.run[side] = 0;
-    if (st.need[side] && !st.passed[side] && iter < st.nblk) {
-      const ProbDev& P = a.prob[nd.prob];
-      const int b = st.tb + iter;
-      const int c0 = b > 0 ? P.sched[b - 1] : 0;
-      const int c1 = P.sched[b];
-      if (c1 >= st.m[side]) {
-        st.passed[side] = 1;
-      } else if (c1 > c0) {
-        st.bc0 = c0;
-        st.bnc = c1 - c0;
-        st.run[side] = 1;
-        go = 1;
-      }
+  // every workgroup of the node takes the same decision from the state at
+  // launch; only the first one writes the state and the GEMM tasks
+  const bool first = blockIdx.y == 0;
+  int go = 0, c0 = 0, nc = 0;
+  if (st.need[side] && !st.passed[side] && iter < st.nblk) {
+    const ProbDev& P = a.prob[nd.prob];
+    const int b = st.tb + iter;
+    const int b0 = b > 0 ? P.sched[b - 1] : 0;
+    const int b1 = P.sched[b];
+    if (b1 < st.m[side] && b1 > b0) {
+      go = 1;
+      c0 = b0;
+      nc = b1 - b0;
     }
-    s_go = go;
   }
   __syncthreads();
-  if (!s_go) return;
+  if (first && threadIdx.x == 0) {
+    TA->M = 0;
+    TB->M = 0;
+    st.run[side] = go;
+    if (go) {
+      st.bc0 = c0;
+      st.bnc = nc;
+    } else if (st.need[side] && !st.passed[side] && iter < st.nblk) {
+      const ProbDev& P = a.prob[nd.prob];
+      if (P.sched[st.tb + iter] >= st.m[side]) st.passed[side] = 1;
+    }
+  }
+  if (!go) return;
   const ProbDev& P = a.prob[nd.prob];
-  const int dcap = P.dcap, m = st.m[side], nc = st.bnc, c0 = st.bc0, q = st.q[side];
-  if (threadIdx.x == 0) kcount(a.kcnt, HSS_K_GATHER, 16.0 * m * nc, 0.0);
+  const int dcap = P.dcap, m = st.m[side], q = st.q[side];
+  if (first && threadIdx.x == 0) kcount(a.kcnt, HSS_K_GATHER, 16.0 * m * nc, 0.0);
   const double* S = cdp(a, nd.S[side]);
   double* Sh = a.wsA + nd.ws;
-  for (int64_t idx = threadIdx.x; idx < (int64_t)m * nc; idx += NB) {
+  CHUNKED_FOR(idx, (int64_t)m * nc) {
     const int i = (int)(idx % m), c = (int)(idx / m);
     Sh[(int64_t)c * nd.mcap + i] = S[(int64_t)i * dcap + c0 + c];
   }
-  if (threadIdx.x == 0) {
+  if (first && threadIdx.x == 0) {
     const double* Q = cdp(a, nd.Q[side]);
     double* W = a.wsB + nd.wsq;
     GemmTask k;
@@ -409,7 +425,7 @@ void launch_fnorm_test(const LevelArgs& a, int side, int32_t iter, int32_t mcap_
                        int32_t ncap, const TestScratch& ts, hipStream_t s) {
   if (a.count <= 0) return;
   prof_begin(s);
-  hipLaunchKernelGGL(k_fn_copy, dim3(a.count), dim3(NB), 0, s, a, side, iter);
+  hipLaunchKernelGGL(k_fn_copy, node_grid(a.count), dim3(NB), 0, s, a, side, iter);
   prof_end(HSS_K_GATHER, s);
   for (int pass = 0; pass < 2; ++pass) {  // block Gram-Schmidt, twice
     launch_gemm(a.tasks, a.count, qcap_max, ncap, s, a.kcnt);
@@ -515,7 +531,7 @@ __global__ __launch_bounds__(NB) void k_red_gather(LevelArgs a, int side) {
   const NodeDesc& nd = a.desc[g];
   const NodeState& st = a.st[g];
   GemmTask* T0 = a.tasks + t;
-  if (threadIdx.x == 0) T0->M = 0;
+  if (threadIdx.x == 0 && blockIdx.y == 0) T0->M = 0;
   if (!st.active) return;
   if (!(st.state == COMPRESSED || st.go)) return;
   const ProbDev& P = a.prob[nd.prob];
@@ -525,7 +541,7 @@ __global__ __launch_bounds__(NB) void k_red_gather(LevelArgs a, int side) {
   const int m = st.m[side], r = st.rank[side];
   const int32_t* J = a.ipool + nd.J[side];
   double* RR = dp(a, nd.RR[side]);
-  if (threadIdx.x == 0) kcount(a.kcnt, HSS_K_GATHER, 16.0 * m * nc, 0.0);
+  if (threadIdx.x == 0 && blockIdx.y == 0) kcount(a.kcnt, HSS_K_GATHER, 16.0 * m * nc, 0.0);
   double* Xr = a.wsA + nd.ws;  // (m - r) x nc, column-major, ld = mcap
   int r1 = 0;
   const double *X1 = nullptr, *X2 = nullptr;
@@ -534,7 +550,7 @@ __global__ __launch_bounds__(NB) void k_red_gather(LevelArgs a, int side) {
     X1 = cdp(a, a.desc[nd.left].RR[side]);
     X2 = cdp(a, a.desc[nd.right].RR[side]);
   }
-  for (int64_t idx = threadIdx.x; idx < (int64_t)m * nc; idx += NB) {
+  CHUNKED_FOR(idx, (int64_t)m * nc) {
     const int c = (int)(idx % nc), i = (int)(idx / nc);
     const int row = J[i];
     double v;
@@ -543,7 +559,7 @@ __global__ __launch_bounds__(NB) void k_red_gather(LevelArgs a, int side) {
     if (i < r) RR[(int64_t)i * dcap + c0 + c] = v;
     else Xr[(int64_t)c * nd.mcap + (i - r)] = v;
   }
-  if (st.go) {
+  if (st.go && blockIdx.y == 0) {
     int64_t* I = a.lpool + nd.I[side];
     const int64_t* I1 = nd.leaf ? nullptr : a.lpool + a.desc[nd.left].I[side];
     const int64_t* I2 = nd.leaf ? nullptr : a.lpool + a.desc[nd.right].I[side];
@@ -552,7 +568,7 @@ __global__ __launch_bounds__(NB) void k_red_gather(LevelArgs a, int side) {
       I[k] = nd.leaf ? (int64_t)nd.lo + row : (row < r1 ? I1[row] : I2[row - r1]);
     }
   }
-  if (threadIdx.x == 0) {
+  if (threadIdx.x == 0 && blockIdx.y == 0) {
     GemmTask k;
     k.A = cdp(a, nd.E[side]); k.a_rs = 1; k.a_cs = nd.rcap;
     k.B = Xr; k.b_rs = 1; k.b_cs = nd.mcap;
@@ -568,7 +584,7 @@ void launch_reduce(const LevelArgs& a, int side, int32_t mcap_max, int32_t rcap_
   (void)mcap_max;
   if (a.count <= 0) return;
   prof_begin(s);
-  hipLaunchKernelGGL(k_red_gather, dim3(a.count), dim3(NB), 0, s, a, side);
+  hipLaunchKernelGGL(k_red_gather, node_grid(a.count), dim3(NB), 0, s, a, side);
   prof_end(HSS_K_GATHER, s);
   launch_gemm(a.tasks, a.count, rcap_max, ncap, s, a.kcnt);
 }
