@@ -84,7 +84,7 @@ struct GenHolder {
 
 // Permuted-space matvec on the compressed job: Yp = H Xp, both n x nrhs (ld n).
 void matvec_permuted(const hss_matrix* h, int32_t nrhs, const double* Xp, double* Yp, double* xh,
-                     double* yh, hipStream_t s) {
+                     double* yh, double* ws, hipStream_t s) {
   Job& J = *h->job;
   const Problem& P = J.probs[h->k];
   // The level lists mix problems; run per problem with its own sub-lists.
@@ -100,8 +100,8 @@ void matvec_permuted(const hss_matrix* h, int32_t nrhs, const double* Xp, double
     if (cnt == 0) continue;
     a.desc = J.desc_d; a.st = J.st_d; a.nodes = J.nodes_d + L.off + first; a.count = cnt;
     a.dpool = J.dpool; a.ipool = J.ipool; a.xh = xh; a.yh = yh; a.xh_off = J.mvoff_d;
-    a.X = Xp; a.Y = Yp; a.n = P.n; a.nrhs = nrhs;
-    launch_mv_up(a, s);
+    a.X = Xp; a.Y = Yp; a.n = P.n; a.nrhs = nrhs; a.ws = ws; a.ws_off = J.mvws_d;
+    launch_mv_up(a, J.mvtasks_d, J.levels[lev].mcap, s);
   }
   for (int lev = 0; lev <= J.maxlevel; ++lev) {
     MvArgs a;
@@ -115,8 +115,8 @@ void matvec_permuted(const hss_matrix* h, int32_t nrhs, const double* Xp, double
     if (cnt == 0) continue;
     a.desc = J.desc_d; a.st = J.st_d; a.nodes = J.nodes_d + L.off + first; a.count = cnt;
     a.dpool = J.dpool; a.ipool = J.ipool; a.xh = xh; a.yh = yh; a.xh_off = J.mvoff_d;
-    a.X = Xp; a.Y = Yp; a.n = P.n; a.nrhs = nrhs;
-    launch_mv_down(a, s);
+    a.X = Xp; a.Y = Yp; a.n = P.n; a.nrhs = nrhs; a.ws = ws; a.ws_off = J.mvws_d;
+    launch_mv_down(a, J.mvtasks_d, J.levels[lev].mcap, s);
   }
   HSS_HIP_CHECK(hipGetLastError());
 }
@@ -319,9 +319,10 @@ hss_status hss_matvec(const hss_matrix* h, int32_t nrhs, const double* X, int64_
     hipStream_t s = (hipStream_t)stream;
     DevBuf xp(sizeof(double) * P.n * nrhs), yp(sizeof(double) * P.n * nrhs);
     DevBuf xh(sizeof(double) * J.mvtot * nrhs), yh(sizeof(double) * J.mvtot * nrhs);
+    DevBuf ws(sizeof(double) * J.mvwstot * nrhs);
     const int64_t* perm = P.dev.gen.perm;
     launch_gather_rows(X, ldx, perm, P.n, nrhs, xp.as<double>(), P.n, 0, s);
-    matvec_permuted(h, nrhs, xp.as<double>(), yp.as<double>(), xh.as<double>(), yh.as<double>(), s);
+    matvec_permuted(h, nrhs, xp.as<double>(), yp.as<double>(), xh.as<double>(), yh.as<double>(), ws.as<double>(), s);
     launch_gather_rows(yp.as<double>(), P.n, perm, P.n, nrhs, Y, ldy, 1, s);
     HSS_HIP_CHECK(hipGetLastError());
     // temporaries are freed at scope exit; hipFree waits for the device to finish with them
@@ -340,12 +341,13 @@ hss_status hss_rel_error(const hss_matrix* h, const hss_generator* gen, double* 
     const int32_t nb = (int32_t)std::min<int64_t>(P.n, 256);
     DevBuf xp(sizeof(double) * P.n * nb), yp(sizeof(double) * P.n * nb);
     DevBuf xh(sizeof(double) * J.mvtot * nb), yh(sizeof(double) * J.mvtot * nb);
+    DevBuf ws(sizeof(double) * J.mvwstot * nb);
     DevBuf acc(sizeof(double) * 2 * 1024);
     HSS_HIP_CHECK(hipMemsetAsync(acc.p, 0, sizeof(double) * 2 * 1024, s));
     for (int64_t j0 = 0; j0 < P.n; j0 += nb) {
       const int32_t w = (int32_t)std::min<int64_t>(nb, P.n - j0);
       launch_eye_block(xp.as<double>(), P.n, j0, w, s);
-      matvec_permuted(h, w, xp.as<double>(), yp.as<double>(), xh.as<double>(), yh.as<double>(), s);
+      matvec_permuted(h, w, xp.as<double>(), yp.as<double>(), xh.as<double>(), yh.as<double>(), ws.as<double>(), s);
       launch_err_block(P.dev.gen, yp.as<double>(), P.n, j0, w, acc.as<double>(), s);
     }
     std::vector<double> hacc(2 * 1024);

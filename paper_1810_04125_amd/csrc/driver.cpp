@@ -44,6 +44,11 @@ struct ProfScope {
   ~ProfScope() { g_prof = saved; }
 };
 
+// Relative noise level of the reduced-precision samples below which the
+// relative thresholds are not lowered (measured sample accuracy, with margin).
+constexpr double kFloorFp32 = 1e-6;
+constexpr double kFloorBf16x3 = 3e-5;
+
 static int64_t align8(int64_t x) { return (x + 7) & ~int64_t(7); }
 
 Job::~Job() {
@@ -232,6 +237,7 @@ void Job::setup(int32_t count, const hss_generator* gens, const hss_tree* const*
   tasks_d = (GemmTask*)dalloc(sizeof(GemmTask) * 2 * std::max(maxcount, 1));
   qtasks_d = (QrcpTask*)dalloc(sizeof(QrcpTask) * std::max(maxcount, 1));
   qform_d = (QformTask*)dalloc(sizeof(QformTask) * std::max(maxcount, 1));
+  mvtasks_d = (GemmTask*)dalloc(sizeof(GemmTask) * 2 * std::max(maxcount, 1));
   for (auto& L : levels) {
     std::vector<int32_t> mc;
     for (int32_t g : L.nodes) mc.push_back(desc[g].mcap);
@@ -254,6 +260,11 @@ void Job::setup(int32_t count, const hss_generator* gens, const hss_tree* const*
     mvtot = acc;
     mvoff_d = (int64_t*)dalloc(sizeof(int64_t) * gnodes);
     HSS_HIP_CHECK(hipMemcpy(mvoff_d, mo.data(), sizeof(int64_t) * gnodes, hipMemcpyHostToDevice));
+    acc = 0;
+    for (int32_t g = 0; g < gnodes; ++g) { mo[g] = acc; acc += desc[g].mcap; }
+    mvwstot = acc;
+    mvws_d = (int64_t*)dalloc(sizeof(int64_t) * gnodes);
+    HSS_HIP_CHECK(hipMemcpy(mvws_d, mo.data(), sizeof(int64_t) * gnodes, hipMemcpyHostToDevice));
   }
   int32_t off = 0;
   std::vector<int32_t> all;
@@ -292,6 +303,21 @@ void Job::setup(int32_t count, const hss_generator* gens, const hss_tree* const*
       g.dense = P.gen.dense;
       g.ld = P.gen.ld;
     }
+    if (P.opt.sample_precision != HSS_SAMPLE_FP64) {
+      // reduced-precision sampling skips the leaf diagonal blocks
+      std::vector<int32_t> llo(P.n), lhi(P.n);
+      const hss_tree* t = trees[&P - probs.data()];
+      for (int32_t v = 0; v < P.nn; ++v)
+        if (t->left[v] < 0)
+          for (int32_t i = t->lo[v]; i < t->hi[v]; ++i) { llo[i] = t->lo[v]; lhi[i] = t->hi[v]; }
+      int32_t* dlo = (int32_t*)dalloc(sizeof(int32_t) * P.n);
+      int32_t* dhi = (int32_t*)dalloc(sizeof(int32_t) * P.n);
+      HSS_HIP_CHECK(hipMemcpy(dlo, llo.data(), sizeof(int32_t) * P.n, hipMemcpyHostToDevice));
+      HSS_HIP_CHECK(hipMemcpy(dhi, lhi.data(), sizeof(int32_t) * P.n, hipMemcpyHostToDevice));
+      g.leaf_lo = dlo;
+      g.leaf_hi = dhi;
+      g.offdiag = 1;
+    }
     ProbDev& pd = P.dev;
     pd.dcap = P.dcap;
     pd.strategy = strategy;
@@ -300,6 +326,15 @@ void Job::setup(int32_t count, const hss_generator* gens, const hss_tree* const*
     pd.n = P.n;
     pd.eps_r = P.opt.eta * P.opt.rtol;
     pd.eps_a = P.opt.eta * P.opt.atol;
+    // precision floor of the relative thresholds for reduced-precision samples
+    pd.eps_floor = P.opt.sample_precision == HSS_SAMPLE_FP32 ? kFloorFp32
+                 : P.opt.sample_precision == HSS_SAMPLE_BF16X3 ? kFloorBf16x3 : 0.0;
+    {
+      int32_t maxlev = 1;
+      const hss_tree* t = trees[&P - probs.data()];
+      for (int32_t v = 0; v < P.nn; ++v) maxlev = std::max(maxlev, t->level[v]);
+      if (pd.eps_floor > 0.0 && pd.eps_r / maxlev < pd.eps_floor) P.status = HSS_TOL_BELOW_SAMPLING_PRECISION;
+    }
     pd.sglob[0] = P.sglob[0];
     pd.sglob[1] = P.sglob[1];
     pd.R = P.opt.R;
@@ -446,7 +481,7 @@ void Job::compress() {
       if (P.d >= P.dcap) {
         P.force = 1;
         P.b = 0;
-        P.status = HSS_NOT_CONVERGED;
+        if (P.status == HSS_OK) P.status = HSS_NOT_CONVERGED;
         continue;
       }
       int32_t b = strategy == HSS_INC_FNORM ? P.opt.delta_d : P.d;

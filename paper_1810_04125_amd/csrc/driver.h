@@ -63,6 +63,9 @@ struct Job {
   QformTask* qform_d = nullptr;
   int64_t* mvoff_d = nullptr;   // per node: prefix sum of rcap (matvec slots)
   int64_t mvtot = 0;
+  int64_t* mvws_d = nullptr;    // per node: prefix sum of mcap (matvec workspace)
+  int64_t mvwstot = 0;
+  GemmTask* mvtasks_d = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   double sample_ms = 0.0, sample_flops = 0.0, total_ms = 0.0;
   Prof prof;

@@ -29,6 +29,10 @@ struct GenDev {
   const int64_t* perm;
   const double* dense;
   int64_t ld;
+  const int32_t* leaf_lo;  // per permuted index: range of its leaf (reduced-precision
+  const int32_t* leaf_hi;  // sampling skips these diagonal blocks when offdiag = 1)
+  int32_t offdiag;
+  int32_t pad;
 };
 
 // Static per-node description.  Offsets are in elements of the pool of the
@@ -98,6 +102,7 @@ struct ProbDev {
   const int32_t* sched;  // d after every sampling step (block edges), nsched entries
   int32_t nsched;
   int32_t pad1;
+  double eps_floor;      // lower bound of eps_r / level(tau) (sampling precision floor)
   GenDev gen;
 };
 
@@ -253,9 +258,11 @@ struct MvArgs {
   double* Y;
   int64_t n;
   int32_t nrhs;
+  double* ws;           // per node: mcap x nrhs workspace (column-major, ld = mcap)
+  const int64_t* ws_off;
 };
-void launch_mv_up(const MvArgs& a, hipStream_t s);
-void launch_mv_down(const MvArgs& a, hipStream_t s);
+void launch_mv_up(const MvArgs& a, GemmTask* tasks, int32_t mcap, hipStream_t s);
+void launch_mv_down(const MvArgs& a, GemmTask* tasks, int32_t mcap, hipStream_t s);
 void launch_gather_rows(const double* X, int64_t ldx, const int64_t* perm, int64_t n, int32_t nrhs,
                         double* out, int64_t ldo, int32_t inverse, hipStream_t s);
 void launch_eye_block(double* X, int64_t n, int64_t j0, int32_t nb, hipStream_t s);

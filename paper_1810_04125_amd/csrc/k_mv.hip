@@ -11,72 +11,111 @@ namespace hss {
 
 constexpr int MB = 256;
 
-// x_hat(k,c) = xin(J[k],c) + sum_l E(k,l) xin(J[r+l],c)  (V^T from side 1)
-__global__ __launch_bounds__(MB) void k_mv_up(MvArgs a) {
-  const int g = a.nodes[blockIdx.x];
+#define MV_FOR(idx, total) \
+  for (int64_t idx = threadIdx.x + (int64_t)blockIdx.y * MB; idx < (total); idx += (int64_t)MB * gridDim.y)
+
+__device__ __forceinline__ double* xh_of(const MvArgs& a, int g) { return a.xh + a.xh_off[g] * a.nrhs; }
+__device__ __forceinline__ double* yh_of(const MvArgs& a, int g) { return a.yh + a.xh_off[g] * a.nrhs; }
+__device__ __forceinline__ double* ws_of(const MvArgs& a, int g) { return a.ws + a.ws_off[g] * a.nrhs; }
+
+// Upward pass, one level: x_hat = V^T x_in = x_in(J) + E x_in(rest) (side-1
+// basis); x_in = x(I_tau) on a leaf, [x_hat_nu1; x_hat_nu2] above.  Copies
+// x_in(J) into x_hat and x_in(rest) into the node's workspace; the product
+// E x_in(rest) is the GEMM task t.
+__global__ __launch_bounds__(MB) void k_mvu_gather(MvArgs a, GemmTask* __restrict__ tasks) {
+  const int t = blockIdx.x;
+  const int g = a.nodes[t];
   const NodeDesc& nd = a.desc[g];
+  if (threadIdx.x == 0 && blockIdx.y == 0) tasks[t].M = 0;
   if (nd.parent < 0) return;
   const NodeState& st = a.st[g];
   const int r = st.rank[1], m = st.m[1];
   const int32_t* J = a.ipool + nd.J[1];
-  const double* E = a.dpool + nd.E[1];
-  double* xh = a.xh + a.xh_off[g] * a.nrhs;
-  const int ldh = nd.rcap;
+  double* xh = xh_of(a, g);
+  double* xr = ws_of(a, g);
   int rl = 0, ldl = 1, ldr = 1;
-  const double *xl = nullptr, *xr = nullptr;
+  const double *xl = nullptr, *xrr = nullptr;
   if (!nd.leaf) {
     rl = a.st[nd.left].rank[1];
-    xl = a.xh + a.xh_off[nd.left] * a.nrhs;
-    xr = a.xh + a.xh_off[nd.right] * a.nrhs;
+    xl = xh_of(a, nd.left);
+    xrr = xh_of(a, nd.right);
     ldl = a.desc[nd.left].rcap;
     ldr = a.desc[nd.right].rcap;
   }
-  auto xin = [&](int i, int c) -> double {
-    if (nd.leaf) return a.X[(int64_t)c * a.n + nd.lo + i];
-    return i < rl ? xl[(int64_t)c * ldl + i] : xr[(int64_t)c * ldr + (i - rl)];
-  };
-  for (int64_t idx = threadIdx.x; idx < (int64_t)r * a.nrhs; idx += MB) {
-    const int k = (int)(idx % r), c = (int)(idx / r);
-    double s = xin(J[k], c);
-    for (int l = 0; l < m - r; ++l) s += E[(int64_t)l * nd.rcap + k] * xin(J[r + l], c);
-    xh[(int64_t)c * ldh + k] = s;
+  MV_FOR(idx, (int64_t)m * a.nrhs) {
+    const int i = (int)(idx % m), c = (int)(idx / m);
+    const int row = J[i];
+    double v;
+    if (nd.leaf) v = a.X[(int64_t)c * a.n + nd.lo + row];
+    else v = row < rl ? xl[(int64_t)c * ldl + row] : xrr[(int64_t)c * ldr + (row - rl)];
+    if (i < r) xh[(int64_t)c * nd.rcap + i] = v;
+    else xr[(int64_t)c * nd.mcap + (i - r)] = v;
+  }
+  if (threadIdx.x == 0 && blockIdx.y == 0) {
+    GemmTask k;
+    k.A = a.dpool + nd.E[1]; k.a_rs = 1; k.a_cs = nd.rcap;
+    k.B = xr; k.b_rs = 1; k.b_cs = nd.mcap;
+    k.C = xh; k.c_rs = 1; k.c_cs = nd.rcap;
+    k.M = r; k.N = a.nrhs; k.K = m - r; k.pad = 0; k.alpha = 1.0; k.beta = 1.0;
+    tasks[t] = k;
   }
 }
 
-// Inner node: y_hat of the children; leaf: output rows.
-__global__ __launch_bounds__(MB) void k_mv_down(MvArgs a) {
-  const int g = a.nodes[blockIdx.x];
+// Downward pass, one level, GEMM tasks before the scatter: z_rest = E^T y_hat
+// (side-0 basis U = Pi [I; E^T]) into the workspace, and Y(I) = D x(I) on leaves.
+__global__ void k_mvd_pre(MvArgs a, GemmTask* __restrict__ tasks) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= a.count) return;
+  const int g = a.nodes[t];
+  const NodeDesc& nd = a.desc[g];
+  const NodeState& st = a.st[g];
+  GemmTask k;
+  k.pad = 0; k.alpha = 1.0; k.beta = 0.0; k.N = a.nrhs;
+  k.M = 0;
+  if (nd.parent >= 0) {
+    const int r = st.rank[0], m = st.m[0];
+    k.A = a.dpool + nd.E[0]; k.a_rs = nd.rcap; k.a_cs = 1;
+    k.B = yh_of(a, g); k.b_rs = 1; k.b_cs = nd.rcap;
+    k.C = ws_of(a, g); k.c_rs = 1; k.c_cs = nd.mcap;
+    k.M = m - r; k.K = r;
+  }
+  tasks[t] = k;
+  k.M = 0;
+  if (nd.leaf) {
+    const int m = nd.hi - nd.lo;
+    k.A = a.dpool + nd.D; k.a_rs = 1; k.a_cs = m;
+    k.B = a.X + nd.lo; k.b_rs = 1; k.b_cs = a.n;
+    k.C = a.Y + nd.lo; k.c_rs = 1; k.c_cs = a.n;
+    k.M = m; k.K = m;
+  }
+  tasks[a.count + t] = k;
+}
+
+// Downward pass, one level, after k_mvd_pre's products: z = U y_hat placed
+// into the children's y_hat (rows J of z are y_hat, the rest E^T y_hat), or
+// added to the output rows on a leaf; the GEMM tasks add the sibling
+// couplings y_hat_nu1 += B12 x_hat_nu2, y_hat_nu2 += B21 x_hat_nu1.
+__global__ __launch_bounds__(MB) void k_mvd_scatter(MvArgs a, GemmTask* __restrict__ tasks) {
+  const int t = blockIdx.x;
+  const int g = a.nodes[t];
   const NodeDesc& nd = a.desc[g];
   const NodeState& st = a.st[g];
   const bool root = nd.parent < 0;
+  if (threadIdx.x == 0 && blockIdx.y == 0) {
+    tasks[t].M = 0;
+    tasks[a.count + t].M = 0;
+  }
   const int r = root ? 0 : st.rank[0];
-  const double* yh = a.yh + a.xh_off[g] * a.nrhs;
-  const int ldy = nd.rcap;
+  const double* yh = yh_of(a, g);
+  const double* zr = ws_of(a, g);
   const int32_t* J = a.ipool + nd.J[0];
-  const double* E = a.dpool + nd.E[0];
-  const int m0 = root ? 0 : st.m[0];
   if (nd.leaf) {
-    const int m = nd.hi - nd.lo;
-    const double* D = a.dpool + nd.D;
-    for (int64_t idx = threadIdx.x; idx < (int64_t)m * a.nrhs; idx += MB) {
-      const int i = (int)(idx % m), c = (int)(idx / m);
-      double s = 0.0;
-      for (int j = 0; j < m; ++j) s += D[(int64_t)j * m + i] * a.X[(int64_t)c * a.n + nd.lo + j];
-      a.Y[(int64_t)c * a.n + nd.lo + i] = s;
-    }
-    __syncthreads();
     if (root) return;
-    // U y_hat: row J[k] gets y_hat(k); row J[r+l] gets sum_k E(k,l) y_hat(k)
-    for (int64_t idx = threadIdx.x; idx < (int64_t)m0 * a.nrhs; idx += MB) {
-      const int i = (int)(idx % m0), c = (int)(idx / m0);
-      double s;
-      if (i < r) s = yh[(int64_t)c * ldy + i];
-      else {
-        s = 0.0;
-        const int l = i - r;
-        for (int k = 0; k < r; ++k) s += E[(int64_t)l * nd.rcap + k] * yh[(int64_t)c * ldy + k];
-      }
-      a.Y[(int64_t)c * a.n + nd.lo + J[i]] += s;
+    const int m = st.m[0];
+    MV_FOR(idx, (int64_t)m * a.nrhs) {
+      const int i = (int)(idx % m), c = (int)(idx / m);
+      const double v = i < r ? yh[(int64_t)c * nd.rcap + i] : zr[(int64_t)c * nd.mcap + (i - r)];
+      a.Y[(int64_t)c * a.n + nd.lo + J[i]] += v;
     }
     return;
   }
@@ -84,53 +123,54 @@ __global__ __launch_bounds__(MB) void k_mv_down(MvArgs a) {
   const NodeDesc& R = a.desc[nd.right];
   const int rl0 = a.st[nd.left].rank[0], rr0 = a.st[nd.right].rank[0];
   const int rl1 = a.st[nd.left].rank[1], rr1 = a.st[nd.right].rank[1];
-  double* yl = a.yh + a.xh_off[nd.left] * a.nrhs;
-  double* yr = a.yh + a.xh_off[nd.right] * a.nrhs;
-  const double* xl = a.xh + a.xh_off[nd.left] * a.nrhs;
-  const double* xr = a.xh + a.xh_off[nd.right] * a.nrhs;
-  const double* B12 = a.dpool + nd.B12;
-  const double* B21 = a.dpool + nd.B21;
-  // z = U_tau y_hat (zero at the root), split into the children's y_hat
+  double* yl = yh_of(a, nd.left);
+  double* yr = yh_of(a, nd.right);
   const int mz = rl0 + rr0;
-  for (int64_t idx = threadIdx.x; idx < (int64_t)mz * a.nrhs; idx += MB) {
+  MV_FOR(idx, (int64_t)mz * a.nrhs) {
     const int i = (int)(idx % mz), c = (int)(idx / mz);
-    double s = 0.0;
+    double v = 0.0;
+    int row = i;
     if (!root) {
-      (void)m0;
-      if (i < r) s = yh[(int64_t)c * ldy + i];
-      else {
-        const int l = i - r;
-        for (int k = 0; k < r; ++k) s += E[(int64_t)l * nd.rcap + k] * yh[(int64_t)c * ldy + k];
-      }
+      v = i < r ? yh[(int64_t)c * nd.rcap + i] : zr[(int64_t)c * nd.mcap + (i - r)];
+      row = J[i];
     }
-    const int row = root ? i : J[i];
-    if (row < rl0) yl[(int64_t)c * L.rcap + row] = s;
-    else yr[(int64_t)c * R.rcap + (row - rl0)] = s;
+    if (row < rl0) yl[(int64_t)c * L.rcap + row] = v;
+    else yr[(int64_t)c * R.rcap + (row - rl0)] = v;
   }
-  __syncthreads();
-  for (int64_t idx = threadIdx.x; idx < (int64_t)(rl0 + rr0) * a.nrhs; idx += MB) {
-    const int i = (int)(idx % (rl0 + rr0)), c = (int)(idx / (rl0 + rr0));
-    if (i < rl0) {
-      double s = 0.0;
-      for (int k = 0; k < rr1; ++k) s += B12[(int64_t)k * L.rcap + i] * xr[(int64_t)c * R.rcap + k];
-      yl[(int64_t)c * L.rcap + i] += s;
-    } else {
-      const int ii = i - rl0;
-      double s = 0.0;
-      for (int k = 0; k < rl1; ++k) s += B21[(int64_t)k * R.rcap + ii] * xl[(int64_t)c * L.rcap + k];
-      yr[(int64_t)c * R.rcap + ii] += s;
-    }
+  if (threadIdx.x == 0 && blockIdx.y == 0) {
+    GemmTask k;
+    k.pad = 0; k.alpha = 1.0; k.beta = 1.0; k.N = a.nrhs;
+    k.A = a.dpool + nd.B12; k.a_rs = 1; k.a_cs = L.rcap;
+    k.B = xh_of(a, nd.right); k.b_rs = 1; k.b_cs = R.rcap;
+    k.C = yl; k.c_rs = 1; k.c_cs = L.rcap;
+    k.M = rl0; k.K = rr1;
+    tasks[t] = k;
+    k.A = a.dpool + nd.B21; k.a_rs = 1; k.a_cs = R.rcap;
+    k.B = xh_of(a, nd.left); k.b_rs = 1; k.b_cs = L.rcap;
+    k.C = yr; k.c_rs = 1; k.c_cs = R.rcap;
+    k.M = rr0; k.K = rl1;
+    tasks[a.count + t] = k;
   }
 }
 
-void launch_mv_up(const MvArgs& a, hipStream_t s) {
-  if (a.count <= 0) return;
-  hipLaunchKernelGGL(k_mv_up, dim3(a.count), dim3(MB), 0, s, a);
+static dim3 mv_grid(int count) {
+  int g = (512 + count - 1) / count;
+  g = g < 1 ? 1 : (g > 32 ? 32 : g);
+  return dim3(count, g);
 }
 
-void launch_mv_down(const MvArgs& a, hipStream_t s) {
+void launch_mv_up(const MvArgs& a, GemmTask* tasks, int32_t mcap, hipStream_t s) {
   if (a.count <= 0) return;
-  hipLaunchKernelGGL(k_mv_down, dim3(a.count), dim3(MB), 0, s, a);
+  hipLaunchKernelGGL(k_mvu_gather, mv_grid(a.count), dim3(MB), 0, s, a, tasks);
+  launch_gemm(tasks, a.count, mcap, a.nrhs, s);
+}
+
+void launch_mv_down(const MvArgs& a, GemmTask* tasks, int32_t mcap, hipStream_t s) {
+  if (a.count <= 0) return;
+  hipLaunchKernelGGL(k_mvd_pre, dim3((a.count + 127) / 128), dim3(128), 0, s, a, tasks);
+  launch_gemm(tasks, 2 * a.count, mcap, a.nrhs, s);
+  hipLaunchKernelGGL(k_mvd_scatter, mv_grid(a.count), dim3(MB), 0, s, a, tasks);
+  launch_gemm(tasks, 2 * a.count, mcap, a.nrhs, s);
 }
 
 // out(i,c) = X(perm[i], c) (inverse = 0) or out(perm[i], c) = X(i, c) (inverse = 1)

@@ -204,7 +204,7 @@ __global__ __launch_bounds__(NB) void k_ls_gather(LevelArgs a, int side) {
       const int i = (int)(idx % m), c = (int)(idx / m);
       S[(int64_t)i * dcap + c0 + c] = Sg[(int64_t)(c0 + c) * P.n + nd.lo + i];
     }
-    if (threadIdx.x == 0 && blockIdx.y == 0) {
+    if (threadIdx.x == 0 && blockIdx.y == 0 && !P.gen.offdiag) {  // off-diagonal samples need no D R
       GemmTask k;
       k.A = cdp(a, nd.D);
       if (side == 0) { k.a_rs = 1; k.a_cs = m; } else { k.a_rs = m; k.a_cs = 1; }
@@ -356,7 +356,7 @@ __global__ __launch_bounds__(NB) void k_fn_norms(LevelArgs a, int side, QrcpTask
   const ProbDev& P = a.prob[nd.prob];
   const int dcap = P.dcap, m = st.m[side], nc = st.bnc, c0 = st.bc0, ld = nd.mcap;
   const double lev = (double)nd.level;
-  const double er = P.eps_r / lev, ea = P.eps_a / lev;
+  const double er = fmax(P.eps_r / lev, P.eps_floor), ea = P.eps_a / lev;
   const double* S = cdp(a, nd.S[side]);
   double* Sh = a.wsA + nd.ws;
   double p1 = 0.0, p2 = 0.0;
@@ -401,7 +401,7 @@ __global__ void k_fn_rtest(LevelArgs a, int side, QformTask* __restrict__ qf) {
   const ProbDev& P = a.prob[nd.prob];
   const int m = st.m[side], nc = st.bnc;
   const double lev = (double)nd.level;
-  const double er = P.eps_r / lev, ea = P.eps_a / lev;
+  const double er = fmax(P.eps_r / lev, P.eps_floor), ea = P.eps_a / lev;
   const double* rdiag = a.wsB + nd.wsq + 16 + 2 * (int64_t)nc;
   const int r = st.qrank;
   double mn = r < nc ? 0.0 : INFINITY;
@@ -483,7 +483,7 @@ __global__ void k_build_qrcp(LevelArgs a, int side, int hmt, QrcpTask* __restric
   q.lde = nd.rcap;
   q.rank_out = &st.rank[side];
   const double lev = (double)nd.level;
-  q.er = P.eps_r / lev;
+  q.er = fmax(P.eps_r / lev, P.eps_floor);
   q.ea = P.eps_a / lev;
   const int64_t size = nd.hi - nd.lo;
   q.hmt_mn = hmt ? (double)min(size, P.n - size) : 0.0;

@@ -177,20 +177,15 @@ static void launch_fam(const GenDev& g, int transpose, const double* R, int64_t 
                        kchunk, nsplit);
 }
 
-void launch_sample_f32(const GenDev& g, int32_t transpose, int32_t bf16x3, const double* R,
-                       int64_t ldr, double* S, int64_t lds, int32_t ncols, double* partial,
-                       hipStream_t s);
+void launch_sample_lp(const GenDev& g, int32_t transpose, int32_t bf16x3, const double* R, int64_t ldr,
+                      double* out, int64_t lds, int32_t ncols, int64_t kchunk, int32_t nz, dim3 grid,
+                      const int32_t* leaf_lo, const int32_t* leaf_hi, int32_t offdiag, hipStream_t s);
 
 void launch_sample(const GenDev& g, int32_t transpose, int32_t precision, const double* R,
                    int64_t ldr, double* S, int64_t lds, int32_t ncols, double* partial,
                    hipStream_t s, unsigned long long* kcnt) {
   (void)kcnt;
   if (ncols <= 0 || g.n <= 0) return;
-  if (precision != HSS_SAMPLE_FP64) {
-    launch_sample_f32(g, transpose, precision == HSS_SAMPLE_BF16X3, R, ldr, S, lds, ncols,
-                      partial, s);
-    return;
-  }
   const int64_t n = g.n;
   const int nsplit = sample_splits(n, ncols);
   int64_t kchunk = (n + nsplit - 1) / nsplit;
@@ -200,7 +195,10 @@ void launch_sample(const GenDev& g, int32_t transpose, int32_t precision, const 
             (unsigned)nz);
   double* out = nz == 1 ? S : partial;
   prof_begin(s);
-  switch (g.family) {
+  if (precision != HSS_SAMPLE_FP64)
+    launch_sample_lp(g, transpose, precision == HSS_SAMPLE_BF16X3, R, ldr, out, lds, ncols, kchunk, nz, grid,
+                     g.leaf_lo, g.leaf_hi, g.offdiag, s);
+  else switch (g.family) {
     case HSS_FAM_TOEPLITZ: launch_fam<HSS_FAM_TOEPLITZ>(g, transpose, R, ldr, out, lds, ncols, kchunk, nz, grid, s); break;
     case HSS_FAM_LAPLACE: launch_fam<HSS_FAM_LAPLACE>(g, transpose, R, ldr, out, lds, ncols, kchunk, nz, grid, s); break;
     case HSS_FAM_GAUSS: launch_fam<HSS_FAM_GAUSS>(g, transpose, R, ldr, out, lds, ncols, kchunk, nz, grid, s); break;

@@ -197,3 +197,37 @@ def test_deterministic():
         H, _ = hss.compress(gen, T, R, rtol=1e-6, eta=0.1, strategy="inc_fnorm", d0=128, delta_d=64)
         outs.append([(H.node(t, "JR").tobytes(), H.node(t, "ER").tobytes()) for t in range(1, T.num_nodes)])
     assert outs[0] == outs[1]
+
+
+def test_full_size_bench_workload_properties():
+    """Sphere-Laplace n=32768 as in bench.py: exact ||A-H||_F/||A||_F <= rtol,
+    U(J,:) = I structure via the stored pivots, skeleton indices inside the
+    node, and sampled rows of S = A R against the oracle's rows."""
+    from oracle.operators import Laplace
+    n = 32768
+    _log("full size laplace %d" % n)
+    pts = inputs.sphere_points(n, 1)
+    T = hss.Tree(n, 128, pts, "rcb")
+    from oracle.tree import build_tree
+    ot = build_tree(n, 128, pts, "rcb")
+    assert np.array_equal(T.perm, ot.perm) and np.array_equal(T.lo, ot.lo)
+    gen = hss.laplace(dev(pts))
+    Rh = inputs.gaussian_matrix(n, 4096, 0)
+    R = dev_colmajor(Rh)
+    H, st = hss.compress(gen, T, R, rtol=1e-6, atol=1e-12, eta=0.1, strategy="inc_fnorm", d0=128, delta_d=64)
+    assert st == hss.OK
+    err = H.rel_error()
+    _log("full size rel err %.3e" % err)
+    assert err <= 1e-6
+    for t in (1, 2, 5, 100, 300, 510):
+        ni = H.node_info(t)
+        J = H.node(t, "JR")
+        assert sorted(J.tolist()) == list(range(ni["m_r"]))
+        I = H.node(t, "IR")
+        assert np.all((I >= ni["lo"]) & (I < ni["hi"]))
+    # rows of S = A_hat R for the first 128 columns, oracle row by row
+    rows = np.array([0, 7, 4096, 20000, n - 1])
+    S = hss.sample(gen, dev(T.perm), dev_colmajor(Rh[:, :128])).cpu().numpy()
+    lap = Laplace(pts)
+    ref = lap.entries(ot.perm[rows], ot.perm) @ Rh[:, :128]
+    assert np.linalg.norm(S[rows] - ref) <= 1e-12 * np.linalg.norm(ref)
