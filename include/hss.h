@@ -159,10 +159,13 @@ hss_status hss_compress(const hss_generator* gen, const hss_tree* tree,
                         const hss_options* opt, hss_matrix** out);
 
 /* `count` independent compressions run together: every kernel launch
- * covers the same tree level of all problems, and one sampling launch
- * covers every problem (Sec. 4, level-synchronised traversal).  gens,
- * trees, opts and out are arrays of length count; all options must use
- * the same strategy and the same stream. */
+ * covers the same tree level of all problems of a group, and each round
+ * samples every open problem before the tree pass (Sec. 4,
+ * level-synchronised traversal).  Problems are taken in order into groups
+ * whose estimated device memory fits in min(60% of the free HBM, 80 GiB); groups run
+ * one after the other.  gens, trees, opts and out are arrays of length
+ * count; all options must use the same strategy and the same stream.
+ * The sampling time in hss_info is that of the problem's group. */
 hss_status hss_compress_batched(int32_t count, const hss_generator* gens,
                                 const hss_tree* const* trees, const hss_options* opts,
                                 hss_matrix** out);
@@ -254,7 +257,8 @@ hss_status hss_copy_node(const hss_matrix* h, int32_t node, int32_t what, void* 
 /* S = op(A_hat) R for ncols columns, A_hat(i,j) = a(perm[i], perm[j]),
  * op = identity (transpose = 0, S^r) or transpose (1, S^c) (Sec. 2.2
  * eq. sample_off_diag).  perm: device int64[n].  R, S: device, n x ncols,
- * column-major.  precision: hss_precision.  Asynchronous on stream. */
+ * column-major.  precision: hss_precision.  Host-synchronous (the call
+ * returns when S is complete). */
 hss_status hss_sample(const hss_generator* gen, const int64_t* perm, int32_t ncols,
                       const double* R, int64_t ldr, double* S, int64_t lds, int32_t transpose,
                       int32_t precision, void* stream);

@@ -3,6 +3,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <new>
@@ -99,7 +102,7 @@ void matvec_permuted(const hss_matrix* h, int32_t nrhs, const double* Xp, double
       }
     if (cnt == 0) continue;
     a.desc = J.desc_d; a.st = J.st_d; a.nodes = J.nodes_d + L.off + first; a.count = cnt;
-    a.dpool = J.dpool; a.ipool = J.ipool; a.xh = xh; a.yh = yh; a.xh_off = J.mvoff_d;
+    a.dpool = J.dpool; a.epool = J.epool; a.ipool = J.ipool; a.xh = xh; a.yh = yh; a.xh_off = J.mvoff_d;
     a.X = Xp; a.Y = Yp; a.n = P.n; a.nrhs = nrhs; a.ws = ws; a.ws_off = J.mvws_d;
     launch_mv_up(a, J.mvtasks_d, J.levels[lev].mcap, s);
   }
@@ -114,7 +117,7 @@ void matvec_permuted(const hss_matrix* h, int32_t nrhs, const double* Xp, double
       }
     if (cnt == 0) continue;
     a.desc = J.desc_d; a.st = J.st_d; a.nodes = J.nodes_d + L.off + first; a.count = cnt;
-    a.dpool = J.dpool; a.ipool = J.ipool; a.xh = xh; a.yh = yh; a.xh_off = J.mvoff_d;
+    a.dpool = J.dpool; a.epool = J.epool; a.ipool = J.ipool; a.xh = xh; a.yh = yh; a.xh_off = J.mvoff_d;
     a.X = Xp; a.Y = Yp; a.n = P.n; a.nrhs = nrhs; a.ws = ws; a.ws_off = J.mvws_d;
     launch_mv_down(a, J.mvtasks_d, J.levels[lev].mcap, s);
   }
@@ -151,19 +154,46 @@ hss_status hss_compress_batched(int32_t count, const hss_generator* gens, const 
   return guarded([&]() -> hss_status {
     if (count < 1 || !gens || !trees || !opts || !out) throw Error(HSS_ERR_INVALID_ARG, "NULL argument");
     for (int32_t k = 0; k < count; ++k) out[k] = nullptr;
-    auto job = std::make_shared<Job>();
-    job->setup(count, gens, trees, opts);
-    job->compress();
-    hss_status worst = HSS_OK;
     for (int32_t k = 0; k < count; ++k)
-      if (job->probs[k].status > worst) worst = job->probs[k].status;
-    std::vector<hss_matrix*> res(count);
-    for (int32_t k = 0; k < count; ++k) {
-      res[k] = new hss_matrix;
-      res[k]->job = job;
-      res[k]->k = k;
+      if (!trees[k]) throw Error(HSS_ERR_INVALID_ARG, "NULL tree");
+    // Problems are taken in order into groups whose estimated device memory
+    // fits the free HBM at the time the group starts (earlier groups keep only
+    // their generators); every group is one level-batched job.
+    std::vector<std::unique_ptr<hss_matrix>> res(count);
+    hss_status worst = HSS_OK;
+    int32_t g0 = 0;
+    while (g0 < count) {
+      size_t free_b = 0, total_b = 0;
+      HSS_HIP_CHECK(hipMemGetInfo(&free_b, &total_b));
+      const size_t budget = std::min<size_t>((size_t)(0.6 * (double)free_b), (size_t)80 << 30);
+      size_t acc = 0;
+      int32_t g1 = g0;
+      while (g1 < count) {
+        const size_t b = Job::estimate_bytes(gens[g1], trees[g1], opts[g1]);
+        if (g1 > g0 && acc + b > budget) break;
+        acc += b;
+        ++g1;
+      }
+      auto job = std::make_shared<Job>();
+      const auto t0 = std::chrono::steady_clock::now();
+      job->setup(g1 - g0, gens + g0, trees + g0, opts + g0);
+      const auto t1 = std::chrono::steady_clock::now();
+      job->compress();
+      if (std::getenv("HSS_TRACE")) {
+        const auto t2 = std::chrono::steady_clock::now();
+        std::fprintf(stderr, "[hss] group %d..%d: est %.1f GB, setup %.1f ms, compress %.1f ms, sample %.1f ms\n",
+                     g0, g1, acc / 1e9, std::chrono::duration<double, std::milli>(t1 - t0).count(),
+                     std::chrono::duration<double, std::milli>(t2 - t1).count(), job->sample_ms);
+      }
+      for (int32_t k = g0; k < g1; ++k) {
+        if (job->probs[k - g0].status > worst) worst = job->probs[k - g0].status;
+        res[k].reset(new hss_matrix);
+        res[k]->job = job;
+        res[k]->k = k - g0;
+      }
+      g0 = g1;
     }
-    for (int32_t k = 0; k < count; ++k) out[k] = res[k];
+    for (int32_t k = 0; k < count; ++k) out[k] = res[k].release();
     if (worst == HSS_NOT_CONVERGED) g_last_error = "d reached d_max before the root compressed";
     return worst;
   });
@@ -273,8 +303,8 @@ hss_status hss_copy_node(const hss_matrix* h, int32_t node, int32_t what, void* 
         const NodeDesc& R = J.desc[d.right];
         const NodeState& sl = J.st_h[d.left];
         const NodeState& sr = J.st_h[d.right];
-        if (what == HSS_NODE_B12) copy2d(J.dpool + d.B12, L.rcap, sl.rank[0], sr.rank[1]);
-        else copy2d(J.dpool + d.B21, R.rcap, sr.rank[0], sl.rank[1]);
+        if (what == HSS_NODE_B12) copy2d(J.epool + d.B12, d.b12ld, sl.rank[0], sr.rank[1]);
+        else copy2d(J.epool + d.B21, d.b21ld, sr.rank[0], sl.rank[1]);
         break;
       }
       case HSS_NODE_JR:
@@ -290,7 +320,7 @@ hss_status hss_copy_node(const hss_matrix* h, int32_t node, int32_t what, void* 
       case HSS_NODE_EC: {
         if (root) throw Error(HSS_ERR_INVALID_ARG, "the root has no basis");
         const int side = what == HSS_NODE_EC;
-        copy2d(J.dpool + d.E[side], d.rcap, s.rank[side], s.m[side] - s.rank[side]);
+        copy2d(J.epool + d.E[side], d.eld[side], s.rank[side], s.m[side] - s.rank[side]);
         break;
       }
       case HSS_NODE_IR:

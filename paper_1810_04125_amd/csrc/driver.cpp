@@ -13,7 +13,9 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -49,27 +51,118 @@ struct ProfScope {
 constexpr double kFloorFp32 = 1e-6;
 constexpr double kFloorBf16x3 = 3e-5;
 
-static int64_t align8(int64_t x) { return (x + 7) & ~int64_t(7); }
+int64_t align8(int64_t x) { return (x + 7) & ~int64_t(7); }
 
 Job::~Job() {
-  for (void* p : allocs) hipFree(p);
+  if (stream) hipStreamSynchronize(stream);
+  for (void* p : transients) hipFreeAsync(p, stream);
+  for (void* p : allocs) hipFreeAsync(p, stream);
+  hipStreamSynchronize(stream);
   if (ev0) hipEventDestroy(ev0);
   if (ev1) hipEventDestroy(ev1);
   if (prof.e0) hipEventDestroy(prof.e0);
   if (prof.e1) hipEventDestroy(prof.e1);
 }
 
-void* Job::dalloc(size_t bytes) {
+// Device memory comes from the device's stream-ordered memory pool with
+// the release threshold raised, so memory freed by one job is kept mapped
+// and reused by the next one instead of being returned and re-mapped.
+static void keep_pool_memory() {
+  static bool done = false;
+  if (done) return;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return;
+  hipMemPool_t pool;
+  if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+    uint64_t thr = UINT64_MAX;
+    hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+  }
+  hipGetLastError();
+  done = true;
+}
+
+void* Job::dalloc(size_t bytes, bool transient) {
   void* p = nullptr;
   if (bytes == 0) bytes = 8;
-  hipError_t e = hipMalloc(&p, bytes);
+  keep_pool_memory();
+  hipError_t e = hipMallocAsync(&p, bytes, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);   // usable from any stream from now on
   if (e != hipSuccess) {
     hipGetLastError();
     throw Error(e == hipErrorOutOfMemory ? HSS_ERR_OUT_OF_MEMORY : HSS_ERR_DEVICE,
                 "hipMalloc of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
   }
-  allocs.push_back(p);
+  (transient ? transients : allocs).push_back(p);
   return p;
+}
+
+// E of every node side and B12 / B21 of every non-leaf move from their
+// capacity-sized slots in the transient pool to exactly sized blocks of the
+// persistent E pool (E: rank x (m - rank); B: ranks of the children).
+void Job::compact_e() {
+  std::vector<Copy2D> cp;
+  int64_t tot = 0;
+  std::vector<int64_t> newoff(4 * desc.size(), 0);
+  for (size_t g = 0; g < desc.size(); ++g) {
+    const NodeDesc& d = desc[g];
+    if (d.left >= 0) {   // B12: rank_r(left) x rank_c(right), B21: rank_r(right) x rank_c(left)
+      const NodeState &sl = st_h[d.left], &sr = st_h[d.right];
+      newoff[4 * g + 2] = tot;
+      tot += align8((int64_t)std::max(sl.rank[0], 1) * std::max(sr.rank[1], 1));
+      newoff[4 * g + 3] = tot;
+      tot += align8((int64_t)std::max(sr.rank[0], 1) * std::max(sl.rank[1], 1));
+    }
+    if (d.parent < 0) continue;
+    const int nsides = probs[d.prob].sym ? 1 : 2;
+    for (int s = 0; s < nsides; ++s) {
+      const int32_t r = st_h[g].rank[s], m = st_h[g].m[s];
+      newoff[4 * g + s] = tot;
+      tot += align8((int64_t)std::max(r, 1) * std::max(m - r, 1));
+    }
+  }
+  epool = (double*)dalloc(sizeof(double) * std::max<int64_t>(tot, 1));
+  for (size_t g = 0; g < desc.size(); ++g) {
+    NodeDesc& d = desc[g];
+    if (d.left >= 0) {
+      const NodeState &sl = st_h[d.left], &sr = st_h[d.right];
+      const int32_t r1 = sl.rank[0], c2 = sr.rank[1], r2 = sr.rank[0], c1 = sl.rank[1];
+      if (r1 > 0 && c2 > 0) cp.push_back(Copy2D{tpool + d.B12, d.b12ld, epool + newoff[4 * g + 2], r1, r1, c2});
+      if (r2 > 0 && c1 > 0) cp.push_back(Copy2D{tpool + d.B21, d.b21ld, epool + newoff[4 * g + 3], r2, r2, c1});
+      d.B12 = newoff[4 * g + 2];
+      d.b12ld = std::max(r1, 1);
+      d.B21 = newoff[4 * g + 3];
+      d.b21ld = std::max(r2, 1);
+    }
+    if (d.parent < 0) continue;
+    const int nsides = probs[d.prob].sym ? 1 : 2;
+    for (int s = 0; s < nsides; ++s) {
+      const int32_t r = st_h[g].rank[s], m = st_h[g].m[s];
+      if (r > 0 && m > r) cp.push_back(Copy2D{tpool + d.E[s], d.rcap, epool + newoff[4 * g + s], r, r, m - r});
+      d.E[s] = newoff[4 * g + s];
+      d.eld[s] = std::max(r, 1);
+    }
+    if (probs[d.prob].sym) {
+      d.E[1] = d.E[0];
+      d.eld[1] = d.eld[0];
+    }
+  }
+  if (!cp.empty()) {
+    Copy2D* cd = (Copy2D*)dalloc(sizeof(Copy2D) * cp.size(), true);
+    HSS_HIP_CHECK(hipMemcpy(cd, cp.data(), sizeof(Copy2D) * cp.size(), hipMemcpyHostToDevice));
+    launch_copy2d(cd, (int32_t)cp.size(), stream);
+  }
+  HSS_HIP_CHECK(hipMemcpyAsync(desc_d, desc.data(), sizeof(NodeDesc) * desc.size(), hipMemcpyHostToDevice, stream));
+  HSS_HIP_CHECK(hipStreamSynchronize(stream));
+}
+
+// After compression only D, B, E, J, I, the node states and the tables the
+// matvec needs stay on the device.
+void Job::release_transients() {
+  HSS_HIP_CHECK(hipStreamSynchronize(stream));
+  for (void* p : transients) hipFreeAsync(p, stream);
+  HSS_HIP_CHECK(hipStreamSynchronize(stream));
+  transients.clear();
+  tpool = wsa = wsb = partial = nullptr;
 }
 
 static void validate(const hss_generator& g, const hss_tree* t, const hss_options& o, int k) {
@@ -112,6 +205,41 @@ static void validate(const hss_generator& g, const hss_tree* t, const hss_option
   }
 }
 
+// Device bytes one problem adds to a job (node pools, its share of the level
+// workspaces, global samples, generator tables), from the same capacities
+// setup() uses; the batched entry point groups problems by this estimate.
+size_t Job::estimate_bytes(const hss_generator& g, const hss_tree* t, const hss_options& o) {
+  const int32_t nn = t->num_nodes;
+  const int64_t dc = std::min<int64_t>(o.d_max, t->n);
+  const bool sym = g.family != HSS_FAM_DENSE || g.symmetric;
+  const int nsides = sym ? 1 : 2;
+  std::vector<int64_t> mcap(nn), rcap(nn);
+  int64_t dbl = 0, ints = 0;
+  int32_t maxlev = 0;
+  for (int32_t v = nn - 1; v >= 0; --v) {
+    const int64_t size = t->hi[v] - t->lo[v];
+    mcap[v] = t->left[v] < 0 ? size : std::min<int64_t>(size, rcap[t->left[v]] + rcap[t->right[v]]);
+    rcap[v] = std::max<int64_t>(1, std::min<int64_t>(mcap[v], dc));
+    maxlev = std::max(maxlev, t->level[v]);
+  }
+  std::vector<int64_t> wsa(maxlev + 1, 0), wsb(maxlev + 1, 0);
+  for (int32_t v = 0; v < nn; ++v) {
+    const int64_t qcap = o.strategy == HSS_DBL_HMT ? 0 : rcap[v];
+    if (t->parent[v] >= 0)
+      dbl += nsides * (align8(mcap[v] * dc) + align8(rcap[v] * dc) + align8(mcap[v] * qcap) + align8(rcap[v] * mcap[v]));
+    ints += nsides * (align8(mcap[v]) + 2 * align8(rcap[v]));
+    if (t->left[v] < 0) dbl += align8((t->hi[v] - t->lo[v]) * (t->hi[v] - t->lo[v]));
+    else dbl += 2 * align8(rcap[t->left[v]] * rcap[t->right[v]]);
+    wsa[t->level[v]] += align8(mcap[v] * dc);
+    wsb[t->level[v]] += align8(std::max<int64_t>(qcap * dc, 16 + 2 * (mcap[v] + dc)));
+    dbl += 2 * mcap[v] + 2 * rcap[v];   // matvec slots
+  }
+  dbl += nsides * align8(t->n * dc) + 8 * t->n;
+  dbl += *std::max_element(wsa.begin(), wsa.end()) + *std::max_element(wsb.begin(), wsb.end());
+  dbl += (int64_t)sample_partial_elems(t->n, (int32_t)dc);
+  return (size_t)(8 * dbl + 4 * ints + 64 * nn + (16 << 20));
+}
+
 void Job::setup(int32_t count, const hss_generator* gens, const hss_tree* const* trees,
                 const hss_options* opts) {
   if (count < 1) throw Error(HSS_ERR_INVALID_ARG, "count must be >= 1");
@@ -129,7 +257,7 @@ void Job::setup(int32_t count, const hss_generator* gens, const hss_tree* const*
   prof.on = false;
   for (int k = 0; k < count; ++k) prof.on = prof.on || opts[k].profile != 0;
   probs.resize(count);
-  int64_t dtot = 0, itot = 0, ltot = 0;
+  int64_t dtot = 0, ttot = 0, itot = 0, ltot = 0;
   int32_t gnodes = 0;
   maxlevel = 0;
   for (int k = 0; k < count; ++k) {
@@ -176,27 +304,30 @@ void Job::setup(int32_t count, const hss_generator* gens, const hss_tree* const*
       const int nsides = P.sym ? 1 : 2;
       for (int s = 0; s < nsides; ++s) {
         if (!root) {
-          d.S[s] = dtot; dtot += align8((int64_t)d.mcap * dc);
-          d.RR[s] = dtot; dtot += align8((int64_t)d.rcap * dc);
-          d.Q[s] = dtot; dtot += align8((int64_t)d.mcap * d.qcap);
-          d.E[s] = dtot; dtot += align8((int64_t)d.rcap * d.mcap);
+          d.S[s] = ttot; ttot += align8((int64_t)d.mcap * dc);
+          d.RR[s] = ttot; ttot += align8((int64_t)d.rcap * dc);
+          d.Q[s] = ttot; ttot += align8((int64_t)d.mcap * d.qcap);
+          d.E[s] = ttot; ttot += align8((int64_t)d.rcap * d.mcap);
+          d.eld[s] = d.rcap;
           d.J[s] = itot; itot += align8(d.mcap);
           d.I[s] = ltot; ltot += align8(d.rcap);
         }
       }
       if (P.sym) {
-        d.S[1] = d.S[0]; d.RR[1] = d.RR[0]; d.Q[1] = d.Q[0]; d.E[1] = d.E[0];
+        d.S[1] = d.S[0]; d.RR[1] = d.RR[0]; d.Q[1] = d.Q[0]; d.E[1] = d.E[0]; d.eld[1] = d.eld[0];
         d.J[1] = d.J[0]; d.I[1] = d.I[0];
       }
       if (d.leaf) { d.D = dtot; dtot += align8((int64_t)(d.hi - d.lo) * (d.hi - d.lo)); }
       else {
-        d.B12 = dtot; dtot += align8((int64_t)desc[d.left].rcap * desc[d.right].rcap);
-        d.B21 = dtot; dtot += align8((int64_t)desc[d.right].rcap * desc[d.left].rcap);
+        d.B12 = ttot; ttot += align8((int64_t)desc[d.left].rcap * desc[d.right].rcap);
+        d.B21 = ttot; ttot += align8((int64_t)desc[d.right].rcap * desc[d.left].rcap);
+        d.b12ld = desc[d.left].rcap;
+        d.b21ld = desc[d.right].rcap;
       }
     }
     for (int s = 0; s < (P.sym ? 1 : 2); ++s) {
-      P.sglob[s] = dtot;
-      dtot += align8(P.n * dc);
+      P.sglob[s] = ttot;
+      ttot += align8(P.n * dc);
     }
     if (P.sym) P.sglob[1] = P.sglob[0];
   }
@@ -226,11 +357,12 @@ void Job::setup(int32_t count, const hss_generator* gens, const hss_tree* const*
   size_t part = 0;
   for (auto& P : probs) part = std::max(part, sample_partial_elems(P.n, P.dcap));
   dpool = (double*)dalloc(sizeof(double) * std::max<int64_t>(dtot, 1));
+  tpool = (double*)dalloc(sizeof(double) * std::max<int64_t>(ttot, 1), true);
   ipool = (int32_t*)dalloc(sizeof(int32_t) * std::max<int64_t>(itot, 1));
   lpool = (int64_t*)dalloc(sizeof(int64_t) * std::max<int64_t>(ltot, 1));
-  wsa = (double*)dalloc(sizeof(double) * std::max<int64_t>(wsA, 1));
-  wsb = (double*)dalloc(sizeof(double) * std::max<int64_t>(wsB, 1));
-  partial = part ? (double*)dalloc(sizeof(double) * part) : nullptr;
+  wsa = (double*)dalloc(sizeof(double) * std::max<int64_t>(wsA, 1), true);
+  wsb = (double*)dalloc(sizeof(double) * std::max<int64_t>(wsB, 1), true);
+  partial = part ? (double*)dalloc(sizeof(double) * part, true) : nullptr;
   desc_d = (NodeDesc*)dalloc(sizeof(NodeDesc) * gnodes);
   st_d = (NodeState*)dalloc(sizeof(NodeState) * gnodes);
   prob_d = (ProbDev*)dalloc(sizeof(ProbDev) * count);
@@ -345,22 +477,28 @@ void Job::setup(int32_t count, const hss_generator* gens, const hss_tree* const*
   HSS_HIP_CHECK(hipGetLastError());
 }
 
-void Job::sample(Problem& P, int32_t c0, int32_t ncols) {
-  if (ncols <= 0) return;
-  const int prec = P.opt.sample_precision;
-  HSS_HIP_CHECK(hipEventRecord(ev0, stream));
-  for (int s = 0; s < (P.sym ? 1 : 2); ++s) {
-    launch_sample(P.dev.gen, s, prec, P.opt.R + (int64_t)c0 * P.opt.ldr, P.opt.ldr,
-                  dpool + P.sglob[s] + (int64_t)c0 * P.n, P.n, ncols, partial, stream, kcnt_d);
-    host_flops[HSS_K_SAMPLE] += 2.0 * (double)P.n * (double)P.n * ncols;
-    host_bytes[HSS_K_SAMPLE] += 16.0 * (double)P.n * ncols + 24.0 * (double)P.n;
-  }
+// Sampling step of a round: all problems' new columns, asynchronously; the
+// HIP events bracket the whole step (one host wait per round).
+void Job::sample_begin() { HSS_HIP_CHECK(hipEventRecord(ev0, stream)); }
+
+void Job::sample_end() {
   HSS_HIP_CHECK(hipEventRecord(ev1, stream));
   HSS_HIP_CHECK(hipGetLastError());
   HSS_HIP_CHECK(hipEventSynchronize(ev1));
   float ms = 0.f;
   HSS_HIP_CHECK(hipEventElapsedTime(&ms, ev0, ev1));
   sample_ms += ms;
+}
+
+void Job::sample(Problem& P, int32_t c0, int32_t ncols) {
+  if (ncols <= 0) return;
+  const int prec = P.opt.sample_precision;
+  for (int s = 0; s < (P.sym ? 1 : 2); ++s) {
+    launch_sample(P.dev.gen, s, prec, P.opt.R + (int64_t)c0 * P.opt.ldr, P.opt.ldr,
+                  tpool + P.sglob[s] + (int64_t)c0 * P.n, P.n, ncols, partial, stream, kcnt_d);
+    host_flops[HSS_K_SAMPLE] += 2.0 * (double)P.n * (double)P.n * ncols;
+    host_bytes[HSS_K_SAMPLE] += 16.0 * (double)P.n * ncols + 24.0 * (double)P.n;
+  }
   sample_flops += 2.0 * (double)P.n * (double)P.n * ncols * (P.sym ? 1 : 2);
 }
 
@@ -373,6 +511,7 @@ void Job::run_level(int lev, int32_t ncap) {
   a.nodes = nodes_d + L.off;
   a.count = (int32_t)L.nodes.size();
   a.dpool = dpool;
+  a.tpool = tpool;
   a.ipool = ipool;
   a.lpool = lpool;
   a.wsA = wsa;
@@ -430,6 +569,7 @@ void Job::compress() {
   auto t0 = std::chrono::steady_clock::now();
   all_sym = true;
   for (auto& P : probs) all_sym = all_sym && P.sym;
+  sample_begin();
   for (auto& P : probs) {
     P.d = std::min(P.opt.d0, P.dcap);
     P.b = P.d;
@@ -439,6 +579,7 @@ void Job::compress() {
     P.sched.push_back(P.d);
     sample(P, 0, P.d);
   }
+  sample_end();
   std::vector<NodeState> roots(probs.size());
   std::vector<ProbDev> pdev(probs.size());
   int32_t flags[4];
@@ -469,6 +610,7 @@ void Job::compress() {
     HSS_HIP_CHECK(hipStreamSynchronize(stream));
     if (flags[0]) throw Error(HSS_ERR_NONFINITE, "non-finite matrix entry generated");
     bool all_done = true;
+    sample_begin();
     for (size_t k = 0; k < probs.size(); ++k) {
       Problem& P = probs[k];
       if (P.done) continue;
@@ -491,6 +633,7 @@ void Job::compress() {
       P.d += b;
       P.sched.push_back(P.d);
     }
+    sample_end();
     if (all_done) break;
   }
   st_h.resize(desc.size());
@@ -498,6 +641,8 @@ void Job::compress() {
   unsigned long long kc[2 * HSS_K_COUNT];
   HSS_HIP_CHECK(hipMemcpyAsync(kc, kcnt_d, sizeof(kc), hipMemcpyDeviceToHost, stream));
   HSS_HIP_CHECK(hipStreamSynchronize(stream));
+  compact_e();
+  release_transients();
   for (int c = 0; c < HSS_K_COUNT; ++c) {
     kstats[c].launches = prof.launches[c];
     kstats[c].ms = prof.ms[c];

@@ -49,8 +49,10 @@ struct Job {
   bool all_sym = true;
   int32_t max_block = 0;   // widest sampling block so far
   hipStream_t stream = nullptr;
-  std::vector<void*> allocs;
-  double *dpool = nullptr, *wsa = nullptr, *wsb = nullptr, *partial = nullptr;
+  std::vector<void*> allocs;       // live until the job is destroyed
+  std::vector<void*> transients;   // freed when the compression ends
+  double *dpool = nullptr, *tpool = nullptr, *wsa = nullptr, *wsb = nullptr, *partial = nullptr;
+  double* epool = nullptr;         // compacted E (after compression)
   int32_t* ipool = nullptr;
   int64_t* lpool = nullptr;
   NodeDesc* desc_d = nullptr;
@@ -74,11 +76,16 @@ struct Job {
   double host_bytes[HSS_K_COUNT] = {}, host_flops[HSS_K_COUNT] = {};
 
   ~Job();
-  void* dalloc(size_t bytes);
+  void* dalloc(size_t bytes, bool transient = false);
+  void release_transients();
+  void compact_e();
   void setup(int32_t count, const hss_generator* gens, const hss_tree* const* trees,
              const hss_options* opts);
+  static size_t estimate_bytes(const hss_generator& g, const hss_tree* t, const hss_options& o);
   void compress();
   void sample(Problem& P, int32_t c0, int32_t ncols);
+  void sample_begin();
+  void sample_end();
   void run_level(int lev, int32_t ncap);
 };
 

@@ -48,16 +48,20 @@ struct NodeDesc {
   int32_t mcap;                 // capacity of local-sample rows
   int32_t rcap;                 // capacity of the rank
   int32_t qcap;                 // capacity of the test basis Q
-  int32_t pad0;
-  int64_t S[2];    // local samples, mcap x dcap, row-major (ld = dcap)
-  int64_t RR[2];   // reduced random matrix built from side s's basis: rcap x dcap row-major
-  int64_t Q[2];    // stopping-test basis, mcap x qcap column-major
-  int64_t E[2];    // interpolation matrix, rcap x mcap column-major (ld = rcap)
+  int32_t eld[2];               // leading dimension of E per side (rcap while compressing,
+                                // the rank once E is compacted into its own pool)
+  int32_t b12ld, b21ld;         // leading dimensions of B12 / B21 (likewise)
+  int64_t S[2];    // (tpool) local samples, mcap x dcap, row-major (ld = dcap)
+  int64_t RR[2];   // (tpool) reduced random matrix from side s's basis: rcap x dcap row-major
+  int64_t Q[2];    // (tpool) stopping-test basis, mcap x qcap column-major
+  int64_t E[2];    // interpolation matrix E, column-major with leading dimension eld:
+                   // rcap x mcap in the transient pool while compressing, then
+                   // rank x (m - rank) in the E pool
   int64_t J[2];    // int32 pool: mcap pivot order
   int64_t I[2];    // int64 pool: rcap skeleton indices
   int64_t D;       // leaf: size x size column-major
-  int64_t B12;     // rcap(left) x rcap(right) column-major (ld = rcap(left))
-  int64_t B21;     // rcap(right) x rcap(left) column-major (ld = rcap(right))
+  int64_t B12;     // B12 column-major with leading dimension b12ld (transient pool
+  int64_t B21;     // while compressing, then compacted like E)
   int64_t ws;      // offset of this node's slot in the level workspace A (mcap x dcap)
   int64_t wsq;     // offset in the level workspace B (qcap x dcap)
 };
@@ -96,7 +100,7 @@ struct ProbDev {
   int32_t symmetric;
   int64_t n;
   double eps_r, eps_a;   // eta * tol (divided by level(tau) in the kernels)
-  int64_t sglob[2];      // offsets of the global samples (n x dcap col-major) in the double pool
+  int64_t sglob[2];      // offsets of the global samples (n x dcap col-major) in the transient pool
   const double* R;
   int64_t ldr;
   const int32_t* sched;  // d after every sampling step (block edges), nsched entries
@@ -207,7 +211,8 @@ struct LevelArgs {
   const ProbDev* prob;
   const int32_t* nodes;  // global ids of this level's nodes
   int32_t count;
-  double* dpool;
+  double* dpool;         // persistent doubles: D, B12, B21, E
+  double* tpool;         // compression-time doubles: S, RR, Q, global samples
   int32_t* ipool;
   int64_t* lpool;
   double* wsA;
@@ -250,6 +255,7 @@ struct MvArgs {
   const int32_t* nodes;
   int32_t count;
   const double* dpool;
+  const double* epool;  // compacted E
   const int32_t* ipool;
   double* xh;           // per node: rcap x nrhs (column-major, ld = rcap)
   double* yh;
@@ -266,6 +272,15 @@ void launch_mv_down(const MvArgs& a, GemmTask* tasks, int32_t mcap, hipStream_t 
 void launch_gather_rows(const double* X, int64_t ldx, const int64_t* perm, int64_t n, int32_t nrhs,
                         double* out, int64_t ldo, int32_t inverse, hipStream_t s);
 void launch_eye_block(double* X, int64_t n, int64_t j0, int32_t nb, hipStream_t s);
+// dst(i,j) = src(i,j) for rows x cols blocks, one workgroup per block
+struct Copy2D {
+  const double* src;
+  int64_t lds;
+  double* dst;
+  int64_t ldd;
+  int32_t rows, cols;
+};
+void launch_copy2d(const Copy2D* tasks, int32_t count, hipStream_t s);
 void launch_err_block(const GenDev& g, const double* Hc, int64_t ldh, int64_t j0, int32_t nb,
                       double* accum, hipStream_t s);
 

@@ -53,7 +53,7 @@ __global__ __launch_bounds__(MB) void k_mvu_gather(MvArgs a, GemmTask* __restric
   }
   if (threadIdx.x == 0 && blockIdx.y == 0) {
     GemmTask k;
-    k.A = a.dpool + nd.E[1]; k.a_rs = 1; k.a_cs = nd.rcap;
+    k.A = a.epool + nd.E[1]; k.a_rs = 1; k.a_cs = nd.eld[1];
     k.B = xr; k.b_rs = 1; k.b_cs = nd.mcap;
     k.C = xh; k.c_rs = 1; k.c_cs = nd.rcap;
     k.M = r; k.N = a.nrhs; k.K = m - r; k.pad = 0; k.alpha = 1.0; k.beta = 1.0;
@@ -74,7 +74,7 @@ __global__ void k_mvd_pre(MvArgs a, GemmTask* __restrict__ tasks) {
   k.M = 0;
   if (nd.parent >= 0) {
     const int r = st.rank[0], m = st.m[0];
-    k.A = a.dpool + nd.E[0]; k.a_rs = nd.rcap; k.a_cs = 1;
+    k.A = a.epool + nd.E[0]; k.a_rs = nd.eld[0]; k.a_cs = 1;
     k.B = yh_of(a, g); k.b_rs = 1; k.b_cs = nd.rcap;
     k.C = ws_of(a, g); k.c_rs = 1; k.c_cs = nd.mcap;
     k.M = m - r; k.K = r;
@@ -140,12 +140,12 @@ __global__ __launch_bounds__(MB) void k_mvd_scatter(MvArgs a, GemmTask* __restri
   if (threadIdx.x == 0 && blockIdx.y == 0) {
     GemmTask k;
     k.pad = 0; k.alpha = 1.0; k.beta = 1.0; k.N = a.nrhs;
-    k.A = a.dpool + nd.B12; k.a_rs = 1; k.a_cs = L.rcap;
+    k.A = a.epool + nd.B12; k.a_rs = 1; k.a_cs = nd.b12ld;
     k.B = xh_of(a, nd.right); k.b_rs = 1; k.b_cs = R.rcap;
     k.C = yl; k.c_rs = 1; k.c_cs = L.rcap;
     k.M = rl0; k.K = rr1;
     tasks[t] = k;
-    k.A = a.dpool + nd.B21; k.a_rs = 1; k.a_cs = R.rcap;
+    k.A = a.epool + nd.B21; k.a_rs = 1; k.a_cs = nd.b21ld;
     k.B = xh_of(a, nd.left); k.b_rs = 1; k.b_cs = L.rcap;
     k.C = yr; k.c_rs = 1; k.c_cs = R.rcap;
     k.M = rr0; k.K = rl1;
@@ -248,6 +248,20 @@ void launch_extract(const GenDev& g, int32_t nI, const int64_t* I, int32_t nJ, c
   if (tot <= 0) return;
   hipLaunchKernelGGL(k_extract_list, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, g, nI, I, nJ, J,
                      out, ldo);
+}
+
+__global__ void k_copy2d(const Copy2D* __restrict__ tasks) {
+  const Copy2D t = tasks[blockIdx.x];
+  const int64_t tot = (int64_t)t.rows * t.cols;
+  for (int64_t idx = threadIdx.x; idx < tot; idx += blockDim.x) {
+    const int64_t i = idx % t.rows, j = idx / t.rows;
+    t.dst[j * t.ldd + i] = t.src[j * t.lds + i];
+  }
+}
+
+void launch_copy2d(const Copy2D* tasks, int32_t count, hipStream_t s) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_copy2d, dim3(count), dim3(256), 0, s, tasks);
 }
 
 void launch_err_block(const GenDev& g, const double* Hc, int64_t ldh, int64_t j0, int32_t nb,

@@ -57,6 +57,8 @@ static dim3 node_grid(int count) {
 
 __device__ __forceinline__ const double* cdp(const LevelArgs& a, int64_t off) { return a.dpool + off; }
 __device__ __forceinline__ double* dp(const LevelArgs& a, int64_t off) { return a.dpool + off; }
+__device__ __forceinline__ const double* ctp(const LevelArgs& a, int64_t off) { return a.tpool + off; }
+__device__ __forceinline__ double* tp(const LevelArgs& a, int64_t off) { return a.tpool + off; }
 
 // ------------------------------------------------------------------ plan
 __global__ void k_plan(LevelArgs a) {
@@ -142,22 +144,22 @@ __global__ __launch_bounds__(NB) void k_extract_nodes(LevelArgs a) {
     const int r1 = sl.rank[0], c2 = sr.rank[1];
     const int64_t* I1r = a.lpool + L.I[0];
     const int64_t* I2c = a.lpool + Rn.I[1];
-    double* B12 = dp(a, nd.B12);
+    double* B12 = tp(a, nd.B12);
     CHUNKED_FOR(idx, (int64_t)r1 * c2) {
       const int i = (int)(idx % r1), j = (int)(idx / r1);
       const double v = gen_entry(gen, I1r[i], I2c[j]);
       bad |= !isfinite(v);
-      B12[(int64_t)j * L.rcap + i] = v;
+      B12[(int64_t)j * nd.b12ld + i] = v;
     }
     const int r2 = sr.rank[0], c1 = sl.rank[1];
     const int64_t* I2r = a.lpool + Rn.I[0];
     const int64_t* I1c = a.lpool + L.I[1];
-    double* B21 = dp(a, nd.B21);
+    double* B21 = tp(a, nd.B21);
     CHUNKED_FOR(idx, (int64_t)r2 * c1) {
       const int i = (int)(idx % r2), j = (int)(idx / r2);
       const double v = gen_entry(gen, I2r[i], I1c[j]);
       bad |= !isfinite(v);
-      B21[(int64_t)j * Rn.rcap + i] = v;
+      B21[(int64_t)j * nd.b21ld + i] = v;
     }
   }
   if (bad) atomicOr(a.flags, 1);
@@ -196,10 +198,10 @@ __global__ __launch_bounds__(NB) void k_ls_gather(LevelArgs a, int side) {
   const int dcap = P.dcap;
   const int c0 = st.c0, nc = st.nc;
   const int m = st.m[side];
-  double* S = dp(a, nd.S[side]);
+  double* S = tp(a, nd.S[side]);
   if (threadIdx.x == 0 && blockIdx.y == 0) kcount(a.kcnt, HSS_K_GATHER, 16.0 * m * nc, 0.0);
   if (nd.leaf) {
-    const double* Sg = cdp(a, P.sglob[side]);
+    const double* Sg = ctp(a, P.sglob[side]);
     CHUNKED_FOR(idx, (int64_t)m * nc) {
       const int i = (int)(idx % m), c = (int)(idx / m);
       S[(int64_t)i * dcap + c0 + c] = Sg[(int64_t)(c0 + c) * P.n + nd.lo + i];
@@ -227,8 +229,8 @@ __global__ __launch_bounds__(NB) void k_ls_gather(LevelArgs a, int side) {
   const int r1 = sl.rank[side];
   const int32_t* J1 = a.ipool + L.J[side];
   const int32_t* J2 = a.ipool + Rn.J[side];
-  const double* S1 = cdp(a, L.S[side]);
-  const double* S2 = cdp(a, Rn.S[side]);
+  const double* S1 = ctp(a, L.S[side]);
+  const double* S2 = ctp(a, Rn.S[side]);
   CHUNKED_FOR(idx, (int64_t)m * nc) {
     const int c = (int)(idx % nc), i = (int)(idx / nc);
     const double v = i < r1 ? S1[(int64_t)J1[i] * dcap + c0 + c] : S2[(int64_t)J2[i - r1] * dcap + c0 + c];
@@ -240,22 +242,22 @@ __global__ __launch_bounds__(NB) void k_ls_gather(LevelArgs a, int side) {
     k.alpha = -1.0; k.beta = 1.0;
     if (side == 0) {
       // [left.S^r(J) - B12 right.R^r ; right.S^r(J) - B21 left.R^r], R^r = V^T R (side-1 basis)
-      k.A = cdp(a, nd.B12); k.a_rs = 1; k.a_cs = L.rcap;
-      k.B = cdp(a, Rn.RR[1]) + c0; k.C = S + c0;
+      k.A = ctp(a, nd.B12); k.a_rs = 1; k.a_cs = nd.b12ld;
+      k.B = ctp(a, Rn.RR[1]) + c0; k.C = S + c0;
       k.M = sl.rank[0]; k.K = sr.rank[1];
       *T0 = k;
-      k.A = cdp(a, nd.B21); k.a_rs = 1; k.a_cs = Rn.rcap;
-      k.B = cdp(a, L.RR[1]) + c0; k.C = S + (int64_t)sl.rank[0] * dcap + c0;
+      k.A = ctp(a, nd.B21); k.a_rs = 1; k.a_cs = nd.b21ld;
+      k.B = ctp(a, L.RR[1]) + c0; k.C = S + (int64_t)sl.rank[0] * dcap + c0;
       k.M = sr.rank[0]; k.K = sl.rank[1];
       *T1 = k;
     } else {
       // [left.S^c(J) - B21^T right.R^c ; right.S^c(J) - B12^T left.R^c], R^c = U^T R
-      k.A = cdp(a, nd.B21); k.a_rs = Rn.rcap; k.a_cs = 1;
-      k.B = cdp(a, Rn.RR[0]) + c0; k.C = S + c0;
+      k.A = ctp(a, nd.B21); k.a_rs = nd.b21ld; k.a_cs = 1;
+      k.B = ctp(a, Rn.RR[0]) + c0; k.C = S + c0;
       k.M = sl.rank[1]; k.K = sr.rank[0];
       *T0 = k;
-      k.A = cdp(a, nd.B12); k.a_rs = L.rcap; k.a_cs = 1;
-      k.B = cdp(a, L.RR[0]) + c0; k.C = S + (int64_t)sl.rank[1] * dcap + c0;
+      k.A = ctp(a, nd.B12); k.a_rs = nd.b12ld; k.a_cs = 1;
+      k.B = ctp(a, L.RR[0]) + c0; k.C = S + (int64_t)sl.rank[1] * dcap + c0;
       k.M = sr.rank[1]; k.K = sl.rank[0];
       *T1 = k;
     }
@@ -316,14 +318,14 @@ __global__ __launch_bounds__(NB) void k_fn_copy(LevelArgs a, int side, int iter)
   const ProbDev& P = a.prob[nd.prob];
   const int dcap = P.dcap, m = st.m[side], q = st.q[side];
   if (first && threadIdx.x == 0) kcount(a.kcnt, HSS_K_GATHER, 16.0 * m * nc, 0.0);
-  const double* S = cdp(a, nd.S[side]);
+  const double* S = ctp(a, nd.S[side]);
   double* Sh = a.wsA + nd.ws;
   CHUNKED_FOR(idx, (int64_t)m * nc) {
     const int i = (int)(idx % m), c = (int)(idx / m);
     Sh[(int64_t)c * nd.mcap + i] = S[(int64_t)i * dcap + c0 + c];
   }
   if (first && threadIdx.x == 0) {
-    const double* Q = cdp(a, nd.Q[side]);
+    const double* Q = ctp(a, nd.Q[side]);
     double* W = a.wsB + nd.wsq;
     GemmTask k;
     k.pad = 0;
@@ -357,7 +359,7 @@ __global__ __launch_bounds__(NB) void k_fn_norms(LevelArgs a, int side, QrcpTask
   const int dcap = P.dcap, m = st.m[side], nc = st.bnc, c0 = st.bc0, ld = nd.mcap;
   const double lev = (double)nd.level;
   const double er = fmax(P.eps_r / lev, P.eps_floor), ea = P.eps_a / lev;
-  const double* S = cdp(a, nd.S[side]);
+  const double* S = ctp(a, nd.S[side]);
   double* Sh = a.wsA + nd.ws;
   double p1 = 0.0, p2 = 0.0;
   for (int64_t idx = threadIdx.x; idx < (int64_t)m * nc; idx += NB) {
@@ -415,7 +417,7 @@ __global__ void k_fn_rtest(LevelArgs a, int side, QformTask* __restrict__ qf) {
   QformTask f;
   f.W = a.wsA + nd.ws; f.ldw = nd.mcap;
   f.rdiag = rdiag;
-  f.Q = dp(a, nd.Q[side]) + (int64_t)st.q[side] * nd.mcap; f.ldq = nd.mcap;
+  f.Q = tp(a, nd.Q[side]) + (int64_t)st.q[side] * nd.mcap; f.ldq = nd.mcap;
   f.m = m; f.nc = nc; f.active = 1; f.pad = 0;
   qf[t] = f;
   st.q[side] += nc;
@@ -473,13 +475,13 @@ __global__ void k_build_qrcp(LevelArgs a, int side, int hmt, QrcpTask* __restric
   const ProbDev& P = a.prob[nd.prob];
   QrcpTask q;
   q.active = st.active && st.test && (hmt || st.go);
-  q.S = a.dpool + nd.S[side];
+  q.S = a.tpool + nd.S[side];
   q.lds = P.dcap;
   q.W = a.wsA + nd.ws;
   q.ldw = P.dcap;
   q.scr = a.wsB + nd.wsq;
   q.J = a.ipool + nd.J[side];
-  q.E = a.dpool + nd.E[side];
+  q.E = a.tpool + nd.E[side];
   q.lde = nd.rcap;
   q.rank_out = &st.rank[side];
   const double lev = (double)nd.level;
@@ -540,15 +542,15 @@ __global__ __launch_bounds__(NB) void k_red_gather(LevelArgs a, int side) {
   const int nc = P.d - c0;
   const int m = st.m[side], r = st.rank[side];
   const int32_t* J = a.ipool + nd.J[side];
-  double* RR = dp(a, nd.RR[side]);
+  double* RR = tp(a, nd.RR[side]);
   if (threadIdx.x == 0 && blockIdx.y == 0) kcount(a.kcnt, HSS_K_GATHER, 16.0 * m * nc, 0.0);
   double* Xr = a.wsA + nd.ws;  // (m - r) x nc, column-major, ld = mcap
   int r1 = 0;
   const double *X1 = nullptr, *X2 = nullptr;
   if (!nd.leaf) {
     r1 = a.st[nd.left].rank[side];
-    X1 = cdp(a, a.desc[nd.left].RR[side]);
-    X2 = cdp(a, a.desc[nd.right].RR[side]);
+    X1 = ctp(a, a.desc[nd.left].RR[side]);
+    X2 = ctp(a, a.desc[nd.right].RR[side]);
   }
   CHUNKED_FOR(idx, (int64_t)m * nc) {
     const int c = (int)(idx % nc), i = (int)(idx / nc);
@@ -570,7 +572,7 @@ __global__ __launch_bounds__(NB) void k_red_gather(LevelArgs a, int side) {
   }
   if (threadIdx.x == 0 && blockIdx.y == 0) {
     GemmTask k;
-    k.A = cdp(a, nd.E[side]); k.a_rs = 1; k.a_cs = nd.rcap;
+    k.A = ctp(a, nd.E[side]); k.a_rs = 1; k.a_cs = nd.rcap;
     k.B = Xr; k.b_rs = 1; k.b_cs = nd.mcap;
     k.C = RR + c0; k.c_rs = dcap; k.c_cs = 1;
     k.M = r; k.N = nc; k.K = m - r; k.pad = 0;
