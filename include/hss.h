@@ -284,6 +284,63 @@ hss_status hss_interpolative_batched(int32_t count, const int32_t* m, const int3
                                      const int64_t* piv_off, double* E, const int64_t* e_off,
                                      int32_t* rank_host);
 
+/* --- learned rank / d0 predictor ----------------------------------------
+ * Not part of the paper's method: the adaptive driver (Alg. 3) needs an
+ * initial sample count d0 and, with the incrementing strategy (Alg. 5),
+ * pays one round of sampling, stopping tests and IDs per increment between
+ * d0 and the final d.  A small network fed with features that are known
+ * before any sampling (family, kernel parameter, n, tree level, node size,
+ * tolerance) predicts per-level node ranks and the final d, so d0 can start
+ * close to it.  The stopping tests of the compression stay the judge: a low
+ * prediction only costs extra rounds, a high one extra sample columns.
+ *
+ * The network is a fully connected ReLU net in FP32: layer l maps
+ * sizes[l] -> sizes[l+1], ReLU after every layer but the last.  Parameters
+ * are one device float array, for each layer W_l (sizes[l+1] x sizes[l],
+ * ROW-major) followed by b_l (sizes[l+1]).  Samples are ROW-major: X is
+ * n x sizes[0], Y, T (targets) and M (0/1 masks) are n x sizes[n_layers].
+ * Loss: sum(M (Y - T)^2) / max(1, sum M); Adam as Kingma and Ba (2015). */
+#define HSS_MLP_MAX_LAYERS 6
+#define HSS_MLP_MAX_WIDTH 128
+typedef struct {
+  int32_t n_layers;                        /* 1 .. HSS_MLP_MAX_LAYERS */
+  int32_t sizes[HSS_MLP_MAX_LAYERS + 1];   /* each 1 .. HSS_MLP_MAX_WIDTH */
+} hss_mlp;
+
+/* Number of parameters (floats) of the network, to host *out. */
+hss_status hss_mlp_num_params(const hss_mlp* net, int64_t* out);
+
+/* Y = net(X) for n samples; device pointers; asynchronous on `stream`. */
+hss_status hss_mlp_forward(const hss_mlp* net, const float* params, const float* X, int64_t n,
+                           float* Y, void* stream);
+
+/* grad (device, num_params floats) = dLoss/dparams over the n samples, and
+ * the loss to *loss_dev (device float, may be NULL).  Partial gradients of
+ * 32-sample tiles are summed in tile order, so the result is deterministic.
+ * Allocates a stream-ordered workspace of about (n/32) * num_params floats;
+ * asynchronous on `stream`. */
+hss_status hss_mlp_gradient(const hss_mlp* net, const float* params, const float* X,
+                            const float* T, const float* M, int64_t n, float* grad,
+                            float* loss_dev, void* stream);
+
+/* One Adam step, in place on params, m, v (device, np floats each); step is
+ * the 1-based step count used in the bias corrections. */
+hss_status hss_mlp_adam(int64_t np, float* params, const float* grad, float* m, float* v,
+                        float lr, float beta1, float beta2, float eps, int64_t step,
+                        void* stream);
+
+/* Mini-batch Adam training, all on the device: `epochs` passes over the n
+ * samples, each in an order given by the affine permutation
+ * i -> (a i + c) mod n with a coprime to n, a and c drawn from `seed` and
+ * the epoch number; batches of `batch` consecutive positions (the last one
+ * ragged).  *step (host, in/out) is the Adam step count.  loss_host (host,
+ * `epochs` floats, may be NULL) receives the mean batch loss of each
+ * epoch.  Host-synchronous. */
+hss_status hss_mlp_train(const hss_mlp* net, float* params, float* m, float* v, int64_t* step,
+                         const float* X, const float* T, const float* M, int64_t n,
+                         int32_t batch, int32_t epochs, float lr, uint64_t seed,
+                         float* loss_host, void* stream);
+
 const char* hss_last_error(void);
 const char* hss_version(void);
 

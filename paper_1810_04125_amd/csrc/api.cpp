@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -130,6 +131,70 @@ struct DevBuf {
   ~DevBuf() { if (p) hipFree(p); }
   template <class T> T* as() const { return (T*)p; }
 };
+
+// Stream-ordered scratch: allocated and freed in the order of `s`, so
+// asynchronous calls may return while their kernels still use it.
+struct StreamBuf {
+  void* p = nullptr;
+  hipStream_t s;
+  StreamBuf(size_t bytes, hipStream_t st) : s(st) {
+    hipError_t e = hipMallocAsync(&p, std::max<size_t>(bytes, 8), s);
+    if (e != hipSuccess) {
+      hipGetLastError();
+      p = nullptr;
+      throw Error(e == hipErrorOutOfMemory ? HSS_ERR_OUT_OF_MEMORY : HSS_ERR_DEVICE,
+                  "hipMallocAsync of " + std::to_string(bytes) + " bytes failed");
+    }
+  }
+  ~StreamBuf() {
+    if (p) hipFreeAsync(p, s);
+  }
+  template <class T> T* as() const { return (T*)p; }
+};
+
+uint64_t splitmix64(uint64_t& x) {  // Steele, Lea and Flood (2014)
+  uint64_t z = (x += 0x9E3779B97F4A7C15ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+int64_t gcd64(int64_t a, int64_t b) {
+  while (b) {
+    const int64_t t = a % b;
+    a = b;
+    b = t;
+  }
+  return a;
+}
+
+// i -> (a i + c) mod n, a coprime to n: the sample order of one epoch
+void epoch_order(uint64_t seed, int64_t epoch, int64_t n, int64_t& a, int64_t& c) {
+  if (n <= 1) {
+    a = 1;
+    c = 0;
+    return;
+  }
+  uint64_t x = seed ^ (0xD1B54A32D192ED03ull * (uint64_t)(epoch + 1));
+  a = 1 + (int64_t)(splitmix64(x) % (uint64_t)(n - 1));
+  while (gcd64(a, n) != 1) a = a % (n - 1) + 1;
+  c = (int64_t)(splitmix64(x) % (uint64_t)n);
+}
+
+MlpAdam adam_consts(float lr, float b1, float b2, float eps, int64_t step) {
+  MlpAdam a;
+  a.lr = lr;
+  a.b1 = b1;
+  a.b2 = b2;
+  a.eps = eps;
+  a.bc1 = (float)(1.0 - std::pow((double)b1, (double)step));
+  a.bc2 = (float)(1.0 - std::pow((double)b2, (double)step));
+  return a;
+}
+
+void need(const void* p, const char* what) {
+  if (!p) throw Error(HSS_ERR_INVALID_ARG, std::string(what) + " must not be NULL");
+}
 
 }  // namespace
 
@@ -485,6 +550,121 @@ hss_status hss_interpolative_batched(int32_t count, const int32_t* m, const int3
              nullptr);
     HSS_HIP_CHECK(hipStreamSynchronize(nullptr));
     HSS_HIP_CHECK(hipMemcpy(rank_host, drk.p, sizeof(int32_t) * count, hipMemcpyDeviceToHost));
+    return HSS_OK;
+  });
+}
+
+hss_status hss_mlp_num_params(const hss_mlp* net, int64_t* out) {
+  return guarded([&]() -> hss_status {
+    need(net, "net");
+    need(out, "out");
+    *out = mlp_shape(*net).np;
+    return HSS_OK;
+  });
+}
+
+hss_status hss_mlp_forward(const hss_mlp* net, const float* params, const float* X, int64_t n, float* Y,
+                           void* stream) {
+  return guarded([&]() -> hss_status {
+    need(net, "net");
+    const MlpShape S = mlp_shape(*net);
+    if (n < 0 || n >= (int64_t(1) << 31)) throw Error(HSS_ERR_INVALID_ARG, "n must be in [0, 2^31)");
+    if (n == 0) return HSS_OK;
+    need(params, "params");
+    need(X, "X");
+    need(Y, "Y");
+    launch_mlp_tile(S, params, X, nullptr, nullptr, 0, n, 1, 0, n, Y, nullptr, nullptr, 0, (hipStream_t)stream);
+    HSS_HIP_CHECK(hipGetLastError());
+    return HSS_OK;
+  });
+}
+
+hss_status hss_mlp_gradient(const hss_mlp* net, const float* params, const float* X, const float* T,
+                            const float* M, int64_t n, float* grad, float* loss_dev, void* stream) {
+  return guarded([&]() -> hss_status {
+    need(net, "net");
+    const MlpShape S = mlp_shape(*net);
+    if (n < 0 || n >= (int64_t(1) << 31)) throw Error(HSS_ERR_INVALID_ARG, "n must be in [0, 2^31)");
+    need(params, "params");
+    need(grad, "grad");
+    if (n > 0) {
+      need(X, "X");
+      need(T, "T");
+      need(M, "M");
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t nblk = mlp_tiles(n);
+    StreamBuf part(sizeof(float) * nblk * S.np, s), cl(sizeof(float) * 2 * nblk, s);
+    launch_mlp_tile(S, params, X, T, M, 0, n, 1, 0, std::max<int64_t>(n, 1), nullptr, part.as<float>(),
+                    cl.as<float>(), 1, s);
+    launch_mlp_reduce(S.np, (int32_t)nblk, part.as<float>(), cl.as<float>(), grad, loss_dev, nullptr, nullptr,
+                      nullptr, MlpAdam{}, 0, s);
+    HSS_HIP_CHECK(hipGetLastError());
+    return HSS_OK;
+  });
+}
+
+hss_status hss_mlp_adam(int64_t np, float* params, const float* grad, float* m, float* v, float lr, float beta1,
+                        float beta2, float eps, int64_t step, void* stream) {
+  return guarded([&]() -> hss_status {
+    if (np < 0) throw Error(HSS_ERR_INVALID_ARG, "np must be >= 0");
+    if (step < 1) throw Error(HSS_ERR_INVALID_ARG, "step must be >= 1");
+    if (np == 0) return HSS_OK;
+    need(params, "params");
+    need(grad, "grad");
+    need(m, "m");
+    need(v, "v");
+    launch_mlp_adam(np, params, grad, m, v, adam_consts(lr, beta1, beta2, eps, step), (hipStream_t)stream);
+    HSS_HIP_CHECK(hipGetLastError());
+    return HSS_OK;
+  });
+}
+
+hss_status hss_mlp_train(const hss_mlp* net, float* params, float* m, float* v, int64_t* step, const float* X,
+                         const float* T, const float* M, int64_t n, int32_t batch, int32_t epochs, float lr,
+                         uint64_t seed, float* loss_host, void* stream) {
+  return guarded([&]() -> hss_status {
+    need(net, "net");
+    const MlpShape S = mlp_shape(*net);
+    if (n < 1 || n >= (int64_t(1) << 31)) throw Error(HSS_ERR_INVALID_ARG, "n must be in [1, 2^31)");
+    if (batch < 1 || epochs < 0) throw Error(HSS_ERR_INVALID_ARG, "batch must be >= 1 and epochs >= 0");
+    need(step, "step");
+    if (*step < 0) throw Error(HSS_ERR_INVALID_ARG, "*step must be >= 0");
+    need(params, "params");
+    need(m, "m");
+    need(v, "v");
+    need(X, "X");
+    need(T, "T");
+    need(M, "M");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t B = std::min<int64_t>(batch, n);
+    const int64_t nbatch = (n + B - 1) / B;
+    const int64_t nblk = mlp_tiles(B);
+    StreamBuf part(sizeof(float) * nblk * S.np, s), cl(sizeof(float) * 2 * nblk, s);
+    StreamBuf losses(sizeof(float) * std::max<int64_t>(1, (int64_t)epochs * nbatch), s);
+    for (int32_t e = 0; e < epochs; ++e) {
+      int64_t a, c;
+      epoch_order(seed, e, n, a, c);
+      for (int64_t b = 0; b < nbatch; ++b) {
+        const int64_t p0 = b * B, p1 = std::min(n, p0 + B);
+        launch_mlp_tile(S, params, X, T, M, p0, p1, a, c, n, nullptr, part.as<float>(), cl.as<float>(), 1, s);
+        ++*step;
+        launch_mlp_reduce(S.np, (int32_t)mlp_tiles(p1 - p0), part.as<float>(), cl.as<float>(), nullptr,
+                          losses.as<float>() + (int64_t)e * nbatch + b, params, m, v,
+                          adam_consts(lr, 0.9f, 0.999f, 1e-8f, *step), 1, s);
+      }
+    }
+    HSS_HIP_CHECK(hipGetLastError());
+    std::vector<float> lh((size_t)std::max<int64_t>(1, (int64_t)epochs * nbatch));
+    if (epochs > 0)
+      HSS_HIP_CHECK(hipMemcpyAsync(lh.data(), losses.p, sizeof(float) * epochs * nbatch, hipMemcpyDeviceToHost, s));
+    HSS_HIP_CHECK(hipStreamSynchronize(s));
+    if (loss_host)
+      for (int32_t e = 0; e < epochs; ++e) {
+        double q = 0.0;
+        for (int64_t b = 0; b < nbatch; ++b) q += lh[(size_t)(e * nbatch + b)];
+        loss_host[e] = (float)(q / (double)nbatch);
+      }
     return HSS_OK;
   });
 }

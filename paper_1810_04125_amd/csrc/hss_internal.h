@@ -284,6 +284,30 @@ void launch_copy2d(const Copy2D* tasks, int32_t count, hipStream_t s);
 void launch_err_block(const GenDev& g, const double* Hc, int64_t ldh, int64_t j0, int32_t nb,
                       double* accum, hipStream_t s);
 
+// ---- learned predictor network (k_mlp.hip) ----
+struct MlpShape {
+  int32_t nl;
+  int32_t sz[HSS_MLP_MAX_LAYERS + 1];
+  int32_t ald[HSS_MLP_MAX_LAYERS + 1];   // LDS leading dimension of each activation tile
+  int32_t aoff[HSS_MLP_MAX_LAYERS + 1];  // LDS offset (floats) of each activation tile
+  int64_t woff[HSS_MLP_MAX_LAYERS];
+  int64_t boff[HSS_MLP_MAX_LAYERS];
+  int64_t np;
+  int32_t lds_floats;
+};
+struct MlpAdam {
+  float lr, b1, b2, eps, bc1, bc2;  // bc = 1 - beta^step
+};
+MlpShape mlp_shape(const hss_mlp& net);
+int64_t mlp_tiles(int64_t rows);
+void launch_mlp_tile(const MlpShape& S, const float* P, const float* X, const float* T, const float* M,
+                     int64_t pos0, int64_t pos1, int64_t pa, int64_t pc, int64_t nd, float* Y, float* part,
+                     float* cl, int mode, hipStream_t s);
+void launch_mlp_reduce(int64_t np, int32_t nblk, const float* part, const float* cl, float* grad, float* loss,
+                       float* params, float* am, float* av, const MlpAdam& a, int adam, hipStream_t s);
+void launch_mlp_adam(int64_t np, float* params, const float* grad, float* am, float* av, const MlpAdam& a,
+                     hipStream_t s);
+
 }  // namespace hss
 
 #define HSS_HIP_CHECK(expr)                                                        \

@@ -78,7 +78,14 @@ _lib = None
 EXPORTS = ["hss_tree_build", "hss_tree_free", "hss_compress", "hss_compress_batched", "hss_destroy",
            "hss_matvec", "hss_rel_error", "hss_get_info", "hss_get_node_info", "hss_copy_node",
            "hss_sample", "hss_extract", "hss_interpolative_batched", "hss_last_error", "hss_version",
-           "hss_get_kernel_stats"]
+           "hss_get_kernel_stats", "hss_mlp_num_params", "hss_mlp_forward", "hss_mlp_gradient",
+           "hss_mlp_adam", "hss_mlp_train"]
+
+MLP_MAX_LAYERS = 6
+
+
+class _Mlp(C.Structure):
+    _fields_ = [("n_layers", C.c_int32), ("sizes", C.c_int32 * (MLP_MAX_LAYERS + 1))]
 
 
 def lib():
@@ -110,6 +117,13 @@ def lib():
     L.hss_sample.argtypes = [C.POINTER(_Gen), vp, i32, vp, i64, vp, i64, i32, i32, vp]
     L.hss_extract.argtypes = [C.POINTER(_Gen), vp, i32, vp, i32, vp, vp, i64, vp]
     L.hss_interpolative_batched.argtypes = [i32, vp, vp, vp, vp, vp, dbl, dbl, vp, vp, vp, vp, vp]
+    flt, mp = C.c_float, C.POINTER(_Mlp)
+    L.hss_mlp_num_params.argtypes = [mp, C.POINTER(i64)]
+    L.hss_mlp_forward.argtypes = [mp, vp, vp, i64, vp, vp]
+    L.hss_mlp_gradient.argtypes = [mp, vp, vp, vp, vp, i64, vp, vp, vp]
+    L.hss_mlp_adam.argtypes = [i64, vp, vp, vp, vp, flt, flt, flt, flt, i64, vp]
+    L.hss_mlp_train.argtypes = [mp, vp, vp, vp, C.POINTER(i64), vp, vp, vp, i64, i32, i32, flt, C.c_uint64,
+                                vp, vp]
     for name in EXPORTS:
         if name not in ("hss_tree_free", "hss_destroy", "hss_last_error", "hss_version"):
             getattr(L, name).restype = C.c_int32
@@ -335,14 +349,20 @@ def compress(gen: Generator, tree: Tree, R, rtol=1e-6, atol=1e-12, eta=1.0, stra
 
 
 def compress_batched(gens, trees, Rs, **kw):
-    """Independent compressions in one job (hss_compress_batched)."""
+    """Independent compressions in one job (hss_compress_batched).  Keyword
+    options are those of compress(); a list or tuple gives one value per problem."""
     k = len(gens)
+
+    def opt(name, i, default):
+        v = kw.get(name, default)
+        return v[i] if isinstance(v, (list, tuple)) else v
+
     G = (_Gen * k)(*[g._c() for g in gens])
     T = (C.POINTER(_Tree) * k)(*[t._t for t in trees])
-    O = (_Opt * k)(*[_opts(R, kw.get("rtol", 1e-6), kw.get("atol", 1e-12), kw.get("eta", 1.0),
-                           kw.get("strategy", "dbl_fnorm"), kw.get("d0", 64), kw.get("delta_d", 64),
-                           kw.get("p", 10), kw.get("d_max"), kw.get("precision", "fp64"))
-                     for R in Rs])
+    O = (_Opt * k)(*[_opts(R, opt("rtol", i, 1e-6), opt("atol", i, 1e-12), opt("eta", i, 1.0),
+                           opt("strategy", i, "dbl_fnorm"), opt("d0", i, 64), opt("delta_d", i, 64),
+                           opt("p", i, 10), opt("d_max", i, None), opt("precision", i, "fp64"))
+                     for i, R in enumerate(Rs)])
     H = (C.c_void_p * k)()
     st = _check(lib().hss_compress_batched(k, G, T, O, H))
     return [HSSMatrix(H[i], (gens[i], trees[i], Rs[i])) for i in range(k)], st
@@ -408,3 +428,73 @@ def interpolative_batched(mats, eps_r, eps_a=0.0):
         Ei = Ev[e_off[i]:e_off[i] + m[i] * m[i]].reshape((m[i], m[i]), order="F")[:r, :m[i] - r]
         out.append((r, pv[p_off[i]:p_off[i] + m[i]].copy(), Ei.copy()))
     return out
+
+
+# --------------------------------------------------------------------------- predictor network
+def _mlp(sizes):
+    if not 2 <= len(sizes) <= MLP_MAX_LAYERS + 1:
+        raise ValueError("between 1 and %d layers" % MLP_MAX_LAYERS)
+    net = _Mlp()
+    net.n_layers = len(sizes) - 1
+    for i, w in enumerate(sizes):
+        net.sizes[i] = int(w)
+    return net
+
+
+def _f32(t, name, shape=None):
+    import torch
+    if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
+        raise TypeError("%s must be a contiguous float32 CUDA tensor" % name)
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError("%s must have shape %s, not %s" % (name, tuple(shape), tuple(t.shape)))
+    return _ptr(t)
+
+
+def mlp_num_params(sizes) -> int:
+    """Parameter count of the ReLU network `sizes` (hss_mlp_num_params)."""
+    out = C.c_int64()
+    _check(lib().hss_mlp_num_params(C.byref(_mlp(sizes)), C.byref(out)))
+    return out.value
+
+
+def mlp_forward(sizes, params, X):
+    """Y = net(X) (hss_mlp_forward); X (n, sizes[0]) float32 CUDA, row-major."""
+    import torch
+    n = X.shape[0]
+    Y = torch.empty((n, sizes[-1]), dtype=torch.float32, device=X.device)
+    _check(lib().hss_mlp_forward(C.byref(_mlp(sizes)), _f32(params, "params", (mlp_num_params(sizes),)),
+                                 _f32(X, "X", (n, sizes[0])), n, _ptr(Y), _stream()))
+    return Y
+
+
+def mlp_gradient(sizes, params, X, T, M):
+    """(gradient, loss) of the masked squared error (hss_mlp_gradient)."""
+    import torch
+    n = X.shape[0]
+    npar = mlp_num_params(sizes)
+    g = torch.empty(npar, dtype=torch.float32, device=params.device)
+    loss = torch.empty(1, dtype=torch.float32, device=params.device)
+    _check(lib().hss_mlp_gradient(C.byref(_mlp(sizes)), _f32(params, "params", (npar,)),
+                                  _f32(X, "X", (n, sizes[0])), _f32(T, "T", (n, sizes[-1])),
+                                  _f32(M, "M", (n, sizes[-1])), n, _ptr(g), _ptr(loss), _stream()))
+    return g, loss
+
+
+def mlp_adam(params, grad, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam step in place (hss_mlp_adam)."""
+    np_ = params.numel()
+    _check(lib().hss_mlp_adam(np_, _f32(params, "params"), _f32(grad, "grad", (np_,)), _f32(m, "m", (np_,)),
+                              _f32(v, "v", (np_,)), lr, beta1, beta2, eps, step, _stream()))
+
+
+def mlp_train(sizes, params, m, v, step, X, T, M, batch, epochs, lr, seed=0):
+    """Mini-batch Adam on the device (hss_mlp_train).  Returns (loss per epoch, new step)."""
+    n = X.shape[0]
+    npar = mlp_num_params(sizes)
+    st = C.c_int64(step)
+    losses = np.zeros(max(1, epochs), dtype=np.float32)
+    _check(lib().hss_mlp_train(C.byref(_mlp(sizes)), _f32(params, "params", (npar,)), _f32(m, "m", (npar,)),
+                               _f32(v, "v", (npar,)), C.byref(st), _f32(X, "X", (n, sizes[0])),
+                               _f32(T, "T", (n, sizes[-1])), _f32(M, "M", (n, sizes[-1])), n, batch, epochs,
+                               lr, seed, losses.ctypes.data, _stream()))
+    return losses[:epochs], st.value

@@ -69,3 +69,53 @@ def batch_problems(count: int, seed: int, n_lo: int = 2048, n_hi: int = 16384):
         else:
             out.append({"family": "laplace", "n": n, "points_seed": 1000 + i})
     return out
+
+
+def mlp_params(sizes, seed: int) -> np.ndarray:
+    """Initial parameters of a fully connected network with layer widths
+    `sizes`, flat float32 in the library's order [W_1, b_1, W_2, b_2, ...]
+    with W_l of shape (sizes[l+1], sizes[l]) row-major: weights uniform in
+    +-sqrt(6 / fan_in) (He et al., 2015), biases zero."""
+    rng = _rng(seed)
+    parts = []
+    for fan_in, fan_out in zip(sizes[:-1], sizes[1:]):
+        lim = math.sqrt(6.0 / fan_in)
+        parts.append(rng.uniform(-lim, lim, fan_out * fan_in))
+        parts.append(np.zeros(fan_out))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def mlp_samples(n: int, n_in: int, n_out: int, seed: int, keep: float = 0.8):
+    """Random (X, T, M) for a network: X, T standard normal, M a 0/1 mask
+    keeping each target with probability `keep`; float32, row-major."""
+    rng = _rng(seed)
+    X = rng.standard_normal((n, n_in)).astype(np.float32)
+    T = rng.standard_normal((n, n_out)).astype(np.float32)
+    M = (rng.random((n, n_out)) < keep).astype(np.float32)
+    return X, T, M
+
+
+def learned_problems(count: int, seed: int, n_lo: int = 1024, n_hi: int = 32768):
+    """Parameters of randomly parameterised problems for the d0 predictor's
+    training set: family uniform over Toeplitz (h ~ U[0.05, 0.5], index
+    bisection, leaf 64 or 128), sphere Laplace (RCB, leaf 128) and cube
+    Gaussian (sigma ~ U[0.2, 1], diag 1e-2, kd tree, leaf 256); n
+    log-uniform in [n_lo, n_hi]; relative tolerance log-uniform in
+    [1e-8, 1e-4].  Each dict has family, n, leaf, rtol and h / sigma /
+    points_seed as the family needs."""
+    rng = _rng(seed)
+    out = []
+    for i in range(count):
+        fam = ("toeplitz", "laplace", "gauss")[int(rng.integers(0, 3))]
+        n = int(math.floor(n_lo * (n_hi / n_lo) ** rng.random()))
+        n = max(n_lo, min(n_hi, n))
+        rtol = float(10.0 ** rng.uniform(-8.0, -4.0))
+        p = {"family": fam, "n": n, "rtol": rtol}
+        if fam == "toeplitz":
+            p.update(h=float(rng.uniform(0.05, 0.5)), leaf=int(rng.choice([64, 128])))
+        elif fam == "laplace":
+            p.update(leaf=128, points_seed=seed * 100000 + i)
+        else:
+            p.update(sigma=float(rng.uniform(0.2, 1.0)), leaf=256, points_seed=seed * 100000 + i)
+        out.append(p)
+    return out
