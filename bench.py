@@ -10,6 +10,13 @@ Gaussian random matrix (seed 0, n x 4096) and the points are resident in
 HBM before the timed region.  One step = one full hss_compress call
 (sampling, extraction, local samples, stopping tests, IDs, reductions).
 
+Other workloads (--workload): sphere Laplace n = 8192; Toeplitz n = 1024
+(doubling strategy, d0 = 64); Gaussian kernel n = 65536 in the unit cube
+(kd tree, leaf 256), with --precision fp32 / bf16x3 sampling and --rtol;
+learned-* workloads time the learned d0 (predictor network) and, beside
+it, the adaptive start d0 = 128 on Toeplitz n = 131072 and sphere Laplace
+n = 65536.
+
 Prints one JSON line.  `roofline` covers the kernel class with the largest
 measured GPU time (HIP events around every launch of one extra profiled
 compression); `cpu_baseline` times the CPU oracle on a bounded sample of
@@ -24,11 +31,15 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "HSS compressions/s + sampling TFLOP/s at rel err≤1e-6; learned/mixed vs FP64"
 PEAK_FP64_TFLOPS = 78.6
+PEAK_FP32_TFLOPS = 157.3
+PEAK_BF16_TFLOPS = 2500.0
 PEAK_HBM_GBS = 8000.0
 
 # kernel class -> (HIP kernel name, bound)
@@ -52,10 +63,24 @@ WORKLOADS = {
                                 strategy="inc_fnorm", d0=128, delta_d=64, d_max=2048),
     "toeplitz-1024": dict(family="toeplitz", n=1024, leaf=64, method="bisect", h=0.1,
                           strategy="dbl_fnorm", d0=64, delta_d=64, d_max=1024),
+    # Gaussian kernel exp(-|x-y|^2 / 0.5) + 1e-2 I on uniform points in the unit cube
+    "gauss-cube-65536": dict(family="gauss", n=65536, leaf=256, method="kd", points_seed=2, sigma=0.5,
+                             strategy="inc_fnorm", d0=128, delta_d=64, d_max=2048),
+    # 256 independent matrices (128 Toeplitz h ~ U[0.05, 0.5], 128 sphere Laplace), n log-uniform in
+    # [2048, 16384], leaf 128, compressed together by hss_compress_batched
+    "batch-256": dict(batch=256, seed=3, n_lo=2048, n_hi=16384, leaf=128, family="toeplitz+laplace",
+                      method="bisect/rcb", strategy="dbl_fnorm", d0=64, delta_d=64, d_max=2048),
+    # learned d0 against the adaptive start d0 = 128 (both incrementing, delta_d = 64)
+    "learned-toeplitz-131072": dict(family="toeplitz", n=131072, leaf=128, method="bisect", h=0.1,
+                                    strategy="inc_fnorm", d0=128, delta_d=64, d_max=2048, learned=True,
+                                    r_seed=4),
+    "learned-laplace-sphere-65536": dict(family="laplace", n=65536, leaf=128, method="rcb", points_seed=4,
+                                         strategy="inc_fnorm", d0=128, delta_d=64, d_max=6144, learned=True,
+                                         r_seed=4),
 }
 
 
-def roofline(stats):
+def roofline(stats, precision="fp64"):
     name = max((k for k in stats if stats[k]["ms"] > 0), key=lambda k: stats[k]["ms"])
     s = stats[name]
     kern, bound = KCLASS_INFO[name]
@@ -63,6 +88,10 @@ def roofline(stats):
     if bound == "mfma":
         ach = s["flops"] / sec / 1e12
         peak, unit = PEAK_FP64_TFLOPS, "TFLOP/s"
+        if name == "SAMPLE" and precision != "fp64":
+            # FP32 MFMA, or bf16 MFMA (three bf16 products per algorithmic flop)
+            kern = "k_sample_lp"
+            peak = PEAK_FP32_TFLOPS if precision == "fp32" else PEAK_BF16_TFLOPS
     else:
         ach = s["bytes"] / sec / 1e9
         peak, unit = PEAK_HBM_GBS, "GB/s"
@@ -80,7 +109,7 @@ def cpu_baseline(W, d_final, budget_rows=16384):
     import numpy as np
     from threadpoolctl import threadpool_info
 
-    from oracle.operators import Laplace, PermutedOperator, Toeplitz
+    from oracle.operators import Gauss, Laplace, PermutedOperator, Toeplitz
     from oracle.tree import build_tree
     from paper_1810_04125_amd import inputs
 
@@ -89,6 +118,10 @@ def cpu_baseline(W, d_final, budget_rows=16384):
         pts = inputs.sphere_points(n, W["points_seed"])
         ot = build_tree(n, W["leaf"], pts, W["method"])
         op = PermutedOperator(Laplace(pts), ot.perm, block=512)
+    elif W["family"] == "gauss":
+        pts = inputs.cube_points(n, W["points_seed"])
+        ot = build_tree(n, W["leaf"], pts, W["method"])
+        op = PermutedOperator(Gauss(pts, W["sigma"], 1e-2), ot.perm, block=512)
     else:
         ot = build_tree(n, W["leaf"])
         op = PermutedOperator(Toeplitz(n, W["h"]), ot.perm, block=512)
@@ -109,12 +142,139 @@ def cpu_baseline(W, d_final, budget_rows=16384):
                        (rows, n, el, n, rows, d_final // 64))}
 
 
+def setup(W):
+    """(generator, tree, R) of a workload on the device."""
+    import numpy as np
+    import torch
+
+    from paper_1810_04125_amd import hss, inputs
+
+    n = W["n"]
+    if W["family"] == "laplace":
+        pts = inputs.sphere_points(n, W["points_seed"])
+        T = hss.Tree(n, W["leaf"], pts, W["method"])
+        gen = hss.laplace(torch.from_numpy(pts).cuda())
+    elif W["family"] == "gauss":
+        pts = inputs.cube_points(n, W["points_seed"])
+        T = hss.Tree(n, W["leaf"], pts, W["method"])
+        gen = hss.gauss(torch.from_numpy(pts).cuda(), W["sigma"], 1e-2)
+    else:
+        T = hss.Tree(n, W["leaf"])
+        gen = hss.toeplitz(n, W["h"])
+    Rh = inputs.gaussian_matrix(n, W["d_max"], W.get("r_seed", 0))
+    R = hss.colmajor(torch.from_numpy(np.ascontiguousarray(Rh.T)).cuda().t())
+    return gen, T, R
+
+
+def probe_error(gen, T, H, n):
+    """(error, kind): exact ||A - H||_F / ||A||_F for n <= 8192, else the
+    64-probe estimate ||(A - H) W||_F / ||A W||_F."""
+    import numpy as np
+    import torch
+
+    from paper_1810_04125_amd import hss, inputs
+
+    if n <= 8192:
+        return H.rel_error(), "exact"
+    Om = hss.colmajor(torch.from_numpy(np.ascontiguousarray(inputs.gaussian_matrix(n, 64, 7).T)).cuda().t())
+    perm = torch.from_numpy(T.perm).cuda()
+    inv = torch.empty_like(perm)
+    inv[perm] = torch.arange(n, device=perm.device)
+    AO = hss.sample(gen, perm, hss.colmajor(Om[perm]))[inv]      # A_hat (P Om), back to original order
+    HO = H.matvec(Om)
+    return float(torch.linalg.norm(AO - HO) / torch.linalg.norm(AO)), "64-probe estimate"
+
+
+def timed(fn, steps, warmup, log, tag):
+    import torch
+    for i in range(warmup):
+        fn()
+        log("bench: %s warmup %d done" % (tag, i))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = fn()
+    torch.cuda.synchronize()
+    return out, time.perf_counter() - t0
+
+
+def main_batch(args, W, log):
+    """Throughput of hss_compress_batched over the 256-matrix batch."""
+    import torch
+
+    from paper_1810_04125_amd import hss, inputs
+
+    specs = inputs.batch_problems(W["batch"], W["seed"], W["n_lo"], W["n_hi"])
+    gens, trees = [], []
+    for sp in specs:
+        if sp["family"] == "toeplitz":
+            gens.append(hss.toeplitz(sp["n"], sp["h"]))
+            trees.append(hss.Tree(sp["n"], W["leaf"]))
+        else:
+            pts = inputs.sphere_points(sp["n"], sp["points_seed"])
+            gens.append(hss.laplace(torch.from_numpy(pts).cuda()))
+            trees.append(hss.Tree(sp["n"], W["leaf"], pts, "rcb"))
+    Rh = inputs.gaussian_matrix(W["n_hi"], W["d_max"], 0)
+    R = hss.colmajor(torch.from_numpy(np.ascontiguousarray(Rh.T)).cuda().t())
+    del Rh
+    Rs = [R[:sp["n"]] for sp in specs]
+    kw = dict(rtol=args.rtol, atol=1e-12, eta=0.1, strategy=W["strategy"], d0=W["d0"], delta_d=W["delta_d"],
+              d_max=[min(W["d_max"], sp["n"]) for sp in specs], precision=args.precision)
+    log("bench: batch of %d, sum n^2 = %.3e" % (len(specs), sum(sp["n"] ** 2 for sp in specs)))
+
+    def step():
+        return hss.compress_batched(gens, trees, Rs, **kw)
+
+    (Hs, st), el = timed(step, args.steps, args.warmup, log, "batch")
+    infos = [H.info() for H in Hs]
+    pick = list(range(0, len(Hs), max(1, len(Hs) // 8)))
+    errs = [Hs[i].rel_error() for i in pick]
+    log("bench: %d steps in %.3f s; errors %s" % (args.steps, el, ["%.2e" % e for e in errs]))
+    rl = None
+    if not args.no_profile:
+        del Hs
+        Hp, _ = hss.compress_batched(gens, trees, Rs, profile=True, **kw)
+        stats = Hp[0].kernel_stats()
+        rl = roofline(stats, args.precision)
+        rl["profiled_gpu_ms_by_class"] = {k: round(v["ms"], 2) for k, v in stats.items()}
+        rl["note"] = "kernel statistics of the first memory group of the batch"
+        del Hp
+    cpu = None
+    if not args.no_cpu:
+        # oracle sampling rate on one Laplace problem of the batch, scaled to every problem's 2 n^2 d_final
+        Wl = dict(family="laplace", n=8192, leaf=W["leaf"], method="rcb", points_seed=1)
+        one = cpu_baseline(Wl, 64, budget_rows=8192)
+        sec_per_flop = (1.0 / one["value"]) / (2.0 * 8192 * 8192 * 64)
+        total = sum(2.0 * sp["n"] ** 2 * inf["d_final"] for sp, inf in zip(specs, infos)) * sec_per_flop
+        cpu = {"value": len(specs) / total, "unit": "compressions/s", "cores": one["cores"], "kind": "oracle",
+               "sample": "oracle dense-block Laplace sampling rate (one 64-column increment, n = 8192), "
+                         "scaled to sum over the batch of 2 n^2 d_final; sampling only, an upper bound"}
+    value = args.steps * len(specs) / el
+    out = {
+        "metric": METRIC, "value": round(value, 4), "unit": "compressions/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * el / args.steps, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f64 (sampling %s)" % args.precision,
+        "data": "synthetic",
+        "config": {"workload": args.workload, "matrices": len(specs), "n_range": [W["n_lo"], W["n_hi"]],
+                   "leaf": W["leaf"], "strategy": W["strategy"], "d0": W["d0"], "rtol": args.rtol,
+                   "atol": 1e-12, "eta": 0.1, "d_max": W["d_max"], "sampling": args.precision},
+        "rel_err_max_of_8": max(errs), "rel_err_ok": bool(max(errs) <= args.rtol), "status": st,
+        "rounds_max": max(i["rounds"] for i in infos), "d_final_max": max(i["d_final"] for i in infos),
+        "roofline": rl, "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=8)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="laplace-sphere-32768", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x3"],
+                    help="arithmetic of the sampling product (everything else is FP64)")
+    ap.add_argument("--rtol", type=float, default=1e-6)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     args = ap.parse_args()
@@ -123,70 +283,81 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
-    from paper_1810_04125_amd import hss, inputs
+    from paper_1810_04125_amd import hss
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     W = WORKLOADS[args.workload]
-    n = W["n"]
     log = lambda m: print(m, file=sys.stderr, flush=True)
-    log("bench: workload %s" % args.workload)
-    if W["family"] == "laplace":
-        pts = inputs.sphere_points(n, W["points_seed"])
-        T = hss.Tree(n, W["leaf"], pts, W["method"])
-        gen = hss.laplace(torch.from_numpy(pts).cuda())
-    else:
-        T = hss.Tree(n, W["leaf"])
-        gen = hss.toeplitz(n, W["h"])
-    Rh = inputs.gaussian_matrix(n, W["d_max"], 0)
-    R = hss.colmajor(torch.from_numpy(np.ascontiguousarray(Rh.T)).cuda().t())
-    del Rh
-    kw = dict(rtol=1e-6, atol=1e-12, eta=0.1, strategy=W["strategy"], d0=W["d0"], delta_d=W["delta_d"],
-              d_max=W["d_max"])
+    if W.get("batch"):
+        return main_batch(args, W, log)
+    n = W["n"]
+    log("bench: workload %s precision %s rtol %g" % (args.workload, args.precision, args.rtol))
+    gen, T, R = setup(W)
+    kw = dict(rtol=args.rtol, atol=1e-12, eta=0.1, strategy=W["strategy"], d0=W["d0"], delta_d=W["delta_d"],
+              d_max=W["d_max"], precision=args.precision)
+    learned = None
+    if W.get("learned"):
+        from paper_1810_04125_amd.learned import D0Predictor
+        pred = D0Predictor()
+        param = W.get("h", W.get("sigma"))
 
-    for i in range(args.warmup):
-        H, st = hss.compress(gen, T, R, **kw)
-        log("bench: warmup %d done" % i)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        H, st = hss.compress(gen, T, R, **kw)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
+        def learned_step():
+            d0 = pred.d0(W["family"], param, n, T, args.rtol, W["delta_d"], W["d_max"])
+            return hss.compress(gen, T, R, **dict(kw, d0=d0))
+
+        (H, st), el = timed(learned_step, args.steps, args.warmup, log, "learned")
+        (Hb, stb), elb = timed(lambda: hss.compress(gen, T, R, **kw), args.steps, args.warmup, log, "baseline")
+        p = pred.predict(W["family"], param, n, T, args.rtol)
+        d0L = pred.d0(W["family"], param, n, T, args.rtol, W["delta_d"], W["d_max"])
+        ib = Hb.info()
+        # largest node rank per level of the baseline compression vs the prediction
+        act = np.zeros(int(T.level.max()) + 1)
+        for node in range(T.num_nodes):
+            ni = Hb.node_info(node)
+            act[T.level[node]] = max(act[T.level[node]], ni["rank_r"], ni["rank_c"])
+        lr_pred = np.array(p["level_rank"])
+        eb, _ = probe_error(gen, T, Hb, n)
+        learned = {"d0_predicted": d0L, "d_final_predicted": round(p["d_final"], 1),
+                   "baseline": {"d0": W["d0"], "compressions_per_s": round(args.steps / elb, 4),
+                                "ms_per_step": round(1e3 * elb / args.steps, 3), "rounds": ib["rounds"],
+                                "d_final": ib["d_final"], "hss_rank": ib["hss_rank"], "rel_err": eb,
+                                "status": stb},
+                   "speedup": round(elb / el, 3),
+                   "rounds_saved": ib["rounds"] - H.info()["rounds"],
+                   "level_rank_predicted": [round(x, 1) for x in lr_pred],
+                   "level_rank_actual": [int(x) for x in act[1:]],
+                   "rank_pred_mae_log2": round(float(np.mean(np.abs(np.log2(1 + lr_pred) -
+                                                                   np.log2(1 + act[1:])))), 4),
+                   "d_final_pred_rel_err": round(p["d_final"] / ib["d_final"] - 1.0, 4)}
+        del Hb
+    else:
+        (H, st), el = timed(lambda: hss.compress(gen, T, R, **kw), args.steps, args.warmup, log, "fp64"
+                            if args.precision == "fp64" else args.precision)
     info = H.info()
     log("bench: timed %d steps in %.3f s; info %s" % (args.steps, el, info))
-
-    # accuracy: Gaussian-probe estimate ||(A - H) W||_F / ||A W||_F (64 probes),
-    # exact ||A - H||_F / ||A||_F for n <= 8192
-    Om = hss.colmajor(torch.from_numpy(np.ascontiguousarray(inputs.gaussian_matrix(n, 64, 7).T)).cuda().t())
-    perm = torch.from_numpy(T.perm).cuda()
-    inv = torch.empty_like(perm)
-    inv[perm] = torch.arange(n, device=perm.device)
-    AO_perm = hss.sample(gen, perm, hss.colmajor(Om[perm]))       # A_hat (P Om)
-    AO = AO_perm[inv]                                            # back to original order
-    HO = H.matvec(Om)
-    est = float(torch.linalg.norm(AO - HO) / torch.linalg.norm(AO))
-    exact = H.rel_error() if n <= 8192 else None
-    err = exact if exact is not None else est
-    log("bench: rel err estimate %.3e exact %s" % (est, exact))
+    err, kind = probe_error(gen, T, H, n)
+    log("bench: rel err %.3e (%s)" % (err, kind))
 
     rl = None
     if not args.no_profile:
-        Hp, _ = hss.compress(gen, T, R, profile=True, **kw)
+        Hp, _ = hss.compress(gen, T, R, profile=True, **dict(kw, d0=(learned or {}).get("d0_predicted", W["d0"])))
         stats = Hp.kernel_stats()
-        rl = roofline(stats)
+        rl = roofline(stats, args.precision)
         samp = stats["SAMPLE"]
-        rl["sampling_kernel"] = {"kernel": "k_sample_f64", "launches": samp["launches"],
+        skern = "k_sample_f64" if args.precision == "fp64" else "k_sample_lp"
+        speak = {"fp64": PEAK_FP64_TFLOPS, "fp32": PEAK_FP32_TFLOPS, "bf16x3": PEAK_BF16_TFLOPS}[args.precision]
+        rl["sampling_kernel"] = {"kernel": skern, "launches": samp["launches"],
                                  "achieved_tflops": round(samp["flops"] / (samp["ms"] / 1e3) / 1e12, 3),
-                                 "frac_of_fp64_peak": round(samp["flops"] / (samp["ms"] / 1e3) / 1e12 /
-                                                            PEAK_FP64_TFLOPS, 4),
+                                 "frac_of_peak": round(samp["flops"] / (samp["ms"] / 1e3) / 1e12 / speak, 4),
+                                 "peak_tflops": speak,
                                  "avg_launch_us": round(1e3 * samp["ms"] / max(1, samp["launches"]), 3)}
         rl["profiled_gpu_ms_by_class"] = {k: round(v["ms"], 2) for k, v in stats.items()}
         log("bench: profile %s" % json.dumps(rl))
+        del Hp
 
     cpu = None
     if not args.no_cpu:
@@ -194,19 +365,19 @@ def main():
         log("bench: cpu baseline %s" % cpu)
 
     value = args.steps / el
+    cfg = {"workload": args.workload, "n": n, "leaf": W["leaf"], "tree": W["method"],
+           "strategy": W["strategy"], "d0": "learned" if learned else W["d0"], "delta_d": W["delta_d"],
+           "rtol": args.rtol, "atol": 1e-12, "eta": 0.1, "d_max": W["d_max"], "sampling": args.precision}
     out = {
         "metric": METRIC, "value": round(value, 4), "unit": "compressions/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * el / args.steps, 3),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": args.workload, "n": n, "leaf": W["leaf"], "tree": W["method"],
-                   "strategy": W["strategy"], "d0": W["d0"], "delta_d": W["delta_d"], "rtol": 1e-6,
-                   "atol": 1e-12, "eta": 0.1, "d_max": W["d_max"], "sampling": "fp64"},
-        "rel_err": err, "rel_err_kind": "exact" if exact is not None else "64-probe estimate",
-        "rel_err_ok": bool(err <= 1e-6),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f64 (sampling %s)" % args.precision,
+        "data": "synthetic", "config": cfg,
+        "rel_err": err, "rel_err_kind": kind, "rel_err_ok": bool(err <= args.rtol), "status": st,
         "sampling_tflops": round(info["sample_flops"] / (info["sample_ms"] / 1e3) / 1e12, 3),
         "rounds": info["rounds"], "d_final": info["d_final"], "hss_rank": info["hss_rank"],
-        "roofline": rl, "cpu_baseline": cpu,
+        "learned": learned, "roofline": rl, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
 

@@ -246,9 +246,11 @@ hss_status hss_compress_batched(int32_t count, const hss_generator* gens, const 
       job->compress();
       if (std::getenv("HSS_TRACE")) {
         const auto t2 = std::chrono::steady_clock::now();
-        std::fprintf(stderr, "[hss] group %d..%d: est %.1f GB, setup %.1f ms, compress %.1f ms, sample %.1f ms\n",
-                     g0, g1, acc / 1e9, std::chrono::duration<double, std::milli>(t1 - t0).count(),
-                     std::chrono::duration<double, std::milli>(t2 - t1).count(), job->sample_ms);
+        std::fprintf(stderr,
+                     "[hss] group %d..%d: est %.1f GB (free %.1f GB), setup %.1f ms (alloc %.1f ms), compress "
+                     "%.1f ms, sample %.1f ms\n",
+                     g0, g1, acc / 1e9, free_b / 1e9, std::chrono::duration<double, std::milli>(t1 - t0).count(),
+                     job->alloc_ms, std::chrono::duration<double, std::milli>(t2 - t1).count(), job->sample_ms);
       }
       for (int32_t k = g0; k < g1; ++k) {
         if (job->probs[k - g0].status > worst) worst = job->probs[k - g0].status;

@@ -85,8 +85,10 @@ void* Job::dalloc(size_t bytes, bool transient) {
   void* p = nullptr;
   if (bytes == 0) bytes = 8;
   keep_pool_memory();
+  const auto t0 = std::chrono::steady_clock::now();
   hipError_t e = hipMallocAsync(&p, bytes, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);   // usable from any stream from now on
+  alloc_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   if (e != hipSuccess) {
     hipGetLastError();
     throw Error(e == hipErrorOutOfMemory ? HSS_ERR_OUT_OF_MEMORY : HSS_ERR_DEVICE,

@@ -70,6 +70,7 @@ struct Job {
   GemmTask* mvtasks_d = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   double sample_ms = 0.0, sample_flops = 0.0, total_ms = 0.0;
+  double alloc_ms = 0.0;           // host time spent in device allocations (setup statistics)
   Prof prof;
   unsigned long long* kcnt_d = nullptr;     // device algorithmic counters
   hss_kernel_stats kstats[HSS_K_COUNT] = {};

@@ -361,7 +361,8 @@ def compress_batched(gens, trees, Rs, **kw):
     T = (C.POINTER(_Tree) * k)(*[t._t for t in trees])
     O = (_Opt * k)(*[_opts(R, opt("rtol", i, 1e-6), opt("atol", i, 1e-12), opt("eta", i, 1.0),
                            opt("strategy", i, "dbl_fnorm"), opt("d0", i, 64), opt("delta_d", i, 64),
-                           opt("p", i, 10), opt("d_max", i, None), opt("precision", i, "fp64"))
+                           opt("p", i, 10), opt("d_max", i, None), opt("precision", i, "fp64"),
+                           opt("profile", i, False))
                      for i, R in enumerate(Rs)])
     H = (C.c_void_p * k)()
     st = _check(lib().hss_compress_batched(k, G, T, O, H))
