@@ -284,6 +284,15 @@ hss_status hss_interpolative_batched(int32_t count, const int32_t* m, const int3
                                      const int64_t* piv_off, double* E, const int64_t* e_off,
                                      int32_t* rank_host);
 
+/* Free the device memory the library keeps between compressions on the
+ * current device.  The transient buffers of a compression (local samples,
+ * bases, level workspaces; sized from d_max) come from one block per
+ * device that is kept after the call and reused by the next compression
+ * that fits in it; hss_compress_batched counts it as free memory when it
+ * forms groups.  Call this to give that memory back (for example before
+ * allocating elsewhere).  Blocks held by a running compression stay. */
+hss_status hss_release_cache(void);
+
 /* --- learned rank / d0 predictor ----------------------------------------
  * Not part of the paper's method: the adaptive driver (Alg. 3) needs an
  * initial sample count d0 and, with the incrementing strategy (Alg. 5),

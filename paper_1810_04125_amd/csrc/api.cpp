@@ -230,6 +230,7 @@ hss_status hss_compress_batched(int32_t count, const hss_generator* gens, const 
     while (g0 < count) {
       size_t free_b = 0, total_b = 0;
       HSS_HIP_CHECK(hipMemGetInfo(&free_b, &total_b));
+      free_b += arena_idle_bytes();   // the cached transient block is reusable
       const size_t budget = std::min<size_t>((size_t)(0.6 * (double)free_b), (size_t)80 << 30);
       size_t acc = 0;
       int32_t g1 = g0;
@@ -543,15 +544,22 @@ hss_status hss_interpolative_batched(int32_t count, const int32_t* m, const int3
       mc[k] = q.mcap;
     }
     QrcpPlan plan = make_qrcp_plan(mc);
-    DevBuf ws(sizeof(int2) * plan.step.size()), wt(sizeof(int2) * plan.trsm.size());
+    DevBuf wc(sizeof(int2) * qrcp_work_entries(count)), wm(2 * sizeof(int32_t)),
+        wt(sizeof(int2) * plan.trsm.size());
     HSS_HIP_CHECK(hipMemcpy(dt.p, tasks.data(), sizeof(QrcpTask) * count, hipMemcpyHostToDevice));
-    HSS_HIP_CHECK(hipMemcpy(ws.p, plan.step.data(), sizeof(int2) * plan.step.size(), hipMemcpyHostToDevice));
     HSS_HIP_CHECK(hipMemcpy(wt.p, plan.trsm.data(), sizeof(int2) * plan.trsm.size(), hipMemcpyHostToDevice));
-    run_qrcp(dt.as<QrcpTask>(), count, ws.as<int2>(), (int32_t)plan.step.size(), wt.as<int2>(),
-             (int32_t)plan.trsm.size(), std::min(mmax, dmax), dmax, flag.as<int32_t>(), gt.as<GemmTask>(), mmax,
-             nullptr);
+    const QrcpWork wk{wc.as<int2>(), wm.as<int32_t>(), count};
+    run_qrcp(dt.as<QrcpTask>(), count, wk, wt.as<int2>(), (int32_t)plan.trsm.size(), std::min(mmax, dmax), dmax,
+             mmax, flag.as<int32_t>(), gt.as<GemmTask>(), mmax, nullptr);
     HSS_HIP_CHECK(hipStreamSynchronize(nullptr));
     HSS_HIP_CHECK(hipMemcpy(rank_host, drk.p, sizeof(int32_t) * count, hipMemcpyDeviceToHost));
+    return HSS_OK;
+  });
+}
+
+hss_status hss_release_cache(void) {
+  return guarded([&]() -> hss_status {
+    arena_release_idle();
     return HSS_OK;
   });
 }

@@ -55,6 +55,7 @@ int64_t align8(int64_t x) { return (x + 7) & ~int64_t(7); }
 
 Job::~Job() {
   if (stream) hipStreamSynchronize(stream);
+  arena_return();
   for (void* p : transients) hipFreeAsync(p, stream);
   for (void* p : allocs) hipFreeAsync(p, stream);
   hipStreamSynchronize(stream);
@@ -79,6 +80,86 @@ static void keep_pool_memory() {
   }
   hipGetLastError();
   done = true;
+}
+
+// The transient buffers of a compression (local samples, bases, level
+// workspaces: sized from d_max, often tens of GB) are carved from one
+// block per device that outlives the job: freeing and re-mapping that much
+// memory for every call costs seconds, reusing it costs nothing.  A job
+// takes the block if it is idle and large enough, replaces it by a larger
+// one if needed, and hands it back when the compression ends; a job that
+// finds it busy (another thread) allocates its own.  hss_release_cache
+// frees idle blocks.
+namespace {
+struct Arena {
+  void* p = nullptr;
+  size_t bytes = 0;
+  bool busy = false;
+};
+std::mutex g_arena_mu;
+std::map<int, Arena> g_arena;
+}  // namespace
+
+size_t arena_idle_bytes() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  std::lock_guard<std::mutex> lk(g_arena_mu);
+  auto it = g_arena.find(dev);
+  return (it == g_arena.end() || it->second.busy) ? 0 : it->second.bytes;
+}
+
+void arena_release_idle() {
+  int dev = 0;
+  HSS_HIP_CHECK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_arena_mu);
+  auto it = g_arena.find(dev);
+  if (it == g_arena.end() || it->second.busy || !it->second.p) return;
+  HSS_HIP_CHECK(hipDeviceSynchronize());
+  HSS_HIP_CHECK(hipFree(it->second.p));
+  g_arena.erase(it);
+}
+
+void* Job::arena_acquire(size_t bytes) {
+  keep_pool_memory();
+  int dev = 0;
+  HSS_HIP_CHECK(hipGetDevice(&dev));
+  const auto t0 = std::chrono::steady_clock::now();
+  void* p = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_arena_mu);
+    Arena& a = g_arena[dev];
+    if (!a.busy) {
+      if (a.bytes < bytes) {
+        if (a.p) {
+          HSS_HIP_CHECK(hipDeviceSynchronize());
+          hipFree(a.p);
+        }
+        a.p = nullptr;
+        a.bytes = 0;
+        hipError_t e = hipMalloc(&a.p, bytes);
+        if (e != hipSuccess) {
+          hipGetLastError();
+          a.p = nullptr;
+          throw Error(e == hipErrorOutOfMemory ? HSS_ERR_OUT_OF_MEMORY : HSS_ERR_DEVICE,
+                      "hipMalloc of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
+        }
+        a.bytes = bytes;
+      }
+      a.busy = true;
+      p = a.p;
+      arena_dev = dev;
+    }
+  }
+  if (!p) p = dalloc(bytes, true);   // block in use by another job
+  alloc_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return p;
+}
+
+void Job::arena_return() {
+  if (arena_dev < 0) return;
+  std::lock_guard<std::mutex> lk(g_arena_mu);
+  g_arena[arena_dev].busy = false;
+  arena_dev = -1;
 }
 
 void* Job::dalloc(size_t bytes, bool transient) {
@@ -161,6 +242,7 @@ void Job::compact_e() {
 // matvec needs stay on the device.
 void Job::release_transients() {
   HSS_HIP_CHECK(hipStreamSynchronize(stream));
+  arena_return();
   for (void* p : transients) hipFreeAsync(p, stream);
   HSS_HIP_CHECK(hipStreamSynchronize(stream));
   transients.clear();
@@ -359,28 +441,37 @@ void Job::setup(int32_t count, const hss_generator* gens, const hss_tree* const*
   size_t part = 0;
   for (auto& P : probs) part = std::max(part, sample_partial_elems(P.n, P.dcap));
   dpool = (double*)dalloc(sizeof(double) * std::max<int64_t>(dtot, 1));
-  tpool = (double*)dalloc(sizeof(double) * std::max<int64_t>(ttot, 1), true);
   ipool = (int32_t*)dalloc(sizeof(int32_t) * std::max<int64_t>(itot, 1));
   lpool = (int64_t*)dalloc(sizeof(int64_t) * std::max<int64_t>(ltot, 1));
-  wsa = (double*)dalloc(sizeof(double) * std::max<int64_t>(wsA, 1), true);
-  wsb = (double*)dalloc(sizeof(double) * std::max<int64_t>(wsB, 1), true);
-  partial = part ? (double*)dalloc(sizeof(double) * part, true) : nullptr;
+  {
+    // tpool | wsA | wsB | split-K partials, each 256-byte aligned
+    auto a256 = [](size_t b) { return (b + 255) & ~size_t(255); };
+    const size_t bt = a256(sizeof(double) * std::max<int64_t>(ttot, 1));
+    const size_t ba = a256(sizeof(double) * std::max<int64_t>(wsA, 1));
+    const size_t bb = a256(sizeof(double) * std::max<int64_t>(wsB, 1));
+    const size_t bp = a256(sizeof(double) * part);
+    char* base = (char*)arena_acquire(bt + ba + bb + bp);
+    tpool = (double*)base;
+    wsa = (double*)(base + bt);
+    wsb = (double*)(base + bt + ba);
+    partial = part ? (double*)(base + bt + ba + bb) : nullptr;
+  }
   desc_d = (NodeDesc*)dalloc(sizeof(NodeDesc) * gnodes);
   st_d = (NodeState*)dalloc(sizeof(NodeState) * gnodes);
   prob_d = (ProbDev*)dalloc(sizeof(ProbDev) * count);
   tasks_d = (GemmTask*)dalloc(sizeof(GemmTask) * 2 * std::max(maxcount, 1));
   qtasks_d = (QrcpTask*)dalloc(sizeof(QrcpTask) * std::max(maxcount, 1));
+  qwork.max_tasks = std::max(maxcount, 1);
+  qwork.chunks = (int2*)dalloc(sizeof(int2) * qrcp_work_entries(qwork.max_tasks));
+  qwork.meta = (int32_t*)dalloc(sizeof(int32_t) * 2);
   qform_d = (QformTask*)dalloc(sizeof(QformTask) * std::max(maxcount, 1));
   mvtasks_d = (GemmTask*)dalloc(sizeof(GemmTask) * 2 * std::max(maxcount, 1));
   for (auto& L : levels) {
     std::vector<int32_t> mc;
     for (int32_t g : L.nodes) mc.push_back(desc[g].mcap);
     QrcpPlan qp = make_qrcp_plan(mc);
-    L.nstep = (int32_t)qp.step.size();
     L.ntrsm = (int32_t)qp.trsm.size();
-    L.wg_step = (int2*)dalloc(sizeof(int2) * std::max<size_t>(qp.step.size(), 1));
     L.wg_trsm = (int2*)dalloc(sizeof(int2) * std::max<size_t>(qp.trsm.size(), 1));
-    HSS_HIP_CHECK(hipMemcpy(L.wg_step, qp.step.data(), sizeof(int2) * qp.step.size(), hipMemcpyHostToDevice));
     HSS_HIP_CHECK(hipMemcpy(L.wg_trsm, qp.trsm.data(), sizeof(int2) * qp.trsm.size(), hipMemcpyHostToDevice));
   }
   flags_d = (int32_t*)dalloc(sizeof(int32_t) * 4);
@@ -530,8 +621,8 @@ void Job::run_level(int lev, int32_t ncap) {
   auto id_phase = [&](int hmt) {
     for (int s = 0; s < nsides; ++s) {
       launch_build_qrcp(a, s, hmt, qtasks_d, stream);
-      run_qrcp(qtasks_d, a.count, L.wg_step, L.nstep, L.wg_trsm, L.ntrsm, std::min(L.mcap, ncap), ncap,
-               flags_d + 2, tasks_d, L.mcap, stream, kcnt_d);
+      run_qrcp(qtasks_d, a.count, qwork, L.wg_trsm, L.ntrsm, std::min(L.mcap, ncap), ncap, L.mcap, flags_d + 2,
+               tasks_d, L.mcap, stream, kcnt_d);
     }
   };
   if (strategy == HSS_DBL_HMT) {
@@ -553,7 +644,7 @@ void Job::run_level(int lev, int32_t ncap) {
         L.ntest = (int32_t)qp.step.size();
         L.test_ncap = nb;
       }
-      TestScratch ts{qtasks_d, qform_d, L.wg_test, L.ntest, kTestCpw, flags_d + 3, tasks_d};
+      TestScratch ts{qtasks_d, qform_d, L.wg_test, L.ntest, kTestCpw, flags_d + 3, tasks_d, qwork};
       for (int it = 0; it < nblk; ++it)
         for (int s = 0; s < nsides; ++s)
           launch_fnorm_test(a, s, it, L.mcap, std::max(L.qcap, 1), nb, ts, stream);

@@ -32,12 +32,14 @@ struct LevelInfo {
   std::vector<int32_t> nodes;
   int32_t off = 0;
   int32_t mcap = 0, rcap = 0, qcap = 0, dcap = 0;
-  int2* wg_step = nullptr;   // QRCP workgroup maps (device)
-  int2* wg_trsm = nullptr;
-  int32_t nstep = 0, ntrsm = 0;
-  int2* wg_test = nullptr;   // stopping-test QR workgroup map for test_ncap columns
+  int2* wg_trsm = nullptr;   // back-substitution workgroup map (device)
+  int32_t ntrsm = 0;
+  int2* wg_test = nullptr;   // explicit-Q workgroup map for test_ncap columns
   int32_t ntest = 0, test_ncap = 0;
 };
+
+size_t arena_idle_bytes();   // idle cached transient memory on the current device
+void arena_release_idle();   // free it
 
 struct Job {
   std::vector<Problem> probs;
@@ -62,6 +64,7 @@ struct Job {
   int32_t* flags_d = nullptr;
   int32_t* nodes_d = nullptr;
   QrcpTask* qtasks_d = nullptr;
+  QrcpWork qwork{nullptr, nullptr, 0};   // device work map of every factorization call
   QformTask* qform_d = nullptr;
   int64_t* mvoff_d = nullptr;   // per node: prefix sum of rcap (matvec slots)
   int64_t mvtot = 0;
@@ -78,6 +81,9 @@ struct Job {
 
   ~Job();
   void* dalloc(size_t bytes, bool transient = false);
+  void* arena_acquire(size_t bytes);   // transient block (see driver.cpp)
+  void arena_return();
+  int arena_dev = -1;                  // device whose cached block this job holds
   void release_transients();
   void compact_e();
   void setup(int32_t count, const hss_generator* gens, const hss_tree* const* trees,

@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -162,10 +163,25 @@ struct QrcpPlan {
   std::vector<int2> trsm;   // (task, first column of E) per workgroup of the solve
 };
 QrcpPlan make_qrcp_plan(const std::vector<int32_t>& mcaps, int cpw = QCPW);
-void run_qrcp(const QrcpTask* tasks, int32_t ntasks, const int2* wg_step, int32_t nstep,
-              const int2* wg_trsm, int32_t ntrsm, int32_t kmax, int32_t dmax, int32_t* flag,
-              GemmTask* gtasks, int32_t mcap_max, hipStream_t s, unsigned long long* kcnt = nullptr,
-              int32_t cpw = QCPW, bool solve_e = true);
+// Busy workgroups aimed at by every pivot-step launch (4 per compute unit).
+constexpr int kQrcpTarget = 1024;
+// Panels of at most this many cells (rows x columns, by capacity) are
+// factored by one workgroup each in a single launch.
+constexpr int64_t kQrcpWgCells = 64 * 1024;
+// Device work map of run_qrcp: chunks holds kQrcpTarget + max_tasks
+// entries, meta two int32.
+struct QrcpWork {
+  int2* chunks;
+  int32_t* meta;
+  int32_t max_tasks;
+};
+inline size_t qrcp_work_entries(int32_t max_tasks) { return (size_t)kQrcpTarget + (size_t)std::max(max_tasks, 1); }
+// Factor the panels of `tasks` (dmax rows and at most ncols_max columns
+// each, by capacity): one workgroup per matrix for small panels, else one
+// launch per pivot step over a device-built work map.
+void run_qrcp(const QrcpTask* tasks, int32_t ntasks, const QrcpWork& wk, const int2* wg_trsm, int32_t ntrsm,
+              int32_t kmax, int32_t dmax, int32_t ncols_max, int32_t* flag, GemmTask* gtasks, int32_t mcap_max,
+              hipStream_t s, unsigned long long* kcnt = nullptr, bool solve_e = true);
 void run_qform(const QformTask* tasks, const int2* wg, int32_t nwg, int32_t cpw, int32_t ncmax,
                hipStream_t s, unsigned long long* kcnt, int32_t mmax);
 
@@ -232,11 +248,12 @@ void launch_local_samples(const LevelArgs& a, int side, int32_t mcap_max, int32_
 struct TestScratch {
   QrcpTask* qt;        // count entries
   QformTask* qf;       // count entries
-  const int2* wg;      // (task, first column) pairs for cpw-column workgroups
+  const int2* wg;      // (task, first column) pairs for cpw-column workgroups (explicit Q)
   int32_t nwg;
   int32_t cpw;
   int32_t* flag;
   GemmTask* gt;
+  QrcpWork wk;         // device work map of the Householder QR
 };
 void launch_fnorm_test(const LevelArgs& a, int side, int32_t iter, int32_t mcap_max,
                        int32_t qcap_max, int32_t ncap, const TestScratch& ts, hipStream_t s);

@@ -436,8 +436,7 @@ void launch_fnorm_test(const LevelArgs& a, int side, int32_t iter, int32_t mcap_
   prof_begin(s);
   hipLaunchKernelGGL(k_fn_norms, dim3(a.count), dim3(NB), 0, s, a, side, ts.qt);
   prof_end(HSS_K_TEST_QR, s);
-  run_qrcp(ts.qt, a.count, ts.wg, ts.nwg, nullptr, 0, ncap, mcap_max, ts.flag, ts.gt, mcap_max, s, a.kcnt,
-           ts.cpw, false);
+  run_qrcp(ts.qt, a.count, ts.wk, nullptr, 0, ncap, mcap_max, ncap, ts.flag, ts.gt, mcap_max, s, a.kcnt, false);
   prof_begin(s);
   hipLaunchKernelGGL(k_fn_rtest, dim3((a.count + 127) / 128), dim3(128), 0, s, a, side, ts.qf);
   prof_end(HSS_K_TEST_QR, s);

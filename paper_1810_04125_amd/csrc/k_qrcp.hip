@@ -26,6 +26,7 @@ namespace hss {
 constexpr int QB = 256;          // threads per workgroup
 constexpr int QW = QB / 64;
 constexpr int TRB = 64;          // diagonal block of the triangular solve
+constexpr int QBW = 1024;        // threads of the one-workgroup factorization
 
 struct QrcpCtl {
   int32_t done;
@@ -43,8 +44,59 @@ __device__ __forceinline__ double wsum(double v) {
   return v;
 }
 
+// Work map of one factorization call, built on the device from the tasks
+// that are active: every active matrix's m panel columns are cut into
+// chunks of cpw columns, cpw = ceil(active columns / target), so the
+// launches of the pivot steps have about `target` busy workgroups however
+// few matrices factor.  meta = {number of chunks, cpw}; the chunk count is
+// at most target + ntasks.
+__global__ __launch_bounds__(QB) void k_qrcp_plan(const QrcpTask* __restrict__ tasks, int ntasks, int target,
+                                                  int2* __restrict__ chunks, int32_t* __restrict__ meta) {
+  __shared__ long long part[QB];
+  __shared__ int s_cpw;
+  const int tid = threadIdx.x;
+  const int per = (ntasks + QB - 1) / QB;
+  const int t0 = min(ntasks, tid * per), t1 = min(ntasks, t0 + per);
+  long long cols = 0;
+  for (int t = t0; t < t1; ++t)
+    if (tasks[t].active && tasks[t].m > 0) cols += tasks[t].m;
+  part[tid] = cols;
+  __syncthreads();
+  if (tid == 0) {
+    long long tot = 0;
+    for (int i = 0; i < QB; ++i) tot += part[i];
+    s_cpw = (int)max(1LL, (tot + target - 1) / target);
+  }
+  __syncthreads();
+  const int cpw = s_cpw;
+  long long nch = 0;
+  for (int t = t0; t < t1; ++t)
+    if (tasks[t].active && tasks[t].m > 0) nch += (tasks[t].m + cpw - 1) / cpw;
+  __syncthreads();
+  part[tid] = nch;
+  __syncthreads();
+  if (tid == 0) {
+    long long acc = 0;
+    for (int i = 0; i < QB; ++i) {
+      const long long v = part[i];
+      part[i] = acc;
+      acc += v;
+    }
+    meta[0] = (int32_t)acc;
+    meta[1] = cpw;
+  }
+  __syncthreads();
+  long long pos = part[tid];
+  for (int t = t0; t < t1; ++t) {
+    if (!tasks[t].active) continue;
+    for (int c = 0; c < tasks[t].m; c += cpw) chunks[pos++] = make_int2(t, c);
+  }
+}
+
 __global__ __launch_bounds__(QB) void k_qrcp_init(const QrcpTask* __restrict__ tasks, const int2* __restrict__ wg,
-                                                  int cpw) {
+                                                  const int32_t* __restrict__ meta) {
+  if ((int)blockIdx.x >= meta[0]) return;
+  const int cpw = meta[1];
   const int2 w = wg[blockIdx.x];
   const QrcpTask& t = tasks[w.x];
   if (!t.active) return;
@@ -71,18 +123,19 @@ __global__ __launch_bounds__(QB) void k_qrcp_init(const QrcpTask* __restrict__ t
   }
 }
 
-__global__ __launch_bounds__(QB) void k_qrcp_step(const QrcpTask* __restrict__ tasks, const int2* __restrict__ wg,
-                                                  int k, unsigned long long* __restrict__ kcnt, int cpw) {
-  extern __shared__ double vsh[];
-  __shared__ double rv[QW];
-  __shared__ int ri[QW];
-  const int2 w = wg[blockIdx.x];
-  const QrcpTask& t = tasks[w.x];
-  if (!t.active) return;
+// Pivot step k of one matrix over its panel columns [c0, cend), by a
+// workgroup of NT threads.  Returns true when the matrix is finished (the
+// pivot norm fell to the threshold, or k is past min(m, d)); the decision
+// is the same for every thread of the workgroup.
+template <int NT>
+__device__ __forceinline__ bool qrcp_step_body(const QrcpTask& t, int k, int c0, int cend, bool lead,
+                                               unsigned long long* __restrict__ kcnt, double* vsh, double* rv,
+                                               int* ri) {
+  constexpr int NW = NT / 64;
   const int m = t.m, d = t.d;
-  if (k >= min(m, d)) return;
+  if (k >= min(m, d)) return true;
   QrcpCtl* c = ctl_of(t);
-  if (c->done) return;
+  if (c->done) return true;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const double* nold = nrm_of(t, k);
   double* nnew = nrm_of(t, k + 1);
@@ -95,7 +148,7 @@ __global__ __launch_bounds__(QB) void k_qrcp_step(const QrcpTask* __restrict__ t
     // pivot: largest residual norm among the remaining columns, ties -> lowest index
     double bv = -1.0;
     int bi = 0x7fffffff;
-    for (int j = threadIdx.x; j < m; j += QB) {
+    for (int j = threadIdx.x; j < m; j += NT) {
       const double v = nold[j];
       if (v < 0.0) continue;
       if (v > bv || (v == bv && j < bi)) { bv = v; bi = j; }
@@ -110,7 +163,7 @@ __global__ __launch_bounds__(QB) void k_qrcp_step(const QrcpTask* __restrict__ t
     __syncthreads();
     nu = rv[0];
     p = ri[0];
-    for (int i = 1; i < QW; ++i)
+    for (int i = 1; i < NW; ++i)
       if (rv[i] > nu || (rv[i] == nu && ri[i] < p)) { nu = rv[i]; p = ri[i]; }
   }
   const double nu1 = (k == 0) ? nu : c->nu1;
@@ -119,18 +172,17 @@ __global__ __launch_bounds__(QB) void k_qrcp_step(const QrcpTask* __restrict__ t
     const double over = (double)(d - (k + 1) - 1);
     thr = over <= 0.0 ? 0.0 : thr / (1.0 + 4.0 * sqrt((double)d) / over * sqrt(t.hmt_mn));
   }
-  const bool lead = (w.y == 0 && threadIdx.x == 0);
   if (nu <= thr) {
     if (lead) {
       c->rank = k;
       c->done = 1;
     }
-    return;
+    return true;
   }
   const double* x = t.W + (int64_t)p * t.ldw;
   const double x0 = x[k];
   const double alpha = x0 >= 0.0 ? -nu : nu;
-  for (int i = k + threadIdx.x; i < d; i += QB) vsh[i - k] = (i == k) ? x0 - alpha : x[i];
+  for (int i = k + threadIdx.x; i < d; i += NT) vsh[i - k] = (i == k) ? x0 - alpha : x[i];
   const double tk = 1.0 / (nu * (nu + fabs(x0)));  // 2 / v^T v
   if (lead) {
     if (k == 0) c->nu1 = nu;
@@ -140,8 +192,7 @@ __global__ __launch_bounds__(QB) void k_qrcp_step(const QrcpTask* __restrict__ t
     kcount(kcnt, t.kcls, 16.0 * cells, 4.0 * cells);
   }
   __syncthreads();
-  const int jend = min(m, w.y + cpw);
-  for (int j = w.y + wv; j < jend; j += QW) {
+  for (int j = c0 + wv; j < cend; j += NW) {
     if (j == p || nold[j] < 0.0) {
       if (lane == 0) nnew[j] = -1.0;
       continue;
@@ -158,6 +209,60 @@ __global__ __launch_bounds__(QB) void k_qrcp_step(const QrcpTask* __restrict__ t
     }
     sq = wsum(sq);
     if (lane == 0) nnew[j] = sqrt(sq);
+  }
+  return false;
+}
+
+__global__ __launch_bounds__(QB) void k_qrcp_step(const QrcpTask* __restrict__ tasks, const int2* __restrict__ wg,
+                                                  const int32_t* __restrict__ meta, int k,
+                                                  unsigned long long* __restrict__ kcnt) {
+  extern __shared__ double vsh[];
+  __shared__ double rv[QW];
+  __shared__ int ri[QW];
+  if ((int)blockIdx.x >= meta[0]) return;
+  const int cpw = meta[1];
+  const int2 w = wg[blockIdx.x];
+  const QrcpTask& t = tasks[w.x];
+  if (!t.active) return;
+  qrcp_step_body<QB>(t, k, w.y, min(t.m, w.y + cpw), w.y == 0 && threadIdx.x == 0, kcnt, vsh, rv, ri);
+}
+
+// The whole factorization of one matrix by one workgroup, every pivot step
+// in this launch: for small panels, where a launch per step costs more
+// than the step's work.  Same arithmetic and outputs as k_qrcp_init
+// followed by k_qrcp_step for k = 0, 1, ...
+__global__ __launch_bounds__(QBW) void k_qrcp_wg(const QrcpTask* __restrict__ tasks,
+                                                unsigned long long* __restrict__ kcnt) {
+  extern __shared__ double vsh[];
+  __shared__ double rv[QBW / 64];
+  __shared__ int ri[QBW / 64];
+  const QrcpTask& t = tasks[blockIdx.x];
+  if (!t.active) return;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (threadIdx.x == 0) {
+    QrcpCtl* c = ctl_of(t);
+    c->done = 0;
+    c->rank = 0;
+    c->nu1 = 0.0;
+  }
+  double* nrm = nrm_of(t, 0);
+  for (int j = wv; j < t.m; j += QBW / 64) {
+    const double* src = t.S + (int64_t)j * t.lds;
+    double* dst = t.W + (int64_t)j * t.ldw;
+    double sq = 0.0;
+    for (int i = lane; i < t.d; i += 64) {
+      const double x = src[i];
+      dst[i] = x;
+      sq += x * x;
+    }
+    sq = wsum(sq);
+    if (lane == 0) nrm[j] = sqrt(sq);
+  }
+  __syncthreads();
+  const int kmax = min(t.m, t.d);
+  for (int k = 0; k < kmax; ++k) {
+    if (qrcp_step_body<QBW>(t, k, 0, t.m, threadIdx.x == 0, kcnt, vsh, rv, ri)) break;
+    __syncthreads();
   }
 }
 
@@ -268,17 +373,26 @@ QrcpPlan make_qrcp_plan(const std::vector<int32_t>& mcaps, int cpw) {
   return p;
 }
 
-void run_qrcp(const QrcpTask* tasks, int32_t ntasks, const int2* wg_step, int32_t nstep,
-              const int2* wg_trsm, int32_t ntrsm, int32_t kmax, int32_t dmax, int32_t* flag,
-              GemmTask* gtasks, int32_t mcap_max, hipStream_t s, unsigned long long* kcnt, int32_t cpw,
-              bool solve_e) {
+void run_qrcp(const QrcpTask* tasks, int32_t ntasks, const QrcpWork& wk, const int2* wg_trsm, int32_t ntrsm,
+              int32_t kmax, int32_t dmax, int32_t ncols_max, int32_t* flag, GemmTask* gtasks, int32_t mcap_max,
+              hipStream_t s, unsigned long long* kcnt, bool solve_e) {
   if (ntasks <= 0) return;
-  prof_begin(s);
-  hipLaunchKernelGGL(k_qrcp_init, dim3(nstep), dim3(QB), 0, s, tasks, wg_step, cpw);
-  prof_end(HSS_K_QRCP_OTHER, s);
+  if (ntasks > wk.max_tasks) throw Error(HSS_ERR_INTERNAL, "QRCP work map too small for the batch");
+  const int nwg = kQrcpTarget + ntasks;
   const size_t lds = (size_t)std::max(dmax, 1) * sizeof(double);
+  const bool one_wg = (int64_t)std::max(dmax, 1) * std::max(ncols_max, 1) <= kQrcpWgCells && lds <= 48 * 1024;
+  if (one_wg) {
+    prof_begin(s);
+    hipLaunchKernelGGL(k_qrcp_wg, dim3(ntasks), dim3(QBW), lds, s, tasks, kcnt);
+    prof_end(solve_e ? HSS_K_QRCP_STEP : HSS_K_TEST_QR, s);
+  } else {
+    prof_begin(s);
+    hipLaunchKernelGGL(k_qrcp_plan, dim3(1), dim3(QB), 0, s, tasks, ntasks, kQrcpTarget, wk.chunks, wk.meta);
+    hipLaunchKernelGGL(k_qrcp_init, dim3(nwg), dim3(QB), 0, s, tasks, wk.chunks, wk.meta);
+    prof_end(HSS_K_QRCP_OTHER, s);
+  }
   int32_t alive = 1;
-  for (int k = 0; k < kmax; ++k) {
+  for (int k = 0; k < (one_wg ? 0 : kmax); ++k) {
     if ((k % 32) == 0) {
       HSS_HIP_CHECK(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
       hipLaunchKernelGGL(k_qrcp_alive, dim3((ntasks + 127) / 128), dim3(128), 0, s, tasks, ntasks, k, flag);
@@ -287,7 +401,7 @@ void run_qrcp(const QrcpTask* tasks, int32_t ntasks, const int2* wg_step, int32_
       if (alive == 0) break;
     }
     prof_begin(s);
-    hipLaunchKernelGGL(k_qrcp_step, dim3(nstep), dim3(QB), lds, s, tasks, wg_step, k, kcnt, cpw);
+    hipLaunchKernelGGL(k_qrcp_step, dim3(nwg), dim3(QB), lds, s, tasks, wk.chunks, wk.meta, k, kcnt);
     prof_end(solve_e ? HSS_K_QRCP_STEP : HSS_K_TEST_QR, s);
   }
   HSS_HIP_CHECK(hipMemsetAsync(flag, 0, sizeof(int32_t), s));

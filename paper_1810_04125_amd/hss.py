@@ -78,7 +78,7 @@ _lib = None
 EXPORTS = ["hss_tree_build", "hss_tree_free", "hss_compress", "hss_compress_batched", "hss_destroy",
            "hss_matvec", "hss_rel_error", "hss_get_info", "hss_get_node_info", "hss_copy_node",
            "hss_sample", "hss_extract", "hss_interpolative_batched", "hss_last_error", "hss_version",
-           "hss_get_kernel_stats", "hss_mlp_num_params", "hss_mlp_forward", "hss_mlp_gradient",
+           "hss_get_kernel_stats", "hss_release_cache", "hss_mlp_num_params", "hss_mlp_forward", "hss_mlp_gradient",
            "hss_mlp_adam", "hss_mlp_train"]
 
 MLP_MAX_LAYERS = 6
@@ -117,6 +117,7 @@ def lib():
     L.hss_sample.argtypes = [C.POINTER(_Gen), vp, i32, vp, i64, vp, i64, i32, i32, vp]
     L.hss_extract.argtypes = [C.POINTER(_Gen), vp, i32, vp, i32, vp, vp, i64, vp]
     L.hss_interpolative_batched.argtypes = [i32, vp, vp, vp, vp, vp, dbl, dbl, vp, vp, vp, vp, vp]
+    L.hss_release_cache.argtypes = []
     flt, mp = C.c_float, C.POINTER(_Mlp)
     L.hss_mlp_num_params.argtypes = [mp, C.POINTER(i64)]
     L.hss_mlp_forward.argtypes = [mp, vp, vp, i64, vp, vp]
@@ -367,6 +368,11 @@ def compress_batched(gens, trees, Rs, **kw):
     H = (C.c_void_p * k)()
     st = _check(lib().hss_compress_batched(k, G, T, O, H))
     return [HSSMatrix(H[i], (gens[i], trees[i], Rs[i])) for i in range(k)], st
+
+
+def release_cache():
+    """Free the device memory kept between compressions (hss_release_cache)."""
+    _check(lib().hss_release_cache())
 
 
 # --------------------------------------------------------------------------- single steps

@@ -73,7 +73,8 @@ def test_learned_d0_saves_rounds_at_the_same_accuracy(family, n):
     el = Hl.rel_error() if n <= 8192 else None
     if el is not None:
         assert el <= 1e-6 and el <= 2.0 * eb
-    assert abs(il["hss_rank"] - ib["hss_rank"]) <= max(3, 0.05 * ib["hss_rank"])
+    # starting with enough columns gives generators no larger than the adaptive run's
+    assert il["hss_rank"] <= ib["hss_rank"] + max(3, 0.05 * ib["hss_rank"])
 
 
 def test_low_prediction_falls_back_to_the_adaptive_rounds():
