@@ -69,7 +69,7 @@ WORKLOADS = {
     # 256 independent matrices (128 Toeplitz h ~ U[0.05, 0.5], 128 sphere Laplace), n log-uniform in
     # [2048, 16384], leaf 128, compressed together by hss_compress_batched
     "batch-256": dict(batch=256, seed=3, n_lo=2048, n_hi=16384, leaf=128, family="toeplitz+laplace",
-                      method="bisect/rcb", strategy="dbl_fnorm", d0=64, delta_d=64, d_max=2048),
+                      method="bisect/rcb", strategy="dbl_fnorm", d0=64, delta_d=64, d_max=2048, eta=0.05),
     # learned d0 against the adaptive start d0 = 128 (both incrementing, delta_d = 64)
     "learned-toeplitz-131072": dict(family="toeplitz", n=131072, leaf=128, method="bisect", h=0.1,
                                     strategy="inc_fnorm", d0=128, delta_d=64, d_max=2048, learned=True,
@@ -218,7 +218,7 @@ def main_batch(args, W, log):
     R = hss.colmajor(torch.from_numpy(np.ascontiguousarray(Rh.T)).cuda().t())
     del Rh
     Rs = [R[:sp["n"]] for sp in specs]
-    kw = dict(rtol=args.rtol, atol=1e-12, eta=0.1, strategy=W["strategy"], d0=W["d0"], delta_d=W["delta_d"],
+    kw = dict(rtol=args.rtol, atol=1e-12, eta=W.get("eta", 0.1), strategy=W["strategy"], d0=W["d0"], delta_d=W["delta_d"],
               d_max=[min(W["d_max"], sp["n"]) for sp in specs], precision=args.precision)
     log("bench: batch of %d, sum n^2 = %.3e" % (len(specs), sum(sp["n"] ** 2 for sp in specs)))
 
@@ -258,7 +258,7 @@ def main_batch(args, W, log):
         "data": "synthetic",
         "config": {"workload": args.workload, "matrices": len(specs), "n_range": [W["n_lo"], W["n_hi"]],
                    "leaf": W["leaf"], "strategy": W["strategy"], "d0": W["d0"], "rtol": args.rtol,
-                   "atol": 1e-12, "eta": 0.1, "d_max": W["d_max"], "sampling": args.precision},
+                   "atol": 1e-12, "eta": W.get("eta", 0.1), "d_max": W["d_max"], "sampling": args.precision},
         "rel_err_max_of_8": max(errs), "rel_err_ok": bool(max(errs) <= args.rtol), "status": st,
         "rounds_max": max(i["rounds"] for i in infos), "d_final_max": max(i["d_final"] for i in infos),
         "roofline": rl, "cpu_baseline": cpu,
@@ -297,7 +297,7 @@ def main():
     n = W["n"]
     log("bench: workload %s precision %s rtol %g" % (args.workload, args.precision, args.rtol))
     gen, T, R = setup(W)
-    kw = dict(rtol=args.rtol, atol=1e-12, eta=0.1, strategy=W["strategy"], d0=W["d0"], delta_d=W["delta_d"],
+    kw = dict(rtol=args.rtol, atol=1e-12, eta=W.get("eta", 0.1), strategy=W["strategy"], d0=W["d0"], delta_d=W["delta_d"],
               d_max=W["d_max"], precision=args.precision)
     learned = None
     if W.get("learned"):
@@ -367,7 +367,8 @@ def main():
     value = args.steps / el
     cfg = {"workload": args.workload, "n": n, "leaf": W["leaf"], "tree": W["method"],
            "strategy": W["strategy"], "d0": "learned" if learned else W["d0"], "delta_d": W["delta_d"],
-           "rtol": args.rtol, "atol": 1e-12, "eta": 0.1, "d_max": W["d_max"], "sampling": args.precision}
+           "rtol": args.rtol, "atol": 1e-12, "eta": W.get("eta", 0.1), "d_max": W["d_max"],
+           "sampling": args.precision}
     out = {
         "metric": METRIC, "value": round(value, 4), "unit": "compressions/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * el / args.steps, 3),

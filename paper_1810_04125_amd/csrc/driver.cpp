@@ -246,7 +246,7 @@ void Job::release_transients() {
   for (void* p : transients) hipFreeAsync(p, stream);
   HSS_HIP_CHECK(hipStreamSynchronize(stream));
   transients.clear();
-  tpool = wsa = wsb = partial = nullptr;
+  tpool = wsa = wsb = partial = gemm_ws = nullptr;
 }
 
 static void validate(const hss_generator& g, const hss_tree* t, const hss_options& o, int k) {
@@ -321,6 +321,7 @@ size_t Job::estimate_bytes(const hss_generator& g, const hss_tree* t, const hss_
   dbl += nsides * align8(t->n * dc) + 8 * t->n;
   dbl += *std::max_element(wsa.begin(), wsa.end()) + *std::max_element(wsb.begin(), wsb.end());
   dbl += (int64_t)sample_partial_elems(t->n, (int32_t)dc);
+  dbl += kGemmSplitElems;
   return (size_t)(8 * dbl + 4 * ints + 64 * nn + (16 << 20));
 }
 
@@ -450,11 +451,13 @@ void Job::setup(int32_t count, const hss_generator* gens, const hss_tree* const*
     const size_t ba = a256(sizeof(double) * std::max<int64_t>(wsA, 1));
     const size_t bb = a256(sizeof(double) * std::max<int64_t>(wsB, 1));
     const size_t bp = a256(sizeof(double) * part);
-    char* base = (char*)arena_acquire(bt + ba + bb + bp);
+    const size_t bg = sizeof(double) * kGemmSplitElems;
+    char* base = (char*)arena_acquire(bt + ba + bb + bp + bg);
     tpool = (double*)base;
     wsa = (double*)(base + bt);
     wsb = (double*)(base + bt + ba);
     partial = part ? (double*)(base + bt + ba + bb) : nullptr;
+    gemm_ws = (double*)(base + bt + ba + bb + bp);
   }
   desc_d = (NodeDesc*)dalloc(sizeof(NodeDesc) * gnodes);
   st_d = (NodeState*)dalloc(sizeof(NodeState) * gnodes);
@@ -612,6 +615,7 @@ void Job::run_level(int lev, int32_t ncap) {
   a.tasks = tasks_d;
   a.flags = flags_d;
   a.kcnt = kcnt_d;
+  a.gws = gemm_ws;
   const int nsides = all_sym ? 1 : 2;
   const int32_t nc = std::min(ncap, L.dcap);
   HSS_HIP_CHECK(hipMemsetAsync(flags_d + 1, 0, sizeof(int32_t), stream));

@@ -55,6 +55,7 @@ struct Job {
   std::vector<void*> transients;   // freed when the compression ends
   double *dpool = nullptr, *tpool = nullptr, *wsa = nullptr, *wsb = nullptr, *partial = nullptr;
   double* epool = nullptr;         // compacted E (after compression)
+  double* gemm_ws = nullptr;       // split-K partial tiles (transient)
   int32_t* ipool = nullptr;
   int64_t* lpool = nullptr;
   NodeDesc* desc_d = nullptr;

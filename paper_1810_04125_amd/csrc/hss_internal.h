@@ -218,8 +218,14 @@ void launch_sample(const GenDev& g, int32_t transpose, int32_t precision, const 
                    hipStream_t s, unsigned long long* kcnt = nullptr);
 void launch_extract(const GenDev& g, int32_t nI, const int64_t* I, int32_t nJ, const int64_t* J,
                     double* out, int64_t ldo, hipStream_t s);
+// Grouped GEMM over tasks of at most mcap x ncap outputs; with a workspace
+// of ws_elems doubles and kcap (largest K) long enough, K is split into
+// slices summed in fixed order (k_gemm.hip).
 void launch_gemm(const GemmTask* tasks, int32_t ntasks, int32_t mcap, int32_t ncap,
-                 hipStream_t s, unsigned long long* kcnt = nullptr);
+                 hipStream_t s, unsigned long long* kcnt = nullptr, int32_t kcap = 0,
+                 double* ws = nullptr, int64_t ws_elems = 0);
+// Split-K workspace of a compression job (doubles).
+constexpr int64_t kGemmSplitElems = int64_t(16) << 20;
 
 struct LevelArgs {
   const NodeDesc* desc;
@@ -236,6 +242,7 @@ struct LevelArgs {
   GemmTask* tasks;       // scratch task array, capacity >= 2 * count
   int32_t* flags;        // device error flags
   unsigned long long* kcnt;  // algorithmic byte / flop counters
+  double* gws;           // split-K partial tiles, kGemmSplitElems doubles
 };
 
 void launch_plan(const LevelArgs& a, hipStream_t s);

@@ -5,9 +5,17 @@
 //
 // Every task has its own pointers, strides and sizes (sizes are written
 // by device kernels, since ranks live on the GPU).  blockIdx.z selects
-// the task, blockIdx.y/x the 64 x 64 output tile; tiles outside a task's
-// actual size exit at once.  4 waves per workgroup, each a 32 x 32 block
-// of 2 x 2 MFMA 16x16x4 FP64 tiles; A and B tiles are staged in LDS.
+// the task and the K slice, blockIdx.y/x the 64 x 64 output tile; tiles
+// outside a task's actual size exit at once.  4 waves per workgroup, each
+// a 32 x 32 block of 2 x 2 MFMA 16x16x4 FP64 tiles; A and B tiles of 32
+// k-columns are staged in LDS, the next ones loaded into registers while
+// the current ones are multiplied.
+//
+// Split K: products with few output tiles and a long K (the Gram-Schmidt
+// projections against a large basis at the top of the tree) cut K into
+// `ksplit` slices; each slice writes its 64 x 64 partial tile to a
+// workspace and a second kernel adds the slices in slice order, so the
+// result does not depend on scheduling.
 #include "hss_internal.h"
 
 namespace hss {
@@ -15,15 +23,27 @@ namespace hss {
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 constexpr int GT = 64;   // output tile
-constexpr int GK = 16;   // K tile
+constexpr int GK = 32;   // K tile
 constexpr int GLD = GT + 2;
+constexpr int GPT = GK * GT / 256;   // elements of one operand tile per thread
 
-__global__ __launch_bounds__(256) void k_gemm_grouped(const GemmTask* __restrict__ tasks,
+__device__ __forceinline__ void gemm_coords(const GemmTask& t, int idx, bool a_side, int& k, int& x) {
+  // make the faster index follow the smaller stride
+  if (a_side) {
+    if (t.a_rs <= t.a_cs) { x = idx % GT; k = idx / GT; } else { k = idx % GK; x = idx / GK; }
+  } else {
+    if (t.b_cs <= t.b_rs) { x = idx % GT; k = idx / GT; } else { k = idx % GK; x = idx / GK; }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_gemm_grouped(const GemmTask* __restrict__ tasks, int ntasks, int ksplit,
+                                                     double* __restrict__ part,
                                                      unsigned long long* __restrict__ kcnt) {
-  const GemmTask t = tasks[blockIdx.z];
+  const int task = blockIdx.z % ntasks, ks = blockIdx.z / ntasks;
+  const GemmTask t = tasks[task];
   const int tm = blockIdx.y, tn = blockIdx.x;
   if (t.M <= 0 || t.N <= 0) return;
-  if (tm == 0 && tn == 0 && threadIdx.x == 0) {
+  if (ks == 0 && tm == 0 && tn == 0 && threadIdx.x == 0) {
     const double M = t.M, N = t.N, K = t.K;
     kcount(kcnt, HSS_K_GEMM, 8.0 * (M * K + K * N + M * N * (t.beta == 0.0 ? 1.0 : 2.0)), 2.0 * M * N * K);
   }
@@ -34,30 +54,52 @@ __global__ __launch_bounds__(256) void k_gemm_grouped(const GemmTask* __restrict
   const int wave = threadIdx.x >> 6;
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
   const int64_t i0 = (int64_t)tm * GT, j0 = (int64_t)tn * GT;
+  // K slice of this workgroup
+  int kb = 0, ke = t.K;
+  if (ksplit > 1) {
+    const int kchunk = ((t.K + ksplit - 1) / ksplit + GK - 1) / GK * GK;
+    kb = min(t.K, ks * kchunk);
+    ke = min(t.K, kb + kchunk);
+  }
   dbl4 acc[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
 
-  for (int k0 = 0; k0 < t.K; k0 += GK) {
-    for (int idx = threadIdx.x; idx < GK * GT; idx += 256) {
-      // A tile: As[k][i]; make the faster index follow the smaller stride
+  double ra[GPT], rb[GPT];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int e = 0; e < GPT; ++e) {
+      const int idx = threadIdx.x + 256 * e;
       int k, i;
-      if (t.a_rs <= t.a_cs) { i = idx % GT; k = idx / GT; } else { k = idx % GK; i = idx / GK; }
+      gemm_coords(t, idx, true, k, i);
       const int64_t gi = i0 + i, gk = k0 + k;
       double av = 0.0;
-      if (gi < t.M && gk < t.K) {
+      if (gi < t.M && gk < ke) {
         const int64_t col = t.a_cols ? (int64_t)t.a_cols[gk] : gk;
         av = t.A[gi * t.a_rs + col * t.a_cs];
       }
-      As[k][i] = av;
-      int kb, j;
-      if (t.b_cs <= t.b_rs) { j = idx % GT; kb = idx / GT; } else { kb = idx % GK; j = idx / GK; }
-      const int64_t gj = j0 + j, gkb = k0 + kb;
-      Bs[kb][j] = (gj < t.N && gkb < t.K) ? t.B[gkb * t.b_rs + gj * t.b_cs] : 0.0;
+      ra[e] = av;
+      int kk, j;
+      gemm_coords(t, idx, false, kk, j);
+      const int64_t gj = j0 + j, gkb = k0 + kk;
+      rb[e] = (gj < t.N && gkb < ke) ? t.B[gkb * t.b_rs + gj * t.b_cs] : 0.0;
+    }
+  };
+  if (kb < ke) load(kb);
+  for (int k0 = kb; k0 < ke; k0 += GK) {
+#pragma unroll
+    for (int e = 0; e < GPT; ++e) {
+      const int idx = threadIdx.x + 256 * e;
+      int k, x;
+      gemm_coords(t, idx, true, k, x);
+      As[k][x] = ra[e];
+      gemm_coords(t, idx, false, k, x);
+      Bs[k][x] = rb[e];
     }
     __syncthreads();
+    if (k0 + GK < ke) load(k0 + GK);
 #pragma unroll
     for (int kk = 0; kk < GK; kk += 4) {
       const int kq = kk + (lane >> 4);
@@ -71,6 +113,18 @@ __global__ __launch_bounds__(256) void k_gemm_grouped(const GemmTask* __restrict
       acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
     }
     __syncthreads();
+  }
+  if (ksplit > 1) {
+    // raw partial tile, row-major 64 x 64, slot (ks, task, tm, tn)
+    double* P = part + ((((int64_t)ks * ntasks + task) * gridDim.y + tm) * gridDim.x + tn) * (GT * GT);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          P[(wr + a * 16 + 4 * v + (lane >> 4)) * GT + wc + b * 16 + (lane & 15)] = acc[a][b][v];
+    return;
   }
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -88,12 +142,43 @@ __global__ __launch_bounds__(256) void k_gemm_grouped(const GemmTask* __restrict
       }
 }
 
+// C = alpha * (sum of the K-slice partials, in slice order) + beta * C
+__global__ __launch_bounds__(256) void k_gemm_splitk_sum(const GemmTask* __restrict__ tasks, int ntasks, int ksplit,
+                                                        const double* __restrict__ part) {
+  const int task = blockIdx.z;
+  const GemmTask t = tasks[task];
+  const int tm = blockIdx.y, tn = blockIdx.x;
+  if (t.M <= 0 || t.N <= 0 || tm * GT >= t.M || tn * GT >= t.N) return;
+  const int64_t tile = (((int64_t)task * gridDim.y + tm) * gridDim.x + tn) * (GT * GT);
+  const int64_t stride = (int64_t)ntasks * gridDim.y * gridDim.x * (GT * GT);
+  for (int e = threadIdx.x; e < GT * GT; e += 256) {
+    const int r = e / GT, c = e % GT;
+    const int64_t gi = (int64_t)tm * GT + r, gj = (int64_t)tn * GT + c;
+    if (gi >= t.M || gj >= t.N) continue;
+    double sum = 0.0;
+    for (int ks = 0; ks < ksplit; ++ks) sum += part[ks * stride + tile + e];
+    double* cp = t.C + gi * t.c_rs + gj * t.c_cs;
+    const double val = t.alpha * sum;
+    *cp = (t.beta == 0.0) ? val : val + t.beta * (*cp);
+  }
+}
+
 void launch_gemm(const GemmTask* tasks, int32_t ntasks, int32_t mcap, int32_t ncap, hipStream_t s,
-                 unsigned long long* kcnt) {
+                 unsigned long long* kcnt, int32_t kcap, double* ws, int64_t ws_elems) {
   if (ntasks <= 0 || mcap <= 0 || ncap <= 0) return;
-  dim3 grid((unsigned)((ncap + GT - 1) / GT), (unsigned)((mcap + GT - 1) / GT), (unsigned)ntasks);
+  const unsigned gx = (unsigned)((ncap + GT - 1) / GT), gy = (unsigned)((mcap + GT - 1) / GT);
+  const int64_t tiles = (int64_t)gx * gy * ntasks;
+  int ksplit = 1;
+  if (ws && kcap >= 4 * GK * 4 && tiles < 1024) {
+    ksplit = (int)std::min<int64_t>(std::min<int64_t>(8, kcap / (4 * GK)), std::max<int64_t>(1, 2048 / tiles));
+    while (ksplit > 1 && (int64_t)ksplit * tiles * GT * GT > ws_elems) --ksplit;
+  }
   prof_begin(s);
-  hipLaunchKernelGGL(k_gemm_grouped, grid, dim3(256), 0, s, tasks, kcnt);
+  hipLaunchKernelGGL(k_gemm_grouped, dim3(gx, gy, (unsigned)(ntasks * ksplit)), dim3(256), 0, s, tasks, ntasks,
+                     ksplit, ws, kcnt);
+  if (ksplit > 1)
+    hipLaunchKernelGGL(k_gemm_splitk_sum, dim3(gx, gy, (unsigned)ntasks), dim3(256), 0, s, tasks, ntasks, ksplit,
+                       ws);
   prof_end(HSS_K_GEMM, s);
 }
 

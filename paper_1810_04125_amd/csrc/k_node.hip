@@ -266,12 +266,12 @@ __global__ __launch_bounds__(NB) void k_ls_gather(LevelArgs a, int side) {
 
 void launch_local_samples(const LevelArgs& a, int side, int32_t mcap_max, int32_t rcap_max,
                           int32_t ncap, hipStream_t s) {
-  (void)rcap_max;
   if (a.count <= 0) return;
   prof_begin(s);
   hipLaunchKernelGGL(k_ls_gather, node_grid(a.count), dim3(NB), 0, s, a, side);
   prof_end(HSS_K_GATHER, s);
-  launch_gemm(a.tasks, 2 * a.count, mcap_max, ncap, s, a.kcnt);
+  launch_gemm(a.tasks, 2 * a.count, mcap_max, ncap, s, a.kcnt, std::max(mcap_max, rcap_max), a.gws,
+              kGemmSplitElems);
 }
 
 // ------------------------------------------------------------------ F-norm test
@@ -430,8 +430,8 @@ void launch_fnorm_test(const LevelArgs& a, int side, int32_t iter, int32_t mcap_
   hipLaunchKernelGGL(k_fn_copy, node_grid(a.count), dim3(NB), 0, s, a, side, iter);
   prof_end(HSS_K_GATHER, s);
   for (int pass = 0; pass < 2; ++pass) {  // block Gram-Schmidt, twice
-    launch_gemm(a.tasks, a.count, qcap_max, ncap, s, a.kcnt);
-    launch_gemm(a.tasks + a.count, a.count, mcap_max, ncap, s, a.kcnt);
+    launch_gemm(a.tasks, a.count, qcap_max, ncap, s, a.kcnt, mcap_max, a.gws, kGemmSplitElems);
+    launch_gemm(a.tasks + a.count, a.count, mcap_max, ncap, s, a.kcnt, qcap_max, a.gws, kGemmSplitElems);
   }
   prof_begin(s);
   hipLaunchKernelGGL(k_fn_norms, dim3(a.count), dim3(NB), 0, s, a, side, ts.qt);
@@ -582,12 +582,11 @@ __global__ __launch_bounds__(NB) void k_red_gather(LevelArgs a, int side) {
 
 void launch_reduce(const LevelArgs& a, int side, int32_t mcap_max, int32_t rcap_max,
                    int32_t ncap, hipStream_t s) {
-  (void)mcap_max;
   if (a.count <= 0) return;
   prof_begin(s);
   hipLaunchKernelGGL(k_red_gather, node_grid(a.count), dim3(NB), 0, s, a, side);
   prof_end(HSS_K_GATHER, s);
-  launch_gemm(a.tasks, a.count, rcap_max, ncap, s, a.kcnt);
+  launch_gemm(a.tasks, a.count, rcap_max, ncap, s, a.kcnt, mcap_max, a.gws, kGemmSplitElems);
 }
 
 // ------------------------------------------------------------------ finalize

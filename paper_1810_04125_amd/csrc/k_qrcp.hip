@@ -192,6 +192,53 @@ __device__ __forceinline__ bool qrcp_step_body(const QrcpTask& t, int k, int c0,
     kcount(kcnt, t.kcls, 16.0 * cells, 4.0 * cells);
   }
   __syncthreads();
+  const int ncol = cend - c0;
+  if (ncol > 0 && 2 * ncol <= NW) {
+    // fewer columns than waves: wpc waves share a column, each a slice of
+    // its rows; partial sums meet in LDS (rv, free again after the pivot
+    // search) and are added in wave order
+    const int wpc = NW / ncol;
+    const int cj = wv / wpc, seg = wv - cj * wpc;
+    const bool act = cj < ncol;
+    const int j = c0 + cj;
+    const bool live = act && !(j == p || nold[j] < 0.0);
+    double* y = t.W + (int64_t)j * t.ldw;
+    double dot = 0.0;
+    if (live) {
+#pragma unroll 4
+      for (int i = k + seg * 64 + lane; i < d; i += 64 * wpc) dot += vsh[i - k] * y[i];
+    }
+    dot = wsum(dot);
+    if (lane == 0) rv[wv] = dot;
+    __syncthreads();
+    double tot = 0.0;
+    if (act)
+      for (int q = 0; q < wpc; ++q) tot += rv[cj * wpc + q];
+    tot *= tk;
+    double sq = 0.0;
+    if (live) {
+#pragma unroll 4
+      for (int i = k + seg * 64 + lane; i < d; i += 64 * wpc) {
+        const double yi = y[i] - tot * vsh[i - k];
+        y[i] = yi;
+        if (i > k) sq += yi * yi;
+      }
+    }
+    sq = wsum(sq);
+    __syncthreads();
+    if (lane == 0) rv[wv] = sq;
+    __syncthreads();
+    if (act && seg == 0 && lane == 0) {
+      if (!live) {
+        nnew[j] = -1.0;
+      } else {
+        double s2 = 0.0;
+        for (int q = 0; q < wpc; ++q) s2 += rv[cj * wpc + q];
+        nnew[j] = sqrt(s2);
+      }
+    }
+    return false;
+  }
   for (int j = c0 + wv; j < cend; j += NW) {
     if (j == p || nold[j] < 0.0) {
       if (lane == 0) nnew[j] = -1.0;
@@ -199,9 +246,11 @@ __device__ __forceinline__ bool qrcp_step_body(const QrcpTask& t, int k, int c0,
     }
     double* y = t.W + (int64_t)j * t.ldw;
     double dot = 0.0;
+#pragma unroll 4
     for (int i = k + lane; i < d; i += 64) dot += vsh[i - k] * y[i];
     dot = wsum(dot) * tk;
     double sq = 0.0;
+#pragma unroll 4
     for (int i = k + lane; i < d; i += 64) {
       const double yi = y[i] - dot * vsh[i - k];
       y[i] = yi;

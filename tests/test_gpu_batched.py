@@ -32,15 +32,21 @@ def test_batched_matches_individual(prec):
     kw = dict(rtol=1e-6, atol=1e-12, eta=0.1, strategy="dbl_fnorm", d0=64, precision=prec)
     Rs = [dev_colmajor(p[4]) for p in probs]
     Hb, st = hss.compress_batched([p[0] for p in probs], [p[1] for p in probs], Rs, **kw)
+    # The work partition of the GEMMs (K slices) and of the pivot steps
+    # depends on the whole batch, so a problem's sums may be taken in another
+    # order than when it runs alone: same decisions, E equal to rounding.
     for (gen, T, ot, op, R), Rd, hb in zip(probs, Rs, Hb):
         hi, _ = hss.compress(gen, T, Rd, **kw)
         assert hb.info()["rounds"] == hi.info()["rounds"]
         for t in range(1, T.num_nodes):
             assert hb.node_info(t) == hi.node_info(t)
             assert np.array_equal(hb.node(t, "JR"), hi.node(t, "JR"))
-            assert np.array_equal(hb.node(t, "ER"), hi.node(t, "ER"))
-        e = hb.rel_error()
+            Eb, Ei = hb.node(t, "ER"), hi.node(t, "ER")
+            if Ei.size:
+                assert np.abs(Eb - Ei).max() <= 1e-7 * max(1.0, np.abs(Ei).max())
+        e, ei = hb.rel_error(), hi.rel_error()
         assert e <= (1e-6 if prec == "fp64" else 2e-5), e
+        assert abs(e - ei) <= 1e-3 * ei
 
 
 def test_batched_fp64_against_oracle():
