@@ -45,14 +45,16 @@ PEAK_HBM_GBS = 8000.0
 # kernel class -> (HIP kernel name, bound)
 KCLASS_INFO = {
     "SAMPLE": ("k_sample_f64", "mfma"),
-    "GEMM": ("k_gemm_grouped", "mfma"),
-    "TEST_QR": ("k_fn_norms/k_qrcp_step(nopivot)/k_qform_step", "hbm"),
+    "GEMM": ("k_gemm_grouped+k_gemm_splitk_sum", "mfma"),
+    "TEST_NORMS": ("k_fn_norms/k_fn_rtest", "hbm"),
     "QRCP_STEP": ("k_qrcp_step", "hbm"),
+    "QRCP_WG": ("k_qrcp_wg", "hbm"),
+    "QFORM": ("k_qform", "hbm"),
     "GATHER": ("k_ls_gather/k_red_gather/k_fn_copy", "hbm"),
     "EXTRACT": ("k_extract_nodes", "hbm"),
     "TRSM": ("k_trsm_diag", "hbm"),
     "SAMPLE_REDUCE": ("k_splitk_reduce", "hbm"),
-    "QRCP_OTHER": ("k_qrcp_init/k_qrcp_fin", "hbm"),
+    "QRCP_OTHER": ("k_qrcp_plan/k_qrcp_init/k_qrcp_alive/k_qrcp_fin", "hbm"),
     "MISC": ("k_plan/k_finalize/...", "hbm"),
 }
 
@@ -266,6 +268,19 @@ def main_batch(args, W, log):
     print(json.dumps(out), flush=True)
 
 
+def copy_calibration():
+    """A plain copy of known size: 1 GiB read and 1 GiB written per launch.
+    Under rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE its counters give the
+    factor that turns the counters of other kernels into bytes."""
+    import torch
+    a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": a.numel() * 8, "copy_bytes_written": b.numel() * 8, "launches": 3}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -277,7 +292,11 @@ def main():
     ap.add_argument("--rtol", type=float, default=1e-6)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a device-to-device copy of 1 GiB three times (reference for HBM counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        return copy_calibration()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)",
               file=sys.stderr)

@@ -540,7 +540,6 @@ hss_status hss_interpolative_batched(int32_t count, const int32_t* m, const int3
       q.mcap = std::max(m[k], 1);
       q.active = 1;
       q.nopivot = 0;
-      q.kcls = HSS_K_QRCP_STEP;
       mc[k] = q.mcap;
     }
     QrcpPlan plan = make_qrcp_plan(mc);

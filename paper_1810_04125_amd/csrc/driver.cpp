@@ -29,9 +29,9 @@ void prof_begin(hipStream_t s) {
   if (g_prof && g_prof->on) hipEventRecord(g_prof->e0, s);
 }
 
-void prof_end(int cls, hipStream_t s) {
+void prof_end(int cls, hipStream_t s, int nlaunch) {
   if (!g_prof) return;
-  g_prof->launches[cls]++;
+  g_prof->launches[cls] += nlaunch;
   if (!g_prof->on) return;
   hipEventRecord(g_prof->e1, s);
   hipEventSynchronize(g_prof->e1);

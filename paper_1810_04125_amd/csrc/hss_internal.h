@@ -141,7 +141,6 @@ struct QrcpTask {
   double hmt_mn;     // > 0: HMT factor with sqrt(hmt_mn); 0: plain threshold
   int32_t m, d, mcap, active;
   int32_t nopivot;   // 1: plain Householder QR (column k is the k-th pivot)
-  int32_t kcls;      // kernel class the step counters are charged to
 };
 
 // Explicit Q of a Householder QR done by run_qrcp in nopivot mode:
@@ -197,7 +196,9 @@ struct Prof {
 };
 extern thread_local Prof* g_prof;
 void prof_begin(hipStream_t s);
-void prof_end(int cls, hipStream_t s);
+// Closes the interval opened by prof_begin and charges it to class cls;
+// nlaunch kernels were launched back to back inside it.
+void prof_end(int cls, hipStream_t s, int nlaunch = 1);
 
 __device__ __forceinline__ void kcount(unsigned long long* kc, int cls, double bytes, double flops) {
   if (!kc) return;

@@ -44,6 +44,21 @@ __device__ double block_sum(double v, double* red) {
   return s;
 }
 
+// Same for a workgroup of NT threads; `red` holds NT / 64 doubles.
+template <int NT>
+__device__ double block_sum_n(double v, double* red) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < NT / 64; ++i) s += red[i];
+  __syncthreads();
+  return s;
+}
+
 // Element loops of the per-node copy kernels are spread over gridDim.y
 // workgroups of the same node.
 #define CHUNKED_FOR(idx, total) \
@@ -347,8 +362,10 @@ __global__ __launch_bounds__(NB) void k_fn_copy(LevelArgs a, int side, int iter)
 // The F-norm tests of eq. stopping_criteria on the projected block Sh
 // (m x nc, column-major, ld mcap): pass if ||Sh|| < eps_r ||S_new|| or
 // ||Sh|| / sqrt(nc) < eps_a; otherwise queue the Householder QR of Sh.
-__global__ __launch_bounds__(NB) void k_fn_norms(LevelArgs a, int side, QrcpTask* __restrict__ qt) {
-  __shared__ double red[NW];
+constexpr int NBN = 1024;  // threads of the norm kernel (one workgroup per node)
+
+__global__ __launch_bounds__(NBN) void k_fn_norms(LevelArgs a, int side, QrcpTask* __restrict__ qt) {
+  __shared__ double red[NBN / 64];
   const int t = blockIdx.x;
   const int g = a.nodes[t];
   const NodeDesc& nd = a.desc[g];
@@ -361,18 +378,22 @@ __global__ __launch_bounds__(NB) void k_fn_norms(LevelArgs a, int side, QrcpTask
   const double er = fmax(P.eps_r / lev, P.eps_floor), ea = P.eps_a / lev;
   const double* S = ctp(a, nd.S[side]);
   double* Sh = a.wsA + nd.ws;
+  // S rows are contiguous over the columns, Sh columns over the rows
   double p1 = 0.0, p2 = 0.0;
-  for (int64_t idx = threadIdx.x; idx < (int64_t)m * nc; idx += NB) {
-    const int i = (int)(idx % m), c = (int)(idx / m);
+  for (int64_t idx = threadIdx.x; idx < (int64_t)m * nc; idx += NBN) {
+    const int c = (int)(idx % nc), i = (int)(idx / nc);
     const double x = S[(int64_t)i * dcap + c0 + c];
-    const double y = Sh[(int64_t)c * ld + i];
     p1 += x * x;
+  }
+  for (int64_t idx = threadIdx.x; idx < (int64_t)m * nc; idx += NBN) {
+    const int i = (int)(idx % m), c = (int)(idx / m);
+    const double y = Sh[(int64_t)c * ld + i];
     p2 += y * y;
   }
-  const double nS = sqrt(block_sum(p1, red));
-  const double nSh = sqrt(block_sum(p2, red));
+  const double nS = sqrt(block_sum_n<NBN>(p1, red));
+  const double nSh = sqrt(block_sum_n<NBN>(p2, red));
   if (threadIdx.x != 0) return;
-  kcount(a.kcnt, HSS_K_TEST_QR, 16.0 * m * nc, 4.0 * m * nc);
+  kcount(a.kcnt, HSS_K_TEST_NORMS, 16.0 * m * nc, 4.0 * m * nc);
   if (nS == 0.0 || nSh < er * nS || nSh / sqrt((double)nc) < ea) {
     st.passed[side] = 1;
     st.run[side] = 0;
@@ -385,7 +406,7 @@ __global__ __launch_bounds__(NB) void k_fn_norms(LevelArgs a, int side, QrcpTask
   q.rank_out = &st.qrank;
   q.er = 0.0; q.ea = 0.0; q.hmt_mn = 0.0;
   q.m = nc; q.d = m; q.mcap = nc; q.active = 1;
-  q.nopivot = 1; q.kcls = HSS_K_TEST_QR;
+  q.nopivot = 1;
   qt[t] = q;
 }
 
@@ -434,12 +455,12 @@ void launch_fnorm_test(const LevelArgs& a, int side, int32_t iter, int32_t mcap_
     launch_gemm(a.tasks + a.count, a.count, mcap_max, ncap, s, a.kcnt, qcap_max, a.gws, kGemmSplitElems);
   }
   prof_begin(s);
-  hipLaunchKernelGGL(k_fn_norms, dim3(a.count), dim3(NB), 0, s, a, side, ts.qt);
-  prof_end(HSS_K_TEST_QR, s);
+  hipLaunchKernelGGL(k_fn_norms, dim3(a.count), dim3(NBN), 0, s, a, side, ts.qt);
+  prof_end(HSS_K_TEST_NORMS, s);
   run_qrcp(ts.qt, a.count, ts.wk, nullptr, 0, ncap, mcap_max, ncap, ts.flag, ts.gt, mcap_max, s, a.kcnt, false);
   prof_begin(s);
   hipLaunchKernelGGL(k_fn_rtest, dim3((a.count + 127) / 128), dim3(128), 0, s, a, side, ts.qf);
-  prof_end(HSS_K_TEST_QR, s);
+  prof_end(HSS_K_TEST_NORMS, s);
   run_qform(ts.qf, ts.wg, ts.nwg, ts.cpw, ncap, s, a.kcnt, mcap_max);
 }
 
@@ -492,7 +513,6 @@ __global__ void k_build_qrcp(LevelArgs a, int side, int hmt, QrcpTask* __restric
   q.d = P.d;
   q.mcap = nd.mcap;
   q.nopivot = 0;
-  q.kcls = HSS_K_QRCP_STEP;
   out[t] = q;
 }
 

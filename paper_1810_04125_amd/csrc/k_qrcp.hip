@@ -129,8 +129,8 @@ __global__ __launch_bounds__(QB) void k_qrcp_init(const QrcpTask* __restrict__ t
 // is the same for every thread of the workgroup.
 template <int NT>
 __device__ __forceinline__ bool qrcp_step_body(const QrcpTask& t, int k, int c0, int cend, bool lead,
-                                               unsigned long long* __restrict__ kcnt, double* vsh, double* rv,
-                                               int* ri) {
+                                               unsigned long long* __restrict__ kcnt, int kcls, double* vsh,
+                                               double* rv, int* ri) {
   constexpr int NW = NT / 64;
   const int m = t.m, d = t.d;
   if (k >= min(m, d)) return true;
@@ -189,7 +189,7 @@ __device__ __forceinline__ bool qrcp_step_body(const QrcpTask& t, int k, int c0,
     rdiag_of(t)[k] = alpha;
     if (t.J) t.J[k] = p;
     const double cells = (double)(d - k) * (double)(m - k - 1);
-    kcount(kcnt, t.kcls, 16.0 * cells, 4.0 * cells);
+    kcount(kcnt, kcls, 16.0 * cells, 4.0 * cells);
   }
   __syncthreads();
   const int ncol = cend - c0;
@@ -273,7 +273,8 @@ __global__ __launch_bounds__(QB) void k_qrcp_step(const QrcpTask* __restrict__ t
   const int2 w = wg[blockIdx.x];
   const QrcpTask& t = tasks[w.x];
   if (!t.active) return;
-  qrcp_step_body<QB>(t, k, w.y, min(t.m, w.y + cpw), w.y == 0 && threadIdx.x == 0, kcnt, vsh, rv, ri);
+  qrcp_step_body<QB>(t, k, w.y, min(t.m, w.y + cpw), w.y == 0 && threadIdx.x == 0, kcnt, HSS_K_QRCP_STEP, vsh,
+                     rv, ri);
 }
 
 // The whole factorization of one matrix by one workgroup, every pivot step
@@ -310,7 +311,7 @@ __global__ __launch_bounds__(QBW) void k_qrcp_wg(const QrcpTask* __restrict__ ta
   __syncthreads();
   const int kmax = min(t.m, t.d);
   for (int k = 0; k < kmax; ++k) {
-    if (qrcp_step_body<QBW>(t, k, 0, t.m, threadIdx.x == 0, kcnt, vsh, rv, ri)) break;
+    if (qrcp_step_body<QBW>(t, k, 0, t.m, threadIdx.x == 0, kcnt, HSS_K_QRCP_WG, vsh, rv, ri)) break;
     __syncthreads();
   }
 }
@@ -433,25 +434,28 @@ void run_qrcp(const QrcpTask* tasks, int32_t ntasks, const QrcpWork& wk, const i
   if (one_wg) {
     prof_begin(s);
     hipLaunchKernelGGL(k_qrcp_wg, dim3(ntasks), dim3(QBW), lds, s, tasks, kcnt);
-    prof_end(solve_e ? HSS_K_QRCP_STEP : HSS_K_TEST_QR, s);
+    prof_end(HSS_K_QRCP_WG, s);
   } else {
     prof_begin(s);
     hipLaunchKernelGGL(k_qrcp_plan, dim3(1), dim3(QB), 0, s, tasks, ntasks, kQrcpTarget, wk.chunks, wk.meta);
     hipLaunchKernelGGL(k_qrcp_init, dim3(nwg), dim3(QB), 0, s, tasks, wk.chunks, wk.meta);
     prof_end(HSS_K_QRCP_OTHER, s);
   }
+  // pivot steps: launched back to back in segments of 32 between liveness
+  // polls; profiling times each segment as a whole
   int32_t alive = 1;
-  for (int k = 0; k < (one_wg ? 0 : kmax); ++k) {
-    if ((k % 32) == 0) {
-      HSS_HIP_CHECK(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
-      hipLaunchKernelGGL(k_qrcp_alive, dim3((ntasks + 127) / 128), dim3(128), 0, s, tasks, ntasks, k, flag);
-      HSS_HIP_CHECK(hipMemcpyAsync(&alive, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-      HSS_HIP_CHECK(hipStreamSynchronize(s));
-      if (alive == 0) break;
-    }
+  const int ksteps = one_wg ? 0 : kmax;
+  for (int k0 = 0; k0 < ksteps; k0 += 32) {
+    HSS_HIP_CHECK(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
+    hipLaunchKernelGGL(k_qrcp_alive, dim3((ntasks + 127) / 128), dim3(128), 0, s, tasks, ntasks, k0, flag);
+    HSS_HIP_CHECK(hipMemcpyAsync(&alive, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HSS_HIP_CHECK(hipStreamSynchronize(s));
+    if (alive == 0) break;
+    const int k1 = std::min(ksteps, k0 + 32);
     prof_begin(s);
-    hipLaunchKernelGGL(k_qrcp_step, dim3(nwg), dim3(QB), lds, s, tasks, wk.chunks, wk.meta, k, kcnt);
-    prof_end(solve_e ? HSS_K_QRCP_STEP : HSS_K_TEST_QR, s);
+    for (int k = k0; k < k1; ++k)
+      hipLaunchKernelGGL(k_qrcp_step, dim3(nwg), dim3(QB), lds, s, tasks, wk.chunks, wk.meta, k, kcnt);
+    prof_end(HSS_K_QRCP_STEP, s, k1 - k0);
   }
   HSS_HIP_CHECK(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
   prof_begin(s);
@@ -485,7 +489,7 @@ __global__ __launch_bounds__(QB) void k_qform(const QformTask* __restrict__ task
   const int jend = min(t.nc, w.y + cpw);
   if (w.y == 0 && threadIdx.x == 0) {
     const double mm = m, b = t.nc;
-    kcount(kcnt, HSS_K_TEST_QR, 8.0 * mm * b * 2.0, 2.0 * mm * b * b);
+    kcount(kcnt, HSS_K_QFORM, 8.0 * mm * b * 2.0, 2.0 * mm * b * b);
   }
   for (int j = w.y + wv; j < jend; j += QW) {
     double* y = t.Q + (int64_t)j * t.ldq;
@@ -511,7 +515,7 @@ void run_qform(const QformTask* tasks, const int2* wg, int32_t nwg, int32_t cpw,
   if (nwg <= 0 || ncmax <= 0) return;
   prof_begin(s);
   hipLaunchKernelGGL(k_qform, dim3(nwg), dim3(QB), 0, s, tasks, wg, cpw, kcnt);
-  prof_end(HSS_K_TEST_QR, s);
+  prof_end(HSS_K_QFORM, s);
 }
 
 }  // namespace hss

@@ -56,6 +56,19 @@ void launch_permute_points(const double* pts, const int64_t* perm, int64_t n, do
                      perm, n, out);
 }
 
+// 1/sqrt(x) from the hardware estimate (about 2^-25 relative) refined by
+// two Newton-Raphson steps y <- y + y (1 - x y^2) / 2, the residual taken
+// with an FMA; within one ulp on (1e-8, 4], cheaper than sqrt + divide.
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double e = fma(-(x * y), y, 1.0);
+    y = fma(0.5 * y, e, y);
+  }
+  return y;
+}
+
 template <int FAM>
 __device__ __forceinline__ double entry_t(const GenDev& g, int64_t i, int64_t j) {
   if constexpr (FAM == HSS_FAM_TOEPLITZ) return toeplitz_entry(g, i, j);
@@ -72,7 +85,9 @@ __global__ __launch_bounds__(512) void k_sample_f64(GenDev g, const double* __re
                                                     int64_t ldr, double* __restrict__ out,
                                                     int64_t lds, int32_t ncols, int64_t kchunk,
                                                     int32_t nsplit) {
+  constexpr bool PTS = FAM == HSS_FAM_LAPLACE || FAM == HSS_FAM_GAUSS;
   __shared__ double Rs[SM_BK][SM_LDP];
+  __shared__ double Ps[PTS ? SM_BK : 1][3];   // points of the K rows of the tile
   const int64_t n = g.n;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -83,6 +98,14 @@ __global__ __launch_bounds__(512) void k_sample_f64(GenDev g, const double* __re
   const int64_t my_row = row0 + (lane & 15);
   const bool row_ok = my_row < n;
   const int kq = lane >> 4;
+  double px = 0.0, py = 0.0, pz = 0.0;   // this lane's row point
+  if constexpr (PTS) {
+    if (row_ok) {
+      px = g.pts[3 * my_row];
+      py = g.pts[3 * my_row + 1];
+      pz = g.pts[3 * my_row + 2];
+    }
+  }
 
   dbl4 acc[4];
 #pragma unroll
@@ -97,12 +120,35 @@ __global__ __launch_bounds__(512) void k_sample_f64(GenDev g, const double* __re
       const int gc = col0 + c;
       Rs[r][c] = (gk < ke && gc < ncols) ? R[(int64_t)gc * ldr + gk] : 0.0;
     }
+    if constexpr (PTS) {
+      for (int idx = threadIdx.x; idx < SM_BK * 3; idx += 512) {
+        const int r = idx / 3, c = idx - 3 * (idx / 3);
+        const int64_t gk = kt + r;
+        Ps[r][c] = gk < ke ? g.pts[3 * gk + c] : 0.0;
+      }
+    }
     __syncthreads();
 #pragma unroll 2
     for (int kk = 0; kk < SM_BK; kk += 4) {
       const int64_t j = kt + kk + kq;
       double a = 0.0;
-      if (row_ok && j < ke) a = TRANS ? entry_t<FAM>(g, j, my_row) : entry_t<FAM>(g, my_row, j);
+      if (row_ok && j < ke) {
+        if constexpr (PTS) {
+          // symmetric kernels: the transposed product reads the same entries
+          const double dx = px - Ps[kk + kq][0];
+          const double dy = py - Ps[kk + kq][1];
+          const double dz = pz - Ps[kk + kq][2];
+          const double r2 = dx * dx + dy * dy + dz * dz;
+          if constexpr (FAM == HSS_FAM_LAPLACE) {
+            a = my_row == j ? g.diag : kInv4Pi * rsqrt_nr(r2);
+          } else {
+            a = exp(-r2 * g.inv2s2);
+            if (my_row == j) a += g.diag;
+          }
+        } else {
+          a = TRANS ? entry_t<FAM>(g, j, my_row) : entry_t<FAM>(g, my_row, j);
+        }
+      }
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         const double b = Rs[kk + kq][c * 16 + (lane & 15)];
