@@ -144,14 +144,17 @@ struct QrcpTask {
 };
 
 // Explicit Q of a Householder QR done by run_qrcp in nopivot mode:
-// Q(:, 0:nc) = H_0 ... H_{nc-1} [I; 0], reflectors rebuilt from the
-// untouched panel columns W(k:m, k) and the diagonal rdiag[k].
+// Q(:, 0:nc) = H_0 ... H_{nc-1} [I; 0], reflectors rebuilt from the panel
+// columns W(k:m, k) and the diagonal rdiag[k].  With a workspace wk of
+// 2 nc^2 + 8 doubles, Q is formed in compact WY form and W is overwritten
+// by V; without (wk == nullptr) column by column.
 struct QformTask {
-  const double* W;
+  double* W;
   int64_t ldw;
   const double* rdiag;
   double* Q;
   int64_t ldq;
+  double* wk;
   int32_t m, nc, active, pad;
 };
 
@@ -181,8 +184,8 @@ inline size_t qrcp_work_entries(int32_t max_tasks) { return (size_t)kQrcpTarget 
 void run_qrcp(const QrcpTask* tasks, int32_t ntasks, const QrcpWork& wk, const int2* wg_trsm, int32_t ntrsm,
               int32_t kmax, int32_t dmax, int32_t ncols_max, int32_t* flag, GemmTask* gtasks, int32_t mcap_max,
               hipStream_t s, unsigned long long* kcnt = nullptr, bool solve_e = true);
-void run_qform(const QformTask* tasks, const int2* wg, int32_t nwg, int32_t cpw, int32_t ncmax,
-               hipStream_t s, unsigned long long* kcnt, int32_t mmax);
+void run_qform(QformTask* tasks, int32_t count, const int2* wg, int32_t nwg, int32_t cpw, int32_t ncmax,
+               int32_t mmax, GemmTask* gt, double* gws, hipStream_t s, unsigned long long* kcnt);
 
 // ------------------------------------------------------------------ profiling
 // Launch counts and (in profile mode) HIP-event time per kernel class; the

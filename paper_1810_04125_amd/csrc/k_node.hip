@@ -440,6 +440,11 @@ __global__ void k_fn_rtest(LevelArgs a, int side, QformTask* __restrict__ qf) {
   f.rdiag = rdiag;
   f.Q = tp(a, nd.Q[side]) + (int64_t)st.q[side] * nd.mcap; f.ldq = nd.mcap;
   f.m = m; f.nc = nc; f.active = 1; f.pad = 0;
+  // compact WY formation needs 2 nc^2 doubles: the node's workspace slot
+  // (mcap x dcap) holds the block in its first nc columns
+  const int64_t used = ((int64_t)nd.mcap * nc + 7) / 8 * 8;
+  const int64_t room = (int64_t)nd.mcap * P.dcap - used;
+  f.wk = (mn > 0.0 && room >= 2 * (int64_t)nc * nc + 8) ? a.wsA + nd.ws + used : nullptr;
   qf[t] = f;
   st.q[side] += nc;
 }
@@ -461,7 +466,7 @@ void launch_fnorm_test(const LevelArgs& a, int side, int32_t iter, int32_t mcap_
   prof_begin(s);
   hipLaunchKernelGGL(k_fn_rtest, dim3((a.count + 127) / 128), dim3(128), 0, s, a, side, ts.qf);
   prof_end(HSS_K_TEST_NORMS, s);
-  run_qform(ts.qf, ts.wg, ts.nwg, ts.cpw, ncap, s, a.kcnt, mcap_max);
+  run_qform(ts.qf, a.count, ts.wg, ts.nwg, ts.cpw, ncap, mcap_max, ts.gt, a.gws, s, a.kcnt);
 }
 
 __global__ void k_decide_fnorm(LevelArgs a) {

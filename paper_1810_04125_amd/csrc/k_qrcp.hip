@@ -474,48 +474,4 @@ void run_qrcp(const QrcpTask* tasks, int32_t ntasks, const QrcpWork& wk, const i
   HSS_HIP_CHECK(hipGetLastError());
 }
 
-// ------------------------------------------------------------------ explicit Q
-// Column j of Q = H_0 H_1 ... H_{nc-1} [I; 0] is H_0 ... H_j e_j (H_k leaves
-// e_j unchanged for k > j), so every column is formed independently: one
-// launch, each workgroup forming its own columns from the read-only
-// reflectors.
-__global__ __launch_bounds__(QB) void k_qform(const QformTask* __restrict__ tasks, const int2* __restrict__ wg,
-                                              int cpw, unsigned long long* __restrict__ kcnt) {
-  const int2 w = wg[blockIdx.x];
-  const QformTask& t = tasks[w.x];
-  if (!t.active) return;
-  const int m = t.m;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int jend = min(t.nc, w.y + cpw);
-  if (w.y == 0 && threadIdx.x == 0) {
-    const double mm = m, b = t.nc;
-    kcount(kcnt, HSS_K_QFORM, 8.0 * mm * b * 2.0, 2.0 * mm * b * b);
-  }
-  for (int j = w.y + wv; j < jend; j += QW) {
-    double* y = t.Q + (int64_t)j * t.ldq;
-    for (int i = lane; i < m; i += 64) y[i] = (i == j) ? 1.0 : 0.0;
-    for (int k = j; k >= 0; --k) {
-      const double alpha = t.rdiag[k];
-      const double nu = fabs(alpha);
-      if (nu == 0.0) continue;
-      const double* x = t.W + (int64_t)k * t.ldw;
-      const double x0 = x[k];
-      const double tk = 1.0 / (nu * (nu + fabs(x0)));
-      double dot = 0.0;
-      for (int i = k + lane; i < m; i += 64) dot += (i == k ? x0 - alpha : x[i]) * y[i];
-      dot = wsum(dot) * tk;
-      for (int i = k + lane; i < m; i += 64) y[i] -= dot * (i == k ? x0 - alpha : x[i]);
-    }
-  }
-}
-
-void run_qform(const QformTask* tasks, const int2* wg, int32_t nwg, int32_t cpw, int32_t ncmax, hipStream_t s,
-               unsigned long long* kcnt, int32_t mmax) {
-  (void)mmax;
-  if (nwg <= 0 || ncmax <= 0) return;
-  prof_begin(s);
-  hipLaunchKernelGGL(k_qform, dim3(nwg), dim3(QB), 0, s, tasks, wg, cpw, kcnt);
-  prof_end(HSS_K_QFORM, s);
-}
-
 }  // namespace hss

@@ -111,43 +111,63 @@ __global__ __launch_bounds__(512) void k_sample_f64(GenDev g, const double* __re
 #pragma unroll
   for (int c = 0; c < 4; ++c) acc[c] = dbl4{0.0, 0.0, 0.0, 0.0};
 
-  for (int64_t kt = kb; kt < ke; kt += SM_BK) {
-    // stage R(kt:kt+BK, col0:col0+64) -> Rs[k][c]
-    for (int idx = threadIdx.x; idx < SM_BK * SM_COLS; idx += 512) {
-      const int r = idx % SM_BK;
-      const int c = idx / SM_BK;
+  // R(kt:kt+BK, col0:col0+64) and the tile's points are loaded into
+  // registers one tile ahead, then stored to LDS (Rs[k][c], Ps[k][xyz])
+  constexpr int RPT = SM_BK * SM_COLS / 512;
+  double rr[RPT];
+  double pp = 0.0;
+  auto load_tile = [&](int64_t kt) {
+#pragma unroll
+    for (int e = 0; e < RPT; ++e) {
+      const int idx = threadIdx.x + 512 * e;
+      const int r = idx % SM_BK, c = idx / SM_BK;
       const int64_t gk = kt + r;
       const int gc = col0 + c;
-      Rs[r][c] = (gk < ke && gc < ncols) ? R[(int64_t)gc * ldr + gk] : 0.0;
+      rr[e] = (gk < ke && gc < ncols) ? R[(int64_t)gc * ldr + gk] : 0.0;
     }
     if constexpr (PTS) {
-      for (int idx = threadIdx.x; idx < SM_BK * 3; idx += 512) {
-        const int r = idx / 3, c = idx - 3 * (idx / 3);
-        const int64_t gk = kt + r;
-        Ps[r][c] = gk < ke ? g.pts[3 * gk + c] : 0.0;
+      if (threadIdx.x < SM_BK * 3) {
+        const int64_t gk = kt + threadIdx.x / 3;
+        pp = gk < ke ? g.pts[3 * kt + threadIdx.x] : 0.0;
       }
     }
+  };
+  if (kb < ke) load_tile(kb);
+  for (int64_t kt = kb; kt < ke; kt += SM_BK) {
+#pragma unroll
+    for (int e = 0; e < RPT; ++e) {
+      const int idx = threadIdx.x + 512 * e;
+      Rs[idx % SM_BK][idx / SM_BK] = rr[e];
+    }
+    if constexpr (PTS) {
+      if (threadIdx.x < SM_BK * 3) Ps[threadIdx.x / 3][threadIdx.x % 3] = pp;
+    }
     __syncthreads();
-#pragma unroll 2
+    if (kt + SM_BK < ke) load_tile(kt + SM_BK);
+#pragma unroll
     for (int kk = 0; kk < SM_BK; kk += 4) {
       const int64_t j = kt + kk + kq;
-      double a = 0.0;
-      if (row_ok && j < ke) {
-        if constexpr (PTS) {
-          // symmetric kernels: the transposed product reads the same entries
-          const double dx = px - Ps[kk + kq][0];
-          const double dy = py - Ps[kk + kq][1];
-          const double dz = pz - Ps[kk + kq][2];
-          const double r2 = dx * dx + dy * dy + dz * dz;
-          if constexpr (FAM == HSS_FAM_LAPLACE) {
-            a = my_row == j ? g.diag : kInv4Pi * rsqrt_nr(r2);
-          } else {
-            a = exp(-r2 * g.inv2s2);
-            if (my_row == j) a += g.diag;
-          }
+      const bool ok = row_ok && j < ke;
+      double a;
+      if constexpr (PTS) {
+        // symmetric kernels: the transposed product reads the same entries;
+        // computed unconditionally and selected, so the loop has no branches
+        const double dx = px - Ps[kk + kq][0];
+        const double dy = py - Ps[kk + kq][1];
+        const double dz = pz - Ps[kk + kq][2];
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        double v;
+        if constexpr (FAM == HSS_FAM_LAPLACE) {
+          v = kInv4Pi * rsqrt_nr(r2);
+          v = my_row == j ? g.diag : v;
         } else {
-          a = TRANS ? entry_t<FAM>(g, j, my_row) : entry_t<FAM>(g, my_row, j);
+          v = exp(-r2 * g.inv2s2);
+          v = my_row == j ? v + g.diag : v;
         }
+        a = ok ? v : 0.0;
+      } else {
+        a = 0.0;
+        if (ok) a = TRANS ? entry_t<FAM>(g, j, my_row) : entry_t<FAM>(g, my_row, j);
       }
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
