@@ -88,30 +88,54 @@ __global__ __launch_bounds__(QFB) void k_qf_prep(const QformTask* __restrict__ t
   }
 }
 
-// M = S^{-1} V_1^T (b x b, column j by thread j, back substitution), then
-// the GEMM task Q_k -= V M.
-__global__ __launch_bounds__(QFB) void k_qf_solve(const QformTask* __restrict__ tasks, GemmTask* __restrict__ gt,
+// M = S^{-1} V_1^T (b x b) by right-looking back substitution over the
+// whole workgroup (rows of M become final from the bottom up), held in LDS
+// for b <= QF_LDS_B and in the workspace otherwise; then the GEMM task
+// Q_k -= V M.
+constexpr int QFS = 1024;
+constexpr int QF_LDS_B = 64;
+
+__global__ __launch_bounds__(QFS) void k_qf_solve(const QformTask* __restrict__ tasks, GemmTask* __restrict__ gt,
                                                   unsigned long long* __restrict__ kcnt) {
+  __shared__ double Rl[QF_LDS_B * QF_LDS_B];
   const QformTask& t = tasks[blockIdx.x];
   GemmTask* g = gt + blockIdx.x;
   if (threadIdx.x == 0) g->M = 0;
   if (!t.active || !t.wk) return;
   const int b = t.nc;
-  const double* G = t.wk;      // b x b, column-major
-  double* M = t.wk + (int64_t)b * b;
-  for (int j = threadIdx.x; j < b; j += QFB) {
-    double* mj = M + (int64_t)j * b;
-    for (int l = b - 1; l >= 0; --l) {
-      // V_1^T(l, j) = V(j, l), zero for j < l
-      double r = j >= l ? t.W[(int64_t)l * t.ldw + j] : 0.0;
-      for (int p = l + 1; p < b; ++p) r -= G[(int64_t)p * b + l] * mj[p];
-      mj[l] = r / (0.5 * G[(int64_t)l * b + l]);
+  const double* G = t.wk;                      // V^T V, b x b column-major
+  double* Mg = t.wk + (int64_t)b * b;          // M, b x b column-major
+  double* R = b <= QF_LDS_B ? Rl : Mg;         // row-major b x b working copy
+  // right-hand side V_1^T: R(l, j) = V(j, l), zero for j < l
+  for (int idx = threadIdx.x; idx < b * b; idx += QFS) {
+    const int l = idx / b, j = idx - l * b;
+    R[idx] = j >= l ? t.W[(int64_t)l * t.ldw + j] : 0.0;
+  }
+  __syncthreads();
+  for (int l = b - 1; l >= 0; --l) {
+    // row l is final: divide by S_ll = G_ll / 2
+    const double inv = 2.0 / G[(int64_t)l * b + l];
+    for (int j = threadIdx.x; j < b; j += QFS) R[l * b + j] *= inv;
+    __syncthreads();
+    // rows p < l: R(p, :) -= S(p, l) R(l, :), S(p, l) = G(p, l)
+    for (int idx = threadIdx.x; idx < l * b; idx += QFS) {
+      const int p = idx / b, j = idx - p * b;
+      R[idx] -= G[(int64_t)l * b + p] * R[l * b + j];
+    }
+    __syncthreads();
+  }
+  // M column-major for the GEMM
+  if (R == Rl) {
+    for (int idx = threadIdx.x; idx < b * b; idx += QFS) {
+      const int l = idx / b, j = idx - l * b;
+      Mg[(int64_t)j * b + l] = Rl[idx];
     }
   }
   if (threadIdx.x == 0) {
     GemmTask q;
     q.A = t.W; q.a_rs = 1; q.a_cs = t.ldw;   // V
-    q.B = M; q.b_rs = 1; q.b_cs = b;
+    q.B = Mg;
+    if (R == Rl) { q.b_rs = 1; q.b_cs = b; } else { q.b_rs = b; q.b_cs = 1; }   // M(l, j)
     q.C = t.Q; q.c_rs = 1; q.c_cs = t.ldq;
     q.M = t.m; q.N = b; q.K = b; q.pad = 0;
     q.alpha = -1.0; q.beta = 1.0;
@@ -131,7 +155,7 @@ void run_qform(QformTask* tasks, int32_t count, const int2* wg, int32_t nwg, int
   prof_end(HSS_K_QFORM, s);
   launch_gemm(gt, count, ncmax, ncmax, s, kcnt, mmax, gws, kGemmSplitElems);
   prof_begin(s);
-  hipLaunchKernelGGL(k_qf_solve, dim3((unsigned)count), dim3(QFB), 0, s, tasks, gt, kcnt);
+  hipLaunchKernelGGL(k_qf_solve, dim3((unsigned)count), dim3(QFS), 0, s, tasks, gt, kcnt);
   prof_end(HSS_K_QFORM, s);
   launch_gemm(gt, count, mmax, ncmax, s, kcnt);
   if (nwg > 0) {
