@@ -46,6 +46,23 @@ __device__ __forceinline__ float lp_entry(const GenDev& g, int64_t row, int64_t 
   return TRANS ? entry32<FAM>(g, col, row) : entry32<FAM>(g, row, col);
 }
 
+// Kernel-family entry from the row point (px, py, pz) and a column point
+// staged in LDS: distance in FP64, then FP32 rsqrt / exp.  Symmetric, so
+// the transposed product uses the same value.
+template <int FAM>
+__device__ __forceinline__ float pts_entry32(double px, double py, double pz, const double* pj, bool diag_hit,
+                                             float diag, double inv2s2) {
+  const double dx = px - pj[0], dy = py - pj[1], dz = pz - pj[2];
+  const double r2 = dx * dx + dy * dy + dz * dz;
+  if constexpr (FAM == HSS_FAM_LAPLACE) {
+    const float v = (float)kInv4Pi * rsqrtf((float)r2);
+    return diag_hit ? diag : v;
+  } else {
+    const float v = expf(-(float)(r2 * inv2s2));
+    return diag_hit ? v + diag : v;
+  }
+}
+
 __device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
   hi = (__bf16)x;
   lo = (__bf16)(x - (float)hi);
@@ -56,9 +73,11 @@ __global__ __launch_bounds__(512) void k_sample_lp(GenDev g, const double* __res
                                                    double* __restrict__ out, int64_t lds, int32_t ncols,
                                                    int64_t kchunk, int32_t nsplit, const int32_t* __restrict__ leaf_lo,
                                                    const int32_t* __restrict__ leaf_hi, int32_t offdiag) {
+  constexpr bool PTS = FAM == HSS_FAM_LAPLACE || FAM == HSS_FAM_GAUSS;
   __shared__ float Rf[LP_BK][LP_COLS + 1];
   __shared__ __bf16 Rhi[LP_COLS][LP_BK + 8];
   __shared__ __bf16 Rlo[LP_COLS][LP_BK + 8];
+  __shared__ double Ps[PTS ? LP_BK : 1][3];
   const int64_t n = g.n;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -74,6 +93,15 @@ __global__ __launch_bounds__(512) void k_sample_lp(GenDev g, const double* __res
     llo = leaf_lo[my_row];
     lhi = leaf_hi[my_row];
   }
+  double px = 0.0, py = 0.0, pz = 0.0;
+  if constexpr (PTS) {
+    if (row_ok) {
+      px = g.pts[3 * my_row];
+      py = g.pts[3 * my_row + 1];
+      pz = g.pts[3 * my_row + 2];
+    }
+  }
+  const float fdiag = (float)g.diag;
   dbl4 acc64[4];
   flt4 acc[4];
 #pragma unroll
@@ -97,6 +125,12 @@ __global__ __launch_bounds__(512) void k_sample_lp(GenDev g, const double* __res
         Rf[r][c] = x;
       }
     }
+    if constexpr (PTS) {
+      for (int idx = threadIdx.x; idx < LP_BK * 3; idx += 512) {
+        const int64_t gk = kt + idx / 3;
+        Ps[idx / 3][idx % 3] = gk < ke ? g.pts[3 * kt + idx] : 0.0;
+      }
+    }
     __syncthreads();
     if (BF) {
       const int64_t j0 = kt + 8 * kq;
@@ -104,7 +138,13 @@ __global__ __launch_bounds__(512) void k_sample_lp(GenDev g, const double* __res
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         const int64_t j = j0 + e;
-        const float a = (row_ok && j < ke) ? lp_entry<FAM, TRANS>(g, my_row, j, llo, lhi, offdiag) : 0.0f;
+        float a;
+        if constexpr (PTS) {
+          const float v = pts_entry32<FAM>(px, py, pz, Ps[8 * kq + e], my_row == j, fdiag, g.inv2s2);
+          a = (row_ok && j < ke && !(offdiag && j >= llo && j < lhi)) ? v : 0.0f;
+        } else {
+          a = (row_ok && j < ke) ? lp_entry<FAM, TRANS>(g, my_row, j, llo, lhi, offdiag) : 0.0f;
+        }
         __bf16 hi, lo;
         split_bf16(a, hi, lo);
         ahi[e] = hi;
@@ -119,10 +159,16 @@ __global__ __launch_bounds__(512) void k_sample_lp(GenDev g, const double* __res
         acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, bhi, acc[c], 0, 0, 0);
       }
     } else {
-#pragma unroll 2
+#pragma unroll
       for (int kk = 0; kk < LP_BK; kk += 4) {
         const int64_t j = kt + kk + kq;
-        const float a = (row_ok && j < ke) ? lp_entry<FAM, TRANS>(g, my_row, j, llo, lhi, offdiag) : 0.0f;
+        float a;
+        if constexpr (PTS) {
+          const float v = pts_entry32<FAM>(px, py, pz, Ps[kk + kq], my_row == j, fdiag, g.inv2s2);
+          a = (row_ok && j < ke && !(offdiag && j >= llo && j < lhi)) ? v : 0.0f;
+        } else {
+          a = (row_ok && j < ke) ? lp_entry<FAM, TRANS>(g, my_row, j, llo, lhi, offdiag) : 0.0f;
+        }
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
           const float b = Rf[kk + kq][c * 16 + (lane & 15)];
