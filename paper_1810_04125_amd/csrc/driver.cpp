@@ -468,6 +468,7 @@ void Job::setup(int32_t count, const hss_generator* gens, const hss_tree* const*
   qwork.chunks = (int2*)dalloc(sizeof(int2) * qrcp_work_entries(qwork.max_tasks));
   qwork.meta = (int32_t*)dalloc(sizeof(int32_t) * 2);
   qform_d = (QformTask*)dalloc(sizeof(QformTask) * std::max(maxcount, 1));
+  chol_d = (CholTask*)dalloc(sizeof(CholTask) * std::max(maxcount, 1));
   mvtasks_d = (GemmTask*)dalloc(sizeof(GemmTask) * 2 * std::max(maxcount, 1));
   for (auto& L : levels) {
     std::vector<int32_t> mc;
@@ -648,7 +649,7 @@ void Job::run_level(int lev, int32_t ncap) {
         L.ntest = (int32_t)qp.step.size();
         L.test_ncap = nb;
       }
-      TestScratch ts{qtasks_d, qform_d, L.wg_test, L.ntest, kTestCpw, flags_d + 3, tasks_d, qwork};
+      TestScratch ts{qtasks_d, qform_d, chol_d, L.wg_test, L.ntest, kTestCpw, flags_d + 3, tasks_d, qwork};
       for (int it = 0; it < nblk; ++it)
         for (int s = 0; s < nsides; ++s)
           launch_fnorm_test(a, s, it, L.mcap, std::max(L.qcap, 1), nb, ts, stream);

@@ -67,6 +67,7 @@ struct Job {
   QrcpTask* qtasks_d = nullptr;
   QrcpWork qwork{nullptr, nullptr, 0};   // device work map of every factorization call
   QformTask* qform_d = nullptr;
+  CholTask* chol_d = nullptr;
   int64_t* mvoff_d = nullptr;   // per node: prefix sum of rcap (matvec slots)
   int64_t mvtot = 0;
   int64_t* mvws_d = nullptr;    // per node: prefix sum of mcap (matvec workspace)

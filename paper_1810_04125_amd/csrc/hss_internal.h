@@ -256,9 +256,23 @@ void launch_local_samples(const LevelArgs& a, int side, int32_t mcap_max, int32_
 // One iteration of the Alg. 5 test on side `side`: copy + CGS2 (GEMMs),
 // norms and the F-norm tests, Householder QR of the projected block on
 // many workgroups (run_qrcp, nopivot), the R-diagonal tests, explicit Q_k.
+// Cholesky QR (two passes) of a projected block S_hat (m x nc, nc <=
+// kCholMaxB): Q1 = S_hat R1^{-1}, Q = Q1 R2^{-1}, Rbar = R2 R1, used to
+// decide a clearly failing stopping test without the Householder QR.
+constexpr int kCholMaxB = 64;
+struct CholTask {
+  const double* S;   // S_hat, column-major, leading dimension lds
+  int64_t lds;
+  double* Q1;        // m x nc, leading dimension lds
+  double* G;         // nc x nc Gram matrix
+  double* X;         // nc x nc inverse triangular factor
+  double* d1;        // nc: diagonal of R1
+  int32_t m, nc, active, pad;
+};
 struct TestScratch {
   QrcpTask* qt;        // count entries
   QformTask* qf;       // count entries
+  CholTask* ct;        // count entries
   const int2* wg;      // (task, first column) pairs for cpw-column workgroups (explicit Q)
   int32_t nwg;
   int32_t cpw;

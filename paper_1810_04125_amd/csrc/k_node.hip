@@ -364,13 +364,18 @@ __global__ __launch_bounds__(NB) void k_fn_copy(LevelArgs a, int side, int iter)
 // ||Sh|| / sqrt(nc) < eps_a; otherwise queue the Householder QR of Sh.
 constexpr int NBN = 1024;  // threads of the norm kernel (one workgroup per node)
 
-__global__ __launch_bounds__(NBN) void k_fn_norms(LevelArgs a, int side, QrcpTask* __restrict__ qt) {
+__global__ __launch_bounds__(NBN) void k_fn_norms(LevelArgs a, int side, QrcpTask* __restrict__ qt,
+                                                 CholTask* __restrict__ ct) {
   __shared__ double red[NBN / 64];
   const int t = blockIdx.x;
   const int g = a.nodes[t];
   const NodeDesc& nd = a.desc[g];
   NodeState& st = a.st[g];
-  if (threadIdx.x == 0) qt[t].active = 0;
+  if (threadIdx.x == 0) {
+    qt[t].active = 0;
+    ct[t].active = 0;
+    a.tasks[t].M = 0;
+  }
   if (!st.run[side]) return;
   const ProbDev& P = a.prob[nd.prob];
   const int dcap = P.dcap, m = st.m[side], nc = st.bnc, c0 = st.bc0, ld = nd.mcap;
@@ -408,6 +413,159 @@ __global__ __launch_bounds__(NBN) void k_fn_norms(LevelArgs a, int side, QrcpTas
   q.m = nc; q.d = m; q.mcap = nc; q.active = 1;
   q.nopivot = 1;
   qt[t] = q;
+  // Cholesky QR first when the block is narrow and the node's workspace
+  // slot (mcap x dcap) holds S_hat, Q1, G, X and d1 side by side
+  const int64_t blk = ((int64_t)ld * nc + 7) / 8 * 8;
+  const int64_t sq = (int64_t)nc * nc;
+  if (nc <= kCholMaxB && 2 * blk + 2 * sq + nc + 16 <= (int64_t)ld * dcap) {
+    CholTask c;
+    c.S = Sh; c.lds = ld;
+    c.Q1 = Sh + blk;
+    c.G = Sh + 2 * blk;
+    c.X = c.G + sq;
+    c.d1 = c.X + sq;
+    c.m = m; c.nc = nc; c.active = 1; c.pad = 0;
+    ct[t] = c;
+    GemmTask k;   // G = S_hat^T S_hat
+    k.A = Sh; k.a_rs = ld; k.a_cs = 1;
+    k.B = Sh; k.b_rs = 1; k.b_cs = ld;
+    k.C = c.G; k.c_rs = 1; k.c_cs = nc;
+    k.M = nc; k.N = nc; k.K = m; k.pad = 0;
+    k.alpha = 1.0; k.beta = 0.0;
+    a.tasks[t] = k;
+  }
+}
+
+// One Cholesky pass of the test's block: R^T R = G (upper R in LDS),
+// X = R^{-1}.  Pass 1: keep diag(R1), queue Q1 = S_hat X and G2 = Q1^T Q1.
+// Pass 2: Rbar = R2 R1 decides the R-diagonal tests of eq.
+// stopping_criteria when the block clearly fails them (min |Rbar_ii| at
+// least 10 times the threshold) and Q1 was nearly orthonormal (|R2_ii - 1|
+// <= 0.1); then Q = Q1 X2 is appended to the basis and the Householder QR
+// of the block is skipped.  Anything else is left to the Householder path.
+template <int PASS>
+__global__ __launch_bounds__(256) void k_cq_chol(LevelArgs a, int side, CholTask* __restrict__ ct,
+                                                 QrcpTask* __restrict__ qt) {
+  __shared__ double A[kCholMaxB][kCholMaxB + 1];
+  const int t = blockIdx.x;
+  GemmTask* T0 = a.tasks + t;
+  GemmTask* T1 = a.tasks + a.count + t;
+  if (threadIdx.x == 0) {
+    T0->M = 0;
+    T1->M = 0;
+  }
+  CholTask& c = ct[t];
+  if (!c.active) return;
+  const int nc = c.nc;
+  // thread (row group ib, column j): 4 row groups x 64 columns
+  const int j = threadIdx.x & 63, ib = threadIdx.x >> 6;
+  if (j < nc)
+    for (int i = ib; i < nc; i += 4) A[i][j] = c.G[(int64_t)j * nc + i];
+  __syncthreads();
+  // outer-product Cholesky on the unscaled rows: after step k the trailing
+  // block holds G - sum_{p<=k} r_p^T r_p with r_p = A(p, p:) / sqrt(A(p,p))
+  bool bad = false;
+  for (int k = 0; k < nc; ++k) {
+    const double dk = A[k][k];
+    if (!(dk > 0.0)) {
+      bad = true;
+      break;
+    }
+    if (j > k && j < nc) {
+      const double akj = A[k][j] / dk;
+      for (int i = k + 1 + ib; i <= j; i += 4) A[i][j] -= A[k][i] * akj;
+    }
+    __syncthreads();
+  }
+  if (bad) {
+    if (threadIdx.x == 0) c.active = 0;
+    return;
+  }
+  // R(i, j) = A(i, j) / sqrt(A(i, i)); diag(R) kept apart for the inversion
+  __shared__ double dR[kCholMaxB];
+  for (int i = threadIdx.x; i < nc; i += 256) dR[i] = sqrt(A[i][i]);
+  __syncthreads();
+  if (j < nc)
+    for (int i = ib; i <= j && i < nc; i += 4) A[i][j] /= dR[i];
+  __syncthreads();
+  // X = R^{-1} by right-looking back substitution of R X = I, bottom row
+  // first: R stays in the upper triangle of A, X(i, j) (i < j) is kept
+  // transposed in the lower triangle (A[j][i]) and X(i, i) in dX.
+  __shared__ double dX[kCholMaxB];
+  for (int i = threadIdx.x; i < nc; i += 256) dX[i] = 1.0;
+  if (j < nc)
+    for (int i = ib; i < j; i += 4) A[j][i] = 0.0;
+  __syncthreads();
+  for (int k = nc - 1; k >= 0; --k) {
+    // row k of X: B(k, :) / R(k, k)
+    for (int q = k + 1 + threadIdx.x; q < nc; q += 256) A[q][k] /= dR[k];
+    if (threadIdx.x == 0) dX[k] /= dR[k];
+    __syncthreads();
+    // B(p, q) -= R(p, k) X(k, q) for p < k, q >= k
+    for (int idx = threadIdx.x; idx < k * (nc - k); idx += 256) {
+      const int p = idx % k, q = k + idx / k;
+      const double xkq = q == k ? dX[k] : A[q][k];
+      if (q == p) continue;
+      A[q][p] -= A[p][k] * xkq;
+    }
+    __syncthreads();
+  }
+  if (j < nc)
+    for (int i = ib; i < nc; i += 4) c.X[(int64_t)j * nc + i] = i < j ? A[j][i] : (i == j ? dX[i] : 0.0);
+  if constexpr (PASS == 1) {
+    for (int i = threadIdx.x; i < nc; i += 256) c.d1[i] = dR[i];
+    if (threadIdx.x == 0) {
+      GemmTask k;
+      k.pad = 0;
+      k.A = c.S; k.a_rs = 1; k.a_cs = c.lds;     // Q1 = S_hat X
+      k.B = c.X; k.b_rs = 1; k.b_cs = nc;
+      k.C = c.Q1; k.c_rs = 1; k.c_cs = c.lds;
+      k.M = c.m; k.N = nc; k.K = nc; k.alpha = 1.0; k.beta = 0.0;
+      *T0 = k;
+      k.A = c.Q1; k.a_rs = c.lds; k.a_cs = 1;    // G2 = Q1^T Q1
+      k.B = c.Q1; k.b_rs = 1; k.b_cs = c.lds;
+      k.C = c.G; k.c_rs = 1; k.c_cs = nc;
+      k.M = nc; k.N = nc; k.K = c.m; k.alpha = 1.0; k.beta = 0.0;
+      *T1 = k;
+    }
+  } else {
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    const int g = a.nodes[t];
+    const NodeDesc& nd = a.desc[g];
+    NodeState& st = a.st[g];
+    const ProbDev& P = a.prob[nd.prob];
+    const double lev = (double)nd.level;
+    const double er = fmax(P.eps_r / lev, P.eps_floor), ea = P.eps_a / lev;
+    double mn = INFINITY, dev = 0.0;
+    for (int i = 0; i < nc; ++i) {
+      mn = fmin(mn, fabs(dR[i] * c.d1[i]));
+      dev = fmax(dev, fabs(dR[i] - 1.0));
+    }
+    const double rho = st.rho[side] < 0.0 ? fabs(dR[0] * c.d1[0]) : st.rho[side];
+    const double thr = fmax(ea, er * rho);
+    c.active = 0;
+    // decide only away from the threshold (rounding of either QR is ~1e-16
+    // of the block's norm, the thresholds ~1e-9 of it or more)
+    if (!(dev <= 0.1) || !(mn >= 1.5 * thr || mn < thr / 1.5)) return;   // Householder decides
+    st.rho[side] = rho;
+    st.run[side] = 0;
+    qt[t].active = 0;
+    if (mn < thr / 1.5) {   // an R-diagonal test passes: no basis growth
+      st.passed[side] = 1;
+      return;
+    }
+    double* Qd = tp(a, nd.Q[side]) + (int64_t)st.q[side] * nd.mcap;
+    st.q[side] += nc;
+    GemmTask k;   // Q(:, q:q+nc) = Q1 X2
+    k.pad = 0;
+    k.A = c.Q1; k.a_rs = 1; k.a_cs = c.lds;
+    k.B = c.X; k.b_rs = 1; k.b_cs = nc;
+    k.C = Qd; k.c_rs = 1; k.c_cs = nd.mcap;
+    k.M = c.m; k.N = nc; k.K = nc; k.alpha = 1.0; k.beta = 0.0;
+    *T0 = k;
+    kcount(a.kcnt, HSS_K_TEST_NORMS, 8.0 * 4.0 * nc * nc, 2.0 * nc * nc * nc);
+  }
 }
 
 // R-diagonal tests of eq. stopping_criteria after the QR of the projected
@@ -460,8 +618,20 @@ void launch_fnorm_test(const LevelArgs& a, int side, int32_t iter, int32_t mcap_
     launch_gemm(a.tasks + a.count, a.count, mcap_max, ncap, s, a.kcnt, qcap_max, a.gws, kGemmSplitElems);
   }
   prof_begin(s);
-  hipLaunchKernelGGL(k_fn_norms, dim3(a.count), dim3(NBN), 0, s, a, side, ts.qt);
+  hipLaunchKernelGGL(k_fn_norms, dim3(a.count), dim3(NBN), 0, s, a, side, ts.qt, ts.ct);
   prof_end(HSS_K_TEST_NORMS, s);
+  // Cholesky QR of the narrow blocks: decides the clearly failing tests
+  const int32_t nb = std::min(ncap, kCholMaxB);
+  launch_gemm(a.tasks, a.count, nb, nb, s, a.kcnt, mcap_max, a.gws, kGemmSplitElems);
+  prof_begin(s);
+  hipLaunchKernelGGL(k_cq_chol<1>, dim3(a.count), dim3(256), 0, s, a, side, ts.ct, ts.qt);
+  prof_end(HSS_K_TEST_NORMS, s);
+  launch_gemm(a.tasks, a.count, mcap_max, nb, s, a.kcnt);
+  launch_gemm(a.tasks + a.count, a.count, nb, nb, s, a.kcnt, mcap_max, a.gws, kGemmSplitElems);
+  prof_begin(s);
+  hipLaunchKernelGGL(k_cq_chol<2>, dim3(a.count), dim3(256), 0, s, a, side, ts.ct, ts.qt);
+  prof_end(HSS_K_TEST_NORMS, s);
+  launch_gemm(a.tasks, a.count, mcap_max, nb, s, a.kcnt);
   run_qrcp(ts.qt, a.count, ts.wk, nullptr, 0, ncap, mcap_max, ncap, ts.flag, ts.gt, mcap_max, s, a.kcnt, false);
   prof_begin(s);
   hipLaunchKernelGGL(k_fn_rtest, dim3((a.count + 127) / 128), dim3(128), 0, s, a, side, ts.qf);
