@@ -46,10 +46,10 @@ PEAK_HBM_GBS = 8000.0
 KCLASS_INFO = {
     "SAMPLE": ("k_sample_f64", "mfma"),
     "GEMM": ("k_gemm_grouped+k_gemm_splitk_sum", "mfma"),
-    "TEST_NORMS": ("k_fn_norms/k_fn_rtest", "hbm"),
+    "TEST_NORMS": ("k_fn_norms/k_cq_chol/k_fn_rtest", "hbm"),
     "QRCP_STEP": ("k_qrcp_step", "hbm"),
     "QRCP_WG": ("k_qrcp_wg", "hbm"),
-    "QFORM": ("k_qform", "hbm"),
+    "QFORM": ("k_qf_prep/k_qf_solve/k_qform", "hbm"),
     "GATHER": ("k_ls_gather/k_red_gather/k_fn_copy", "hbm"),
     "EXTRACT": ("k_extract_nodes", "hbm"),
     "TRSM": ("k_trsm_diag", "hbm"),

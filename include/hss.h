@@ -202,19 +202,31 @@ hss_status hss_get_info(const hss_matrix* h, hss_info* out);
  * (summed HIP-event time around each launch, only when the compression
  * ran with options.profile = 1, else 0) and the algorithmic bytes and
  * flops the launches had to move / perform by their definition:
- *   SAMPLE       2 n^2 c flops, 16 n c + 24 n bytes per c sampled columns
- *   GEMM         2 M N K flops, 8 (MK + KN + MN [+ MN if accumulating]) bytes
- *   TEST_QR      Householder QR of the projected block (m x b): 2 m b^2 flops
- *                (4 m b^2 when Q_k is formed), 8 m b (2 or 3) bytes
- *   QRCP_STEP    one pivot step on the (d-k) x (m-k-1) trailing panel:
- *                4 (d-k)(m-k-1) flops, 16 (d-k)(m-k-1) bytes
+ *   SAMPLE       k_sample_f64 / k_sample_lp: 2 n^2 c flops, 16 n c + 24 n bytes
+ *                per c sampled columns
+ *   SAMPLE_REDUCE  fixed-order sum of split-K sampling partials
+ *   EXTRACT      k_extract_nodes: 8 bytes per generated entry
  *   GATHER       copies of local samples / reduced random matrices: 16 bytes per entry
- *   EXTRACT      8 bytes per generated entry
- *   TRSM         diagonal blocks of the back substitution for E */
+ *   GEMM         k_gemm_grouped (+ its split-K sum): 2 M N K flops,
+ *                8 (MK + KN + MN [+ MN if accumulating]) bytes
+ *   TEST_NORMS   k_fn_norms, k_cq_chol, k_fn_rtest: F-norm tests of the
+ *                projected block (m x b, 16 m b bytes, 4 m b flops), its
+ *                Cholesky factors and the R-diagonal tests
+ *   QRCP_STEP    k_qrcp_step, one Householder step (pivoted for the ID, plain
+ *                for the stopping test) on the (d-k) x (m-k-1) trailing
+ *                panel: 16 (d-k)(m-k-1) bytes, 4 (d-k)(m-k-1) flops
+ *   QRCP_OTHER   plan, copy-in, liveness and finish kernels of the factorizations
+ *   TRSM         k_trsm_diag: diagonal blocks of the back substitution for E
+ *   MISC         per-level bookkeeping kernels
+ *   QRCP_WG      k_qrcp_wg: whole factorizations of small panels, per step as
+ *                QRCP_STEP
+ *   QFORM        k_qf_prep, k_qf_solve, k_qform: explicit Q_k of the stopping
+ *                test (compact WY form; its GEMMs count as GEMM) */
 enum {
   HSS_K_SAMPLE = 0, HSS_K_SAMPLE_REDUCE = 1, HSS_K_EXTRACT = 2, HSS_K_GATHER = 3, HSS_K_GEMM = 4,
-  HSS_K_TEST_QR = 5, HSS_K_QRCP_STEP = 6, HSS_K_QRCP_OTHER = 7, HSS_K_TRSM = 8, HSS_K_MISC = 9,
-  HSS_K_COUNT = 10
+  HSS_K_TEST_NORMS = 5, HSS_K_QRCP_STEP = 6, HSS_K_QRCP_OTHER = 7, HSS_K_TRSM = 8, HSS_K_MISC = 9,
+  HSS_K_QRCP_WG = 10, HSS_K_QFORM = 11,
+  HSS_K_COUNT = 12
 };
 typedef struct {
   int64_t launches;

@@ -64,8 +64,8 @@ class _KStats(C.Structure):
     _fields_ = [("launches", C.c_int64), ("ms", C.c_double), ("bytes", C.c_double), ("flops", C.c_double)]
 
 
-KCLASS = ["SAMPLE", "SAMPLE_REDUCE", "EXTRACT", "GATHER", "GEMM", "TEST_QR", "QRCP_STEP", "QRCP_OTHER",
-          "TRSM", "MISC"]
+KCLASS = ["SAMPLE", "SAMPLE_REDUCE", "EXTRACT", "GATHER", "GEMM", "TEST_NORMS", "QRCP_STEP", "QRCP_OTHER",
+          "TRSM", "MISC", "QRCP_WG", "QFORM"]
 
 
 class _NodeInfo(C.Structure):
