@@ -82,6 +82,33 @@ WORKLOADS = {
 }
 
 
+# HBM traffic of the dominant kernel, from two rocprofv3 --pmc passes
+# (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch, averaged over the
+# kernel's dispatches in one compression of the workload) scaled by what the
+# same counters read for a 1 GiB device copy (bench.py --copy-calibration).
+# The figure is only reported while the kernel's source file is the one the
+# counters were taken on (sha256); profiles/ holds the summaries.
+TRAFFIC = {
+    ("laplace-sphere-32768", "QRCP_STEP"): {
+        "source": "paper_1810_04125_amd/csrc/k_qrcp.hip",
+        "sha256": "d604cc7632350ade4cb677f7edd12c201e743f9b008813e894dd35d07c0f395a",
+        "fetch_kib": 8456.775, "write_kib": 13330.794,            # k_qrcp_step, 17376 dispatches
+        "fetch_scale": 1048576.0 / 524302.354, "write_scale": 1.0,  # 1 GiB copy: FETCH 524302 KiB, WRITE 1048576 KiB
+    },
+}
+
+
+def traffic_bytes(workload, cls):
+    import hashlib
+    t = TRAFFIC.get((workload, cls))
+    if not t:
+        return None
+    src = os.path.join(ROOT, t["source"])
+    if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != t["sha256"]:
+        return None
+    return 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
+
+
 def roofline(stats, precision="fp64"):
     name = max((k for k in stats if stats[k]["ms"] > 0), key=lambda k: stats[k]["ms"])
     s = stats[name]
@@ -366,6 +393,9 @@ def main():
         Hp, _ = hss.compress(gen, T, R, profile=True, **dict(kw, d0=(learned or {}).get("d0_predicted", W["d0"])))
         stats = Hp.kernel_stats()
         rl = roofline(stats, args.precision)
+        rl["traffic"] = traffic_bytes(args.workload, rl["class"])
+        rl["traffic_unit"] = "bytes per launch (HBM, measured)"
+        rl["algorithmic_bytes_per_launch"] = round(stats[rl["class"]]["bytes"] / max(1, rl["launches"]), 1)
         samp = stats["SAMPLE"]
         skern = "k_sample_f64" if args.precision == "fp64" else "k_sample_lp"
         speak = {"fp64": PEAK_FP64_TFLOPS, "fp32": PEAK_FP32_TFLOPS, "bf16x3": PEAK_BF16_TFLOPS}[args.precision]
