@@ -44,3 +44,19 @@ def test_tree_rejects_bad_input():
     bad[3, 1] = np.nan
     with pytest.raises(hss.HSSError):
         hss.Tree(10, 4, bad, "rcb")
+
+
+def test_bench_traffic_record_tracks_the_kernel_source(tmp_path, monkeypatch):
+    import bench
+    rec = dict(bench.TRAFFIC[("laplace-sphere-32768", "QRCP_STEP")])
+    src = tmp_path / "k.hip"
+    src.write_bytes(b"kernel v1")
+    import hashlib
+    rec.update(source=str(src), sha256=hashlib.sha256(b"kernel v1").hexdigest())
+    monkeypatch.setattr(bench, "TRAFFIC", {("w", "C"): rec})
+    monkeypatch.setattr(bench, "ROOT", "/")
+    want = 1024.0 * (rec["fetch_kib"] * rec["fetch_scale"] + rec["write_kib"] * rec["write_scale"])
+    assert bench.traffic_bytes("w", "C") == pytest.approx(want)
+    src.write_bytes(b"kernel v2")
+    assert bench.traffic_bytes("w", "C") is None
+    assert bench.traffic_bytes("other", "C") is None

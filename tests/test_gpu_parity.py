@@ -231,3 +231,36 @@ def test_full_size_bench_workload_properties():
     lap = Laplace(pts)
     ref = lap.entries(ot.perm[rows], ot.perm) @ Rh[:, :128]
     assert np.linalg.norm(S[rows] - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("family,n,leaf,dd", [("gauss", 2048, 256, 32), ("laplace", 2048, 128, 16)])
+def test_compress_inc_narrow_blocks_rounds(family, n, leaf, dd):
+    """Narrow increments: the stopping test's blocks run through the
+    Cholesky-QR decision (well-conditioned, clearly failing or passing) or
+    the Householder QR (near the threshold); the outcome must match the
+    oracle's Householder-only test round for round."""
+    _log("compress %s %d inc dd=%d" % (family, n, dd))
+    gen, T, ot, op = problem(family, n, leaf, seed=2 if family == "gauss" else 1)
+    R = inputs.gaussian_matrix(n, 1024, 0)
+    H, st = hss.compress(gen, T, dev_colmajor(R), rtol=1e-6, atol=1e-12, eta=0.1, strategy="inc_fnorm",
+                         d0=dd, delta_d=dd)
+    oh = ocompress(op, ot, R, 1e-6, 1e-12, "inc_fnorm", d0=dd, delta_d=dd, eta=0.1)
+    _compare(H, oh, ot, gen, op, T, 1e-6)
+    assert H.info()["rounds"] == oh.rounds
+    assert H.info()["d_final"] == oh.d
+
+
+def test_release_cache_between_compressions():
+    _log("release cache")
+    n = 2048
+    gen, T, ot, op = problem("laplace", n, 128, seed=1)
+    R = dev_colmajor(inputs.gaussian_matrix(n, 1024, 0))
+    kw = dict(rtol=1e-6, atol=1e-12, eta=0.1, strategy="inc_fnorm", d0=128, delta_d=64)
+    H1, _ = hss.compress(gen, T, R, **kw)
+    hss.release_cache()
+    H2, _ = hss.compress(gen, T, R, **kw)
+    H3, _ = hss.compress(gen, T, R, **kw)    # reuses the kept block
+    for H in (H2, H3):
+        assert H.info()["rounds"] == H1.info()["rounds"]
+        for t in (1, 2, T.num_nodes - 1):
+            assert np.array_equal(H.node(t, "ER"), H1.node(t, "ER"))
