@@ -627,7 +627,7 @@ void Job::run_level(int lev, int32_t ncap) {
     for (int s = 0; s < nsides; ++s) {
       launch_build_qrcp(a, s, hmt, qtasks_d, stream);
       run_qrcp(qtasks_d, a.count, qwork, L.wg_trsm, L.ntrsm, std::min(L.mcap, ncap), ncap, L.mcap, flags_d + 2,
-               tasks_d, L.mcap, stream, kcnt_d);
+               tasks_d, L.mcap, stream, kcnt_d, true, gemm_ws);
     }
   };
   if (strategy == HSS_DBL_HMT) {

@@ -141,6 +141,8 @@ struct QrcpTask {
   double hmt_mn;     // > 0: HMT factor with sqrt(hmt_mn); 0: plain threshold
   int32_t m, d, mcap, active;
   int32_t nopivot;   // 1: plain Householder QR (column k is the k-th pivot)
+  double* qrf = nullptr;     // workspace of the QR-first reduction of a tall panel (k_qrfirst.hip)
+  int64_t qrf_elems = 0;
 };
 
 // Explicit Q of a Householder QR done by run_qrcp in nopivot mode:
@@ -181,9 +183,13 @@ inline size_t qrcp_work_entries(int32_t max_tasks) { return (size_t)kQrcpTarget 
 // Factor the panels of `tasks` (dmax rows and at most ncols_max columns
 // each, by capacity): one workgroup per matrix for small panels, else one
 // launch per pivot step over a device-built work map.
-void run_qrcp(const QrcpTask* tasks, int32_t ntasks, const QrcpWork& wk, const int2* wg_trsm, int32_t ntrsm,
+void run_qrcp(QrcpTask* tasks, int32_t ntasks, const QrcpWork& wk, const int2* wg_trsm, int32_t ntrsm,
               int32_t kmax, int32_t dmax, int32_t ncols_max, int32_t* flag, GemmTask* gtasks, int32_t mcap_max,
-              hipStream_t s, unsigned long long* kcnt = nullptr, bool solve_e = true);
+              hipStream_t s, unsigned long long* kcnt = nullptr, bool solve_e = true, double* gws = nullptr);
+// Reduce tall ID panels (d >= 2 m) to their m x m triangle before the
+// pivoted steps (k_qrfirst.hip).
+void run_qr_first(QrcpTask* tasks, int32_t ntasks, int32_t dmax, int32_t mcap_max, int32_t* flag,
+                  GemmTask* gtasks, double* gws, hipStream_t s, unsigned long long* kcnt);
 void run_qform(QformTask* tasks, int32_t count, const int2* wg, int32_t nwg, int32_t cpw, int32_t ncmax,
                int32_t mmax, GemmTask* gt, double* gws, hipStream_t s, unsigned long long* kcnt);
 

@@ -688,6 +688,11 @@ __global__ void k_build_qrcp(LevelArgs a, int side, int hmt, QrcpTask* __restric
   q.d = P.d;
   q.mcap = nd.mcap;
   q.nopivot = 0;
+  // QR-first workspace: the rest of the node's wsB slot after the scratch
+  const int64_t slot = max((int64_t)nd.qcap * P.dcap, 16 + 2 * ((int64_t)nd.mcap + P.dcap));
+  const int64_t off = (16 + 3 * (int64_t)nd.mcap + 7) / 8 * 8;
+  q.qrf = slot > off ? q.scr + off : nullptr;
+  q.qrf_elems = slot > off ? slot - off : 0;
   out[t] = q;
 }
 

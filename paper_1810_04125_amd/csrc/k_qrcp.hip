@@ -423,9 +423,9 @@ QrcpPlan make_qrcp_plan(const std::vector<int32_t>& mcaps, int cpw) {
   return p;
 }
 
-void run_qrcp(const QrcpTask* tasks, int32_t ntasks, const QrcpWork& wk, const int2* wg_trsm, int32_t ntrsm,
+void run_qrcp(QrcpTask* tasks, int32_t ntasks, const QrcpWork& wk, const int2* wg_trsm, int32_t ntrsm,
               int32_t kmax, int32_t dmax, int32_t ncols_max, int32_t* flag, GemmTask* gtasks, int32_t mcap_max,
-              hipStream_t s, unsigned long long* kcnt, bool solve_e) {
+              hipStream_t s, unsigned long long* kcnt, bool solve_e, double* gws) {
   if (ntasks <= 0) return;
   if (ntasks > wk.max_tasks) throw Error(HSS_ERR_INTERNAL, "QRCP work map too small for the batch");
   const int nwg = kQrcpTarget + ntasks;
@@ -440,6 +440,7 @@ void run_qrcp(const QrcpTask* tasks, int32_t ntasks, const QrcpWork& wk, const i
     hipLaunchKernelGGL(k_qrcp_plan, dim3(1), dim3(QB), 0, s, tasks, ntasks, kQrcpTarget, wk.chunks, wk.meta);
     hipLaunchKernelGGL(k_qrcp_init, dim3(nwg), dim3(QB), 0, s, tasks, wk.chunks, wk.meta);
     prof_end(HSS_K_QRCP_OTHER, s);
+    if (solve_e && dmax >= 128) run_qr_first(tasks, ntasks, dmax, ncols_max, flag, gtasks, gws, s, kcnt);
   }
   // pivot steps: launched back to back in segments of 32 between liveness
   // polls; profiling times each segment as a whole

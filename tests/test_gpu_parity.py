@@ -264,3 +264,20 @@ def test_release_cache_between_compressions():
         assert H.info()["rounds"] == H1.info()["rounds"]
         for t in (1, 2, T.num_nodes - 1):
             assert np.array_equal(H.node(t, "ER"), H1.node(t, "ER"))
+
+
+@pytest.mark.parametrize("strategy", ["inc_fnorm", "dbl_fnorm"])
+def test_compress_large_first_block_tall_panels(strategy):
+    """A first block of 1024 columns: the IDs of the lower levels factor
+    tall panels (d >= 2 m), which are reduced to their m x m triangle by a
+    blocked Householder QR before the pivoted steps; ranks, rounds and the
+    error must match the oracle's direct QRCP."""
+    _log("compress laplace 4096 d0=1024 " + strategy)
+    n = 4096
+    gen, T, ot, op = problem("laplace", n, 128, seed=3)
+    R = inputs.gaussian_matrix(n, 2048, 0)
+    kw = dict(rtol=1e-6, atol=1e-12, eta=0.1, strategy=strategy, d0=1024, delta_d=64)
+    H, st = hss.compress(gen, T, dev_colmajor(R), **kw)
+    oh = ocompress(op, ot, R, 1e-6, 1e-12, strategy, d0=1024, delta_d=64, eta=0.1)
+    _compare(H, oh, ot, gen, op, T, 1e-6)
+    assert H.info()["rounds"] == oh.rounds
