@@ -69,6 +69,8 @@ __global__ __launch_bounds__(QRF_T) void k_qrf_panel(const QrcpTask* __restrict_
                                                     GemmTask* __restrict__ gt,
                                                     unsigned long long* __restrict__ kcnt) {
   __shared__ double red[QRF_T / 64];
+  __shared__ double part[QRF_T / 64][NBQ];
+  __shared__ double dots[NBQ];
   const QrcpTask& t = tasks[blockIdx.x];
   GemmTask* g = gt + blockIdx.x;
   if (threadIdx.x == 0) g->M = 0;
@@ -99,12 +101,38 @@ __global__ __launch_bounds__(QRF_T) void k_qrf_panel(const QrcpTask* __restrict_
       P.tau[k] = tk;
     }
     __syncthreads();
-    for (int j = k + 1 + wv; j < c1; j += NW) {
-      double* y = t.W + (int64_t)j * t.ldw;
-      double dot = 0.0;
-      for (int i = k + lane; i < d; i += 64) dot += vk[i] * y[i];
-      dot = qrf_wsum(dot) * tk;
-      for (int i = k + lane; i < d; i += 64) y[i] -= dot * vk[i];
+    // every thread owns rows k + tid, k + tid + QRF_T, ...: partial dot
+    // products with all the block's columns at once, one reduction, then
+    // each thread updates its own rows
+    double acc[NBQ];
+#pragma unroll
+    for (int jj = 0; jj < NBQ; ++jj) acc[jj] = 0.0;
+    for (int i = k + threadIdx.x; i < d; i += QRF_T) {
+      const double vi = vk[i];
+      const double* wi = t.W + i;
+#pragma unroll
+      for (int jj = 0; jj < NBQ; ++jj)
+        if (c + jj > k && c + jj < c1) acc[jj] += vi * wi[(int64_t)(c + jj) * t.ldw];
+    }
+#pragma unroll
+    for (int jj = 0; jj < NBQ; ++jj) {
+      const double v = qrf_wsum(acc[jj]);
+      if (lane == 0) part[wv][jj] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < NBQ) {
+      double sdot = 0.0;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) sdot += part[w][threadIdx.x];
+      dots[threadIdx.x] = sdot * tk;
+    }
+    __syncthreads();
+    for (int i = k + threadIdx.x; i < d; i += QRF_T) {
+      const double vi = vk[i];
+      double* wi = t.W + i;
+#pragma unroll
+      for (int jj = 0; jj < NBQ; ++jj)
+        if (c + jj > k && c + jj < c1) wi[(int64_t)(c + jj) * t.ldw] -= dots[jj] * vi;
     }
     __syncthreads();
   }
