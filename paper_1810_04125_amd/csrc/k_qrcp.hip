@@ -329,24 +329,39 @@ __global__ void k_qrcp_alive(const QrcpTask* __restrict__ tasks, int ntasks, int
 __global__ __launch_bounds__(QB) void k_qrcp_fin(const QrcpTask* __restrict__ tasks, int32_t* maxrank) {
   const QrcpTask& t = tasks[blockIdx.x];
   if (!t.active) return;
-  __shared__ int s_r;
+  __shared__ int cnt[QB];
   const int m = t.m, d = t.d;
   const int kmax = min(m, d);
-  if (threadIdx.x == 0) {
-    const QrcpCtl* c = ctl_of(t);
-    const int r = (kmax > 0 && c->done) ? c->rank : kmax;
+  const QrcpCtl* c = ctl_of(t);
+  const int r = (kmax > 0 && c->done) ? c->rank : kmax;
+  if (t.J) {
+    // the columns never pivoted, ascending, after the r pivots: each thread
+    // counts its contiguous share, an exclusive scan gives its offset
     const double* nfin = nrm_of(t, r);
-    int pos = r;
-    if (t.J) {
-      for (int j = 0; j < m; ++j)
-        if (nfin[j] >= 0.0) t.J[pos++] = j;
+    const int per = (m + QB - 1) / QB;
+    const int j0 = min(m, (int)threadIdx.x * per), j1 = min(m, j0 + per);
+    int n = 0;
+    for (int j = j0; j < j1; ++j) n += nfin[j] >= 0.0;
+    cnt[threadIdx.x] = n;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int acc = 0;
+      for (int i = 0; i < QB; ++i) {
+        const int v = cnt[i];
+        cnt[i] = acc;
+        acc += v;
+      }
     }
+    __syncthreads();
+    int pos = r + cnt[threadIdx.x];
+    for (int j = j0; j < j1; ++j)
+      if (nfin[j] >= 0.0) t.J[pos++] = j;
+  }
+  if (threadIdx.x == 0) {
     *t.rank_out = r;
     atomicMax(maxrank, r);
-    s_r = r;
   }
   __syncthreads();
-  const int r = s_r;
   const int nrest = m - r;
   if (!t.E) return;
   for (int64_t idx = threadIdx.x; idx < (int64_t)r * nrest; idx += QB) {
