@@ -91,12 +91,11 @@ WORKLOADS = {
 TRAFFIC = {
     ("laplace-sphere-32768", "QRCP_STEP"): {
         "source": "paper_1810_04125_amd/csrc/k_qrcp.hip",
-        "sha256": "d604cc7632350ade4cb677f7edd12c201e743f9b008813e894dd35d07c0f395a",
-        "fetch_kib": 8456.775, "write_kib": 13330.794,            # k_qrcp_step, 17376 dispatches
-        "fetch_scale": 1048576.0 / 524302.354, "write_scale": 1.0,  # 1 GiB copy: FETCH 524302 KiB, WRITE 1048576 KiB
+        "sha256": "622253a06d0f47a34e2cb13f1ae1d40c858cd99b4179465a69d171aebd39125f",
+        "fetch_kib": 8461.892, "write_kib": 13331.466,            # k_qrcp_step, 17376 dispatches
+        "fetch_scale": 1048576.0 / 524302.208, "write_scale": 1.0,  # 1 GiB copy: FETCH 524302 KiB, WRITE 1048576 KiB
     },
 }
-
 
 def traffic_bytes(workload, cls):
     import hashlib
