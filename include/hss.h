@@ -312,7 +312,7 @@ hss_status hss_release_cache(void);
  * d0 and the final d.  A small network fed with features that are known
  * before any sampling (family, kernel parameter, n, tree level, node size,
  * tolerance) predicts per-level node ranks and the final d, so d0 can start
- * close to it.  The stopping tests of the compression stay the judge: a low
+ * close to it.  The stopping tests of the compression still decide: a low
  * prediction only costs extra rounds, a high one extra sample columns.
  *
  * The network is a fully connected ReLU net in FP32: layer l maps

@@ -11,7 +11,7 @@ Weights are stored row-major, W_l of shape (out, in).  Backward is the
 chain rule written out layer by layer; the tests pin it by finite
 differences.  The network is not part of the paper: it is the learned
 predictor the HIP library adds on top of the paper's adaptive method, which
-stays the judge of every node.
+still decides every node.
 """
 from __future__ import annotations
 

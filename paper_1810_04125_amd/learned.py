@@ -16,7 +16,7 @@ from what is known before sampling, so d0 can start close to it:
     level 0 (root) row: log2(d_final) of an incrementing run with d0 = delta_d
   network: 8 -> 128 -> 128 -> 128 -> 2, ReLU, FP32 (hss_mlp_* kernels)
 
-The compression's stopping tests stay the judge of every node: a low
+The compression's stopping tests still decide every node: a low
 prediction costs extra rounds, a high one extra sample columns, neither
 changes the accuracy guarantee.
 

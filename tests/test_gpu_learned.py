@@ -1,6 +1,6 @@
 """Learned d0 on the GPU: the predictor's forward pass against the FP64
 oracle on the committed weights, and the gain it brings to the adaptive
-compression with the stopping tests as judge.
+compression, with the stopping tests still deciding every node.
 
 The network's quality has no value in the paper to compare with; these
 tests check that a predicted start keeps the accuracy of the adaptive run
