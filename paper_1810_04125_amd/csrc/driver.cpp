@@ -478,7 +478,7 @@ void Job::setup(int32_t count, const hss_generator* gens, const hss_tree* const*
     L.wg_trsm = (int2*)dalloc(sizeof(int2) * std::max<size_t>(qp.trsm.size(), 1));
     HSS_HIP_CHECK(hipMemcpy(L.wg_trsm, qp.trsm.data(), sizeof(int2) * qp.trsm.size(), hipMemcpyHostToDevice));
   }
-  flags_d = (int32_t*)dalloc(sizeof(int32_t) * 4);
+  flags_d = (int32_t*)dalloc(sizeof(int32_t) * 8);
   kcnt_d = (unsigned long long*)dalloc(sizeof(unsigned long long) * 2 * HSS_K_COUNT);
   HSS_HIP_CHECK(hipMemset(kcnt_d, 0, sizeof(unsigned long long) * 2 * HSS_K_COUNT));
   nodes_d = (int32_t*)dalloc(sizeof(int32_t) * gnodes);
@@ -505,7 +505,7 @@ void Job::setup(int32_t count, const hss_generator* gens, const hss_tree* const*
   HSS_HIP_CHECK(hipMemcpy(nodes_d, all.data(), sizeof(int32_t) * all.size(), hipMemcpyHostToDevice));
   HSS_HIP_CHECK(hipMemcpy(desc_d, desc.data(), sizeof(NodeDesc) * gnodes, hipMemcpyHostToDevice));
   HSS_HIP_CHECK(hipMemsetAsync(st_d, 0, sizeof(NodeState) * gnodes, stream));
-  HSS_HIP_CHECK(hipMemsetAsync(flags_d, 0, sizeof(int32_t) * 4, stream));
+  HSS_HIP_CHECK(hipMemsetAsync(flags_d, 0, sizeof(int32_t) * 8, stream));
   // per-problem generator data
   for (auto& P : probs) {
     GenDev& g = P.dev.gen;
@@ -626,7 +626,7 @@ void Job::run_level(int lev, int32_t ncap) {
   auto id_phase = [&](int hmt) {
     for (int s = 0; s < nsides; ++s) {
       launch_build_qrcp(a, s, hmt, qtasks_d, stream);
-      run_qrcp(qtasks_d, a.count, qwork, L.wg_trsm, L.ntrsm, std::min(L.mcap, ncap), ncap, L.mcap, flags_d + 2,
+      run_qrcp(qtasks_d, a.count, qwork, L.wg_trsm, L.ntrsm, std::min(L.mcap, ncap), ncap, L.mcap, flags_d + 4,
                tasks_d, L.mcap, stream, kcnt_d, true, gemm_ws);
     }
   };

@@ -182,12 +182,17 @@ struct QrcpWork {
 inline size_t qrcp_work_entries(int32_t max_tasks) { return (size_t)kQrcpTarget + (size_t)std::max(max_tasks, 1); }
 // Factor the panels of `tasks` (dmax rows and at most ncols_max columns
 // each, by capacity): one workgroup per matrix for small panels, else one
-// launch per pivot step over a device-built work map.
+// launch per pivot step over a device-built work map.  `flag` points at
+// two int32 of device scratch.
 void run_qrcp(QrcpTask* tasks, int32_t ntasks, const QrcpWork& wk, const int2* wg_trsm, int32_t ntrsm,
               int32_t kmax, int32_t dmax, int32_t ncols_max, int32_t* flag, GemmTask* gtasks, int32_t mcap_max,
               hipStream_t s, unsigned long long* kcnt = nullptr, bool solve_e = true, double* gws = nullptr);
 // Reduce tall ID panels (d >= 2 m) to their m x m triangle before the
-// pivoted steps (k_qrfirst.hip).
+// pivoted steps (k_qrfirst.hip), when the rows this takes out of every
+// pivot step, summed over the tall panels, reach kQrFirstMinCells: below
+// that the steps are bound by launch latency rather than by their
+// traffic, and the reduction's own launches would not pay.
+constexpr int64_t kQrFirstMinCells = int64_t(2) << 20;
 void run_qr_first(QrcpTask* tasks, int32_t ntasks, int32_t dmax, int32_t mcap_max, int32_t* flag,
                   GemmTask* gtasks, double* gws, hipStream_t s, unsigned long long* kcnt);
 void run_qform(QformTask* tasks, int32_t count, const int2* wg, int32_t nwg, int32_t cpw, int32_t ncmax,

@@ -56,10 +56,16 @@ __device__ __forceinline__ double qrf_wsum(double v) {
 }
 }  // namespace
 
-// largest m among the tall panels
+// out[0]: the largest m among the tall panels; out[1]: the cells the
+// reduction takes out of the first pivot step, (d - m) m summed over them,
+// in units of 1024
 __global__ void k_qrf_scan(const QrcpTask* __restrict__ tasks, int ntasks, int32_t* __restrict__ out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < ntasks && qrf_tall(tasks[i])) atomicMax(out, tasks[i].m);
+  if (i < ntasks && qrf_tall(tasks[i])) {
+    const QrcpTask& t = tasks[i];
+    atomicMax(out, t.m);
+    atomicAdd(out + 1, (int32_t)(((int64_t)(t.d - t.m) * t.m) >> 10));
+  }
 }
 
 // Householder factorization of columns [c, c1) over rows c..d-1, one
@@ -255,12 +261,13 @@ __global__ __launch_bounds__(256) void k_qrf_finish(QrcpTask* __restrict__ tasks
 void run_qr_first(QrcpTask* tasks, int32_t ntasks, int32_t dmax, int32_t mcap_max, int32_t* flag,
                   GemmTask* gtasks, double* gws, hipStream_t s, unsigned long long* kcnt) {
   if (ntasks <= 0) return;
-  int32_t mtall = 0;
-  HSS_HIP_CHECK(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
+  int32_t scan[2] = {0, 0};
+  HSS_HIP_CHECK(hipMemsetAsync(flag, 0, 2 * sizeof(int32_t), s));
   hipLaunchKernelGGL(k_qrf_scan, dim3((ntasks + 127) / 128), dim3(128), 0, s, tasks, ntasks, flag);
-  HSS_HIP_CHECK(hipMemcpyAsync(&mtall, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HSS_HIP_CHECK(hipMemcpyAsync(scan, flag, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HSS_HIP_CHECK(hipStreamSynchronize(s));
-  if (mtall <= 0) return;
+  const int32_t mtall = scan[0];
+  if (mtall <= 0 || ((int64_t)scan[1] << 10) < kQrFirstMinCells) return;
   const int64_t split_ws = gws ? kGemmSplitElems : 0;
   for (int c = 0; c < mtall; c += NBQ) {
     prof_begin(s);
