@@ -5,8 +5,9 @@
  * Mary, Rouet and Li, "Matrix-free construction of HSS representation
  * using adaptive randomized sampling" (arXiv 1810.04125):
  *   - random sampling S^r = A R, S^c = A^T R and element extraction
- *     A(I,J) (Sec. 2.2 eq. sample_off_diag; Sec. 4 partially matrix-free
- *     interface), here matrix-free with entries generated on the GPU;
+ *     A(I,J) (Sec. 2.2 eq. sample_off_diag; Sec. 4.1 partially matrix-free
+ *     interface): entries generated on the GPU for the built-in operator
+ *     families, or caller routines for both (HSS_FAM_CALLBACK);
  *   - bottom-up interpolative decompositions of the local samples
  *     (eqs. ID, QRCPSr; Alg. 1 and 2);
  *   - the adaptive driver (Alg. 3) with the doubling (Alg. 4, with the
@@ -46,6 +47,7 @@ typedef enum {
   HSS_ERR_INVALID_ARG = -1,
   HSS_ERR_OUT_OF_MEMORY = -2,
   HSS_ERR_DEVICE = -3,                 /* a HIP runtime call failed */
+  HSS_ERR_CALLBACK = -4,               /* a caller routine of HSS_FAM_CALLBACK returned non-zero */
   HSS_ERR_NONFINITE = -5,              /* a non-finite sample or entry was met */
   HSS_ERR_INTERNAL = -6
 } hss_status;
@@ -55,8 +57,48 @@ typedef enum {
   HSS_FAM_TOEPLITZ = 0, /* symmetric Toeplitz: t(0)=pi^2/(6h^2), t(k)=(-1)^k/(k^2 h^2) */
   HSS_FAM_LAPLACE = 1,  /* 1/(4 pi |x_i-x_j|) for i != j, `diag` on the diagonal */
   HSS_FAM_GAUSS = 2,    /* exp(-|x_i-x_j|^2/(2 sigma^2)) + diag * delta_ij */
-  HSS_FAM_DENSE = 3     /* explicit n x n matrix in device memory (read from HBM) */
+  HSS_FAM_DENSE = 3,    /* explicit n x n matrix in device memory (read from HBM) */
+  HSS_FAM_CALLBACK = 4  /* caller routines for the products and the entries (below) */
 } hss_family;
+
+/* Partially matrix-free operator (Sec. 4.1): the method needs only the
+ * products with random blocks and selected sub-blocks of A, so a caller
+ * with a fast product (sparse, low-rank, FFT-based, another hierarchical
+ * matrix) supplies two routines instead of the entries.
+ *
+ * Both routines work in the PERMUTED order of the tree (A_hat(i, j) =
+ * a(perm[i], perm[j])), on device memory of the current device, with
+ * column-major blocks.  They are called from the thread that called the
+ * library, with `stream` the stream of the call: they may enqueue their
+ * work asynchronously on it (the library orders its own work behind
+ * theirs on that stream) or finish it before they return.  A non-zero
+ * return aborts the call with HSS_ERR_CALLBACK; nothing they wrote is
+ * used.  `ctx` is the generator's ctx, passed through.
+ *
+ * hss_sample_fn: Sr = A_hat R and Sc = A_hat^T R for the n x ncols block
+ *   R (leading dimension ldr); Sr and Sc have leading dimension lds.
+ *   Either output may be NULL and is then not wanted (Sc is always NULL
+ *   when the generator is symmetric).  Called once per sampling step with
+ *   the new columns only.
+ *
+ * hss_extract_fn: out_k(a, b) = A_hat(I_k[a], J_k[b]) for every block k
+ *   of `blocks` (a host array of nblocks entries, valid during the call).
+ *   The blocks of one call are all the sub-blocks one tree level needs in
+ *   a sampling round (the diagonal blocks D of its leaves and the
+ *   couplings B12, B21 of its nodes whose children have just compressed),
+ *   gathered so that the caller can serve them together (Sec. 4.2:
+ *   extraction synchronized per level). */
+typedef struct {
+  int32_t nI, nJ;
+  const int64_t* I;   /* device, nI permuted row positions */
+  const int64_t* J;   /* device, nJ permuted column positions */
+  double* out;        /* device, nI x nJ, column-major */
+  int64_t ldo;        /* leading dimension of out, >= max(nI, 1) */
+} hss_block;
+
+typedef int32_t (*hss_sample_fn)(void* ctx, int64_t n, int32_t ncols, const double* R, int64_t ldr,
+                                 double* Sr, double* Sc, int64_t lds, void* stream);
+typedef int32_t (*hss_extract_fn)(void* ctx, int32_t nblocks, const hss_block* blocks, void* stream);
 
 /* Sample-growth strategy and stopping test (Alg. 3-5). */
 typedef enum {
@@ -78,7 +120,10 @@ typedef enum {
  *   laplace : points (n x 3, xyz interleaved, row-major), diag (A_ii)
  *   gauss   : points, sigma, diag
  *   dense   : dense (column-major, leading dimension ld >= n); symmetric
- *             tells whether A = A^T may be assumed (then S^c = S^r). */
+ *             tells whether A = A^T may be assumed (then S^c = S^r)
+ *   callback: sample, extract, ctx; symmetric as for dense.  The
+ *             routines receive PERMUTED positions, so the tree's
+ *             permutation is the caller's to apply. */
 typedef struct {
   int32_t family;
   int32_t symmetric;
@@ -89,6 +134,9 @@ typedef struct {
   const double* points;
   const double* dense;
   int64_t ld;
+  hss_sample_fn sample;
+  hss_extract_fn extract;
+  void* ctx;
 } hss_generator;
 
 /* Cluster tree (Sec. 2.1): binary, numbered level by level top-down from
@@ -180,6 +228,9 @@ hss_status hss_matvec(const hss_matrix* h, int32_t nrhs, const double* X, int64_
 
 /* ||A - H||_F / ||A||_F over all n^2 entries (the error measure of
  * table HMT), in FP64, by column blocks of H and generated blocks of A.
+ * gen may be NULL for the built-in families (the compression keeps their
+ * tables); for HSS_FAM_CALLBACK it must describe the compressed operator,
+ * whose sample routine then yields the column blocks A_hat [e_j ...].
  * Host-synchronous. */
 hss_status hss_rel_error(const hss_matrix* h, const hss_generator* gen, double* rel_err);
 
@@ -270,13 +321,15 @@ hss_status hss_copy_node(const hss_matrix* h, int32_t node, int32_t what, void* 
  * op = identity (transpose = 0, S^r) or transpose (1, S^c) (Sec. 2.2
  * eq. sample_off_diag).  perm: device int64[n].  R, S: device, n x ncols,
  * column-major.  precision: hss_precision.  Host-synchronous (the call
- * returns when S is complete). */
+ * returns when S is complete).  HSS_FAM_CALLBACK forwards to gen->sample
+ * (FP64 only; perm is not used, the routine works in permuted order). */
 hss_status hss_sample(const hss_generator* gen, const int64_t* perm, int32_t ncols,
                       const double* R, int64_t ldr, double* S, int64_t lds, int32_t transpose,
                       int32_t precision, void* stream);
 
 /* out = A_hat(I, J), nI x nJ column-major (ldo >= nI); I, J device int64
- * permuted indices (Sec. 4: B = A(J^r, J^c) is a sub-block of A). */
+ * permuted indices (Sec. 4.1: B = A(J^r, J^c) is a sub-block of A).
+ * HSS_FAM_CALLBACK forwards one block to gen->extract (perm not used). */
 hss_status hss_extract(const hss_generator* gen, const int64_t* perm, int32_t nI,
                        const int64_t* I, int32_t nJ, const int64_t* J, double* out,
                        int64_t ldo, void* stream);

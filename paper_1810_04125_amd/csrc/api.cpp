@@ -57,13 +57,14 @@ struct GenHolder {
   }
   GenHolder(const hss_generator& gen, const int64_t* perm, hipStream_t s) {
     if (!perm) throw Error(HSS_ERR_INVALID_ARG, "perm must be a device int64[n] array");
-    if (gen.n < 1 || gen.family < 0 || gen.family > 3) throw Error(HSS_ERR_INVALID_ARG, "bad generator");
+    if (gen.n < 1 || !(gen_formula(gen.family) || gen.family == HSS_FAM_DENSE))
+      throw Error(HSS_ERR_INVALID_ARG, "bad generator");
     std::memset(&g, 0, sizeof(g));
     g.family = gen.family;
     g.n = gen.n;
     g.diag = gen.diag;
     g.perm = perm;
-    g.symmetric = gen.family != HSS_FAM_DENSE || gen.symmetric;
+    g.symmetric = gen_symmetric(gen);
     if (gen.family == HSS_FAM_TOEPLITZ) {
       if (!(gen.h > 0.0)) throw Error(HSS_ERR_INVALID_ARG, "toeplitz needs h > 0");
       double* t = (double*)alloc(sizeof(double) * gen.n);
@@ -432,12 +433,16 @@ hss_status hss_matvec(const hss_matrix* h, int32_t nrhs, const double* X, int64_
 hss_status hss_rel_error(const hss_matrix* h, const hss_generator* gen, double* rel_err) {
   return guarded([&]() -> hss_status {
     if (!h || !rel_err) throw Error(HSS_ERR_INVALID_ARG, "NULL argument");
-    (void)gen;  // the compressed job keeps its own generator tables
     const Job& J = *h->job;
     const Problem& P = J.probs[h->k];
+    // the built-in families: the job keeps its own generator tables
+    const bool cb = P.gen.family == HSS_FAM_CALLBACK;
+    if (cb && (!gen || gen->family != HSS_FAM_CALLBACK || !gen->sample || gen->n != P.n))
+      throw Error(HSS_ERR_INVALID_ARG, "a caller operator needs its generator (same n, sample routine)");
     hipStream_t s = J.stream;
     const int32_t nb = (int32_t)std::min<int64_t>(P.n, 256);
     DevBuf xp(sizeof(double) * P.n * nb), yp(sizeof(double) * P.n * nb);
+    DevBuf ac(cb ? sizeof(double) * P.n * nb : 8);
     DevBuf xh(sizeof(double) * J.mvtot * nb), yh(sizeof(double) * J.mvtot * nb);
     DevBuf ws(sizeof(double) * J.mvwstot * nb);
     DevBuf acc(sizeof(double) * 2 * 1024);
@@ -446,7 +451,13 @@ hss_status hss_rel_error(const hss_matrix* h, const hss_generator* gen, double* 
       const int32_t w = (int32_t)std::min<int64_t>(nb, P.n - j0);
       launch_eye_block(xp.as<double>(), P.n, j0, w, s);
       matvec_permuted(h, w, xp.as<double>(), yp.as<double>(), xh.as<double>(), yh.as<double>(), ws.as<double>(), s);
-      launch_err_block(P.dev.gen, yp.as<double>(), P.n, j0, w, acc.as<double>(), s);
+      if (cb) {   // A_hat [e_j0 ... e_j0+w-1] from the caller's product
+        const int32_t rc = gen->sample(gen->ctx, P.n, w, xp.as<double>(), P.n, ac.as<double>(), nullptr, P.n, s);
+        if (rc != 0) throw Error(HSS_ERR_CALLBACK, "sample routine returned " + std::to_string(rc));
+        launch_err_cols(ac.as<double>(), P.n, yp.as<double>(), P.n, P.n, w, acc.as<double>(), s);
+      } else {
+        launch_err_block(P.dev.gen, yp.as<double>(), P.n, j0, w, acc.as<double>(), s);
+      }
     }
     std::vector<double> hacc(2 * 1024);
     HSS_HIP_CHECK(hipMemcpyAsync(hacc.data(), acc.p, sizeof(double) * 2 * 1024, hipMemcpyDeviceToHost, s));
@@ -467,9 +478,17 @@ hss_status hss_sample(const hss_generator* gen, const int64_t* perm, int32_t nco
     if (!gen || !R || !S || ncols < 0) throw Error(HSS_ERR_INVALID_ARG, "bad arguments");
     if (ldr < gen->n || lds < gen->n) throw Error(HSS_ERR_INVALID_ARG, "leading dimension < n");
     if (precision < 0 || precision > 2) throw Error(HSS_ERR_INVALID_ARG, "bad precision");
-    if (precision != HSS_SAMPLE_FP64 && gen->family == HSS_FAM_DENSE)
+    if (precision != HSS_SAMPLE_FP64 && !gen_formula(gen->family))
       throw Error(HSS_ERR_INVALID_ARG, "reduced-precision sampling needs a generated family");
     hipStream_t s = (hipStream_t)stream;
+    if (gen->family == HSS_FAM_CALLBACK) {
+      if (!gen->sample) throw Error(HSS_ERR_INVALID_ARG, "callback family needs a sample routine");
+      const int32_t rc = gen->sample(gen->ctx, gen->n, ncols, R, ldr, transpose ? nullptr : S,
+                                     transpose ? S : nullptr, lds, s);
+      if (rc != 0) throw Error(HSS_ERR_CALLBACK, "sample routine returned " + std::to_string(rc));
+      HSS_HIP_CHECK(hipStreamSynchronize(s));
+      return HSS_OK;
+    }
     GenHolder G(*gen, perm, s);
     const size_t pe = sample_partial_elems(gen->n, ncols);
     DevBuf part(sizeof(double) * std::max<size_t>(pe, 1));
@@ -486,6 +505,16 @@ hss_status hss_extract(const hss_generator* gen, const int64_t* perm, int32_t nI
     if (!gen || nI < 0 || nJ < 0 || (nI && !I) || (nJ && !Jx) || !out || ldo < std::max(nI, 1))
       throw Error(HSS_ERR_INVALID_ARG, "bad arguments");
     hipStream_t s = (hipStream_t)stream;
+    if (gen->family == HSS_FAM_CALLBACK) {
+      if (!gen->extract) throw Error(HSS_ERR_INVALID_ARG, "callback family needs an extract routine");
+      if ((int64_t)nI * nJ > 0) {
+        const hss_block b{nI, nJ, I, Jx, out, ldo};
+        const int32_t rc = gen->extract(gen->ctx, 1, &b, s);
+        if (rc != 0) throw Error(HSS_ERR_CALLBACK, "extract routine returned " + std::to_string(rc));
+      }
+      HSS_HIP_CHECK(hipStreamSynchronize(s));
+      return HSS_OK;
+    }
     GenHolder G(*gen, perm, s);
     launch_extract(G.g, nI, I, nJ, Jx, out, ldo, s);
     HSS_HIP_CHECK(hipGetLastError());

@@ -254,7 +254,9 @@ static void validate(const hss_generator& g, const hss_tree* t, const hss_option
   if (!t || !t->perm || !t->lo || !t->hi || !t->left || !t->right || !t->parent || !t->level)
     throw Error(HSS_ERR_INVALID_ARG, who + "incomplete tree");
   if (g.n != t->n || g.n < 1) throw Error(HSS_ERR_INVALID_ARG, who + "generator n != tree n");
-  if (g.family < 0 || g.family > 3) throw Error(HSS_ERR_INVALID_ARG, who + "unknown family");
+  if (g.family < 0 || g.family > HSS_FAM_CALLBACK) throw Error(HSS_ERR_INVALID_ARG, who + "unknown family");
+  if (g.family == HSS_FAM_CALLBACK && (!g.sample || !g.extract))
+    throw Error(HSS_ERR_INVALID_ARG, who + "callback family needs sample and extract routines");
   if ((g.family == HSS_FAM_LAPLACE || g.family == HSS_FAM_GAUSS) && !g.points)
     throw Error(HSS_ERR_INVALID_ARG, who + "kernel family needs points");
   if (g.family == HSS_FAM_DENSE && (!g.dense || g.ld < g.n))
@@ -270,7 +272,7 @@ static void validate(const hss_generator& g, const hss_tree* t, const hss_option
   if (!o.R || o.ldr < g.n || o.ncols_R < std::min<int64_t>(o.d_max, g.n))
     throw Error(HSS_ERR_INVALID_ARG, who + "R must be n x ncols_R with ncols_R >= min(d_max, n)");
   if (o.sample_precision < 0 || o.sample_precision > 2) throw Error(HSS_ERR_INVALID_ARG, who + "bad precision");
-  if (o.sample_precision != HSS_SAMPLE_FP64 && g.family == HSS_FAM_DENSE)
+  if (o.sample_precision != HSS_SAMPLE_FP64 && !gen_formula(g.family))
     throw Error(HSS_ERR_INVALID_ARG, who + "reduced-precision sampling needs a generated family");
   // tree structure
   const int32_t nn = t->num_nodes;
@@ -295,7 +297,7 @@ static void validate(const hss_generator& g, const hss_tree* t, const hss_option
 size_t Job::estimate_bytes(const hss_generator& g, const hss_tree* t, const hss_options& o) {
   const int32_t nn = t->num_nodes;
   const int64_t dc = std::min<int64_t>(o.d_max, t->n);
-  const bool sym = g.family != HSS_FAM_DENSE || g.symmetric;
+  const bool sym = gen_symmetric(g);
   const int nsides = sym ? 1 : 2;
   std::vector<int64_t> mcap(nn), rcap(nn);
   int64_t dbl = 0, ints = 0;
@@ -352,7 +354,7 @@ void Job::setup(int32_t count, const hss_generator* gens, const hss_tree* const*
     P.opt = opts[k];
     P.n = t->n;
     P.nn = t->num_nodes;
-    P.sym = (gens[k].family != HSS_FAM_DENSE) || gens[k].symmetric ? 1 : 0;
+    P.sym = gen_symmetric(gens[k]) ? 1 : 0;
     P.dcap = (int32_t)std::min<int64_t>(opts[k].d_max, t->n);
     P.node0 = gnodes;
     P.perm.assign(t->perm, t->perm + t->n);
@@ -532,6 +534,15 @@ void Job::setup(int32_t count, const hss_generator* gens, const hss_tree* const*
       g.dense = P.gen.dense;
       g.ld = P.gen.ld;
     }
+    if (P.gen.family == HSS_FAM_CALLBACK) {
+      // permuted positions 0..n-1: the row and column lists of the leaves'
+      // diagonal blocks handed to the extraction routine
+      std::vector<int64_t> pos(P.n);
+      for (int64_t i = 0; i < P.n; ++i) pos[i] = i;
+      P.pos_d = (int64_t*)dalloc(sizeof(int64_t) * P.n);
+      HSS_HIP_CHECK(hipMemcpy(P.pos_d, pos.data(), sizeof(int64_t) * P.n, hipMemcpyHostToDevice));
+      has_callback = true;
+    }
     if (P.opt.sample_precision != HSS_SAMPLE_FP64) {
       // reduced-precision sampling skips the leaf diagonal blocks
       std::vector<int32_t> llo(P.n), lhi(P.n);
@@ -589,6 +600,18 @@ void Job::sample_end() {
 
 void Job::sample(Problem& P, int32_t c0, int32_t ncols) {
   if (ncols <= 0) return;
+  if (P.gen.family == HSS_FAM_CALLBACK) {
+    double* S0 = tpool + P.sglob[0] + (int64_t)c0 * P.n;
+    double* S1 = P.sym ? nullptr : tpool + P.sglob[1] + (int64_t)c0 * P.n;
+    const int32_t rc = P.gen.sample(P.gen.ctx, P.n, ncols, P.opt.R + (int64_t)c0 * P.opt.ldr, P.opt.ldr, S0, S1,
+                                    P.n, stream);
+    if (rc != 0) throw Error(HSS_ERR_CALLBACK, "sample routine returned " + std::to_string(rc));
+    launch_check_finite(S0, P.n, ncols, P.n, flags_d, stream);
+    if (S1) launch_check_finite(S1, P.n, ncols, P.n, flags_d, stream);
+    require_finite("the sample routine");
+    sample_flops += 2.0 * (double)P.n * (double)P.n * ncols * (P.sym ? 1 : 2);
+    return;
+  }
   const int prec = P.opt.sample_precision;
   for (int s = 0; s < (P.sym ? 1 : 2); ++s) {
     launch_sample(P.dev.gen, s, prec, P.opt.R + (int64_t)c0 * P.opt.ldr, P.opt.ldr,
@@ -597,6 +620,63 @@ void Job::sample(Problem& P, int32_t c0, int32_t ncols) {
     host_bytes[HSS_K_SAMPLE] += 16.0 * (double)P.n * ncols + 24.0 * (double)P.n;
   }
   sample_flops += 2.0 * (double)P.n * (double)P.n * ncols * (P.sym ? 1 : 2);
+}
+
+// The sub-blocks of A that the nodes of one level need this round (leaf
+// diagonal blocks, couplings of nodes whose children just compressed), for
+// the problems with caller routines: one extraction call per problem and
+// level with all of its blocks.  Block sizes are ranks, decided on the
+// device, so the node states come to the host first.
+void Job::extract_callbacks(int lev) {
+  const LevelInfo& L = levels[lev];
+  st_h.resize(desc.size());
+  HSS_HIP_CHECK(hipMemcpyAsync(st_h.data(), st_d, sizeof(NodeState) * desc.size(), hipMemcpyDeviceToHost, stream));
+  HSS_HIP_CHECK(hipStreamSynchronize(stream));
+  std::vector<std::vector<hss_block>> blocks(probs.size());
+  for (int32_t g : L.nodes) {
+    const NodeDesc& nd = desc[g];
+    const Problem& P = probs[nd.prob];
+    if (P.gen.family != HSS_FAM_CALLBACK || !st_h[g].extract) continue;
+    std::vector<hss_block>& B = blocks[nd.prob];
+    if (nd.leaf) {
+      const int32_t m = nd.hi - nd.lo;
+      B.push_back(hss_block{m, m, P.pos_d + nd.lo, P.pos_d + nd.lo, dpool + nd.D, m});
+    } else {
+      const NodeDesc& L1 = desc[nd.left];
+      const NodeDesc& L2 = desc[nd.right];
+      const NodeState& s1 = st_h[nd.left];
+      const NodeState& s2 = st_h[nd.right];
+      // B12 = A(left.I^r, right.I^c), B21 = A(right.I^r, left.I^c)
+      if (s1.rank[0] > 0 && s2.rank[1] > 0)
+        B.push_back(hss_block{s1.rank[0], s2.rank[1], lpool + L1.I[0], lpool + L2.I[1], tpool + nd.B12,
+                              (int64_t)nd.b12ld});
+      if (s2.rank[0] > 0 && s1.rank[1] > 0)
+        B.push_back(hss_block{s2.rank[0], s1.rank[1], lpool + L2.I[0], lpool + L1.I[1], tpool + nd.B21,
+                              (int64_t)nd.b21ld});
+    }
+  }
+  for (size_t k = 0; k < probs.size(); ++k) {
+    const std::vector<hss_block>& B = blocks[k];
+    if (B.empty()) continue;
+    const hss_generator& G = probs[k].gen;
+    const int32_t rc = G.extract(G.ctx, (int32_t)B.size(), B.data(), stream);
+    if (rc != 0) throw Error(HSS_ERR_CALLBACK, "extract routine returned " + std::to_string(rc));
+    for (const hss_block& b : B) {
+      launch_check_finite(b.out, b.nI, b.nJ, b.ldo, flags_d, stream);
+      host_bytes[HSS_K_EXTRACT] += 8.0 * (double)b.nI * b.nJ;
+    }
+    require_finite("the extract routine");
+  }
+}
+
+// Caller data is checked before any kernel uses it: a non-finite value
+// ends the call here.
+void Job::require_finite(const char* who) {
+  int32_t bad = 0;
+  HSS_HIP_CHECK(hipGetLastError());
+  HSS_HIP_CHECK(hipMemcpyAsync(&bad, flags_d, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+  HSS_HIP_CHECK(hipStreamSynchronize(stream));
+  if (bad) throw Error(HSS_ERR_NONFINITE, std::string("non-finite value from ") + who);
 }
 
 void Job::run_level(int lev, int32_t ncap) {
@@ -621,6 +701,7 @@ void Job::run_level(int lev, int32_t ncap) {
   const int32_t nc = std::min(ncap, L.dcap);
   HSS_HIP_CHECK(hipMemsetAsync(flags_d + 1, 0, sizeof(int32_t), stream));
   launch_plan(a, stream);
+  if (has_callback) extract_callbacks(lev);
   launch_extract_nodes(a, stream);
   for (int s = 0; s < nsides; ++s) launch_local_samples(a, s, L.mcap, L.rcap, nc, stream);
   auto id_phase = [&](int hmt) {

@@ -26,6 +26,7 @@ struct Problem {
   hss_status status = HSS_OK;
   std::vector<int32_t> sched;
   int32_t* sched_d = nullptr;
+  int64_t* pos_d = nullptr;   // caller operators: device 0..n-1 (leaf index lists)
 };
 
 struct LevelInfo {
@@ -49,6 +50,7 @@ struct Job {
   int32_t maxlevel = 0;
   int32_t strategy = 0;
   bool all_sym = true;
+  bool has_callback = false;   // some problem has caller routines (HSS_FAM_CALLBACK)
   int32_t max_block = 0;   // widest sampling block so far
   hipStream_t stream = nullptr;
   std::vector<void*> allocs;       // live until the job is destroyed
@@ -98,6 +100,8 @@ struct Job {
   void sample_begin();
   void sample_end();
   void run_level(int lev, int32_t ncap);
+  void extract_callbacks(int lev);
+  void require_finite(const char* who);
 };
 
 }  // namespace hss

@@ -36,6 +36,16 @@ struct GenDev {
   int32_t pad;
 };
 
+// The generated families are symmetric; dense and caller operators say
+// whether they are.
+inline bool gen_symmetric(const hss_generator& g) {
+  return (g.family != HSS_FAM_DENSE && g.family != HSS_FAM_CALLBACK) || g.symmetric != 0;
+}
+// Families whose entries the kernels compute from a formula.
+inline bool gen_formula(int32_t family) {
+  return family == HSS_FAM_TOEPLITZ || family == HSS_FAM_LAPLACE || family == HSS_FAM_GAUSS;
+}
+
 // Static per-node description.  Offsets are in elements of the pool of the
 // matching type (double pool, int32 pool, int64 pool).  Side 0 is the row
 // side (S^r, U, J^r, I^r, R^c = U^T R), side 1 the column side (S^c, V,
@@ -336,6 +346,9 @@ struct Copy2D {
 void launch_copy2d(const Copy2D* tasks, int32_t count, hipStream_t s);
 void launch_err_block(const GenDev& g, const double* Hc, int64_t ldh, int64_t j0, int32_t nb,
                       double* accum, hipStream_t s);
+void launch_err_cols(const double* Ac, int64_t lda, const double* Hc, int64_t ldh, int64_t n, int32_t nb,
+                     double* accum, hipStream_t s);
+void launch_check_finite(const double* p, int64_t rows, int32_t cols, int64_t ld, int32_t* flag, hipStream_t s);
 
 // ---- learned predictor network (k_mlp.hip) ----
 struct MlpShape {

@@ -220,6 +220,59 @@ __global__ __launch_bounds__(256) void k_err_block(GenDev g, const double* __res
   }
 }
 
+// Same sums with the column block of A given explicitly (n x nb, ld lda):
+// the columns a caller's sample routine returned for A_hat [e_j0 ...].
+__global__ __launch_bounds__(256) void k_err_cols(const double* __restrict__ Ac, int64_t lda,
+                                                 const double* __restrict__ Hc, int64_t ldh, int64_t n,
+                                                 int32_t nb, double* __restrict__ accum) {
+  __shared__ double r1[4], r2[4];
+  const int64_t tot = n * nb;
+  double e = 0.0, a2 = 0.0;
+  for (int64_t idx = blockIdx.x * 256 + threadIdx.x; idx < tot; idx += (int64_t)gridDim.x * 256) {
+    const int64_t i = idx % n, c = idx / n;
+    const double av = Ac[c * lda + i];
+    const double df = av - Hc[c * ldh + i];
+    e += df * df;
+    a2 += av * av;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    e += __shfl_xor(e, o, 64);
+    a2 += __shfl_xor(a2, o, 64);
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) { r1[w] = e; r2[w] = a2; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    accum[2 * blockIdx.x] += r1[0] + r1[1] + r1[2] + r1[3];
+    accum[2 * blockIdx.x + 1] += r2[0] + r2[1] + r2[2] + r2[3];
+  }
+}
+
+// flag |= 1 if any entry of the rows x cols block (ld ld) is not finite
+__global__ __launch_bounds__(256) void k_check_finite(const double* __restrict__ p, int64_t rows, int32_t cols,
+                                                     int64_t ld, int32_t* __restrict__ flag) {
+  const int64_t tot = rows * cols;
+  int bad = 0;
+  for (int64_t idx = blockIdx.x * 256 + threadIdx.x; idx < tot; idx += (int64_t)gridDim.x * 256) {
+    const int64_t i = idx % rows, c = idx / rows;
+    bad |= !isfinite(p[c * ld + i]);
+  }
+  if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
+}
+
+void launch_check_finite(const double* p, int64_t rows, int32_t cols, int64_t ld, int32_t* flag, hipStream_t s) {
+  const int64_t tot = rows * cols;
+  if (tot <= 0) return;
+  const unsigned g = (unsigned)std::min<int64_t>(1024, (tot + 255) / 256);
+  hipLaunchKernelGGL(k_check_finite, dim3(g), dim3(256), 0, s, p, rows, cols, ld, flag);
+}
+
+void launch_err_cols(const double* Ac, int64_t lda, const double* Hc, int64_t ldh, int64_t n, int32_t nb,
+                     double* accum, hipStream_t s) {
+  hipLaunchKernelGGL(k_err_cols, dim3(1024), dim3(256), 0, s, Ac, lda, Hc, ldh, n, nb, accum);
+}
+
 __global__ void k_eye_block(double* __restrict__ X, int64_t n, int64_t j0, int32_t nb) {
   const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (idx >= n * nb) return;

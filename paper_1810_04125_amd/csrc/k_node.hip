@@ -140,6 +140,7 @@ __global__ __launch_bounds__(NB) void k_extract_nodes(LevelArgs a) {
   if (!st.extract) return;
   const ProbDev& P = a.prob[nd.prob];
   const GenDev& gen = P.gen;
+  if (gen.family == HSS_FAM_CALLBACK) return;   // served by the caller's extraction routine
   int bad = 0;
   if (nd.leaf) {
     const int m = nd.hi - nd.lo;

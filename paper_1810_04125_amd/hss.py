@@ -17,7 +17,7 @@ import numpy as np
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libhss.so")
 
-FAMILY = {"toeplitz": 0, "laplace": 1, "gauss": 2, "dense": 3}
+FAMILY = {"toeplitz": 0, "laplace": 1, "gauss": 2, "dense": 3, "callback": 4}
 STRATEGY = {"dbl_fnorm": 0, "inc_fnorm": 1, "dbl_hmt": 2}
 PRECISION = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 TREE_METHOD = {"bisect": 0, "rcb": 1, "kd": 2}
@@ -35,7 +35,18 @@ class HSSError(RuntimeError):
 class _Gen(C.Structure):
     _fields_ = [("family", C.c_int32), ("symmetric", C.c_int32), ("n", C.c_int64),
                 ("h", C.c_double), ("sigma", C.c_double), ("diag", C.c_double),
-                ("points", C.c_void_p), ("dense", C.c_void_p), ("ld", C.c_int64)]
+                ("points", C.c_void_p), ("dense", C.c_void_p), ("ld", C.c_int64),
+                ("sample", C.c_void_p), ("extract", C.c_void_p), ("ctx", C.c_void_p)]
+
+
+class _Block(C.Structure):
+    _fields_ = [("nI", C.c_int32), ("nJ", C.c_int32), ("I", C.c_void_p), ("J", C.c_void_p),
+                ("out", C.c_void_p), ("ldo", C.c_int64)]
+
+
+_SAMPLE_FN = C.CFUNCTYPE(C.c_int32, C.c_void_p, C.c_int64, C.c_int32, C.c_void_p, C.c_int64, C.c_void_p,
+                         C.c_void_p, C.c_int64, C.c_void_p)
+_EXTRACT_FN = C.CFUNCTYPE(C.c_int32, C.c_void_p, C.c_int32, C.POINTER(_Block), C.c_void_p)
 
 
 class _Tree(C.Structure):
@@ -132,9 +143,18 @@ def lib():
     return L
 
 
+ERR_CALLBACK = -4
+_callback_exc = []   # exception raised inside a caller routine, re-raised by _check
+
+
 def _check(code):
     if code < 0:
-        raise HSSError(code, lib().hss_last_error().decode())
+        err = HSSError(code, lib().hss_last_error().decode())
+        cause = _callback_exc.pop() if (code == ERR_CALLBACK and _callback_exc) else None
+        _callback_exc.clear()
+        if cause is not None:
+            raise err from cause
+        raise err
     return code
 
 
@@ -212,6 +232,7 @@ class Generator:
     points: object = None    # (n, 3) float64 CUDA tensor, original order
     dense: object = None     # (n, n) float64 CUDA tensor, column-major
     symmetric: bool = True
+    routines: object = None  # callback family: (sample C function, extract C function)
 
     def _c(self):
         g = _Gen()
@@ -223,6 +244,9 @@ class Generator:
         if self.dense is not None:
             g.ld = _colmajor(self.dense, "dense")
             g.dense = self.dense.data_ptr()
+        if self.routines is not None:
+            g.sample = C.cast(self.routines[0], C.c_void_p).value
+            g.extract = C.cast(self.routines[1], C.c_void_p).value
         return g
 
 
@@ -240,6 +264,75 @@ def gauss(points, sigma=0.5, diag=1e-2):
 
 def dense(A, symmetric=False):
     return Generator("dense", A.shape[0], dense=colmajor(A), symmetric=symmetric)
+
+
+class _DevArray:
+    """A block of library device memory, seen by torch.as_tensor without a copy."""
+
+    def __init__(self, ptr, shape, strides, typestr):
+        self.__cuda_array_interface__ = {"shape": shape, "strides": strides, "typestr": typestr,
+                                         "data": (ptr, False), "version": 2}
+
+
+def _device_view(ptr, rows, cols, ld, dtype="f8"):
+    """(rows, cols) column-major view (leading dimension ld) of device memory at ptr;
+    cols=None gives a 1-D view of rows entries."""
+    import torch
+    tdt = torch.float64 if dtype == "f8" else torch.int64
+    if not ptr or rows == 0 or cols == 0:
+        return torch.empty((rows,) if cols is None else (rows, cols), dtype=tdt, device="cuda")
+    if cols is None:
+        return torch.as_tensor(_DevArray(ptr, (rows,), (8,), "<" + dtype), device="cuda")
+    return torch.as_tensor(_DevArray(ptr, (rows, cols), (8, 8 * ld), "<" + dtype), device="cuda")
+
+
+def _on_stream(stream, fn):
+    import torch
+    if stream and stream != torch.cuda.current_stream().cuda_stream:
+        with torch.cuda.stream(torch.cuda.ExternalStream(stream)):
+            return fn()
+    return fn()
+
+
+def callback(n, sample, extract, symmetric=False):
+    """Partially matrix-free operator (hss_generator with HSS_FAM_CALLBACK; Sec. 4.1).
+
+    sample(R, Sr, Sc): R is an (n, k) float64 CUDA tensor; write A_hat @ R into
+        Sr and A_hat.T @ R into Sc (each may be None: not wanted).
+    extract(blocks): blocks is a list of (I, J, out), I and J int64 CUDA tensors
+        of permuted positions and out a (len(I), len(J)) float64 tensor; write
+        A_hat[I][:, J] into out.  One call serves all blocks of a tree level.
+    A_hat is the operator in the tree's permuted order.  The tensors are views of
+    library memory, valid during the call only; the routines run with the
+    library's stream as torch's current stream.  An exception inside a routine
+    aborts the library call, which raises HSSError from it."""
+
+    def c_sample(ctx, nn, k, R, ldr, Sr, Sc, lds, stream):
+        try:
+            Rt = _device_view(R, nn, k, ldr)
+            St = _device_view(Sr, nn, k, lds) if Sr else None
+            Ct = _device_view(Sc, nn, k, lds) if Sc else None
+            _on_stream(stream, lambda: sample(Rt, St, Ct))
+            return 0
+        except BaseException as e:   # noqa: BLE001  (handed back through the C call)
+            _callback_exc.append(e)
+            return 1
+
+    def c_extract(ctx, nb, blocks, stream):
+        try:
+            bl = []
+            for i in range(nb):
+                b = blocks[i]
+                bl.append((_device_view(b.I, b.nI, None, 0, "i8"), _device_view(b.J, b.nJ, None, 0, "i8"),
+                           _device_view(b.out, b.nI, b.nJ, b.ldo)))
+            _on_stream(stream, lambda: extract(bl))
+            return 0
+        except BaseException as e:   # noqa: BLE001
+            _callback_exc.append(e)
+            return 1
+
+    return Generator("callback", n, symmetric=symmetric,
+                     routines=(_SAMPLE_FN(c_sample), _EXTRACT_FN(c_extract)))
 
 
 # --------------------------------------------------------------------------- compression
@@ -318,7 +411,9 @@ class HSSMatrix:
 
     def rel_error(self) -> float:
         e = C.c_double()
-        _check(lib().hss_rel_error(self._h, None, C.byref(e)))
+        gen = self._keep[0]
+        g = C.byref(gen._c()) if gen.family == "callback" else None
+        _check(lib().hss_rel_error(self._h, g, C.byref(e)))
         return e.value
 
 

@@ -60,3 +60,33 @@ def test_bench_traffic_record_tracks_the_kernel_source(tmp_path, monkeypatch):
     src.write_bytes(b"kernel v2")
     assert bench.traffic_bytes("w", "C") is None
     assert bench.traffic_bytes("other", "C") is None
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """Every ctypes mirror in the binding has the size and field offsets of its C struct."""
+    import ctypes as C
+    import shutil
+    import subprocess
+
+    from paper_1810_04125_amd import hss as H
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    pairs = {"hss_generator": H._Gen, "hss_block": H._Block, "hss_tree": H._Tree, "hss_options": H._Opt,
+             "hss_info": H._Info, "hss_kernel_stats": H._KStats, "hss_node_info": H._NodeInfo,
+             "hss_mlp": H._Mlp}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "hss.h"', "int main(void) {"]
+    for cname, cls in pairs.items():
+        lines.append('printf("%s %%zu\\n", sizeof(%s));' % (cname, cname))
+        for f, _ in cls._fields_:
+            lines.append('printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (cname, f, cname, f))
+    lines += ["return 0;", "}"]
+    (tmp_path / "layout.c").write_text("\n".join(lines) + "\n")
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run(["gcc", "-std=c99", "-I", inc, "-o", str(tmp_path / "layout"), str(tmp_path / "layout.c")],
+                   check=True)
+    got = dict(l.split() for l in subprocess.run([str(tmp_path / "layout")], check=True, capture_output=True,
+                                                 text=True).stdout.splitlines())
+    for cname, cls in pairs.items():
+        assert int(got[cname]) == C.sizeof(cls), cname
+        for f, _ in cls._fields_:
+            assert int(got[cname + "." + f]) == getattr(cls, f).offset, cname + "." + f
