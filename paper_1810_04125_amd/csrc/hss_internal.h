@@ -208,6 +208,22 @@ void run_qr_first(QrcpTask* tasks, int32_t ntasks, int32_t dmax, int32_t mcap_ma
 void run_qform(QformTask* tasks, int32_t count, const int2* wg, int32_t nwg, int32_t cpw, int32_t ncmax,
                int32_t mmax, GemmTask* gt, double* gws, hipStream_t s, unsigned long long* kcnt);
 
+// ------------------------------------------------------------------ global views
+// Device pointers read from task structures are generic (flat) to the
+// compiler, and a flat access is counted both as a vector-memory and as an
+// LDS operation: every wait for an LDS result then also waits for all flat
+// loads in flight, which serializes loops that mix the two.  Accesses
+// through these views are global-memory instructions instead.
+#define HSS_GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ const HSS_GLOBAL T* gview(const T* p) {
+  return (const HSS_GLOBAL T*)p;
+}
+template <class T>
+__device__ __forceinline__ HSS_GLOBAL T* gview_w(T* p) {
+  return (HSS_GLOBAL T*)p;
+}
+
 // ------------------------------------------------------------------ profiling
 // Launch counts and (in profile mode) HIP-event time per kernel class; the
 // algorithmic bytes / flops are accumulated on the device in kcnt[2 * class

@@ -67,24 +67,38 @@ __global__ __launch_bounds__(256) void k_gemm_grouped(const GemmTask* __restrict
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
 
+  // Operand elements of a K tile, loaded without branches from clamped
+  // indices: the column indices of a gathered A as one batch of loads, then
+  // all values as another; the elements outside the operands are recorded
+  // in a bit mask and written to LDS as 0.
+  const HSS_GLOBAL double* gA = gview(t.A);
+  const HSS_GLOBAL double* gB = gview(t.B);
+  const HSS_GLOBAL int32_t* gcols = t.a_cols ? gview(t.a_cols) : nullptr;
   double ra[GPT], rb[GPT];
+  uint32_t valid = 0;
   auto load = [&](int k0) {
+    int64_t col[GPT];
+#pragma unroll
+    for (int e = 0; e < GPT; ++e) {
+      int k, i;
+      gemm_coords(t, threadIdx.x + 256 * e, true, k, i);
+      const int gk = min(k0 + k, ke - 1);
+      col[e] = gcols ? (int64_t)gcols[gk] : (int64_t)gk;
+    }
+    valid = 0;
 #pragma unroll
     for (int e = 0; e < GPT; ++e) {
       const int idx = threadIdx.x + 256 * e;
       int k, i;
       gemm_coords(t, idx, true, k, i);
       const int64_t gi = i0 + i, gk = k0 + k;
-      double av = 0.0;
-      if (gi < t.M && gk < ke) {
-        const int64_t col = t.a_cols ? (int64_t)t.a_cols[gk] : gk;
-        av = t.A[gi * t.a_rs + col * t.a_cs];
-      }
-      ra[e] = av;
+      ra[e] = gA[min(gi, (int64_t)t.M - 1) * t.a_rs + col[e] * t.a_cs];
+      valid |= (uint32_t)(gi < t.M && gk < ke) << e;
       int kk, j;
       gemm_coords(t, idx, false, kk, j);
       const int64_t gj = j0 + j, gkb = k0 + kk;
-      rb[e] = (gj < t.N && gkb < ke) ? t.B[gkb * t.b_rs + gj * t.b_cs] : 0.0;
+      rb[e] = gB[min(gkb, (int64_t)ke - 1) * t.b_rs + min(gj, (int64_t)t.N - 1) * t.b_cs];
+      valid |= (uint32_t)(gj < t.N && gkb < ke) << (GPT + e);
     }
   };
   if (kb < ke) load(kb);
@@ -94,9 +108,9 @@ __global__ __launch_bounds__(256) void k_gemm_grouped(const GemmTask* __restrict
       const int idx = threadIdx.x + 256 * e;
       int k, x;
       gemm_coords(t, idx, true, k, x);
-      As[k][x] = ra[e];
+      As[k][x] = (valid >> e) & 1u ? ra[e] : 0.0;
       gemm_coords(t, idx, false, k, x);
-      Bs[k][x] = rb[e];
+      Bs[k][x] = (valid >> (GPT + e)) & 1u ? rb[e] : 0.0;
     }
     __syncthreads();
     if (k0 + GK < ke) load(k0 + GK);
@@ -136,7 +150,7 @@ __global__ __launch_bounds__(256) void k_gemm_grouped(const GemmTask* __restrict
         const int64_t gi = i0 + wr + a * 16 + 4 * v + (lane >> 4);
         const int64_t gj = j0 + wc + b * 16 + (lane & 15);
         if (gi >= t.M || gj >= t.N) continue;
-        double* c = t.C + gi * t.c_rs + gj * t.c_cs;
+        HSS_GLOBAL double* c = gview_w(t.C + gi * t.c_rs + gj * t.c_cs);
         const double val = t.alpha * acc[a][b][v];
         *c = (t.beta == 0.0) ? val : val + t.beta * (*c);
       }
@@ -157,7 +171,7 @@ __global__ __launch_bounds__(256) void k_gemm_splitk_sum(const GemmTask* __restr
     if (gi >= t.M || gj >= t.N) continue;
     double sum = 0.0;
     for (int ks = 0; ks < ksplit; ++ks) sum += part[ks * stride + tile + e];
-    double* cp = t.C + gi * t.c_rs + gj * t.c_cs;
+    HSS_GLOBAL double* cp = gview_w(t.C + gi * t.c_rs + gj * t.c_cs);
     const double val = t.alpha * sum;
     *cp = (t.beta == 0.0) ? val : val + t.beta * (*cp);
   }

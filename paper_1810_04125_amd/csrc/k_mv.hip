@@ -303,18 +303,38 @@ void launch_extract(const GenDev& g, int32_t nI, const int64_t* I, int32_t nJ, c
                      out, ldo);
 }
 
-__global__ void k_copy2d(const Copy2D* __restrict__ tasks) {
+// Block copies: blockIdx.x selects the block, the gridDim.y workgroups of
+// a block share its elements, and every thread loads 8 elements before it
+// stores them.
+__global__ __launch_bounds__(256) void k_copy2d(const Copy2D* __restrict__ tasks) {
+  constexpr int U = 8;
   const Copy2D t = tasks[blockIdx.x];
-  const int64_t tot = (int64_t)t.rows * t.cols;
-  for (int64_t idx = threadIdx.x; idx < tot; idx += blockDim.x) {
-    const int64_t i = idx % t.rows, j = idx / t.rows;
-    t.dst[j * t.ldd + i] = t.src[j * t.lds + i];
+  const int tot = t.rows * t.cols;
+  const int stride = 256 * gridDim.y;
+  const HSS_GLOBAL double* src = gview(t.src);
+  HSS_GLOBAL double* dst = gview_w(t.dst);
+  for (int base = threadIdx.x + blockIdx.y * 256; base < tot; base += stride * U) {
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int idx = min(base + u * stride, tot - 1);
+      const int i = idx % t.rows, j = idx / t.rows;
+      v[u] = src[(int64_t)j * t.lds + i];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int idx = base + u * stride;
+      if (idx < tot) {
+        const int i = idx % t.rows, j = idx / t.rows;
+        dst[(int64_t)j * t.ldd + i] = v[u];
+      }
+    }
   }
 }
 
 void launch_copy2d(const Copy2D* tasks, int32_t count, hipStream_t s) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(k_copy2d, dim3(count), dim3(256), 0, s, tasks);
+  hipLaunchKernelGGL(k_copy2d, dim3(count, 8), dim3(256), 0, s, tasks);
 }
 
 void launch_err_block(const GenDev& g, const double* Hc, int64_t ldh, int64_t j0, int32_t nb,

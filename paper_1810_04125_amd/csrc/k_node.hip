@@ -64,6 +64,35 @@ __device__ double block_sum_n(double v, double* red) {
 #define CHUNKED_FOR(idx, total) \
   for (int64_t idx = threadIdx.x + (int64_t)blockIdx.y * NB; idx < (total); idx += (int64_t)NB * gridDim.y)
 
+// Copy loops of the per-node kernels: the node's elements [0, total) are
+// spread over the gridDim.y workgroups of the node, and every thread loads
+// CU elements (addresses from `at`, which maps an element index to its
+// source and destination) before it stores any, so that the loads of a
+// thread are in flight together.
+struct CopyAt {
+  const HSS_GLOBAL double* src;
+  HSS_GLOBAL double* dst;
+};
+constexpr int CU = 8;
+
+template <class At>
+__device__ __forceinline__ void copy_elems(int total, At at) {
+  const int stride = NB * gridDim.y;
+  for (int base = threadIdx.x + blockIdx.y * NB; base < total; base += stride * CU) {
+    double v[CU];
+    HSS_GLOBAL double* dst[CU];
+#pragma unroll
+    for (int u = 0; u < CU; ++u) {
+      const CopyAt p = at(min(base + u * stride, total - 1));
+      v[u] = *p.src;
+      dst[u] = p.dst;
+    }
+#pragma unroll
+    for (int u = 0; u < CU; ++u)
+      if (base + u * stride < total) *dst[u] = v[u];
+  }
+}
+
 static dim3 node_grid(int count) {
   int g = (1024 + count - 1) / count;
   g = g < 1 ? 1 : (g > 64 ? 64 : g);
@@ -218,10 +247,10 @@ __global__ __launch_bounds__(NB) void k_ls_gather(LevelArgs a, int side) {
   if (threadIdx.x == 0 && blockIdx.y == 0) kcount(a.kcnt, HSS_K_GATHER, 16.0 * m * nc, 0.0);
   if (nd.leaf) {
     const double* Sg = ctp(a, P.sglob[side]);
-    CHUNKED_FOR(idx, (int64_t)m * nc) {
-      const int i = (int)(idx % m), c = (int)(idx / m);
-      S[(int64_t)i * dcap + c0 + c] = Sg[(int64_t)(c0 + c) * P.n + nd.lo + i];
-    }
+    copy_elems(m * nc, [&](int idx) {
+      const int i = idx % m, c = idx / m;
+      return CopyAt{gview(Sg + (int64_t)(c0 + c) * P.n + nd.lo + i), gview_w(S + (int64_t)i * dcap + c0 + c)};
+    });
     if (threadIdx.x == 0 && blockIdx.y == 0 && !P.gen.offdiag) {  // off-diagonal samples need no D R
       GemmTask k;
       k.A = cdp(a, nd.D);
@@ -247,11 +276,13 @@ __global__ __launch_bounds__(NB) void k_ls_gather(LevelArgs a, int side) {
   const int32_t* J2 = a.ipool + Rn.J[side];
   const double* S1 = ctp(a, L.S[side]);
   const double* S2 = ctp(a, Rn.S[side]);
-  CHUNKED_FOR(idx, (int64_t)m * nc) {
-    const int c = (int)(idx % nc), i = (int)(idx / nc);
-    const double v = i < r1 ? S1[(int64_t)J1[i] * dcap + c0 + c] : S2[(int64_t)J2[i - r1] * dcap + c0 + c];
-    S[(int64_t)i * dcap + c0 + c] = v;
-  }
+  const HSS_GLOBAL int32_t* gJ1 = gview(J1);
+  const HSS_GLOBAL int32_t* gJ2 = gview(J2);
+  copy_elems(m * nc, [&](int idx) {
+    const int c = idx % nc, i = idx / nc;
+    const double* src = i < r1 ? S1 + (int64_t)gJ1[i] * dcap : S2 + (int64_t)gJ2[max(i - r1, 0)] * dcap;
+    return CopyAt{gview(src + c0 + c), gview_w(S + (int64_t)i * dcap + c0 + c)};
+  });
   if (threadIdx.x == 0 && blockIdx.y == 0) {
     GemmTask k;
     k.b_rs = dcap; k.b_cs = 1; k.c_rs = dcap; k.c_cs = 1; k.N = nc; k.pad = 0;
@@ -336,10 +367,10 @@ __global__ __launch_bounds__(NB) void k_fn_copy(LevelArgs a, int side, int iter)
   if (first && threadIdx.x == 0) kcount(a.kcnt, HSS_K_GATHER, 16.0 * m * nc, 0.0);
   const double* S = ctp(a, nd.S[side]);
   double* Sh = a.wsA + nd.ws;
-  CHUNKED_FOR(idx, (int64_t)m * nc) {
-    const int i = (int)(idx % m), c = (int)(idx / m);
-    Sh[(int64_t)c * nd.mcap + i] = S[(int64_t)i * dcap + c0 + c];
-  }
+  copy_elems(m * nc, [&](int idx) {
+    const int i = idx % m, c = idx / m;
+    return CopyAt{gview(S + (int64_t)i * dcap + c0 + c), gview_w(Sh + (int64_t)c * nd.mcap + i)};
+  });
   if (first && threadIdx.x == 0) {
     const double* Q = ctp(a, nd.Q[side]);
     double* W = a.wsB + nd.wsq;
@@ -384,17 +415,29 @@ __global__ __launch_bounds__(NBN) void k_fn_norms(LevelArgs a, int side, QrcpTas
   const double er = fmax(P.eps_r / lev, P.eps_floor), ea = P.eps_a / lev;
   const double* S = ctp(a, nd.S[side]);
   double* Sh = a.wsA + nd.ws;
-  // S rows are contiguous over the columns, Sh columns over the rows
+  // S rows are contiguous over the columns, Sh columns over the rows; each
+  // thread loads NU entries before it adds them
+  constexpr int NU = 8;
   double p1 = 0.0, p2 = 0.0;
-  for (int64_t idx = threadIdx.x; idx < (int64_t)m * nc; idx += NBN) {
-    const int c = (int)(idx % nc), i = (int)(idx / nc);
-    const double x = S[(int64_t)i * dcap + c0 + c];
-    p1 += x * x;
-  }
-  for (int64_t idx = threadIdx.x; idx < (int64_t)m * nc; idx += NBN) {
-    const int i = (int)(idx % m), c = (int)(idx / m);
-    const double y = Sh[(int64_t)c * ld + i];
-    p2 += y * y;
+  const int tot = m * nc;
+  const HSS_GLOBAL double* gS = gview(S);
+  const HSS_GLOBAL double* gSh = gview(Sh);
+  for (int base = threadIdx.x; base < tot; base += NBN * NU) {
+    double x[NU], y[NU];
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      const int idx = min(base + u * NBN, tot - 1);
+      const int c = idx % nc, i = idx / nc;
+      x[u] = gS[(int64_t)i * dcap + c0 + c];
+      const int i2 = idx % m, c2 = idx / m;
+      y[u] = gSh[(int64_t)c2 * ld + i2];
+    }
+#pragma unroll
+    for (int u = 0; u < NU; ++u)
+      if (base + u * NBN < tot) {
+        p1 += x[u] * x[u];
+        p2 += y[u] * y[u];
+      }
   }
   const double nS = sqrt(block_sum_n<NBN>(p1, red));
   const double nSh = sqrt(block_sum_n<NBN>(p2, red));
@@ -460,8 +503,16 @@ __global__ __launch_bounds__(256) void k_cq_chol(LevelArgs a, int side, CholTask
   const int nc = c.nc;
   // thread (row group ib, column j): 4 row groups x 64 columns
   const int j = threadIdx.x & 63, ib = threadIdx.x >> 6;
-  if (j < nc)
-    for (int i = ib; i < nc; i += 4) A[i][j] = c.G[(int64_t)j * nc + i];
+  constexpr int RPT = kCholMaxB / 4;   // rows per thread
+  {
+    const HSS_GLOBAL double* G = gview(c.G);
+    double gv[RPT];
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) gv[u] = G[(int64_t)min(j, nc - 1) * nc + min(ib + 4 * u, nc - 1)];
+#pragma unroll
+    for (int u = 0; u < RPT; ++u)
+      if (j < nc && ib + 4 * u < nc) A[ib + 4 * u][j] = gv[u];
+  }
   __syncthreads();
   // outer-product Cholesky on the unscaled rows: after step k the trailing
   // block holds G - sum_{p<=k} r_p^T r_p with r_p = A(p, p:) / sqrt(A(p,p))
@@ -502,19 +553,21 @@ __global__ __launch_bounds__(256) void k_cq_chol(LevelArgs a, int side, CholTask
     for (int q = k + 1 + threadIdx.x; q < nc; q += 256) A[q][k] /= dR[k];
     if (threadIdx.x == 0) dX[k] /= dR[k];
     __syncthreads();
-    // B(p, q) -= R(p, k) X(k, q) for p < k, q >= k
-    for (int idx = threadIdx.x; idx < k * (nc - k); idx += 256) {
-      const int p = idx % k, q = k + idx / k;
-      const double xkq = q == k ? dX[k] : A[q][k];
-      if (q == p) continue;
-      A[q][p] -= A[p][k] * xkq;
+    // B(p, q) -= R(p, k) X(k, q) for p < k, q >= k: thread (ib, j) takes
+    // column q = j and the rows p = ib, ib + 4, ...
+    if (j >= k && j < nc) {
+      const double xkq = j == k ? dX[k] : A[j][k];
+      for (int p = ib; p < k; p += 4) A[j][p] -= A[p][k] * xkq;
     }
     __syncthreads();
   }
-  if (j < nc)
-    for (int i = ib; i < nc; i += 4) c.X[(int64_t)j * nc + i] = i < j ? A[j][i] : (i == j ? dX[i] : 0.0);
+  {
+    HSS_GLOBAL double* X = gview_w(c.X);
+    if (j < nc)
+      for (int i = ib; i < nc; i += 4) X[(int64_t)j * nc + i] = i < j ? A[j][i] : (i == j ? dX[i] : 0.0);
+  }
   if constexpr (PASS == 1) {
-    for (int i = threadIdx.x; i < nc; i += 256) c.d1[i] = dR[i];
+    for (int i = threadIdx.x; i < nc; i += 256) gview_w(c.d1)[i] = dR[i];
     if (threadIdx.x == 0) {
       GemmTask k;
       k.pad = 0;
@@ -530,6 +583,9 @@ __global__ __launch_bounds__(256) void k_cq_chol(LevelArgs a, int side, CholTask
       *T1 = k;
     }
   } else {
+    // diag(R1) of the first pass, loaded by all threads at once
+    __shared__ double d1[kCholMaxB];
+    for (int i = threadIdx.x; i < nc; i += 256) d1[i] = gview(c.d1)[i];
     __syncthreads();
     if (threadIdx.x != 0) return;
     const int g = a.nodes[t];
@@ -540,10 +596,10 @@ __global__ __launch_bounds__(256) void k_cq_chol(LevelArgs a, int side, CholTask
     const double er = fmax(P.eps_r / lev, P.eps_floor), ea = P.eps_a / lev;
     double mn = INFINITY, dev = 0.0;
     for (int i = 0; i < nc; ++i) {
-      mn = fmin(mn, fabs(dR[i] * c.d1[i]));
+      mn = fmin(mn, fabs(dR[i] * d1[i]));
       dev = fmax(dev, fabs(dR[i] - 1.0));
     }
-    const double rho = st.rho[side] < 0.0 ? fabs(dR[0] * c.d1[0]) : st.rho[side];
+    const double rho = st.rho[side] < 0.0 ? fabs(dR[0] * d1[0]) : st.rho[side];
     const double thr = fmax(ea, er * rho);
     c.active = 0;
     // decide only away from the threshold (rounding of either QR is ~1e-16
@@ -752,15 +808,15 @@ __global__ __launch_bounds__(NB) void k_red_gather(LevelArgs a, int side) {
     X1 = ctp(a, a.desc[nd.left].RR[side]);
     X2 = ctp(a, a.desc[nd.right].RR[side]);
   }
-  CHUNKED_FOR(idx, (int64_t)m * nc) {
-    const int c = (int)(idx % nc), i = (int)(idx / nc);
-    const int row = J[i];
-    double v;
-    if (nd.leaf) v = P.R[(int64_t)(c0 + c) * P.ldr + nd.lo + row];
-    else v = row < r1 ? X1[(int64_t)row * dcap + c0 + c] : X2[(int64_t)(row - r1) * dcap + c0 + c];
-    if (i < r) RR[(int64_t)i * dcap + c0 + c] = v;
-    else Xr[(int64_t)c * nd.mcap + (i - r)] = v;
-  }
+  const HSS_GLOBAL int32_t* gJ = gview(J);
+  copy_elems(m * nc, [&](int idx) {
+    const int c = idx % nc, i = idx / nc;
+    const int row = gJ[i];
+    const double* src = nd.leaf ? P.R + (int64_t)(c0 + c) * P.ldr + nd.lo + row
+                                : (row < r1 ? X1 + (int64_t)row * dcap : X2 + (int64_t)(row - r1) * dcap) + c0 + c;
+    double* dst = i < r ? RR + (int64_t)i * dcap + c0 + c : Xr + (int64_t)c * nd.mcap + (i - r);
+    return CopyAt{gview(src), gview_w(dst)};
+  });
   if (st.go && blockIdx.y == 0) {
     int64_t* I = a.lpool + nd.I[side];
     const int64_t* I1 = nd.leaf ? nullptr : a.lpool + a.desc[nd.left].I[side];

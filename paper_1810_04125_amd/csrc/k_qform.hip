@@ -90,52 +90,77 @@ __global__ __launch_bounds__(QFB) void k_qf_prep(const QformTask* __restrict__ t
 
 // M = S^{-1} V_1^T (b x b) by right-looking back substitution over the
 // whole workgroup (rows of M become final from the bottom up), held in LDS
-// for b <= QF_LDS_B and in the workspace otherwise; then the GEMM task
-// Q_k -= V M.
+// with G for b <= QF_LDS_B and in the workspace otherwise; then the GEMM
+// task Q_k -= V M.  Thread (row group pg, column j) updates column j of the
+// rows pg, pg + QFS/64, ... of each step.
 constexpr int QFS = 1024;
 constexpr int QF_LDS_B = 64;
+constexpr int QF_RG = QFS / 64;   // row groups
 
 __global__ __launch_bounds__(QFS) void k_qf_solve(const QformTask* __restrict__ tasks, GemmTask* __restrict__ gt,
                                                   unsigned long long* __restrict__ kcnt) {
   __shared__ double Rl[QF_LDS_B * QF_LDS_B];
+  __shared__ double Gl[QF_LDS_B * QF_LDS_B];
   const QformTask& t = tasks[blockIdx.x];
   GemmTask* g = gt + blockIdx.x;
   if (threadIdx.x == 0) g->M = 0;
   if (!t.active || !t.wk) return;
   const int b = t.nc;
-  const double* G = t.wk;                      // V^T V, b x b column-major
+  const bool in_lds = b <= QF_LDS_B;
   double* Mg = t.wk + (int64_t)b * b;          // M, b x b column-major
-  double* R = b <= QF_LDS_B ? Rl : Mg;         // row-major b x b working copy
-  // right-hand side V_1^T: R(l, j) = V(j, l), zero for j < l
-  for (int idx = threadIdx.x; idx < b * b; idx += QFS) {
-    const int l = idx / b, j = idx - l * b;
-    R[idx] = j >= l ? t.W[(int64_t)l * t.ldw + j] : 0.0;
+  // working copies: R row-major b x b, G column-major b x b
+  double* R = in_lds ? Rl : Mg;
+  const double* G = in_lds ? Gl : t.wk;
+  {
+    const HSS_GLOBAL double* gW = gview(t.W);
+    const HSS_GLOBAL double* gG = gview(t.wk);
+    constexpr int LU = 4;
+    const int tot = b * b;
+    for (int base = threadIdx.x; base < tot; base += QFS * LU) {
+      double rv[LU], gv[LU];
+#pragma unroll
+      for (int u = 0; u < LU; ++u) {
+        const int idx = min(base + u * QFS, tot - 1);
+        const int l = idx / b, j = idx - l * b;
+        rv[u] = gW[(int64_t)l * t.ldw + j];   // R(l, j) = V(j, l), zero for j < l
+        gv[u] = gG[idx];
+      }
+#pragma unroll
+      for (int u = 0; u < LU; ++u) {
+        const int idx = base + u * QFS;
+        if (idx < tot) {
+          const int l = idx / b, j = idx - l * b;
+          R[idx] = j >= l ? rv[u] : 0.0;
+          if (in_lds) Gl[idx] = gv[u];
+        }
+      }
+    }
   }
   __syncthreads();
+  const int jl = threadIdx.x & 63, pg = threadIdx.x >> 6;
   for (int l = b - 1; l >= 0; --l) {
     // row l is final: divide by S_ll = G_ll / 2
     const double inv = 2.0 / G[(int64_t)l * b + l];
     for (int j = threadIdx.x; j < b; j += QFS) R[l * b + j] *= inv;
     __syncthreads();
     // rows p < l: R(p, :) -= S(p, l) R(l, :), S(p, l) = G(p, l)
-    for (int idx = threadIdx.x; idx < l * b; idx += QFS) {
-      const int p = idx / b, j = idx - p * b;
-      R[idx] -= G[(int64_t)l * b + p] * R[l * b + j];
-    }
+    for (int j = jl; j < b; j += 64)
+      for (int p = pg; p < l; p += QF_RG) R[p * b + j] -= G[(int64_t)l * b + p] * R[l * b + j];
     __syncthreads();
   }
   // M column-major for the GEMM
-  if (R == Rl) {
+  if (in_lds) {
+    HSS_GLOBAL double* gM = gview_w(Mg);
     for (int idx = threadIdx.x; idx < b * b; idx += QFS) {
       const int l = idx / b, j = idx - l * b;
-      Mg[(int64_t)j * b + l] = Rl[idx];
+      gM[(int64_t)j * b + l] = Rl[idx];
     }
   }
   if (threadIdx.x == 0) {
     GemmTask q;
     q.A = t.W; q.a_rs = 1; q.a_cs = t.ldw;   // V
     q.B = Mg;
-    if (R == Rl) { q.b_rs = 1; q.b_cs = b; } else { q.b_rs = b; q.b_cs = 1; }   // M(l, j)
+    if (in_lds) { q.b_rs = 1; q.b_cs = b; } else { q.b_rs = b; q.b_cs = 1; }   // M(l, j)
     q.C = t.Q; q.c_rs = 1; q.c_cs = t.ldq;
     q.M = t.m; q.N = b; q.K = b; q.pad = 0;
     q.alpha = -1.0; q.beta = 1.0;

@@ -325,7 +325,7 @@ __global__ void k_qrcp_alive(const QrcpTask* __restrict__ tasks, int ntasks, int
   if (k < min(t.m, t.d) && !ctl_of(t)->done) atomicAdd(out, 1);
 }
 
-// rank, the ascending rest of J, R2 copied into E, max rank of the batch
+// rank, the ascending rest of J, max rank of the batch
 __global__ __launch_bounds__(QB) void k_qrcp_fin(const QrcpTask* __restrict__ tasks, int32_t* maxrank) {
   const QrcpTask& t = tasks[blockIdx.x];
   if (!t.active) return;
@@ -361,12 +361,30 @@ __global__ __launch_bounds__(QB) void k_qrcp_fin(const QrcpTask* __restrict__ ta
     *t.rank_out = r;
     atomicMax(maxrank, r);
   }
-  __syncthreads();
-  const int nrest = m - r;
-  if (!t.E) return;
-  for (int64_t idx = threadIdx.x; idx < (int64_t)r * nrest; idx += QB) {
-    const int i = (int)(idx % r), l = (int)(idx / r);
-    t.E[(int64_t)l * t.lde + i] = t.W[(int64_t)t.J[r + l] * t.ldw + i];
+}
+
+// Right-hand side of the back substitution: E(:, l) = R(0:r, J(r + l)),
+// the first r entries of panel column J(r + l).  The columns l of a matrix
+// are spread over the gridDim.y workgroups; a workgroup copies one column
+// at a time, every thread loading its EU entries together.
+constexpr int EU = 4;
+__global__ __launch_bounds__(QB) void k_qrcp_egather(const QrcpTask* __restrict__ tasks) {
+  const QrcpTask& t = tasks[blockIdx.x];
+  if (!t.active || !t.E) return;
+  const int r = *t.rank_out;
+  const int nrest = t.m - r;
+  const HSS_GLOBAL int32_t* J = gview(t.J);
+  for (int l = blockIdx.y; l < nrest; l += gridDim.y) {
+    const HSS_GLOBAL double* src = gview(t.W + (int64_t)J[r + l] * t.ldw);
+    HSS_GLOBAL double* dst = gview_w(t.E + (int64_t)l * t.lde);
+    for (int i0 = threadIdx.x; i0 < r; i0 += QB * EU) {
+      double v[EU];
+#pragma unroll
+      for (int u = 0; u < EU; ++u) v[u] = src[min(i0 + u * QB, r - 1)];
+#pragma unroll
+      for (int u = 0; u < EU; ++u)
+        if (i0 + u * QB < r) dst[i0 + u * QB] = v[u];
+    }
   }
 }
 
@@ -388,18 +406,34 @@ __global__ __launch_bounds__(QB) void k_trsm_diag(const QrcpTask* __restrict__ t
   const int i1 = min(r, i0 + TRB);
   const int nb = i1 - i0;
   const int nrest = t.m - r;
-  const double* rdiag = rdiag_of(t);
-  for (int idx = threadIdx.x; idx < TRB * TRB; idx += QB) {
-    const int ii = idx % TRB, jj = idx / TRB;
-    double v = 0.0;
-    if (ii < nb && jj < nb && ii <= jj)
-      v = (ii == jj) ? rdiag[i0 + jj] : t.W[(int64_t)t.J[i0 + jj] * t.ldw + i0 + ii];
-    T[ii][jj] = v;
+  {
+    // R1 block: column jj is panel column J(i0 + jj); every thread loads its
+    // TPT entries (their column indices first) before writing any to LDS
+    constexpr int TPT = TRB * TRB / QB;
+    const HSS_GLOBAL double* rdiag = gview(rdiag_of(t));
+    const HSS_GLOBAL int32_t* J = gview(t.J);
+    const HSS_GLOBAL double* W = gview(t.W);
+    int col[TPT];
+#pragma unroll
+    for (int u = 0; u < TPT; ++u) col[u] = J[i0 + min((int)(threadIdx.x + QB * u) / TRB, nb - 1)];
+    double v[TPT];
+#pragma unroll
+    for (int u = 0; u < TPT; ++u) {
+      const int idx = threadIdx.x + QB * u;
+      const int ii = idx % TRB, jj = idx / TRB;
+      v[u] = ii == jj ? rdiag[i0 + min(jj, nb - 1)] : W[(int64_t)col[u] * t.ldw + i0 + min(ii, nb - 1)];
+    }
+#pragma unroll
+    for (int u = 0; u < TPT; ++u) {
+      const int idx = threadIdx.x + QB * u;
+      const int ii = idx % TRB, jj = idx / TRB;
+      T[ii][jj] = (ii < nb && jj < nb && ii <= jj) ? v[u] : 0.0;
+    }
   }
   __syncthreads();
   const int l = w.y + threadIdx.x;
   if (l < nrest) {
-    double* e = t.E + (int64_t)l * t.lde + i0;
+    HSS_GLOBAL double* e = gview_w(t.E + (int64_t)l * t.lde + i0);
     double x[TRB];
 #pragma unroll
     for (int ii = 0; ii < TRB; ++ii) x[ii] = ii < nb ? e[ii] : 0.0;
@@ -478,6 +512,10 @@ void run_qrcp(QrcpTask* tasks, int32_t ntasks, const QrcpWork& wk, const int2* w
   hipLaunchKernelGGL(k_qrcp_fin, dim3(ntasks), dim3(QB), 0, s, tasks, flag);
   prof_end(HSS_K_QRCP_OTHER, s);
   if (!solve_e) return;
+  prof_begin(s);
+  hipLaunchKernelGGL(k_qrcp_egather, dim3(ntasks, (unsigned)std::max(1, std::min(256, 4096 / ntasks))), dim3(QB),
+                     0, s, tasks);
+  prof_end(HSS_K_QRCP_OTHER, s);
   int32_t rmax = 0;
   HSS_HIP_CHECK(hipMemcpyAsync(&rmax, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HSS_HIP_CHECK(hipStreamSynchronize(s));
