@@ -36,7 +36,7 @@ __device__ __forceinline__ void gemm_coords(const GemmTask& t, int idx, bool a_s
   }
 }
 
-__global__ __launch_bounds__(256) void k_gemm_grouped(const GemmTask* __restrict__ tasks, int ntasks, int ksplit,
+__global__ __launch_bounds__(256, 3) void k_gemm_grouped(const GemmTask* __restrict__ tasks, int ntasks, int ksplit,
                                                      double* __restrict__ part,
                                                      unsigned long long* __restrict__ kcnt) {
   const int task = blockIdx.z % ntasks, ks = blockIdx.z / ntasks;
@@ -156,25 +156,35 @@ __global__ __launch_bounds__(256) void k_gemm_grouped(const GemmTask* __restrict
       }
 }
 
-// C = alpha * (sum of the K-slice partials, in slice order) + beta * C
+// C = alpha * (sum of the K-slice partials, in slice order) + beta * C.
+// blockIdx.z = task * SUM_SPLIT + part: each workgroup adds one 256-element
+// part of a 64 x 64 tile, a thread one element, loading SUM_U slices at once.
+constexpr int SUM_SPLIT = GT * GT / 256;
+constexpr int SUM_U = 8;
 __global__ __launch_bounds__(256) void k_gemm_splitk_sum(const GemmTask* __restrict__ tasks, int ntasks, int ksplit,
                                                         const double* __restrict__ part) {
-  const int task = blockIdx.z;
+  const int task = blockIdx.z / SUM_SPLIT, piece = blockIdx.z % SUM_SPLIT;
   const GemmTask t = tasks[task];
   const int tm = blockIdx.y, tn = blockIdx.x;
   if (t.M <= 0 || t.N <= 0 || tm * GT >= t.M || tn * GT >= t.N) return;
+  const int e = piece * 256 + threadIdx.x;
+  const int r = e / GT, c = e % GT;
+  const int64_t gi = (int64_t)tm * GT + r, gj = (int64_t)tn * GT + c;
+  if (gi >= t.M || gj >= t.N) return;
   const int64_t tile = (((int64_t)task * gridDim.y + tm) * gridDim.x + tn) * (GT * GT);
   const int64_t stride = (int64_t)ntasks * gridDim.y * gridDim.x * (GT * GT);
-  for (int e = threadIdx.x; e < GT * GT; e += 256) {
-    const int r = e / GT, c = e % GT;
-    const int64_t gi = (int64_t)tm * GT + r, gj = (int64_t)tn * GT + c;
-    if (gi >= t.M || gj >= t.N) continue;
-    double sum = 0.0;
-    for (int ks = 0; ks < ksplit; ++ks) sum += part[ks * stride + tile + e];
-    HSS_GLOBAL double* cp = gview_w(t.C + gi * t.c_rs + gj * t.c_cs);
-    const double val = t.alpha * sum;
-    *cp = (t.beta == 0.0) ? val : val + t.beta * (*cp);
+  double sum = 0.0;
+  for (int k0 = 0; k0 < ksplit; k0 += SUM_U) {
+    double v[SUM_U];
+#pragma unroll
+    for (int u = 0; u < SUM_U; ++u) v[u] = part[min(k0 + u, ksplit - 1) * stride + tile + e];
+#pragma unroll
+    for (int u = 0; u < SUM_U; ++u)
+      if (k0 + u < ksplit) sum += v[u];
   }
+  HSS_GLOBAL double* cp = gview_w(t.C + gi * t.c_rs + gj * t.c_cs);
+  const double val = t.alpha * sum;
+  *cp = (t.beta == 0.0) ? val : val + t.beta * (*cp);
 }
 
 void launch_gemm(const GemmTask* tasks, int32_t ntasks, int32_t mcap, int32_t ncap, hipStream_t s,
@@ -182,17 +192,28 @@ void launch_gemm(const GemmTask* tasks, int32_t ntasks, int32_t mcap, int32_t nc
   if (ntasks <= 0 || mcap <= 0 || ncap <= 0) return;
   const unsigned gx = (unsigned)((ncap + GT - 1) / GT), gy = (unsigned)((mcap + GT - 1) / GT);
   const int64_t tiles = (int64_t)gx * gy * ntasks;
+  // split K until about 2048 workgroups are busy, K slices of at least
+  // 4 tiles, within the workspace
   int ksplit = 1;
-  if (ws && kcap >= 4 * GK * 4 && tiles < 1024) {
-    ksplit = (int)std::min<int64_t>(std::min<int64_t>(8, kcap / (4 * GK)), std::max<int64_t>(1, 2048 / tiles));
+  if (ws && kcap >= 8 * GK && tiles < 2048) {
+    ksplit = (int)std::min<int64_t>(std::min<int64_t>(32, kcap / (4 * GK)), std::max<int64_t>(1, 2048 / tiles));
     while (ksplit > 1 && (int64_t)ksplit * tiles * GT * GT > ws_elems) --ksplit;
   }
   prof_begin(s);
-  hipLaunchKernelGGL(k_gemm_grouped, dim3(gx, gy, (unsigned)(ntasks * ksplit)), dim3(256), 0, s, tasks, ntasks,
-                     ksplit, ws, kcnt);
+  if (ksplit == 1) {
+    // grid z is at most 65535: very large batches go in several launches
+    constexpr int kMaxZ = 65535;
+    for (int t0 = 0; t0 < ntasks; t0 += kMaxZ) {
+      const int nt = std::min(kMaxZ, ntasks - t0);
+      hipLaunchKernelGGL(k_gemm_grouped, dim3(gx, gy, (unsigned)nt), dim3(256), 0, s, tasks + t0, nt, 1, ws, kcnt);
+    }
+  } else {
+    hipLaunchKernelGGL(k_gemm_grouped, dim3(gx, gy, (unsigned)(ntasks * ksplit)), dim3(256), 0, s, tasks, ntasks,
+                       ksplit, ws, kcnt);
+  }
   if (ksplit > 1)
-    hipLaunchKernelGGL(k_gemm_splitk_sum, dim3(gx, gy, (unsigned)ntasks), dim3(256), 0, s, tasks, ntasks, ksplit,
-                       ws);
+    hipLaunchKernelGGL(k_gemm_splitk_sum, dim3(gx, gy, (unsigned)(ntasks * SUM_SPLIT)), dim3(256), 0, s, tasks,
+                       ntasks, ksplit, ws);
   prof_end(HSS_K_GEMM, s);
 }
 

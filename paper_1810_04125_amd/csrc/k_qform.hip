@@ -143,9 +143,23 @@ __global__ __launch_bounds__(QFS) void k_qf_solve(const QformTask* __restrict__ 
     const double inv = 2.0 / G[(int64_t)l * b + l];
     for (int j = threadIdx.x; j < b; j += QFS) R[l * b + j] *= inv;
     __syncthreads();
-    // rows p < l: R(p, :) -= S(p, l) R(l, :), S(p, l) = G(p, l)
-    for (int j = jl; j < b; j += 64)
-      for (int p = pg; p < l; p += QF_RG) R[p * b + j] -= G[(int64_t)l * b + p] * R[l * b + j];
+    // rows p < l: R(p, :) -= S(p, l) R(l, :), S(p, l) = G(p, l); in LDS the
+    // rows of a thread are unrolled so that their reads are in flight together
+    if (in_lds) {
+      if (jl < b) {
+        const double rl = Rl[l * b + jl];
+#pragma unroll
+        for (int u = 0; u < QF_LDS_B / QF_RG; ++u) {
+          const int p = pg + QF_RG * u;
+          const int pc = min(p, QF_LDS_B - 1);
+          const double v = Rl[pc * b + jl] - Gl[l * b + pc] * rl;
+          if (p < l) Rl[pc * b + jl] = v;
+        }
+      }
+    } else {
+      for (int j = jl; j < b; j += 64)
+        for (int p = pg; p < l; p += QF_RG) R[p * b + j] -= G[(int64_t)l * b + p] * R[l * b + j];
+    }
     __syncthreads();
   }
   // M column-major for the GEMM
