@@ -487,8 +487,16 @@ __global__ __launch_bounds__(NBN) void k_fn_norms(LevelArgs a, int side, QrcpTas
 // least 10 times the threshold) and Q1 was nearly orthonormal (|R2_ii - 1|
 // <= 0.1); then Q = Q1 X2 is appended to the basis and the Householder QR
 // of the block is skipped.  Anything else is left to the Householder path.
+//
+// 16 waves per node: thread (row group ib, column j) updates the rows ib,
+// ib + 16, ... of column j, at most CRW of them per step, unrolled so that
+// their LDS reads are in flight together.
+constexpr int CHT = 1024;               // threads of the Cholesky kernel
+constexpr int CRG = CHT / 64;           // row groups
+constexpr int CRW = kCholMaxB / CRG;    // rows per thread and step
+
 template <int PASS>
-__global__ __launch_bounds__(256) void k_cq_chol(LevelArgs a, int side, CholTask* __restrict__ ct,
+__global__ __launch_bounds__(CHT) void k_cq_chol(LevelArgs a, int side, CholTask* __restrict__ ct,
                                                  QrcpTask* __restrict__ qt) {
   __shared__ double A[kCholMaxB][kCholMaxB + 1];
   const int t = blockIdx.x;
@@ -501,17 +509,15 @@ __global__ __launch_bounds__(256) void k_cq_chol(LevelArgs a, int side, CholTask
   CholTask& c = ct[t];
   if (!c.active) return;
   const int nc = c.nc;
-  // thread (row group ib, column j): 4 row groups x 64 columns
   const int j = threadIdx.x & 63, ib = threadIdx.x >> 6;
-  constexpr int RPT = kCholMaxB / 4;   // rows per thread
   {
     const HSS_GLOBAL double* G = gview(c.G);
-    double gv[RPT];
+    double gv[CRW];
 #pragma unroll
-    for (int u = 0; u < RPT; ++u) gv[u] = G[(int64_t)min(j, nc - 1) * nc + min(ib + 4 * u, nc - 1)];
+    for (int u = 0; u < CRW; ++u) gv[u] = G[(int64_t)min(j, nc - 1) * nc + min(ib + CRG * u, nc - 1)];
 #pragma unroll
-    for (int u = 0; u < RPT; ++u)
-      if (j < nc && ib + 4 * u < nc) A[ib + 4 * u][j] = gv[u];
+    for (int u = 0; u < CRW; ++u)
+      if (j < nc && ib + CRG * u < nc) A[ib + CRG * u][j] = gv[u];
   }
   __syncthreads();
   // outer-product Cholesky on the unscaled rows: after step k the trailing
@@ -525,7 +531,13 @@ __global__ __launch_bounds__(256) void k_cq_chol(LevelArgs a, int side, CholTask
     }
     if (j > k && j < nc) {
       const double akj = A[k][j] / dk;
-      for (int i = k + 1 + ib; i <= j; i += 4) A[i][j] -= A[k][i] * akj;
+#pragma unroll
+      for (int u = 0; u < CRW; ++u) {
+        const int i = k + 1 + ib + CRG * u;
+        const int ic = min(i, kCholMaxB - 1);
+        const double v = A[ic][j] - A[k][ic] * akj;
+        if (i <= j) A[ic][j] = v;
+      }
     }
     __syncthreads();
   }
@@ -535,39 +547,44 @@ __global__ __launch_bounds__(256) void k_cq_chol(LevelArgs a, int side, CholTask
   }
   // R(i, j) = A(i, j) / sqrt(A(i, i)); diag(R) kept apart for the inversion
   __shared__ double dR[kCholMaxB];
-  for (int i = threadIdx.x; i < nc; i += 256) dR[i] = sqrt(A[i][i]);
+  for (int i = threadIdx.x; i < nc; i += CHT) dR[i] = sqrt(A[i][i]);
   __syncthreads();
   if (j < nc)
-    for (int i = ib; i <= j && i < nc; i += 4) A[i][j] /= dR[i];
+    for (int i = ib; i <= j && i < nc; i += CRG) A[i][j] /= dR[i];
   __syncthreads();
   // X = R^{-1} by right-looking back substitution of R X = I, bottom row
   // first: R stays in the upper triangle of A, X(i, j) (i < j) is kept
   // transposed in the lower triangle (A[j][i]) and X(i, i) in dX.
   __shared__ double dX[kCholMaxB];
-  for (int i = threadIdx.x; i < nc; i += 256) dX[i] = 1.0;
+  for (int i = threadIdx.x; i < nc; i += CHT) dX[i] = 1.0;
   if (j < nc)
-    for (int i = ib; i < j; i += 4) A[j][i] = 0.0;
+    for (int i = ib; i < j; i += CRG) A[j][i] = 0.0;
   __syncthreads();
   for (int k = nc - 1; k >= 0; --k) {
     // row k of X: B(k, :) / R(k, k)
-    for (int q = k + 1 + threadIdx.x; q < nc; q += 256) A[q][k] /= dR[k];
+    for (int q = k + 1 + threadIdx.x; q < nc; q += CHT) A[q][k] /= dR[k];
     if (threadIdx.x == 0) dX[k] /= dR[k];
     __syncthreads();
     // B(p, q) -= R(p, k) X(k, q) for p < k, q >= k: thread (ib, j) takes
-    // column q = j and the rows p = ib, ib + 4, ...
+    // column q = j and the rows p = ib + 16u
     if (j >= k && j < nc) {
       const double xkq = j == k ? dX[k] : A[j][k];
-      for (int p = ib; p < k; p += 4) A[j][p] -= A[p][k] * xkq;
+#pragma unroll
+      for (int u = 0; u < CRW; ++u) {
+        const int p = ib + CRG * u;
+        const double v = A[j][p] - A[p][k] * xkq;
+        if (p < k) A[j][p] = v;
+      }
     }
     __syncthreads();
   }
   {
     HSS_GLOBAL double* X = gview_w(c.X);
     if (j < nc)
-      for (int i = ib; i < nc; i += 4) X[(int64_t)j * nc + i] = i < j ? A[j][i] : (i == j ? dX[i] : 0.0);
+      for (int i = ib; i < nc; i += CRG) X[(int64_t)j * nc + i] = i < j ? A[j][i] : (i == j ? dX[i] : 0.0);
   }
   if constexpr (PASS == 1) {
-    for (int i = threadIdx.x; i < nc; i += 256) gview_w(c.d1)[i] = dR[i];
+    for (int i = threadIdx.x; i < nc; i += CHT) gview_w(c.d1)[i] = dR[i];
     if (threadIdx.x == 0) {
       GemmTask k;
       k.pad = 0;
@@ -585,7 +602,7 @@ __global__ __launch_bounds__(256) void k_cq_chol(LevelArgs a, int side, CholTask
   } else {
     // diag(R1) of the first pass, loaded by all threads at once
     __shared__ double d1[kCholMaxB];
-    for (int i = threadIdx.x; i < nc; i += 256) d1[i] = gview(c.d1)[i];
+    for (int i = threadIdx.x; i < nc; i += CHT) d1[i] = gview(c.d1)[i];
     __syncthreads();
     if (threadIdx.x != 0) return;
     const int g = a.nodes[t];
@@ -681,12 +698,12 @@ void launch_fnorm_test(const LevelArgs& a, int side, int32_t iter, int32_t mcap_
   const int32_t nb = std::min(ncap, kCholMaxB);
   launch_gemm(a.tasks, a.count, nb, nb, s, a.kcnt, mcap_max, a.gws, kGemmSplitElems);
   prof_begin(s);
-  hipLaunchKernelGGL(k_cq_chol<1>, dim3(a.count), dim3(256), 0, s, a, side, ts.ct, ts.qt);
+  hipLaunchKernelGGL(k_cq_chol<1>, dim3(a.count), dim3(CHT), 0, s, a, side, ts.ct, ts.qt);
   prof_end(HSS_K_TEST_NORMS, s);
   launch_gemm(a.tasks, a.count, mcap_max, nb, s, a.kcnt);
   launch_gemm(a.tasks + a.count, a.count, nb, nb, s, a.kcnt, mcap_max, a.gws, kGemmSplitElems);
   prof_begin(s);
-  hipLaunchKernelGGL(k_cq_chol<2>, dim3(a.count), dim3(256), 0, s, a, side, ts.ct, ts.qt);
+  hipLaunchKernelGGL(k_cq_chol<2>, dim3(a.count), dim3(CHT), 0, s, a, side, ts.ct, ts.qt);
   prof_end(HSS_K_TEST_NORMS, s);
   launch_gemm(a.tasks, a.count, mcap_max, nb, s, a.kcnt);
   run_qrcp(ts.qt, a.count, ts.wk, nullptr, 0, ncap, mcap_max, ncap, ts.flag, ts.gt, mcap_max, s, a.kcnt, false);
