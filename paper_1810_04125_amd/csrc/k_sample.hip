@@ -56,17 +56,15 @@ void launch_permute_points(const double* pts, const int64_t* perm, int64_t n, do
                      perm, n, out);
 }
 
-// 1/sqrt(x) from the hardware estimate (about 2^-25 relative) refined by
-// two Newton-Raphson steps y <- y + y (1 - x y^2) / 2, the residual taken
-// with an FMA; within one ulp on (1e-8, 4], cheaper than sqrt + divide.
+// 1/sqrt(x) from the hardware estimate y (about 2^-25 relative) refined by
+// one third-order step of the series (1 - e)^(-1/2) = 1 + e/2 + 3e^2/8 + ...
+// with e = 1 - x y^2 taken by an FMA: y <- y + y e (1/2 + 3e/8).  The
+// truncation is about (5/16) e^3, far below FP64 rounding; five operations
+// instead of the eight of two Newton steps.
 __device__ __forceinline__ double rsqrt_nr(double x) {
-  double y = __builtin_amdgcn_rsq(x);
-#pragma unroll
-  for (int it = 0; it < 2; ++it) {
-    const double e = fma(-(x * y), y, 1.0);
-    y = fma(0.5 * y, e, y);
-  }
-  return y;
+  const double y = __builtin_amdgcn_rsq(x);
+  const double e = fma(-(x * y), y, 1.0);
+  return fma(y * e, fma(0.375, e, 0.5), y);
 }
 
 template <int FAM>
@@ -81,7 +79,7 @@ __device__ __forceinline__ double entry_t(const GenDev& g, int64_t i, int64_t j)
 // (nsplit == 1, column-major with lds) or the split-K partial buffer
 // P[z][row][col] with row length ncp = gridDim.y * SM_COLS.
 template <int FAM, int TRANS>
-__global__ __launch_bounds__(512) void k_sample_f64(GenDev g, const double* __restrict__ R,
+__global__ __launch_bounds__(512, 4) void k_sample_f64(GenDev g, const double* __restrict__ R,
                                                     int64_t ldr, double* __restrict__ out,
                                                     int64_t lds, int32_t ncols, int64_t kchunk,
                                                     int32_t nsplit) {
@@ -133,6 +131,7 @@ __global__ __launch_bounds__(512) void k_sample_f64(GenDev g, const double* __re
     }
   };
   if (kb < ke) load_tile(kb);
+  const int64_t rb0 = (int64_t)blockIdx.x * SM_ROWS, rb1 = rb0 + SM_ROWS;   // rows of the workgroup
   for (int64_t kt = kb; kt < ke; kt += SM_BK) {
 #pragma unroll
     for (int e = 0; e < RPT; ++e) {
@@ -144,7 +143,31 @@ __global__ __launch_bounds__(512) void k_sample_f64(GenDev g, const double* __re
     }
     __syncthreads();
     if (kt + SM_BK < ke) load_tile(kt + SM_BK);
+    // A tile inside the matrix and off its diagonal needs neither the
+    // bounds nor the diagonal selects: the kernel families take a short
+    // path there (all but the few tiles that meet the diagonal or an edge).
+    bool fast = false;
+    if constexpr (PTS) fast = rb1 <= n && kt + SM_BK <= ke && (kt + SM_BK <= rb0 || kt >= rb1);
+    if (fast) {
 #pragma unroll
+      for (int kk = 0; kk < SM_BK; kk += 4) {
+        const double dx = px - Ps[kk + kq][0];
+        const double dy = py - Ps[kk + kq][1];
+        const double dz = pz - Ps[kk + kq][2];
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        double a;
+        if constexpr (FAM == HSS_FAM_LAPLACE) a = kInv4Pi * rsqrt_nr(r2);
+        else a = exp(-r2 * g.inv2s2);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const double b = Rs[kk + kq][c * 16 + (lane & 15)];
+          acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[c], 0, 0, 0);
+        }
+      }
+      __syncthreads();
+      continue;
+    }
+#pragma unroll 2
     for (int kk = 0; kk < SM_BK; kk += 4) {
       const int64_t j = kt + kk + kq;
       const bool ok = row_ok && j < ke;
