@@ -316,13 +316,44 @@ __global__ __launch_bounds__(QBW) void k_qrcp_wg(const QrcpTask* __restrict__ ta
   }
 }
 
-// count of matrices still factoring after step k-1 has run
-__global__ void k_qrcp_alive(const QrcpTask* __restrict__ tasks, int ntasks, int k, int32_t* out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= ntasks) return;
-  const QrcpTask& t = tasks[i];
-  if (!t.active) return;
-  if (k < min(t.m, t.d) && !ctl_of(t)->done) atomicAdd(out, 1);
+// out[0]: matrices still factoring after step k-1 has run; out[1]: the
+// largest rank of the batch so far (the final one once out[0] is 0), with
+// the rank rule of k_qrcp_fin.  One workgroup; writes its result directly.
+constexpr int QAL = 1024;
+__global__ __launch_bounds__(QAL) void k_qrcp_alive(const QrcpTask* __restrict__ tasks, int ntasks, int k,
+                                                   int32_t* __restrict__ out) {
+  __shared__ int sa[QAL / 64], sr[QAL / 64];
+  int alive = 0, rmax = 0;
+  for (int i = threadIdx.x; i < ntasks; i += QAL) {
+    const QrcpTask& t = tasks[i];
+    if (!t.active) continue;
+    const int kmax = min(t.m, t.d);
+    const QrcpCtl* c = ctl_of(t);
+    const bool done = c->done != 0;
+    if (k < kmax && !done) ++alive;
+    rmax = max(rmax, (kmax > 0 && done) ? c->rank : kmax);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    alive += __shfl_xor(alive, o, 64);
+    rmax = max(rmax, __shfl_xor(rmax, o, 64));
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) { sa[wv] = alive; sr[wv] = rmax; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int a = 0, r = 0;
+    for (int w = 0; w < QAL / 64; ++w) { a += sa[w]; r = max(r, sr[w]); }
+    out[0] = a;
+    out[1] = r;
+  }
+}
+
+// Pinned host words for the values read back at the host's decisions.
+static int32_t* host_words() {
+  thread_local int32_t* p = nullptr;
+  if (!p) HSS_HIP_CHECK(hipHostMalloc((void**)&p, 64, 0));
+  return p;
 }
 
 // rank, the ascending rest of J, max rank of the batch
@@ -359,7 +390,7 @@ __global__ __launch_bounds__(QB) void k_qrcp_fin(const QrcpTask* __restrict__ ta
   }
   if (threadIdx.x == 0) {
     *t.rank_out = r;
-    atomicMax(maxrank, r);
+    if (maxrank) atomicMax(maxrank, r);
   }
 }
 
@@ -480,6 +511,7 @@ void run_qrcp(QrcpTask* tasks, int32_t ntasks, const QrcpWork& wk, const int2* w
   const int nwg = kQrcpTarget + ntasks;
   const size_t lds = (size_t)std::max(dmax, 1) * sizeof(double);
   const bool one_wg = (int64_t)std::max(dmax, 1) * std::max(ncols_max, 1) <= kQrcpWgCells && lds <= 48 * 1024;
+  bool known_active = false;   // some panel is known to be active
   if (one_wg) {
     prof_begin(s);
     hipLaunchKernelGGL(k_qrcp_wg, dim3(ntasks), dim3(QBW), lds, s, tasks, kcnt);
@@ -489,36 +521,50 @@ void run_qrcp(QrcpTask* tasks, int32_t ntasks, const QrcpWork& wk, const int2* w
     hipLaunchKernelGGL(k_qrcp_plan, dim3(1), dim3(QB), 0, s, tasks, ntasks, kQrcpTarget, wk.chunks, wk.meta);
     hipLaunchKernelGGL(k_qrcp_init, dim3(nwg), dim3(QB), 0, s, tasks, wk.chunks, wk.meta);
     prof_end(HSS_K_QRCP_OTHER, s);
-    if (solve_e && dmax >= 128) run_qr_first(tasks, ntasks, dmax, ncols_max, flag, gtasks, gws, s, kcnt);
+    if (solve_e && dmax >= 128) {
+      const int32_t nact = run_qr_first(tasks, ntasks, dmax, ncols_max, flag, gtasks, gws, s, kcnt);
+      if (nact == 0) return;   // no panel to factor
+      known_active = true;
+    }
   }
-  // pivot steps: launched back to back in segments of 32 between liveness
-  // polls; profiling times each segment as a whole
-  int32_t alive = 1;
+  // pivot steps: launched back to back in segments of 32 after liveness
+  // polls (none before the first segment when a panel is known to be
+  // active); profiling times each segment as a whole.  The poll that finds
+  // no matrix alive also gives the largest rank.
+  int32_t* hw = host_words();
+  bool rank_known = false;
   const int ksteps = one_wg ? 0 : kmax;
   for (int k0 = 0; k0 < ksteps; k0 += 32) {
-    HSS_HIP_CHECK(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
-    hipLaunchKernelGGL(k_qrcp_alive, dim3((ntasks + 127) / 128), dim3(128), 0, s, tasks, ntasks, k0, flag);
-    HSS_HIP_CHECK(hipMemcpyAsync(&alive, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    HSS_HIP_CHECK(hipStreamSynchronize(s));
-    if (alive == 0) break;
+    if (k0 > 0 || !known_active) {
+      hipLaunchKernelGGL(k_qrcp_alive, dim3(1), dim3(QAL), 0, s, tasks, ntasks, k0, flag);
+      HSS_HIP_CHECK(hipMemcpyAsync(hw, flag, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      HSS_HIP_CHECK(hipStreamSynchronize(s));
+      if (hw[0] == 0) {
+        rank_known = true;
+        break;
+      }
+    }
     const int k1 = std::min(ksteps, k0 + 32);
     prof_begin(s);
     for (int k = k0; k < k1; ++k)
       hipLaunchKernelGGL(k_qrcp_step, dim3(nwg), dim3(QB), lds, s, tasks, wk.chunks, wk.meta, k, kcnt);
     prof_end(HSS_K_QRCP_STEP, s, k1 - k0);
   }
-  HSS_HIP_CHECK(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
+  int32_t rmax = rank_known ? hw[1] : 0;
+  if (!rank_known) HSS_HIP_CHECK(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
   prof_begin(s);
-  hipLaunchKernelGGL(k_qrcp_fin, dim3(ntasks), dim3(QB), 0, s, tasks, flag);
+  hipLaunchKernelGGL(k_qrcp_fin, dim3(ntasks), dim3(QB), 0, s, tasks, rank_known ? nullptr : flag);
   prof_end(HSS_K_QRCP_OTHER, s);
   if (!solve_e) return;
   prof_begin(s);
   hipLaunchKernelGGL(k_qrcp_egather, dim3(ntasks, (unsigned)std::max(1, std::min(256, 4096 / ntasks))), dim3(QB),
                      0, s, tasks);
   prof_end(HSS_K_QRCP_OTHER, s);
-  int32_t rmax = 0;
-  HSS_HIP_CHECK(hipMemcpyAsync(&rmax, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  HSS_HIP_CHECK(hipStreamSynchronize(s));
+  if (!rank_known) {
+    HSS_HIP_CHECK(hipMemcpyAsync(hw, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HSS_HIP_CHECK(hipStreamSynchronize(s));
+    rmax = hw[0];
+  }
   for (int ib = (rmax + TRB - 1) / TRB - 1; ib >= 0; --ib) {
     prof_begin(s);
     hipLaunchKernelGGL(k_trsm_diag, dim3(ntrsm), dim3(QB), 0, s, tasks, wg_trsm, ib, gtasks, kcnt);

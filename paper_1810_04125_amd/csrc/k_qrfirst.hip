@@ -58,9 +58,10 @@ __device__ __forceinline__ double qrf_wsum(double v) {
 
 // out[0]: the largest m among the tall panels; out[1]: the cells the
 // reduction takes out of the first pivot step, (d - m) m summed over them,
-// in units of 1024
+// in units of 1024; out[2]: the number of active panels
 __global__ void k_qrf_scan(const QrcpTask* __restrict__ tasks, int ntasks, int32_t* __restrict__ out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < ntasks && tasks[i].active) atomicAdd(out + 2, 1);
   if (i < ntasks && qrf_tall(tasks[i])) {
     const QrcpTask& t = tasks[i];
     atomicMax(out, t.m);
@@ -258,16 +259,16 @@ __global__ __launch_bounds__(256) void k_qrf_finish(QrcpTask* __restrict__ tasks
   if (threadIdx.x == 0) t.d = m;
 }
 
-void run_qr_first(QrcpTask* tasks, int32_t ntasks, int32_t dmax, int32_t mcap_max, int32_t* flag,
-                  GemmTask* gtasks, double* gws, hipStream_t s, unsigned long long* kcnt) {
-  if (ntasks <= 0) return;
-  int32_t scan[2] = {0, 0};
-  HSS_HIP_CHECK(hipMemsetAsync(flag, 0, 2 * sizeof(int32_t), s));
+int32_t run_qr_first(QrcpTask* tasks, int32_t ntasks, int32_t dmax, int32_t mcap_max, int32_t* flag,
+                     GemmTask* gtasks, double* gws, hipStream_t s, unsigned long long* kcnt) {
+  if (ntasks <= 0) return 0;
+  int32_t scan[3] = {0, 0, 0};
+  HSS_HIP_CHECK(hipMemsetAsync(flag, 0, 3 * sizeof(int32_t), s));
   hipLaunchKernelGGL(k_qrf_scan, dim3((ntasks + 127) / 128), dim3(128), 0, s, tasks, ntasks, flag);
-  HSS_HIP_CHECK(hipMemcpyAsync(scan, flag, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HSS_HIP_CHECK(hipMemcpyAsync(scan, flag, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HSS_HIP_CHECK(hipStreamSynchronize(s));
   const int32_t mtall = scan[0];
-  if (mtall <= 0 || ((int64_t)scan[1] << 10) < kQrFirstMinCells) return;
+  if (mtall <= 0 || ((int64_t)scan[1] << 10) < kQrFirstMinCells) return scan[2];
   const int64_t split_ws = gws ? kGemmSplitElems : 0;
   for (int c = 0; c < mtall; c += NBQ) {
     prof_begin(s);
@@ -288,6 +289,7 @@ void run_qr_first(QrcpTask* tasks, int32_t ntasks, int32_t dmax, int32_t mcap_ma
   hipLaunchKernelGGL(k_qrf_finish, dim3(ntasks), dim3(256), 0, s, tasks);
   prof_end(HSS_K_QRCP_OTHER, s);
   HSS_HIP_CHECK(hipGetLastError());
+  return scan[2];
 }
 
 }  // namespace hss
