@@ -61,6 +61,8 @@ Job::~Job() {
   hipStreamSynchronize(stream);
   if (ev0) hipEventDestroy(ev0);
   if (ev1) hipEventDestroy(ev1);
+  if (ev_flag) hipEventDestroy(ev_flag);
+  if (hflags) hipHostFree(hflags);
   if (prof.e0) hipEventDestroy(prof.e0);
   if (prof.e1) hipEventDestroy(prof.e1);
 }
@@ -339,6 +341,8 @@ void Job::setup(int32_t count, const hss_generator* gens, const hss_tree* const*
   }
   HSS_HIP_CHECK(hipEventCreate(&ev0));
   HSS_HIP_CHECK(hipEventCreate(&ev1));
+  HSS_HIP_CHECK(hipEventCreateWithFlags(&ev_flag, hipEventDisableTiming));
+  HSS_HIP_CHECK(hipHostMalloc((void**)&hflags, 64, 0));
   HSS_HIP_CHECK(hipEventCreate(&prof.e0));
   HSS_HIP_CHECK(hipEventCreate(&prof.e1));
   prof.on = false;
@@ -701,6 +705,13 @@ void Job::run_level(int lev, int32_t ncap) {
   const int32_t nc = std::min(ncap, L.dcap);
   HSS_HIP_CHECK(hipMemsetAsync(flags_d + 1, 0, sizeof(int32_t), stream));
   launch_plan(a, stream);
+  // the number of test blocks is read back while the extraction and the
+  // local samples run
+  const bool fnorm = strategy != HSS_DBL_HMT;
+  if (fnorm) {
+    HSS_HIP_CHECK(hipMemcpyAsync(hflags, flags_d + 1, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+    HSS_HIP_CHECK(hipEventRecord(ev_flag, stream));
+  }
   if (has_callback) extract_callbacks(lev);
   launch_extract_nodes(a, stream);
   for (int s = 0; s < nsides; ++s) launch_local_samples(a, s, L.mcap, L.rcap, nc, stream);
@@ -715,9 +726,8 @@ void Job::run_level(int lev, int32_t ncap) {
     id_phase(1);
     launch_decide_hmt(a, stream);
   } else {
-    int32_t nblk = 0;
-    HSS_HIP_CHECK(hipMemcpyAsync(&nblk, flags_d + 1, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
-    HSS_HIP_CHECK(hipStreamSynchronize(stream));
+    HSS_HIP_CHECK(hipEventSynchronize(ev_flag));
+    const int32_t nblk = hflags[0];
     if (nblk > 0) {
       const int32_t nb = std::min(max_block, L.dcap);
       constexpr int kTestCpw = 4;

@@ -79,6 +79,8 @@ struct Job {
   int64_t mvwstot = 0;
   GemmTask* mvtasks_d = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipEvent_t ev_flag = nullptr;    // marks a read-back of flags into hflags
+  int32_t* hflags = nullptr;       // pinned host words for read-backs
   double sample_ms = 0.0, sample_flops = 0.0, total_ms = 0.0;
   double alloc_ms = 0.0;           // host time spent in device allocations (setup statistics)
   Prof prof;

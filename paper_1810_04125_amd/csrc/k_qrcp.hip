@@ -349,10 +349,17 @@ __global__ __launch_bounds__(QAL) void k_qrcp_alive(const QrcpTask* __restrict__
   }
 }
 
-// Pinned host words for the values read back at the host's decisions.
-static int32_t* host_words() {
+// Pinned, device-mapped host words for the values the host decides on:
+// the liveness poll writes them directly (no copy), the host reads them
+// after the stream has drained.  `dev` is the device-side address.
+static int32_t* host_words(int32_t** dev) {
   thread_local int32_t* p = nullptr;
-  if (!p) HSS_HIP_CHECK(hipHostMalloc((void**)&p, 64, 0));
+  thread_local int32_t* d = nullptr;
+  if (!p) {
+    HSS_HIP_CHECK(hipHostMalloc((void**)&p, 64, hipHostMallocMapped | hipHostMallocPortable));
+    HSS_HIP_CHECK(hipHostGetDevicePointer((void**)&d, p, 0));
+  }
+  *dev = d;
   return p;
 }
 
@@ -531,13 +538,13 @@ void run_qrcp(QrcpTask* tasks, int32_t ntasks, const QrcpWork& wk, const int2* w
   // polls (none before the first segment when a panel is known to be
   // active); profiling times each segment as a whole.  The poll that finds
   // no matrix alive also gives the largest rank.
-  int32_t* hw = host_words();
+  int32_t* hw_dev = nullptr;
+  int32_t* hw = host_words(&hw_dev);
   bool rank_known = false;
   const int ksteps = one_wg ? 0 : kmax;
   for (int k0 = 0; k0 < ksteps; k0 += 32) {
     if (k0 > 0 || !known_active) {
-      hipLaunchKernelGGL(k_qrcp_alive, dim3(1), dim3(QAL), 0, s, tasks, ntasks, k0, flag);
-      HSS_HIP_CHECK(hipMemcpyAsync(hw, flag, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      hipLaunchKernelGGL(k_qrcp_alive, dim3(1), dim3(QAL), 0, s, tasks, ntasks, k0, hw_dev);
       HSS_HIP_CHECK(hipStreamSynchronize(s));
       if (hw[0] == 0) {
         rank_known = true;
