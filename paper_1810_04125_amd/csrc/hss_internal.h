@@ -193,7 +193,7 @@ inline size_t qrcp_work_entries(int32_t max_tasks) { return (size_t)kQrcpTarget 
 // Factor the panels of `tasks` (dmax rows and at most ncols_max columns
 // each, by capacity): one workgroup per matrix for small panels, else one
 // launch per pivot step over a device-built work map.  `flag` points at
-// three int32 of device scratch.
+// one int32 of device scratch.
 void run_qrcp(QrcpTask* tasks, int32_t ntasks, const QrcpWork& wk, const int2* wg_trsm, int32_t ntrsm,
               int32_t kmax, int32_t dmax, int32_t ncols_max, int32_t* flag, GemmTask* gtasks, int32_t mcap_max,
               hipStream_t s, unsigned long long* kcnt = nullptr, bool solve_e = true, double* gws = nullptr);
@@ -202,10 +202,10 @@ void run_qrcp(QrcpTask* tasks, int32_t ntasks, const QrcpWork& wk, const int2* w
 // pivot step, summed over the tall panels, reach kQrFirstMinCells: below
 // that the steps are bound by launch latency rather than by their
 // traffic, and the reduction's own launches would not pay.
-// Returns the number of active panels (`flag`: three int32 of scratch).
+// Returns the number of active panels.
 constexpr int64_t kQrFirstMinCells = int64_t(2) << 20;
-int32_t run_qr_first(QrcpTask* tasks, int32_t ntasks, int32_t dmax, int32_t mcap_max, int32_t* flag,
-                     GemmTask* gtasks, double* gws, hipStream_t s, unsigned long long* kcnt);
+int32_t run_qr_first(QrcpTask* tasks, int32_t ntasks, int32_t dmax, int32_t mcap_max, GemmTask* gtasks,
+                     double* gws, hipStream_t s, unsigned long long* kcnt);
 void run_qform(QformTask* tasks, int32_t count, const int2* wg, int32_t nwg, int32_t cpw, int32_t ncmax,
                int32_t mmax, GemmTask* gt, double* gws, hipStream_t s, unsigned long long* kcnt);
 

@@ -529,7 +529,7 @@ void run_qrcp(QrcpTask* tasks, int32_t ntasks, const QrcpWork& wk, const int2* w
     hipLaunchKernelGGL(k_qrcp_init, dim3(nwg), dim3(QB), 0, s, tasks, wk.chunks, wk.meta);
     prof_end(HSS_K_QRCP_OTHER, s);
     if (solve_e && dmax >= 128) {
-      const int32_t nact = run_qr_first(tasks, ntasks, dmax, ncols_max, flag, gtasks, gws, s, kcnt);
+      const int32_t nact = run_qr_first(tasks, ntasks, dmax, ncols_max, gtasks, gws, s, kcnt);
       if (nact == 0) return;   // no panel to factor
       known_active = true;
     }

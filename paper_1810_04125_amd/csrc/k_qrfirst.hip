@@ -57,16 +57,50 @@ __device__ __forceinline__ double qrf_wsum(double v) {
 }  // namespace
 
 // out[0]: the largest m among the tall panels; out[1]: the cells the
-// reduction takes out of the first pivot step, (d - m) m summed over them,
-// in units of 1024; out[2]: the number of active panels
-__global__ void k_qrf_scan(const QrcpTask* __restrict__ tasks, int ntasks, int32_t* __restrict__ out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < ntasks && tasks[i].active) atomicAdd(out + 2, 1);
-  if (i < ntasks && qrf_tall(tasks[i])) {
+// reduction takes out of the first pivot step, (d - m) m summed over them;
+// out[2]: the number of active panels.  One workgroup; writes its result
+// directly (out may be mapped host memory).
+constexpr int QRS = 1024;
+__global__ __launch_bounds__(QRS) void k_qrf_scan(const QrcpTask* __restrict__ tasks, int ntasks,
+                                                 int64_t* __restrict__ out) {
+  __shared__ int64_t s0[QRS / 64], s1[QRS / 64], s2[QRS / 64];
+  int64_t mt = 0, cells = 0, act = 0;
+  for (int i = threadIdx.x; i < ntasks; i += QRS) {
     const QrcpTask& t = tasks[i];
-    atomicMax(out, t.m);
-    atomicAdd(out + 1, (int32_t)(((int64_t)(t.d - t.m) * t.m) >> 10));
+    act += t.active ? 1 : 0;
+    if (qrf_tall(t)) {
+      mt = max(mt, (int64_t)t.m);
+      cells += (int64_t)(t.d - t.m) * t.m;
+    }
   }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    mt = max(mt, (int64_t)__shfl_xor(mt, o, 64));
+    cells += __shfl_xor(cells, o, 64);
+    act += __shfl_xor(act, o, 64);
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) { s0[wv] = mt; s1[wv] = cells; s2[wv] = act; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t a = 0, b = 0, c = 0;
+    for (int w = 0; w < QRS / 64; ++w) { a = max(a, s0[w]); b += s1[w]; c += s2[w]; }
+    out[0] = a;
+    out[1] = b;
+    out[2] = c;
+  }
+}
+
+// Pinned, device-mapped host words for the scan's result.
+static int64_t* scan_words(int64_t** dev) {
+  thread_local int64_t* p = nullptr;
+  thread_local int64_t* d = nullptr;
+  if (!p) {
+    HSS_HIP_CHECK(hipHostMalloc((void**)&p, 64, hipHostMallocMapped | hipHostMallocPortable));
+    HSS_HIP_CHECK(hipHostGetDevicePointer((void**)&d, p, 0));
+  }
+  *dev = d;
+  return p;
 }
 
 // Householder factorization of columns [c, c1) over rows c..d-1, one
@@ -259,16 +293,16 @@ __global__ __launch_bounds__(256) void k_qrf_finish(QrcpTask* __restrict__ tasks
   if (threadIdx.x == 0) t.d = m;
 }
 
-int32_t run_qr_first(QrcpTask* tasks, int32_t ntasks, int32_t dmax, int32_t mcap_max, int32_t* flag,
-                     GemmTask* gtasks, double* gws, hipStream_t s, unsigned long long* kcnt) {
+int32_t run_qr_first(QrcpTask* tasks, int32_t ntasks, int32_t dmax, int32_t mcap_max, GemmTask* gtasks,
+                     double* gws, hipStream_t s, unsigned long long* kcnt) {
   if (ntasks <= 0) return 0;
-  int32_t scan[3] = {0, 0, 0};
-  HSS_HIP_CHECK(hipMemsetAsync(flag, 0, 3 * sizeof(int32_t), s));
-  hipLaunchKernelGGL(k_qrf_scan, dim3((ntasks + 127) / 128), dim3(128), 0, s, tasks, ntasks, flag);
-  HSS_HIP_CHECK(hipMemcpyAsync(scan, flag, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  int64_t* sw_dev = nullptr;
+  int64_t* sw = scan_words(&sw_dev);
+  hipLaunchKernelGGL(k_qrf_scan, dim3(1), dim3(QRS), 0, s, tasks, ntasks, sw_dev);
   HSS_HIP_CHECK(hipStreamSynchronize(s));
-  const int32_t mtall = scan[0];
-  if (mtall <= 0 || ((int64_t)scan[1] << 10) < kQrFirstMinCells) return scan[2];
+  const int32_t mtall = (int32_t)sw[0];
+  const int32_t nact = (int32_t)sw[2];
+  if (mtall <= 0 || sw[1] < kQrFirstMinCells) return nact;
   const int64_t split_ws = gws ? kGemmSplitElems : 0;
   for (int c = 0; c < mtall; c += NBQ) {
     prof_begin(s);
@@ -289,7 +323,7 @@ int32_t run_qr_first(QrcpTask* tasks, int32_t ntasks, int32_t dmax, int32_t mcap
   hipLaunchKernelGGL(k_qrf_finish, dim3(ntasks), dim3(256), 0, s, tasks);
   prof_end(HSS_K_QRCP_OTHER, s);
   HSS_HIP_CHECK(hipGetLastError());
-  return scan[2];
+  return nact;
 }
 
 }  // namespace hss
