@@ -745,8 +745,16 @@ void Job::run_level(int lev, int32_t ncap) {
         for (int s = 0; s < nsides; ++s)
           launch_fnorm_test(a, s, it, L.mcap, std::max(L.qcap, 1), nb, ts, stream);
     }
-    launch_decide_fnorm(a, stream);
-    id_phase(0);
+    // A node passes only through a test of this round (a side that passed
+    // earlier passed with the other, and the node compressed then) or when
+    // its problem is forced: without either no node can go, and the ID of
+    // the level, with its host round trips, is skipped.  The decision
+    // kernel reports a node that goes anyway (checked after the round).
+    bool any_force = false;
+    for (const Problem& P : probs) any_force = any_force || (P.force && !P.done);
+    const bool skip_id = nblk == 0 && !any_force;
+    launch_decide_fnorm(a, stream, skip_id ? flags_d + 2 : nullptr);
+    if (!skip_id) id_phase(0);
   }
   for (int s = 0; s < nsides; ++s) launch_reduce(a, s, L.mcap, L.rcap, nc, stream);
   launch_finalize(a, stream);
@@ -798,6 +806,7 @@ void Job::compress() {
     HSS_HIP_CHECK(hipMemcpyAsync(flags, flags_d, sizeof(flags), hipMemcpyDeviceToHost, stream));
     HSS_HIP_CHECK(hipStreamSynchronize(stream));
     if (flags[0]) throw Error(HSS_ERR_NONFINITE, "non-finite matrix entry generated");
+    if (flags[2]) throw Error(HSS_ERR_INTERNAL, "a node passed in a level whose factorization was skipped");
     bool all_done = true;
     sample_begin();
     for (size_t k = 0; k < probs.size(); ++k) {

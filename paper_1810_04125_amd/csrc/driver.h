@@ -64,8 +64,9 @@ struct Job {
   NodeState* st_d = nullptr;
   ProbDev* prob_d = nullptr;
   GemmTask* tasks_d = nullptr;
-  // [0] non-finite entry seen, [1] largest block count of a level, [3] the
-  // stopping test's factorization scratch, [4] the ID's
+  // [0] non-finite entry seen, [1] largest block count of a level, [2] a
+  // node passed in a level whose ID was skipped, [3] the stopping test's
+  // factorization scratch, [4] the ID's
   int32_t* flags_d = nullptr;
   int32_t* nodes_d = nullptr;
   QrcpTask* qtasks_d = nullptr;

@@ -320,7 +320,7 @@ struct TestScratch {
 };
 void launch_fnorm_test(const LevelArgs& a, int side, int32_t iter, int32_t mcap_max,
                        int32_t qcap_max, int32_t ncap, const TestScratch& ts, hipStream_t s);
-void launch_decide_fnorm(const LevelArgs& a, hipStream_t s);
+void launch_decide_fnorm(const LevelArgs& a, hipStream_t s, int32_t* unexpected = nullptr);
 void launch_build_qrcp(const LevelArgs& a, int side, int32_t hmt, QrcpTask* out, hipStream_t s);
 void launch_decide_hmt(const LevelArgs& a, hipStream_t s);
 void launch_reduce(const LevelArgs& a, int side, int32_t mcap_max, int32_t rcap_max,

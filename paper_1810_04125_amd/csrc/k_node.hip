@@ -713,7 +713,10 @@ void launch_fnorm_test(const LevelArgs& a, int side, int32_t iter, int32_t mcap_
   run_qform(ts.qf, a.count, ts.wg, ts.nwg, ts.cpw, ncap, mcap_max, ts.gt, a.gws, s, a.kcnt);
 }
 
-__global__ void k_decide_fnorm(LevelArgs a) {
+// `unexpected` (when not null): the host skips this level's ID because no
+// node ran a test and none is forced, so none can pass; a node that does
+// is reported there.
+__global__ void k_decide_fnorm(LevelArgs a, int32_t* unexpected) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= a.count) return;
   const int g = a.nodes[t];
@@ -722,12 +725,13 @@ __global__ void k_decide_fnorm(LevelArgs a) {
   const ProbDev& P = a.prob[a.desc[g].prob];
   const bool ok = st.passed[0] && (P.symmetric || st.passed[1]);
   st.go = (ok || P.force) ? 1 : 0;
+  if (st.go && unexpected) atomicOr(unexpected, 1);
 }
 
-void launch_decide_fnorm(const LevelArgs& a, hipStream_t s) {
+void launch_decide_fnorm(const LevelArgs& a, hipStream_t s, int32_t* unexpected) {
   if (a.count <= 0) return;
   prof_begin(s);
-  hipLaunchKernelGGL(k_decide_fnorm, dim3((a.count + 127) / 128), dim3(128), 0, s, a);
+  hipLaunchKernelGGL(k_decide_fnorm, dim3((a.count + 127) / 128), dim3(128), 0, s, a, unexpected);
   prof_end(HSS_K_MISC, s);
 }
 
