@@ -202,10 +202,17 @@ void run_qrcp(QrcpTask* tasks, int32_t ntasks, const QrcpWork& wk, const int2* w
 // pivot step, summed over the tall panels, reach kQrFirstMinCells: below
 // that the steps are bound by launch latency rather than by their
 // traffic, and the reduction's own launches would not pay.
-// Returns the number of active panels.
 constexpr int64_t kQrFirstMinCells = int64_t(2) << 20;
-int32_t run_qr_first(QrcpTask* tasks, int32_t ntasks, int32_t dmax, int32_t mcap_max, GemmTask* gtasks,
-                     double* gws, hipStream_t s, unsigned long long* kcnt);
+// Host-synchronous scan of the panels of a factorization call: the largest
+// m and the summed (d - m) m of the tall ones, and the number of active ones.
+struct QrfScan {
+  int32_t mtall = 0;
+  int64_t cells = 0;
+  int32_t nact = 0;
+};
+QrfScan qrf_scan(const QrcpTask* tasks, int32_t ntasks, hipStream_t s);
+void run_qr_first(QrcpTask* tasks, int32_t ntasks, int32_t dmax, int32_t mcap_max, const QrfScan& sc,
+                  GemmTask* gtasks, double* gws, hipStream_t s, unsigned long long* kcnt);
 void run_qform(QformTask* tasks, int32_t count, const int2* wg, int32_t nwg, int32_t cpw, int32_t ncmax,
                int32_t mmax, GemmTask* gt, double* gws, hipStream_t s, unsigned long long* kcnt);
 

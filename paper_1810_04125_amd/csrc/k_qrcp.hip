@@ -517,8 +517,25 @@ void run_qrcp(QrcpTask* tasks, int32_t ntasks, const QrcpWork& wk, const int2* w
   if (ntasks > wk.max_tasks) throw Error(HSS_ERR_INTERNAL, "QRCP work map too small for the batch");
   const int nwg = kQrcpTarget + ntasks;
   const size_t lds = (size_t)std::max(dmax, 1) * sizeof(double);
-  const bool one_wg = (int64_t)std::max(dmax, 1) * std::max(ncols_max, 1) <= kQrcpWgCells && lds <= 48 * 1024;
-  bool known_active = false;   // some panel is known to be active
+  // The ID first counts its active panels (and finds the tall ones): with
+  // none it is done, and the count picks the factorization kernel.
+  QrfScan sc;
+  if (solve_e) {
+    sc = qrf_scan(tasks, ntasks, s);
+    if (sc.nact == 0) return;
+  }
+  const bool known_active = solve_e;   // some panel is known to be active
+  const int64_t cells = (int64_t)std::max(dmax, 1) * std::max(ncols_max, 1);
+  bool one_wg = cells <= kQrcpWgCells && lds <= 48 * 1024;
+  if (one_wg && solve_e) {
+    // Per pivot step, the one-workgroup kernel walks the columns 16 at a
+    // time (about 5 + 2.2 us per 16 columns, measured); the many-workgroup
+    // step costs about 7 us, or its traffic at about 3.4 TB/s when larger
+    // (2.35 ps per cell of all active panels).
+    const double t_wg = 5.0 + 2.2 * std::ceil(ncols_max / 16.0);
+    const double t_step = std::max(7.0, 2.35e-6 * (double)sc.nact * (double)cells);
+    one_wg = t_wg < t_step;
+  }
   if (one_wg) {
     prof_begin(s);
     hipLaunchKernelGGL(k_qrcp_wg, dim3(ntasks), dim3(QBW), lds, s, tasks, kcnt);
@@ -528,11 +545,7 @@ void run_qrcp(QrcpTask* tasks, int32_t ntasks, const QrcpWork& wk, const int2* w
     hipLaunchKernelGGL(k_qrcp_plan, dim3(1), dim3(QB), 0, s, tasks, ntasks, kQrcpTarget, wk.chunks, wk.meta);
     hipLaunchKernelGGL(k_qrcp_init, dim3(nwg), dim3(QB), 0, s, tasks, wk.chunks, wk.meta);
     prof_end(HSS_K_QRCP_OTHER, s);
-    if (solve_e && dmax >= 128) {
-      const int32_t nact = run_qr_first(tasks, ntasks, dmax, ncols_max, gtasks, gws, s, kcnt);
-      if (nact == 0) return;   // no panel to factor
-      known_active = true;
-    }
+    if (solve_e && dmax >= 128) run_qr_first(tasks, ntasks, dmax, ncols_max, sc, gtasks, gws, s, kcnt);
   }
   // pivot steps: launched back to back in segments of 32 after liveness
   // polls (none before the first segment when a panel is known to be

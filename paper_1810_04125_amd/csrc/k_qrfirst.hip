@@ -293,16 +293,23 @@ __global__ __launch_bounds__(256) void k_qrf_finish(QrcpTask* __restrict__ tasks
   if (threadIdx.x == 0) t.d = m;
 }
 
-int32_t run_qr_first(QrcpTask* tasks, int32_t ntasks, int32_t dmax, int32_t mcap_max, GemmTask* gtasks,
-                     double* gws, hipStream_t s, unsigned long long* kcnt) {
-  if (ntasks <= 0) return 0;
+QrfScan qrf_scan(const QrcpTask* tasks, int32_t ntasks, hipStream_t s) {
+  QrfScan r;
+  if (ntasks <= 0) return r;
   int64_t* sw_dev = nullptr;
   int64_t* sw = scan_words(&sw_dev);
   hipLaunchKernelGGL(k_qrf_scan, dim3(1), dim3(QRS), 0, s, tasks, ntasks, sw_dev);
   HSS_HIP_CHECK(hipStreamSynchronize(s));
-  const int32_t mtall = (int32_t)sw[0];
-  const int32_t nact = (int32_t)sw[2];
-  if (mtall <= 0 || sw[1] < kQrFirstMinCells) return nact;
+  r.mtall = (int32_t)sw[0];
+  r.cells = sw[1];
+  r.nact = (int32_t)sw[2];
+  return r;
+}
+
+void run_qr_first(QrcpTask* tasks, int32_t ntasks, int32_t dmax, int32_t mcap_max, const QrfScan& sc,
+                  GemmTask* gtasks, double* gws, hipStream_t s, unsigned long long* kcnt) {
+  const int32_t mtall = sc.mtall;
+  if (ntasks <= 0 || mtall <= 0 || sc.cells < kQrFirstMinCells) return;
   const int64_t split_ws = gws ? kGemmSplitElems : 0;
   for (int c = 0; c < mtall; c += NBQ) {
     prof_begin(s);
@@ -323,7 +330,6 @@ int32_t run_qr_first(QrcpTask* tasks, int32_t ntasks, int32_t dmax, int32_t mcap
   hipLaunchKernelGGL(k_qrf_finish, dim3(ntasks), dim3(256), 0, s, tasks);
   prof_end(HSS_K_QRCP_OTHER, s);
   HSS_HIP_CHECK(hipGetLastError());
-  return nact;
 }
 
 }  // namespace hss
