@@ -63,6 +63,7 @@ Job::~Job() {
   if (ev1) hipEventDestroy(ev1);
   if (ev_flag) hipEventDestroy(ev_flag);
   if (hflags) hipHostFree(hflags);
+  if (sched_h) hipHostFree(sched_h);
   if (prof.e0) hipEventDestroy(prof.e0);
   if (prof.e1) hipEventDestroy(prof.e1);
 }
@@ -583,8 +584,16 @@ void Job::setup(int32_t count, const hss_generator* gens, const hss_tree* const*
     pd.sglob[1] = P.sglob[1];
     pd.R = P.opt.R;
     pd.ldr = P.opt.ldr;
-    P.sched_d = (int32_t*)dalloc(sizeof(int32_t) * (P.dcap + 2));
-    pd.sched = P.sched_d;
+  }
+  // sampling schedules of all problems in one device array (one copy per
+  // round from a pinned staging array)
+  sched_stride = 2;
+  for (const Problem& P : probs) sched_stride = std::max(sched_stride, (int64_t)P.dcap + 2);
+  sched_all_d = (int32_t*)dalloc(sizeof(int32_t) * sched_stride * probs.size());
+  HSS_HIP_CHECK(hipHostMalloc((void**)&sched_h, sizeof(int32_t) * sched_stride * probs.size(), 0));
+  for (size_t k = 0; k < probs.size(); ++k) {
+    probs[k].sched_d = sched_all_d + sched_stride * (int64_t)k;
+    probs[k].dev.sched = probs[k].sched_d;
   }
   HSS_HIP_CHECK(hipGetLastError());
 }
@@ -703,8 +712,7 @@ void Job::run_level(int lev, int32_t ncap) {
   a.gws = gemm_ws;
   const int nsides = all_sym ? 1 : 2;
   const int32_t nc = std::min(ncap, L.dcap);
-  HSS_HIP_CHECK(hipMemsetAsync(flags_d + 1, 0, sizeof(int32_t), stream));
-  launch_plan(a, stream);
+  launch_plan(a, stream);   // flags_d[1] is zero here: set up so, reset by each level's finalize
   // the number of test blocks is read back while the extraction and the
   // local samples run
   const bool fnorm = strategy != HSS_DBL_HMT;
@@ -790,7 +798,7 @@ void Job::compress() {
       P.dev.force = P.force;
       P.dev.done = P.done;
       P.dev.nsched = (int32_t)P.sched.size();
-      HSS_HIP_CHECK(hipMemcpy(P.sched_d, P.sched.data(), sizeof(int32_t) * P.sched.size(), hipMemcpyHostToDevice));
+      std::memcpy(sched_h + sched_stride * (int64_t)k, P.sched.data(), sizeof(int32_t) * P.sched.size());
       for (size_t i = 0; i < P.sched.size(); ++i)
         max_block = std::max(max_block, P.sched[i] - (i ? P.sched[i - 1] : 0));
       pdev[k] = P.dev;
@@ -799,6 +807,8 @@ void Job::compress() {
         P.rounds++;
       }
     }
+    HSS_HIP_CHECK(hipMemcpyAsync(sched_all_d, sched_h, sizeof(int32_t) * sched_stride * probs.size(),
+                                 hipMemcpyHostToDevice, stream));
     HSS_HIP_CHECK(hipMemcpyAsync(prob_d, pdev.data(), sizeof(ProbDev) * pdev.size(), hipMemcpyHostToDevice, stream));
     for (int lev = maxlevel; lev >= 0; --lev) run_level(lev, ncap);
     for (size_t k = 0; k < probs.size(); ++k)

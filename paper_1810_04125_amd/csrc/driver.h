@@ -80,6 +80,9 @@ struct Job {
   GemmTask* mvtasks_d = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   hipEvent_t ev_flag = nullptr;    // marks a read-back of flags into hflags
+  int32_t* sched_all_d = nullptr;  // sampling schedules, sched_stride int32 per problem
+  int32_t* sched_h = nullptr;      // their pinned staging copy
+  int64_t sched_stride = 0;
   int32_t* hflags = nullptr;       // pinned host words for read-backs
   double sample_ms = 0.0, sample_flops = 0.0, total_ms = 0.0;
   double alloc_ms = 0.0;           // host time spent in device allocations (setup statistics)

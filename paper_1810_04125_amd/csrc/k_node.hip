@@ -870,6 +870,7 @@ void launch_reduce(const LevelArgs& a, int side, int32_t mcap_max, int32_t rcap_
 // ------------------------------------------------------------------ finalize
 __global__ void k_finalize(LevelArgs a) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t == 0) a.flags[1] = 0;   // the next level's test block count starts from zero
   if (t >= a.count) return;
   const int g = a.nodes[t];
   NodeState& st = a.st[g];
