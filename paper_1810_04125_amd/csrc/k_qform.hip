@@ -88,11 +88,13 @@ __global__ __launch_bounds__(QFB) void k_qf_prep(const QformTask* __restrict__ t
   }
 }
 
-// M = S^{-1} V_1^T (b x b) by right-looking back substitution over the
-// whole workgroup (rows of M become final from the bottom up), held in LDS
-// with G for b <= QF_LDS_B and in the workspace otherwise; then the GEMM
-// task Q_k -= V M.  Thread (row group pg, column j) updates column j of the
-// rows pg, pg + QFS/64, ... of each step.
+// M = S^{-1} V_1^T (b x b; S and V_1^T are upper triangular, so is M).
+// For b <= QF_LDS_B: right-looking back substitution over the whole
+// workgroup, M and G in LDS, rows of M final from the bottom up; then the
+// GEMM task Q_k -= V M.  Thread (row group pg, column j) updates column j
+// of the rows pg, pg + QFS/64, ... of each step.  For wider blocks this
+// kernel only lays out M = V_1^T (column-major) and the blocked solve below
+// finishes it.
 constexpr int QFS = 1024;
 constexpr int QF_LDS_B = 64;
 constexpr int QF_RG = QFS / 64;   // row groups
@@ -108,11 +110,16 @@ __global__ __launch_bounds__(QFS) void k_qf_solve(const QformTask* __restrict__ 
   const int b = t.nc;
   const bool in_lds = b <= QF_LDS_B;
   double* Mg = t.wk + (int64_t)b * b;          // M, b x b column-major
-  // working copies: R row-major b x b, G column-major b x b
-  double* R = in_lds ? Rl : Mg;
-  const double* G = in_lds ? Gl : t.wk;
+  const HSS_GLOBAL double* gW = gview(t.W);
+  if (!in_lds) {
+    // M(l, j) = V(j, l) for j >= l, else 0, column-major
+    HSS_GLOBAL double* gM = gview_w(Mg);
+    for (int j = threadIdx.x / 64; j < b; j += QFS / 64)
+      for (int l = threadIdx.x & 63; l < b; l += 64) gM[(int64_t)j * b + l] = j >= l ? gW[(int64_t)l * t.ldw + j] : 0.0;
+    return;
+  }
   {
-    const HSS_GLOBAL double* gW = gview(t.W);
+    // working copies: R row-major b x b, G column-major b x b
     const HSS_GLOBAL double* gG = gview(t.wk);
     constexpr int LU = 4;
     const int tot = b * b;
@@ -130,8 +137,8 @@ __global__ __launch_bounds__(QFS) void k_qf_solve(const QformTask* __restrict__ 
         const int idx = base + u * QFS;
         if (idx < tot) {
           const int l = idx / b, j = idx - l * b;
-          R[idx] = j >= l ? rv[u] : 0.0;
-          if (in_lds) Gl[idx] = gv[u];
+          Rl[idx] = j >= l ? rv[u] : 0.0;
+          Gl[idx] = gv[u];
         }
       }
     }
@@ -140,47 +147,111 @@ __global__ __launch_bounds__(QFS) void k_qf_solve(const QformTask* __restrict__ 
   const int jl = threadIdx.x & 63, pg = threadIdx.x >> 6;
   for (int l = b - 1; l >= 0; --l) {
     // row l is final: divide by S_ll = G_ll / 2
-    const double inv = 2.0 / G[(int64_t)l * b + l];
-    for (int j = threadIdx.x; j < b; j += QFS) R[l * b + j] *= inv;
+    const double inv = 2.0 / Gl[l * b + l];
+    for (int j = threadIdx.x; j < b; j += QFS) Rl[l * b + j] *= inv;
     __syncthreads();
-    // rows p < l: R(p, :) -= S(p, l) R(l, :), S(p, l) = G(p, l); in LDS the
-    // rows of a thread are unrolled so that their reads are in flight together
-    if (in_lds) {
-      if (jl < b) {
-        const double rl = Rl[l * b + jl];
+    // rows p < l: R(p, :) -= S(p, l) R(l, :), S(p, l) = G(p, l); the rows of
+    // a thread are unrolled so that their reads are in flight together
+    if (jl < b) {
+      const double rl = Rl[l * b + jl];
 #pragma unroll
-        for (int u = 0; u < QF_LDS_B / QF_RG; ++u) {
-          const int p = pg + QF_RG * u;
-          const int pc = min(p, QF_LDS_B - 1);
-          const double v = Rl[pc * b + jl] - Gl[l * b + pc] * rl;
-          if (p < l) Rl[pc * b + jl] = v;
-        }
+      for (int u = 0; u < QF_LDS_B / QF_RG; ++u) {
+        const int p = pg + QF_RG * u;
+        const int pc = min(p, QF_LDS_B - 1);
+        const double v = Rl[pc * b + jl] - Gl[l * b + pc] * rl;
+        if (p < l) Rl[pc * b + jl] = v;
       }
-    } else {
-      for (int j = jl; j < b; j += 64)
-        for (int p = pg; p < l; p += QF_RG) R[p * b + j] -= G[(int64_t)l * b + p] * R[l * b + j];
     }
     __syncthreads();
   }
   // M column-major for the GEMM
-  if (in_lds) {
-    HSS_GLOBAL double* gM = gview_w(Mg);
-    for (int idx = threadIdx.x; idx < b * b; idx += QFS) {
-      const int l = idx / b, j = idx - l * b;
-      gM[(int64_t)j * b + l] = Rl[idx];
-    }
+  HSS_GLOBAL double* gM = gview_w(Mg);
+  for (int idx = threadIdx.x; idx < b * b; idx += QFS) {
+    const int l = idx / b, j = idx - l * b;
+    gM[(int64_t)j * b + l] = Rl[idx];
   }
   if (threadIdx.x == 0) {
     GemmTask q;
     q.A = t.W; q.a_rs = 1; q.a_cs = t.ldw;   // V
-    q.B = Mg;
-    if (in_lds) { q.b_rs = 1; q.b_cs = b; } else { q.b_rs = b; q.b_cs = 1; }   // M(l, j)
+    q.B = Mg; q.b_rs = 1; q.b_cs = b;        // M(l, j)
     q.C = t.Q; q.c_rs = 1; q.c_cs = t.ldq;
     q.M = t.m; q.N = b; q.K = b; q.pad = 0;
     q.alpha = -1.0; q.beta = 1.0;
     *g = q;
     const double bb = b;
     kcount(kcnt, HSS_K_QFORM, 8.0 * 2.0 * bb * bb, bb * bb * bb);
+  }
+}
+
+// Blocked back substitution for the blocks wider than QF_LDS_B: diagonal
+// block ib (rows i0 = 64 ib ... i1) of S M = V_1^T, every column of M on its
+// own thread (the 64 x 64 block of S in LDS, the column's 64 entries in
+// registers); the workgroup with blockIdx.y == 0 then writes the GEMM task
+// of the update of the rows above, M(0:i0, i0:b) -= S(0:i0, i0:i1) M(i0:i1, i0:b)
+// (into gu), and with ib == 0 the final task Q_k -= V M (into gf).
+constexpr int QFD = 64;
+__global__ __launch_bounds__(256) void k_qf_diag(const QformTask* __restrict__ tasks, int ib,
+                                                 GemmTask* __restrict__ gu, GemmTask* __restrict__ gf,
+                                                 unsigned long long* __restrict__ kcnt) {
+  __shared__ double Sd[QFD][QFD + 1];
+  const QformTask& t = tasks[blockIdx.x];
+  const bool wide = t.active && t.wk && t.nc > QF_LDS_B;
+  const int b = t.nc;
+  const int i0 = ib * QFD;
+  if (blockIdx.y == 0 && threadIdx.x == 0) gu[blockIdx.x].M = 0;
+  if (!wide || i0 >= b) return;
+  const int i1 = min(b, i0 + QFD), nb = i1 - i0;
+  const double* G = t.wk;                        // b x b column-major
+  double* M = t.wk + (int64_t)b * b;             // b x b column-major
+  const HSS_GLOBAL double* gG = gview(G);
+  for (int idx = threadIdx.x; idx < QFD * QFD; idx += 256) {
+    const int r = idx % QFD, c = idx / QFD;
+    double v = 0.0;
+    if (r < nb && c < nb && r <= c) {
+      v = gG[(int64_t)(i0 + c) * b + i0 + r];
+      if (r == c) v *= 0.5;                      // S_ll = G_ll / 2
+    }
+    Sd[r][c] = v;
+  }
+  __syncthreads();
+  const int j = i0 + blockIdx.y * 256 + threadIdx.x;   // columns j < i0 are zero in these rows
+  if (j < b) {
+    HSS_GLOBAL double* col = gview_w(M + (int64_t)j * b + i0);
+    double x[QFD];
+#pragma unroll
+    for (int u = 0; u < QFD; ++u) x[u] = u < nb ? col[u] : 0.0;
+#pragma unroll
+    for (int l = QFD - 1; l >= 0; --l) {
+      if (l < nb) {
+        const double xl = x[l] / Sd[l][l];
+        x[l] = xl;
+#pragma unroll
+        for (int p = 0; p < l; ++p) x[p] -= Sd[p][l] * xl;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < QFD; ++u)
+      if (u < nb) col[u] = x[u];
+  }
+  if (blockIdx.y != 0 || threadIdx.x != 0) return;
+  const double bb = b, nn = nb;
+  kcount(kcnt, HSS_K_QFORM, 16.0 * nn * bb, nn * nn * bb);
+  if (i0 > 0) {
+    GemmTask q;
+    q.A = G + (int64_t)i0 * b; q.a_rs = 1; q.a_cs = b;   // S(0:i0, i0:i1) = G(0:i0, i0:i1)
+    q.B = M + (int64_t)i0 * b + i0; q.b_rs = 1; q.b_cs = b;   // M(i0:i1, i0:b); its columns < i0 are zero
+    q.C = M + (int64_t)i0 * b; q.c_rs = 1; q.c_cs = b;        // M(0:i0, i0:b)
+    q.M = i0; q.N = b - i0; q.K = nb; q.pad = 0;
+    q.alpha = -1.0; q.beta = 1.0;
+    gu[blockIdx.x] = q;
+  } else {
+    GemmTask q;
+    q.A = t.W; q.a_rs = 1; q.a_cs = t.ldw;               // V
+    q.B = M; q.b_rs = 1; q.b_cs = b;                     // M(l, j), column-major
+    q.C = t.Q; q.c_rs = 1; q.c_cs = t.ldq;
+    q.M = t.m; q.N = b; q.K = b; q.pad = 0;
+    q.alpha = -1.0; q.beta = 1.0;
+    gf[blockIdx.x] = q;
   }
 }
 
@@ -196,6 +267,17 @@ void run_qform(QformTask* tasks, int32_t count, const int2* wg, int32_t nwg, int
   prof_begin(s);
   hipLaunchKernelGGL(k_qf_solve, dim3((unsigned)count), dim3(QFS), 0, s, tasks, gt, kcnt);
   prof_end(HSS_K_QFORM, s);
+  if (ncmax > QF_LDS_B) {
+    // blocks of 64 rows from the bottom; updates on the matrix cores (their
+    // tasks in the second half of gt, the final tasks stay in the first)
+    const unsigned gy = (unsigned)((ncmax + 255) / 256);
+    for (int ib = (ncmax + QFD - 1) / QFD - 1; ib >= 0; --ib) {
+      prof_begin(s);
+      hipLaunchKernelGGL(k_qf_diag, dim3((unsigned)count, gy), dim3(256), 0, s, tasks, ib, gt + count, gt, kcnt);
+      prof_end(HSS_K_QFORM, s);
+      if (ib > 0) launch_gemm(gt + count, count, ib * QFD, ncmax, s, kcnt, QFD, gws, kGemmSplitElems);
+    }
+  }
   launch_gemm(gt, count, mmax, ncmax, s, kcnt);
   if (nwg > 0) {
     prof_begin(s);

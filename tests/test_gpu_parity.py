@@ -281,3 +281,20 @@ def test_compress_large_first_block_tall_panels(strategy):
     oh = ocompress(op, ot, R, 1e-6, 1e-12, strategy, d0=1024, delta_d=64, eta=0.1)
     _compare(H, oh, ot, gen, op, T, 1e-6)
     assert H.info()["rounds"] == oh.rounds
+
+
+@pytest.mark.parametrize("family,n,leaf,dd", [("laplace", 2048, 128, 100), ("gauss", 2048, 256, 200)])
+def test_compress_inc_wide_ragged_blocks_rounds(family, n, leaf, dd):
+    """Test blocks wider than 64 columns and not a multiple of 64: the
+    triangular solve for Q_k (Sec. 3.2) runs in 64-row diagonal blocks with
+    the updates on the matrix cores and a ragged last block; the rounds and
+    the compressed nodes must match the oracle's."""
+    _log("compress %s %d inc dd=%d" % (family, n, dd))
+    gen, T, ot, op = problem(family, n, leaf, seed=3)
+    R = inputs.gaussian_matrix(n, 1200, 1)
+    H, st = hss.compress(gen, T, dev_colmajor(R), rtol=1e-6, atol=1e-12, eta=0.1, strategy="inc_fnorm",
+                         d0=dd, delta_d=dd)
+    oh = ocompress(op, ot, R, 1e-6, 1e-12, "inc_fnorm", d0=dd, delta_d=dd, eta=0.1)
+    _compare(H, oh, ot, gen, op, T, 1e-6)
+    assert H.info()["rounds"] == oh.rounds
+    assert H.info()["d_final"] == oh.d
