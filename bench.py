@@ -91,9 +91,9 @@ WORKLOADS = {
 TRAFFIC = {
     ("laplace-sphere-32768", "QRCP_STEP"): {
         "source": "paper_1810_04125_amd/csrc/k_qrcp.hip",
-        "sha256": "372086dfed55ee350e67bd9accc2ada9b0bd5427df21861b47d880a5a5f14c3e",
-        "fetch_kib": 8467.049, "write_kib": 13331.651,            # k_qrcp_step, 17376 dispatches
-        "fetch_scale": 1048576.0 / 524302.313, "write_scale": 1.0,  # 1 GiB copy: FETCH 524302 KiB, WRITE 1048576 KiB
+        "sha256": "adf35a7e6268e1257417f39b823069e2023bdf65d4c573faceb54ea368b0af76",
+        "fetch_kib": 8401.816, "write_kib": 13248.489,            # k_qrcp_step, 17920 dispatches
+        "fetch_scale": 1048576.0 / 524302.458, "write_scale": 1.0,  # 1 GiB copy: FETCH 524302 KiB, WRITE 1048576 KiB
     },
 }
 
