@@ -712,17 +712,26 @@ void Job::run_level(int lev, int32_t ncap) {
   a.gws = gemm_ws;
   const int nsides = all_sym ? 1 : 2;
   const int32_t nc = std::min(ncap, L.dcap);
-  launch_plan(a, stream);   // flags_d[1] is zero here: set up so, reset by each level's finalize
-  // the number of test blocks is read back while the extraction and the
-  // local samples run
-  const bool fnorm = strategy != HSS_DBL_HMT;
-  if (fnorm) {
-    HSS_HIP_CHECK(hipMemcpyAsync(hflags, flags_d + 1, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
-    HSS_HIP_CHECK(hipEventRecord(ev_flag, stream));
-  }
+  launch_plan(a, stream);   // flags_d[1], [5], [6] are zero here: set up so, reset by each level's finalize
+  // The level's test block count, largest column count and largest row
+  // count are read back while the extraction runs.  The capacities alone
+  // would size the GEMMs of the local samples for all d columns and
+  // capacity rows, though most nodes take only the newest block; launched
+  // that large, their K dimension is not split.
+  HSS_HIP_CHECK(hipMemcpyAsync(hflags, flags_d + 1, 6 * sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+  HSS_HIP_CHECK(hipEventRecord(ev_flag, stream));
   if (has_callback) extract_callbacks(lev);
   launch_extract_nodes(a, stream);
-  for (int s = 0; s < nsides; ++s) launch_local_samples(a, s, L.mcap, L.rcap, nc, stream);
+  HSS_HIP_CHECK(hipEventSynchronize(ev_flag));
+  const int32_t nblk = hflags[0];
+  const int32_t lv_nc = std::max(1, std::min(nc, hflags[4]));
+  const int32_t lv_m = std::max(1, std::min(L.mcap, hflags[5]));
+  // local samples: T0 has M = left rows (at most lv_m), K = right rank or the leaf size
+  for (int s = 0; s < nsides; ++s) launch_local_samples(a, s, lv_m, std::min(L.rcap, lv_m), lv_nc, stream);
+  int32_t max_b = 1;
+  for (const Problem& P : probs)
+    if (!P.done) max_b = std::max(max_b, P.b);
+  int32_t red_nc = nc;
   auto id_phase = [&](int hmt) {
     for (int s = 0; s < nsides; ++s) {
       launch_build_qrcp(a, s, hmt, qtasks_d, stream);
@@ -734,8 +743,6 @@ void Job::run_level(int lev, int32_t ncap) {
     id_phase(1);
     launch_decide_hmt(a, stream);
   } else {
-    HSS_HIP_CHECK(hipEventSynchronize(ev_flag));
-    const int32_t nblk = hflags[0];
     if (nblk > 0) {
       const int32_t nb = std::min(max_block, L.dcap);
       constexpr int kTestCpw = 4;
@@ -751,7 +758,7 @@ void Job::run_level(int lev, int32_t ncap) {
       TestScratch ts{qtasks_d, qform_d, chol_d, L.wg_test, L.ntest, kTestCpw, flags_d + 3, tasks_d, qwork};
       for (int it = 0; it < nblk; ++it)
         for (int s = 0; s < nsides; ++s)
-          launch_fnorm_test(a, s, it, L.mcap, std::max(L.qcap, 1), nb, ts, stream);
+          launch_fnorm_test(a, s, it, lv_m, std::max(1, std::min(L.qcap, lv_m)), nb, ts, stream);
     }
     // A node passes only through a test of this round (a side that passed
     // earlier passed with the other, and the node compressed then) or when
@@ -763,8 +770,11 @@ void Job::run_level(int lev, int32_t ncap) {
     const bool skip_id = nblk == 0 && !any_force;
     launch_decide_fnorm(a, stream, skip_id ? flags_d + 2 : nullptr);
     if (!skip_id) id_phase(0);
+    red_nc = skip_id ? std::min(nc, max_b) : nc;
   }
-  for (int s = 0; s < nsides; ++s) launch_reduce(a, s, L.mcap, L.rcap, nc, stream);
+  // reduce (M = rank, K = rows - rank): a node compressed earlier takes its
+  // problem's newest block, one compressed now all d columns
+  for (int s = 0; s < nsides; ++s) launch_reduce(a, s, lv_m, std::min(L.rcap, lv_m), red_nc, stream);
   launch_finalize(a, stream);
   HSS_HIP_CHECK(hipGetLastError());
 }

@@ -66,7 +66,8 @@ struct Job {
   GemmTask* tasks_d = nullptr;
   // [0] non-finite entry seen, [1] largest block count of a level, [2] a
   // node passed in a level whose ID was skipped, [3] the stopping test's
-  // factorization scratch, [4] the ID's
+  // factorization scratch, [4] the ID's, [5] and [6] largest column count
+  // and local-sample row count of a level's active nodes
   int32_t* flags_d = nullptr;
   int32_t* nodes_d = nullptr;
   QrcpTask* qtasks_d = nullptr;

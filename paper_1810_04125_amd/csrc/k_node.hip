@@ -134,6 +134,9 @@ __global__ void k_plan(LevelArgs a) {
   for (int s = 0; s < 2; ++s)
     st.m[s] = nd.leaf ? (nd.hi - nd.lo) : a.st[nd.left].rank[s] + a.st[nd.right].rank[s];
   if (P.symmetric) st.m[1] = st.m[0];
+  // the level's largest column count and row count size its GEMM launches
+  atomicMax(a.flags + 5, st.nc);
+  atomicMax(a.flags + 6, max(st.m[0], st.m[1]));
   st.test = st.state != COMPRESSED;
   if (!st.test) return;
   if (st.fresh) {
@@ -870,7 +873,11 @@ void launch_reduce(const LevelArgs& a, int side, int32_t mcap_max, int32_t rcap_
 // ------------------------------------------------------------------ finalize
 __global__ void k_finalize(LevelArgs a) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t == 0) a.flags[1] = 0;   // the next level's test block count starts from zero
+  if (t == 0) {   // the next level's test block count and sizes start from zero
+    a.flags[1] = 0;
+    a.flags[5] = 0;
+    a.flags[6] = 0;
+  }
   if (t >= a.count) return;
   const int g = a.nodes[t];
   NodeState& st = a.st[g];
