@@ -735,8 +735,9 @@ void Job::run_level(int lev, int32_t ncap) {
   auto id_phase = [&](int hmt) {
     for (int s = 0; s < nsides; ++s) {
       launch_build_qrcp(a, s, hmt, qtasks_d, stream);
-      run_qrcp(qtasks_d, a.count, qwork, L.wg_trsm, L.ntrsm, std::min(L.mcap, ncap), ncap, L.mcap, flags_d + 4,
-               tasks_d, L.mcap, stream, kcnt_d, true, gemm_ws);
+      // panels of P.d <= ncap rows and st.m <= lv_m columns
+      run_qrcp(qtasks_d, a.count, qwork, L.wg_trsm, L.ntrsm, std::min(lv_m, ncap), ncap, lv_m, flags_d + 4,
+               tasks_d, lv_m, stream, kcnt_d, true, gemm_ws);
     }
   };
   if (strategy == HSS_DBL_HMT) {
@@ -744,16 +745,20 @@ void Job::run_level(int lev, int32_t ncap) {
     launch_decide_hmt(a, stream);
   } else {
     if (nblk > 0) {
-      const int32_t nb = std::min(max_block, L.dcap);
+      // widest block of any schedule; with a single block to test, every
+      // node tests its problem's newest block (a node tested before) or
+      // its only one (the first round), at most max_b wide
+      const int32_t nb_all = std::min(max_block, L.dcap);
+      const int32_t nb = nblk == 1 ? std::min(nb_all, max_b) : nb_all;
       constexpr int kTestCpw = 4;
-      if (L.test_ncap != nb) {   // workgroup map: kTestCpw block columns per workgroup
-        std::vector<int32_t> caps(L.nodes.size(), nb);
+      if (L.test_ncap != nb_all) {   // workgroup map: kTestCpw block columns per workgroup
+        std::vector<int32_t> caps(L.nodes.size(), nb_all);
         QrcpPlan qp = make_qrcp_plan(caps, kTestCpw);
         if (L.wg_test == nullptr || (int32_t)qp.step.size() > L.ntest)
           L.wg_test = (int2*)dalloc(sizeof(int2) * qp.step.size());
         HSS_HIP_CHECK(hipMemcpy(L.wg_test, qp.step.data(), sizeof(int2) * qp.step.size(), hipMemcpyHostToDevice));
         L.ntest = (int32_t)qp.step.size();
-        L.test_ncap = nb;
+        L.test_ncap = nb_all;
       }
       TestScratch ts{qtasks_d, qform_d, chol_d, L.wg_test, L.ntest, kTestCpw, flags_d + 3, tasks_d, qwork};
       for (int it = 0; it < nblk; ++it)
