@@ -177,8 +177,9 @@ struct QrcpPlan {
   std::vector<int2> trsm;   // (task, first column of E) per workgroup of the solve
 };
 QrcpPlan make_qrcp_plan(const std::vector<int32_t>& mcaps, int cpw = QCPW);
-// Busy workgroups aimed at by every pivot-step launch (4 per compute unit).
-constexpr int kQrcpTarget = 1024;
+// Busy workgroups aimed at by every pivot-step launch (5 per compute unit:
+// more waves keep more column loads in flight; 4 and 7 per unit were slower).
+constexpr int kQrcpTarget = 1280;
 // Panels of at most this many cells (rows x columns, by capacity) are
 // factored by one workgroup each in a single launch.
 constexpr int64_t kQrcpWgCells = 64 * 1024;
