@@ -713,24 +713,30 @@ void Job::run_level(int lev, int32_t ncap) {
   const int nsides = all_sym ? 1 : 2;
   const int32_t nc = std::min(ncap, L.dcap);
   launch_plan(a, stream);   // flags_d[1], [5], [6] are zero here: set up so, reset by each level's finalize
+  int32_t max_b = 1;
+  for (const Problem& P : probs)
+    if (!P.done) max_b = std::max(max_b, P.b);
   // The level's test block count, largest column count and largest row
   // count are read back while the extraction runs.  The capacities alone
   // would size the GEMMs of the local samples for all d columns and
   // capacity rows, though most nodes take only the newest block; launched
-  // that large, their K dimension is not split.
+  // that large, their K dimension is not split.  The local samples wait for
+  // the counts only where d is well above the newest block (a host round
+  // trip costs more than it saves on small levels); the later launches of
+  // the level use them in any case.
   HSS_HIP_CHECK(hipMemcpyAsync(hflags, flags_d + 1, 6 * sizeof(int32_t), hipMemcpyDeviceToHost, stream));
   HSS_HIP_CHECK(hipEventRecord(ev_flag, stream));
   if (has_callback) extract_callbacks(lev);
   launch_extract_nodes(a, stream);
-  HSS_HIP_CHECK(hipEventSynchronize(ev_flag));
+  const bool wait_counts = nc > 2 * max_b;
+  if (wait_counts) HSS_HIP_CHECK(hipEventSynchronize(ev_flag));
+  const int32_t ls_nc = wait_counts ? std::max(1, std::min(nc, hflags[4])) : nc;
+  const int32_t ls_m = wait_counts ? std::max(1, std::min(L.mcap, hflags[5])) : L.mcap;
+  // local samples: T0 has M = left rows (at most ls_m), K = right rank or the leaf size
+  for (int s = 0; s < nsides; ++s) launch_local_samples(a, s, ls_m, std::min(L.rcap, ls_m), ls_nc, stream);
+  if (!wait_counts) HSS_HIP_CHECK(hipEventSynchronize(ev_flag));
   const int32_t nblk = hflags[0];
-  const int32_t lv_nc = std::max(1, std::min(nc, hflags[4]));
   const int32_t lv_m = std::max(1, std::min(L.mcap, hflags[5]));
-  // local samples: T0 has M = left rows (at most lv_m), K = right rank or the leaf size
-  for (int s = 0; s < nsides; ++s) launch_local_samples(a, s, lv_m, std::min(L.rcap, lv_m), lv_nc, stream);
-  int32_t max_b = 1;
-  for (const Problem& P : probs)
-    if (!P.done) max_b = std::max(max_b, P.b);
   int32_t red_nc = nc;
   auto id_phase = [&](int hmt) {
     for (int s = 0; s < nsides; ++s) {
