@@ -92,8 +92,8 @@ TRAFFIC = {
     ("laplace-sphere-32768", "QRCP_STEP"): {
         "source": "paper_1810_04125_amd/csrc/k_qrcp.hip",
         "sha256": "adf35a7e6268e1257417f39b823069e2023bdf65d4c573faceb54ea368b0af76",
-        "fetch_kib": 8401.816, "write_kib": 13248.489,            # k_qrcp_step, 17920 dispatches
-        "fetch_scale": 1048576.0 / 524302.458, "write_scale": 1.0,  # 1 GiB copy: FETCH 524302 KiB, WRITE 1048576 KiB
+        "fetch_kib": 8614.458, "write_kib": 13431.852,            # k_qrcp_step, 17664 dispatches
+        "fetch_scale": 1048576.0 / 524302.438, "write_scale": 1.0,  # 1 GiB copy: FETCH 524302 KiB, WRITE 1048576 KiB
     },
 }
 
