@@ -36,7 +36,14 @@ Readings of points the paper leaves open (the HIP path uses the same):
   * pivot ties go to the lowest row index; residual norms are recomputed
     exactly at every step (no downdating);
   * ID stops at the first pivot with norm <= threshold (eq. RRQRHMTstop
-    uses <=); the F-norm tests use strict < (eq. stopping_criteria).
+    uses <=); the F-norm tests use strict < (eq. stopping_criteria);
+  * the HMT-lemma test (eq. HMT_IQQH, strategy inc_hmt) takes the columns
+    of the block under test as the Gaussian vectors omega_i (p = block
+    width) and the projection (I - QQ^T) of Alg. 5 with the basis Q of the
+    blocks tested before; it passes iff alpha sqrt(2/pi) max_i ||.||_2 <=
+    eps_a (the paper's <=).  It has no relative tolerance: eps_r = 0 in
+    the test and in the ID.  A projected block whose QR has an exactly
+    zero diagonal entry passes, as in the F-norm test.
 """
 from __future__ import annotations
 
@@ -48,7 +55,7 @@ from scipy.linalg import solve_triangular
 
 UNTOUCHED, PARTIALLY_COMPRESSED, COMPRESSED = 0, 1, 2
 
-STRATEGIES = ("dbl_fnorm", "inc_fnorm", "dbl_hmt")
+STRATEGIES = ("dbl_fnorm", "inc_fnorm", "dbl_hmt", "inc_hmt")
 
 
 # ---------------------------------------------------------------------------
@@ -175,6 +182,40 @@ def fnorm_test(st: FnormSide, S_new: np.ndarray, d: int, eps_r: float, eps_a: fl
     return False
 
 
+def hmt_lemma_test(st: FnormSide, S_new: np.ndarray, d: int, eps_a: float, alpha: float) -> bool:
+    """Stopping test of eq. HMT_IQQH: by Lemma 4.1 of Halko, Martinsson and
+    Tropp, ||(I - QQ^T) F||_2 <= alpha sqrt(2/pi) max_i ||(I - QQ^T) F w_i||_2
+    except with probability alpha^-p.  The columns of S_new are the samples
+    F w_i of the block's p = b Gaussian vectors; Q is the orthonormal basis
+    of the blocks tested before (Alg. 5 bookkeeping)."""
+    if st.passed:
+        return True
+    m, b = S_new.shape
+    if d >= m:
+        st.passed = True
+        return True
+    Q = st.Q if st.Q is not None else np.zeros((m, 0))
+    Sh = S_new - Q @ (Q.T @ S_new)          # block Gram-Schmidt, twice
+    Sh = Sh - Q @ (Q.T @ Sh)
+    worst = float(np.max(np.linalg.norm(Sh, axis=0))) if b > 0 else 0.0
+    if alpha * math.sqrt(2.0 / math.pi) * worst <= eps_a:
+        st.passed = True
+        return True
+    Qk, Rk = np.linalg.qr(Sh, mode="reduced")
+    if float(np.abs(np.diag(Rk)).min()) == 0.0:
+        st.passed = True
+        return True
+    # Columns of S_hat at rounding level (the block is numerically rank
+    # deficient) give directions of Qk that are not orthogonal to Q after
+    # normalisation; Gram-Schmidt against Q twice more and a second QR keep
+    # [Q Qk] orthonormal (such directions are then arbitrary but harmless).
+    Qk = Qk - Q @ (Q.T @ Qk)
+    Qk = Qk - Q @ (Q.T @ Qk)
+    Qk, _ = np.linalg.qr(Qk, mode="reduced")
+    st.Q = np.hstack([Q, Qk])
+    return False
+
+
 # ---------------------------------------------------------------------------
 # HSS node payload and the adaptive driver (Alg. 2, Alg. 3)
 # ---------------------------------------------------------------------------
@@ -224,12 +265,13 @@ class HSS:
 
 
 class _Compressor:
-    def __init__(self, op, tree, R, rtol, atol, strategy, d0, delta_d, p, d_max, eta):
+    def __init__(self, op, tree, R, rtol, atol, strategy, d0, delta_d, p, d_max, eta, alpha=10.0):
         if strategy not in STRATEGIES:
             raise ValueError("strategy must be one of %s" % (STRATEGIES,))
         self.op, self.tree, self.Rall = op, tree, R
         self.rtol, self.atol, self.strategy = rtol, atol, strategy
         self.d0, self.delta_d, self.p, self.eta = d0, delta_d, p, eta
+        self.alpha = alpha
         self.N = tree.n
         self.d_max = min(d_max if d_max is not None else self.N, R.shape[1])
         self.nodes = [Node() for _ in range(tree.num_nodes)]
@@ -248,7 +290,8 @@ class _Compressor:
 
     def eps(self, t: int):
         lev = int(self.tree.level[t])
-        return self.eta * self.rtol / lev, self.eta * self.atol / lev
+        er = 0.0 if self.strategy == "inc_hmt" else self.eta * self.rtol / lev   # absolute only
+        return er, self.eta * self.atol / lev
 
     # -- Alg. 2 ComputeLocalSamples -------------------------------------
     def local_samples(self, t: int, cols: np.ndarray):
@@ -328,7 +371,10 @@ class _Compressor:
             for c0, c1 in blocks:
                 if passed or c1 <= c0:
                     break
-                passed = fnorm_test(st, S[:, c0:c1], c1, er, ea)
+                if self.strategy == "inc_hmt":
+                    passed = hmt_lemma_test(st, S[:, c0:c1], c1, ea, self.alpha)
+                else:
+                    passed = fnorm_test(st, S[:, c0:c1], c1, er, ea)
             ok.append(passed)
         if all(ok) or self.force:
             nd.idr = interpolative(nd.Sr, er, ea)
@@ -400,14 +446,15 @@ class _Compressor:
 
 
 def compress(op, tree, R, rtol=1e-6, atol=1e-12, strategy="dbl_fnorm", d0=64,
-             delta_d=64, p=10, d_max=None, eta=1.0) -> HSS:
+             delta_d=64, p=10, d_max=None, eta=1.0, alpha=10.0) -> HSS:
     """Adaptive HSS compression of the permuted operator `op` (Alg. 3).
 
     R is the N x d_cap Gaussian matrix (rows in permuted order); its
-    columns are consumed in order, so d never exceeds d_cap.
+    columns are consumed in order, so d never exceeds d_cap.  `alpha` is
+    the factor of the HMT-lemma test (strategy inc_hmt).
     """
     return _Compressor(op, tree, np.asarray(R), rtol, atol, strategy, d0,
-                       delta_d, p, d_max, eta).run()
+                       delta_d, p, d_max, eta, alpha).run()
 
 
 def compress_fixed(op, tree, R, d, rtol=1e-6, atol=1e-12, eta=1.0) -> HSS:

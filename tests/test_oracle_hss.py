@@ -6,7 +6,7 @@ import pytest
 from scipy.linalg import qr
 
 from oracle.hss import (COMPRESSED, FnormSide, compress, compress_fixed, fnorm_test,
-                        hmt_factor, interpolative)
+                        hmt_factor, hmt_lemma_test, interpolative)
 from oracle.matvec import dense_from_generators, hss_matvec, rel_error
 from oracle.operators import Dense, Laplace, PermutedOperator, Toeplitz
 from oracle.tree import build_tree
@@ -86,6 +86,51 @@ def test_fnorm_test_projection_and_rank_deficiency():
     assert fnorm_test(FnormSide(), np.zeros((30, 4)), 4, 1e-8, 0.0)
 
 
+def test_hmt_lemma_test_by_hand():
+    """eq. HMT_IQQH on a 4 x 2 block with Q = e1: the projected columns are
+    0.1 e2 and 0.2 e3, so the statistic is alpha sqrt(2/pi) * 0.2 (the
+    F-norm of the block, 0.2236, or its unprojected column norm, 1.005,
+    would decide differently)."""
+    e1 = np.array([[1.0], [0.0], [0.0], [0.0]])
+    S = np.array([[1.0, 0.0], [0.1, 0.0], [0.0, 0.2], [0.0, 0.0]])
+    c = math.sqrt(2.0 / math.pi) * 0.2
+    for alpha in (1.0, 10.0):
+        assert hmt_lemma_test(FnormSide(Q=e1.copy()), S, 3, alpha * c * (1 + 1e-12), alpha)
+        assert hmt_lemma_test(FnormSide(Q=e1.copy()), S, 3, alpha * c, alpha)   # the bound is <=
+        st = FnormSide(Q=e1.copy())
+        assert not hmt_lemma_test(st, S, 3, alpha * c * (1 - 1e-9), alpha)
+        # failing appends an orthonormal basis of the projected block
+        assert st.Q.shape == (4, 3)
+        assert np.allclose(st.Q.T @ st.Q, np.eye(3), atol=1e-14)
+        assert np.allclose(np.abs(st.Q[:, 1:]), np.array([[0, 0], [1, 0], [0, 1], [0, 0]]), atol=1e-14)
+    # the shortcut d >= m and an exactly rank-deficient projected block pass
+    assert hmt_lemma_test(FnormSide(), S, 4, 0.0, 10.0)
+    assert hmt_lemma_test(FnormSide(Q=e1.copy()), np.array([[0.0, 0.0], [0.3, 0.6], [0.0, 0.0], [0.0, 0.0]]),
+                          3, 0.0, 10.0)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_hmt_lemma_pass_bounds_the_spectral_error(seed):
+    """Lemma 4.1: when the test passes, ||(I - QQ^T) F||_2 <= eps (failure
+    probability alpha^-p = 1e-8 here); exact spectral norms by SVD."""
+    rng = np.random.default_rng(100 + seed)
+    m, n = 90, 300
+    F = _lowrank(m, n, 40, 200 + seed, decay=0.6)
+    st = FnormSide()
+    eps = 1e-5 * np.linalg.norm(F, 2)
+    d, passed = 0, False
+    while not passed and d < m:
+        S = F @ rng.standard_normal((n, 8))
+        d += 8
+        Q0 = st.Q
+        passed = hmt_lemma_test(st, S, d, eps, 10.0)
+    assert passed and d < m
+    Q = Q0 if Q0 is not None else np.zeros((m, 0))
+    err = np.linalg.norm(F - Q @ (Q.T @ F), 2)
+    assert err <= eps
+    assert Q.shape[1] >= 8   # blocks failed before the pass: the bound was exercised
+
+
 # --------------------------------------------------------------------- full driver
 def _toeplitz_problem(n=1024, leaf=64, h=0.1):
     T = build_tree(n, leaf)
@@ -131,7 +176,8 @@ def _planted(n, r, seed):
 
 
 @pytest.mark.parametrize("strategy,r,d0,dd", [("inc_fnorm", 20, 8, 8), ("inc_fnorm", 5, 16, 16),
-                                              ("dbl_fnorm", 20, 8, 0), ("dbl_hmt", 20, 8, 0)])
+                                              ("dbl_fnorm", 20, 8, 0), ("dbl_hmt", 20, 8, 0),
+                                              ("inc_hmt", 20, 8, 8)])
 def test_planted_rank(strategy, r, d0, dd):
     """I + U V^T: every Hankel block has rank exactly r; rounds are predictable."""
     n, leaf = 512, 64
@@ -139,12 +185,22 @@ def test_planted_rank(strategy, r, d0, dd):
     A = _planted(n, r, 40)
     op = PermutedOperator(Dense(A), T.perm)
     R = inputs.gaussian_matrix(n, 256, 9)
-    h = compress(op, T, R, 1e-8, 1e-14, strategy, d0=d0, delta_d=dd)
+    # the HMT-lemma test is absolute only: rounding of the projected block
+    # (about 1e-15 of its norm) must stay below atol
+    atol = 1e-10 if strategy == "inc_hmt" else 1e-14
+    h = compress(op, T, R, 1e-8, atol, strategy, d0=d0, delta_d=dd)
     for t in range(1, T.num_nodes):
         assert h.nodes[t].rank_r == r and h.nodes[t].rank_c == r, t
     if strategy == "inc_fnorm":
         k = 0
         while d0 + k * dd <= r:
+            k += 1
+        assert h.rounds == k + 1
+    elif strategy == "inc_hmt":
+        # no R-diagonal test: the block that completes the range still fails
+        # (its projection is not small); the next one lies in the span
+        k = 1
+        while d0 + (k - 1) * dd < r:
             k += 1
         assert h.rounds == k + 1
     elif strategy == "dbl_fnorm":
@@ -158,6 +214,26 @@ def test_planted_rank(strategy, r, d0, dd):
             k += 1
         assert h.rounds == k + 1
     assert rel_error(h, op) < 1e-12
+
+
+def test_inc_hmt_ignores_rtol_and_alpha_is_monotone():
+    """The HMT-lemma test has an absolute tolerance only; a larger alpha
+    asks for more samples, so it never gives smaller ranks (Table HMT's
+    HMT row: ranks above the F-norm test's at equal atol)."""
+    T, op = _toeplitz_problem(512, 64)
+    R = inputs.gaussian_matrix(T.n, 512, 3)
+    kw = dict(strategy="inc_hmt", d0=16, delta_d=16)
+    a = compress(op, T, R, 1e-2, 1e-8, **kw)
+    b = compress(op, T, R, 1e-12, 1e-8, **kw)
+    assert a.ranks() == b.ranks() and a.rounds == b.rounds
+    for t in range(1, T.num_nodes):
+        assert np.array_equal(a.nodes[t].idr.J, b.nodes[t].idr.J)
+    lo = compress(op, T, R, 0.0, 1e-8, alpha=1.0, **kw)
+    hi = compress(op, T, R, 0.0, 1e-8, alpha=100.0, **kw)
+    assert hi.rounds >= lo.rounds and hi.d >= lo.d
+    assert rel_error(hi, op) <= rel_error(lo, op) * (1 + 1e-9) or hi.hss_rank() >= lo.hss_rank()
+    f = compress(op, T, R, 0.0, 1e-8, strategy="inc_fnorm", d0=16, delta_d=16)
+    assert b.d >= f.d
 
 
 def test_block_diagonal_gives_rank_zero():
