@@ -104,7 +104,12 @@ typedef int32_t (*hss_extract_fn)(void* ctx, int32_t nblocks, const hss_block* b
 typedef enum {
   HSS_DBL_FNORM = 0, /* doubling, block Gram-Schmidt F-norm test (eq. stopping_criteria) */
   HSS_INC_FNORM = 1, /* incrementing by delta_d, same test (Alg. 5) */
-  HSS_DBL_HMT = 2    /* doubling, RRQR with the HMT factor, accept iff r < d - p (Alg. 4) */
+  HSS_DBL_HMT = 2,   /* doubling, RRQR with the HMT factor, accept iff r < d - p (Alg. 4) */
+  HSS_INC_HMT = 3    /* incrementing by delta_d, test of eq. HMT_IQQH (Sec. 3.1, Lemma 4.1 of
+                        Halko, Martinsson and Tropp): a side passes when hmt_alpha sqrt(2/pi)
+                        times the largest 2-norm of the newest block's columns projected off
+                        the basis of the earlier blocks is <= eta*atol/level; absolute
+                        tolerance only (rtol is not used, by the test or by the ID) */
 } hss_strategy;
 
 /* Arithmetic of the sampling product A R (the ID and the tests stay FP64). */
@@ -172,8 +177,10 @@ void hss_tree_free(hss_tree* tree);
  *                eta*rtol/level(tau) and eta*atol/level(tau)
  *   eta        : global safety factor on the per-node tolerance (1 = literal)
  *   d0         : initial number of random vectors
- *   delta_d    : increment (HSS_INC_FNORM)
+ *   delta_d    : increment (HSS_INC_FNORM, HSS_INC_HMT)
  *   oversample_p : p of the HMT acceptance r < d - p (HSS_DBL_HMT)
+ *   hmt_alpha  : alpha of eq. HMT_IQQH (HSS_INC_HMT; 0 = 10): the bound holds
+ *                except with probability alpha^-p, p = delta_d
  *   d_max      : cap on the number of random vectors; <= ncols_R
  *   R, ldr, ncols_R : device, the n x ncols_R Gaussian matrix the method
  *                draws from, rows in PERMUTED order; columns are consumed
@@ -194,6 +201,7 @@ typedef struct {
   int32_t ncols_R;
   int32_t profile;   /* 1: time every kernel launch with HIP events (slower; see hss_get_kernel_stats) */
   void* stream;
+  double hmt_alpha;
 } hss_options;
 
 typedef struct hss_matrix hss_matrix;

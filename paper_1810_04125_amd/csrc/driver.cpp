@@ -268,9 +268,11 @@ static void validate(const hss_generator& g, const hss_tree* t, const hss_option
   if (g.family == HSS_FAM_GAUSS && !(g.sigma > 0.0)) throw Error(HSS_ERR_INVALID_ARG, who + "gauss needs sigma > 0");
   if (!(o.rtol >= 0.0) || !(o.atol >= 0.0) || !(o.eta > 0.0))
     throw Error(HSS_ERR_INVALID_ARG, who + "need rtol >= 0, atol >= 0, eta > 0");
-  if (o.strategy < 0 || o.strategy > 2) throw Error(HSS_ERR_INVALID_ARG, who + "unknown strategy");
+  if (o.strategy < 0 || o.strategy > 3) throw Error(HSS_ERR_INVALID_ARG, who + "unknown strategy");
   if (o.d0 < 1 || o.d_max < 1) throw Error(HSS_ERR_INVALID_ARG, who + "need d0 >= 1 and d_max >= 1");
-  if (o.strategy == HSS_INC_FNORM && o.delta_d < 1) throw Error(HSS_ERR_INVALID_ARG, who + "need delta_d >= 1");
+  if ((o.strategy == HSS_INC_FNORM || o.strategy == HSS_INC_HMT) && o.delta_d < 1)
+    throw Error(HSS_ERR_INVALID_ARG, who + "need delta_d >= 1");
+  if (o.strategy == HSS_INC_HMT && !(o.hmt_alpha >= 0.0)) throw Error(HSS_ERR_INVALID_ARG, who + "need hmt_alpha >= 0");
   if (o.strategy == HSS_DBL_HMT && o.oversample_p < 0) throw Error(HSS_ERR_INVALID_ARG, who + "need p >= 0");
   if (!o.R || o.ldr < g.n || o.ncols_R < std::min<int64_t>(o.d_max, g.n))
     throw Error(HSS_ERR_INVALID_ARG, who + "R must be n x ncols_R with ncols_R >= min(d_max, n)");
@@ -569,8 +571,9 @@ void Job::setup(int32_t count, const hss_generator* gens, const hss_tree* const*
     pd.p = P.opt.oversample_p;
     pd.symmetric = P.sym;
     pd.n = P.n;
-    pd.eps_r = P.opt.eta * P.opt.rtol;
+    pd.eps_r = strategy == HSS_INC_HMT ? 0.0 : P.opt.eta * P.opt.rtol;   // HMT-lemma test: absolute only
     pd.eps_a = P.opt.eta * P.opt.atol;
+    pd.hmt_alpha = P.opt.hmt_alpha > 0.0 ? P.opt.hmt_alpha : 10.0;
     // precision floor of the relative thresholds for reduced-precision samples
     pd.eps_floor = P.opt.sample_precision == HSS_SAMPLE_FP32 ? kFloorFp32
                  : P.opt.sample_precision == HSS_SAMPLE_BF16X3 ? kFloorBf16x3 : 0.0;
@@ -769,7 +772,8 @@ void Job::run_level(int lev, int32_t ncap) {
       TestScratch ts{qtasks_d, qform_d, chol_d, L.wg_test, L.ntest, kTestCpw, flags_d + 3, tasks_d, qwork};
       for (int it = 0; it < nblk; ++it)
         for (int s = 0; s < nsides; ++s)
-          launch_fnorm_test(a, s, it, lv_m, std::max(1, std::min(L.qcap, lv_m)), nb, ts, stream);
+          launch_fnorm_test(a, s, it, lv_m, std::max(1, std::min(L.qcap, lv_m)), nb, ts, stream,
+                            strategy == HSS_INC_HMT);
     }
     // A node passes only through a test of this round (a side that passed
     // earlier passed with the other, and the node compressed then) or when
@@ -855,7 +859,7 @@ void Job::compress() {
         if (P.status == HSS_OK) P.status = HSS_NOT_CONVERGED;
         continue;
       }
-      int32_t b = strategy == HSS_INC_FNORM ? P.opt.delta_d : P.d;
+      int32_t b = (strategy == HSS_INC_FNORM || strategy == HSS_INC_HMT) ? P.opt.delta_d : P.d;
       b = std::min(b, P.dcap - P.d);
       sample(P, P.d, b);
       P.b = b;

@@ -95,7 +95,7 @@ struct NodeState {
   int32_t run[2];   // the current test iteration runs its QR on this side
   int32_t bc0, bnc; // columns of the block under test
   int32_t qrank;    // columns the QR of the projected block reached
-  int32_t pad2;
+  int32_t reo;      // HMT-lemma test: the block appended to Q on side reo - 1 awaits re-orthogonalization
   double rho[2];
 };
 
@@ -118,6 +118,7 @@ struct ProbDev {
   int32_t nsched;
   int32_t pad1;
   double eps_floor;      // lower bound of eps_r / level(tau) (sampling precision floor)
+  double hmt_alpha;      // alpha of the HMT-lemma test (HSS_INC_HMT)
   GenDev gen;
 };
 
@@ -326,8 +327,11 @@ struct TestScratch {
   GemmTask* gt;
   QrcpWork wk;         // device work map of the Householder QR
 };
+// One iteration of the stopping test on one side: the F-norm test of
+// Alg. 5, or with `hmt` the test of eq. HMT_IQQH (HSS_INC_HMT), whose
+// appended blocks are re-orthogonalized against the earlier basis.
 void launch_fnorm_test(const LevelArgs& a, int side, int32_t iter, int32_t mcap_max,
-                       int32_t qcap_max, int32_t ncap, const TestScratch& ts, hipStream_t s);
+                       int32_t qcap_max, int32_t ncap, const TestScratch& ts, hipStream_t s, bool hmt);
 void launch_decide_fnorm(const LevelArgs& a, hipStream_t s, int32_t* unexpected = nullptr);
 void launch_build_qrcp(const LevelArgs& a, int side, int32_t hmt, QrcpTask* out, hipStream_t s);
 void launch_decide_hmt(const LevelArgs& a, hipStream_t s);

@@ -118,6 +118,7 @@ __global__ void k_plan(LevelArgs a) {
   st.test = 0;
   st.need[0] = st.need[1] = 0;
   st.nc = 0;
+  st.reo = 0;
   if (P.done) return;
   if (st.state == COMPRESSED && nd.parent < 0) return;
   const bool kids = nd.leaf || (a.st[nd.left].state == COMPRESSED && a.st[nd.right].state == COMPRESSED);
@@ -444,9 +445,30 @@ __global__ __launch_bounds__(NBN) void k_fn_norms(LevelArgs a, int side, QrcpTas
   }
   const double nS = sqrt(block_sum_n<NBN>(p1, red));
   const double nSh = sqrt(block_sum_n<NBN>(p2, red));
+  const bool hmt = P.strategy == HSS_INC_HMT;
+  double cmax = 0.0;
+  if (hmt) {
+    // eq. HMT_IQQH: the largest column norm of S_hat, one wave per column
+    // (sums in lane order), the maximum over the waves
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    double wmax = 0.0;
+    for (int c = wv; c < nc; c += NBN / 64) {
+      double s2 = 0.0;
+      for (int i = lane; i < m; i += 64) {
+        const double v = gSh[(int64_t)c * ld + i];
+        s2 += v * v;
+      }
+      wmax = fmax(wmax, sqrt(wave_sum(s2)));
+    }
+    if (lane == 0) red[wv] = wmax;
+    __syncthreads();
+    for (int w = 0; w < NBN / 64; ++w) cmax = fmax(cmax, red[w]);
+  }
   if (threadIdx.x != 0) return;
   kcount(a.kcnt, HSS_K_TEST_NORMS, 16.0 * m * nc, 4.0 * m * nc);
-  if (nS == 0.0 || nSh < er * nS || nSh / sqrt((double)nc) < ea) {
+  const bool pass = hmt ? (nS == 0.0 || P.hmt_alpha * sqrt(2.0 / kPi) * cmax <= ea)
+                        : (nS == 0.0 || nSh < er * nS || nSh / sqrt((double)nc) < ea);
+  if (pass) {
     st.passed[side] = 1;
     st.run[side] = 0;
     return;
@@ -464,7 +486,8 @@ __global__ __launch_bounds__(NBN) void k_fn_norms(LevelArgs a, int side, QrcpTas
   // slot (mcap x dcap) holds S_hat, Q1, G, X and d1 side by side
   const int64_t blk = ((int64_t)ld * nc + 7) / 8 * 8;
   const int64_t sq = (int64_t)nc * nc;
-  if (nc <= kCholMaxB && 2 * blk + 2 * sq + nc + 16 <= (int64_t)ld * dcap) {
+  // (the HMT-lemma test appends every failing block: Householder path)
+  if (!hmt && nc <= kCholMaxB && 2 * blk + 2 * sq + nc + 16 <= (int64_t)ld * dcap) {
     CholTask c;
     c.S = Sh; c.lds = ld;
     c.Q1 = Sh + blk;
@@ -666,10 +689,12 @@ __global__ void k_fn_rtest(LevelArgs a, int side, QformTask* __restrict__ qf) {
   for (int k = 0; k < r; ++k) mn = fmin(mn, fabs(rdiag[k]));
   if (st.rho[side] < 0.0) st.rho[side] = r > 0 ? fabs(rdiag[0]) : 0.0;
   st.run[side] = 0;
-  if (r < nc || mn < ea || mn < er * st.rho[side]) {  // an exactly zero Rbar_ii also passes
+  const bool hmt = P.strategy == HSS_INC_HMT;   // no R-diagonal tests there
+  if (r < nc || (!hmt && (mn < ea || mn < er * st.rho[side]))) {  // an exactly zero Rbar_ii also passes
     st.passed[side] = 1;
     return;
   }
+  if (hmt) st.reo = side + 1;
   QformTask f;
   f.W = a.wsA + nd.ws; f.ldw = nd.mcap;
   f.rdiag = rdiag;
@@ -684,8 +709,98 @@ __global__ void k_fn_rtest(LevelArgs a, int side, QformTask* __restrict__ qf) {
   st.q[side] += nc;
 }
 
+// HMT-lemma test, after a failing block's Q_k was appended at columns
+// q - nc .. q of Q: columns of S_hat at rounding level give directions of
+// Q_k that are not orthogonal to the earlier basis once normalised.  Q_k
+// is projected off the earlier basis twice more (GEMM tasks as in
+// k_fn_copy) and factored again; the second Q replaces Q_k.
+__global__ __launch_bounds__(NB) void k_hmt_reo_copy(LevelArgs a, int side) {
+  const int t = blockIdx.x;
+  const int g = a.nodes[t];
+  const NodeDesc& nd = a.desc[g];
+  const NodeState& st = a.st[g];
+  GemmTask* TA = a.tasks + t;
+  GemmTask* TB = a.tasks + a.count + t;
+  const bool first = blockIdx.y == 0;
+  if (first && threadIdx.x == 0) {
+    TA->M = 0;
+    TB->M = 0;
+  }
+  if (st.reo != side + 1) return;
+  const int m = st.m[side], nc = st.bnc, q0 = st.q[side] - nc;
+  const double* Q = ctp(a, nd.Q[side]);
+  double* Sh = a.wsA + nd.ws;
+  copy_elems(m * nc, [&](int idx) {
+    const int i = idx % m, c = idx / m;
+    return CopyAt{gview(Q + (int64_t)(q0 + c) * nd.mcap + i), gview_w(Sh + (int64_t)c * nd.mcap + i)};
+  });
+  if (first && threadIdx.x == 0) {
+    double* W = a.wsB + nd.wsq;
+    GemmTask k;
+    k.pad = 0;
+    k.A = Q; k.a_rs = nd.mcap; k.a_cs = 1;     // W = Q(:, 0:q0)^T Sh
+    k.B = Sh; k.b_rs = 1; k.b_cs = nd.mcap;
+    k.C = W; k.c_rs = 1; k.c_cs = nd.qcap;
+    k.M = q0; k.N = nc; k.K = m; k.alpha = 1.0; k.beta = 0.0;
+    *TA = k;
+    k.A = Q; k.a_rs = 1; k.a_cs = nd.mcap;     // Sh -= Q(:, 0:q0) W
+    k.B = W; k.b_rs = 1; k.b_cs = nd.qcap;
+    k.C = Sh; k.c_rs = 1; k.c_cs = nd.mcap;
+    k.M = m; k.N = nc; k.K = q0; k.alpha = -1.0; k.beta = 1.0;
+    *TB = k;
+    kcount(a.kcnt, HSS_K_GATHER, 16.0 * m * nc, 0.0);
+  }
+}
+
+// Householder QR (no pivoting) of the re-projected block.
+__global__ void k_hmt_reo_qr(LevelArgs a, int side, QrcpTask* __restrict__ qt) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= a.count) return;
+  const int g = a.nodes[t];
+  const NodeDesc& nd = a.desc[g];
+  NodeState& st = a.st[g];
+  qt[t].active = 0;
+  if (st.reo != side + 1) return;
+  double* Sh = a.wsA + nd.ws;
+  const int ld = nd.mcap;
+  QrcpTask q;
+  q.S = Sh; q.lds = ld; q.W = Sh; q.ldw = ld;
+  q.scr = a.wsB + nd.wsq;
+  q.J = nullptr; q.E = nullptr; q.lde = 1;
+  q.rank_out = &st.qrank;
+  q.er = 0.0; q.ea = 0.0; q.hmt_mn = 0.0;
+  q.m = st.bnc; q.d = st.m[side]; q.mcap = st.bnc; q.active = 1;
+  q.nopivot = 1;
+  q.qrf = nullptr; q.qrf_elems = 0;
+  qt[t] = q;
+}
+
+// Explicit Q of that QR over Q_k's columns; the re-orthogonalization ends.
+__global__ void k_hmt_reo_form(LevelArgs a, int side, QformTask* __restrict__ qf) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= a.count) return;
+  const int g = a.nodes[t];
+  const NodeDesc& nd = a.desc[g];
+  NodeState& st = a.st[g];
+  qf[t].active = 0;
+  if (st.reo != side + 1) return;
+  st.reo = 0;
+  const ProbDev& P = a.prob[nd.prob];
+  const int m = st.m[side], nc = st.bnc;
+  if (st.qrank < nc) return;   // cannot happen for orthonormal input; Q_k is kept then
+  QformTask f;
+  f.W = a.wsA + nd.ws; f.ldw = nd.mcap;
+  f.rdiag = a.wsB + nd.wsq + 16 + 2 * (int64_t)nc;
+  f.Q = tp(a, nd.Q[side]) + (int64_t)(st.q[side] - nc) * nd.mcap; f.ldq = nd.mcap;
+  f.m = m; f.nc = nc; f.active = 1; f.pad = 0;
+  const int64_t used = ((int64_t)nd.mcap * nc + 7) / 8 * 8;
+  const int64_t room = (int64_t)nd.mcap * P.dcap - used;
+  f.wk = room >= 2 * (int64_t)nc * nc + 8 ? a.wsA + nd.ws + used : nullptr;
+  qf[t] = f;
+}
+
 void launch_fnorm_test(const LevelArgs& a, int side, int32_t iter, int32_t mcap_max, int32_t qcap_max,
-                       int32_t ncap, const TestScratch& ts, hipStream_t s) {
+                       int32_t ncap, const TestScratch& ts, hipStream_t s, bool hmt) {
   if (a.count <= 0) return;
   prof_begin(s);
   hipLaunchKernelGGL(k_fn_copy, node_grid(a.count), dim3(NB), 0, s, a, side, iter);
@@ -712,6 +827,22 @@ void launch_fnorm_test(const LevelArgs& a, int side, int32_t iter, int32_t mcap_
   run_qrcp(ts.qt, a.count, ts.wk, nullptr, 0, ncap, mcap_max, ncap, ts.flag, ts.gt, mcap_max, s, a.kcnt, false);
   prof_begin(s);
   hipLaunchKernelGGL(k_fn_rtest, dim3((a.count + 127) / 128), dim3(128), 0, s, a, side, ts.qf);
+  prof_end(HSS_K_TEST_NORMS, s);
+  run_qform(ts.qf, a.count, ts.wg, ts.nwg, ts.cpw, ncap, mcap_max, ts.gt, a.gws, s, a.kcnt);
+  if (!hmt) return;
+  prof_begin(s);
+  hipLaunchKernelGGL(k_hmt_reo_copy, node_grid(a.count), dim3(NB), 0, s, a, side);
+  prof_end(HSS_K_GATHER, s);
+  for (int pass = 0; pass < 2; ++pass) {
+    launch_gemm(a.tasks, a.count, qcap_max, ncap, s, a.kcnt, mcap_max, a.gws, kGemmSplitElems);
+    launch_gemm(a.tasks + a.count, a.count, mcap_max, ncap, s, a.kcnt, qcap_max, a.gws, kGemmSplitElems);
+  }
+  prof_begin(s);
+  hipLaunchKernelGGL(k_hmt_reo_qr, dim3((a.count + 127) / 128), dim3(128), 0, s, a, side, ts.qt);
+  prof_end(HSS_K_TEST_NORMS, s);
+  run_qrcp(ts.qt, a.count, ts.wk, nullptr, 0, ncap, mcap_max, ncap, ts.flag, ts.gt, mcap_max, s, a.kcnt, false);
+  prof_begin(s);
+  hipLaunchKernelGGL(k_hmt_reo_form, dim3((a.count + 127) / 128), dim3(128), 0, s, a, side, ts.qf);
   prof_end(HSS_K_TEST_NORMS, s);
   run_qform(ts.qf, a.count, ts.wg, ts.nwg, ts.cpw, ncap, mcap_max, ts.gt, a.gws, s, a.kcnt);
 }

@@ -18,7 +18,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libhss.so")
 
 FAMILY = {"toeplitz": 0, "laplace": 1, "gauss": 2, "dense": 3, "callback": 4}
-STRATEGY = {"dbl_fnorm": 0, "inc_fnorm": 1, "dbl_hmt": 2}
+STRATEGY = {"dbl_fnorm": 0, "inc_fnorm": 1, "dbl_hmt": 2, "inc_hmt": 3}
 PRECISION = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 TREE_METHOD = {"bisect": 0, "rcb": 1, "kd": 2}
 NODE = {"D": 0, "B12": 1, "B21": 2, "JR": 3, "JC": 4, "ER": 5, "EC": 6, "IR": 7, "IC": 8}
@@ -61,7 +61,7 @@ class _Opt(C.Structure):
                 ("strategy", C.c_int32), ("d0", C.c_int32), ("delta_d", C.c_int32),
                 ("oversample_p", C.c_int32), ("d_max", C.c_int32), ("sample_precision", C.c_int32),
                 ("R", C.c_void_p), ("ldr", C.c_int64), ("ncols_R", C.c_int32),
-                ("profile", C.c_int32), ("stream", C.c_void_p)]
+                ("profile", C.c_int32), ("stream", C.c_void_p), ("hmt_alpha", C.c_double)]
 
 
 class _Info(C.Structure):
@@ -417,7 +417,7 @@ class HSSMatrix:
         return e.value
 
 
-def _opts(R, rtol, atol, eta, strategy, d0, delta_d, p, d_max, precision, profile=False):
+def _opts(R, rtol, atol, eta, strategy, d0, delta_d, p, d_max, precision, profile=False, hmt_alpha=10.0):
     ldr = _colmajor(R, "R")
     o = _Opt()
     o.rtol, o.atol, o.eta = rtol, atol, eta
@@ -430,15 +430,16 @@ def _opts(R, rtol, atol, eta, strategy, d0, delta_d, p, d_max, precision, profil
     o.ncols_R = R.shape[1]
     o.profile = int(bool(profile))
     o.stream = _stream()
+    o.hmt_alpha = hmt_alpha
     return o
 
 
 def compress(gen: Generator, tree: Tree, R, rtol=1e-6, atol=1e-12, eta=1.0, strategy="dbl_fnorm",
-             d0=64, delta_d=64, p=10, d_max=None, precision="fp64", profile=False):
+             d0=64, delta_d=64, p=10, d_max=None, precision="fp64", profile=False, hmt_alpha=10.0):
     """Adaptive HSS compression (hss_compress).  R: (n, d_cap) float64 CUDA tensor,
     column-major, rows in permuted order.  Returns (HSSMatrix, status)."""
     g = gen._c()
-    o = _opts(R, rtol, atol, eta, strategy, d0, delta_d, p, d_max, precision, profile)
+    o = _opts(R, rtol, atol, eta, strategy, d0, delta_d, p, d_max, precision, profile, hmt_alpha)
     h = C.c_void_p()
     st = _check(lib().hss_compress(C.byref(g), tree._t, C.byref(o), C.byref(h)))
     return HSSMatrix(h.value, (gen, tree, R)), st
@@ -458,7 +459,7 @@ def compress_batched(gens, trees, Rs, **kw):
     O = (_Opt * k)(*[_opts(R, opt("rtol", i, 1e-6), opt("atol", i, 1e-12), opt("eta", i, 1.0),
                            opt("strategy", i, "dbl_fnorm"), opt("d0", i, 64), opt("delta_d", i, 64),
                            opt("p", i, 10), opt("d_max", i, None), opt("precision", i, "fp64"),
-                           opt("profile", i, False))
+                           opt("profile", i, False), opt("hmt_alpha", i, 10.0))
                      for i, R in enumerate(Rs)])
     H = (C.c_void_p * k)()
     st = _check(lib().hss_compress_batched(k, G, T, O, H))
