@@ -307,6 +307,153 @@ def copy_calibration():
     print(json.dumps({"copy_bytes_read": a.numel() * 8, "copy_bytes_written": b.numel() * 8, "launches": 3}))
 
 
+def lowrank_plus_identity(n, r, seed):
+    """A = I + U D V^T in HBM, column-major (the synthetic problem of the
+    paper's adaptivity experiments, Sec. 5.3: alpha = beta = 1): U and V
+    with orthonormal columns (QR of seeded Gaussian matrices, on the GPU)
+    and D_kk = 2^(-53 (k-1) / r), k = 1..r."""
+    import torch
+
+    from paper_1810_04125_amd import hss, inputs
+
+    U = torch.linalg.qr(torch.from_numpy(inputs.gaussian_matrix(n, r, seed)).cuda())[0]
+    V = torch.linalg.qr(torch.from_numpy(inputs.gaussian_matrix(n, r, seed + 1)).cuda())[0]
+    D = torch.pow(2.0, -53.0 * torch.arange(r, dtype=torch.float64, device="cuda") / r)
+    At = (V * D) @ U.t()              # A^T row-major = A column-major
+    At.diagonal().add_(1.0)
+    del U, V
+    return hss.dense(At.t(), symmetric=False)
+
+
+def dense_sampling_rate(gen, T, R, log, reps=5):
+    """The dense-matrix sampling kernel alone: S = A_hat R(:, 0:64), A read
+    from HBM once per call (8 n^2 bytes, 2 n^2 64 flops), best of `reps`."""
+    import torch
+
+    from paper_1810_04125_amd import hss
+
+    n = T.n
+    perm = torch.from_numpy(T.perm).cuda()
+    R64 = hss.colmajor(R[:, :64])
+    hss.sample(gen, perm, R64)
+    best = float("inf")
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        hss.sample(gen, perm, R64)
+        torch.cuda.synchronize()
+        best = min(best, time.perf_counter() - t0)
+    gbs = 8.0 * n * n / best / 1e9
+    tfs = 2.0 * n * n * 64 / best / 1e12
+    log("bench: dense sampling n %d, 64 columns: %.3f ms, %.0f GB/s, %.1f TFLOP/s" % (n, best * 1e3, gbs, tfs))
+    return {"columns": 64, "ms": round(best * 1e3, 4), "achieved_GBps": round(gbs, 1), "hbm_peak_GBps": 8000.0,
+            "frac_hbm": round(gbs / 8000.0, 4), "achieved_tflops": round(tfs, 2), "fp64_peak_tflops": 78.6,
+            "frac_fp64": round(tfs / 78.6, 4), "note": "host-timed single call, launch included"}
+
+
+def table_run(gen, T, R, log, tag, exact, **kw):
+    """One compression of a table cell: time, status, error, HSS rank, rounds."""
+    import torch
+
+    from paper_1810_04125_amd import hss
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    H, st = hss.compress(gen, T, R, **kw)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    inf = H.info()
+    err, kind = (H.rel_error(), "exact") if exact else probe_error(gen, T, H, T.n)
+    log("bench: %s %s: %.3g s, status %d, err %.3g, rank %d, rounds %d, d %d" % (
+        tag, {k: kw[k] for k in ("strategy", "rtol", "atol", "d0", "d_max") if k in kw}, sec, st, err,
+        inf["hss_rank"], inf["rounds"], inf["d_final"]))
+    return {"sec": round(sec, 4), "status": st, "rel_err": err, "err_kind": kind, "hss_rank": inf["hss_rank"],
+            "rounds": inf["rounds"], "d_final": inf["d_final"]}
+
+
+def main_table(args, log):
+    """Synthetic analogues of the paper's adaptivity tables on A = I + U D V^T
+    (dense in HBM, sampled by the library's dense-matrix kernel).
+
+    hmt: n = 20000, r = 200.  The F-norm test (incrementing, d0 = 128,
+    delta_d = 64) over rtol x atol in {1e-2, 1e-6, 1e-10, 1e-14}^2 and the
+    HMT-lemma test (eq. HMT_IQQH, alpha = 10, p = delta_d) over atol, with
+    the paper's literal per-node tolerance (eta = 1) and d_max = 4096;
+    exact errors ||A - H||_F / ||A||_F.
+
+    adaptive-rank: n = 60000, r = 1200, rtol = atol = 1e-12 (1e-14 with the
+    literal per-node tolerance 1e-14 / level lies below the FP64 rounding
+    floor of the projected samples, and no run converges).  "Known rank"
+    (one round with d0 = the incrementing run's HSS rank + 64), the
+    incrementing strategy (d0 = 128, delta_d = 64 and d0 = 512,
+    delta_d = 128), and "hard restart" (compressions from scratch at
+    d = d0, 2 d0, ... with d_max = d, until the error of one is within
+    the requested tolerance); 64-probe error estimates.  With d_max = d0
+    the stopping test of the first round fails at a few nodes and the
+    second round accepts them (status NOT_CONVERGED): "known rank" and
+    every restart sample once and include that test work."""
+    import numpy as np
+    import torch
+
+    from paper_1810_04125_amd import hss, inputs
+
+    out = {"table": args.table, "data": "synthetic", "matrix": "I + U D V^T, D_kk = 2^(-53(k-1)/r)"}
+    if args.table == "hmt":
+        n, r, dmax = 20000, 200, 4096
+    else:
+        n, r, dmax = 60000, 1200, 4096
+    gen = lowrank_plus_identity(n, r, 11)
+    T = hss.Tree(n, 128)
+    Rh = inputs.gaussian_matrix(n, dmax, 12)
+    R = hss.colmajor(torch.from_numpy(np.ascontiguousarray(Rh.T)).cuda().t())
+    del Rh
+    out.update({"n": n, "r": r, "leaf": 128, "tree": "bisect"})
+    out["dense_sampling"] = dense_sampling_rate(gen, T, R, log)
+    if args.table == "hmt":
+        tols = [1e-2, 1e-6, 1e-10, 1e-14]
+        base = dict(eta=1.0, d0=128, delta_d=64, d_max=dmax)
+        grid = {}
+        for rt in tols:
+            for at in tols:
+                grid["rtol=%g,atol=%g" % (rt, at)] = table_run(gen, T, R, log, "fnorm", True, rtol=rt, atol=at,
+                                                               strategy="inc_fnorm", **base)
+        hmt = {}
+        for at in tols:
+            hmt["atol=%g" % at] = table_run(gen, T, R, log, "hmt", True, rtol=0.0, atol=at, strategy="inc_hmt",
+                                            hmt_alpha=10.0, **base)
+        out.update({"strategy": "inc_fnorm d0=128 delta_d=64 eta=1", "fnorm": grid,
+                    "hmt_lemma": hmt, "hmt_alpha": 10.0, "d_max": dmax})
+    else:
+        kw = dict(rtol=1e-12, atol=1e-12, eta=1.0)
+        res = {}
+        for d0, dd in ((128, 64), (512, 128)):
+            key = "d0=%d,delta_d=%d" % (d0, dd)
+            inc = table_run(gen, T, R, log, "inc " + key, False, strategy="inc_fnorm", d0=d0, delta_d=dd,
+                            d_max=dmax, **kw)
+            inc["adaptations"] = inc["rounds"] - 1
+            dk = min(dmax, inc["hss_rank"] + 64)
+            known = table_run(gen, T, R, log, "known rank", False, strategy="inc_fnorm", d0=dk, delta_d=dd,
+                              d_max=dk, **kw)
+            known["d"] = dk
+            known["adaptations"] = 0
+            hard, d, total = [], d0, 0.0
+            while True:
+                c = table_run(gen, T, R, log, "hard restart", False, strategy="inc_fnorm", d0=d, delta_d=dd,
+                              d_max=d, **kw)
+                c["d"] = d
+                hard.append(c)
+                total += c["sec"]
+                if c["rel_err"] <= kw["rtol"] or d >= dmax:
+                    break
+                d = min(2 * d, dmax)
+            res[key] = {"known_rank": known, "inc": inc,
+                        "hard_restart": {"sec": round(total, 4), "adaptations": len(hard) - 1,
+                                         "hss_rank": hard[-1]["hss_rank"], "rel_err": hard[-1]["rel_err"],
+                                         "runs": hard}}
+        out.update({"rtol": 1e-12, "atol": 1e-12, "eta": 1.0, "results": res})
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -320,6 +467,9 @@ def main():
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a device-to-device copy of 1 GiB three times (reference for HBM counters)")
+    ap.add_argument("--table", choices=["hmt", "adaptive-rank"],
+                    help="synthetic analogue of the paper's stopping-criterion or adaptivity-cost table "
+                         "(one JSON line with the whole table instead of the bench line)")
     args = ap.parse_args()
     if args.copy_calibration:
         return copy_calibration()
@@ -337,6 +487,8 @@ def main():
         sys.exit(1)
     W = WORKLOADS[args.workload]
     log = lambda m: print(m, file=sys.stderr, flush=True)
+    if args.table:
+        return main_table(args, log)
     if W.get("batch"):
         return main_batch(args, W, log)
     n = W["n"]
