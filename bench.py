@@ -381,9 +381,10 @@ def main_table(args, log):
     the paper's literal per-node tolerance (eta = 1) and d_max = 4096;
     exact errors ||A - H||_F / ||A||_F.
 
-    adaptive-rank: n = 60000, r = 1200, rtol = atol = 1e-12 (1e-14 with the
-    literal per-node tolerance 1e-14 / level lies below the FP64 rounding
-    floor of the projected samples, and no run converges).  "Known rank"
+    adaptive-rank: n = 60000, r = 1200, rtol = atol = 1e-10 (with the
+    literal per-node tolerance eps / level, 1e-14 lies below the FP64
+    rounding floor of samples summed over 60000 terms, and 1e-12 within a
+    few times of it, where test outcomes follow rounding).  "Known rank"
     (one round with d0 = the incrementing run's HSS rank + 64), the
     incrementing strategy (d0 = 128, delta_d = 64 and d0 = 512,
     delta_d = 128), and "hard restart" (compressions from scratch at
@@ -424,7 +425,7 @@ def main_table(args, log):
         out.update({"strategy": "inc_fnorm d0=128 delta_d=64 eta=1", "fnorm": grid,
                     "hmt_lemma": hmt, "hmt_alpha": 10.0, "d_max": dmax})
     else:
-        kw = dict(rtol=1e-12, atol=1e-12, eta=1.0)
+        kw = dict(rtol=1e-10, atol=1e-10, eta=1.0)
         res = {}
         for d0, dd in ((128, 64), (512, 128)):
             key = "d0=%d,delta_d=%d" % (d0, dd)
@@ -450,7 +451,7 @@ def main_table(args, log):
                         "hard_restart": {"sec": round(total, 4), "adaptations": len(hard) - 1,
                                          "hss_rank": hard[-1]["hss_rank"], "rel_err": hard[-1]["rel_err"],
                                          "runs": hard}}
-        out.update({"rtol": 1e-12, "atol": 1e-12, "eta": 1.0, "results": res})
+        out.update({"rtol": 1e-10, "atol": 1e-10, "eta": 1.0, "results": res})
     print(json.dumps(out))
 
 

@@ -9,7 +9,10 @@
 // LDS and shared by the 8 waves.  The K dimension (n) is split over
 // blockIdx.z when the tile grid alone would not fill the 256 CUs; split
 // partial sums are reduced in fixed order, so results are deterministic.
+#include <rocblas/rocblas.h>
+
 #include <algorithm>
+#include <map>
 
 #include "gen.h"
 
@@ -270,11 +273,68 @@ void launch_sample_lp(const GenDev& g, int32_t transpose, int32_t bf16x3, const 
                       double* out, int64_t lds, int32_t ncols, int64_t kchunk, int32_t nz, dim3 grid,
                       const int32_t* leaf_lo, const int32_t* leaf_hi, int32_t offdiag, hipStream_t s);
 
+// Dense matrices in HBM: A_hat R = P A P^T R is a plain GEMM between two
+// row permutations, X = P^T R (X(perm(i), :) = R(i, :)), Y = op(A) X on
+// rocBLAS, S(i, :) = Y(perm(i), :).  The entry-generating kernel would
+// load every entry of A through the permutation inside its MFMA loop.
+__global__ void k_perm_rows(const double* __restrict__ src, int64_t lds_, double* __restrict__ dst, int64_t ldd,
+                            const int64_t* __restrict__ perm, int64_t n, int32_t ncols, int32_t scatter) {
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= n * ncols) return;
+  const int64_t i = idx % n, c = idx / n;
+  const int64_t p = perm[i];
+  if (scatter) dst[c * ldd + p] = src[c * lds_ + i];
+  else dst[c * ldd + i] = src[c * lds_ + p];
+}
+
+static rocblas_handle blas_handle(hipStream_t s) {
+  thread_local std::map<int, rocblas_handle> handles;   // per thread and device, kept until exit
+  int dev = 0;
+  HSS_HIP_CHECK(hipGetDevice(&dev));
+  rocblas_handle& h = handles[dev];
+  if (!h && rocblas_create_handle(&h) != rocblas_status_success) {
+    h = nullptr;
+    throw Error(HSS_ERR_DEVICE, "rocblas_create_handle failed");
+  }
+  if (rocblas_set_stream(h, s) != rocblas_status_success) throw Error(HSS_ERR_DEVICE, "rocblas_set_stream failed");
+  return h;
+}
+
+// Returns false when the workspace cannot hold one 64-column chunk of X and Y.
+static bool sample_dense_gemm(const GenDev& g, int32_t transpose, const double* R, int64_t ldr, double* S,
+                              int64_t lds, int32_t ncols, double* partial, hipStream_t s) {
+  const int64_t n = g.n;
+  const int64_t cap = (int64_t)sample_partial_elems(n, ncols);   // at most what the caller allocated
+  const int64_t chunk = partial ? std::min<int64_t>(ncols, cap / (2 * n) / 64 * 64) : 0;
+  if (chunk < std::min<int64_t>(ncols, 64)) return false;
+  double* X = partial;
+  double* Y = partial + n * chunk;
+  rocblas_handle h = blas_handle(s);
+  const double one = 1.0, zero = 0.0;
+  for (int64_t c0 = 0; c0 < ncols; c0 += chunk) {
+    const int32_t c = (int32_t)std::min<int64_t>(chunk, ncols - c0);
+    const unsigned blocks = (unsigned)((n * c + 255) / 256);
+    hipLaunchKernelGGL(k_perm_rows, dim3(blocks), dim3(256), 0, s, R + c0 * ldr, ldr, X, n, g.perm, n, c, 1);
+    prof_begin(s);
+    const rocblas_status st = rocblas_dgemm(h, transpose ? rocblas_operation_transpose : rocblas_operation_none,
+                                            rocblas_operation_none, (rocblas_int)n, c, (rocblas_int)n, &one,
+                                            g.dense, (rocblas_int)g.ld, X, (rocblas_int)n, &zero, Y,
+                                            (rocblas_int)n);
+    prof_end(HSS_K_SAMPLE, s);
+    if (st != rocblas_status_success) throw Error(HSS_ERR_DEVICE, "rocblas_dgemm failed");
+    hipLaunchKernelGGL(k_perm_rows, dim3(blocks), dim3(256), 0, s, Y, n, S + c0 * lds, lds, g.perm, n, c, 0);
+  }
+  return true;
+}
+
 void launch_sample(const GenDev& g, int32_t transpose, int32_t precision, const double* R,
                    int64_t ldr, double* S, int64_t lds, int32_t ncols, double* partial,
                    hipStream_t s, unsigned long long* kcnt) {
   (void)kcnt;
   if (ncols <= 0 || g.n <= 0) return;
+  if (precision == HSS_SAMPLE_FP64 && g.family == HSS_FAM_DENSE &&
+      sample_dense_gemm(g, transpose, R, ldr, S, lds, ncols, partial, s))
+    return;
   const int64_t n = g.n;
   const int nsplit = sample_splits(n, ncols);
   int64_t kchunk = (n + nsplit - 1) / nsplit;
