@@ -3,10 +3,11 @@
 // every Hankel block derive from S^r = A R and S^c = A^* R).
 //
 // A is never stored: each lane generates the entries it feeds to the
-// matrix core.  One workgroup = 8 waves computes a 128 x 64 tile of S
-// (each wave 16 rows x 64 columns = four 16x16 FP64 MFMA blocks), so every
-// generated entry is reused for 64 columns of R.  R tiles are staged in
-// LDS and shared by the 8 waves.  The K dimension (n) is split over
+// matrix core.  One workgroup = 4 waves computes a 128 x 64 tile of S
+// (each wave 32 rows x 64 columns = eight 16x16 FP64 MFMA blocks), so every
+// generated entry is reused for 64 columns of R and every value of R read
+// from LDS for two row blocks.  R tiles are staged in LDS and shared by
+// the 4 waves.  The K dimension (n) is split over
 // blockIdx.z when the tile grid alone would not fill the 256 CUs; split
 // partial sums are reduced in fixed order, so results are deterministic.
 #include <rocblas/rocblas.h>
@@ -21,6 +22,7 @@ namespace hss {
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 constexpr int SM_ROWS = 128;   // rows of S per workgroup
+constexpr int SM_T = 256;      // threads per workgroup: 4 waves of 32 rows
 constexpr int SM_COLS = 64;    // columns of S per workgroup
 constexpr int SM_BK = 32;      // K rows of R staged per LDS tile
 constexpr int SM_LDP = SM_COLS + 2;
@@ -82,45 +84,54 @@ __device__ __forceinline__ double entry_t(const GenDev& g, int64_t i, int64_t j)
 // (nsplit == 1, column-major with lds) or the split-K partial buffer
 // P[z][row][col] with row length ncp = gridDim.y * SM_COLS.
 template <int FAM, int TRANS>
-__global__ __launch_bounds__(512, 4) void k_sample_f64(GenDev g, const double* __restrict__ R,
-                                                    int64_t ldr, double* __restrict__ out,
-                                                    int64_t lds, int32_t ncols, int64_t kchunk,
-                                                    int32_t nsplit) {
+__global__ __launch_bounds__(SM_T, 2) void k_sample_f64(GenDev g, const double* __restrict__ R,
+                                                     int64_t ldr, double* __restrict__ out,
+                                                     int64_t lds, int32_t ncols, int64_t kchunk,
+                                                     int32_t nsplit) {
   constexpr bool PTS = FAM == HSS_FAM_LAPLACE || FAM == HSS_FAM_GAUSS;
   __shared__ double Rs[SM_BK][SM_LDP];
   __shared__ double Ps[PTS ? SM_BK : 1][3];   // points of the K rows of the tile
   const int64_t n = g.n;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int64_t row0 = (int64_t)blockIdx.x * SM_ROWS + wave * 16;
+  const int64_t row0 = (int64_t)blockIdx.x * SM_ROWS + wave * 32;   // two 16-row blocks per wave
   const int col0 = blockIdx.y * SM_COLS;
   const int64_t kb = (int64_t)blockIdx.z * kchunk;
   const int64_t ke = min(n, kb + kchunk);
-  const int64_t my_row = row0 + (lane & 15);
-  const bool row_ok = my_row < n;
+  int64_t my_row[2];
+  bool row_ok[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    my_row[h] = row0 + 16 * h + (lane & 15);
+    row_ok[h] = my_row[h] < n;
+  }
   const int kq = lane >> 4;
-  double px = 0.0, py = 0.0, pz = 0.0;   // this lane's row point
+  double px[2] = {0.0, 0.0}, py[2] = {0.0, 0.0}, pz[2] = {0.0, 0.0};   // this lane's row points
   if constexpr (PTS) {
-    if (row_ok) {
-      px = g.pts[3 * my_row];
-      py = g.pts[3 * my_row + 1];
-      pz = g.pts[3 * my_row + 2];
-    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+      if (row_ok[h]) {
+        px[h] = g.pts[3 * my_row[h]];
+        py[h] = g.pts[3 * my_row[h] + 1];
+        pz[h] = g.pts[3 * my_row[h] + 2];
+      }
   }
 
-  dbl4 acc[4];
+  dbl4 acc[2][4];
 #pragma unroll
-  for (int c = 0; c < 4; ++c) acc[c] = dbl4{0.0, 0.0, 0.0, 0.0};
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[h][c] = dbl4{0.0, 0.0, 0.0, 0.0};
 
   // R(kt:kt+BK, col0:col0+64) and the tile's points are loaded into
   // registers one tile ahead, then stored to LDS (Rs[k][c], Ps[k][xyz])
-  constexpr int RPT = SM_BK * SM_COLS / 512;
+  constexpr int RPT = SM_BK * SM_COLS / SM_T;
   double rr[RPT];
   double pp = 0.0;
   auto load_tile = [&](int64_t kt) {
 #pragma unroll
     for (int e = 0; e < RPT; ++e) {
-      const int idx = threadIdx.x + 512 * e;
+      const int idx = threadIdx.x + SM_T * e;
       const int r = idx % SM_BK, c = idx / SM_BK;
       const int64_t gk = kt + r;
       const int gc = col0 + c;
@@ -138,7 +149,7 @@ __global__ __launch_bounds__(512, 4) void k_sample_f64(GenDev g, const double* _
   for (int64_t kt = kb; kt < ke; kt += SM_BK) {
 #pragma unroll
     for (int e = 0; e < RPT; ++e) {
-      const int idx = threadIdx.x + 512 * e;
+      const int idx = threadIdx.x + SM_T * e;
       Rs[idx % SM_BK][idx / SM_BK] = rr[e];
     }
     if constexpr (PTS) {
@@ -154,17 +165,20 @@ __global__ __launch_bounds__(512, 4) void k_sample_f64(GenDev g, const double* _
     if (fast) {
 #pragma unroll
       for (int kk = 0; kk < SM_BK; kk += 4) {
-        const double dx = px - Ps[kk + kq][0];
-        const double dy = py - Ps[kk + kq][1];
-        const double dz = pz - Ps[kk + kq][2];
-        const double r2 = dx * dx + dy * dy + dz * dz;
-        double a;
-        if constexpr (FAM == HSS_FAM_LAPLACE) a = kInv4Pi * rsqrt_nr(r2);
-        else a = exp(-r2 * g.inv2s2);
+        const double qx = Ps[kk + kq][0], qy = Ps[kk + kq][1], qz = Ps[kk + kq][2];
+        double a[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const double dx = px[h] - qx, dy = py[h] - qy, dz = pz[h] - qz;
+          const double r2 = dx * dx + dy * dy + dz * dz;
+          if constexpr (FAM == HSS_FAM_LAPLACE) a[h] = kInv4Pi * rsqrt_nr(r2);
+          else a[h] = exp(-r2 * g.inv2s2);
+        }
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
           const double b = Rs[kk + kq][c * 16 + (lane & 15)];
-          acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[c], 0, 0, 0);
+          acc[0][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[0], b, acc[0][c], 0, 0, 0);
+          acc[1][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[1], b, acc[1][c], 0, 0, 0);
         }
       }
       __syncthreads();
@@ -173,52 +187,58 @@ __global__ __launch_bounds__(512, 4) void k_sample_f64(GenDev g, const double* _
 #pragma unroll 2
     for (int kk = 0; kk < SM_BK; kk += 4) {
       const int64_t j = kt + kk + kq;
-      const bool ok = row_ok && j < ke;
-      double a;
-      if constexpr (PTS) {
-        // symmetric kernels: the transposed product reads the same entries;
-        // computed unconditionally and selected, so the loop has no branches
-        const double dx = px - Ps[kk + kq][0];
-        const double dy = py - Ps[kk + kq][1];
-        const double dz = pz - Ps[kk + kq][2];
-        const double r2 = dx * dx + dy * dy + dz * dz;
-        double v;
-        if constexpr (FAM == HSS_FAM_LAPLACE) {
-          v = kInv4Pi * rsqrt_nr(r2);
-          v = my_row == j ? g.diag : v;
+      double a[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const bool ok = row_ok[h] && j < ke;
+        if constexpr (PTS) {
+          // symmetric kernels: the transposed product reads the same entries;
+          // computed unconditionally and selected, so the loop has no branches
+          const double dx = px[h] - Ps[kk + kq][0];
+          const double dy = py[h] - Ps[kk + kq][1];
+          const double dz = pz[h] - Ps[kk + kq][2];
+          const double r2 = dx * dx + dy * dy + dz * dz;
+          double v;
+          if constexpr (FAM == HSS_FAM_LAPLACE) {
+            v = kInv4Pi * rsqrt_nr(r2);
+            v = my_row[h] == j ? g.diag : v;
+          } else {
+            v = exp(-r2 * g.inv2s2);
+            v = my_row[h] == j ? v + g.diag : v;
+          }
+          a[h] = ok ? v : 0.0;
         } else {
-          v = exp(-r2 * g.inv2s2);
-          v = my_row == j ? v + g.diag : v;
+          a[h] = 0.0;
+          if (ok) a[h] = TRANS ? entry_t<FAM>(g, j, my_row[h]) : entry_t<FAM>(g, my_row[h], j);
         }
-        a = ok ? v : 0.0;
-      } else {
-        a = 0.0;
-        if (ok) a = TRANS ? entry_t<FAM>(g, j, my_row) : entry_t<FAM>(g, my_row, j);
       }
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         const double b = Rs[kk + kq][c * 16 + (lane & 15)];
-        acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[c], 0, 0, 0);
+        acc[0][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[0], b, acc[0][c], 0, 0, 0);
+        acc[1][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[1], b, acc[1][c], 0, 0, 0);
       }
     }
     __syncthreads();
   }
   // FP64 16x16x4 result layout: D[i][j] with i = 4*v + lane/16, j = lane % 16
 #pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    const int gc = col0 + c * 16 + (lane & 15);
+  for (int h = 0; h < 2; ++h)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int64_t gr = row0 + 4 * v + kq;
-      if (gr >= n || gc >= ncols) continue;
-      if (nsplit == 1) {
-        out[(int64_t)gc * lds + gr] = acc[c][v];
-      } else {
-        const int64_t ncp = (int64_t)gridDim.y * SM_COLS;
-        out[((int64_t)blockIdx.z * n + gr) * ncp + gc] = acc[c][v];
+    for (int c = 0; c < 4; ++c) {
+      const int gc = col0 + c * 16 + (lane & 15);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t gr = row0 + 16 * h + 4 * v + kq;
+        if (gr >= n || gc >= ncols) continue;
+        if (nsplit == 1) {
+          out[(int64_t)gc * lds + gr] = acc[h][c][v];
+        } else {
+          const int64_t ncp = (int64_t)gridDim.y * SM_COLS;
+          out[((int64_t)blockIdx.z * n + gr) * ncp + gc] = acc[h][c][v];
+        }
       }
     }
-  }
 }
 
 __global__ void k_splitk_reduce(const double* __restrict__ P, int64_t n, int32_t ncols, int64_t ncp,
@@ -262,10 +282,10 @@ static void launch_fam(const GenDev& g, int transpose, const double* R, int64_t 
                        int64_t lds, int32_t ncols, int64_t kchunk, int nsplit, dim3 grid,
                        hipStream_t s) {
   if (transpose)
-    hipLaunchKernelGGL((k_sample_f64<FAM, 1>), grid, dim3(512), 0, s, g, R, ldr, out, lds, ncols,
+    hipLaunchKernelGGL((k_sample_f64<FAM, 1>), grid, dim3(SM_T), 0, s, g, R, ldr, out, lds, ncols,
                        kchunk, nsplit);
   else
-    hipLaunchKernelGGL((k_sample_f64<FAM, 0>), grid, dim3(512), 0, s, g, R, ldr, out, lds, ncols,
+    hipLaunchKernelGGL((k_sample_f64<FAM, 0>), grid, dim3(SM_T), 0, s, g, R, ldr, out, lds, ncols,
                        kchunk, nsplit);
 }
 
