@@ -37,6 +37,26 @@ def test_sampling_transpose_nonsymmetric_dense():
         assert np.linalg.norm(S - ref) <= 1e-12 * np.linalg.norm(ref)
 
 
+@pytest.mark.parametrize("n,ncols", [(700, 45), (1000, 640), (130, 1), (8000, 4096)])
+def test_dense_sampling_random_permutation(n, ncols):
+    """Dense matrices sample as a row scatter of R, one GEMM and a row gather:
+    a random permutation (not a tree's); one workspace chunk, two chunks
+    (n = 8000, 4096 columns: columns on both sides of the boundary are
+    checked), and no workspace at all (n = 130: the entry kernel)."""
+    _log("dense sample perm n=%d ncols=%d" % (n, ncols))
+    A = inputs.gaussian_matrix(n, n, 21)
+    gen = hss.dense(dev(A), symmetric=False)
+    perm = np.random.default_rng(n).permutation(n).astype(np.int64)
+    Ah = A[np.ix_(perm, perm)]
+    R = inputs.gaussian_matrix(n, ncols, 22)
+    cols = sorted({0, ncols // 2 - 1 if ncols > 1 else 0, ncols // 2, ncols - 1} | set(range(0, ncols, 97)))
+    for tr in (False, True):
+        S = hss.sample(gen, dev(perm), dev_colmajor(R), transpose=tr).cpu().numpy()
+        ref = (Ah.T if tr else Ah) @ R[:, cols]
+        err = np.linalg.norm(S[:, cols] - ref, axis=0) / np.linalg.norm(ref, axis=0)
+        assert err.max() <= 1e-13, (tr, err.max())
+
+
 @pytest.mark.parametrize("family", ["toeplitz", "laplace", "gauss"])
 def test_extraction_matches_entries(family):
     n = 900
