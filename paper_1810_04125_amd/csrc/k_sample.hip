@@ -82,7 +82,8 @@ __device__ __forceinline__ double entry_t(const GenDev& g, int64_t i, int64_t j)
 
 // out(row, col) for rows [0,n), cols [0, ncols): either S directly
 // (nsplit == 1, column-major with lds) or the split-K partial buffer
-// P[z][row][col] with row length ncp = gridDim.y * SM_COLS.
+// P[z][col][row]: split z's partial sums column-major, ncp = gridDim.y * SM_COLS
+// columns of n rows each (the reduce then reads and writes along rows).
 template <int FAM, int TRANS>
 __global__ __launch_bounds__(SM_T, 2) void k_sample_f64(GenDev g, const double* __restrict__ R,
                                                      int64_t ldr, double* __restrict__ out,
@@ -235,7 +236,7 @@ __global__ __launch_bounds__(SM_T, 2) void k_sample_f64(GenDev g, const double* 
           out[(int64_t)gc * lds + gr] = acc[h][c][v];
         } else {
           const int64_t ncp = (int64_t)gridDim.y * SM_COLS;
-          out[((int64_t)blockIdx.z * n + gr) * ncp + gc] = acc[h][c][v];
+          out[((int64_t)blockIdx.z * ncp + gc) * n + gr] = acc[h][c][v];
         }
       }
     }
@@ -247,8 +248,9 @@ __global__ void k_splitk_reduce(const double* __restrict__ P, int64_t n, int32_t
   if (idx >= n * ncols) return;
   const int64_t row = idx % n;
   const int64_t col = idx / n;
-  double s = 0.0;
-  for (int z = 0; z < nsplit; ++z) s += P[((int64_t)z * n + row) * ncp + col];
+  double s = 0.0;   // added in split order; the loads of 8 splits in flight together
+#pragma unroll 8
+  for (int z = 0; z < nsplit; ++z) s += P[((int64_t)z * ncp + col) * n + row];
   S[col * lds + row] = s;
 }
 

@@ -204,7 +204,7 @@ __global__ __launch_bounds__(512) void k_sample_lp(GenDev g, const double* __res
         out[(int64_t)gc * lds + gr] = acc64[c][v];
       } else {
         const int64_t ncp = (int64_t)gridDim.y * LP_COLS;
-        out[((int64_t)blockIdx.z * n + gr) * ncp + gc] = acc64[c][v];
+        out[((int64_t)blockIdx.z * ncp + gc) * n + gr] = acc64[c][v];
       }
     }
   }
