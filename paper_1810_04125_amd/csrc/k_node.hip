@@ -93,6 +93,49 @@ __device__ __forceinline__ void copy_elems(int total, At at) {
   }
 }
 
+// m x nc block copied between a column-major and a row-major layout
+// through 32 x 32 LDS tiles, so that both the loads and the stores run
+// along the contiguous dimension of their side.  SRC_RM: the source is
+// row-major (row i at src + i * sld) and the destination column-major;
+// otherwise the reverse.  The node's tiles are spread over its gridDim.y
+// workgroups; every thread of the workgroup must call it.
+template <bool SRC_RM>
+__device__ void copy_transpose(const double* src, int64_t sld, double* dst, int64_t dld, int m, int nc) {
+  __shared__ double tile[32][33];
+  const HSS_GLOBAL double* gs = gview(src);
+  HSS_GLOBAL double* gd = gview_w(dst);
+  const int tr = (m + 31) / 32, tcn = (nc + 31) / 32;
+  const int lx = threadIdx.x & 31, ly = threadIdx.x >> 5;   // NB = 256: 32 x 8
+  for (int t = blockIdx.y; t < tr * tcn; t += gridDim.y) {
+    const int r0 = (t % tr) * 32, k0 = (t / tr) * 32;
+    double v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int b = ly + 8 * u;
+      const int i = SRC_RM ? r0 + b : r0 + lx, c = SRC_RM ? k0 + lx : k0 + b;
+      v[u] = (i < m && c < nc) ? (SRC_RM ? gs[(int64_t)i * sld + c] : gs[(int64_t)c * sld + i]) : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int b = ly + 8 * u;
+      if (SRC_RM) tile[b][lx] = v[u];
+      else tile[lx][b] = v[u];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int b = ly + 8 * u;
+      const int ti = SRC_RM ? lx : b, tc = SRC_RM ? b : lx;
+      const int i = r0 + ti, c = k0 + tc;
+      if (i < m && c < nc) {
+        if (SRC_RM) gd[(int64_t)c * dld + i] = tile[ti][tc];
+        else gd[(int64_t)i * dld + c] = tile[ti][tc];
+      }
+    }
+    __syncthreads();
+  }
+}
+
 static dim3 node_grid(int count) {
   int g = (1024 + count - 1) / count;
   g = g < 1 ? 1 : (g > 64 ? 64 : g);
@@ -250,11 +293,9 @@ __global__ __launch_bounds__(NB) void k_ls_gather(LevelArgs a, int side) {
   double* S = tp(a, nd.S[side]);
   if (threadIdx.x == 0 && blockIdx.y == 0) kcount(a.kcnt, HSS_K_GATHER, 16.0 * m * nc, 0.0);
   if (nd.leaf) {
+    // global samples (column-major) into the node's rows
     const double* Sg = ctp(a, P.sglob[side]);
-    copy_elems(m * nc, [&](int idx) {
-      const int i = idx % m, c = idx / m;
-      return CopyAt{gview(Sg + (int64_t)(c0 + c) * P.n + nd.lo + i), gview_w(S + (int64_t)i * dcap + c0 + c)};
-    });
+    copy_transpose<false>(Sg + (int64_t)c0 * P.n + nd.lo, P.n, S + c0, dcap, m, nc);
     if (threadIdx.x == 0 && blockIdx.y == 0 && !P.gen.offdiag) {  // off-diagonal samples need no D R
       GemmTask k;
       k.A = cdp(a, nd.D);
@@ -371,10 +412,7 @@ __global__ __launch_bounds__(NB) void k_fn_copy(LevelArgs a, int side, int iter)
   if (first && threadIdx.x == 0) kcount(a.kcnt, HSS_K_GATHER, 16.0 * m * nc, 0.0);
   const double* S = ctp(a, nd.S[side]);
   double* Sh = a.wsA + nd.ws;
-  copy_elems(m * nc, [&](int idx) {
-    const int i = idx % m, c = idx / m;
-    return CopyAt{gview(S + (int64_t)i * dcap + c0 + c), gview_w(Sh + (int64_t)c * nd.mcap + i)};
-  });
+  copy_transpose<true>(S + c0, dcap, Sh, nd.mcap, m, nc);   // node rows into the column-major block
   if (first && threadIdx.x == 0) {
     const double* Q = ctp(a, nd.Q[side]);
     double* W = a.wsB + nd.wsq;
