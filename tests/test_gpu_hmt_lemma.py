@@ -100,3 +100,22 @@ def test_inc_hmt_nonsymmetric_both_sides():
     A = Laplace(pts).entries(np.arange(n), np.arange(n)) * (1.0 + 0.3 * pts[:, 0])[:, None]
     H, st, oh, ot, op = _run("dense", n, 50, 1e-9, 16, 16, seed=2, dense=A, symmetric=False)
     _check(H, oh, ot, 1e-6)
+
+
+def test_inc_hmt_batched_equals_single():
+    """A batch of two problems under the HMT-lemma test: each result has the
+    rounds, ranks and skeleton rows of its own compression."""
+    _log("inc_hmt batched")
+    n, leaf = 1024, 64
+    gens = [hss.toeplitz(n, 0.1), hss.toeplitz(n, 0.3)]
+    trees = [hss.Tree(n, leaf), hss.Tree(n, leaf)]
+    Rs = [dev_colmajor(inputs.gaussian_matrix(n, 1024, 7)), dev_colmajor(inputs.gaussian_matrix(n, 1024, 8))]
+    kw = dict(rtol=0.0, atol=1e-9, strategy="inc_hmt", d0=32, delta_d=32)
+    Hb, st = hss.compress_batched(gens, trees, Rs, **kw)
+    for k in range(2):
+        Hs, _ = hss.compress(gens[k], trees[k], Rs[k], **kw)
+        assert Hb[k].info()["rounds"] == Hs.info()["rounds"]
+        for t in range(1, trees[k].num_nodes):
+            assert Hb[k].node_info(t)["rank_r"] == Hs.node_info(t)["rank_r"]
+            assert np.array_equal(Hb[k].node(t, "JR"), Hs.node(t, "JR"))
+        assert Hb[k].rel_error() <= 1e-6
