@@ -438,8 +438,64 @@ __global__ __launch_bounds__(NB) void k_fn_copy(LevelArgs a, int side, int iter)
 // ||Sh|| / sqrt(nc) < eps_a; otherwise queue the Householder QR of Sh.
 constexpr int NBN = 1024;  // threads of the norm kernel (one workgroup per node)
 
+// Sums of squares of the block under test S(:, c0:c0+nc) and of its
+// projection S_hat over contiguous chunks of the elements, one chunk per
+// workgroup of the node (the chunk count capped by the node's slot of
+// workspace B, free between the projection GEMMs and the QR); k_fn_norms
+// adds the chunks in order.
+constexpr int NBP = 256;
+__device__ __forceinline__ int fn_chunks(const NodeDesc& nd, const ProbDev& P, int grid) {
+  return min(grid, 8 + nd.mcap + P.dcap);
+}
+
+__global__ __launch_bounds__(NBP) void k_fn_partial(LevelArgs a, int side) {
+  __shared__ double red[NBP / 64];
+  const int t = blockIdx.x;
+  const int g = a.nodes[t];
+  const NodeDesc& nd = a.desc[g];
+  const NodeState& st = a.st[g];
+  if (!st.run[side]) return;
+  const ProbDev& P = a.prob[nd.prob];
+  const int nch = fn_chunks(nd, P, gridDim.y);
+  if ((int)blockIdx.y >= nch) return;
+  const int dcap = P.dcap, m = st.m[side], nc = st.bnc, c0 = st.bc0, ld = nd.mcap;
+  const int tot = m * nc;
+  const int per = (tot + nch - 1) / nch;
+  const int e0 = blockIdx.y * per, e1 = min(tot, e0 + per);
+  const HSS_GLOBAL double* gS = gview(ctp(a, nd.S[side]));
+  const HSS_GLOBAL double* gSh = gview(a.wsA + nd.ws);
+  // S rows are contiguous over the columns, S_hat columns over the rows;
+  // each thread loads NU entries before it adds them
+  constexpr int NU = 8;
+  double p1 = 0.0, p2 = 0.0;
+  for (int base = e0 + threadIdx.x; base < e1; base += NBP * NU) {
+    double x[NU], y[NU];
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      const int idx = min(base + u * NBP, e1 - 1);
+      const int c = idx % nc, i = idx / nc;
+      x[u] = gS[(int64_t)i * dcap + c0 + c];
+      const int i2 = idx % m, c2 = idx / m;
+      y[u] = gSh[(int64_t)c2 * ld + i2];
+    }
+#pragma unroll
+    for (int u = 0; u < NU; ++u)
+      if (base + u * NBP < e1) {
+        p1 += x[u] * x[u];
+        p2 += y[u] * y[u];
+      }
+  }
+  p1 = block_sum_n<NBP>(p1, red);
+  p2 = block_sum_n<NBP>(p2, red);
+  if (threadIdx.x == 0) {
+    HSS_GLOBAL double* part = gview_w(a.wsB + nd.wsq);
+    part[2 * blockIdx.y] = p1;
+    part[2 * blockIdx.y + 1] = p2;
+  }
+}
+
 __global__ __launch_bounds__(NBN) void k_fn_norms(LevelArgs a, int side, QrcpTask* __restrict__ qt,
-                                                 CholTask* __restrict__ ct) {
+                                                 CholTask* __restrict__ ct, int chunk_grid) {
   __shared__ double red[NBN / 64];
   const int t = blockIdx.x;
   const int g = a.nodes[t];
@@ -455,34 +511,8 @@ __global__ __launch_bounds__(NBN) void k_fn_norms(LevelArgs a, int side, QrcpTas
   const int dcap = P.dcap, m = st.m[side], nc = st.bnc, c0 = st.bc0, ld = nd.mcap;
   const double lev = (double)nd.level;
   const double er = fmax(P.eps_r / lev, P.eps_floor), ea = P.eps_a / lev;
-  const double* S = ctp(a, nd.S[side]);
   double* Sh = a.wsA + nd.ws;
-  // S rows are contiguous over the columns, Sh columns over the rows; each
-  // thread loads NU entries before it adds them
-  constexpr int NU = 8;
-  double p1 = 0.0, p2 = 0.0;
-  const int tot = m * nc;
-  const HSS_GLOBAL double* gS = gview(S);
   const HSS_GLOBAL double* gSh = gview(Sh);
-  for (int base = threadIdx.x; base < tot; base += NBN * NU) {
-    double x[NU], y[NU];
-#pragma unroll
-    for (int u = 0; u < NU; ++u) {
-      const int idx = min(base + u * NBN, tot - 1);
-      const int c = idx % nc, i = idx / nc;
-      x[u] = gS[(int64_t)i * dcap + c0 + c];
-      const int i2 = idx % m, c2 = idx / m;
-      y[u] = gSh[(int64_t)c2 * ld + i2];
-    }
-#pragma unroll
-    for (int u = 0; u < NU; ++u)
-      if (base + u * NBN < tot) {
-        p1 += x[u] * x[u];
-        p2 += y[u] * y[u];
-      }
-  }
-  const double nS = sqrt(block_sum_n<NBN>(p1, red));
-  const double nSh = sqrt(block_sum_n<NBN>(p2, red));
   const bool hmt = P.strategy == HSS_INC_HMT;
   double cmax = 0.0;
   if (hmt) {
@@ -504,6 +534,16 @@ __global__ __launch_bounds__(NBN) void k_fn_norms(LevelArgs a, int side, QrcpTas
   }
   if (threadIdx.x != 0) return;
   kcount(a.kcnt, HSS_K_TEST_NORMS, 16.0 * m * nc, 4.0 * m * nc);
+  double p1 = 0.0, p2 = 0.0;   // the chunks of k_fn_partial, in order
+  {
+    const HSS_GLOBAL double* part = gview(a.wsB + nd.wsq);
+    const int nch = fn_chunks(nd, P, chunk_grid);
+    for (int y = 0; y < nch; ++y) {
+      p1 += part[2 * y];
+      p2 += part[2 * y + 1];
+    }
+  }
+  const double nS = sqrt(p1), nSh = sqrt(p2);
   const bool pass = hmt ? (nS == 0.0 || P.hmt_alpha * sqrt(2.0 / kPi) * cmax <= ea)
                         : (nS == 0.0 || nSh < er * nS || nSh / sqrt((double)nc) < ea);
   if (pass) {
@@ -847,8 +887,11 @@ void launch_fnorm_test(const LevelArgs& a, int side, int32_t iter, int32_t mcap_
     launch_gemm(a.tasks, a.count, qcap_max, ncap, s, a.kcnt, mcap_max, a.gws, kGemmSplitElems);
     launch_gemm(a.tasks + a.count, a.count, mcap_max, ncap, s, a.kcnt, qcap_max, a.gws, kGemmSplitElems);
   }
+  // chunks per node: about 2048 workgroups in all, at most 64 per node
+  const int chunk_grid = std::max(1, std::min(64, 2048 / std::max(a.count, 1)));
   prof_begin(s);
-  hipLaunchKernelGGL(k_fn_norms, dim3(a.count), dim3(NBN), 0, s, a, side, ts.qt, ts.ct);
+  hipLaunchKernelGGL(k_fn_partial, dim3(a.count, chunk_grid), dim3(NBP), 0, s, a, side);
+  hipLaunchKernelGGL(k_fn_norms, dim3(a.count), dim3(NBN), 0, s, a, side, ts.qt, ts.ct, chunk_grid);
   prof_end(HSS_K_TEST_NORMS, s);
   // Cholesky QR of the narrow blocks: decides the clearly failing tests
   const int32_t nb = std::min(ncap, kCholMaxB);
