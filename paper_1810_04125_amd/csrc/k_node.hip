@@ -657,22 +657,26 @@ __global__ __launch_bounds__(CHT) void k_cq_chol(LevelArgs a, int side, CholTask
     for (int i = ib; i <= j && i < nc; i += CRG) A[i][j] /= dR[i];
   __syncthreads();
   // X = R^{-1} by right-looking back substitution of R X = I, bottom row
-  // first: R stays in the upper triangle of A, X(i, j) (i < j) is kept
-  // transposed in the lower triangle (A[j][i]) and X(i, i) in dX.
-  __shared__ double dX[kCholMaxB];
-  for (int i = threadIdx.x; i < nc; i += CHT) dX[i] = 1.0;
+  // first: R stays in the upper triangle of A, the right-hand side B(p, q)
+  // (p < q) is kept transposed in the lower triangle (A[q][p]).  At step k
+  // row k of B is final: the threads of column q form X(k, q) =
+  // B(k, q) / R(k, k) (B(k, k) = 1), write it out and update the rows
+  // p < k of their column, so a step reads and writes disjoint entries and
+  // needs one barrier.
+  __shared__ double rinv[kCholMaxB];
+  for (int i = threadIdx.x; i < nc; i += CHT) rinv[i] = 1.0 / dR[i];
   if (j < nc)
     for (int i = ib; i < j; i += CRG) A[j][i] = 0.0;
+  HSS_GLOBAL double* X = gview_w(c.X);
+  if (j < nc)
+    for (int i = j + 1 + ib; i < nc; i += CRG) X[(int64_t)j * nc + i] = 0.0;   // below the diagonal
   __syncthreads();
   for (int k = nc - 1; k >= 0; --k) {
-    // row k of X: B(k, :) / R(k, k)
-    for (int q = k + 1 + threadIdx.x; q < nc; q += CHT) A[q][k] /= dR[k];
-    if (threadIdx.x == 0) dX[k] /= dR[k];
-    __syncthreads();
     // B(p, q) -= R(p, k) X(k, q) for p < k, q >= k: thread (ib, j) takes
     // column q = j and the rows p = ib + 16u
     if (j >= k && j < nc) {
-      const double xkq = j == k ? dX[k] : A[j][k];
+      const double xkq = j == k ? rinv[k] : A[j][k] * rinv[k];
+      if (ib == 0) X[(int64_t)j * nc + k] = xkq;
 #pragma unroll
       for (int u = 0; u < CRW; ++u) {
         const int p = ib + CRG * u;
@@ -681,11 +685,6 @@ __global__ __launch_bounds__(CHT) void k_cq_chol(LevelArgs a, int side, CholTask
       }
     }
     __syncthreads();
-  }
-  {
-    HSS_GLOBAL double* X = gview_w(c.X);
-    if (j < nc)
-      for (int i = ib; i < nc; i += CRG) X[(int64_t)j * nc + i] = i < j ? A[j][i] : (i == j ? dX[i] : 0.0);
   }
   if constexpr (PASS == 1) {
     for (int i = threadIdx.x; i < nc; i += CHT) gview_w(c.d1)[i] = dR[i];
