@@ -91,9 +91,9 @@ WORKLOADS = {
 TRAFFIC = {
     ("laplace-sphere-32768", "QRCP_STEP"): {
         "source": "paper_1810_04125_amd/csrc/k_qrcp.hip",
-        "sha256": "adf35a7e6268e1257417f39b823069e2023bdf65d4c573faceb54ea368b0af76",
-        "fetch_kib": 8614.458, "write_kib": 13431.852,            # k_qrcp_step, 17664 dispatches
-        "fetch_scale": 1048576.0 / 524302.438, "write_scale": 1.0,  # 1 GiB copy: FETCH 524302 KiB, WRITE 1048576 KiB
+        "sha256": "c55da76fdd8bbadd2cbe034128834e8ee218052a4e10aae3dc8892847db9ad3f",
+        "fetch_kib": 8615.684, "write_kib": 13428.357,            # k_qrcp_step, 17664 dispatches
+        "fetch_scale": 1048576.0 / 524302.271, "write_scale": 1.0,  # 1 GiB copy: FETCH 524302 KiB, WRITE 1048576 KiB
     },
 }
 

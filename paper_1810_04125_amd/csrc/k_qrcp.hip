@@ -148,10 +148,18 @@ __device__ __forceinline__ bool qrcp_step_body(const QrcpTask& t, int k, int c0,
     // pivot: largest residual norm among the remaining columns, ties -> lowest index
     double bv = -1.0;
     int bi = 0x7fffffff;
-    for (int j = threadIdx.x; j < m; j += NT) {
-      const double v = nold[j];
-      if (v < 0.0) continue;
-      if (v > bv || (v == bv && j < bi)) { bv = v; bi = j; }
+    // four loads in flight per thread, then compared in ascending j
+    for (int j0 = threadIdx.x; j0 < m; j0 += 4 * NT) {
+      double v4[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v4[u] = j0 + u * NT < m ? nold[j0 + u * NT] : -1.0;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int j = j0 + u * NT;
+        const double v = v4[u];
+        if (v < 0.0) continue;
+        if (v > bv || (v == bv && j < bi)) { bv = v; bi = j; }
+      }
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
@@ -182,7 +190,16 @@ __device__ __forceinline__ bool qrcp_step_body(const QrcpTask& t, int k, int c0,
   const double* x = t.W + (int64_t)p * t.ldw;
   const double x0 = x[k];
   const double alpha = x0 >= 0.0 ? -nu : nu;
-  for (int i = k + threadIdx.x; i < d; i += NT) vsh[i - k] = (i == k) ? x0 - alpha : x[i];
+  for (int i0 = k + threadIdx.x; i0 < d; i0 += 4 * NT) {
+    double x4[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) x4[u] = i0 + u * NT < d ? x[i0 + u * NT] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = i0 + u * NT;
+      if (i < d) vsh[i - k] = (i == k) ? x0 - alpha : x4[u];
+    }
+  }
   const double tk = 1.0 / (nu * (nu + fabs(x0)));  // 2 / v^T v
   if (lead) {
     if (k == 0) c->nu1 = nu;
