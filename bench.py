@@ -91,9 +91,9 @@ WORKLOADS = {
 TRAFFIC = {
     ("laplace-sphere-32768", "QRCP_STEP"): {
         "source": "paper_1810_04125_amd/csrc/k_qrcp.hip",
-        "sha256": "c55da76fdd8bbadd2cbe034128834e8ee218052a4e10aae3dc8892847db9ad3f",
-        "fetch_kib": 8615.684, "write_kib": 13428.357,            # k_qrcp_step, 17664 dispatches
-        "fetch_scale": 1048576.0 / 524302.271, "write_scale": 1.0,  # 1 GiB copy: FETCH 524302 KiB, WRITE 1048576 KiB
+        "sha256": "864c0ca733e79a4b3818ac1c6d86e04403727913a90b57264a911571f5d83437",
+        "fetch_kib": 8623.105, "write_kib": 13428.407,            # k_qrcp_step, 17664 dispatches
+        "fetch_scale": 1048576.0 / 524302.229, "write_scale": 1.0,  # 1 GiB copy: FETCH 524302 KiB, WRITE 1048576 KiB
     },
 }
 

@@ -135,10 +135,17 @@ __device__ __forceinline__ bool qrcp_step_body(const QrcpTask& t, int k, int c0,
   const int m = t.m, d = t.d;
   if (k >= min(m, d)) return true;
   QrcpCtl* c = ctl_of(t);
-  if (c->done) return true;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const double* nold = nrm_of(t, k);
   double* nnew = nrm_of(t, k + 1);
+  // the first norms are loaded before the finished flag is known, so the
+  // two reads overlap (in bounds either way)
+  double v4[4];
+  if (!t.nopivot) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v4[u] = threadIdx.x + u * NT < m ? nold[threadIdx.x + u * NT] : -1.0;
+  }
+  if (c->done) return true;
   double nu;
   int p;
   if (t.nopivot) {
@@ -150,9 +157,10 @@ __device__ __forceinline__ bool qrcp_step_body(const QrcpTask& t, int k, int c0,
     int bi = 0x7fffffff;
     // four loads in flight per thread, then compared in ascending j
     for (int j0 = threadIdx.x; j0 < m; j0 += 4 * NT) {
-      double v4[4];
+      if (j0 != (int)threadIdx.x) {
 #pragma unroll
-      for (int u = 0; u < 4; ++u) v4[u] = j0 + u * NT < m ? nold[j0 + u * NT] : -1.0;
+        for (int u = 0; u < 4; ++u) v4[u] = j0 + u * NT < m ? nold[j0 + u * NT] : -1.0;
+      }
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int j = j0 + u * NT;
@@ -285,9 +293,9 @@ __global__ __launch_bounds__(QB) void k_qrcp_step(const QrcpTask* __restrict__ t
   extern __shared__ double vsh[];
   __shared__ double rv[QW];
   __shared__ int ri[QW];
+  const int2 w = wg[blockIdx.x];   // in bounds: the grid never exceeds the map's entries
   if ((int)blockIdx.x >= meta[0]) return;
   const int cpw = meta[1];
-  const int2 w = wg[blockIdx.x];
   const QrcpTask& t = tasks[w.x];
   if (!t.active) return;
   qrcp_step_body<QB>(t, k, w.y, min(t.m, w.y + cpw), w.y == 0 && threadIdx.x == 0, kcnt, HSS_K_QRCP_STEP, vsh,
