@@ -91,9 +91,9 @@ WORKLOADS = {
 TRAFFIC = {
     ("laplace-sphere-32768", "QRCP_STEP"): {
         "source": "paper_1810_04125_amd/csrc/k_qrcp.hip",
-        "sha256": "864c0ca733e79a4b3818ac1c6d86e04403727913a90b57264a911571f5d83437",
-        "fetch_kib": 8623.105, "write_kib": 13428.407,            # k_qrcp_step, 17664 dispatches
-        "fetch_scale": 1048576.0 / 524302.229, "write_scale": 1.0,  # 1 GiB copy: FETCH 524302 KiB, WRITE 1048576 KiB
+        "sha256": "7e0d2fd8dcbe8cb30989a3a722ccfaec9f1bfff046895d6c3a235b1e24a6b3e6",
+        "fetch_kib": 8631.853, "write_kib": 13430.088,            # k_qrcp_step, 17664 dispatches
+        "fetch_scale": 1048576.0 / 524302.292, "write_scale": 1.0,  # 1 GiB copy: FETCH 524302 KiB, WRITE 1048576 KiB
     },
 }
 

@@ -180,18 +180,20 @@ struct QrcpPlan {
 QrcpPlan make_qrcp_plan(const std::vector<int32_t>& mcaps, int cpw = QCPW);
 // Busy workgroups aimed at by every pivot-step launch (5 per compute unit:
 // more waves keep more column loads in flight; 4 and 7 per unit were slower).
+// The plan kernel doubles it for steps that would give a workgroup 16 or
+// more columns (large batches of panels).
 constexpr int kQrcpTarget = 1280;
 // Panels of at most this many cells (rows x columns, by capacity) are
 // factored by one workgroup each in a single launch.
 constexpr int64_t kQrcpWgCells = 64 * 1024;
-// Device work map of run_qrcp: chunks holds kQrcpTarget + max_tasks
-// entries, meta two int32.
+// Device work map of run_qrcp: chunks holds 2 kQrcpTarget + max_tasks
+// entries (the target doubles for large steps), meta two int32.
 struct QrcpWork {
   int2* chunks;
   int32_t* meta;
   int32_t max_tasks;
 };
-inline size_t qrcp_work_entries(int32_t max_tasks) { return (size_t)kQrcpTarget + (size_t)std::max(max_tasks, 1); }
+inline size_t qrcp_work_entries(int32_t max_tasks) { return (size_t)2 * kQrcpTarget + (size_t)std::max(max_tasks, 1); }
 // Factor the panels of `tasks` (dmax rows and at most ncols_max columns
 // each, by capacity): one workgroup per matrix for small panels, else one
 // launch per pivot step over a device-built work map.  `flag` points at

@@ -48,8 +48,9 @@ __device__ __forceinline__ double wsum(double v) {
 // that are active: every active matrix's m panel columns are cut into
 // chunks of cpw columns, cpw = ceil(active columns / target), so the
 // launches of the pivot steps have about `target` busy workgroups however
-// few matrices factor.  meta = {number of chunks, cpw}; the chunk count is
-// at most target + ntasks.
+// few matrices factor; the target doubles when it would leave 16 or more
+// columns to a workgroup.  meta = {number of chunks, cpw}; the chunk count
+// is at most 2 target + ntasks.
 __global__ __launch_bounds__(QB) void k_qrcp_plan(const QrcpTask* __restrict__ tasks, int ntasks, int target,
                                                   int2* __restrict__ chunks, int32_t* __restrict__ meta) {
   __shared__ long long part[QB];
@@ -65,7 +66,9 @@ __global__ __launch_bounds__(QB) void k_qrcp_plan(const QrcpTask* __restrict__ t
   if (tid == 0) {
     long long tot = 0;
     for (int i = 0; i < QB; ++i) tot += part[i];
-    s_cpw = (int)max(1LL, (tot + target - 1) / target);
+    // steps with at least 16 columns per workgroup get twice the workgroups
+    const long long tg = tot >= 16LL * target ? 2LL * target : (long long)target;
+    s_cpw = (int)max(1LL, (tot + tg - 1) / tg);
   }
   __syncthreads();
   const int cpw = s_cpw;
@@ -540,7 +543,7 @@ void run_qrcp(QrcpTask* tasks, int32_t ntasks, const QrcpWork& wk, const int2* w
               hipStream_t s, unsigned long long* kcnt, bool solve_e, double* gws) {
   if (ntasks <= 0) return;
   if (ntasks > wk.max_tasks) throw Error(HSS_ERR_INTERNAL, "QRCP work map too small for the batch");
-  const int nwg = kQrcpTarget + ntasks;
+  const int nwg = 2 * kQrcpTarget + ntasks;
   const size_t lds = (size_t)std::max(dmax, 1) * sizeof(double);
   // The ID first counts its active panels (and finds the tall ones): with
   // none it is done, and the count picks the factorization kernel.
