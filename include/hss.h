@@ -181,11 +181,16 @@ void hss_tree_free(hss_tree* tree);
  *   oversample_p : p of the HMT acceptance r < d - p (HSS_DBL_HMT)
  *   hmt_alpha  : alpha of eq. HMT_IQQH (HSS_INC_HMT; 0 = 10): the bound holds
  *                except with probability alpha^-p, p = delta_d
- *   d_max      : cap on the number of random vectors; <= ncols_R
+ *   d_max      : cap on the number of random vectors; min(d_max, n) <= HSS_MAX_D,
+ *                <= ncols_R when R is given
  *   R, ldr, ncols_R : device, the n x ncols_R Gaussian matrix the method
  *                draws from, rows in PERMUTED order; columns are consumed
- *                left to right and never regenerated
- *   stream     : hipStream_t for all work (NULL = default stream) */
+ *                left to right and never regenerated.  R = NULL: the
+ *                library draws the columns itself on the device, each
+ *                round only the new ones, from the counter-based generator
+ *                of hss_random_normal with `seed` (ldr and ncols_R unused)
+ *   stream     : hipStream_t for all work (NULL = default stream)
+ *   seed       : key of the generated R (used only when R is NULL) */
 typedef struct {
   double rtol;
   double atol;
@@ -202,7 +207,13 @@ typedef struct {
   int32_t profile;   /* 1: time every kernel launch with HIP events (slower; see hss_get_kernel_stats) */
   void* stream;
   double hmt_alpha;
+  uint64_t seed;
 } hss_options;
+
+/* Largest sample count of a compression: a pivot step of the ID keeps its
+ * Householder vector (one double per sample) in the 160 KB of LDS of a
+ * compute unit. */
+#define HSS_MAX_D 16384
 
 typedef struct hss_matrix hss_matrix;
 
@@ -229,8 +240,11 @@ hss_status hss_compress_batched(int32_t count, const hss_generator* gens,
 void hss_destroy(hss_matrix* h);
 
 /* Y = H X for nrhs right-hand sides, X and Y device, ORIGINAL ordering,
- * asynchronous on `stream`.  Upward pass x_hat = V^T x, top-down sibling
- * couplings through B12/B21 and the nested bases (eq. nestedUV). */
+ * asynchronous on `stream`: the call returns once the work is queued; its
+ * temporaries are stream-ordered allocations freed behind it on `stream`.
+ * Upward pass x_hat = V^T x, top-down sibling couplings through B12/B21 and
+ * the nested bases (eq. nestedUV).  Calls on one hss_matrix share its task
+ * arrays: issue them on one stream (calls on different streams race). */
 hss_status hss_matvec(const hss_matrix* h, int32_t nrhs, const double* X, int64_t ldx,
                       double* Y, int64_t ldy, void* stream);
 
@@ -280,12 +294,17 @@ hss_status hss_get_info(const hss_matrix* h, hss_info* out);
  *   QRCP_WG      k_qrcp_wg: whole factorizations of small panels, per step as
  *                QRCP_STEP
  *   QFORM        k_qf_prep, k_qf_solve, k_qform: explicit Q_k of the stopping
- *                test (compact WY form; its GEMMs count as GEMM) */
+ *                test (compact WY form; its GEMMs count as GEMM)
+ *   RNG          k_randn: the new columns of R when the library draws them
+ *                (8 bytes written per entry)
+ *   TEST_QR      Householder steps of the stopping test's QR of the projected
+ *                block (no pivoting), counted as QRCP_STEP; QRCP_STEP then
+ *                holds the pivot steps of the ID only */
 enum {
   HSS_K_SAMPLE = 0, HSS_K_SAMPLE_REDUCE = 1, HSS_K_EXTRACT = 2, HSS_K_GATHER = 3, HSS_K_GEMM = 4,
   HSS_K_TEST_NORMS = 5, HSS_K_QRCP_STEP = 6, HSS_K_QRCP_OTHER = 7, HSS_K_TRSM = 8, HSS_K_MISC = 9,
-  HSS_K_QRCP_WG = 10, HSS_K_QFORM = 11,
-  HSS_K_COUNT = 12
+  HSS_K_QRCP_WG = 10, HSS_K_QFORM = 11, HSS_K_RNG = 12, HSS_K_TEST_QR = 13,
+  HSS_K_COUNT = 14
 };
 typedef struct {
   int64_t launches;
@@ -327,7 +346,8 @@ hss_status hss_copy_node(const hss_matrix* h, int32_t node, int32_t what, void* 
 
 /* S = op(A_hat) R for ncols columns, A_hat(i,j) = a(perm[i], perm[j]),
  * op = identity (transpose = 0, S^r) or transpose (1, S^c) (Sec. 2.2
- * eq. sample_off_diag).  perm: device int64[n].  R, S: device, n x ncols,
+ * eq. sample_off_diag).  perm: device int64[n], checked on the host to be a
+ * permutation of [0, n) (HSS_ERR_INVALID_ARG otherwise).  R, S: device, n x ncols,
  * column-major.  precision: hss_precision.  Host-synchronous (the call
  * returns when S is complete).  HSS_FAM_CALLBACK forwards to gen->sample
  * (FP64 only; perm is not used, the routine works in permuted order). */
@@ -336,7 +356,8 @@ hss_status hss_sample(const hss_generator* gen, const int64_t* perm, int32_t nco
                       int32_t precision, void* stream);
 
 /* out = A_hat(I, J), nI x nJ column-major (ldo >= nI); I, J device int64
- * permuted indices (Sec. 4.1: B = A(J^r, J^c) is a sub-block of A).
+ * permuted indices (Sec. 4.1: B = A(J^r, J^c) is a sub-block of A).  perm,
+ * I and J are checked on the host (a permutation; indices in [0, n)).
  * HSS_FAM_CALLBACK forwards one block to gen->extract (perm not used). */
 hss_status hss_extract(const hss_generator* gen, const int64_t* perm, int32_t nI,
                        const int64_t* I, int32_t nJ, const int64_t* J, double* out,
@@ -356,6 +377,28 @@ hss_status hss_interpolative_batched(int32_t count, const int32_t* m, const int3
                                      double eps_r, double eps_a, int32_t* piv,
                                      const int64_t* piv_off, double* E, const int64_t* e_off,
                                      int32_t* rank_host);
+
+/* Columns c0 .. c0+ncols-1 of the Gaussian matrix R that hss_compress draws
+ * when options.R is NULL (Alg. 3: R-bar = randn(N, delta_d) in every
+ * round), into R (device, n x ncols column-major, leading dimension
+ * ldr >= n; output column t holds column c0 + t).  Entry (i, j), i a
+ * PERMUTED row, depends on (seed, i, j) only:
+ *   - Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC 2011) of the counter
+ *     (i >> 2, j, 0, 0) under the key (seed, 0) gives words w0..w3 for the
+ *     rows 4q .. 4q+3, q = i >> 2;
+ *   - u_t = ((w_t >> 11) + 1) 2^-53 in (0, 1];
+ *   - Box-Muller in FP64: rows 4q, 4q+1 get sqrt(-2 log u0) cos(2 pi u1) and
+ *     sqrt(-2 log u0) sin(2 pi u1), rows 4q+2, 4q+3 the same of (u2, u3),
+ *     with 2 pi the nearest double, multiplied into u before cos and sin.
+ * Asynchronous on `stream`.  n >= 1, c0 >= 0, ncols >= 0. */
+hss_status hss_random_normal(int64_t n, int32_t c0, int32_t ncols, uint64_t seed, double* R, int64_t ldr,
+                             void* stream);
+
+/* The raw Philox words behind hss_random_normal: W(i, t) = word (i & 3) of
+ * the counter (i >> 2, c0 + t, 0, 0) (device, n x ncols column-major,
+ * leading dimension ldw >= n).  Asynchronous on `stream`. */
+hss_status hss_random_words(int64_t n, int32_t c0, int32_t ncols, uint64_t seed, uint64_t* W, int64_t ldw,
+                            void* stream);
 
 /* Free the device memory the library keeps between compressions on the
  * current device.  The transient buffers of a compression (local samples,

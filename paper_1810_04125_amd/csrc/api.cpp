@@ -193,6 +193,27 @@ MlpAdam adam_consts(float lr, float b1, float b2, float eps, int64_t step) {
   return a;
 }
 
+// The single-step entry points take device index arrays that select points
+// and generated entries: they are copied back and checked on the host.
+void check_device_perm(const int64_t* perm, int64_t n) {
+  if (!perm) throw Error(HSS_ERR_INVALID_ARG, "perm must be a device int64[n] array");
+  std::vector<int64_t> h((size_t)n);
+  HSS_HIP_CHECK(hipMemcpy(h.data(), perm, sizeof(int64_t) * n, hipMemcpyDeviceToHost));
+  std::vector<uint8_t> seen((size_t)n, 0);
+  for (int64_t v : h) {
+    if (v < 0 || v >= n || seen[(size_t)v]) throw Error(HSS_ERR_INVALID_ARG, "perm is not a permutation of [0, n)");
+    seen[(size_t)v] = 1;
+  }
+}
+
+void check_device_index(const int64_t* idx, int32_t cnt, int64_t n, const char* what) {
+  if (cnt <= 0) return;
+  std::vector<int64_t> h((size_t)cnt);
+  HSS_HIP_CHECK(hipMemcpy(h.data(), idx, sizeof(int64_t) * cnt, hipMemcpyDeviceToHost));
+  for (int64_t v : h)
+    if (v < 0 || v >= n) throw Error(HSS_ERR_INVALID_ARG, std::string(what) + " holds an index outside [0, n)");
+}
+
 void need(const void* p, const char* what) {
   if (!p) throw Error(HSS_ERR_INVALID_ARG, std::string(what) + " must not be NULL");
 }
@@ -222,6 +243,8 @@ hss_status hss_compress_batched(int32_t count, const hss_generator* gens, const 
     for (int32_t k = 0; k < count; ++k) out[k] = nullptr;
     for (int32_t k = 0; k < count; ++k)
       if (!trees[k]) throw Error(HSS_ERR_INVALID_ARG, "NULL tree");
+    // every argument is checked on the host before the first HIP call
+    for (int32_t k = 0; k < count; ++k) Job::validate(gens[k], trees[k], opts[k], k);
     // Problems are taken in order into groups whose estimated device memory
     // fits the free HBM at the time the group starts (earlier groups keep only
     // their generators); every group is one level-batched job.
@@ -416,16 +439,16 @@ hss_status hss_matvec(const hss_matrix* h, int32_t nrhs, const double* X, int64_
     const Problem& P = J.probs[h->k];
     if (ldx < P.n || ldy < P.n) throw Error(HSS_ERR_INVALID_ARG, "leading dimension < n");
     hipStream_t s = (hipStream_t)stream;
-    DevBuf xp(sizeof(double) * P.n * nrhs), yp(sizeof(double) * P.n * nrhs);
-    DevBuf xh(sizeof(double) * J.mvtot * nrhs), yh(sizeof(double) * J.mvtot * nrhs);
-    DevBuf ws(sizeof(double) * J.mvwstot * nrhs);
+    // stream-ordered temporaries: freed behind the kernels on `s`, so the
+    // call returns without waiting for them
+    StreamBuf xp(sizeof(double) * P.n * nrhs, s), yp(sizeof(double) * P.n * nrhs, s);
+    StreamBuf xh(sizeof(double) * J.mvtot * nrhs, s), yh(sizeof(double) * J.mvtot * nrhs, s);
+    StreamBuf ws(sizeof(double) * J.mvwstot * nrhs, s);
     const int64_t* perm = P.dev.gen.perm;
     launch_gather_rows(X, ldx, perm, P.n, nrhs, xp.as<double>(), P.n, 0, s);
     matvec_permuted(h, nrhs, xp.as<double>(), yp.as<double>(), xh.as<double>(), yh.as<double>(), ws.as<double>(), s);
     launch_gather_rows(yp.as<double>(), P.n, perm, P.n, nrhs, Y, ldy, 1, s);
     HSS_HIP_CHECK(hipGetLastError());
-    // temporaries are freed at scope exit; hipFree waits for the device to finish with them
-    HSS_HIP_CHECK(hipStreamSynchronize(s));
     return HSS_OK;
   });
 }
@@ -489,12 +512,35 @@ hss_status hss_sample(const hss_generator* gen, const int64_t* perm, int32_t nco
       HSS_HIP_CHECK(hipStreamSynchronize(s));
       return HSS_OK;
     }
+    check_device_perm(perm, gen->n);
     GenHolder G(*gen, perm, s);
     const size_t pe = sample_partial_elems(gen->n, ncols);
     DevBuf part(sizeof(double) * std::max<size_t>(pe, 1));
     launch_sample(G.g, transpose ? 1 : 0, precision, R, ldr, S, lds, ncols, part.as<double>(), s);
     HSS_HIP_CHECK(hipGetLastError());
     HSS_HIP_CHECK(hipStreamSynchronize(s));
+    return HSS_OK;
+  });
+}
+
+hss_status hss_random_normal(int64_t n, int32_t c0, int32_t ncols, uint64_t seed, double* R, int64_t ldr,
+                             void* stream) {
+  return guarded([&]() -> hss_status {
+    if (n < 1 || c0 < 0 || ncols < 0 || (ncols > 0 && !R) || ldr < n)
+      throw Error(HSS_ERR_INVALID_ARG, "bad arguments (n >= 1, c0 >= 0, ncols >= 0, ldr >= n)");
+    launch_randn(R, ldr, n, c0, ncols, seed, (hipStream_t)stream);
+    HSS_HIP_CHECK(hipGetLastError());
+    return HSS_OK;
+  });
+}
+
+hss_status hss_random_words(int64_t n, int32_t c0, int32_t ncols, uint64_t seed, uint64_t* W, int64_t ldw,
+                            void* stream) {
+  return guarded([&]() -> hss_status {
+    if (n < 1 || c0 < 0 || ncols < 0 || (ncols > 0 && !W) || ldw < n)
+      throw Error(HSS_ERR_INVALID_ARG, "bad arguments (n >= 1, c0 >= 0, ncols >= 0, ldw >= n)");
+    launch_rand_words(W, ldw, n, c0, ncols, seed, (hipStream_t)stream);
+    HSS_HIP_CHECK(hipGetLastError());
     return HSS_OK;
   });
 }
@@ -515,6 +561,9 @@ hss_status hss_extract(const hss_generator* gen, const int64_t* perm, int32_t nI
       HSS_HIP_CHECK(hipStreamSynchronize(s));
       return HSS_OK;
     }
+    check_device_perm(perm, gen->n);
+    check_device_index(I, nI, gen->n, "I");
+    check_device_index(Jx, nJ, gen->n, "J");
     GenHolder G(*gen, perm, s);
     launch_extract(G.g, nI, I, nJ, Jx, out, ldo, s);
     HSS_HIP_CHECK(hipGetLastError());
@@ -532,6 +581,8 @@ hss_status hss_interpolative_batched(int32_t count, const int32_t* m, const int3
       throw Error(HSS_ERR_INVALID_ARG, "NULL argument");
     if (count == 0) return HSS_OK;
     if (!(eps_r >= 0.0) || !(eps_a >= 0.0)) throw Error(HSS_ERR_INVALID_ARG, "need eps >= 0");
+    for (int32_t k = 0; k < count; ++k)
+      if (d[k] > HSS_MAX_D) throw Error(HSS_ERR_INVALID_ARG, "d above HSS_MAX_D (the pivot step's LDS vector)");
     int32_t mmax = 1, dmax = 1;
     std::vector<int64_t> woff(count), soff(count);
     int64_t wtot = 0, stot = 0;

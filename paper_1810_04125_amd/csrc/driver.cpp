@@ -252,7 +252,7 @@ void Job::release_transients() {
   tpool = wsa = wsb = partial = gemm_ws = nullptr;
 }
 
-static void validate(const hss_generator& g, const hss_tree* t, const hss_options& o, int k) {
+void Job::validate(const hss_generator& g, const hss_tree* t, const hss_options& o, int k) {
   const std::string who = "problem " + std::to_string(k) + ": ";
   if (!t || !t->perm || !t->lo || !t->hi || !t->left || !t->right || !t->parent || !t->level)
     throw Error(HSS_ERR_INVALID_ARG, who + "incomplete tree");
@@ -274,15 +274,28 @@ static void validate(const hss_generator& g, const hss_tree* t, const hss_option
     throw Error(HSS_ERR_INVALID_ARG, who + "need delta_d >= 1");
   if (o.strategy == HSS_INC_HMT && !(o.hmt_alpha >= 0.0)) throw Error(HSS_ERR_INVALID_ARG, who + "need hmt_alpha >= 0");
   if (o.strategy == HSS_DBL_HMT && o.oversample_p < 0) throw Error(HSS_ERR_INVALID_ARG, who + "need p >= 0");
-  if (!o.R || o.ldr < g.n || o.ncols_R < std::min<int64_t>(o.d_max, g.n))
+  if (std::min<int64_t>(o.d_max, g.n) > HSS_MAX_D)
+    throw Error(HSS_ERR_INVALID_ARG, who + "d_max above HSS_MAX_D (" + std::to_string(HSS_MAX_D) +
+                                         "): the ID's pivot step keeps one double per sample in LDS");
+  if (o.R && (o.ldr < g.n || o.ncols_R < std::min<int64_t>(o.d_max, g.n)))
     throw Error(HSS_ERR_INVALID_ARG, who + "R must be n x ncols_R with ncols_R >= min(d_max, n)");
   if (o.sample_precision < 0 || o.sample_precision > 2) throw Error(HSS_ERR_INVALID_ARG, who + "bad precision");
   if (o.sample_precision != HSS_SAMPLE_FP64 && !gen_formula(g.family))
     throw Error(HSS_ERR_INVALID_ARG, who + "reduced-precision sampling needs a generated family");
   // tree structure
   const int32_t nn = t->num_nodes;
-  if (nn < 1 || t->lo[0] != 0 || t->hi[0] != g.n || t->parent[0] != -1)
-    throw Error(HSS_ERR_INVALID_ARG, who + "root must own [0, n)");
+  if (nn < 1 || t->lo[0] != 0 || t->hi[0] != g.n || t->parent[0] != -1 || t->level[0] != 0)
+    throw Error(HSS_ERR_INVALID_ARG, who + "root must own [0, n) at level 0");
+  {
+    // perm gathers points and indexes generated entries on the device: it
+    // must hold every index of [0, n) exactly once
+    std::vector<uint8_t> seen((size_t)g.n, 0);
+    for (int64_t i = 0; i < g.n; ++i) {
+      const int64_t v = t->perm[i];
+      if (v < 0 || v >= g.n || seen[(size_t)v]) throw Error(HSS_ERR_INVALID_ARG, who + "perm is not a permutation of [0, n)");
+      seen[(size_t)v] = 1;
+    }
+  }
   for (int32_t v = 0; v < nn; ++v) {
     if (t->hi[v] <= t->lo[v]) throw Error(HSS_ERR_INVALID_ARG, who + "empty tree node");
     const int32_t l = t->left[v], r = t->right[v];
@@ -326,6 +339,7 @@ size_t Job::estimate_bytes(const hss_generator& g, const hss_tree* t, const hss_
     dbl += 2 * mcap[v] + 2 * rcap[v];   // matvec slots
   }
   dbl += nsides * align8(t->n * dc) + 8 * t->n;
+  if (!o.R) dbl += align8(t->n * dc);   // R drawn by the library
   dbl += *std::max_element(wsa.begin(), wsa.end()) + *std::max_element(wsb.begin(), wsb.end());
   dbl += (int64_t)sample_partial_elems(t->n, (int32_t)dc);
   dbl += kGemmSplitElems;
@@ -424,6 +438,10 @@ void Job::setup(int32_t count, const hss_generator* gens, const hss_tree* const*
       ttot += align8(P.n * dc);
     }
     if (P.sym) P.sglob[1] = P.sglob[0];
+    if (!P.opt.R) {   // the library draws R: n x dcap, column-major
+      P.rglob = ttot;
+      ttot += align8(P.n * dc);
+    }
   }
   // levels and workspaces
   levels.assign(maxlevel + 1, LevelInfo());
@@ -585,8 +603,8 @@ void Job::setup(int32_t count, const hss_generator* gens, const hss_tree* const*
     }
     pd.sglob[0] = P.sglob[0];
     pd.sglob[1] = P.sglob[1];
-    pd.R = P.opt.R;
-    pd.ldr = P.opt.ldr;
+    pd.R = P.rglob >= 0 ? tpool + P.rglob : P.opt.R;
+    pd.ldr = P.rglob >= 0 ? P.n : P.opt.ldr;
   }
   // sampling schedules of all problems in one device array (one copy per
   // round from a pinned staging array)
@@ -616,11 +634,17 @@ void Job::sample_end() {
 
 void Job::sample(Problem& P, int32_t c0, int32_t ncols) {
   if (ncols <= 0) return;
+  double* Rc = const_cast<double*>(P.dev.R) + (int64_t)c0 * P.dev.ldr;   // the new columns of R
+  if (P.rglob >= 0) {   // drawn here, only the new columns (Alg. 3)
+    prof_begin(stream);
+    launch_randn(Rc, P.dev.ldr, P.n, c0, ncols, P.opt.seed, stream);
+    prof_end(HSS_K_RNG, stream);
+    host_bytes[HSS_K_RNG] += 8.0 * (double)P.n * ncols;
+  }
   if (P.gen.family == HSS_FAM_CALLBACK) {
     double* S0 = tpool + P.sglob[0] + (int64_t)c0 * P.n;
     double* S1 = P.sym ? nullptr : tpool + P.sglob[1] + (int64_t)c0 * P.n;
-    const int32_t rc = P.gen.sample(P.gen.ctx, P.n, ncols, P.opt.R + (int64_t)c0 * P.opt.ldr, P.opt.ldr, S0, S1,
-                                    P.n, stream);
+    const int32_t rc = P.gen.sample(P.gen.ctx, P.n, ncols, Rc, P.dev.ldr, S0, S1, P.n, stream);
     if (rc != 0) throw Error(HSS_ERR_CALLBACK, "sample routine returned " + std::to_string(rc));
     launch_check_finite(S0, P.n, ncols, P.n, flags_d, stream);
     if (S1) launch_check_finite(S1, P.n, ncols, P.n, flags_d, stream);
@@ -630,7 +654,7 @@ void Job::sample(Problem& P, int32_t c0, int32_t ncols) {
   }
   const int prec = P.opt.sample_precision;
   for (int s = 0; s < (P.sym ? 1 : 2); ++s) {
-    launch_sample(P.dev.gen, s, prec, P.opt.R + (int64_t)c0 * P.opt.ldr, P.opt.ldr,
+    launch_sample(P.dev.gen, s, prec, Rc, P.dev.ldr,
                   tpool + P.sglob[s] + (int64_t)c0 * P.n, P.n, ncols, partial, stream, kcnt_d);
     host_flops[HSS_K_SAMPLE] += 2.0 * (double)P.n * (double)P.n * ncols;
     host_bytes[HSS_K_SAMPLE] += 16.0 * (double)P.n * ncols + 24.0 * (double)P.n;

@@ -21,6 +21,7 @@ struct Problem {
   int32_t node0 = 0;
   std::vector<int64_t> perm;
   int64_t sglob[2] = {0, 0};
+  int64_t rglob = -1;          // offset of the library-drawn R in the transient pool (-1: caller's R)
   ProbDev dev;
   int32_t d = 0, b = 0, force = 0, done = 0, rounds = 0;
   hss_status status = HSS_OK;
@@ -102,6 +103,9 @@ struct Job {
   void setup(int32_t count, const hss_generator* gens, const hss_tree* const* trees,
              const hss_options* opts);
   static size_t estimate_bytes(const hss_generator& g, const hss_tree* t, const hss_options& o);
+  // Host-only checks of one problem's arguments (no HIP call): throws
+  // HSS_ERR_INVALID_ARG naming problem k.
+  static void validate(const hss_generator& g, const hss_tree* t, const hss_options& o, int k);
   void compress();
   void sample(Problem& P, int32_t c0, int32_t ncols);
   void sample_begin();

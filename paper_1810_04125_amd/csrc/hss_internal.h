@@ -380,6 +380,11 @@ void launch_err_block(const GenDev& g, const double* Hc, int64_t ldh, int64_t j0
 void launch_err_cols(const double* Ac, int64_t lda, const double* Hc, int64_t ldh, int64_t n, int32_t nb,
                      double* accum, hipStream_t s);
 void launch_check_finite(const double* p, int64_t rows, int32_t cols, int64_t ld, int32_t* flag, hipStream_t s);
+// Columns c0 .. c0+ncols-1 of the counter-based Gaussian R (k_rng.hip),
+// written to R (n x ncols, leading dimension ldr), or their raw Philox words.
+void launch_randn(double* R, int64_t ldr, int64_t n, int32_t c0, int32_t ncols, uint64_t seed, hipStream_t s);
+void launch_rand_words(uint64_t* W, int64_t ldw, int64_t n, int32_t c0, int32_t ncols, uint64_t seed,
+                       hipStream_t s);
 
 // ---- learned predictor network (k_mlp.hip) ----
 struct MlpShape {

@@ -148,7 +148,11 @@ __device__ __forceinline__ bool qrcp_step_body(const QrcpTask& t, int k, int c0,
 #pragma unroll
     for (int u = 0; u < 4; ++u) v4[u] = threadIdx.x + u * NT < m ? nold[threadIdx.x + u * NT] : -1.0;
   }
-  if (c->done) return true;
+  // The lead workgroup of a matrix may set `done` during this very launch
+  // (the other workgroups then reach the same stopping decision from the
+  // same norms): the flag is read once per workgroup, so all its waves
+  // return together or carry on together.
+  if (__syncthreads_or(c->done != 0)) return true;
   double nu;
   int p;
   if (t.nopivot) {
@@ -301,8 +305,8 @@ __global__ __launch_bounds__(QB) void k_qrcp_step(const QrcpTask* __restrict__ t
   const int cpw = meta[1];
   const QrcpTask& t = tasks[w.x];
   if (!t.active) return;
-  qrcp_step_body<QB>(t, k, w.y, min(t.m, w.y + cpw), w.y == 0 && threadIdx.x == 0, kcnt, HSS_K_QRCP_STEP, vsh,
-                     rv, ri);
+  qrcp_step_body<QB>(t, k, w.y, min(t.m, w.y + cpw), w.y == 0 && threadIdx.x == 0, kcnt,
+                     t.nopivot ? HSS_K_TEST_QR : HSS_K_QRCP_STEP, vsh, rv, ri);
 }
 
 // The whole factorization of one matrix by one workgroup, every pivot step
@@ -596,7 +600,7 @@ void run_qrcp(QrcpTask* tasks, int32_t ntasks, const QrcpWork& wk, const int2* w
     prof_begin(s);
     for (int k = k0; k < k1; ++k)
       hipLaunchKernelGGL(k_qrcp_step, dim3(nwg), dim3(QB), lds, s, tasks, wk.chunks, wk.meta, k, kcnt);
-    prof_end(HSS_K_QRCP_STEP, s, k1 - k0);
+    prof_end(solve_e ? HSS_K_QRCP_STEP : HSS_K_TEST_QR, s, k1 - k0);
   }
   int32_t rmax = rank_known ? hw[1] : 0;
   if (!rank_known) HSS_HIP_CHECK(hipMemsetAsync(flag, 0, sizeof(int32_t), s));

@@ -61,7 +61,8 @@ class _Opt(C.Structure):
                 ("strategy", C.c_int32), ("d0", C.c_int32), ("delta_d", C.c_int32),
                 ("oversample_p", C.c_int32), ("d_max", C.c_int32), ("sample_precision", C.c_int32),
                 ("R", C.c_void_p), ("ldr", C.c_int64), ("ncols_R", C.c_int32),
-                ("profile", C.c_int32), ("stream", C.c_void_p), ("hmt_alpha", C.c_double)]
+                ("profile", C.c_int32), ("stream", C.c_void_p), ("hmt_alpha", C.c_double),
+                ("seed", C.c_uint64)]
 
 
 class _Info(C.Structure):
@@ -76,7 +77,9 @@ class _KStats(C.Structure):
 
 
 KCLASS = ["SAMPLE", "SAMPLE_REDUCE", "EXTRACT", "GATHER", "GEMM", "TEST_NORMS", "QRCP_STEP", "QRCP_OTHER",
-          "TRSM", "MISC", "QRCP_WG", "QFORM"]
+          "TRSM", "MISC", "QRCP_WG", "QFORM", "RNG", "TEST_QR"]
+
+MAX_D = 16384   # HSS_MAX_D
 
 
 class _NodeInfo(C.Structure):
@@ -90,7 +93,7 @@ EXPORTS = ["hss_tree_build", "hss_tree_free", "hss_compress", "hss_compress_batc
            "hss_matvec", "hss_rel_error", "hss_get_info", "hss_get_node_info", "hss_copy_node",
            "hss_sample", "hss_extract", "hss_interpolative_batched", "hss_last_error", "hss_version",
            "hss_get_kernel_stats", "hss_release_cache", "hss_mlp_num_params", "hss_mlp_forward", "hss_mlp_gradient",
-           "hss_mlp_adam", "hss_mlp_train"]
+           "hss_mlp_adam", "hss_mlp_train", "hss_random_normal", "hss_random_words"]
 
 MLP_MAX_LAYERS = 6
 
@@ -129,6 +132,8 @@ def lib():
     L.hss_extract.argtypes = [C.POINTER(_Gen), vp, i32, vp, i32, vp, vp, i64, vp]
     L.hss_interpolative_batched.argtypes = [i32, vp, vp, vp, vp, vp, dbl, dbl, vp, vp, vp, vp, vp]
     L.hss_release_cache.argtypes = []
+    L.hss_random_normal.argtypes = [i64, i32, i32, C.c_uint64, vp, i64, vp]
+    L.hss_random_words.argtypes = [i64, i32, i32, C.c_uint64, vp, i64, vp]
     flt, mp = C.c_float, C.POINTER(_Mlp)
     L.hss_mlp_num_params.argtypes = [mp, C.POINTER(i64)]
     L.hss_mlp_forward.argtypes = [mp, vp, vp, i64, vp, vp]
@@ -417,29 +422,35 @@ class HSSMatrix:
         return e.value
 
 
-def _opts(R, rtol, atol, eta, strategy, d0, delta_d, p, d_max, precision, profile=False, hmt_alpha=10.0):
-    ldr = _colmajor(R, "R")
+def _opts(R, rtol, atol, eta, strategy, d0, delta_d, p, d_max, precision, profile=False, hmt_alpha=10.0,
+          seed=0, n=None):
     o = _Opt()
     o.rtol, o.atol, o.eta = rtol, atol, eta
     o.strategy = STRATEGY[strategy]
     o.d0, o.delta_d, o.oversample_p = d0, delta_d, p
-    o.d_max = d_max if d_max is not None else R.shape[1]
     o.sample_precision = PRECISION[precision]
-    o.R = R.data_ptr()
-    o.ldr = ldr
-    o.ncols_R = R.shape[1]
+    if R is None:   # the library draws R from `seed`
+        o.d_max = d_max if d_max is not None else min(n, MAX_D)
+        o.R, o.ldr, o.ncols_R = None, 0, 0
+    else:
+        o.d_max = d_max if d_max is not None else R.shape[1]
+        o.R = R.data_ptr()
+        o.ldr = _colmajor(R, "R")
+        o.ncols_R = R.shape[1]
     o.profile = int(bool(profile))
     o.stream = _stream()
     o.hmt_alpha = hmt_alpha
+    o.seed = int(seed)
     return o
 
 
-def compress(gen: Generator, tree: Tree, R, rtol=1e-6, atol=1e-12, eta=1.0, strategy="dbl_fnorm",
-             d0=64, delta_d=64, p=10, d_max=None, precision="fp64", profile=False, hmt_alpha=10.0):
+def compress(gen: Generator, tree: Tree, R=None, rtol=1e-6, atol=1e-12, eta=1.0, strategy="dbl_fnorm",
+             d0=64, delta_d=64, p=10, d_max=None, precision="fp64", profile=False, hmt_alpha=10.0, seed=0):
     """Adaptive HSS compression (hss_compress).  R: (n, d_cap) float64 CUDA tensor,
-    column-major, rows in permuted order.  Returns (HSSMatrix, status)."""
+    column-major, rows in permuted order; or None, and the library draws R
+    on the device from `seed` (hss_random_normal).  Returns (HSSMatrix, status)."""
     g = gen._c()
-    o = _opts(R, rtol, atol, eta, strategy, d0, delta_d, p, d_max, precision, profile, hmt_alpha)
+    o = _opts(R, rtol, atol, eta, strategy, d0, delta_d, p, d_max, precision, profile, hmt_alpha, seed, gen.n)
     h = C.c_void_p()
     st = _check(lib().hss_compress(C.byref(g), tree._t, C.byref(o), C.byref(h)))
     return HSSMatrix(h.value, (gen, tree, R)), st
@@ -456,10 +467,11 @@ def compress_batched(gens, trees, Rs, **kw):
 
     G = (_Gen * k)(*[g._c() for g in gens])
     T = (C.POINTER(_Tree) * k)(*[t._t for t in trees])
+    Rs = list(Rs) if Rs is not None else [None] * k
     O = (_Opt * k)(*[_opts(R, opt("rtol", i, 1e-6), opt("atol", i, 1e-12), opt("eta", i, 1.0),
                            opt("strategy", i, "dbl_fnorm"), opt("d0", i, 64), opt("delta_d", i, 64),
                            opt("p", i, 10), opt("d_max", i, None), opt("precision", i, "fp64"),
-                           opt("profile", i, False), opt("hmt_alpha", i, 10.0))
+                           opt("profile", i, False), opt("hmt_alpha", i, 10.0), opt("seed", i, 0), gens[i].n)
                      for i, R in enumerate(Rs)])
     H = (C.c_void_p * k)()
     st = _check(lib().hss_compress_batched(k, G, T, O, H))
@@ -481,6 +493,24 @@ def sample(gen: Generator, perm, R, transpose=False, precision="fp64"):
     _check(lib().hss_sample(C.byref(g), _ptr(perm), R.shape[1], _ptr(R), ldr, _ptr(S),
                             _colmajor(S, "S"), int(transpose), PRECISION[precision], _stream()))
     return S
+
+
+def random_normal(n, c0, ncols, seed, device="cuda"):
+    """Columns c0 .. c0+ncols-1 of the library's Gaussian R (hss_random_normal),
+    an (n, ncols) column-major float64 CUDA tensor."""
+    import torch
+    R = colmajor(torch.empty((n, ncols), dtype=torch.float64, device=device))
+    _check(lib().hss_random_normal(n, c0, ncols, int(seed), _ptr(R), max(1, n), _stream()))
+    return R
+
+
+def random_words(n, c0, ncols, seed, device="cuda"):
+    """The raw Philox words behind random_normal (hss_random_words), as an
+    (n, ncols) column-major int64 CUDA tensor holding the uint64 bits."""
+    import torch
+    W = colmajor(torch.empty((n, ncols), dtype=torch.int64, device=device))
+    _check(lib().hss_random_words(n, c0, ncols, int(seed), _ptr(W), max(1, n), _stream()))
+    return W
 
 
 def extract(gen: Generator, perm, I, J):

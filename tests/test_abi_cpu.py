@@ -90,3 +90,62 @@ def test_binding_structs_match_the_header(tmp_path):
         assert int(got[cname]) == C.sizeof(cls), cname
         for f, _ in cls._fields_:
             assert int(got[cname + "." + f]) == getattr(cls, f).offset, cname + "." + f
+
+
+def _host_compress(tree, **over):
+    """hss_compress on a Toeplitz generator with host-only arguments (no
+    stream, no device pointers): argument errors must come back before any
+    HIP call, so this runs without a GPU."""
+    import ctypes as C
+
+    from paper_1810_04125_amd import hss as H
+    g = H._Gen()
+    g.family, g.symmetric, g.n, g.h = 0, 1, tree.n, 0.1
+    o = H._Opt()
+    o.rtol, o.atol, o.eta = 1e-6, 1e-12, 0.05
+    o.strategy, o.d0, o.delta_d, o.oversample_p, o.d_max = 1, 16, 16, 10, 64
+    o.R, o.seed = None, 0
+    for k, v in over.items():
+        setattr(o, k, v)
+    h = C.c_void_p()
+    st = H.lib().hss_compress(C.byref(g), tree._t, C.byref(o), C.byref(h))
+    return st, H.lib().hss_last_error().decode()
+
+
+def test_compress_rejects_a_perm_that_is_not_a_permutation():
+    T = hss.Tree(64, 16)
+    p = T._t.contents.perm
+    saved = p[5]
+    p[5] = p[6]               # index 6 twice, index 5 missing
+    st, msg = _host_compress(T)
+    assert st == -1 and "permutation" in msg
+    p[5] = 64                 # outside [0, n)
+    st, msg = _host_compress(T)
+    assert st == -1 and "permutation" in msg
+    p[5] = saved
+
+
+def test_compress_rejects_a_root_off_level_zero():
+    T = hss.Tree(64, 16)
+    lv = T._t.contents.level
+    for v in range(T.num_nodes):   # every level shifted: children still one below their parent
+        lv[v] = lv[v] - 1
+    st, msg = _host_compress(T)
+    assert st == -1 and "level 0" in msg
+    for v in range(T.num_nodes):
+        lv[v] = lv[v] + 1
+
+
+def test_compress_rejects_a_sample_cap_beyond_the_lds_vector():
+    T = hss.Tree(40000, 2048)
+    st, msg = _host_compress(T, d_max=hss.MAX_D + 1)
+    assert st == -1 and "HSS_MAX_D" in msg
+    # the cap that counts is min(d_max, n)
+    T2 = hss.Tree(64, 16)
+    st, msg = _host_compress(T2, d_max=hss.MAX_D + 1, rtol=-1.0)
+    assert st == -1 and "rtol" in msg
+
+
+def test_max_d_matches_the_header():
+    src = open(os.path.join(ROOT, "include", "hss.h")).read()
+    assert int(re.search(r"#define HSS_MAX_D (\d+)", src).group(1)) == hss.MAX_D
