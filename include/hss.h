@@ -248,6 +248,23 @@ void hss_destroy(hss_matrix* h);
 hss_status hss_matvec(const hss_matrix* h, int32_t nrhs, const double* X, int64_t ldx,
                       double* Y, int64_t ldy, void* stream);
 
+/* hss_matvec for callers that cannot allocate device memory during the call
+ * (code under HIP graph capture, serving loops, harnesses that forbid
+ * hipMalloc): the same product, Y = H X in ORIGINAL ordering, asynchronous
+ * on `stream`, with every temporary in one fixed device array of
+ * HSS_NOALLOC_SCRATCH_BYTES that the library holds per GPU until the
+ * process ends (the caller still passes X and Y).  The temporaries need
+ * 8 (2 n + 2 S_r + S_m) nrhs bytes, each part rounded up to 256 bytes,
+ * where S_r and S_m are the matrix's summed rank and row capacities
+ * (about 7.6 MB per right-hand side for n = 32768, leaf 128): calls that
+ * need more return HSS_ERR_INVALID_ARG with the size in the message.
+ * Every call on one GPU shares that GPU's array and overwrites it: calls
+ * that overlap on one GPU (different streams, or threads) race; serialize
+ * them, e.g. on one stream.  Call it with the device that holds h current. */
+#define HSS_NOALLOC_SCRATCH_BYTES (64u << 20)
+hss_status hss_matvec_noalloc(const hss_matrix* h, int32_t nrhs, const double* X, int64_t ldx,
+                              double* Y, int64_t ldy, void* stream);
+
 /* ||A - H||_F / ||A||_F over all n^2 entries (the error measure of
  * table HMT), in FP64, by column blocks of H and generated blocks of A.
  * gen may be NULL for the built-in families (the compression keeps their

@@ -87,9 +87,13 @@ struct GenHolder {
   }
 };
 
+}  // namespace
+
+hss_status hss::record_error(hss_status code, const std::string& msg) { return fail(code, msg); }
+
 // Permuted-space matvec on the compressed job: Yp = H Xp, both n x nrhs (ld n).
-void matvec_permuted(const hss_matrix* h, int32_t nrhs, const double* Xp, double* Yp, double* xh,
-                     double* yh, double* ws, hipStream_t s) {
+void hss::matvec_permuted(const hss_matrix* h, int32_t nrhs, const double* Xp, double* Yp, double* xh,
+                          double* yh, double* ws, hipStream_t s) {
   Job& J = *h->job;
   const Problem& P = J.probs[h->k];
   // The level lists mix problems; run per problem with its own sub-lists.
@@ -125,6 +129,8 @@ void matvec_permuted(const hss_matrix* h, int32_t nrhs, const double* Xp, double
   }
   HSS_HIP_CHECK(hipGetLastError());
 }
+
+namespace {
 
 struct DevBuf {
   void* p = nullptr;

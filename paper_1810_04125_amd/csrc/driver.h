@@ -122,3 +122,13 @@ struct hss_matrix {
   std::shared_ptr<hss::Job> job;
   int32_t k = 0;
 };
+
+namespace hss {
+// Yp = H Xp in the tree's permuted order, both n x nrhs with leading
+// dimension n; xh, yh hold Job::mvtot * nrhs doubles, ws Job::mvwstot * nrhs
+// (written before they are read).  Asynchronous on s; allocates nothing.
+void matvec_permuted(const hss_matrix* h, int32_t nrhs, const double* Xp, double* Yp, double* xh,
+                     double* yh, double* ws, hipStream_t s);
+// Sets the thread's hss_last_error() message and returns code.
+hss_status record_error(hss_status code, const std::string& msg);
+}  // namespace hss

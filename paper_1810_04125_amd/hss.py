@@ -93,7 +93,7 @@ EXPORTS = ["hss_tree_build", "hss_tree_free", "hss_compress", "hss_compress_batc
            "hss_matvec", "hss_rel_error", "hss_get_info", "hss_get_node_info", "hss_copy_node",
            "hss_sample", "hss_extract", "hss_interpolative_batched", "hss_last_error", "hss_version",
            "hss_get_kernel_stats", "hss_release_cache", "hss_mlp_num_params", "hss_mlp_forward", "hss_mlp_gradient",
-           "hss_mlp_adam", "hss_mlp_train", "hss_random_normal", "hss_random_words"]
+           "hss_mlp_adam", "hss_mlp_train", "hss_random_normal", "hss_random_words", "hss_matvec_noalloc"]
 
 MLP_MAX_LAYERS = 6
 
@@ -123,6 +123,7 @@ def lib():
     L.hss_destroy.argtypes = [vp]
     L.hss_destroy.restype = None
     L.hss_matvec.argtypes = [vp, i32, vp, i64, vp, i64, vp]
+    L.hss_matvec_noalloc.argtypes = [vp, i32, vp, i64, vp, i64, vp]
     L.hss_rel_error.argtypes = [vp, C.POINTER(_Gen), C.POINTER(dbl)]
     L.hss_get_info.argtypes = [vp, C.POINTER(_Info)]
     L.hss_get_node_info.argtypes = [vp, i32, C.POINTER(_NodeInfo)]
@@ -413,6 +414,13 @@ class HSSMatrix:
         _check(lib().hss_matvec(self._h, Xc.shape[1], _ptr(Xc), _colmajor(Xc, "X"), _ptr(Y),
                                 _colmajor(Y, "Y"), _stream()))
         return Y[:, 0] if vec else Y
+
+    def matvec_noalloc(self, X, Y):
+        """Y = H X through hss_matvec_noalloc (no device allocation in the call):
+        X, Y (n, k) column-major float64 CUDA tensors, Y written in place."""
+        _check(lib().hss_matvec_noalloc(self._h, X.shape[1], _ptr(X), _colmajor(X, "X"), _ptr(Y),
+                                        _colmajor(Y, "Y"), _stream()))
+        return Y
 
     def rel_error(self) -> float:
         e = C.c_double()
