@@ -53,7 +53,9 @@ KCLASS_INFO = {
     "SAMPLE": ("k_sample_f64", "mfma"),
     "GEMM": ("k_gemm_grouped+k_gemm_splitk_sum", "mfma"),
     "TEST_NORMS": ("k_fn_norms/k_cq_chol/k_fn_rtest", "hbm"),
-    "QRCP_STEP": ("k_qrcp_step", "hbm"),
+    "QRCP_STEP": ("k_qrcp_step", "mfma"),   # FP64-compute-bound by the ID's arithmetic intensity (r/2 flop/byte)
+    "TEST_QR": ("k_qrcp_step (stopping-test QR, no pivoting)", "hbm"),
+    "RNG": ("k_randn", "hbm"),
     "QRCP_WG": ("k_qrcp_wg", "hbm"),
     "QFORM": ("k_qf_prep/k_qf_solve/k_qform", "hbm"),
     "GATHER": ("k_ls_gather/k_red_gather/k_fn_copy", "hbm"),
@@ -102,6 +104,12 @@ TRAFFIC = {
         "fetch_scale": 1048576.0 / 524302.292, "write_scale": 1.0,  # 1 GiB copy: FETCH 524302 KiB, WRITE 1048576 KiB
     },
 }
+
+# Counters of the sampling kernel from rocprofv3 --pmc passes over one
+# compression of the workload (profiles/ holds the summaries): MFMA-busy and
+# VALU-busy fractions of the kernel's busy cycles.
+SAMPLE_COUNTERS = {}
+
 
 def traffic_bytes(workload, cls):
     import hashlib
@@ -457,6 +465,94 @@ def main_table(args, log):
     print(json.dumps(out))
 
 
+def run_once(W, gen, T, kw, steps, warmup, log, tag):
+    """Time `steps` compressions of one workload (after `warmup`), then check
+    the error of the last one.  Returns (H, status, seconds, summary)."""
+    from paper_1810_04125_amd import hss
+    (H, st), el = timed(lambda: hss.compress(gen, T, None, **kw), steps, warmup, log, tag)
+    info = H.info()
+    err, kind = probe_error(gen, T, H, W["n"])
+    summ = {"compressions_per_s": round(steps / el, 4), "ms_per_step": round(1e3 * el / steps, 3),
+            "rel_err": err, "rel_err_kind": kind, "rel_err_ok": bool(err <= kw["rtol"]), "status": st,
+            "rounds": info["rounds"], "d_final": info["d_final"], "hss_rank": info["hss_rank"]}
+    log("bench: %s %s" % (tag, json.dumps(summ)))
+    return H, st, el, summ
+
+
+def mixed_leg(args, log):
+    """Sampling in FP32 and BF16x3 against FP64 on the Gaussian-kernel
+    workload (n = 65536, kd tree, leaf 256, incrementing d0 = 128), at rtol
+    1e-6 and 1e-4: compressions/s, error and status of each."""
+    W = WORKLOADS["gauss-cube-65536"]
+    gen, T, _ = setup(W)
+    out = {"workload": "gauss-cube-65536", "steps": args.leg_steps}
+    for rtol in (1e-6, 1e-4):
+        row = {}
+        for prec in ("fp64", "fp32", "bf16x3"):
+            kw = dict(rtol=rtol, atol=1e-12, eta=ETA, strategy=W["strategy"], d0=W["d0"], delta_d=W["delta_d"],
+                      d_max=W["d_max"], precision=prec, seed=0)
+            H, st, el, summ = run_once(W, gen, T, kw, args.leg_steps, 1, log, "mixed %s rtol %g" % (prec, rtol))
+            row[prec] = summ
+            del H
+        for prec in ("fp32", "bf16x3"):
+            row[prec]["speedup_vs_fp64"] = round(row[prec]["compressions_per_s"] / row["fp64"]["compressions_per_s"], 3)
+        out["rtol=%g" % rtol] = row
+    return out
+
+
+def learned_leg(args, name, log):
+    """Learned d0 (the predictor network run inside hss_compress) against the
+    adaptive start d0 = 128 on one workload: compressions/s, rounds saved and
+    the rank-prediction error per tree level."""
+    import numpy as np
+
+    from paper_1810_04125_amd import hss
+    from paper_1810_04125_amd.learned import D0Predictor
+    W = WORKLOADS[name]
+    gen, T, _ = setup(W)
+    n = W["n"]
+    kw = dict(rtol=args.rtol, atol=1e-12, eta=ETA, strategy=W["strategy"], d0=W["d0"], delta_d=W["delta_d"],
+              d_max=W["d_max"], seed=W.get("r_seed", 0))
+    pred = D0Predictor()
+    Hl, stl, ell, sl = run_once(W, gen, T, dict(kw, predictor=pred.handle()), args.leg_steps, 1, log,
+                                "learned %s" % name)
+    Hb, stb, elb, sb = run_once(W, gen, T, kw, args.leg_steps, 1, log, "adaptive %s" % name)
+    param = W.get("h", W.get("sigma"))
+    p = pred.predict(W["family"], param, n, T, args.rtol)
+    act = np.zeros(int(T.level.max()) + 1)
+    for node in range(T.num_nodes):
+        ni = Hb.node_info(node)
+        act[T.level[node]] = max(act[T.level[node]], ni["rank_r"], ni["rank_c"])
+    lr_pred = np.array(p["level_rank"])
+    return {"workload": name, "steps": args.leg_steps, "learned": sl, "adaptive": sb,
+            "d0_learned": Hl.info()["d0"], "d0_adaptive": W["d0"],
+            "speedup": round(sb["ms_per_step"] / sl["ms_per_step"], 3),
+            "rounds_saved": sb["rounds"] - sl["rounds"],
+            "d_final_predicted": round(p["d_final"], 1),
+            "d_final_pred_rel_err": round(p["d_final"] / sb["d_final"] - 1.0, 4),
+            "level_rank_predicted": [round(x, 1) for x in lr_pred],
+            "level_rank_actual": [int(x) for x in act[1:]],
+            "rank_pred_mae_log2": round(float(np.mean(np.abs(np.log2(1 + lr_pred) - np.log2(1 + act[1:])))), 4)}
+
+
+def id_roofline(stats):
+    """The per-level ID (rows a6-a8 of the method): its algorithmic work as the
+    method defines it (class ID: 4 d m r flops, 8 d m + 8 r (m - r) bytes per
+    factored panel) over the GPU time of the kernels that ran it."""
+    ms = sum(stats[c]["ms"] for c in ("QRCP_STEP", "QRCP_WG", "QRCP_OTHER", "TRSM"))
+    idc = stats["ID"]
+    sec = ms / 1e3
+    if sec <= 0:
+        return None
+    tf = idc["flops"] / sec / 1e12
+    gb = idc["bytes"] / sec / 1e9
+    return {"kernels": "k_qrcp_step+k_qrcp_wg+k_qrcp_plan/init/alive/fin/egather+k_qrfirst*+k_trsm_diag",
+            "id_calls": idc["launches"], "ms": round(ms, 2), "alg_tflop": round(idc["flops"] / 1e12, 4),
+            "alg_gb": round(idc["bytes"] / 1e9, 3), "achieved_tflops": round(tf, 3),
+            "frac_fp64_peak": round(tf / PEAK_FP64_TFLOPS, 5), "achieved_GBps": round(gb, 1),
+            "frac_hbm_peak": round(gb / PEAK_HBM_GBS, 5)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -468,6 +564,9 @@ def main():
     ap.add_argument("--rtol", type=float, default=1e-6)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="skip the mixed-precision and learned-d0 legs of the default line")
+    ap.add_argument("--leg-steps", type=int, default=3)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a device-to-device copy of 1 GiB three times (reference for HBM counters)")
     ap.add_argument("--table", choices=["hmt", "adaptive-rank"],
@@ -494,73 +593,52 @@ def main():
         return main_table(args, log)
     if W.get("batch"):
         return main_batch(args, W, log)
+    if W.get("learned"):
+        print(json.dumps(learned_leg(args, args.workload, log)), flush=True)
+        return
     n = W["n"]
     log("bench: workload %s precision %s rtol %g" % (args.workload, args.precision, args.rtol))
-    gen, T, R = setup(W)
+    gen, T, _ = setup(W)
     kw = dict(rtol=args.rtol, atol=1e-12, eta=ETA, strategy=W["strategy"], d0=W["d0"], delta_d=W["delta_d"],
               d_max=W["d_max"], precision=args.precision, seed=W.get("r_seed", 0))
-    learned = None
-    if W.get("learned"):
-        from paper_1810_04125_amd.learned import D0Predictor
-        pred = D0Predictor()
-        param = W.get("h", W.get("sigma"))
-
-        def learned_step():
-            d0 = pred.d0(W["family"], param, n, T, args.rtol, W["delta_d"], W["d_max"])
-            return hss.compress(gen, T, R, **dict(kw, d0=d0))
-
-        (H, st), el = timed(learned_step, args.steps, args.warmup, log, "learned")
-        (Hb, stb), elb = timed(lambda: hss.compress(gen, T, R, **kw), args.steps, args.warmup, log, "baseline")
-        p = pred.predict(W["family"], param, n, T, args.rtol)
-        d0L = pred.d0(W["family"], param, n, T, args.rtol, W["delta_d"], W["d_max"])
-        ib = Hb.info()
-        # largest node rank per level of the baseline compression vs the prediction
-        act = np.zeros(int(T.level.max()) + 1)
-        for node in range(T.num_nodes):
-            ni = Hb.node_info(node)
-            act[T.level[node]] = max(act[T.level[node]], ni["rank_r"], ni["rank_c"])
-        lr_pred = np.array(p["level_rank"])
-        eb, _ = probe_error(gen, T, Hb, n)
-        learned = {"d0_predicted": d0L, "d_final_predicted": round(p["d_final"], 1),
-                   "baseline": {"d0": W["d0"], "compressions_per_s": round(args.steps / elb, 4),
-                                "ms_per_step": round(1e3 * elb / args.steps, 3), "rounds": ib["rounds"],
-                                "d_final": ib["d_final"], "hss_rank": ib["hss_rank"], "rel_err": eb,
-                                "status": stb},
-                   "speedup": round(elb / el, 3),
-                   "rounds_saved": ib["rounds"] - H.info()["rounds"],
-                   "level_rank_predicted": [round(x, 1) for x in lr_pred],
-                   "level_rank_actual": [int(x) for x in act[1:]],
-                   "rank_pred_mae_log2": round(float(np.mean(np.abs(np.log2(1 + lr_pred) -
-                                                                   np.log2(1 + act[1:])))), 4),
-                   "d_final_pred_rel_err": round(p["d_final"] / ib["d_final"] - 1.0, 4)}
-        del Hb
-    else:
-        (H, st), el = timed(lambda: hss.compress(gen, T, R, **kw), args.steps, args.warmup, log, "fp64"
-                            if args.precision == "fp64" else args.precision)
+    (H, st), el = timed(lambda: hss.compress(gen, T, None, **kw), args.steps, args.warmup, log,
+                        args.precision)
     info = H.info()
     log("bench: timed %d steps in %.3f s; info %s" % (args.steps, el, info))
     err, kind = probe_error(gen, T, H, n)
     log("bench: rel err %.3e (%s)" % (err, kind))
+    del H
 
     rl = None
     if not args.no_profile:
-        Hp, _ = hss.compress(gen, T, R, profile=True, **dict(kw, d0=(learned or {}).get("d0_predicted", W["d0"])))
+        Hp, _ = hss.compress(gen, T, None, profile=True, **kw)
         stats = Hp.kernel_stats()
         rl = roofline(stats, args.precision)
         rl["traffic"] = traffic_bytes(args.workload, rl["class"])
         rl["traffic_unit"] = "bytes per launch (HBM, measured)"
-        rl["algorithmic_bytes_per_launch"] = round(stats[rl["class"]]["bytes"] / max(1, rl["launches"]), 1)
+        rl["algorithmic_per_launch"] = {"flops": round(stats[rl["class"]]["flops"] / max(1, rl["launches"]), 1),
+                                        "bytes": round(stats[rl["class"]]["bytes"] / max(1, rl["launches"]), 1)}
         samp = stats["SAMPLE"]
         skern = "k_sample_f64" if args.precision == "fp64" else "k_sample_lp"
         speak = {"fp64": PEAK_FP64_TFLOPS, "fp32": PEAK_FP32_TFLOPS, "bf16x3": PEAK_BF16_TFLOPS}[args.precision]
+        mult = 3.0 if args.precision == "bf16x3" else 1.0   # BF16x3: three bf16 products per product
+        stf = samp["flops"] / (samp["ms"] / 1e3) / 1e12
         rl["sampling_kernel"] = {"kernel": skern, "launches": samp["launches"],
-                                 "achieved_tflops": round(samp["flops"] / (samp["ms"] / 1e3) / 1e12, 3),
-                                 "frac_of_peak": round(samp["flops"] / (samp["ms"] / 1e3) / 1e12 / speak, 4),
-                                 "peak_tflops": speak,
-                                 "avg_launch_us": round(1e3 * samp["ms"] / max(1, samp["launches"]), 3)}
+                                 "achieved_tflops": round(stf, 3),
+                                 "mfma_tflops": round(mult * stf, 3),
+                                 "frac_of_peak": round(mult * stf / speak, 4), "peak_tflops": speak,
+                                 "avg_launch_us": round(1e3 * samp["ms"] / max(1, samp["launches"]), 3),
+                                 "counters": SAMPLE_COUNTERS.get((args.workload, args.precision))}
+        rl["id"] = id_roofline(stats)
         rl["profiled_gpu_ms_by_class"] = {k: round(v["ms"], 2) for k, v in stats.items()}
         log("bench: profile %s" % json.dumps(rl))
         del Hp
+
+    legs = {}
+    if not args.no_legs and args.workload == "laplace-sphere-32768" and args.precision == "fp64":
+        legs["mixed"] = mixed_leg(args, log)
+        legs["learned"] = [learned_leg(args, nm, log) for nm in ("learned-laplace-sphere-65536",
+                                                                 "learned-toeplitz-131072")]
 
     cpu = None
     if not args.no_cpu:
@@ -569,9 +647,9 @@ def main():
 
     value = args.steps / el
     cfg = {"workload": args.workload, "n": n, "leaf": W["leaf"], "tree": W["method"],
-           "strategy": W["strategy"], "d0": "learned" if learned else W["d0"], "delta_d": W["delta_d"],
+           "strategy": W["strategy"], "d0": W["d0"], "delta_d": W["delta_d"],
            "rtol": args.rtol, "atol": 1e-12, "eta": ETA, "d_max": W["d_max"],
-           "sampling": args.precision}
+           "sampling": args.precision, "r": "device Philox4x64-10 + Box-Muller, seed %d" % W.get("r_seed", 0)}
     out = {
         "metric": METRIC, "value": round(value, 4), "unit": "compressions/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * el / args.steps, 3),
@@ -581,8 +659,9 @@ def main():
         "rel_err": err, "rel_err_kind": kind, "rel_err_ok": bool(err <= args.rtol), "status": st,
         "sampling_tflops": round(info["sample_flops"] / (info["sample_ms"] / 1e3) / 1e12, 3),
         "rounds": info["rounds"], "d_final": info["d_final"], "hss_rank": info["hss_rank"],
-        "learned": learned, "roofline": rl, "cpu_baseline": cpu,
+        "roofline": rl, "cpu_baseline": cpu,
     }
+    out.update(legs)
     print(json.dumps(out), flush=True)
 
 

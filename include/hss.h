@@ -172,6 +172,29 @@ hss_status hss_tree_build(int64_t n, const double* points_host, int32_t leaf_siz
                           int32_t method, hss_tree** out);
 void hss_tree_free(hss_tree* tree);
 
+/* Learned start of the incrementing strategy (not part of the paper's
+ * method; see the predictor network calls below).  With
+ * options.predictor set, hss_compress first runs the network on one
+ * feature row per tree level of the problem (family one-hot; 0.5 log2 of
+ * the kernel parameter, h for Toeplitz or sigma for the Gaussian kernel,
+ * 0 for Laplace; (log2 n - 14)/3; level/8; (log2 of the level's mean node
+ * size - 10)/4; (-log10 rtol - 6)/2) and takes d0 = the predicted final
+ * sample count 2^y (output 1 of the root row) rounded down to a multiple
+ * of delta_d, within [delta_d, min(d_max, n)].  The stopping tests still
+ * decide every node: a low prediction costs rounds, a high one samples.
+ * Only for HSS_FAM_TOEPLITZ, HSS_FAM_LAPLACE and HSS_FAM_GAUSS with the
+ * incrementing strategies; options.d0 is then ignored. */
+#define HSS_MLP_MAX_LAYERS 6
+#define HSS_MLP_MAX_WIDTH 128
+typedef struct {
+  int32_t n_layers;                        /* 1 .. HSS_MLP_MAX_LAYERS */
+  int32_t sizes[HSS_MLP_MAX_LAYERS + 1];   /* each 1 .. HSS_MLP_MAX_WIDTH */
+} hss_mlp;
+typedef struct {
+  hss_mlp net;             /* sizes[0] = 8 inputs, sizes[n_layers] = 2 outputs */
+  const float* params;     /* device, hss_mlp_num_params floats (layout below) */
+} hss_predictor;
+
 /* Options of one compression (Alg. 3).
  *   rtol, atol : relative / absolute tolerance; every node tau uses
  *                eta*rtol/level(tau) and eta*atol/level(tau)
@@ -190,7 +213,8 @@ void hss_tree_free(hss_tree* tree);
  *                round only the new ones, from the counter-based generator
  *                of hss_random_normal with `seed` (ldr and ncols_R unused)
  *   stream     : hipStream_t for all work (NULL = default stream)
- *   seed       : key of the generated R (used only when R is NULL) */
+ *   seed       : key of the generated R (used only when R is NULL)
+ *   predictor  : learned d0 (hss_predictor above), or NULL */
 typedef struct {
   double rtol;
   double atol;
@@ -208,6 +232,7 @@ typedef struct {
   void* stream;
   double hmt_alpha;
   uint64_t seed;
+  const hss_predictor* predictor;   /* host struct, NULL = off: learned d0 (above) */
 } hss_options;
 
 /* Largest sample count of a compression: a pivot step of the ID keeps its
@@ -284,6 +309,9 @@ typedef struct {
   double sample_ms;    /* summed HIP-event time of the sampling launches */
   double total_ms;     /* wall time of hss_compress */
   double sample_flops; /* 2 n^2 d_final per product computed */
+  int32_t d0;          /* initial sample count used (the predictor's when one was given) */
+  int32_t pad;
+  double d_predicted;  /* the predictor's final sample count (0 without one) */
 } hss_info;
 
 hss_status hss_get_info(const hss_matrix* h, hss_info* out);
@@ -316,12 +344,17 @@ hss_status hss_get_info(const hss_matrix* h, hss_info* out);
  *                (8 bytes written per entry)
  *   TEST_QR      Householder steps of the stopping test's QR of the projected
  *                block (no pivoting), counted as QRCP_STEP; QRCP_STEP then
- *                holds the pivot steps of the ID only */
+ *                holds the pivot steps of the ID only
+ *   ID           totals of the interpolative decompositions as the method
+ *                defines their work, whatever kernels ran them: per factored
+ *                d x m panel of rank r, 8 d m + 8 r (m - r) bytes (the panel
+ *                read once, E written) and 4 d m r flops; launches = ID calls
+ *                (one per level and side with a node to factor), ms = 0 */
 enum {
   HSS_K_SAMPLE = 0, HSS_K_SAMPLE_REDUCE = 1, HSS_K_EXTRACT = 2, HSS_K_GATHER = 3, HSS_K_GEMM = 4,
   HSS_K_TEST_NORMS = 5, HSS_K_QRCP_STEP = 6, HSS_K_QRCP_OTHER = 7, HSS_K_TRSM = 8, HSS_K_MISC = 9,
-  HSS_K_QRCP_WG = 10, HSS_K_QFORM = 11, HSS_K_RNG = 12, HSS_K_TEST_QR = 13,
-  HSS_K_COUNT = 14
+  HSS_K_QRCP_WG = 10, HSS_K_QFORM = 11, HSS_K_RNG = 12, HSS_K_TEST_QR = 13, HSS_K_ID = 14,
+  HSS_K_COUNT = 15
 };
 typedef struct {
   int64_t launches;
@@ -442,12 +475,7 @@ hss_status hss_release_cache(void);
  * ROW-major) followed by b_l (sizes[l+1]).  Samples are ROW-major: X is
  * n x sizes[0], Y, T (targets) and M (0/1 masks) are n x sizes[n_layers].
  * Loss: sum(M (Y - T)^2) / max(1, sum M); Adam as Kingma and Ba (2015). */
-#define HSS_MLP_MAX_LAYERS 6
-#define HSS_MLP_MAX_WIDTH 128
-typedef struct {
-  int32_t n_layers;                        /* 1 .. HSS_MLP_MAX_LAYERS */
-  int32_t sizes[HSS_MLP_MAX_LAYERS + 1];   /* each 1 .. HSS_MLP_MAX_WIDTH */
-} hss_mlp;
+/* (hss_mlp and HSS_MLP_MAX_* are defined above, with hss_predictor.) */
 
 /* Number of parameters (floats) of the network, to host *out. */
 hss_status hss_mlp_num_params(const hss_mlp* net, int64_t* out);

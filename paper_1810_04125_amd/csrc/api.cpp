@@ -220,6 +220,51 @@ void check_device_index(const int64_t* idx, int32_t cnt, int64_t n, const char* 
     if (v < 0 || v >= n) throw Error(HSS_ERR_INVALID_ARG, std::string(what) + " holds an index outside [0, n)");
 }
 
+// Learned start (hss_predictor): the network's prediction of the final
+// sample count from one feature row per tree level, turned into d0.
+int32_t predict_d0(const hss_generator& g, const hss_tree* t, const hss_options& o, hipStream_t s,
+                   double* dpred) {
+  const hss_predictor& pr = *o.predictor;
+  if (!pr.params) throw Error(HSS_ERR_INVALID_ARG, "predictor: params is NULL");
+  const MlpShape S = mlp_shape(pr.net);
+  if (pr.net.sizes[0] != 8 || pr.net.sizes[pr.net.n_layers] != 2)
+    throw Error(HSS_ERR_INVALID_ARG, "predictor: the network must map 8 features to 2 outputs");
+  int32_t L = 0;
+  for (int32_t v = 0; v < t->num_nodes; ++v) L = std::max(L, t->level[v]);
+  std::vector<double> sum(L + 1, 0.0), cnt(L + 1, 0.0);
+  for (int32_t v = 0; v < t->num_nodes; ++v) {
+    sum[t->level[v]] += (double)(t->hi[v] - t->lo[v]);
+    cnt[t->level[v]] += 1.0;
+  }
+  const int fam = g.family == HSS_FAM_TOEPLITZ ? 0 : g.family == HSS_FAM_LAPLACE ? 1 : 2;
+  const double param = g.family == HSS_FAM_TOEPLITZ ? g.h : g.family == HSS_FAM_GAUSS ? g.sigma : 0.0;
+  std::vector<float> X((size_t)(L + 1) * 8, 0.0f), Y((size_t)(L + 1) * 2, 0.0f);
+  for (int32_t l = 0; l <= L; ++l) {
+    float* f = X.data() + 8 * l;
+    f[fam] = 1.0f;
+    f[3] = fam == 1 ? 0.0f : (float)(0.5 * std::log2(param));
+    f[4] = (float)((std::log2((double)g.n) - 14.0) / 3.0);
+    f[5] = (float)(l / 8.0);
+    f[6] = (float)((std::log2(std::max(1.0, sum[l] / cnt[l])) - 10.0) / 4.0);
+    f[7] = (float)((-std::log10(o.rtol) - 6.0) / 2.0);
+  }
+  DevBuf xd(sizeof(float) * X.size()), yd(sizeof(float) * Y.size());
+  HSS_HIP_CHECK(hipMemcpyAsync(xd.p, X.data(), sizeof(float) * X.size(), hipMemcpyHostToDevice, s));
+  launch_mlp_tile(S, pr.params, xd.as<float>(), nullptr, nullptr, 0, L + 1, 1, 0, L + 1, yd.as<float>(), nullptr,
+                  nullptr, 0, s);
+  HSS_HIP_CHECK(hipGetLastError());
+  HSS_HIP_CHECK(hipMemcpyAsync(Y.data(), yd.p, sizeof(float) * Y.size(), hipMemcpyDeviceToHost, s));
+  HSS_HIP_CHECK(hipStreamSynchronize(s));
+  const double d = std::exp2((double)Y[1]);   // root row, output 1: log2 of the final sample count
+  if (!std::isfinite(d)) throw Error(HSS_ERR_NONFINITE, "predictor output is not finite");
+  *dpred = d;
+  const int32_t dd = o.delta_d;
+  const int64_t cap = std::min<int64_t>(o.d_max, g.n);
+  const double q = std::floor(std::min(d, (double)cap) / dd);
+  int64_t d0 = std::max<int64_t>(dd, (int64_t)dd * (int64_t)q);
+  return (int32_t)std::min<int64_t>(d0, cap);
+}
+
 void need(const void* p, const char* what) {
   if (!p) throw Error(HSS_ERR_INVALID_ARG, std::string(what) + " must not be NULL");
 }
@@ -251,6 +296,12 @@ hss_status hss_compress_batched(int32_t count, const hss_generator* gens, const 
       if (!trees[k]) throw Error(HSS_ERR_INVALID_ARG, "NULL tree");
     // every argument is checked on the host before the first HIP call
     for (int32_t k = 0; k < count; ++k) Job::validate(gens[k], trees[k], opts[k], k);
+    // learned starts: the predictor's d0 replaces options.d0
+    std::vector<hss_options> op(opts, opts + count);
+    std::vector<double> dpred(count, 0.0);
+    for (int32_t k = 0; k < count; ++k)
+      if (op[k].predictor) op[k].d0 = predict_d0(gens[k], trees[k], op[k], (hipStream_t)op[k].stream, &dpred[k]);
+    opts = op.data();
     // Problems are taken in order into groups whose estimated device memory
     // fits the free HBM at the time the group starts (earlier groups keep only
     // their generators); every group is one level-batched job.
@@ -284,6 +335,7 @@ hss_status hss_compress_batched(int32_t count, const hss_generator* gens, const 
                      job->alloc_ms, std::chrono::duration<double, std::milli>(t2 - t1).count(), job->sample_ms);
       }
       for (int32_t k = g0; k < g1; ++k) {
+        job->probs[k - g0].d_pred = dpred[k];
         if (job->probs[k - g0].status > worst) worst = job->probs[k - g0].status;
         res[k].reset(new hss_matrix);
         res[k]->job = job;
@@ -327,6 +379,8 @@ hss_status hss_get_info(const hss_matrix* h, hss_info* out) {
     out->sample_ms = J.sample_ms;
     out->total_ms = J.total_ms;
     out->sample_flops = 2.0 * (double)P.n * (double)P.n * P.d * (P.sym ? 1 : 2);
+    out->d0 = P.sched.empty() ? 0 : P.sched[0];
+    out->d_predicted = P.d_pred;
     return HSS_OK;
   });
 }

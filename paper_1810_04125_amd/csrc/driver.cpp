@@ -39,6 +39,10 @@ void prof_end(int cls, hipStream_t s, int nlaunch) {
   if (hipEventElapsedTime(&ms, g_prof->e0, g_prof->e1) == hipSuccess) g_prof->ms[cls] += ms;
 }
 
+void prof_count(int cls, int n) {
+  if (g_prof) g_prof->launches[cls] += n;
+}
+
 // Makes the job's profiler current for the calling thread while alive.
 struct ProfScope {
   Prof* saved;
@@ -269,7 +273,10 @@ void Job::validate(const hss_generator& g, const hss_tree* t, const hss_options&
   if (!(o.rtol >= 0.0) || !(o.atol >= 0.0) || !(o.eta > 0.0))
     throw Error(HSS_ERR_INVALID_ARG, who + "need rtol >= 0, atol >= 0, eta > 0");
   if (o.strategy < 0 || o.strategy > 3) throw Error(HSS_ERR_INVALID_ARG, who + "unknown strategy");
-  if (o.d0 < 1 || o.d_max < 1) throw Error(HSS_ERR_INVALID_ARG, who + "need d0 >= 1 and d_max >= 1");
+  if ((!o.predictor && o.d0 < 1) || o.d_max < 1) throw Error(HSS_ERR_INVALID_ARG, who + "need d0 >= 1 and d_max >= 1");
+  if (o.predictor && (!gen_formula(g.family) || (o.strategy != HSS_INC_FNORM && o.strategy != HSS_INC_HMT)))
+    throw Error(HSS_ERR_INVALID_ARG, who + "the predictor needs a generated family and an incrementing strategy");
+  if (o.predictor && !(o.rtol > 0.0)) throw Error(HSS_ERR_INVALID_ARG, who + "the predictor needs rtol > 0");
   if ((o.strategy == HSS_INC_FNORM || o.strategy == HSS_INC_HMT) && o.delta_d < 1)
     throw Error(HSS_ERR_INVALID_ARG, who + "need delta_d >= 1");
   if (o.strategy == HSS_INC_HMT && !(o.hmt_alpha >= 0.0)) throw Error(HSS_ERR_INVALID_ARG, who + "need hmt_alpha >= 0");

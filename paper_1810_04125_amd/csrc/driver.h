@@ -28,6 +28,7 @@ struct Problem {
   std::vector<int32_t> sched;
   int32_t* sched_d = nullptr;
   int64_t* pos_d = nullptr;   // caller operators: device 0..n-1 (leaf index lists)
+  double d_pred = 0.0;        // the learned predictor's final sample count (0: none)
 };
 
 struct LevelInfo {

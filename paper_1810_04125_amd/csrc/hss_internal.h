@@ -154,6 +154,8 @@ struct QrcpTask {
   int32_t nopivot;   // 1: plain Householder QR (column k is the k-th pivot)
   double* qrf = nullptr;     // workspace of the QR-first reduction of a tall panel (k_qrfirst.hip)
   int64_t qrf_elems = 0;
+  int32_t d_orig = 0;        // samples of the local sample (d before a QR-first reduction); 0: d
+  int32_t pad2 = 0;
 };
 
 // Explicit Q of a Householder QR done by run_qrcp in nopivot mode:
@@ -251,6 +253,8 @@ void prof_begin(hipStream_t s);
 // Closes the interval opened by prof_begin and charges it to class cls;
 // nlaunch kernels were launched back to back inside it.
 void prof_end(int cls, hipStream_t s, int nlaunch = 1);
+// Counts n units of class cls without timing (classes that only total work).
+void prof_count(int cls, int n);
 
 __device__ __forceinline__ void kcount(unsigned long long* kc, int cls, double bytes, double flops) {
   if (!kc) return;

@@ -978,6 +978,7 @@ __global__ void k_build_qrcp(LevelArgs a, int side, int hmt, QrcpTask* __restric
   q.hmt_mn = hmt ? (double)min(size, P.n - size) : 0.0;
   q.m = st.m[side];
   q.d = P.d;
+  q.d_orig = P.d;
   q.mcap = nd.mcap;
   q.nopivot = 0;
   // QR-first workspace: the rest of the node's wsB slot after the scratch

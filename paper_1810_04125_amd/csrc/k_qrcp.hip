@@ -396,7 +396,8 @@ static int32_t* host_words(int32_t** dev) {
 }
 
 // rank, the ascending rest of J, max rank of the batch
-__global__ __launch_bounds__(QB) void k_qrcp_fin(const QrcpTask* __restrict__ tasks, int32_t* maxrank) {
+__global__ __launch_bounds__(QB) void k_qrcp_fin(const QrcpTask* __restrict__ tasks, int32_t* maxrank,
+                                                 unsigned long long* __restrict__ kcnt) {
   const QrcpTask& t = tasks[blockIdx.x];
   if (!t.active) return;
   __shared__ int cnt[QB];
@@ -430,6 +431,10 @@ __global__ __launch_bounds__(QB) void k_qrcp_fin(const QrcpTask* __restrict__ ta
   if (threadIdx.x == 0) {
     *t.rank_out = r;
     if (maxrank) atomicMax(maxrank, r);
+    // the ID's algorithmic work: the d x m panel read once, E written, and
+    // 4 d m r flops of a QR with column pivoting to rank r
+    const double d0 = (double)max(d, t.d_orig);
+    if (!t.nopivot) kcount(kcnt, HSS_K_ID, 8.0 * d0 * m + 8.0 * (double)r * (m - r), 4.0 * d0 * m * r);
   }
 }
 
@@ -605,8 +610,9 @@ void run_qrcp(QrcpTask* tasks, int32_t ntasks, const QrcpWork& wk, const int2* w
   int32_t rmax = rank_known ? hw[1] : 0;
   if (!rank_known) HSS_HIP_CHECK(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
   prof_begin(s);
-  hipLaunchKernelGGL(k_qrcp_fin, dim3(ntasks), dim3(QB), 0, s, tasks, rank_known ? nullptr : flag);
+  hipLaunchKernelGGL(k_qrcp_fin, dim3(ntasks), dim3(QB), 0, s, tasks, rank_known ? nullptr : flag, kcnt);
   prof_end(HSS_K_QRCP_OTHER, s);
+  if (solve_e) prof_count(HSS_K_ID, 1);
   if (!solve_e) return;
   prof_begin(s);
   hipLaunchKernelGGL(k_qrcp_egather, dim3(ntasks, (unsigned)std::max(1, std::min(256, 4096 / ntasks))), dim3(QB),

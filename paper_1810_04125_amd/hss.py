@@ -62,14 +62,14 @@ class _Opt(C.Structure):
                 ("oversample_p", C.c_int32), ("d_max", C.c_int32), ("sample_precision", C.c_int32),
                 ("R", C.c_void_p), ("ldr", C.c_int64), ("ncols_R", C.c_int32),
                 ("profile", C.c_int32), ("stream", C.c_void_p), ("hmt_alpha", C.c_double),
-                ("seed", C.c_uint64)]
+                ("seed", C.c_uint64), ("predictor", C.c_void_p)]
 
 
 class _Info(C.Structure):
     _fields_ = [("n", C.c_int64), ("num_nodes", C.c_int32), ("rounds", C.c_int32),
                 ("d_final", C.c_int32), ("hss_rank", C.c_int32), ("status", C.c_int32),
                 ("symmetric", C.c_int32), ("sample_ms", C.c_double), ("total_ms", C.c_double),
-                ("sample_flops", C.c_double)]
+                ("sample_flops", C.c_double), ("d0", C.c_int32), ("pad", C.c_int32), ("d_predicted", C.c_double)]
 
 
 class _KStats(C.Structure):
@@ -77,7 +77,7 @@ class _KStats(C.Structure):
 
 
 KCLASS = ["SAMPLE", "SAMPLE_REDUCE", "EXTRACT", "GATHER", "GEMM", "TEST_NORMS", "QRCP_STEP", "QRCP_OTHER",
-          "TRSM", "MISC", "QRCP_WG", "QFORM", "RNG", "TEST_QR"]
+          "TRSM", "MISC", "QRCP_WG", "QFORM", "RNG", "TEST_QR", "ID"]
 
 MAX_D = 16384   # HSS_MAX_D
 
@@ -100,6 +100,19 @@ MLP_MAX_LAYERS = 6
 
 class _Mlp(C.Structure):
     _fields_ = [("n_layers", C.c_int32), ("sizes", C.c_int32 * (MLP_MAX_LAYERS + 1))]
+
+
+class _Predictor(C.Structure):
+    _fields_ = [("net", _Mlp), ("params", C.c_void_p)]
+
+
+class Predictor:
+    """hss_predictor: a network (layer sizes 8 -> ... -> 2) and its device
+    FP32 parameters, run by hss_compress to pick d0."""
+
+    def __init__(self, sizes, params):
+        self.params = params            # keeps the device tensor alive
+        self._c = _Predictor(_mlp(sizes), params.data_ptr())
 
 
 def lib():
@@ -431,7 +444,7 @@ class HSSMatrix:
 
 
 def _opts(R, rtol, atol, eta, strategy, d0, delta_d, p, d_max, precision, profile=False, hmt_alpha=10.0,
-          seed=0, n=None):
+          seed=0, n=None, predictor=None):
     o = _Opt()
     o.rtol, o.atol, o.eta = rtol, atol, eta
     o.strategy = STRATEGY[strategy]
@@ -449,16 +462,20 @@ def _opts(R, rtol, atol, eta, strategy, d0, delta_d, p, d_max, precision, profil
     o.stream = _stream()
     o.hmt_alpha = hmt_alpha
     o.seed = int(seed)
+    o.predictor = C.cast(C.pointer(predictor._c), C.c_void_p).value if predictor is not None else None
     return o
 
 
 def compress(gen: Generator, tree: Tree, R=None, rtol=1e-6, atol=1e-12, eta=1.0, strategy="dbl_fnorm",
-             d0=64, delta_d=64, p=10, d_max=None, precision="fp64", profile=False, hmt_alpha=10.0, seed=0):
+             d0=64, delta_d=64, p=10, d_max=None, precision="fp64", profile=False, hmt_alpha=10.0, seed=0,
+             predictor=None):
     """Adaptive HSS compression (hss_compress).  R: (n, d_cap) float64 CUDA tensor,
     column-major, rows in permuted order; or None, and the library draws R
-    on the device from `seed` (hss_random_normal).  Returns (HSSMatrix, status)."""
+    on the device from `seed` (hss_random_normal).  predictor: a Predictor
+    (hss_predictor), whose d0 then replaces `d0`.  Returns (HSSMatrix, status)."""
     g = gen._c()
-    o = _opts(R, rtol, atol, eta, strategy, d0, delta_d, p, d_max, precision, profile, hmt_alpha, seed, gen.n)
+    o = _opts(R, rtol, atol, eta, strategy, d0, delta_d, p, d_max, precision, profile, hmt_alpha, seed, gen.n,
+              predictor)
     h = C.c_void_p()
     st = _check(lib().hss_compress(C.byref(g), tree._t, C.byref(o), C.byref(h)))
     return HSSMatrix(h.value, (gen, tree, R)), st
@@ -479,7 +496,8 @@ def compress_batched(gens, trees, Rs, **kw):
     O = (_Opt * k)(*[_opts(R, opt("rtol", i, 1e-6), opt("atol", i, 1e-12), opt("eta", i, 1.0),
                            opt("strategy", i, "dbl_fnorm"), opt("d0", i, 64), opt("delta_d", i, 64),
                            opt("p", i, 10), opt("d_max", i, None), opt("precision", i, "fp64"),
-                           opt("profile", i, False), opt("hmt_alpha", i, 10.0), opt("seed", i, 0), gens[i].n)
+                           opt("profile", i, False), opt("hmt_alpha", i, 10.0), opt("seed", i, 0), gens[i].n,
+                           opt("predictor", i, None))
                      for i, R in enumerate(Rs)])
     H = (C.c_void_p * k)()
     st = _check(lib().hss_compress_batched(k, G, T, O, H))

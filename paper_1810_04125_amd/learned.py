@@ -166,6 +166,11 @@ class D0Predictor:
                 params = z["params"]
         self.params = torch.from_numpy(np.ascontiguousarray(params, np.float32)).cuda()
 
+    def handle(self):
+        """The network as an hss_predictor for hss_compress (options.predictor),
+        which then computes the same features and d0 itself."""
+        return hss.Predictor(SIZES, self.params)
+
     def predict(self, family, param, n, tree, rtol):
         """{'d_final': predicted final d, 'level_rank': [largest rank per level 1..L]}."""
         import torch

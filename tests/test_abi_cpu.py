@@ -73,7 +73,7 @@ def test_binding_structs_match_the_header(tmp_path):
         pytest.skip("no C compiler")
     pairs = {"hss_generator": H._Gen, "hss_block": H._Block, "hss_tree": H._Tree, "hss_options": H._Opt,
              "hss_info": H._Info, "hss_kernel_stats": H._KStats, "hss_node_info": H._NodeInfo,
-             "hss_mlp": H._Mlp}
+             "hss_mlp": H._Mlp, "hss_predictor": H._Predictor}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "hss.h"', "int main(void) {"]
     for cname, cls in pairs.items():
         lines.append('printf("%s %%zu\\n", sizeof(%s));' % (cname, cname))
@@ -149,3 +149,18 @@ def test_compress_rejects_a_sample_cap_beyond_the_lds_vector():
 def test_max_d_matches_the_header():
     src = open(os.path.join(ROOT, "include", "hss.h")).read()
     assert int(re.search(r"#define HSS_MAX_D (\d+)", src).group(1)) == hss.MAX_D
+
+
+def test_compress_rejects_a_predictor_outside_its_scope():
+    """The learned start applies to generated families with an incrementing
+    strategy and rtol > 0; other uses are argument errors (host checks)."""
+    import ctypes as C
+
+    from paper_1810_04125_amd import hss as H
+    pr = H._Predictor(H._mlp([8, 4, 2]), 8)   # never dereferenced on the device here
+    ptr = C.cast(C.pointer(pr), C.c_void_p).value
+    T = hss.Tree(64, 16)
+    st, msg = _host_compress(T, predictor=ptr, strategy=0)
+    assert st == -1 and "incrementing" in msg
+    st, msg = _host_compress(T, predictor=ptr, rtol=0.0)
+    assert st == -1 and "rtol" in msg

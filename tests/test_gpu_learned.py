@@ -62,8 +62,11 @@ def test_learned_d0_saves_rounds_at_the_same_accuracy(family, n):
     d0 = pred.d0(family, param, n, T, 1e-6, 64, d_max)
     assert d0 % 64 == 0 and 64 <= d0 <= d_max
     Hb, stb = hss.compress(gen, T, R, d0=128, **kw)
-    Hl, stl = hss.compress(gen, T, R, d0=d0, **kw)
+    # the predictor runs inside hss_compress: its features and d0 equal the Python route's
+    Hl, stl = hss.compress(gen, T, R, predictor=pred.handle(), **kw)
     ib, il = Hb.info(), Hl.info()
+    assert il["d0"] == d0
+    assert il["d_predicted"] == pytest.approx(pred.predict(family, param, n, T, 1e-6)["d_final"], rel=1e-5)
     print("baseline", ib, "learned d0", d0, il, flush=True)
     assert stb == stl == hss.OK
     assert il["rounds"] <= ib["rounds"]
