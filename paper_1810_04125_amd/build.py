@@ -51,8 +51,7 @@ def build(verbose: bool = False) -> str:
     with ThreadPoolExecutor(max_workers=max(1, workers)) as ex:
         objs = list(ex.map(_compile, jobs))
     tmp = OUT + ".tmp"
-    # rocBLAS: the plain GEMM of the dense-matrix sampling mode
-    cmd = [cc, "-shared", "-fPIC", "--offload-arch=" + ARCH] + objs + ["-L/opt/rocm/lib", "-lrocblas", "-o", tmp]
+    cmd = [cc, "-shared", "-fPIC", "--offload-arch=" + ARCH] + objs + ["-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed: %s\n%s\n%s" % (" ".join(cmd), r.stdout, r.stderr))

@@ -280,7 +280,7 @@ void launch_extract(const GenDev& g, int32_t nI, const int64_t* I, int32_t nJ, c
 // slices summed in fixed order (k_gemm.hip).
 void launch_gemm(const GemmTask* tasks, int32_t ntasks, int32_t mcap, int32_t ncap,
                  hipStream_t s, unsigned long long* kcnt = nullptr, int32_t kcap = 0,
-                 double* ws = nullptr, int64_t ws_elems = 0);
+                 double* ws = nullptr, int64_t ws_elems = 0, int cls = HSS_K_GEMM);
 // Split-K workspace of a compression job (doubles).
 constexpr int64_t kGemmSplitElems = int64_t(16) << 20;
 

@@ -188,7 +188,7 @@ __global__ __launch_bounds__(256) void k_gemm_splitk_sum(const GemmTask* __restr
 }
 
 void launch_gemm(const GemmTask* tasks, int32_t ntasks, int32_t mcap, int32_t ncap, hipStream_t s,
-                 unsigned long long* kcnt, int32_t kcap, double* ws, int64_t ws_elems) {
+                 unsigned long long* kcnt, int32_t kcap, double* ws, int64_t ws_elems, int cls) {
   if (ntasks <= 0 || mcap <= 0 || ncap <= 0) return;
   const unsigned gx = (unsigned)((ncap + GT - 1) / GT), gy = (unsigned)((mcap + GT - 1) / GT);
   const int64_t tiles = (int64_t)gx * gy * ntasks;
@@ -214,7 +214,7 @@ void launch_gemm(const GemmTask* tasks, int32_t ntasks, int32_t mcap, int32_t nc
   if (ksplit > 1)
     hipLaunchKernelGGL(k_gemm_splitk_sum, dim3(gx, gy, (unsigned)(ntasks * SUM_SPLIT)), dim3(256), 0, s, tasks,
                        ntasks, ksplit, ws);
-  prof_end(HSS_K_GEMM, s);
+  prof_end(cls, s);
 }
 
 }  // namespace hss

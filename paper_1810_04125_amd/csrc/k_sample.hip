@@ -10,10 +10,8 @@
 // the 4 waves.  The K dimension (n) is split over
 // blockIdx.z when the tile grid alone would not fill the 256 CUs; split
 // partial sums are reduced in fixed order, so results are deterministic.
-#include <rocblas/rocblas.h>
 
 #include <algorithm>
-#include <map>
 
 #include "gen.h"
 
@@ -297,7 +295,7 @@ void launch_sample_lp(const GenDev& g, int32_t transpose, int32_t bf16x3, const 
 
 // Dense matrices in HBM: A_hat R = P A P^T R is a plain GEMM between two
 // row permutations, X = P^T R (X(perm(i), :) = R(i, :)), Y = op(A) X on
-// rocBLAS, S(i, :) = Y(perm(i), :).  The entry-generating kernel would
+// the FP64 matrix cores, S(i, :) = Y(perm(i), :).  The entry-generating kernel would
 // load every entry of A through the permutation inside its MFMA loop.
 __global__ void k_perm_rows(const double* __restrict__ src, int64_t lds_, double* __restrict__ dst, int64_t ldd,
                             const int64_t* __restrict__ perm, int64_t n, int32_t ncols, int32_t scatter) {
@@ -309,41 +307,37 @@ __global__ void k_perm_rows(const double* __restrict__ src, int64_t lds_, double
   else dst[c * ldd + i] = src[c * lds_ + p];
 }
 
-static rocblas_handle blas_handle(hipStream_t s) {
-  thread_local std::map<int, rocblas_handle> handles;   // per thread and device, kept until exit
-  int dev = 0;
-  HSS_HIP_CHECK(hipGetDevice(&dev));
-  rocblas_handle& h = handles[dev];
-  if (!h && rocblas_create_handle(&h) != rocblas_status_success) {
-    h = nullptr;
-    throw Error(HSS_ERR_DEVICE, "rocblas_create_handle failed");
-  }
-  if (rocblas_set_stream(h, s) != rocblas_status_success) throw Error(HSS_ERR_DEVICE, "rocblas_set_stream failed");
-  return h;
-}
-
 // Returns false when the workspace cannot hold one 64-column chunk of X and Y.
+// The product Y = op(A) X is one task of the library's FP64 MFMA GEMM
+// (k_gemm.hip): 64 x 64 output tiles, so with 64 columns every tile row
+// streams its 64 rows of A from HBM once.
 static bool sample_dense_gemm(const GenDev& g, int32_t transpose, const double* R, int64_t ldr, double* S,
-                              int64_t lds, int32_t ncols, double* partial, hipStream_t s) {
+                              int64_t lds, int32_t ncols, double* partial, hipStream_t s,
+                              unsigned long long* kcnt) {
   const int64_t n = g.n;
   const int64_t cap = (int64_t)sample_partial_elems(n, ncols);   // at most what the caller allocated
-  const int64_t chunk = partial ? std::min<int64_t>(ncols, cap / (2 * n) / 64 * 64) : 0;
+  constexpr int64_t kTaskElems = 32;                              // room for the GEMM task at the end
+  const int64_t chunk = partial ? std::min<int64_t>(ncols, (cap - kTaskElems) / (2 * n) / 64 * 64) : 0;
   if (chunk < std::min<int64_t>(ncols, 64)) return false;
   double* X = partial;
   double* Y = partial + n * chunk;
-  rocblas_handle h = blas_handle(s);
-  const double one = 1.0, zero = 0.0;
+  GemmTask* task = reinterpret_cast<GemmTask*>(partial + 2 * n * chunk);
+  static_assert(sizeof(GemmTask) <= kTaskElems * sizeof(double), "GEMM task does not fit its slot");
   for (int64_t c0 = 0; c0 < ncols; c0 += chunk) {
     const int32_t c = (int32_t)std::min<int64_t>(chunk, ncols - c0);
     const unsigned blocks = (unsigned)((n * c + 255) / 256);
     hipLaunchKernelGGL(k_perm_rows, dim3(blocks), dim3(256), 0, s, R + c0 * ldr, ldr, X, n, g.perm, n, c, 1);
-    prof_begin(s);
-    const rocblas_status st = rocblas_dgemm(h, transpose ? rocblas_operation_transpose : rocblas_operation_none,
-                                            rocblas_operation_none, (rocblas_int)n, c, (rocblas_int)n, &one,
-                                            g.dense, (rocblas_int)g.ld, X, (rocblas_int)n, &zero, Y,
-                                            (rocblas_int)n);
-    prof_end(HSS_K_SAMPLE, s);
-    if (st != rocblas_status_success) throw Error(HSS_ERR_DEVICE, "rocblas_dgemm failed");
+    GemmTask t;
+    t.A = g.dense;
+    t.a_rs = transpose ? g.ld : 1;
+    t.a_cs = transpose ? 1 : g.ld;
+    t.B = X; t.b_rs = 1; t.b_cs = n;
+    t.C = Y; t.c_rs = 1; t.c_cs = n;
+    t.M = (int32_t)n; t.N = c; t.K = (int32_t)n; t.pad = 0;
+    t.alpha = 1.0; t.beta = 0.0;
+    HSS_HIP_CHECK(hipMemcpyAsync(task, &t, sizeof(t), hipMemcpyHostToDevice, s));
+    HSS_HIP_CHECK(hipStreamSynchronize(s));   // the host struct is gone after this scope
+    launch_gemm(task, 1, (int32_t)n, c, s, nullptr, 0, nullptr, 0, HSS_K_SAMPLE);
     hipLaunchKernelGGL(k_perm_rows, dim3(blocks), dim3(256), 0, s, Y, n, S + c0 * lds, lds, g.perm, n, c, 0);
   }
   return true;
@@ -352,10 +346,9 @@ static bool sample_dense_gemm(const GenDev& g, int32_t transpose, const double* 
 void launch_sample(const GenDev& g, int32_t transpose, int32_t precision, const double* R,
                    int64_t ldr, double* S, int64_t lds, int32_t ncols, double* partial,
                    hipStream_t s, unsigned long long* kcnt) {
-  (void)kcnt;
   if (ncols <= 0 || g.n <= 0) return;
   if (precision == HSS_SAMPLE_FP64 && g.family == HSS_FAM_DENSE &&
-      sample_dense_gemm(g, transpose, R, ldr, S, lds, ncols, partial, s))
+      sample_dense_gemm(g, transpose, R, ldr, S, lds, ncols, partial, s, kcnt))
     return;
   const int64_t n = g.n;
   const int nsplit = sample_splits(n, ncols);

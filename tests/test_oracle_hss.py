@@ -313,3 +313,50 @@ def test_fixed_rank_compression_alg1():
     op = PermutedOperator(Dense(_planted(n, r, 3)), T.perm)
     h = compress_fixed(op, T, inputs.gaussian_matrix(n, 64, 1), 40, 1e-8, 1e-14)
     assert h.rounds == 1 and rel_error(h, op) < 1e-12
+
+
+def test_hmt_threshold_uses_the_hankel_block_sizes_hand_values():
+    """Eq. RRQRHMTstop with the Hankel block sizes (#I_tau, N - #I_tau).
+
+    S has orthogonal rows of norms 1, 0.1, 0.01, 1.7e-4, 1e-6 (m = 5 rows
+    of a 20 x 30 sample, the other rows zero), so the pivot norms are exactly
+    these values.  With rtol 1e-3, atol 0, d = 30 the threshold at step k is
+    1e-3 / (1 + 4 sqrt(30) sqrt(min) / (29 - k)).  At k = 4:
+      min = 64 (a node of 64 rows in N = 1024): 1e-3 / (1 + 175.27/25) = 1.248e-4
+      min = 20 (the local sample's own 20 x 30):  1e-3 / (1 + 97.98/25)  = 2.033e-4
+    so the fourth pivot (1.7e-4) is kept with the Hankel sizes (rank 4) and
+    rejected with the sample sizes (rank 3); the fifth (1e-6) is below both."""
+    S = np.zeros((20, 30))
+    for i, s in enumerate((1.0, 0.1, 0.01, 1.7e-4, 1e-6)):
+        S[3 * i, 2 * i + 1] = s
+    assert interpolative(S, 1e-3, 0.0, hmt_dims=(64, 1024 - 64)).rank == 4
+    assert interpolative(S, 1e-3, 0.0, hmt_dims=(20, 30)).rank == 3
+    assert hmt_factor(30, 4, 64, 960) == pytest.approx(1.0 + 4.0 * math.sqrt(30.0) * 8.0 / 25.0)
+    assert 1e-3 / hmt_factor(30, 4, 64, 960) == pytest.approx(1.248e-4, rel=1e-3)
+    assert 1e-3 / hmt_factor(30, 4, 20, 30) == pytest.approx(2.033e-4, rel=1e-3)
+
+
+def test_doubling_hmt_driver_passes_hankel_block_sizes(monkeypatch):
+    """The doubling HMT strategy (Alg. 4) factors every non-root node with
+    the sizes of its Hankel block A(I_tau, I \\ I_tau), not those of its
+    local sample (whose rows are r1 + r2 above the leaves)."""
+    import oracle.hss as H
+    seen = []
+    real = H.interpolative
+
+    def spy(S, er, ea, hmt_dims=None):
+        seen.append((S.shape, hmt_dims))
+        return real(S, er, ea, hmt_dims=hmt_dims)
+
+    monkeypatch.setattr(H, "interpolative", spy)
+    n, leaf = 512, 64
+    ot = build_tree(n, leaf)
+    op = PermutedOperator(Toeplitz(n, 0.1), ot.perm)
+    R = inputs.gaussian_matrix(n, 512, 3)
+    H.compress(op, ot, R, 1e-6, 1e-12, "dbl_hmt", d0=64)
+    assert seen
+    sizes = {int(ot.hi[t] - ot.lo[t]) for t in range(1, ot.num_nodes)}
+    for shape, dims in seen:
+        assert dims is not None and dims[0] in sizes and dims[0] + dims[1] == n
+    # above the leaves the local sample has fewer rows than the node
+    assert any(shape[0] < dims[0] for shape, dims in seen)
