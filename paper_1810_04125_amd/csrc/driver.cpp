@@ -350,6 +350,15 @@ size_t Job::estimate_bytes(const hss_generator& g, const hss_tree* t, const hss_
   dbl += *std::max_element(wsa.begin(), wsa.end()) + *std::max_element(wsb.begin(), wsb.end());
   dbl += (int64_t)sample_partial_elems(t->n, (int32_t)dc);
   dbl += kGemmSplitElems;
+  {
+    // block-ID slots of the largest level
+    std::vector<int64_t> ld(maxlev + 1, 0), li(maxlev + 1, 0);
+    for (int32_t v = 0; v < nn; ++v) {
+      ld[t->level[v]] += idblk_doubles(dc, mcap[v]);
+      li[t->level[v]] += idblk_ints(mcap[v]);
+    }
+    dbl += *std::max_element(ld.begin(), ld.end()) + *std::max_element(li.begin(), li.end()) / 2 + 1;
+  }
   return (size_t)(8 * dbl + 4 * ints + 64 * nn + (16 << 20));
 }
 
@@ -475,6 +484,18 @@ void Job::setup(int32_t count, const hss_generator* gens, const hss_tree* const*
   }
   size_t part = 0;
   for (auto& P : probs) part = std::max(part, sample_partial_elems(P.n, P.dcap));
+  // block-pivoted ID workspace: one slot per node of a level, sized from its
+  // capacities; the levels take turns, so the largest level's total is kept
+  int64_t idb_d = 0, idb_i = 0;
+  for (auto& L : levels) {
+    int64_t dsum = 0, isum = 0;
+    for (int32_t g : L.nodes) {
+      dsum += idblk_doubles(probs[desc[g].prob].dcap, desc[g].mcap);
+      isum += idblk_ints(desc[g].mcap);
+    }
+    idb_d = std::max(idb_d, dsum);
+    idb_i = std::max(idb_i, isum);
+  }
   dpool = (double*)dalloc(sizeof(double) * std::max<int64_t>(dtot, 1));
   ipool = (int32_t*)dalloc(sizeof(int32_t) * std::max<int64_t>(itot, 1));
   lpool = (int64_t*)dalloc(sizeof(int64_t) * std::max<int64_t>(ltot, 1));
@@ -485,13 +506,17 @@ void Job::setup(int32_t count, const hss_generator* gens, const hss_tree* const*
     const size_t ba = a256(sizeof(double) * std::max<int64_t>(wsA, 1));
     const size_t bb = a256(sizeof(double) * std::max<int64_t>(wsB, 1));
     const size_t bp = a256(sizeof(double) * part);
-    const size_t bg = sizeof(double) * kGemmSplitElems;
-    char* base = (char*)arena_acquire(bt + ba + bb + bp + bg);
+    const size_t bg = a256(sizeof(double) * kGemmSplitElems);
+    const size_t bd = a256(sizeof(double) * std::max<int64_t>(idb_d, 1));
+    const size_t bi = a256(sizeof(int32_t) * std::max<int64_t>(idb_i, 1));
+    char* base = (char*)arena_acquire(bt + ba + bb + bp + bg + bd + bi);
     tpool = (double*)base;
     wsa = (double*)(base + bt);
     wsb = (double*)(base + bt + ba);
     partial = part ? (double*)(base + bt + ba + bb) : nullptr;
     gemm_ws = (double*)(base + bt + ba + bb + bp);
+    idb_dpool = (double*)(base + bt + ba + bb + bp + bg);
+    idb_ipool = (int32_t*)(base + bt + ba + bb + bp + bg + bd);
   }
   desc_d = (NodeDesc*)dalloc(sizeof(NodeDesc) * gnodes);
   st_d = (NodeState*)dalloc(sizeof(NodeState) * gnodes);
@@ -501,9 +526,44 @@ void Job::setup(int32_t count, const hss_generator* gens, const hss_tree* const*
   qwork.max_tasks = std::max(maxcount, 1);
   qwork.chunks = (int2*)dalloc(sizeof(int2) * qrcp_work_entries(qwork.max_tasks));
   qwork.meta = (int32_t*)dalloc(sizeof(int32_t) * 2);
+  qwork.kbuf = (int32_t*)dalloc(sizeof(int32_t) * 2);
+  qwork.graphs = &qgraphs;
   qform_d = (QformTask*)dalloc(sizeof(QformTask) * std::max(maxcount, 1));
   chol_d = (CholTask*)dalloc(sizeof(CholTask) * std::max(maxcount, 1));
   mvtasks_d = (GemmTask*)dalloc(sizeof(GemmTask) * 2 * std::max(maxcount, 1));
+  idb_gt = (GemmTask*)dalloc(sizeof(GemmTask) * 3 * std::max(maxcount, 1));
+  for (auto& L : levels) {
+    // block-ID slots of this level's nodes (task t of an ID call = node t)
+    std::vector<IdBlk> hb(L.nodes.size());
+    int64_t doff = 0, ioff = 0;
+    for (size_t t = 0; t < L.nodes.size(); ++t) {
+      const NodeDesc& d = desc[L.nodes[t]];
+      const int64_t dc = probs[d.prob].dcap, mc = d.mcap;
+      const auto a8 = [](int64_t x) { return (x + 7) & ~int64_t(7); };
+      IdBlk& B = hb[t];
+      std::memset(&B, 0, sizeof(B));
+      double* dp = idb_dpool + doff;
+      B.C = dp; dp += a8(dc * kIdbCmax);
+      B.G = dp; dp += a8((int64_t)kIdbCmax * kIdbCmax);
+      B.V = dp; dp += a8(dc * kIdbLmax);
+      B.U = dp; dp += a8(dc * kIdbLmax);
+      B.Y = dp; dp += a8(kIdbLmax * mc);
+      B.F = dp; dp += a8(4 * (int64_t)kIdbLmax * kIdbLmax);
+      B.P = dp;
+      B.ldc = dc;
+      B.ldv = dc;
+      B.cmax = kIdbCmax;
+      B.cand = idb_ipool + ioff;
+      B.piv = B.cand + kIdbCmax;
+      B.rest = B.piv + kIdbLmax;
+      doff += idblk_doubles(dc, mc);
+      ioff += idblk_ints(mc);
+    }
+    L.idb.blk = (IdBlk*)dalloc(sizeof(IdBlk) * std::max<size_t>(hb.size(), 1));
+    HSS_HIP_CHECK(hipMemcpy(L.idb.blk, hb.data(), sizeof(IdBlk) * hb.size(), hipMemcpyHostToDevice));
+    L.idb.gt = idb_gt;
+    L.idb.max_tasks = (int32_t)L.nodes.size();
+  }
   for (auto& L : levels) {
     std::vector<int32_t> mc;
     for (int32_t g : L.nodes) mc.push_back(desc[g].mcap);
@@ -777,7 +837,7 @@ void Job::run_level(int lev, int32_t ncap) {
       launch_build_qrcp(a, s, hmt, qtasks_d, stream);
       // panels of P.d <= ncap rows and st.m <= lv_m columns
       run_qrcp(qtasks_d, a.count, qwork, L.wg_trsm, L.ntrsm, std::min(lv_m, ncap), ncap, lv_m, flags_d + 4,
-               tasks_d, lv_m, stream, kcnt_d, true, gemm_ws);
+               tasks_d, lv_m, stream, kcnt_d, true, gemm_ws, kBlockId ? &L.idb : nullptr);
     }
   };
   if (strategy == HSS_DBL_HMT) {

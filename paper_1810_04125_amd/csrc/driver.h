@@ -39,7 +39,12 @@ struct LevelInfo {
   int32_t ntrsm = 0;
   int2* wg_test = nullptr;   // explicit-Q workgroup map for test_ncap columns
   int32_t ntest = 0, test_ncap = 0;
+  IdBlockWork idb;           // block-pivoted ID slots of the level's nodes
 };
+
+// The IDs of the compression use the block-pivoted factorization
+// (k_idblock.hip); the one-step kernels still factor the stopping test's blocks.
+constexpr bool kBlockId = true;
 
 size_t arena_idle_bytes();   // idle cached transient memory on the current device
 void arena_release_idle();   // free it
@@ -74,6 +79,10 @@ struct Job {
   int32_t* nodes_d = nullptr;
   QrcpTask* qtasks_d = nullptr;
   QrcpWork qwork{nullptr, nullptr, 0};   // device work map of every factorization call
+  QrcpGraphs qgraphs;                    // replayed pivot-step segments
+  double* idb_dpool = nullptr;           // block-ID slots (transient)
+  int32_t* idb_ipool = nullptr;
+  GemmTask* idb_gt = nullptr;            // block-ID GEMM tasks, 3 per node of a level
   QformTask* qform_d = nullptr;
   CholTask* chol_d = nullptr;
   int64_t* mvoff_d = nullptr;   // per node: prefix sum of rcap (matvec slots)

@@ -8,7 +8,9 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <map>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/hss.h"
@@ -123,7 +125,8 @@ struct ProbDev {
 };
 
 // C(i,j) = alpha * sum_k A(i,k) B(k,j) + beta * C(i,j) with arbitrary strides.
-// a_cols, when set, maps column k of A to the physical column a_cols[k].
+// a_cols, when set, maps column k of A to the physical column a_cols[k];
+// b_cols and c_cols map column j of B and of C to physical columns.
 struct GemmTask {
   const double* A;
   const double* B;
@@ -132,6 +135,8 @@ struct GemmTask {
   int32_t M, N, K, pad;
   double alpha, beta;
   const int32_t* a_cols = nullptr;
+  const int32_t* b_cols = nullptr;
+  const int32_t* c_cols = nullptr;
 };
 
 // One matrix of a batched interpolative decomposition (k_qrcp.hip).
@@ -190,19 +195,79 @@ constexpr int kQrcpTarget = 1280;
 constexpr int64_t kQrcpWgCells = 64 * 1024;
 // Device work map of run_qrcp: chunks holds 2 kQrcpTarget + max_tasks
 // entries (the target doubles for large steps), meta two int32.
+struct QrcpWork;
+// Instantiated graphs of kSegSteps back-to-back pivot steps, per (grid,
+// LDS bytes), owned by a compression job.
+constexpr int kSegSteps = 32;
+struct QrcpGraphs {
+  std::map<std::pair<int, size_t>, hipGraphExec_t> execs;
+  hipGraphExec_t segment(const QrcpTask* tasks, const QrcpWork& wk, int nwg, size_t lds, unsigned long long* kcnt);
+  ~QrcpGraphs();
+};
 struct QrcpWork {
   int2* chunks;
   int32_t* meta;
   int32_t max_tasks;
+  int32_t* kbuf = nullptr;        // 2 int32: step counter of the graph replays (nullptr: no graphs)
+  QrcpGraphs* graphs = nullptr;   // graph cache (nullptr: plain launches)
 };
 inline size_t qrcp_work_entries(int32_t max_tasks) { return (size_t)2 * kQrcpTarget + (size_t)std::max(max_tasks, 1); }
+// Block-pivoted ID (k_idblock.hip): per task, a slot of workspace sized
+// from its capacities (panel rows dcap, columns mcap).
+constexpr int kIdbCmax = 128;   // candidate columns per block (their Gram matrix fits in LDS)
+constexpr int kIdbLmax = 32;    // pivots per block at most
+constexpr int kIdbMaxM = 16384; // panel columns the selection kernel stages in LDS (larger: one-step path)
+constexpr int kIdbRows = 256;   // panel rows per workgroup of the block's row kernels
+// per row workgroup: the upper 4 x 4 blocks of its share of Q1^T Q1
+constexpr int kIdbPart = (kIdbLmax / 4) * (kIdbLmax / 4 + 1) / 2 * 16;
+struct IdBlk {
+  int32_t* cand;     // kIdbCmax candidate columns, ascending
+  int32_t* rest;     // mcap columns left after the block, ascending
+  int32_t* piv;      // kIdbLmax: the block's pivots (indices into cand), in order
+  double* C;         // ldc x kIdbCmax: the candidates' rows k .. d
+  int64_t ldc;
+  double* G;         // kIdbCmax x kIdbCmax Gram matrix
+  double* V;         // ldv x kIdbLmax: Q1 of the pivot columns, then the block's reflectors
+  double* U;         // ldv x kIdbLmax: V T^T
+  int64_t ldv;
+  double* Y;         // kIdbLmax x mcap: V^T times the remaining columns
+  double* F;         // 4 kIdbLmax x kIdbLmax, row-major: R1, M, T, Y_1
+  double* P;         // ceil(ldv / kIdbRows) x kIdbPart: partial sums of Q1^T Q1
+  double bound;      // largest residual norm among the non-candidates
+  int32_t k;         // first panel row of the next block
+  int32_t kb;        // first panel row of the last block factored
+  int32_t ncand, nrest;
+  int32_t L;         // pivots of the last block (0: none)
+  int32_t lc;        // pivots the block's Cholesky step took
+  int32_t stop;      // the threshold ended the Cholesky step
+  int32_t cmax;
+};
+// Doubles and int32 of one task's slot.
+inline int64_t idblk_doubles(int64_t dcap, int64_t mcap) {
+  const auto a8 = [](int64_t x) { return (x + 7) & ~int64_t(7); };
+  return a8(dcap * kIdbCmax) + a8((int64_t)kIdbCmax * kIdbCmax) + 2 * a8(dcap * kIdbLmax) + a8(kIdbLmax * mcap) +
+         a8(4 * (int64_t)kIdbLmax * kIdbLmax) + a8((dcap + kIdbRows - 1) / kIdbRows * kIdbPart);
+}
+inline int64_t idblk_ints(int64_t mcap) { return ((kIdbCmax + kIdbLmax + mcap) + 7) & ~int64_t(7); }
+struct IdBlockWork {
+  IdBlk* blk = nullptr;      // device, one per task
+  GemmTask* gt = nullptr;    // device, 3 per task (Gram, V^T A, update)
+  int32_t max_tasks = 0;
+};
+// The block pivot steps of one factorization call, after the panels and
+// their norms are in place (k_qrcp_init, QR first); hw_dev / hw: a mapped
+// host word for the liveness polls.
+void run_id_blocks(QrcpTask* tasks, int32_t ntasks, const IdBlockWork& bw, int32_t dmax, int32_t mmax,
+                   int32_t* hw_dev, const int32_t* hw, double* gws, hipStream_t s, unsigned long long* kcnt);
 // Factor the panels of `tasks` (dmax rows and at most ncols_max columns
-// each, by capacity): one workgroup per matrix for small panels, else one
-// launch per pivot step over a device-built work map.  `flag` points at
-// one int32 of device scratch.
+// each, by capacity): for an ID with a block workspace, the block-pivoted
+// factorization (k_idblock.hip); otherwise one workgroup per matrix for
+// small panels, or one launch per pivot step over a device-built work map.
+// `flag` points at one int32 of device scratch.
 void run_qrcp(QrcpTask* tasks, int32_t ntasks, const QrcpWork& wk, const int2* wg_trsm, int32_t ntrsm,
               int32_t kmax, int32_t dmax, int32_t ncols_max, int32_t* flag, GemmTask* gtasks, int32_t mcap_max,
-              hipStream_t s, unsigned long long* kcnt = nullptr, bool solve_e = true, double* gws = nullptr);
+              hipStream_t s, unsigned long long* kcnt = nullptr, bool solve_e = true, double* gws = nullptr,
+              const IdBlockWork* bw = nullptr);
 // Reduce tall ID panels (d >= 2 m) to their m x m triangle before the
 // pivoted steps (k_qrfirst.hip), when the rows this takes out of every
 // pivot step, summed over the tall panels, reach kQrFirstMinCells: below

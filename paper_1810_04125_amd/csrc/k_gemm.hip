@@ -74,6 +74,16 @@ __global__ __launch_bounds__(256, 3) void k_gemm_grouped(const GemmTask* __restr
   const HSS_GLOBAL double* gA = gview(t.A);
   const HSS_GLOBAL double* gB = gview(t.B);
   const HSS_GLOBAL int32_t* gcols = t.a_cols ? gview(t.a_cols) : nullptr;
+  const HSS_GLOBAL int32_t* gbcols = t.b_cols ? gview(t.b_cols) : nullptr;
+  // physical columns of B of this thread's elements (fixed over K)
+  int64_t bcol[GPT];
+#pragma unroll
+  for (int e = 0; e < GPT; ++e) {
+    int kk, j;
+    gemm_coords(t, threadIdx.x + 256 * e, false, kk, j);
+    const int64_t gj = min(j0 + j, (int64_t)t.N - 1);
+    bcol[e] = gbcols ? (int64_t)gbcols[gj] : gj;
+  }
   double ra[GPT], rb[GPT];
   uint32_t valid = 0;
   auto load = [&](int k0) {
@@ -97,7 +107,7 @@ __global__ __launch_bounds__(256, 3) void k_gemm_grouped(const GemmTask* __restr
       int kk, j;
       gemm_coords(t, idx, false, kk, j);
       const int64_t gj = j0 + j, gkb = k0 + kk;
-      rb[e] = gB[min(gkb, (int64_t)ke - 1) * t.b_rs + min(gj, (int64_t)t.N - 1) * t.b_cs];
+      rb[e] = gB[min(gkb, (int64_t)ke - 1) * t.b_rs + bcol[e] * t.b_cs];
       valid |= (uint32_t)(gj < t.N && gkb < ke) << (GPT + e);
     }
   };
@@ -150,7 +160,8 @@ __global__ __launch_bounds__(256, 3) void k_gemm_grouped(const GemmTask* __restr
         const int64_t gi = i0 + wr + a * 16 + 4 * v + (lane >> 4);
         const int64_t gj = j0 + wc + b * 16 + (lane & 15);
         if (gi >= t.M || gj >= t.N) continue;
-        HSS_GLOBAL double* c = gview_w(t.C + gi * t.c_rs + gj * t.c_cs);
+        const int64_t cj = t.c_cols ? (int64_t)t.c_cols[gj] : gj;
+        HSS_GLOBAL double* c = gview_w(t.C + gi * t.c_rs + cj * t.c_cs);
         const double val = t.alpha * acc[a][b][v];
         *c = (t.beta == 0.0) ? val : val + t.beta * (*c);
       }
@@ -182,7 +193,8 @@ __global__ __launch_bounds__(256) void k_gemm_splitk_sum(const GemmTask* __restr
     for (int u = 0; u < SUM_U; ++u)
       if (k0 + u < ksplit) sum += v[u];
   }
-  HSS_GLOBAL double* cp = gview_w(t.C + gi * t.c_rs + gj * t.c_cs);
+  const int64_t cj = t.c_cols ? (int64_t)t.c_cols[gj] : gj;
+  HSS_GLOBAL double* cp = gview_w(t.C + gi * t.c_rs + cj * t.c_cs);
   const double val = t.alpha * sum;
   *cp = (t.beta == 0.0) ? val : val + t.beta * (*cp);
 }

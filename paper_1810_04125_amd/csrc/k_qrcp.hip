@@ -97,7 +97,8 @@ __global__ __launch_bounds__(QB) void k_qrcp_plan(const QrcpTask* __restrict__ t
 }
 
 __global__ __launch_bounds__(QB) void k_qrcp_init(const QrcpTask* __restrict__ tasks, const int2* __restrict__ wg,
-                                                  const int32_t* __restrict__ meta) {
+                                                  const int32_t* __restrict__ meta, int32_t* __restrict__ kbuf) {
+  if (kbuf && blockIdx.x == 0 && threadIdx.x == 0) kbuf[0] = 0;   // step counter of the graph replays
   if ((int)blockIdx.x >= meta[0]) return;
   const int cpw = meta[1];
   const int2 w = wg[blockIdx.x];
@@ -294,12 +295,10 @@ __device__ __forceinline__ bool qrcp_step_body(const QrcpTask& t, int k, int c0,
   return false;
 }
 
-__global__ __launch_bounds__(QB) void k_qrcp_step(const QrcpTask* __restrict__ tasks, const int2* __restrict__ wg,
-                                                  const int32_t* __restrict__ meta, int k,
-                                                  unsigned long long* __restrict__ kcnt) {
-  extern __shared__ double vsh[];
-  __shared__ double rv[QW];
-  __shared__ int ri[QW];
+__device__ __forceinline__ void qrcp_step_wg(const QrcpTask* __restrict__ tasks, const int2* __restrict__ wg,
+                                             const int32_t* __restrict__ meta, int k,
+                                             unsigned long long* __restrict__ kcnt, double* vsh, double* rv,
+                                             int* ri) {
   const int2 w = wg[blockIdx.x];   // in bounds: the grid never exceeds the map's entries
   if ((int)blockIdx.x >= meta[0]) return;
   const int cpw = meta[1];
@@ -307,6 +306,84 @@ __global__ __launch_bounds__(QB) void k_qrcp_step(const QrcpTask* __restrict__ t
   if (!t.active) return;
   qrcp_step_body<QB>(t, k, w.y, min(t.m, w.y + cpw), w.y == 0 && threadIdx.x == 0, kcnt,
                      t.nopivot ? HSS_K_TEST_QR : HSS_K_QRCP_STEP, vsh, rv, ri);
+}
+
+__global__ __launch_bounds__(QB) void k_qrcp_step(const QrcpTask* __restrict__ tasks, const int2* __restrict__ wg,
+                                                  const int32_t* __restrict__ meta, int k,
+                                                  unsigned long long* __restrict__ kcnt) {
+  extern __shared__ double vsh[];
+  __shared__ double rv[QW];
+  __shared__ int ri[QW];
+  qrcp_step_wg(tasks, wg, meta, k, kcnt, vsh, rv, ri);
+}
+
+// The same step with k read from device memory, for replay in a graph of
+// back-to-back steps: kin holds k, and workgroup 0 writes k + 1 to kout (the
+// next step's kin; the two words alternate, so no step writes the word it
+// reads).
+__global__ __launch_bounds__(QB) void k_qrcp_step_g(const QrcpTask* __restrict__ tasks,
+                                                    const int2* __restrict__ wg, const int32_t* __restrict__ meta,
+                                                    const int32_t* __restrict__ kin, int32_t* __restrict__ kout,
+                                                    unsigned long long* __restrict__ kcnt) {
+  extern __shared__ double vsh[];
+  __shared__ double rv[QW];
+  __shared__ int ri[QW];
+  const int k = *kin;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *kout = k + 1;
+  qrcp_step_wg(tasks, wg, meta, k, kcnt, vsh, rv, ri);
+}
+
+// A graph of kSegSteps pivot steps (k_qrcp_step_g, k from kbuf[0] back to
+// kbuf[0]) for one grid size and LDS size; instantiated once per job and
+// shape, replayed for every full segment.
+hipGraphExec_t QrcpGraphs::segment(const QrcpTask* tasks, const QrcpWork& wk, int nwg, size_t lds,
+                                   unsigned long long* kcnt) {
+  const auto key = std::make_pair(nwg, lds);
+  auto it = execs.find(key);
+  if (it != execs.end()) return it->second;
+  hipGraph_t g = nullptr;
+  HSS_HIP_CHECK(hipGraphCreate(&g, 0));
+  hipGraphNode_t prev = nullptr;
+  // kernel arguments of the two alternating node kinds
+  struct Args {
+    const QrcpTask* tasks;
+    const int2* wg;
+    const int32_t* meta;
+    const int32_t* kin;
+    int32_t* kout;
+    unsigned long long* kcnt;
+  } args[2] = {{tasks, wk.chunks, wk.meta, wk.kbuf, wk.kbuf + 1, kcnt},
+               {tasks, wk.chunks, wk.meta, wk.kbuf + 1, wk.kbuf, kcnt}};
+  void* params[2][6];
+  for (int a = 0; a < 2; ++a) {
+    params[a][0] = &args[a].tasks;
+    params[a][1] = &args[a].wg;
+    params[a][2] = &args[a].meta;
+    params[a][3] = &args[a].kin;
+    params[a][4] = &args[a].kout;
+    params[a][5] = &args[a].kcnt;
+  }
+  for (int i = 0; i < kSegSteps; ++i) {
+    hipKernelNodeParams p{};
+    p.func = reinterpret_cast<void*>(k_qrcp_step_g);
+    p.gridDim = dim3(nwg);
+    p.blockDim = dim3(QB);
+    p.sharedMemBytes = (unsigned)lds;
+    p.kernelParams = params[i & 1];
+    p.extra = nullptr;
+    hipGraphNode_t node = nullptr;
+    HSS_HIP_CHECK(hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &p));
+    prev = node;
+  }
+  hipGraphExec_t ex = nullptr;
+  HSS_HIP_CHECK(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
+  HSS_HIP_CHECK(hipGraphDestroy(g));
+  execs[key] = ex;
+  return ex;
+}
+
+QrcpGraphs::~QrcpGraphs() {
+  for (auto& kv : execs) hipGraphExecDestroy(kv.second);
 }
 
 // The whole factorization of one matrix by one workgroup, every pivot step
@@ -549,7 +626,7 @@ QrcpPlan make_qrcp_plan(const std::vector<int32_t>& mcaps, int cpw) {
 
 void run_qrcp(QrcpTask* tasks, int32_t ntasks, const QrcpWork& wk, const int2* wg_trsm, int32_t ntrsm,
               int32_t kmax, int32_t dmax, int32_t ncols_max, int32_t* flag, GemmTask* gtasks, int32_t mcap_max,
-              hipStream_t s, unsigned long long* kcnt, bool solve_e, double* gws) {
+              hipStream_t s, unsigned long long* kcnt, bool solve_e, double* gws, const IdBlockWork* bw) {
   if (ntasks <= 0) return;
   if (ntasks > wk.max_tasks) throw Error(HSS_ERR_INTERNAL, "QRCP work map too small for the batch");
   const int nwg = 2 * kQrcpTarget + ntasks;
@@ -563,7 +640,8 @@ void run_qrcp(QrcpTask* tasks, int32_t ntasks, const QrcpWork& wk, const int2* w
   }
   const bool known_active = solve_e;   // some panel is known to be active
   const int64_t cells = (int64_t)std::max(dmax, 1) * std::max(ncols_max, 1);
-  bool one_wg = cells <= kQrcpWgCells && lds <= 48 * 1024;
+  const bool blocks = solve_e && bw && bw->blk && ncols_max <= kIdbMaxM;
+  bool one_wg = !blocks && cells <= kQrcpWgCells && lds <= 48 * 1024;
   if (one_wg && solve_e) {
     // Per pivot step, the one-workgroup kernel walks the columns 16 at a
     // time (about 5 + 2.2 us per 16 columns, measured); the many-workgroup
@@ -580,7 +658,7 @@ void run_qrcp(QrcpTask* tasks, int32_t ntasks, const QrcpWork& wk, const int2* w
   } else {
     prof_begin(s);
     hipLaunchKernelGGL(k_qrcp_plan, dim3(1), dim3(QB), 0, s, tasks, ntasks, kQrcpTarget, wk.chunks, wk.meta);
-    hipLaunchKernelGGL(k_qrcp_init, dim3(nwg), dim3(QB), 0, s, tasks, wk.chunks, wk.meta);
+    hipLaunchKernelGGL(k_qrcp_init, dim3(nwg), dim3(QB), 0, s, tasks, wk.chunks, wk.meta, wk.kbuf);
     prof_end(HSS_K_QRCP_OTHER, s);
     if (solve_e && dmax >= 128) run_qr_first(tasks, ntasks, dmax, ncols_max, sc, gtasks, gws, s, kcnt);
   }
@@ -591,8 +669,9 @@ void run_qrcp(QrcpTask* tasks, int32_t ntasks, const QrcpWork& wk, const int2* w
   int32_t* hw_dev = nullptr;
   int32_t* hw = host_words(&hw_dev);
   bool rank_known = false;
-  const int ksteps = one_wg ? 0 : kmax;
-  for (int k0 = 0; k0 < ksteps; k0 += 32) {
+  if (blocks) run_id_blocks(tasks, ntasks, *bw, dmax, ncols_max, hw_dev, hw, gws, s, kcnt);
+  const int ksteps = (one_wg || blocks) ? 0 : kmax;
+  for (int k0 = 0; k0 < ksteps; k0 += kSegSteps) {
     if (k0 > 0 || !known_active) {
       hipLaunchKernelGGL(k_qrcp_alive, dim3(1), dim3(QAL), 0, s, tasks, ntasks, k0, hw_dev);
       HSS_HIP_CHECK(hipStreamSynchronize(s));
@@ -601,10 +680,15 @@ void run_qrcp(QrcpTask* tasks, int32_t ntasks, const QrcpWork& wk, const int2* w
         break;
       }
     }
-    const int k1 = std::min(ksteps, k0 + 32);
+    const int k1 = std::min(ksteps, k0 + kSegSteps);
     prof_begin(s);
-    for (int k = k0; k < k1; ++k)
-      hipLaunchKernelGGL(k_qrcp_step, dim3(nwg), dim3(QB), lds, s, tasks, wk.chunks, wk.meta, k, kcnt);
+    if (wk.graphs && wk.kbuf && k1 - k0 == kSegSteps) {
+      // a full segment: one replay of the step graph (kbuf[0] == k0 here)
+      HSS_HIP_CHECK(hipGraphLaunch(wk.graphs->segment(tasks, wk, nwg, lds, kcnt), s));
+    } else {
+      for (int k = k0; k < k1; ++k)
+        hipLaunchKernelGGL(k_qrcp_step, dim3(nwg), dim3(QB), lds, s, tasks, wk.chunks, wk.meta, k, kcnt);
+    }
     prof_end(solve_e ? HSS_K_QRCP_STEP : HSS_K_TEST_QR, s, k1 - k0);
   }
   int32_t rmax = rank_known ? hw[1] : 0;
