@@ -53,7 +53,9 @@ KCLASS_INFO = {
     "SAMPLE": ("k_sample_f64", "mfma"),
     "GEMM": ("k_gemm_grouped+k_gemm_splitk_sum", "mfma"),
     "TEST_NORMS": ("k_fn_norms/k_cq_chol/k_fn_rtest", "hbm"),
-    "QRCP_STEP": ("k_qrcp_step", "mfma"),   # FP64-compute-bound by the ID's arithmetic intensity (r/2 flop/byte)
+    # block-pivoted ID (k_idb_select/gather/chol/rows1/small/rows2/norms and its GEMMs); one-step pivot
+    # steps where a panel is too wide for it.  FP64-compute-bound by the ID's arithmetic intensity
+    "QRCP_STEP": ("k_idb_* + block GEMMs (block-pivoted ID)", "mfma"),
     "TEST_QR": ("k_qrcp_step (stopping-test QR, no pivoting)", "hbm"),
     "RNG": ("k_randn", "hbm"),
     "QRCP_WG": ("k_qrcp_wg", "hbm"),
@@ -97,18 +99,40 @@ WORKLOADS = {
 # The figure is only reported while the kernel's source file is the one the
 # counters were taken on (sha256); profiles/ holds the summaries.
 TRAFFIC = {
-    ("laplace-sphere-32768", "QRCP_STEP"): {
-        "source": "paper_1810_04125_amd/csrc/k_qrcp.hip",
-        "sha256": "7e0d2fd8dcbe8cb30989a3a722ccfaec9f1bfff046895d6c3a235b1e24a6b3e6",
-        "fetch_kib": 8631.853, "write_kib": 13430.088,            # k_qrcp_step, 17664 dispatches
-        "fetch_scale": 1048576.0 / 524302.292, "write_scale": 1.0,  # 1 GiB copy: FETCH 524302 KiB, WRITE 1048576 KiB
+    ("laplace-sphere-32768", "SAMPLE"): {
+        "source": "paper_1810_04125_amd/csrc/k_sample.hip",
+        "sha256": "9bf22f6c3e9f3c475194941b7e3826c6c8d8b4854dadbdb14a6d2892ae151fdb",
+        "fetch_kib": 71856.5, "write_kib": 131072.0,               # k_sample_f64, 44 dispatches
+        "fetch_scale": 1048576.0 / 524302.0, "write_scale": 1.0,   # 1 GiB copy: FETCH 524302 KiB, WRITE 1048576 KiB
     },
 }
 
 # Counters of the sampling kernel from rocprofv3 --pmc passes over one
-# compression of the workload (profiles/ holds the summaries): MFMA-busy and
-# VALU-busy fractions of the kernel's busy cycles.
-SAMPLE_COUNTERS = {}
+# compression of the workload (profiles/ holds the summaries), averaged per
+# dispatch: SQ_VALU_MFMA_BUSY_CYCLES and SQ_ACTIVE_INST_VALU over the SIMD
+# cycles of the busy CUs (4 SQ_BUSY_CU_CYCLES); FP64 MFMA work from
+# SQ_INSTS_VALU_MFMA_MOPS_F64 (512 flops per MOP).
+SAMPLE_COUNTERS = {
+    ("laplace-sphere-32768", "fp64"): {
+        "source_sha256": "9bf22f6c3e9f3c475194941b7e3826c6c8d8b4854dadbdb14a6d2892ae151fdb",
+        "mfma_busy_frac": round(4.39258e9 / (4 * 1.67242e9), 4),
+        "valu_active_frac": round(4.39561e8 / (4 * 1.67242e9), 4),
+        "mfma_valu_coexec_cycles": 0,
+        "mfma_flops_per_dispatch": 2.74536e8 * 512,
+        "valu_fp64_flops_per_dispatch": 3.08853e8,
+        "avg_dispatch_us": 2981.997,
+        "counter_tflops": round(2.74536e8 * 512 / 2981.997e-6 / 1e12, 2),
+    },
+}
+
+
+def sample_counters(workload, precision):
+    import hashlib
+    c = SAMPLE_COUNTERS.get((workload, precision))
+    src = os.path.join(ROOT, "paper_1810_04125_amd", "csrc", "k_sample.hip")
+    if not c or hashlib.sha256(open(src, "rb").read()).hexdigest() != c["source_sha256"]:
+        return None
+    return {k: v for k, v in c.items() if k != "source_sha256"}
 
 
 def traffic_bytes(workload, cls):
@@ -122,8 +146,13 @@ def traffic_bytes(workload, cls):
     return 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
 
 
+# classes whose launches are one kernel each (the roofline is reported for
+# the dominant one of these; the others mix kernels)
+SINGLE_KERNEL = {"SAMPLE", "RNG", "QRCP_WG", "EXTRACT", "TRSM", "SAMPLE_REDUCE"}
+
+
 def roofline(stats, precision="fp64"):
-    name = max((k for k in stats if stats[k]["ms"] > 0), key=lambda k: stats[k]["ms"])
+    name = max((k for k in stats if stats[k]["ms"] > 0 and k in SINGLE_KERNEL), key=lambda k: stats[k]["ms"])
     s = stats[name]
     kern, bound = KCLASS_INFO[name]
     sec = s["ms"] / 1e3
@@ -140,7 +169,8 @@ def roofline(stats, precision="fp64"):
     return {"bound": bound, "achieved": round(ach, 3), "peak": peak, "unit": unit,
             "frac": round(ach / peak, 5), "traffic": None, "kernel": kern, "class": name,
             "launches": s["launches"], "avg_launch_us": round(1e3 * s["ms"] / max(1, s["launches"]), 3),
-            "share_of_profiled_gpu_time": round(s["ms"] / sum(v["ms"] for v in stats.values()), 4)}
+            "share_of_profiled_gpu_time": round(s["ms"] / sum(v["ms"] for v in stats.values()), 4),
+            "largest_class": max(stats, key=lambda k: stats[k]["ms"])}
 
 
 def cpu_baseline(W, d_final, budget_rows=16384):
@@ -546,7 +576,8 @@ def id_roofline(stats):
         return None
     tf = idc["flops"] / sec / 1e12
     gb = idc["bytes"] / sec / 1e9
-    return {"kernels": "k_qrcp_step+k_qrcp_wg+k_qrcp_plan/init/alive/fin/egather+k_qrfirst*+k_trsm_diag",
+    return {"kernels": "k_idb_* + block GEMMs, k_qrcp_wg/step (small or very wide panels), "
+                       "k_qrcp_plan/init/alive/fin, k_qrfirst*, k_trsm_diag",
             "id_calls": idc["launches"], "ms": round(ms, 2), "alg_tflop": round(idc["flops"] / 1e12, 4),
             "alg_gb": round(idc["bytes"] / 1e9, 3), "achieved_tflops": round(tf, 3),
             "frac_fp64_peak": round(tf / PEAK_FP64_TFLOPS, 5), "achieved_GBps": round(gb, 1),
@@ -628,7 +659,7 @@ def main():
                                  "mfma_tflops": round(mult * stf, 3),
                                  "frac_of_peak": round(mult * stf / speak, 4), "peak_tflops": speak,
                                  "avg_launch_us": round(1e3 * samp["ms"] / max(1, samp["launches"]), 3),
-                                 "counters": SAMPLE_COUNTERS.get((args.workload, args.precision))}
+                                 "counters": sample_counters(args.workload, args.precision)}
         rl["id"] = id_roofline(stats)
         rl["profiled_gpu_ms_by_class"] = {k: round(v["ms"], 2) for k, v in stats.items()}
         log("bench: profile %s" % json.dumps(rl))

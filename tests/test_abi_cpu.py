@@ -48,7 +48,7 @@ def test_tree_rejects_bad_input():
 
 def test_bench_traffic_record_tracks_the_kernel_source(tmp_path, monkeypatch):
     import bench
-    rec = dict(bench.TRAFFIC[("laplace-sphere-32768", "QRCP_STEP")])
+    rec = dict(bench.TRAFFIC[("laplace-sphere-32768", "SAMPLE")])
     src = tmp_path / "k.hip"
     src.write_bytes(b"kernel v1")
     import hashlib
