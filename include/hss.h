@@ -195,6 +195,23 @@ typedef struct {
   const float* params;     /* device, hss_mlp_num_params floats (layout below) */
 } hss_predictor;
 
+/* Device memory from the caller (e.g. a framework's caching allocator).
+ * alloc returns `bytes` of device memory usable on `stream`, or NULL when
+ * it cannot (the call then fails with HSS_ERR_OUT_OF_MEMORY and frees
+ * what it took); free gives back a block alloc returned, on the stream it
+ * was used on.  Both run on the calling thread, during hss_compress /
+ * hss_compress_batched (the compression's working memory, freed when it
+ * ends) and during hss_matvec (its temporaries) and hss_destroy (the
+ * generators the handle keeps).  The functions and ctx must stay valid
+ * until the handle is destroyed.  alloc = NULL: the library allocates
+ * itself (hipMallocAsync, plus one cached block per device for the
+ * compression's working memory; see hss_release_cache). */
+typedef struct {
+  void* (*alloc)(void* ctx, size_t bytes, void* stream);
+  void (*free)(void* ctx, void* p, void* stream);
+  void* ctx;
+} hss_allocator;
+
 /* Options of one compression (Alg. 3).
  *   rtol, atol : relative / absolute tolerance; every node tau uses
  *                eta*rtol/level(tau) and eta*atol/level(tau)
@@ -214,7 +231,9 @@ typedef struct {
  *                of hss_random_normal with `seed` (ldr and ncols_R unused)
  *   stream     : hipStream_t for all work (NULL = default stream)
  *   seed       : key of the generated R (used only when R is NULL)
- *   predictor  : learned d0 (hss_predictor above), or NULL */
+ *   predictor  : learned d0 (hss_predictor above), or NULL
+ *   allocator  : device memory from the caller (hss_allocator above); all
+ *                problems of a batched call take the first one's */
 typedef struct {
   double rtol;
   double atol;
@@ -233,6 +252,7 @@ typedef struct {
   double hmt_alpha;
   uint64_t seed;
   const hss_predictor* predictor;   /* host struct, NULL = off: learned d0 (above) */
+  hss_allocator allocator;          /* alloc = NULL: the library's own */
 } hss_options;
 
 /* Largest sample count of a compression: a pivot step of the ID keeps its

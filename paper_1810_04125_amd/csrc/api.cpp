@@ -140,11 +140,19 @@ struct DevBuf {
 };
 
 // Stream-ordered scratch: allocated and freed in the order of `s`, so
-// asynchronous calls may return while their kernels still use it.
+// asynchronous calls may return while their kernels still use it; from the
+// caller's allocator when one is given.
 struct StreamBuf {
   void* p = nullptr;
   hipStream_t s;
-  StreamBuf(size_t bytes, hipStream_t st) : s(st) {
+  hss_allocator a{};
+  StreamBuf(size_t bytes, hipStream_t st, const hss_allocator* ua = nullptr) : s(st) {
+    if (ua && ua->alloc) {
+      a = *ua;
+      p = a.alloc(a.ctx, std::max<size_t>(bytes, 8), s);
+      if (!p) throw Error(HSS_ERR_OUT_OF_MEMORY, "the caller's allocator returned NULL for " + std::to_string(bytes) + " bytes");
+      return;
+    }
     hipError_t e = hipMallocAsync(&p, std::max<size_t>(bytes, 8), s);
     if (e != hipSuccess) {
       hipGetLastError();
@@ -154,7 +162,12 @@ struct StreamBuf {
     }
   }
   ~StreamBuf() {
-    if (p) hipFreeAsync(p, s);
+    if (!p) return;
+    if (a.alloc) {
+      if (a.free) a.free(a.ctx, p, s);
+    } else {
+      hipFreeAsync(p, s);
+    }
   }
   template <class T> T* as() const { return (T*)p; }
 };
@@ -501,9 +514,10 @@ hss_status hss_matvec(const hss_matrix* h, int32_t nrhs, const double* X, int64_
     hipStream_t s = (hipStream_t)stream;
     // stream-ordered temporaries: freed behind the kernels on `s`, so the
     // call returns without waiting for them
-    StreamBuf xp(sizeof(double) * P.n * nrhs, s), yp(sizeof(double) * P.n * nrhs, s);
-    StreamBuf xh(sizeof(double) * J.mvtot * nrhs, s), yh(sizeof(double) * J.mvtot * nrhs, s);
-    StreamBuf ws(sizeof(double) * J.mvwstot * nrhs, s);
+    const hss_allocator* ua = &J.ualloc;
+    StreamBuf xp(sizeof(double) * P.n * nrhs, s, ua), yp(sizeof(double) * P.n * nrhs, s, ua);
+    StreamBuf xh(sizeof(double) * J.mvtot * nrhs, s, ua), yh(sizeof(double) * J.mvtot * nrhs, s, ua);
+    StreamBuf ws(sizeof(double) * J.mvwstot * nrhs, s, ua);
     const int64_t* perm = P.dev.gen.perm;
     launch_gather_rows(X, ldx, perm, P.n, nrhs, xp.as<double>(), P.n, 0, s);
     matvec_permuted(h, nrhs, xp.as<double>(), yp.as<double>(), xh.as<double>(), yh.as<double>(), ws.as<double>(), s);

@@ -62,8 +62,8 @@ int64_t align8(int64_t x) { return (x + 7) & ~int64_t(7); }
 Job::~Job() {
   if (stream) hipStreamSynchronize(stream);
   arena_return();
-  for (void* p : transients) hipFreeAsync(p, stream);
-  for (void* p : allocs) hipFreeAsync(p, stream);
+  for (void* p : transients) dfree(p);
+  for (void* p : allocs) dfree(p);
   hipStreamSynchronize(stream);
   if (ev0) hipEventDestroy(ev0);
   if (ev1) hipEventDestroy(ev1);
@@ -129,6 +129,7 @@ void arena_release_idle() {
 }
 
 void* Job::arena_acquire(size_t bytes) {
+  if (ualloc.alloc) return dalloc(bytes, true);   // the caller's allocator keeps its own cache
   keep_pool_memory();
   int dev = 0;
   HSS_HIP_CHECK(hipGetDevice(&dev));
@@ -174,8 +175,15 @@ void Job::arena_return() {
 void* Job::dalloc(size_t bytes, bool transient) {
   void* p = nullptr;
   if (bytes == 0) bytes = 8;
-  keep_pool_memory();
   const auto t0 = std::chrono::steady_clock::now();
+  if (ualloc.alloc) {
+    p = ualloc.alloc(ualloc.ctx, bytes, stream);
+    alloc_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (!p) throw Error(HSS_ERR_OUT_OF_MEMORY, "the caller's allocator returned NULL for " + std::to_string(bytes) + " bytes");
+    (transient ? transients : allocs).push_back(p);
+    return p;
+  }
+  keep_pool_memory();
   hipError_t e = hipMallocAsync(&p, bytes, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);   // usable from any stream from now on
   alloc_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -186,6 +194,15 @@ void* Job::dalloc(size_t bytes, bool transient) {
   }
   (transient ? transients : allocs).push_back(p);
   return p;
+}
+
+void Job::dfree(void* p) {
+  if (!p) return;
+  if (ualloc.alloc) {
+    if (ualloc.free) ualloc.free(ualloc.ctx, p, stream);
+  } else {
+    hipFreeAsync(p, stream);
+  }
 }
 
 // E of every node side and B12 / B21 of every non-leaf move from their
@@ -252,7 +269,7 @@ void Job::compact_e() {
 void Job::release_transients() {
   HSS_HIP_CHECK(hipStreamSynchronize(stream));
   arena_return();
-  for (void* p : transients) hipFreeAsync(p, stream);
+  for (void* p : transients) dfree(p);
   HSS_HIP_CHECK(hipStreamSynchronize(stream));
   transients.clear();
   tpool = wsa = wsb = partial = gemm_ws = nullptr;
@@ -263,6 +280,8 @@ void Job::validate(const hss_generator& g, const hss_tree* t, const hss_options&
   if (!t || !t->perm || !t->lo || !t->hi || !t->left || !t->right || !t->parent || !t->level)
     throw Error(HSS_ERR_INVALID_ARG, who + "incomplete tree");
   if (g.n != t->n || g.n < 1) throw Error(HSS_ERR_INVALID_ARG, who + "generator n != tree n");
+  if ((o.allocator.alloc == nullptr) != (o.allocator.free == nullptr))
+    throw Error(HSS_ERR_INVALID_ARG, who + "allocator needs both alloc and free");
   if (g.family < 0 || g.family > HSS_FAM_CALLBACK) throw Error(HSS_ERR_INVALID_ARG, who + "unknown family");
   if (g.family == HSS_FAM_CALLBACK && (!g.sample || !g.extract))
     throw Error(HSS_ERR_INVALID_ARG, who + "callback family needs sample and extract routines");
@@ -369,6 +388,7 @@ void Job::setup(int32_t count, const hss_generator* gens, const hss_tree* const*
   if (count < 1) throw Error(HSS_ERR_INVALID_ARG, "count must be >= 1");
   strategy = opts[0].strategy;
   stream = (hipStream_t)opts[0].stream;
+  ualloc = opts[0].allocator;
   for (int k = 0; k < count; ++k) {
     validate(gens[k], trees[k], opts[k], k);
     if (opts[k].strategy != strategy || opts[k].stream != opts[0].stream)

@@ -60,6 +60,7 @@ struct Job {
   bool has_callback = false;   // some problem has caller routines (HSS_FAM_CALLBACK)
   int32_t max_block = 0;   // widest sampling block so far
   hipStream_t stream = nullptr;
+  hss_allocator ualloc{};          // caller's device memory (alloc = NULL: the library's own)
   std::vector<void*> allocs;       // live until the job is destroyed
   std::vector<void*> transients;   // freed when the compression ends
   double *dpool = nullptr, *tpool = nullptr, *wsa = nullptr, *wsb = nullptr, *partial = nullptr;
@@ -105,6 +106,7 @@ struct Job {
 
   ~Job();
   void* dalloc(size_t bytes, bool transient = false);
+  void dfree(void* p);                 // a block from dalloc, stream-ordered
   void* arena_acquire(size_t bytes);   // transient block (see driver.cpp)
   void arena_return();
   int arena_dev = -1;                  // device whose cached block this job holds

@@ -56,13 +56,52 @@ class _Tree(C.Structure):
                 ("parent", C.POINTER(C.c_int32)), ("level", C.POINTER(C.c_int32))]
 
 
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
+
+class _Alloc(C.Structure):
+    _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("ctx", C.c_void_p)]
+
+
 class _Opt(C.Structure):
     _fields_ = [("rtol", C.c_double), ("atol", C.c_double), ("eta", C.c_double),
                 ("strategy", C.c_int32), ("d0", C.c_int32), ("delta_d", C.c_int32),
                 ("oversample_p", C.c_int32), ("d_max", C.c_int32), ("sample_precision", C.c_int32),
                 ("R", C.c_void_p), ("ldr", C.c_int64), ("ncols_R", C.c_int32),
                 ("profile", C.c_int32), ("stream", C.c_void_p), ("hmt_alpha", C.c_double),
-                ("seed", C.c_uint64), ("predictor", C.c_void_p)]
+                ("seed", C.c_uint64), ("predictor", C.c_void_p), ("allocator", _Alloc)]
+
+
+class Allocator:
+    """Device memory for the library from Python callables (hss_allocator):
+    alloc(nbytes, stream) returns an int device pointer (0 or an exception:
+    none available), free(ptr, stream) gives a block back.  Keep the object
+    alive while handles made with it exist (the handles hold a reference)."""
+
+    def __init__(self, alloc, free):
+        def _a(ctx, nbytes, stream):
+            try:
+                return alloc(int(nbytes), stream or 0) or None
+            except Exception:
+                return None
+
+        def _f(ctx, ptr, stream):
+            try:
+                free(ptr, stream or 0)
+            except Exception:
+                pass
+
+        self._fa, self._ff = _ALLOC_FN(_a), _FREE_FN(_f)
+        self._c = _Alloc(self._fa, self._ff, None)
+
+
+def torch_allocator(device=None):
+    """An Allocator backed by torch's CUDA caching allocator."""
+    import torch
+    dev = torch.cuda.current_device() if device is None else device
+    return Allocator(lambda n, s: torch.cuda.caching_allocator_alloc(n, dev, s),
+                     lambda p, s: torch.cuda.caching_allocator_delete(p))
 
 
 class _Info(C.Structure):
@@ -444,8 +483,10 @@ class HSSMatrix:
 
 
 def _opts(R, rtol, atol, eta, strategy, d0, delta_d, p, d_max, precision, profile=False, hmt_alpha=10.0,
-          seed=0, n=None, predictor=None):
+          seed=0, n=None, predictor=None, allocator=None):
     o = _Opt()
+    if allocator is not None:
+        o.allocator = allocator._c
     o.rtol, o.atol, o.eta = rtol, atol, eta
     o.strategy = STRATEGY[strategy]
     o.d0, o.delta_d, o.oversample_p = d0, delta_d, p
@@ -468,17 +509,19 @@ def _opts(R, rtol, atol, eta, strategy, d0, delta_d, p, d_max, precision, profil
 
 def compress(gen: Generator, tree: Tree, R=None, rtol=1e-6, atol=1e-12, eta=1.0, strategy="dbl_fnorm",
              d0=64, delta_d=64, p=10, d_max=None, precision="fp64", profile=False, hmt_alpha=10.0, seed=0,
-             predictor=None):
+             predictor=None, allocator=None):
     """Adaptive HSS compression (hss_compress).  R: (n, d_cap) float64 CUDA tensor,
     column-major, rows in permuted order; or None, and the library draws R
     on the device from `seed` (hss_random_normal).  predictor: a Predictor
-    (hss_predictor), whose d0 then replaces `d0`.  Returns (HSSMatrix, status)."""
+    (hss_predictor), whose d0 then replaces `d0`.  allocator: an Allocator
+    (e.g. torch_allocator()) for all device memory of the compression and
+    of the handle, or None for the library's own.  Returns (HSSMatrix, status)."""
     g = gen._c()
     o = _opts(R, rtol, atol, eta, strategy, d0, delta_d, p, d_max, precision, profile, hmt_alpha, seed, gen.n,
-              predictor)
+              predictor, allocator)
     h = C.c_void_p()
     st = _check(lib().hss_compress(C.byref(g), tree._t, C.byref(o), C.byref(h)))
-    return HSSMatrix(h.value, (gen, tree, R)), st
+    return HSSMatrix(h.value, (gen, tree, R, allocator)), st
 
 
 def compress_batched(gens, trees, Rs, **kw):
@@ -497,11 +540,11 @@ def compress_batched(gens, trees, Rs, **kw):
                            opt("strategy", i, "dbl_fnorm"), opt("d0", i, 64), opt("delta_d", i, 64),
                            opt("p", i, 10), opt("d_max", i, None), opt("precision", i, "fp64"),
                            opt("profile", i, False), opt("hmt_alpha", i, 10.0), opt("seed", i, 0), gens[i].n,
-                           opt("predictor", i, None))
+                           opt("predictor", i, None), kw.get("allocator"))
                      for i, R in enumerate(Rs)])
     H = (C.c_void_p * k)()
     st = _check(lib().hss_compress_batched(k, G, T, O, H))
-    return [HSSMatrix(H[i], (gens[i], trees[i], Rs[i])) for i in range(k)], st
+    return [HSSMatrix(H[i], (gens[i], trees[i], Rs[i], kw.get("allocator"))) for i in range(k)], st
 
 
 def release_cache():

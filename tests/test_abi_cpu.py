@@ -73,7 +73,7 @@ def test_binding_structs_match_the_header(tmp_path):
         pytest.skip("no C compiler")
     pairs = {"hss_generator": H._Gen, "hss_block": H._Block, "hss_tree": H._Tree, "hss_options": H._Opt,
              "hss_info": H._Info, "hss_kernel_stats": H._KStats, "hss_node_info": H._NodeInfo,
-             "hss_mlp": H._Mlp, "hss_predictor": H._Predictor}
+             "hss_mlp": H._Mlp, "hss_predictor": H._Predictor, "hss_allocator": H._Alloc}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "hss.h"', "int main(void) {"]
     for cname, cls in pairs.items():
         lines.append('printf("%s %%zu\\n", sizeof(%s));' % (cname, cname))
@@ -164,3 +164,15 @@ def test_compress_rejects_a_predictor_outside_its_scope():
     assert st == -1 and "incrementing" in msg
     st, msg = _host_compress(T, predictor=ptr, rtol=0.0)
     assert st == -1 and "rtol" in msg
+
+
+def test_compress_rejects_an_allocator_without_free():
+    """alloc without free (or the reverse) is an argument error, caught on
+    the host before any device call."""
+    from paper_1810_04125_amd import hss as H
+    a = H.Allocator(lambda n, s: 0, lambda p, s: None)
+    half = H._Alloc()
+    half.alloc = a._fa
+    T = hss.Tree(64, 16)
+    st, msg = _host_compress(T, allocator=half)
+    assert st == -1 and "allocator" in msg
