@@ -640,17 +640,19 @@ void run_qrcp(QrcpTask* tasks, int32_t ntasks, const QrcpWork& wk, const int2* w
   }
   const bool known_active = solve_e;   // some panel is known to be active
   const int64_t cells = (int64_t)std::max(dmax, 1) * std::max(ncols_max, 1);
-  const bool blocks = solve_e && bw && bw->blk && ncols_max <= kIdbMaxM;
-  bool one_wg = !blocks && cells <= kQrcpWgCells && lds <= 48 * 1024;
+  bool one_wg = cells <= kQrcpWgCells && lds <= 48 * 1024;
   if (one_wg && solve_e) {
     // Per pivot step, the one-workgroup kernel walks the columns 16 at a
     // time (about 5 + 2.2 us per 16 columns, measured); the many-workgroup
     // step costs about 7 us, or its traffic at about 3.4 TB/s when larger
-    // (2.35 ps per cell of all active panels).
+    // (2.35 ps per cell of all active panels), and a pivot of the blocked
+    // ID about 10 us on the sphere-Laplace levels (a block of 12 launches
+    // per 19 pivots on average), so small panels stay on one workgroup.
     const double t_wg = 5.0 + 2.2 * std::ceil(ncols_max / 16.0);
     const double t_step = std::max(7.0, 2.35e-6 * (double)sc.nact * (double)cells);
     one_wg = t_wg < t_step;
   }
+  const bool blocks = !one_wg && solve_e && bw && bw->blk && ncols_max <= kIdbMaxM;
   if (one_wg) {
     prof_begin(s);
     hipLaunchKernelGGL(k_qrcp_wg, dim3(ntasks), dim3(QBW), lds, s, tasks, kcnt);

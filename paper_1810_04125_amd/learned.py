@@ -22,6 +22,7 @@ changes the accuracy guarantee.
 
     python -m paper_1810_04125_amd.learned generate --count 1536 --out FILE
     python -m paper_1810_04125_amd.learned train --data FILE --out WEIGHTS
+    python -m paper_1810_04125_amd.learned curve --data FILE
 """
 from __future__ import annotations
 
@@ -94,7 +95,7 @@ def rows_of(spec, tree, level_rank, d_final):
     return X, T, M
 
 
-def generate(count, seed, chunk=48, delta_d=64, eta=0.1, d_max=4096, log=print):
+def generate(count, seed, chunk=48, delta_d=64, eta=0.05, d_max=4096, log=print):
     """Compress `count` random problems on the GPU (incrementing strategy,
     d0 = delta_d) and return the training set as a dict of arrays."""
     import torch
@@ -132,7 +133,28 @@ def generate(count, seed, chunk=48, delta_d=64, eta=0.1, d_max=4096, log=print):
         log("generate: %d / %d problems, %.1f s" % (min(count, c0 + chunk), count, time.time() - t0))
     out = {"X": np.array(X, np.float32), "T": np.array(T, np.float32), "M": np.array(M, np.float32)}
     out.update({"p_" + k: np.array(v) for k, v in meta.items()})
+    out["p_eta"] = np.array([eta])
     return out
+
+
+def _split(data, holdout):
+    """(training rows, held-out rows, problem starts, number held out): whole
+    problems are held out (rows are grouped per problem, root row first)."""
+    starts = np.flatnonzero(data["X"][:, 5] == 0.0)
+    nprob = len(starts)
+    nhold = int(round(holdout * nprob))
+    cut = starts[nprob - nhold] if nhold else len(data["X"])
+    return ({k: data[k][:cut] for k in ("X", "T", "M")}, {k: data[k][cut:] for k in ("X", "T", "M")},
+            starts, nhold)
+
+
+def holdout_error(params, ho):
+    """Mean absolute error on held-out rows: log2(1 + rank) and log2 d_final."""
+    import torch
+    Y = hss.mlp_forward(SIZES, torch.from_numpy(params).cuda(), torch.from_numpy(ho["X"]).cuda()).cpu().numpy()
+    err = np.abs(Y - ho["T"]) * ho["M"]
+    return (float(err[:, 0].sum() / max(1.0, ho["M"][:, 0].sum())),
+            float(err[:, 1].sum() / max(1.0, ho["M"][:, 1].sum())))
 
 
 def train(data, epochs=400, batch=256, lr=1e-3, seed=0, init_seed=1):
@@ -194,6 +216,13 @@ def _main():
     g.add_argument("--count", type=int, default=1536)
     g.add_argument("--seed", type=int, default=10000)
     g.add_argument("--out", default=TRAIN_DATA)
+    g.add_argument("--eta", type=float, default=0.05)
+    c = sub.add_parser("curve", help="held-out error against the number of training problems")
+    c.add_argument("--data", default=TRAIN_DATA)
+    c.add_argument("--sizes", default="256,512,1024,2048,0")
+    c.add_argument("--steps", type=int, default=0, help="optimizer steps per run (0: those of 400 epochs on all)")
+    c.add_argument("--batch", type=int, default=256)
+    c.add_argument("--holdout", type=float, default=0.1)
     t = sub.add_parser("train")
     t.add_argument("--data", default=TRAIN_DATA)
     t.add_argument("--out", default=WEIGHTS)
@@ -204,31 +233,37 @@ def _main():
     a = ap.parse_args()
     log = lambda m: print(m, flush=True)
     if a.cmd == "generate":
-        d = generate(a.count, a.seed, log=log)
+        d = generate(a.count, a.seed, eta=a.eta, log=log)
         np.savez_compressed(a.out, **d)
         log("wrote %s: %d rows from %d problems" % (a.out, len(d["X"]), a.count))
         return
     with np.load(a.data, allow_pickle=False) as z:
         data = {k: z[k] for k in z.files}
-    # hold out whole problems: rows are grouped per problem, root row first
-    starts = np.flatnonzero(data["X"][:, 5] == 0.0)
+    tr, ho, starts, nhold = _split(data, a.holdout)
     nprob = len(starts)
-    nhold = int(round(a.holdout * nprob))
-    cut = starts[nprob - nhold] if nhold else len(data["X"])
-    tr = {k: data[k][:cut] for k in ("X", "T", "M")}
-    ho = {k: data[k][cut:] for k in ("X", "T", "M")}
+    if a.cmd == "curve":
+        ntr = nprob - nhold
+        steps = a.steps or 400 * math.ceil(len(tr["X"]) / a.batch)
+        for size in [int(x) for x in a.sizes.split(",")]:
+            size = ntr if size <= 0 or size > ntr else size
+            rows = starts[size] if size < ntr else len(tr["X"])
+            sub_tr = {k: v[:rows] for k, v in tr.items()}
+            epochs = max(1, round(steps / math.ceil(rows / a.batch)))
+            t0 = time.time()
+            params, losses = train(sub_tr, epochs=epochs, batch=a.batch)
+            e_rank, e_d = holdout_error(params, ho)
+            log(json.dumps({"train_problems": size, "train_rows": int(rows), "epochs": epochs,
+                            "seconds": round(time.time() - t0, 1), "loss_last": float(losses[-1]),
+                            "holdout_problems": nhold, "holdout_mae_log2_rank": round(e_rank, 4),
+                            "holdout_mae_log2_dfinal": round(e_d, 4)}))
+        return
     t0 = time.time()
     params, losses = train(tr, epochs=a.epochs, batch=a.batch, lr=a.lr)
     el = time.time() - t0
     res = {"epochs": a.epochs, "train_seconds": round(el, 2), "loss_first": float(losses[0]),
            "loss_last": float(losses[-1]), "train_problems": nprob - nhold, "holdout_problems": nhold}
     if nhold:
-        import torch
-        Y = hss.mlp_forward(SIZES, torch.from_numpy(params).cuda(),
-                            torch.from_numpy(ho["X"]).cuda()).cpu().numpy()
-        err = np.abs(Y - ho["T"]) * ho["M"]
-        res["holdout_mae_log2_rank"] = float(err[:, 0].sum() / max(1.0, ho["M"][:, 0].sum()))
-        res["holdout_mae_log2_dfinal"] = float(err[:, 1].sum() / max(1.0, ho["M"][:, 1].sum()))
+        res["holdout_mae_log2_rank"], res["holdout_mae_log2_dfinal"] = holdout_error(params, ho)
     save(params, a.out, **res)
     log(json.dumps(res))
 
