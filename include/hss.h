@@ -179,8 +179,8 @@ void hss_tree_free(hss_tree* tree);
  * the kernel parameter, h for Toeplitz or sigma for the Gaussian kernel,
  * 0 for Laplace; (log2 n - 14)/3; level/8; (log2 of the level's mean node
  * size - 10)/4; (-log10 rtol - 6)/2) and takes d0 = the predicted final
- * sample count 2^y (output 1 of the root row) rounded down to a multiple
- * of delta_d, within [delta_d, min(d_max, n)].  The stopping tests still
+ * sample count 2^y (output 1 of the root row) rounded to the nearest
+ * multiple of delta_d, within [delta_d, min(d_max, n)].  The stopping tests still
  * decide every node: a low prediction costs rounds, a high one samples.
  * Only for HSS_FAM_TOEPLITZ, HSS_FAM_LAPLACE and HSS_FAM_GAUSS with the
  * incrementing strategies; options.d0 is then ignored. */

@@ -273,7 +273,7 @@ int32_t predict_d0(const hss_generator& g, const hss_tree* t, const hss_options&
   *dpred = d;
   const int32_t dd = o.delta_d;
   const int64_t cap = std::min<int64_t>(o.d_max, g.n);
-  const double q = std::floor(std::min(d, (double)cap) / dd);
+  const double q = std::floor(std::min(d, (double)cap) / dd + 0.5);   // the nearest multiple of delta_d
   int64_t d0 = std::max<int64_t>(dd, (int64_t)dd * (int64_t)q);
   return (int32_t)std::min<int64_t>(d0, cap);
 }

@@ -203,9 +203,11 @@ class D0Predictor:
 
     def d0(self, family, param, n, tree, rtol, delta_d=64, d_max=None, margin=0.0):
         """Initial sample count: the predicted d_final, shrunk by `margin`,
-        rounded down to a multiple of delta_d, at least delta_d."""
+        rounded to the nearest multiple of delta_d, at least delta_d (a
+        prediction a little low would cost a whole round, one a little
+        high some sample columns)."""
         d = self.predict(family, param, n, tree, rtol)["d_final"] * (1.0 - margin)
-        d0 = max(delta_d, delta_d * int(math.floor(d / delta_d)))
+        d0 = max(delta_d, delta_d * int(math.floor(d / delta_d + 0.5)))
         return min(d0, d_max) if d_max else d0
 
 
