@@ -95,25 +95,21 @@ def rows_of(spec, tree, level_rank, d_final):
     return X, T, M
 
 
-def generate(count, seed, chunk=48, delta_d=64, eta=0.05, d_max=4096, log=print):
+def generate(count, seed, chunk=48, delta_d=64, eta=0.05, d_max=4096, log=print, n_lo=1024, n_hi=32768):
     """Compress `count` random problems on the GPU (incrementing strategy,
-    d0 = delta_d) and return the training set as a dict of arrays."""
-    import torch
-    specs = inputs.learned_problems(count, seed)
-    nmax = max(s["n"] for s in specs)
-    Rh = inputs.gaussian_matrix(nmax, d_max, seed + 1)
-    R = hss.colmajor(torch.from_numpy(np.ascontiguousarray(Rh.T)).cuda().t())
-    del Rh
+    d0 = delta_d, R drawn by the library from the seed) and return the
+    training set as a dict of arrays."""
+    specs = inputs.learned_problems(count, seed, n_lo, n_hi)
     X, T, M = [], [], []
     meta = {k: [] for k in ("family", "n", "leaf", "param", "rtol", "d_final", "rounds", "status", "max_rank")}
     t0 = time.time()
     for c0 in range(0, count, chunk):
         part = specs[c0:c0 + chunk]
         probs = [make_problem(s) for s in part]
-        Hs, _ = hss.compress_batched([p[0] for p in probs], [p[1] for p in probs],
-                                     [R[:s["n"]] for s in part], rtol=[s["rtol"] for s in part],
-                                     atol=1e-12, eta=eta, strategy="inc_fnorm", d0=delta_d,
-                                     delta_d=delta_d, d_max=d_max)
+        Hs, _ = hss.compress_batched([p[0] for p in probs], [p[1] for p in probs], None,
+                                     rtol=[s["rtol"] for s in part], atol=1e-12, eta=eta,
+                                     strategy="inc_fnorm", d0=delta_d, delta_d=delta_d,
+                                     d_max=[min(d_max, s["n"]) for s in part], seed=seed + 1)
         for s, (gen, tree), H in zip(part, probs, Hs):
             info = H.info()
             lr = np.zeros(int(tree.level.max()) + 1)
@@ -134,6 +130,29 @@ def generate(count, seed, chunk=48, delta_d=64, eta=0.05, d_max=4096, log=print)
     out = {"X": np.array(X, np.float32), "T": np.array(T, np.float32), "M": np.array(M, np.float32)}
     out.update({"p_" + k: np.array(v) for k, v in meta.items()})
     out["p_eta"] = np.array([eta])
+    return out
+
+
+def merge(a, b, every):
+    """Training sets a and b as one, b's problems placed after every
+    `every` problems of a (rows stay grouped per problem, root row first)."""
+    def groups(d):
+        st = list(np.flatnonzero(d["X"][:, 5] == 0.0)) + [len(d["X"])]
+        return [(st[i], st[i + 1]) for i in range(len(st) - 1)]
+    ga, gb = groups(a), groups(b)
+    order, ib = [], 0   # (set, problem index)
+    for i in range(len(ga)):
+        order.append((0, i))
+        if (i + 1) % every == 0 and ib < len(gb):
+            order.append((1, ib))
+            ib += 1
+    order += [(1, j) for j in range(ib, len(gb))]
+    src, grp = (a, b), (ga, gb)
+    out = {k: np.concatenate([src[w][k][grp[w][i][0]:grp[w][i][1]] for w, i in order]) for k in ("X", "T", "M")}
+    for k in a:
+        if k.startswith("p_") and k != "p_eta" and k in b:
+            out[k] = np.array([src[w][k][i] for w, i in order])
+    out["p_eta"] = a.get("p_eta", np.array([0.05]))
     return out
 
 
@@ -219,6 +238,12 @@ def _main():
     g.add_argument("--seed", type=int, default=10000)
     g.add_argument("--out", default=TRAIN_DATA)
     g.add_argument("--eta", type=float, default=0.05)
+    g.add_argument("--n-lo", type=int, default=1024)
+    g.add_argument("--n-hi", type=int, default=32768)
+    g.add_argument("--d-max", type=int, default=4096)
+    g.add_argument("--merge-into", default=None,
+                   help="an existing set: write it with the new problems interleaved (one after every k-th)")
+    g.add_argument("--every", type=int, default=4)
     c = sub.add_parser("curve", help="held-out error against the number of training problems")
     c.add_argument("--data", default=TRAIN_DATA)
     c.add_argument("--sizes", default="256,512,1024,2048,0")
@@ -235,9 +260,12 @@ def _main():
     a = ap.parse_args()
     log = lambda m: print(m, flush=True)
     if a.cmd == "generate":
-        d = generate(a.count, a.seed, eta=a.eta, log=log)
+        d = generate(a.count, a.seed, eta=a.eta, log=log, n_lo=a.n_lo, n_hi=a.n_hi, d_max=a.d_max)
+        if a.merge_into:
+            with np.load(a.merge_into, allow_pickle=False) as z:
+                d = merge({k: z[k] for k in z.files}, d, a.every)
         np.savez_compressed(a.out, **d)
-        log("wrote %s: %d rows from %d problems" % (a.out, len(d["X"]), a.count))
+        log("wrote %s: %d rows from %d problems" % (a.out, len(d["X"]), len(d["p_n"])))
         return
     with np.load(a.data, allow_pickle=False) as z:
         data = {k: z[k] for k in z.files}

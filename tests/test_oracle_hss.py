@@ -360,3 +360,86 @@ def test_doubling_hmt_driver_passes_hankel_block_sizes(monkeypatch):
         assert dims is not None and dims[0] in sizes and dims[0] + dims[1] == n
     # above the leaves the local sample has fewer rows than the node
     assert any(shape[0] < dims[0] for shape, dims in seen)
+
+
+def test_fnorm_absolute_test_divides_by_sqrt_of_the_block_width():
+    """eq. stopping_criteria, absolute part: ||S_hat||_F / sqrt(b) < eps_a with
+    b the width of the block under test (Sec. 3.4: E||S||_F^2 = b ||A||_F^2).
+    S = [I_4; 0] (m = 16, b = 4, d = 8): ||S_hat||_F = 2, ||S_hat||_F/sqrt(b) = 1,
+    every R diagonal entry 1, eps_r = 0.  Dividing by sqrt(d) (0.707) would
+    pass at eps_a = 0.9; not dividing (2) would fail at eps_a = 1.5."""
+    S = np.vstack([np.eye(4), np.zeros((12, 4))])
+    assert fnorm_test(FnormSide(), S, 8, 0.0, 1.5)
+    st = FnormSide()
+    assert not fnorm_test(st, S, 8, 0.0, 0.9)
+    assert st.Q.shape == (16, 4)        # a failed block joins the basis
+
+
+def test_fnorm_relative_diagonal_test_uses_the_first_blocks_r11():
+    """rho = |R11| of the first block QR'd on the side (the Alg. 5 choice):
+    block 1 (R diagonal 10, 9) fails and sets rho = 10; block 2, orthogonal
+    to it (R diagonal 1, 0.5), passes min|R_ii| = 0.5 < eps_r rho = 1.0 with
+    eps_r = 0.1, where its own R11 (1) would give 0.5 < 0.1 and fail."""
+    m = 12
+    E = np.eye(m)
+    st = FnormSide()
+    S1 = np.column_stack([10.0 * E[:, 0], 9.0 * E[:, 1]])
+    assert not fnorm_test(st, S1, 2, 0.1, 0.0)
+    assert st.rho == pytest.approx(10.0)
+    S2 = np.column_stack([1.0 * E[:, 2], 0.5 * E[:, 3]])
+    assert fnorm_test(st, S2, 4, 0.1, 0.0)
+    # the same block as a first block fails: its own R11 would be rho
+    assert not fnorm_test(FnormSide(), S2, 2, 0.1, 0.0)
+
+
+def test_fnorm_zero_diagonal_passes_with_zero_tolerances():
+    """A projected block whose QR has an exactly zero diagonal entry passes
+    (the block completes the range), even with eps_r = eps_a = 0; without
+    the zero it fails."""
+    E = np.eye(10)
+    assert fnorm_test(FnormSide(), np.column_stack([E[:, 0], np.zeros(10)]), 2, 0.0, 0.0)
+    assert not fnorm_test(FnormSide(), np.column_stack([E[:, 0], 1e-300 * E[:, 1]]), 2, 0.0, 0.0)
+
+
+def test_first_test_replays_the_sampled_blocks_in_order(monkeypatch):
+    """Reading 3: a node tested for the first time while several blocks are
+    sampled runs Alg. 5 over them in sampling order, block by block with
+    the schedule's widths (d = the cumulative count), and stops at the
+    first pass, as if it had been tested every round.  The other reading
+    (all d columns as one block) would make one call of width d."""
+    import oracle.hss as H
+    calls = []
+    real_test, real_node = H.fnorm_test, H._Compressor.node_test_and_id
+    visit = [0]
+
+    def spy(st, S_new, d, er, ea):
+        out = real_test(st, S_new, d, er, ea)
+        calls.append((visit[0], id(st), S_new.shape[1], d, out))
+        return out
+
+    def node_spy(self, t, cols):
+        visit[0] += 1
+        return real_node(self, t, cols)
+
+    monkeypatch.setattr(H, "fnorm_test", spy)
+    monkeypatch.setattr(H._Compressor, "node_test_and_id", node_spy)
+    n, leaf = 1024, 64
+    ot = build_tree(n, leaf)
+    op = PermutedOperator(Toeplitz(n, 0.1), ot.perm)
+    R = inputs.gaussian_matrix(n, 512, 6)
+    h = H.compress(op, ot, R, 1e-10, 1e-14, "inc_fnorm", d0=16, delta_d=16, d_max=512)
+    sched = h.d_schedule
+    widths = {c1: c1 - c0 for c0, c1 in zip([0] + sched, sched)}
+    per_visit = {}
+    for v, sid, b, d, out in calls:
+        per_visit.setdefault((v, sid), []).append((b, d, out))
+    replays = 0
+    for seq in per_visit.values():
+        ds = [d for _, d, _ in seq]
+        assert ds == sorted(ds)                         # sampling order
+        assert all(widths[d] == b for b, d, _ in seq)   # one sampled block per call
+        assert all(not out for _, _, out in seq[:-1])   # nothing after a pass
+        if len(seq) > 1:
+            assert ds[0] == sched[0]                    # a replay starts at the first block
+            replays += 1
+    assert replays > 0
