@@ -146,6 +146,9 @@ def traffic_bytes(workload, cls):
     return 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
 
 
+# launch-shape table from the autotuner (python -m paper_1810_04125_amd.autotune), loaded when present
+TUNE_FILE = os.path.join(ROOT, "paper_1810_04125_amd", "data", "tunables_gfx950.txt")
+
 # classes whose launches are one kernel each (the roofline is reported for
 # the dominant one of these; the others mix kernels)
 SINGLE_KERNEL = {"SAMPLE", "RNG", "QRCP_WG", "EXTRACT", "TRSM", "SAMPLE_REDUCE"}
@@ -598,6 +601,8 @@ def main():
     ap.add_argument("--no-legs", action="store_true",
                     help="skip the mixed-precision and learned-d0 legs of the default line")
     ap.add_argument("--leg-steps", type=int, default=3)
+    ap.add_argument("--tunables", default=TUNE_FILE,
+                    help="launch-shape table written by the autotuner ('none': the built-in shapes)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a device-to-device copy of 1 GiB three times (reference for HBM counters)")
     ap.add_argument("--table", choices=["hmt", "adaptive-rank"],
@@ -620,6 +625,11 @@ def main():
         sys.exit(1)
     W = WORKLOADS[args.workload]
     log = lambda m: print(m, file=sys.stderr, flush=True)
+    tune_file = None
+    if args.tunables != "none" and os.path.exists(args.tunables):
+        hss.load_tunables(args.tunables)
+        tune_file = os.path.relpath(args.tunables, ROOT)
+        log("bench: launch shapes from %s" % tune_file)
     if args.table:
         return main_table(args, log)
     if W.get("batch"):
@@ -680,7 +690,8 @@ def main():
     cfg = {"workload": args.workload, "n": n, "leaf": W["leaf"], "tree": W["method"],
            "strategy": W["strategy"], "d0": W["d0"], "delta_d": W["delta_d"],
            "rtol": args.rtol, "atol": 1e-12, "eta": ETA, "d_max": W["d_max"],
-           "sampling": args.precision, "r": "device Philox4x64-10 + Box-Muller, seed %d" % W.get("r_seed", 0)}
+           "sampling": args.precision, "r": "device Philox4x64-10 + Box-Muller, seed %d" % W.get("r_seed", 0),
+           "tunables": tune_file or "built-in"}
     out = {
         "metric": METRIC, "value": round(value, 4), "unit": "compressions/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * el / args.steps, 3),

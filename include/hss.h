@@ -212,6 +212,37 @@ typedef struct {
   void* ctx;
 } hss_allocator;
 
+/* Launch-shape tunables (not part of the method): the workgroup counts
+ * the grouped GEMMs (gemm_wg, at most gemm_max_split K slices) and the
+ * sampling product (sample_wg) split K to reach, and the workgroup target
+ * of the one-step pivot kernels (qrcp_wg, 64 .. HSS_QRCP_WG_MAX).  Results
+ * depend on them only through the order of floating-point sums. */
+#define HSS_QRCP_WG_MAX 4096
+typedef struct {
+  int32_t gemm_wg;
+  int32_t gemm_max_split;
+  int32_t sample_wg;
+  int32_t qrcp_wg;
+} hss_tunables;
+
+/* The built-in tunables. */
+hss_status hss_default_tunables(hss_tunables* out);
+/* Load a tunables table (the autotuner, python -m
+ * paper_1810_04125_amd.autotune, writes one): text lines
+ *   arch family precision n_lo n_hi gemm_wg gemm_max_split sample_wg qrcp_wg
+ * (arch as the device reports it, e.g. gfx950; family and precision as
+ * the hss_family / hss_precision numbers; '#' starts a comment).  A
+ * compression takes the first line that matches its device, the family
+ * and precision of its first problem and n_lo <= n < n_hi of that
+ * problem, else the defaults.  path NULL or "" clears the table.  Without a
+ * call, the first compression loads the file named by the environment
+ * variable HSS_TUNE_FILE, if set.  Host only; errors in the file return
+ * HSS_ERR_INVALID_ARG and leave the table unchanged. */
+hss_status hss_load_tunables(const char* path);
+/* The tunables a compression with this key would take. */
+hss_status hss_lookup_tunables(const char* arch, int32_t family, int32_t precision, int64_t n,
+                               hss_tunables* out);
+
 /* Options of one compression (Alg. 3).
  *   rtol, atol : relative / absolute tolerance; every node tau uses
  *                eta*rtol/level(tau) and eta*atol/level(tau)

@@ -335,6 +335,9 @@ hss_status hss_compress_batched(int32_t count, const hss_generator* gens, const 
         ++g1;
       }
       auto job = std::make_shared<Job>();
+      // launch shapes from the tunables table (the group's first problem)
+      const hss_tunables tv = tunables_for(gens[g0].family, opts[g0].sample_precision, gens[g0].n);
+      TuneScope scope(tv);
       const auto t0 = std::chrono::steady_clock::now();
       job->setup(g1 - g0, gens + g0, trees + g0, opts + g0);
       const auto t1 = std::chrono::steady_clock::now();

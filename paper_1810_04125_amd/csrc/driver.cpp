@@ -91,6 +91,18 @@ static void keep_pool_memory() {
   done = true;
 }
 
+// After an out-of-memory failure: memory freed into the stream-ordered pool
+// stays mapped (the release threshold above), and plain allocations cannot
+// use it; give it back to the device before one retry.
+static void trim_pool_memory() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return;
+  hipDeviceSynchronize();
+  hipMemPool_t pool;
+  if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) hipMemPoolTrimTo(pool, 0);
+  hipGetLastError();
+}
+
 // The transient buffers of a compression (local samples, bases, level
 // workspaces: sized from d_max, often tens of GB) are carved from one
 // block per device that outlives the job: freeing and re-mapping that much
@@ -147,6 +159,11 @@ void* Job::arena_acquire(size_t bytes) {
         a.p = nullptr;
         a.bytes = 0;
         hipError_t e = hipMalloc(&a.p, bytes);
+        if (e == hipErrorOutOfMemory) {
+          hipGetLastError();
+          trim_pool_memory();
+          e = hipMalloc(&a.p, bytes);
+        }
         if (e != hipSuccess) {
           hipGetLastError();
           a.p = nullptr;
@@ -185,6 +202,11 @@ void* Job::dalloc(size_t bytes, bool transient) {
   }
   keep_pool_memory();
   hipError_t e = hipMallocAsync(&p, bytes, stream);
+  if (e == hipErrorOutOfMemory) {
+    hipGetLastError();
+    trim_pool_memory();
+    e = hipMallocAsync(&p, bytes, stream);
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(stream);   // usable from any stream from now on
   alloc_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   if (e != hipSuccess) {

@@ -189,7 +189,7 @@ QrcpPlan make_qrcp_plan(const std::vector<int32_t>& mcaps, int cpw = QCPW);
 // more waves keep more column loads in flight; 4 and 7 per unit were slower).
 // The plan kernel doubles it for steps that would give a workgroup 16 or
 // more columns (large batches of panels).
-constexpr int kQrcpTarget = 1280;
+constexpr int kQrcpTarget = 1280;   // default; the active tunables' qrcp_wg (<= HSS_QRCP_WG_MAX) is used
 // Panels of at most this many cells (rows x columns, by capacity) are
 // factored by one workgroup each in a single launch.
 constexpr int64_t kQrcpWgCells = 64 * 1024;
@@ -211,7 +211,17 @@ struct QrcpWork {
   int32_t* kbuf = nullptr;        // 2 int32: step counter of the graph replays (nullptr: no graphs)
   QrcpGraphs* graphs = nullptr;   // graph cache (nullptr: plain launches)
 };
-inline size_t qrcp_work_entries(int32_t max_tasks) { return (size_t)2 * kQrcpTarget + (size_t)std::max(max_tasks, 1); }
+inline size_t qrcp_work_entries(int32_t max_tasks) { return (size_t)2 * HSS_QRCP_WG_MAX + (size_t)std::max(max_tasks, 1); }
+
+// Launch-shape tunables of the calling thread's compression (the defaults
+// outside one); TuneScope makes a table entry active for a compression.
+const hss_tunables& tune();
+struct TuneScope {
+  explicit TuneScope(const hss_tunables& t);
+  ~TuneScope();
+  const hss_tunables* saved;
+};
+hss_tunables tunables_for(int32_t family, int32_t precision, int64_t n);   // device 0 of the current context
 // Block-pivoted ID (k_idblock.hip): per task, a slot of workspace sized
 // from its capacities (panel rows dcap, columns mcap).
 constexpr int kIdbCmax = 128;   // candidate columns per block (their Gram matrix fits in LDS)

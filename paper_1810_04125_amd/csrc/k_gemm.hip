@@ -204,11 +204,12 @@ void launch_gemm(const GemmTask* tasks, int32_t ntasks, int32_t mcap, int32_t nc
   if (ntasks <= 0 || mcap <= 0 || ncap <= 0) return;
   const unsigned gx = (unsigned)((ncap + GT - 1) / GT), gy = (unsigned)((mcap + GT - 1) / GT);
   const int64_t tiles = (int64_t)gx * gy * ntasks;
-  // split K until about 2048 workgroups are busy, K slices of at least
-  // 4 tiles, within the workspace
+  // split K until about tune().gemm_wg (2048) workgroups are busy, K slices
+  // of at least 4 tiles, at most tune().gemm_max_split, within the workspace
+  const int64_t target = tune().gemm_wg, maxsplit = tune().gemm_max_split;
   int ksplit = 1;
-  if (ws && kcap >= 8 * GK && tiles < 2048) {
-    ksplit = (int)std::min<int64_t>(std::min<int64_t>(32, kcap / (4 * GK)), std::max<int64_t>(1, 2048 / tiles));
+  if (ws && kcap >= 8 * GK && tiles < target) {
+    ksplit = (int)std::min<int64_t>(std::min<int64_t>(maxsplit, kcap / (4 * GK)), std::max<int64_t>(1, target / tiles));
     while (ksplit > 1 && (int64_t)ksplit * tiles * GT * GT > ws_elems) --ksplit;
   }
   prof_begin(s);

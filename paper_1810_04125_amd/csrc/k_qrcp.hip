@@ -629,7 +629,8 @@ void run_qrcp(QrcpTask* tasks, int32_t ntasks, const QrcpWork& wk, const int2* w
               hipStream_t s, unsigned long long* kcnt, bool solve_e, double* gws, const IdBlockWork* bw) {
   if (ntasks <= 0) return;
   if (ntasks > wk.max_tasks) throw Error(HSS_ERR_INTERNAL, "QRCP work map too small for the batch");
-  const int nwg = 2 * kQrcpTarget + ntasks;
+  const int target = tune().qrcp_wg;   // kQrcpTarget by default
+  const int nwg = 2 * target + ntasks;
   const size_t lds = (size_t)std::max(dmax, 1) * sizeof(double);
   // The ID first counts its active panels (and finds the tall ones): with
   // none it is done, and the count picks the factorization kernel.
@@ -659,7 +660,7 @@ void run_qrcp(QrcpTask* tasks, int32_t ntasks, const QrcpWork& wk, const int2* w
     prof_end(HSS_K_QRCP_WG, s);
   } else {
     prof_begin(s);
-    hipLaunchKernelGGL(k_qrcp_plan, dim3(1), dim3(QB), 0, s, tasks, ntasks, kQrcpTarget, wk.chunks, wk.meta);
+    hipLaunchKernelGGL(k_qrcp_plan, dim3(1), dim3(QB), 0, s, tasks, ntasks, target, wk.chunks, wk.meta);
     hipLaunchKernelGGL(k_qrcp_init, dim3(nwg), dim3(QB), 0, s, tasks, wk.chunks, wk.meta, wk.kbuf);
     prof_end(HSS_K_QRCP_OTHER, s);
     if (solve_e && dmax >= 128) run_qr_first(tasks, ntasks, dmax, ncols_max, sc, gtasks, gws, s, kcnt);

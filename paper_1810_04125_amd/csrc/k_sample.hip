@@ -256,7 +256,7 @@ int sample_splits(int64_t n, int32_t ncols) {
   const int64_t gx = (n + SM_ROWS - 1) / SM_ROWS;
   const int64_t gy = (ncols + SM_COLS - 1) / SM_COLS;
   const int64_t tiles = gx * gy;
-  const int64_t target = 2048;
+  const int64_t target = tune().sample_wg;   // 2048 by default
   int64_t z = (target + tiles - 1) / tiles;
   const int64_t zmax = (n + 255) / 256;   // at least 256 K rows per split
   if (z > zmax) z = zmax;

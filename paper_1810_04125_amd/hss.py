@@ -132,7 +132,8 @@ EXPORTS = ["hss_tree_build", "hss_tree_free", "hss_compress", "hss_compress_batc
            "hss_matvec", "hss_rel_error", "hss_get_info", "hss_get_node_info", "hss_copy_node",
            "hss_sample", "hss_extract", "hss_interpolative_batched", "hss_last_error", "hss_version",
            "hss_get_kernel_stats", "hss_release_cache", "hss_mlp_num_params", "hss_mlp_forward", "hss_mlp_gradient",
-           "hss_mlp_adam", "hss_mlp_train", "hss_random_normal", "hss_random_words", "hss_matvec_noalloc"]
+           "hss_mlp_adam", "hss_mlp_train", "hss_random_normal", "hss_random_words", "hss_matvec_noalloc",
+           "hss_default_tunables", "hss_load_tunables", "hss_lookup_tunables"]
 
 MLP_MAX_LAYERS = 6
 
@@ -550,6 +551,35 @@ def compress_batched(gens, trees, Rs, **kw):
 def release_cache():
     """Free the device memory kept between compressions (hss_release_cache)."""
     _check(lib().hss_release_cache())
+
+
+class _Tunables(C.Structure):
+    _fields_ = [("gemm_wg", C.c_int32), ("gemm_max_split", C.c_int32), ("sample_wg", C.c_int32),
+                ("qrcp_wg", C.c_int32)]
+
+
+QRCP_WG_MAX = 4096   # HSS_QRCP_WG_MAX
+
+
+def default_tunables() -> dict:
+    """The built-in launch-shape tunables (hss_default_tunables)."""
+    t = _Tunables()
+    _check(lib().hss_default_tunables(C.byref(t)))
+    return {k: getattr(t, k) for k, _ in _Tunables._fields_}
+
+
+def load_tunables(path):
+    """Load (path) or clear (None) the tunables table (hss_load_tunables)."""
+    _check(lib().hss_load_tunables(path.encode() if path else None))
+
+
+def lookup_tunables(arch, family, precision, n) -> dict:
+    """The tunables a compression with this key takes (hss_lookup_tunables)."""
+    t = _Tunables()
+    _check(lib().hss_lookup_tunables(arch.encode(), FAMILY[family] if isinstance(family, str) else family,
+                                     PRECISION[precision] if isinstance(precision, str) else precision,
+                                     int(n), C.byref(t)))
+    return {k: getattr(t, k) for k, _ in _Tunables._fields_}
 
 
 # --------------------------------------------------------------------------- single steps

@@ -101,6 +101,7 @@ def generate(count, seed, chunk=48, delta_d=64, eta=0.05, d_max=4096, log=print,
     training set as a dict of arrays."""
     specs = inputs.learned_problems(count, seed, n_lo, n_hi)
     X, T, M = [], [], []
+    dropped = 0
     meta = {k: [] for k in ("family", "n", "leaf", "param", "rtol", "d_final", "rounds", "status", "max_rank")}
     t0 = time.time()
     for c0 in range(0, count, chunk):
@@ -112,6 +113,9 @@ def generate(count, seed, chunk=48, delta_d=64, eta=0.05, d_max=4096, log=print,
                                      d_max=[min(d_max, s["n"]) for s in part], seed=seed + 1)
         for s, (gen, tree), H in zip(part, probs, Hs):
             info = H.info()
+            if info["status"] == hss.NOT_CONVERGED:   # d_final capped at d_max: no label
+                dropped += 1
+                continue
             lr = np.zeros(int(tree.level.max()) + 1)
             for node in range(tree.num_nodes):
                 ni = H.node_info(node)
@@ -126,7 +130,8 @@ def generate(count, seed, chunk=48, delta_d=64, eta=0.05, d_max=4096, log=print,
                          ("rounds", info["rounds"]), ("status", info["status"]), ("max_rank", lr.max())):
                 meta[k].append(v)
         del Hs, probs
-        log("generate: %d / %d problems, %.1f s" % (min(count, c0 + chunk), count, time.time() - t0))
+        log("generate: %d / %d problems (%d not converged, left out), %.1f s"
+            % (min(count, c0 + chunk), count, dropped, time.time() - t0))
     out = {"X": np.array(X, np.float32), "T": np.array(T, np.float32), "M": np.array(M, np.float32)}
     out.update({"p_" + k: np.array(v) for k, v in meta.items()})
     out["p_eta"] = np.array([eta])
@@ -244,6 +249,7 @@ def _main():
     g.add_argument("--merge-into", default=None,
                    help="an existing set: write it with the new problems interleaved (one after every k-th)")
     g.add_argument("--every", type=int, default=4)
+    g.add_argument("--chunk", type=int, default=48, help="problems per batched compression")
     c = sub.add_parser("curve", help="held-out error against the number of training problems")
     c.add_argument("--data", default=TRAIN_DATA)
     c.add_argument("--sizes", default="256,512,1024,2048,0")
@@ -260,7 +266,8 @@ def _main():
     a = ap.parse_args()
     log = lambda m: print(m, flush=True)
     if a.cmd == "generate":
-        d = generate(a.count, a.seed, eta=a.eta, log=log, n_lo=a.n_lo, n_hi=a.n_hi, d_max=a.d_max)
+        d = generate(a.count, a.seed, chunk=a.chunk, eta=a.eta, log=log, n_lo=a.n_lo, n_hi=a.n_hi,
+                     d_max=a.d_max)
         if a.merge_into:
             with np.load(a.merge_into, allow_pickle=False) as z:
                 d = merge({k: z[k] for k in z.files}, d, a.every)

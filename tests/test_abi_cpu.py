@@ -176,3 +176,42 @@ def test_compress_rejects_an_allocator_without_free():
     T = hss.Tree(64, 16)
     st, msg = _host_compress(T, allocator=half)
     assert st == -1 and "allocator" in msg
+
+
+def test_tunables_table_lookup_and_errors(tmp_path):
+    """The launch-shape table: a matching line by (arch, family, precision,
+    n range), the defaults otherwise, bad files rejected with the table
+    left as it was (host only)."""
+    d = hss.default_tunables()
+    assert d == {"gemm_wg": 2048, "gemm_max_split": 32, "sample_wg": 2048, "qrcp_wg": 1280}
+    good = tmp_path / "t.tune"
+    good.write_text("# arch family precision n_lo n_hi gemm_wg gemm_max_split sample_wg qrcp_wg\n"
+                    "gfx950 1 0 16384 32768 4096 16 1024 2560\n"
+                    "gfx950 1 0 32768 65536 1024 64 4096 640  # next bucket\n")
+    try:
+        hss.load_tunables(str(good))
+        assert hss.lookup_tunables("gfx950", "laplace", "fp64", 20000) == \
+            {"gemm_wg": 4096, "gemm_max_split": 16, "sample_wg": 1024, "qrcp_wg": 2560}
+        assert hss.lookup_tunables("gfx950", "laplace", "fp64", 32768)["qrcp_wg"] == 640
+        assert hss.lookup_tunables("gfx950", "laplace", "fp64", 65536) == d      # past the ranges
+        assert hss.lookup_tunables("gfx950", "toeplitz", "fp64", 20000) == d     # other family
+        assert hss.lookup_tunables("gfx950", "laplace", "fp32", 20000) == d      # other precision
+        assert hss.lookup_tunables("gfx942", "laplace", "fp64", 20000) == d      # other device
+        for text in ("gfx950 1 0 16384 32768 4096 16 1024\n",                   # 8 fields
+                     "gfx950 1 0 16384 32768 4096 16 1024 9999\n",              # qrcp_wg > HSS_QRCP_WG_MAX
+                     "gfx950 1 0 32768 16384 4096 16 1024 1280\n"):             # empty n range
+            bad = tmp_path / "bad.tune"
+            bad.write_text(text)
+            with pytest.raises(hss.HSSError):
+                hss.load_tunables(str(bad))
+            assert hss.lookup_tunables("gfx950", "laplace", "fp64", 20000)["gemm_wg"] == 4096   # unchanged
+        with pytest.raises(hss.HSSError):
+            hss.load_tunables(str(tmp_path / "missing.tune"))
+    finally:
+        hss.load_tunables(None)
+    assert hss.lookup_tunables("gfx950", "laplace", "fp64", 20000) == d
+
+
+def test_qrcp_wg_max_matches_the_header():
+    src = open(os.path.join(ROOT, "include", "hss.h")).read()
+    assert int(re.search(r"#define HSS_QRCP_WG_MAX (\d+)", src).group(1)) == hss.QRCP_WG_MAX
