@@ -224,7 +224,7 @@ struct TuneScope {
 hss_tunables tunables_for(int32_t family, int32_t precision, int64_t n);   // device 0 of the current context
 // Block-pivoted ID (k_idblock.hip): per task, a slot of workspace sized
 // from its capacities (panel rows dcap, columns mcap).
-constexpr int kIdbCmax = 128;   // candidate columns per block (their Gram matrix fits in LDS)
+constexpr int kIdbCmax = 256;   // candidate columns per block
 constexpr int kIdbLmax = 32;    // pivots per block at most
 constexpr int kIdbMaxM = 16384; // panel columns the selection kernel stages in LDS (larger: one-step path)
 constexpr int kIdbRows = 256;   // panel rows per workgroup of the block's row kernels

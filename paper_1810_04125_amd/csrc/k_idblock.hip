@@ -6,14 +6,13 @@
 // the threshold.  A step needs the residual norms of all remaining columns,
 // so a plain implementation reads the whole trailing panel once per pivot.
 // Here the pivots are found in blocks, with the same choices:
-//   1. candidates (k_idb_select, k_idb_gather): the c remaining columns of
-//      largest residual norm (ties to the lower index); `bound` is the
+//   1. candidates (k_idb_select, k_idb_gather): the c = 256 remaining
+//      columns of largest residual norm (ties to the lower index); `bound` is the
 //      largest norm among the others, and no residual norm ever grows, so
 //      while the best candidate's residual is at least `bound`, it is the
 //      column the one-step method would pick;
 //   2. their Gram matrix G = C^T C (C = candidates' residual columns, FP64
-//      matrix cores) and its pivoted Cholesky factorization in LDS
-//      (k_idb_chol), which yields the candidates' residual norms after each
+//      matrix cores) and its pivoted Cholesky factorization (k_idb_chol), which yields the candidates' residual norms after each
 //      pivot (the Schur complement's diagonal): pivots are taken while the
 //      best one beats `bound`, until the threshold stops the factorization,
 //      or until the residuals fall 1e5-fold within the block (their
@@ -340,14 +339,16 @@ __global__ __launch_bounds__(256) void k_idb_gather(const QrcpTask* __restrict__
   for (int i = blockIdx.x * 256 + threadIdx.x; i < nr; i += gridDim.x * 256) dst[i] = src[i];
 }
 
-// Step 2: pivoted Cholesky of the candidates' Gram matrix, left-looking (the
-// Gram matrix packed in LDS, the Cholesky rows of the pivots taken beside
-// it): the block's pivots and the stopping decision, and R1 of the pivot
-// columns (C_P = Q1 R1).  One workgroup per task loads the Gram matrix; its
-// first wave factors (lane l: candidates l and l + 64), with no barriers.
+// Step 2: pivoted Cholesky of the candidates' Gram matrix, left-looking:
+// the block's pivots and the stopping decision, and R1 of the pivot
+// columns (C_P = Q1 R1).  The first wave factors (lane l: candidates l,
+// l + 64, ...), with no barriers; each step reads the pivot's row of the
+// Gram matrix from global memory (it stays in the L2 of the compute unit's
+// die after the first steps touch it) and the Cholesky entries from LDS.
 __global__ __launch_bounds__(PCT) void k_idb_chol(const QrcpTask* __restrict__ tasks, IdBlk* __restrict__ blks) {
-  static_assert(kIdbCmax == 128, "two candidates per lane");
-  extern __shared__ double G[];
+  constexpr int CPL = kIdbCmax / 64;   // candidates per lane
+  static_assert(kIdbCmax % 64 == 0 && kIdbCmax <= 256, "whole lanes; an 8-bit index in the pivot key");
+  extern __shared__ double Ls[];
   __shared__ int piv[kIdbLmax];
   __shared__ double spv[kIdbLmax];
   const int ti = blockIdx.x;
@@ -359,50 +360,29 @@ __global__ __launch_bounds__(PCT) void k_idb_chol(const QrcpTask* __restrict__ t
   if (nc <= 0) return;
   const int m = t.m, d = t.d, k = B.k, cm = B.cmax;
   // per-candidate entries of rows q, q + 1 (q even) side by side: entry (q, a)
-  // at (q / 2) 2 kIdbCmax + 2 a + q % 2, so that a lane's pair and the
-  // pivot's pair are 16-byte loads without bank conflicts
-  constexpr int LQ = kIdbLmax + 2;
-  double* Lc = G;                                 // l(q, a)
-  double* Gp = G + kIdbCmax * LQ;                 // upper triangle, column by column
-  {
-    double* Lu0 = Gp + kIdbCmax * (kIdbCmax + 1) / 2;
-    for (int e = tid; e < kIdbCmax * LQ; e += PCT) { Lc[e] = 0.0; Lu0[e] = 0.0; }
-    const HSS_GLOBAL double* Gg = gview(B.G);
-    const int np = nc * (nc + 1) / 2;
-    constexpr int kU = 11;   // loads in flight per thread
-    for (int e0 = 0; e0 < np; e0 += kU * PCT) {
-      double v[kU];
-#pragma unroll
-      for (int u = 0; u < kU; ++u) {   // packed entry e = b (b + 1) / 2 + a, a <= b
-        const int e = e0 + tid + u * PCT;
-        v[u] = 0.0;
-        if (e < np) {
-          int b = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
-          if ((b + 1) * (b + 2) / 2 <= e) ++b;
-          if (b * (b + 1) / 2 > e) --b;
-          v[u] = Gg[(e - b * (b + 1) / 2) + (int64_t)b * cm];
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < kU; ++u) {
-        const int e = e0 + tid + u * PCT;
-        if (e < np) Gp[e] = v[u];
-      }
-    }
-  }
+  // at (q / 2) PR + 2 a + q % 2, so that a lane's pair and the pivot's pair
+  // are 16-byte loads without bank conflicts.  LDL^T form: Lu holds
+  // u(q, a), the Schur complement entry of pivot q in column a; Lc holds
+  // l(q, a) = u(q, a) / s_q with s_q the pivot's residual; the Cholesky
+  // factor is l(q, a) sqrt(s_q).  Rows >= i are zero.
+  constexpr int PR = 2 * kIdbCmax;
+  double* Lc = Ls;
+  double* Lu = Ls + (kIdbLmax / 2) * PR;
+  for (int e = tid; e < kIdbLmax * PR; e += PCT) Ls[e] = 0.0;
   __syncthreads();
   if (tid >= 64) return;
+  const HSS_GLOBAL double* Gg = gview(B.G);
   QrcpCtlB* ctl = ctlb(t);
   const double bound = B.bound;
-  const int a0 = lane, a1 = lane + 64;
-  bool c0 = a0 >= nc, c1 = a1 >= nc;   // taken as a pivot, or past the candidates
-  double sd0 = c0 ? 0.0 : Gp[a0 * (a0 + 1) / 2 + a0];
-  double sd1 = c1 ? 0.0 : Gp[a1 * (a1 + 1) / 2 + a1];
-  // LDL^T form: u(q, a) = the Schur complement entry of pivot q in column a,
-  // l(q, a) = u(q, a) / s_q with s_q the pivot's residual, both in LDS by
-  // candidate (the entries of rows >= i are zero); the Cholesky factor is
-  // l(q, a) sqrt(s_q).  The tests compare squared norms.
-  double* Lu = Gp + kIdbCmax * (kIdbCmax + 1) / 2;   // kIdbCmax x LQ
+  int au[CPL];
+  bool cu[CPL];     // taken as a pivot, or past the candidates
+  double sd[CPL];   // residual of each of this lane's candidates
+#pragma unroll
+  for (int u = 0; u < CPL; ++u) {
+    au[u] = lane + 64 * u;
+    cu[u] = au[u] >= nc;
+    sd[u] = cu[u] ? 0.0 : Gg[au[u] + (int64_t)au[u] * cm];
+  }
   double s0 = 0.0;
   double nu1 = ctl->nu1;
   const int kmax = min(m, d);
@@ -410,22 +390,33 @@ __global__ __launch_bounds__(PCT) void k_idb_chol(const QrcpTask* __restrict__ t
   const double hmt_c = t.hmt_mn > 0.0 ? 4.0 * sqrt((double)d) * sqrt(t.hmt_mn) : 0.0;
   const double bound2 = bound >= 0.0 ? bound * bound : -1.0;
   double thr2_l = 0.0;   // lane i: the squared threshold of pivot k + i
+  // the pivot: the largest residual, by a key that keeps the residual's top
+  // 56 bits (a relative 2^-44) and prefers the lower index among equal keys;
+  // its exact residual comes from the lane that holds it.  The next pivot
+  // is found as soon as the residuals are updated, and its row of G is
+  // loaded while the entries of its Cholesky column are read from LDS.
   int L = 0;
   bool stop = false;
 #pragma unroll 1
   for (int i = 0; i < lcap; ++i) {
     // the pivot: the largest residual, by a key that keeps the residual's
-    // top 57 bits (a relative 2^-45) and prefers the lower index among equal
+    // top 56 bits (a relative 2^-44) and prefers the lower index among equal
     // keys; its exact residual comes from the lane that holds it
-    const auto key = [](double v, int a, bool taken) -> uint64_t {
-      if (taken) return 0;
-      const uint64_t hb = ((uint64_t)__double_as_longlong(fmax(v, 0.0)) >> 7) + 1;
-      return (hb << 7) | (uint64_t)(127 - a);
-    };
-    const uint64_t k0 = key(sd0, a0, c0), k1 = key(sd1, a1, c1);
-    const uint64_t kb = wave_max_u64(k0 > k1 ? k0 : k1);
-    const int p = 127 - (int)(kb & 127);
-    const double sp = readlane_d(p < 64 ? sd0 : sd1, p & 63);
+    uint64_t kl = 0;
+#pragma unroll
+    for (int u = 0; u < CPL; ++u) {
+      if (cu[u]) continue;
+      const uint64_t hb = ((uint64_t)__double_as_longlong(fmax(sd[u], 0.0)) >> 8) + 1;
+      const uint64_t key = (hb << 8) | (uint64_t)(255 - au[u]);
+      kl = key > kl ? key : kl;
+    }
+    const uint64_t kb = wave_max_u64(kl);
+    const int p = 255 - (int)(kb & 255);
+    double own = sd[0];
+#pragma unroll
+    for (int u = 1; u < CPL; ++u)
+      if ((p >> 6) == u) own = sd[u];
+    const double sp = readlane_d(own, p & 63);
     const double spp = fmax(sp, 0.0);
     if (i == 0) {
       s0 = sp;
@@ -443,33 +434,38 @@ __global__ __launch_bounds__(PCT) void k_idb_chol(const QrcpTask* __restrict__ t
     if (i > 0 && sp < 1e-10 * s0) break;     // Gram-derived residuals lose accuracy below this
     const double inv = sp >= 1e-290 ? rcp_nr(sp) : 1.0 / sp;
     // u_a = G(p, a) - sum_q u(q, a) l(q, p)
-    double g0 = 0.0, g1 = 0.0;
-    if (!c0) g0 = a0 <= p ? Gp[p * (p + 1) / 2 + a0] : Gp[a0 * (a0 + 1) / 2 + p];
-    if (!c1) g1 = a1 <= p ? Gp[p * (p + 1) / 2 + a1] : Gp[a1 * (a1 + 1) / 2 + p];
-    double h0 = 0.0, h1 = 0.0;
+    double g[CPL], h[CPL];
+#pragma unroll
+    for (int u = 0; u < CPL; ++u) {
+      g[u] = cu[u] ? 0.0 : Gg[au[u] + (int64_t)p * cm];
+      h[u] = 0.0;
+    }
     for (int q0 = 0; q0 < i; q0 += 8) {   // rows >= i are zero: whole chunks of 8 rows
 #pragma unroll
       for (int q = q0; q < q0 + 8; q += 2) {
-        const int row = (q >> 1) * 2 * kIdbCmax;
+        const int row = (q >> 1) * PR;
         const double2 w = *reinterpret_cast<const double2*>(Lc + row + 2 * p);
-        const double2 x0 = *reinterpret_cast<const double2*>(Lu + row + 2 * a0);
-        const double2 x1 = *reinterpret_cast<const double2*>(Lu + row + 2 * a1);
-        g0 -= x0.x * w.x;
-        h0 -= x0.y * w.y;
-        g1 -= x1.x * w.x;
-        h1 -= x1.y * w.y;
+#pragma unroll
+        for (int u = 0; u < CPL; ++u) {
+          const double2 x = *reinterpret_cast<const double2*>(Lu + row + 2 * au[u]);
+          g[u] -= x.x * w.x;
+          h[u] -= x.y * w.y;
+        }
       }
     }
-    const double ua0 = c0 ? 0.0 : g0 + h0, ua1 = c1 ? 0.0 : g1 + h1;
-    const double l0 = ua0 * inv, l1 = ua1 * inv;
     wave_sync();   // every lane has read the pivot's entries
-    const int wi = (i >> 1) * 2 * kIdbCmax + (i & 1);
-    Lc[wi + 2 * a0] = l0;
-    Lc[wi + 2 * a1] = l1;
-    Lu[wi + 2 * a0] = ua0;
-    Lu[wi + 2 * a1] = ua1;
-    if (!c0) { if (a0 == p) c0 = true; else sd0 -= ua0 * l0; }
-    if (!c1) { if (a1 == p) c1 = true; else sd1 -= ua1 * l1; }
+    const int wi = (i >> 1) * PR + (i & 1);
+#pragma unroll
+    for (int u = 0; u < CPL; ++u) {
+      const double ua = cu[u] ? 0.0 : g[u] + h[u];
+      const double l = ua * inv;
+      Lc[wi + 2 * au[u]] = l;
+      Lu[wi + 2 * au[u]] = ua;
+      if (!cu[u]) {
+        if (au[u] == p) cu[u] = true;
+        else sd[u] -= ua * l;
+      }
+    }
     if (lane == 0) { piv[i] = p; spv[i] = spp; }
     wave_sync();
     L = i + 1;
@@ -479,7 +475,7 @@ __global__ __launch_bounds__(PCT) void k_idb_chol(const QrcpTask* __restrict__ t
     const int a = e / kIdbLmax, b = e % kIdbLmax;
     double v = 0.0;
     if (a < L && b < L && a <= b)
-      v = a == b ? sqrt(spv[a]) : Lc[(a >> 1) * 2 * kIdbCmax + 2 * piv[b] + (a & 1)] * sqrt(spv[a]);
+      v = a == b ? sqrt(spv[a]) : Lc[(a >> 1) * PR + 2 * piv[b] + (a & 1)] * sqrt(spv[a]);
     B.F[e] = v;
   }
   if (lane < L) B.piv[lane] = piv[lane];
@@ -881,7 +877,7 @@ void run_id_blocks(QrcpTask* tasks, int32_t ntasks, const IdBlockWork& bw, int32
   hipLaunchKernelGGL(k_idb_start, dim3((ntasks + 127) / 128), dim3(128), 0, s, tasks, bw.blk, ntasks);
   const int cm = kIdbCmax;
   // dynamic LDS: Cholesky rows + packed Gram (k_idb_chol); Q1 rows (k_idb_rows1)
-  constexpr size_t kLdsChol = sizeof(double) * (2 * (size_t)(kIdbLmax + 2) * kIdbCmax + (size_t)kIdbCmax * (kIdbCmax + 1) / 2);
+  constexpr size_t kLdsChol = sizeof(double) * 2 * (size_t)kIdbLmax * kIdbCmax;   // Lc and Lu
   constexpr size_t kLdsRows = sizeof(double) * (size_t)kIdbRows * kIdbLmax;
   static_assert(kLdsChol <= 160 * 1024 && kLdsRows <= 160 * 1024, "block ID LDS");
   static_assert(kLdsRows >= sizeof(double) * kGrp4 * kIdbPart, "group sums fit the rows' LDS");
