@@ -326,14 +326,17 @@ hss_status hss_compress_batched(int32_t count, const hss_generator* gens, const 
       HSS_HIP_CHECK(hipMemGetInfo(&free_b, &total_b));
       free_b += arena_idle_bytes();   // the cached transient block is reusable
       const size_t budget = std::min<size_t>((size_t)(0.6 * (double)free_b), (size_t)80 << 30);
-      size_t acc = 0;
+      size_t acc = 0, shared = 0;
       int32_t g1 = g0;
       while (g1 < count) {
-        const size_t b = Job::estimate_bytes(gens[g1], trees[g1], opts[g1]);
-        if (g1 > g0 && acc + b > budget) break;
+        size_t sh = 0;
+        const size_t b = Job::estimate_bytes(gens[g1], trees[g1], opts[g1], &sh);
+        if (g1 > g0 && acc + b + std::max(shared, sh) > budget) break;
         acc += b;
+        shared = std::max(shared, sh);
         ++g1;
       }
+      acc += shared;
       auto job = std::make_shared<Job>();
       // launch shapes from the tunables table (the group's first problem)
       const hss_tunables tv = tunables_for(gens[g0].family, opts[g0].sample_precision, gens[g0].n);

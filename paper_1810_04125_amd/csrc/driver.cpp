@@ -362,7 +362,7 @@ void Job::validate(const hss_generator& g, const hss_tree* t, const hss_options&
 // Device bytes one problem adds to a job (node pools, its share of the level
 // workspaces, global samples, generator tables), from the same capacities
 // setup() uses; the batched entry point groups problems by this estimate.
-size_t Job::estimate_bytes(const hss_generator& g, const hss_tree* t, const hss_options& o) {
+size_t Job::estimate_bytes(const hss_generator& g, const hss_tree* t, const hss_options& o, size_t* shared) {
   const int32_t nn = t->num_nodes;
   const int64_t dc = std::min<int64_t>(o.d_max, t->n);
   const bool sym = gen_symmetric(g);
@@ -391,8 +391,9 @@ size_t Job::estimate_bytes(const hss_generator& g, const hss_tree* t, const hss_
   dbl += nsides * align8(t->n * dc) + 8 * t->n;
   if (!o.R) dbl += align8(t->n * dc);   // R drawn by the library
   dbl += *std::max_element(wsa.begin(), wsa.end()) + *std::max_element(wsb.begin(), wsb.end());
-  dbl += (int64_t)sample_partial_elems(t->n, (int32_t)dc);
-  dbl += kGemmSplitElems;
+  // one split-K partial buffer and one GEMM split workspace serve the whole
+  // job (sized for its largest problem)
+  *shared = 8 * (sample_partial_elems(t->n, (int32_t)dc) + (size_t)kGemmSplitElems);
   {
     // block-ID slots of the largest level
     std::vector<int64_t> ld(maxlev + 1, 0), li(maxlev + 1, 0);

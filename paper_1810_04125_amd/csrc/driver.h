@@ -114,7 +114,10 @@ struct Job {
   void compact_e();
   void setup(int32_t count, const hss_generator* gens, const hss_tree* const* trees,
              const hss_options* opts);
-  static size_t estimate_bytes(const hss_generator& g, const hss_tree* t, const hss_options& o);
+  // Device bytes of one problem in a job; *shared: bytes of the buffers one
+  // job keeps for all of its problems, sized by this problem (the job
+  // allocates their maximum once).
+  static size_t estimate_bytes(const hss_generator& g, const hss_tree* t, const hss_options& o, size_t* shared);
   // Host-only checks of one problem's arguments (no HIP call): throws
   // HSS_ERR_INVALID_ARG naming problem k.
   static void validate(const hss_generator& g, const hss_tree* t, const hss_options& o, int k);

@@ -343,7 +343,6 @@ void launch_permute_points(const double* pts, const int64_t* perm, int64_t n, do
                            hipStream_t s);
 // Sampling: S(:, 0:ncols) = op(A_hat) R(:, 0:ncols); `partial` is workspace of
 // partial_cap doubles for the split-K partial sums.
-int sample_splits(int64_t n, int32_t ncols);
 size_t sample_partial_elems(int64_t n, int32_t ncols);
 void launch_sample(const GenDev& g, int32_t transpose, int32_t precision, const double* R,
                    int64_t ldr, double* S, int64_t lds, int32_t ncols, double* partial,

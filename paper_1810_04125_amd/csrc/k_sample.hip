@@ -6,10 +6,12 @@
 // matrix core.  One workgroup = 4 waves computes a 128 x 64 tile of S
 // (each wave 32 rows x 64 columns = eight 16x16 FP64 MFMA blocks), so every
 // generated entry is reused for 64 columns of R and every value of R read
-// from LDS for two row blocks.  R tiles are staged in LDS and shared by
-// the 4 waves.  The K dimension (n) is split over
-// blockIdx.z when the tile grid alone would not fill the 256 CUs; split
-// partial sums are reduced in fixed order, so results are deterministic.
+// from LDS for two row blocks.  With 128 or more columns the Toeplitz and
+// Gaussian kernels take wider tiles that reuse each entry for 128 columns
+// (see sample_tile).  R tiles are staged in LDS and shared by the 4 waves.
+// The K dimension (n) is split over blockIdx.z when the tile grid alone
+// would not fill the 256 CUs; split partial sums are reduced in fixed
+// order, so results are deterministic.
 
 #include <algorithm>
 
@@ -19,11 +21,11 @@ namespace hss {
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
-constexpr int SM_ROWS = 128;   // rows of S per workgroup
+constexpr int SM_ROWS = 128;   // rows of S per workgroup (narrow tile)
 constexpr int SM_T = 256;      // threads per workgroup: 4 waves of 32 rows
-constexpr int SM_COLS = 64;    // columns of S per workgroup
+constexpr int SM_COLS = 64;    // columns of S per workgroup (narrow tile)
+constexpr int SM_COLS_W = 128; // wide tile
 constexpr int SM_BK = 32;      // K rows of R staged per LDS tile
-constexpr int SM_LDP = SM_COLS + 2;
 
 __global__ void k_toeplitz_table(double* __restrict__ t, int64_t n, double h) {
   int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -80,35 +82,42 @@ __device__ __forceinline__ double entry_t(const GenDev& g, int64_t i, int64_t j)
 
 // out(row, col) for rows [0,n), cols [0, ncols): either S directly
 // (nsplit == 1, column-major with lds) or the split-K partial buffer
-// P[z][col][row]: split z's partial sums column-major, ncp = gridDim.y * SM_COLS
+// P[z][col][row]: split z's partial sums column-major, ncp = gridDim.y * COLS
 // columns of n rows each (the reduce then reads and writes along rows).
-template <int FAM, int TRANS>
+// Each wave computes NH x NCB blocks of 16 x 16: the workgroup's tile is
+// ROWS = 64 NH rows by COLS = 16 NCB columns, and each generated entry
+// feeds NCB MFMAs.
+template <int FAM, int TRANS, int NH, int NCB>
 __global__ __launch_bounds__(SM_T, 2) void k_sample_f64(GenDev g, const double* __restrict__ R,
                                                      int64_t ldr, double* __restrict__ out,
                                                      int64_t lds, int32_t ncols, int64_t kchunk,
                                                      int32_t nsplit) {
   constexpr bool PTS = FAM == HSS_FAM_LAPLACE || FAM == HSS_FAM_GAUSS;
-  __shared__ double Rs[SM_BK][SM_LDP];
+  constexpr int COLS = 16 * NCB;
+  constexpr int ROWS = 64 * NH;
+  __shared__ double Rs[SM_BK][COLS + 2];
   __shared__ double Ps[PTS ? SM_BK : 1][3];   // points of the K rows of the tile
   const int64_t n = g.n;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int64_t row0 = (int64_t)blockIdx.x * SM_ROWS + wave * 32;   // two 16-row blocks per wave
-  const int col0 = blockIdx.y * SM_COLS;
+  const int64_t row0 = (int64_t)blockIdx.x * ROWS + wave * 16 * NH;   // NH 16-row blocks per wave
+  const int col0 = blockIdx.y * COLS;
   const int64_t kb = (int64_t)blockIdx.z * kchunk;
   const int64_t ke = min(n, kb + kchunk);
-  int64_t my_row[2];
-  bool row_ok[2];
+  int64_t my_row[NH];
+  bool row_ok[NH];
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
+  for (int h = 0; h < NH; ++h) {
     my_row[h] = row0 + 16 * h + (lane & 15);
     row_ok[h] = my_row[h] < n;
   }
   const int kq = lane >> 4;
-  double px[2] = {0.0, 0.0}, py[2] = {0.0, 0.0}, pz[2] = {0.0, 0.0};   // this lane's row points
+  double px[NH], py[NH], pz[NH];   // this lane's row points
+#pragma unroll
+  for (int h = 0; h < NH; ++h) px[h] = py[h] = pz[h] = 0.0;
   if constexpr (PTS) {
 #pragma unroll
-    for (int h = 0; h < 2; ++h)
+    for (int h = 0; h < NH; ++h)
       if (row_ok[h]) {
         px[h] = g.pts[3 * my_row[h]];
         py[h] = g.pts[3 * my_row[h] + 1];
@@ -116,15 +125,15 @@ __global__ __launch_bounds__(SM_T, 2) void k_sample_f64(GenDev g, const double* 
       }
   }
 
-  dbl4 acc[2][4];
+  dbl4 acc[NH][NCB];
 #pragma unroll
-  for (int h = 0; h < 2; ++h)
+  for (int h = 0; h < NH; ++h)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) acc[h][c] = dbl4{0.0, 0.0, 0.0, 0.0};
+    for (int c = 0; c < NCB; ++c) acc[h][c] = dbl4{0.0, 0.0, 0.0, 0.0};
 
-  // R(kt:kt+BK, col0:col0+64) and the tile's points are loaded into
+  // R(kt:kt+BK, col0:col0+COLS) and the tile's points are loaded into
   // registers one tile ahead, then stored to LDS (Rs[k][c], Ps[k][xyz])
-  constexpr int RPT = SM_BK * SM_COLS / SM_T;
+  constexpr int RPT = SM_BK * COLS / SM_T;
   double rr[RPT];
   double pp = 0.0;
   auto load_tile = [&](int64_t kt) {
@@ -144,7 +153,7 @@ __global__ __launch_bounds__(SM_T, 2) void k_sample_f64(GenDev g, const double* 
     }
   };
   if (kb < ke) load_tile(kb);
-  const int64_t rb0 = (int64_t)blockIdx.x * SM_ROWS, rb1 = rb0 + SM_ROWS;   // rows of the workgroup
+  const int64_t rb0 = (int64_t)blockIdx.x * ROWS, rb1 = rb0 + ROWS;   // rows of the workgroup
   for (int64_t kt = kb; kt < ke; kt += SM_BK) {
 #pragma unroll
     for (int e = 0; e < RPT; ++e) {
@@ -165,19 +174,20 @@ __global__ __launch_bounds__(SM_T, 2) void k_sample_f64(GenDev g, const double* 
 #pragma unroll
       for (int kk = 0; kk < SM_BK; kk += 4) {
         const double qx = Ps[kk + kq][0], qy = Ps[kk + kq][1], qz = Ps[kk + kq][2];
-        double a[2];
+        double a[NH];
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
+        for (int h = 0; h < NH; ++h) {
           const double dx = px[h] - qx, dy = py[h] - qy, dz = pz[h] - qz;
           const double r2 = dx * dx + dy * dy + dz * dz;
           if constexpr (FAM == HSS_FAM_LAPLACE) a[h] = kInv4Pi * rsqrt_nr(r2);
           else a[h] = exp(-r2 * g.inv2s2);
         }
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
+        for (int c = 0; c < NCB; ++c) {
           const double b = Rs[kk + kq][c * 16 + (lane & 15)];
-          acc[0][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[0], b, acc[0][c], 0, 0, 0);
-          acc[1][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[1], b, acc[1][c], 0, 0, 0);
+#pragma unroll
+          for (int h = 0; h < NH; ++h)
+            acc[h][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[h], b, acc[h][c], 0, 0, 0);
         }
       }
       __syncthreads();
@@ -186,9 +196,9 @@ __global__ __launch_bounds__(SM_T, 2) void k_sample_f64(GenDev g, const double* 
 #pragma unroll 2
     for (int kk = 0; kk < SM_BK; kk += 4) {
       const int64_t j = kt + kk + kq;
-      double a[2];
+      double a[NH];
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
+      for (int h = 0; h < NH; ++h) {
         const bool ok = row_ok[h] && j < ke;
         if constexpr (PTS) {
           // symmetric kernels: the transposed product reads the same entries;
@@ -212,19 +222,20 @@ __global__ __launch_bounds__(SM_T, 2) void k_sample_f64(GenDev g, const double* 
         }
       }
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
+      for (int c = 0; c < NCB; ++c) {
         const double b = Rs[kk + kq][c * 16 + (lane & 15)];
-        acc[0][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[0], b, acc[0][c], 0, 0, 0);
-        acc[1][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[1], b, acc[1][c], 0, 0, 0);
+#pragma unroll
+        for (int h = 0; h < NH; ++h)
+          acc[h][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[h], b, acc[h][c], 0, 0, 0);
       }
     }
     __syncthreads();
   }
   // FP64 16x16x4 result layout: D[i][j] with i = 4*v + lane/16, j = lane % 16
 #pragma unroll
-  for (int h = 0; h < 2; ++h)
+  for (int h = 0; h < NH; ++h)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
+    for (int c = 0; c < NCB; ++c) {
       const int gc = col0 + c * 16 + (lane & 15);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
@@ -233,7 +244,7 @@ __global__ __launch_bounds__(SM_T, 2) void k_sample_f64(GenDev g, const double* 
         if (nsplit == 1) {
           out[(int64_t)gc * lds + gr] = acc[h][c][v];
         } else {
-          const int64_t ncp = (int64_t)gridDim.y * SM_COLS;
+          const int64_t ncp = (int64_t)gridDim.y * COLS;
           out[((int64_t)blockIdx.z * ncp + gc) * n + gr] = acc[h][c][v];
         }
       }
@@ -252,9 +263,24 @@ __global__ void k_splitk_reduce(const double* __restrict__ P, int64_t n, int32_t
   S[col * lds + row] = s;
 }
 
-int sample_splits(int64_t n, int32_t ncols) {
-  const int64_t gx = (n + SM_ROWS - 1) / SM_ROWS;
-  const int64_t gy = (ncols + SM_COLS - 1) / SM_COLS;
+// Workgroup tile of the FP64 kernels: 128 x 64 (two row blocks and four
+// column blocks per wave), or for large problems where the column count
+// allows, 64 x 128 for the Gaussian kernel
+// (one row block and eight column blocks per wave: half the entries per
+// MFMA in the same registers; its exponential is the costliest entry) and
+// 128 x 128 for Toeplitz (its table gathers leave registers for two row
+// blocks).  The Laplace kernel keeps the narrow tile: its entries are
+// cheap enough that the wide tile's doubled LDS reads per MFMA cancel the
+// saving.
+struct SampleTile {
+  int32_t rows, cols;
+};
+constexpr SampleTile kTileNarrow{SM_ROWS, SM_COLS}, kTileWideGauss{SM_ROWS / 2, SM_COLS_W},
+    kTileWideToep{SM_ROWS, SM_COLS_W};
+
+static int sample_splits(int64_t n, int32_t ncols, SampleTile t) {
+  const int64_t gx = (n + t.rows - 1) / t.rows;
+  const int64_t gy = (ncols + t.cols - 1) / t.cols;
   const int64_t tiles = gx * gy;
   const int64_t target = tune().sample_wg;   // 2048 by default
   int64_t z = (target + tiles - 1) / tiles;
@@ -264,29 +290,69 @@ int sample_splits(int64_t n, int32_t ncols) {
   return (int)z;
 }
 
-// Partial-sum capacity covering every column count up to ncols_max (the split
-// count is not monotone in the column count, so take the maximum).
+static SampleTile sample_tile(int32_t precision, int32_t family, int64_t n, int32_t ncols) {
+  // the wide tiles where they leave at most half a narrow tile's columns
+  // idle (192 columns: three narrow tiles beat two wide ones)
+  if (precision != HSS_SAMPLE_FP64 || ncols < SM_COLS_W) return kTileNarrow;
+  const int32_t r = ncols % SM_COLS_W;
+  if (r != 0 && r <= SM_COLS) return kTileNarrow;
+  SampleTile t = kTileNarrow;
+  if (family == HSS_FAM_TOEPLITZ) t = kTileWideToep;
+  else if (family == HSS_FAM_GAUSS) t = kTileWideGauss;
+  else return kTileNarrow;
+  // only where the wide grid fills the device with at most four K splits:
+  // with fewer tiles, the split count that restores the workgroup count
+  // multiplies the split-K partial sums written and read (at n = 16384 the
+  // wide Toeplitz tile ran slower than the narrow one)
+  const int64_t tiles = ((n + t.rows - 1) / t.rows) * ((ncols + t.cols - 1) / t.cols);
+  return 4 * tiles >= tune().sample_wg ? t : kTileNarrow;
+}
+
+// Partial-sum capacity covering every column count up to ncols_max in
+// every tile shape (the split count is not monotone in the column count,
+// so take the maximum).
 size_t sample_partial_elems(int64_t n, int32_t ncols_max) {
   size_t best = 0;
-  const int64_t gymax = (ncols_max + SM_COLS - 1) / SM_COLS;
-  for (int64_t gy = 1; gy <= gymax; ++gy) {
-    const int z = sample_splits(n, (int32_t)(gy * SM_COLS));
-    if (z == 1) continue;
-    best = std::max(best, (size_t)z * (size_t)n * (size_t)(gy * SM_COLS));
+  for (const SampleTile t : {kTileNarrow, kTileWideGauss, kTileWideToep}) {
+    const int64_t gymax = (ncols_max + t.cols - 1) / t.cols;
+    for (int64_t gy = 1; gy <= gymax; ++gy) {
+      const int z = sample_splits(n, (int32_t)(gy * t.cols), t);
+      if (z == 1) continue;
+      best = std::max(best, (size_t)z * (size_t)n * (size_t)(gy * t.cols));
+    }
   }
   return best;
+}
+
+template <int FAM, int NH, int NCB>
+static void launch_fam(const GenDev& g, int transpose, const double* R, int64_t ldr, double* out,
+                       int64_t lds, int32_t ncols, int64_t kchunk, int nsplit, dim3 grid,
+                       hipStream_t s) {
+  if (transpose)
+    hipLaunchKernelGGL((k_sample_f64<FAM, 1, NH, NCB>), grid, dim3(SM_T), 0, s, g, R, ldr, out, lds,
+                       ncols, kchunk, nsplit);
+  else
+    hipLaunchKernelGGL((k_sample_f64<FAM, 0, NH, NCB>), grid, dim3(SM_T), 0, s, g, R, ldr, out, lds,
+                       ncols, kchunk, nsplit);
 }
 
 template <int FAM>
 static void launch_fam(const GenDev& g, int transpose, const double* R, int64_t ldr, double* out,
                        int64_t lds, int32_t ncols, int64_t kchunk, int nsplit, dim3 grid,
-                       hipStream_t s) {
-  if (transpose)
-    hipLaunchKernelGGL((k_sample_f64<FAM, 1>), grid, dim3(SM_T), 0, s, g, R, ldr, out, lds, ncols,
-                       kchunk, nsplit);
-  else
-    hipLaunchKernelGGL((k_sample_f64<FAM, 0>), grid, dim3(SM_T), 0, s, g, R, ldr, out, lds, ncols,
-                       kchunk, nsplit);
+                       SampleTile t, hipStream_t s) {
+  if constexpr (FAM == HSS_FAM_TOEPLITZ) {
+    if (t.cols == SM_COLS_W) {
+      launch_fam<FAM, 2, 8>(g, transpose, R, ldr, out, lds, ncols, kchunk, nsplit, grid, s);
+      return;
+    }
+  }
+  if constexpr (FAM == HSS_FAM_GAUSS) {
+    if (t.cols == SM_COLS_W) {
+      launch_fam<FAM, 1, 8>(g, transpose, R, ldr, out, lds, ncols, kchunk, nsplit, grid, s);
+      return;
+    }
+  }
+  launch_fam<FAM, 2, 4>(g, transpose, R, ldr, out, lds, ncols, kchunk, nsplit, grid, s);
 }
 
 void launch_sample_lp(const GenDev& g, int32_t transpose, int32_t bf16x3, const double* R, int64_t ldr,
@@ -351,11 +417,12 @@ void launch_sample(const GenDev& g, int32_t transpose, int32_t precision, const 
       sample_dense_gemm(g, transpose, R, ldr, S, lds, ncols, partial, s, kcnt))
     return;
   const int64_t n = g.n;
-  const int nsplit = sample_splits(n, ncols);
+  const SampleTile tile = sample_tile(precision, g.family, n, ncols);
+  const int nsplit = sample_splits(n, ncols, tile);
   int64_t kchunk = (n + nsplit - 1) / nsplit;
   kchunk = (kchunk + SM_BK - 1) / SM_BK * SM_BK;
   const int nz = (int)((n + kchunk - 1) / kchunk);
-  dim3 grid((unsigned)((n + SM_ROWS - 1) / SM_ROWS), (unsigned)((ncols + SM_COLS - 1) / SM_COLS),
+  dim3 grid((unsigned)((n + tile.rows - 1) / tile.rows), (unsigned)((ncols + tile.cols - 1) / tile.cols),
             (unsigned)nz);
   double* out = nz == 1 ? S : partial;
   prof_begin(s);
@@ -363,14 +430,14 @@ void launch_sample(const GenDev& g, int32_t transpose, int32_t precision, const 
     launch_sample_lp(g, transpose, precision == HSS_SAMPLE_BF16X3, R, ldr, out, lds, ncols, kchunk, nz, grid,
                      g.leaf_lo, g.leaf_hi, g.offdiag, s);
   else switch (g.family) {
-    case HSS_FAM_TOEPLITZ: launch_fam<HSS_FAM_TOEPLITZ>(g, transpose, R, ldr, out, lds, ncols, kchunk, nz, grid, s); break;
-    case HSS_FAM_LAPLACE: launch_fam<HSS_FAM_LAPLACE>(g, transpose, R, ldr, out, lds, ncols, kchunk, nz, grid, s); break;
-    case HSS_FAM_GAUSS: launch_fam<HSS_FAM_GAUSS>(g, transpose, R, ldr, out, lds, ncols, kchunk, nz, grid, s); break;
-    default: launch_fam<HSS_FAM_DENSE>(g, transpose, R, ldr, out, lds, ncols, kchunk, nz, grid, s); break;
+    case HSS_FAM_TOEPLITZ: launch_fam<HSS_FAM_TOEPLITZ>(g, transpose, R, ldr, out, lds, ncols, kchunk, nz, grid, tile, s); break;
+    case HSS_FAM_LAPLACE: launch_fam<HSS_FAM_LAPLACE>(g, transpose, R, ldr, out, lds, ncols, kchunk, nz, grid, tile, s); break;
+    case HSS_FAM_GAUSS: launch_fam<HSS_FAM_GAUSS>(g, transpose, R, ldr, out, lds, ncols, kchunk, nz, grid, tile, s); break;
+    default: launch_fam<HSS_FAM_DENSE>(g, transpose, R, ldr, out, lds, ncols, kchunk, nz, grid, tile, s); break;
   }
   prof_end(HSS_K_SAMPLE, s);
   if (nz > 1) {
-    const int64_t ncp = (int64_t)grid.y * SM_COLS;
+    const int64_t ncp = (int64_t)grid.y * tile.cols;
     const int64_t tot = n * ncols;
     prof_begin(s);
     hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,

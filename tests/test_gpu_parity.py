@@ -15,7 +15,8 @@ def _log(msg):
 
 
 @pytest.mark.parametrize("family,n,leaf,ncols", [("toeplitz", 1000, 64, 70), ("laplace", 777, 50, 64),
-                                                 ("gauss", 1500, 100, 130), ("toeplitz", 3, 2, 1)])
+                                                 ("gauss", 1500, 100, 130), ("toeplitz", 3, 2, 1),
+                                                 ("toeplitz", 1000, 64, 128), ("toeplitz", 1000, 64, 200)])
 def test_sampling_matches_dense_product(family, n, leaf, ncols):
     _log("sample %s n=%d ncols=%d" % (family, n, ncols))
     gen, T, ot, op = problem(family, n, leaf, seed=3)
@@ -24,6 +25,25 @@ def test_sampling_matches_dense_product(family, n, leaf, ncols):
     ref = op.dense() @ R
     err = np.linalg.norm(S - ref, axis=0) / np.linalg.norm(ref, axis=0)
     assert err.max() <= 1e-12
+
+
+@pytest.mark.parametrize("family,n,leaf", [("toeplitz", 80000, 128), ("gauss", 40000, 256)])
+@pytest.mark.parametrize("ncols", [128, 200, 192])
+def test_sampling_wide_tiles_split_k(family, n, leaf, ncols):
+    """Sizes where the Toeplitz and Gaussian kernels take their 128-column
+    tiles (128 and 200 columns; 192 runs as three narrow tiles), with the K
+    dimension split over workgroups and ragged rows and columns: sampled
+    rows against the oracle's entries, in both orientations (both
+    operators are symmetric)."""
+    _log("sample %s wide n=%d ncols=%d" % (family, n, ncols))
+    gen, T, ot, op = problem(family, n, leaf, seed=6)
+    R = inputs.gaussian_matrix(n, ncols, 9)
+    rows = np.unique(np.concatenate([[0, 63, 64, 127, 128, n - 1], np.random.default_rng(4).integers(0, n, 12)]))
+    ref = op.extract(rows, np.arange(n)) @ R
+    for tr in (False, True):
+        S = hss.sample(gen, dev(T.perm), dev_colmajor(R), transpose=tr).cpu().numpy()
+        err = np.linalg.norm(S[rows] - ref, axis=1) / np.linalg.norm(ref, axis=1)
+        assert err.max() <= 1e-12, (tr, err.max())
 
 
 def test_sampling_transpose_nonsymmetric_dense():
