@@ -370,8 +370,17 @@ __global__ __launch_bounds__(PCT) void k_idb_chol(const QrcpTask* __restrict__ t
   double* Lu = Ls + (kIdbLmax / 2) * PR;
   for (int e = tid; e < kIdbLmax * PR; e += PCT) Ls[e] = 0.0;
   __syncthreads();
-  if (tid >= 64) return;
   const HSS_GLOBAL double* Gg = gview(B.G);
+  if (tid >= 64) {
+    // the other waves read the candidates' columns of G once (one load per
+    // 128-byte line), so that the pivot rows the first wave reads later
+    // come from this die's L2 rather than from another die's
+    double acc = 0.0;
+    const int64_t lines = ((int64_t)nc * cm + 15) / 16;
+    for (int64_t e = tid - 64; e < lines; e += PCT - 64) acc += Gg[16 * e];
+    asm volatile("" ::"v"(acc));
+    return;
+  }
   QrcpCtlB* ctl = ctlb(t);
   const double bound = B.bound;
   int au[CPL];
@@ -434,10 +443,13 @@ __global__ __launch_bounds__(PCT) void k_idb_chol(const QrcpTask* __restrict__ t
     if (i > 0 && sp < 1e-10 * s0) break;     // Gram-derived residuals lose accuracy below this
     const double inv = sp >= 1e-290 ? rcp_nr(sp) : 1.0 / sp;
     // u_a = G(p, a) - sum_q u(q, a) l(q, p)
-    double g[CPL], h[CPL];
+    // the row of G is added last, so that the LDS reads and products run
+    // while its load is in flight
+    double gp[CPL], g[CPL], h[CPL];
 #pragma unroll
     for (int u = 0; u < CPL; ++u) {
-      g[u] = cu[u] ? 0.0 : Gg[au[u] + (int64_t)p * cm];
+      gp[u] = cu[u] ? 0.0 : Gg[au[u] + (int64_t)p * cm];
+      g[u] = 0.0;
       h[u] = 0.0;
     }
     for (int q0 = 0; q0 < i; q0 += 8) {   // rows >= i are zero: whole chunks of 8 rows
@@ -457,7 +469,7 @@ __global__ __launch_bounds__(PCT) void k_idb_chol(const QrcpTask* __restrict__ t
     const int wi = (i >> 1) * PR + (i & 1);
 #pragma unroll
     for (int u = 0; u < CPL; ++u) {
-      const double ua = cu[u] ? 0.0 : g[u] + h[u];
+      const double ua = cu[u] ? 0.0 : gp[u] + (g[u] + h[u]);
       const double l = ua * inv;
       Lc[wi + 2 * au[u]] = l;
       Lu[wi + 2 * au[u]] = ua;
