@@ -101,8 +101,8 @@ WORKLOADS = {
 TRAFFIC = {
     ("laplace-sphere-32768", "SAMPLE"): {
         "source": "paper_1810_04125_amd/csrc/k_sample.hip",
-        "sha256": "9bf22f6c3e9f3c475194941b7e3826c6c8d8b4854dadbdb14a6d2892ae151fdb",
-        "fetch_kib": 71856.5, "write_kib": 131072.0,               # k_sample_f64, 44 dispatches
+        "sha256": "74ad7940505467123688df4a495769f4cd6d2282639d319bdc8a988a1d6d43e0",
+        "fetch_kib": 71868.0, "write_kib": 131072.0,               # k_sample_f64, 44 dispatches
         "fetch_scale": 1048576.0 / 524302.0, "write_scale": 1.0,   # 1 GiB copy: FETCH 524302 KiB, WRITE 1048576 KiB
     },
 }
@@ -114,14 +114,14 @@ TRAFFIC = {
 # SQ_INSTS_VALU_MFMA_MOPS_F64 (512 flops per MOP).
 SAMPLE_COUNTERS = {
     ("laplace-sphere-32768", "fp64"): {
-        "source_sha256": "9bf22f6c3e9f3c475194941b7e3826c6c8d8b4854dadbdb14a6d2892ae151fdb",
-        "mfma_busy_frac": round(4.39258e9 / (4 * 1.67242e9), 4),
-        "valu_active_frac": round(4.39561e8 / (4 * 1.67242e9), 4),
+        "source_sha256": "74ad7940505467123688df4a495769f4cd6d2282639d319bdc8a988a1d6d43e0",
+        "mfma_busy_frac": round(4.39258e9 / (4 * 1.67236e9), 4),
+        "valu_active_frac": round(4.39561e8 / (4 * 1.67236e9), 4),
         "mfma_valu_coexec_cycles": 0,
         "mfma_flops_per_dispatch": 2.74536e8 * 512,
         "valu_fp64_flops_per_dispatch": 3.08853e8,
-        "avg_dispatch_us": 2981.997,
-        "counter_tflops": round(2.74536e8 * 512 / 2981.997e-6 / 1e12, 2),
+        "avg_dispatch_us": 3033.249,
+        "counter_tflops": round(2.74536e8 * 512 / 3033.249e-6 / 1e12, 2),
     },
 }
 
