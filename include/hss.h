@@ -49,7 +49,8 @@ typedef enum {
   HSS_ERR_DEVICE = -3,                 /* a HIP runtime call failed */
   HSS_ERR_CALLBACK = -4,               /* a caller routine of HSS_FAM_CALLBACK returned non-zero */
   HSS_ERR_NONFINITE = -5,              /* a non-finite sample or entry was met */
-  HSS_ERR_INTERNAL = -6
+  HSS_ERR_INTERNAL = -6,
+  HSS_ERR_SINGULAR = -7                /* hss_factor met a zero pivot */
 } hss_status;
 
 /* Operator families whose entries the kernels generate on the fly. */
@@ -323,6 +324,35 @@ void hss_destroy(hss_matrix* h);
  * arrays: issue them on one stream (calls on different streams race). */
 hss_status hss_matvec(const hss_matrix* h, int32_t nrhs, const double* X, int64_t ldx,
                       double* Y, int64_t ldy, void* stream);
+
+/* Direct factorization of the compressed matrix for hss_solve (the ULV
+ * factorization column of the paper's table sixdrivers; the paper gives no
+ * algorithm, this one follows from the interpolative bases of Sec. 2.2).
+ * Per node, in the order [redundant; skeleton] of its local rows and
+ * columns, the transforms [[I, -E^T], [0, I]] of its row and column bases
+ * leave the redundant unknowns coupled to the node's own block only; an LU
+ * with partial pivoting (pivots among the redundant rows) eliminates them,
+ * and the skeleton Schur complements join into the parent's block with
+ * B12 and B21; the root's block is factored whole.  Needs equal row and
+ * column ranks at every node (every symmetric family gives them):
+ * HSS_ERR_INVALID_ARG otherwise; HSS_ERR_SINGULAR on a zero pivot.  The
+ * factor (about 8 (sum over nodes of m^2) bytes, m = a leaf's size or the
+ * children's summed ranks) stays with h until hss_destroy; a second call
+ * returns at once.  Runs on the stream h was compressed on and returns when
+ * it is done. */
+hss_status hss_factor(hss_matrix* h);
+
+/* X = H^{-1} B for nrhs right-hand sides, B and X device (n x nrhs,
+ * column-major, leading dimensions >= n), ORIGINAL ordering, after
+ * hss_factor (HSS_ERR_INVALID_ARG before).  Bottom-up the row transforms
+ * and the forward substitutions with each node's pivots and L pass the
+ * skeleton part of the right-hand side to the parent; top-down the
+ * skeleton unknowns from the parent give the redundant ones (back
+ * substitution with U) and x = T_c^T xhat.  The call waits for the work
+ * already queued on `stream`, uploads its task arrays, and returns with the
+ * solve queued on `stream`; its temporaries are stream-ordered. */
+hss_status hss_solve(const hss_matrix* h, int32_t nrhs, const double* B, int64_t ldb, double* X,
+                     int64_t ldx, void* stream);
 
 /* hss_matvec for callers that cannot allocate device memory during the call
  * (code under HIP graph capture, serving loops, harnesses that forbid

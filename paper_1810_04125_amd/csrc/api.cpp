@@ -533,6 +533,33 @@ hss_status hss_matvec(const hss_matrix* h, int32_t nrhs, const double* X, int64_
   });
 }
 
+hss_status hss_factor(hss_matrix* h) {
+  return guarded([&]() -> hss_status {
+    if (!h) throw Error(HSS_ERR_INVALID_ARG, "NULL matrix");
+    ulv_factor(h);
+    return HSS_OK;
+  });
+}
+
+hss_status hss_solve(const hss_matrix* h, int32_t nrhs, const double* B, int64_t ldb, double* X, int64_t ldx,
+                     void* stream) {
+  return guarded([&]() -> hss_status {
+    if (!h || !B || !X || nrhs < 1) throw Error(HSS_ERR_INVALID_ARG, "bad arguments");
+    const Job& J = *h->job;
+    const Problem& P = J.probs[h->k];
+    if (ldb < P.n || ldx < P.n) throw Error(HSS_ERR_INVALID_ARG, "leading dimension < n");
+    hipStream_t s = (hipStream_t)stream;
+    const hss_allocator* ua = &J.ualloc;
+    StreamBuf bp(sizeof(double) * P.n * nrhs, s, ua), xp(sizeof(double) * P.n * nrhs, s, ua);
+    const int64_t* perm = P.dev.gen.perm;
+    launch_gather_rows(B, ldb, perm, P.n, nrhs, bp.as<double>(), P.n, 0, s);
+    ulv_solve_permuted(h, nrhs, bp.as<double>(), xp.as<double>(), s);
+    launch_gather_rows(xp.as<double>(), P.n, perm, P.n, nrhs, X, ldx, 1, s);
+    HSS_HIP_CHECK(hipGetLastError());
+    return HSS_OK;
+  });
+}
+
 hss_status hss_rel_error(const hss_matrix* h, const hss_generator* gen, double* rel_err) {
   return guarded([&]() -> hss_status {
     if (!h || !rel_err) throw Error(HSS_ERR_INVALID_ARG, "NULL argument");

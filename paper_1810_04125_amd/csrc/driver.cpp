@@ -227,6 +227,15 @@ void Job::dfree(void* p) {
   }
 }
 
+void Job::drop(void* p) {
+  if (!p) return;
+  for (std::vector<void*>* v : {&allocs, &transients}) {
+    auto it = std::find(v->begin(), v->end(), p);
+    if (it != v->end()) v->erase(it);
+  }
+  dfree(p);
+}
+
 // E of every node side and B12 / B21 of every non-leaf move from their
 // capacity-sized slots in the transient pool to exactly sized blocks of the
 // persistent E pool (E: rank x (m - rank); B: ranks of the children).

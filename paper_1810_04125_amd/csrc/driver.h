@@ -49,8 +49,32 @@ constexpr bool kBlockId = true;
 size_t arena_idle_bytes();   // idle cached transient memory on the current device
 void arena_release_idle();   // free it
 
+// The factorization of one compressed problem (ulv.cpp, k_ulv.hip).
+struct UlvFactor {
+  struct Node {
+    int32_t g = -1;                       // global node id
+    int32_t m = 0, k = 0, r = 0;          // local size, redundant count, rank
+    int32_t level = 0, leaf = 0, lo = 0;
+    int32_t left = -1, right = -1;        // local ids of the children
+    int32_t rl = 0;                       // left child's rank
+    int64_t F = 0, inv = 0, piv = 0, Y = 0;   // offsets: block, inverses, pivots, solve rows
+    const int32_t *Jr = nullptr, *Jc = nullptr;
+    const double *Er = nullptr, *Ec = nullptr;   // r x k, column-major
+    int32_t eldr = 1, eldc = 1;
+  };
+  std::vector<Node> nodes;                // local ids in the tree's order (root 0)
+  int32_t maxlevel = 0;
+  double* fpool = nullptr;                // the nodes' blocks
+  double* ipool = nullptr;                // diagonal-block inverses
+  int32_t* ppool = nullptr;               // pivots
+  int64_t ytot = 0;                       // rows of the solve's per-node buffers
+  int64_t fbytes = 0;                     // device bytes held
+  double factor_ms = 0.0;
+};
+
 struct Job {
   std::vector<Problem> probs;
+  std::vector<std::unique_ptr<UlvFactor>> ulv;   // per problem, once hss_factor ran
   std::vector<NodeDesc> desc;
   std::vector<NodeState> st_h;
   std::vector<LevelInfo> levels;
@@ -107,6 +131,7 @@ struct Job {
   ~Job();
   void* dalloc(size_t bytes, bool transient = false);
   void dfree(void* p);                 // a block from dalloc, stream-ordered
+  void drop(void* p);                  // dfree of a dalloc block the job no longer tracks
   void* arena_acquire(size_t bytes);   // transient block (see driver.cpp)
   void arena_return();
   int arena_dev = -1;                  // device whose cached block this job holds
@@ -144,6 +169,10 @@ namespace hss {
 // (written before they are read).  Asynchronous on s; allocates nothing.
 void matvec_permuted(const hss_matrix* h, int32_t nrhs, const double* Xp, double* Yp, double* xh,
                      double* yh, double* ws, hipStream_t s);
+// Factorization of problem h->k (hss_factor) and X = H^{-1} B in the
+// tree's permuted order (hss_solve; Bp, Xp: n x nrhs, ld n; asynchronous on s).
+void ulv_factor(hss_matrix* h);
+void ulv_solve_permuted(const hss_matrix* h, int32_t nrhs, const double* Bp, double* Xp, hipStream_t s);
 // Sets the thread's hss_last_error() message and returns code.
 hss_status record_error(hss_status code, const std::string& msg);
 }  // namespace hss

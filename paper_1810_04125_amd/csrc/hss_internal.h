@@ -421,6 +421,45 @@ void launch_finalize(const LevelArgs& a, hipStream_t s);
 
 
 // Matvec pieces (one workgroup per node of a level).
+// Tasks of the HSS factorization and solve (k_ulv.hip), one per node.
+// F: the node's m x m block in [redundant; skeleton] order (column-major,
+// ld m); k = m - r redundant unknowns (the root: k = m, no basis, J null).
+struct UlvBuild {
+  double* F;
+  const double* D;              // leaf: m x m in local order (else null)
+  const double *Fl, *Fr;        // children's blocks (their trailing r x r blocks are read)
+  const double *B12, *B21;
+  const int32_t *Jr, *Jc;       // the node's row / column ID order (null at the root)
+  int32_t m, k, r;
+  int32_t rl, kl, ml, kr, mr;   // left rank; children's k and m
+  int32_t ld12, ld21;
+};
+struct UlvPanel {
+  double* F;
+  double* inv;     // Linv then Uinv, 32 x 32 each, column-major
+  int32_t* piv;    // the node's pivot rows (k entries)
+  int32_t m, k, jb, nb;
+};
+struct UlvSwap {   // the row swaps of one panel on columns [c0, c1) of X
+  double* X;
+  const int32_t* piv;
+  int64_t ld, c0, c1;
+  int32_t jb, nb;
+};
+struct UlvMove {   // right-hand sides into / solutions out of a node's Y
+  double* Y;                    // m x nrhs, ld m, [R; S] order
+  double* ext;                  // leaf: permuted B or X (n rows, ld ldext); else null
+  double *Yl, *Yr;              // children's Y (their rows k.. hold the skeleton)
+  const int32_t* J;             // the node's row (in) or column (out) ID order; null at the root
+  int64_t ldext;
+  int32_t m, k, r, lo, rl, kl, ml, kr, mr;
+};
+void launch_ulv_build(const UlvBuild* t, int32_t count, int64_t maxelems, hipStream_t s);
+void launch_ulv_panel(const UlvPanel* t, int32_t count, int32_t* flag, hipStream_t s);
+void launch_ulv_swap(const UlvSwap* t, int32_t count, int64_t maxcols, hipStream_t s);
+void launch_ulv_rhs_in(const UlvMove* t, int32_t count, int32_t nrhs, int64_t maxelems, hipStream_t s);
+void launch_ulv_x_out(const UlvMove* t, int32_t count, int32_t nrhs, int64_t maxelems, hipStream_t s);
+
 struct MvArgs {
   const NodeDesc* desc;
   const NodeState* st;

@@ -1,0 +1,243 @@
+// Direct factorization and solve of a compressed HSS matrix, the downstream
+// use the paper times beside the compression (ULV factorization and solve,
+// table sixdrivers).  The paper gives no algorithm for it; this is the one
+// the interpolative bases of Sec. 2.2 lead to.
+//
+// A non-root node tau has the row basis U = Pi_r [I; E_r^T] and the column
+// basis V = Pi_c [I; E_c^T].  In the order [redundant R; skeleton S] of its
+// local rows, T_r = [[I, -E_r^T], [0, I]] maps U to [0; I] (T_c maps V
+// likewise), so after the two transforms tau's redundant unknowns couple
+// only to tau's local block D' (the leaf's D, or the children's skeleton
+// Schur complements joined by B12 and B21, eq. HSSexamplematrix):
+//
+//   Dhat = T_r D' T_c^T:  Dhat_RR = D'_RR - E_r^T D'_SR - D'_RS E_c + E_r^T D'_SS E_c,
+//                         Dhat_RS = D'_RS - E_r^T D'_SS,  Dhat_SR = D'_SR - D'_SS E_c.
+//
+// F_tau (m x m, column-major) holds Dhat in those orders; an LU with
+// partial pivoting of its first k = m - r columns, the pivots taken among
+// the redundant rows only, leaves L and U of Dhat_RR, L_SR and U_RS, and in
+// the trailing r x r block the Schur complement S_tau, which the parent
+// gathers into its own local block.  The root's block is factored whole.
+//
+// The LU is blocked by 32 columns: a panel kernel (one workgroup per node,
+// the panel in global memory) picks the pivots and forms the multipliers
+// and the inverses of the panel's diagonal L and U blocks; the row swaps
+// then go to the columns right of the panel (the columns left of it keep
+// the rows as they stood at their own step, which the solve replays in the
+// same order); U12 = L11^{-1} A12 and the trailing update A22 -= L21 U12
+// run on the matrix cores as grouped GEMMs over all nodes of a level.
+//
+// The solve: bottom-up, each node's right-hand side in [R; S] order, the
+// row transform (b_R -= E_r^T b_S) and the forward substitution with the
+// node's pivots and L, whose skeleton rows then hold the reduced
+// right-hand side its parent gathers; at the root the whole block is
+// solved.  Top-down: the node's skeleton unknowns come from its parent,
+// x_R = U_RR^{-1} (y_R - U_RS x_S), x_S -= E_c x_R (x = T_c^T xhat), and
+// the result goes to the children's skeleton rows or to the output.
+#include <cstring>
+
+#include "driver.h"
+
+namespace hss {
+
+constexpr int UNB = 32;   // panel width: the GEMM's K tile
+constexpr int UPT = 256;  // threads of the panel kernel
+
+// Local index i of F's [R; S] order -> the node's local row (column): R =
+// J[r..m), S = J[0..r); the root has no basis (identity).
+__device__ __forceinline__ int rs_index(const int32_t* __restrict__ J, int i, int k, int r) {
+  if (!J) return i;
+  return i < k ? J[r + i] : J[i - k];
+}
+
+// ---------------------------------------------------------------- gather
+// F = D'(order_r, order_c): the leaf's D, or [[S_l, B12], [B21, S_r]] from
+// the children's factors (their trailing blocks).
+__global__ __launch_bounds__(256) void k_ulv_build(const UlvBuild* __restrict__ tasks) {
+  const UlvBuild& t = tasks[blockIdx.x];
+  const int m = t.m;
+  const int64_t tot = (int64_t)m * m;
+  for (int64_t e = threadIdx.x + (int64_t)blockIdx.y * 256; e < tot; e += (int64_t)256 * gridDim.y) {
+    const int i = (int)(e % m), j = (int)(e / m);
+    const int a = rs_index(t.Jr, i, t.k, t.r), b = rs_index(t.Jc, j, t.k, t.r);
+    double v;
+    if (t.D) {
+      v = t.D[a + (int64_t)b * m];
+    } else if (a < t.rl) {
+      v = b < t.rl ? t.Fl[(t.kl + a) + (int64_t)(t.kl + b) * t.ml] : t.B12[a + (int64_t)(b - t.rl) * t.ld12];
+    } else {
+      const int a2 = a - t.rl;
+      v = b < t.rl ? t.B21[a2 + (int64_t)b * t.ld21] : t.Fr[(t.kr + a2) + (int64_t)(t.kr + b - t.rl) * t.mr];
+    }
+    t.F[e] = v;
+  }
+}
+
+// ---------------------------------------------------------------- panel
+// LU with partial pivoting of F(jb:m, jb:jb+nb), pivots among rows [jb, k);
+// the panel's row swaps stay in its own columns.  Then Linv and Uinv, the
+// inverses of the panel's diagonal block's unit-lower and upper parts
+// (UNB x UNB, column-major, zero outside nb x nb).
+__global__ __launch_bounds__(UPT) void k_ulv_panel(const UlvPanel* __restrict__ tasks, int32_t* __restrict__ flag) {
+  const UlvPanel& t = tasks[blockIdx.x];
+  const int nb = t.nb;
+  if (nb <= 0) return;
+  const int m = t.m, k = t.k, jb = t.jb, tid = threadIdx.x;
+  HSS_GLOBAL double* F = gview_w(t.F);
+  __shared__ double prow[UNB];
+  __shared__ double rv[UPT / 64];
+  __shared__ int ri[UPT / 64];
+  __shared__ int prow_i;
+  for (int c = 0; c < nb; ++c) {
+    const int j = jb + c;
+    const HSS_GLOBAL double* col = F + (int64_t)j * m;
+    // the pivot: largest |F(i, j)| over i in [j, k), the lowest i on ties
+    double bv = -1.0;
+    int bi = 0x7fffffff;
+    for (int i = j + tid; i < k; i += UPT) {
+      const double v = fabs(col[i]);
+      if (v > bv) { bv = v; bi = i; }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ov = __shfl_down(bv, off);
+      const int oi = __shfl_down(bi, off);
+      if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+    }
+    if ((tid & 63) == 0) { rv[tid >> 6] = bv; ri[tid >> 6] = bi; }
+    __syncthreads();
+    if (tid == 0) {
+      for (int w = 1; w < UPT / 64; ++w)
+        if (rv[w] > rv[0] || (rv[w] == rv[0] && ri[w] < ri[0])) { rv[0] = rv[w]; ri[0] = ri[w]; }
+      if (!(rv[0] > 0.0)) {   // a zero (or non-finite) column: the block is singular
+        atomicOr(flag, 1);
+        ri[0] = j;
+      }
+      prow_i = ri[0];
+      t.piv[j] = ri[0];
+    }
+    __syncthreads();
+    const int p = prow_i;
+    if (tid < nb) {
+      HSS_GLOBAL double* a = F + j + (int64_t)(jb + tid) * m;
+      HSS_GLOBAL double* b = F + p + (int64_t)(jb + tid) * m;
+      const double x = *a, y = *b;
+      if (p != j) { *a = y; *b = x; }
+      prow[tid] = p != j ? y : x;   // the pivot row after the swap
+    }
+    __syncthreads();
+    const double d = prow[c];
+    const double rinv = d != 0.0 ? 1.0 / d : 0.0;
+    for (int i = j + 1 + tid; i < m; i += UPT) {
+      HSS_GLOBAL double* fi = F + i;
+      const double l = fi[(int64_t)j * m] * rinv;
+      fi[(int64_t)j * m] = l;
+      for (int cc = c + 1; cc < nb; ++cc) fi[(int64_t)(jb + cc) * m] -= l * prow[cc];
+    }
+    __syncthreads();
+  }
+  // inverses of the diagonal block's L (unit lower) and U, one column per thread
+  if (tid < UNB) {
+    const int c = tid;
+    HSS_GLOBAL double* Li = gview_w(t.inv);
+    HSS_GLOBAL double* Ui = gview_w(t.inv + UNB * UNB);
+    const HSS_GLOBAL double* A = F + jb + (int64_t)jb * m;   // A(i, q) = F(jb + i, jb + q)
+    for (int i = 0; i < UNB; ++i) {
+      Li[i + c * UNB] = 0.0;
+      Ui[i + c * UNB] = 0.0;
+    }
+    if (c < nb) {
+      // L X = e_c: X(c) = 1, X(i) = -sum_{q in [c, i)} L(i, q) X(q)
+      Li[c + c * UNB] = 1.0;
+      for (int i = c + 1; i < nb; ++i) {
+        double s = 0.0;
+        for (int q = c; q < i; ++q) s += A[i + (int64_t)q * m] * Li[q + c * UNB];
+        Li[i + c * UNB] = -s;
+      }
+      // U X = e_c: X(c) = 1 / U(c, c), X(i) = -sum_{q in (i, c]} U(i, q) X(q) / U(i, i)
+      Ui[c + c * UNB] = 1.0 / A[c + (int64_t)c * m];
+      for (int i = c - 1; i >= 0; --i) {
+        double s = 0.0;
+        for (int q = i + 1; q <= c; ++q) s += A[i + (int64_t)q * m] * Ui[q + c * UNB];
+        Ui[i + c * UNB] = -s / A[i + (int64_t)i * m];
+      }
+    }
+  }
+}
+
+// The panel's row swaps applied to columns [c0, c1) of a matrix with
+// leading dimension ld (F right of the panel, or a right-hand side block):
+// one thread per column, the swaps in order.
+__global__ __launch_bounds__(256) void k_ulv_swap(const UlvSwap* __restrict__ tasks) {
+  const UlvSwap& t = tasks[blockIdx.x];
+  const int64_t col = t.c0 + (int64_t)blockIdx.y * 256 + threadIdx.x;
+  if (t.nb <= 0 || col >= t.c1) return;
+  HSS_GLOBAL double* X = gview_w(t.X + col * t.ld);
+  for (int c = 0; c < t.nb; ++c) {
+    const int j = t.jb + c, p = t.piv[j];
+    if (p != j) {
+      const double a = X[j], b = X[p];
+      X[j] = b;
+      X[p] = a;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- solve moves
+// Y (m x nrhs, column-major, ld m) = the node's right-hand side in [R; S] row
+// order: permuted B rows (leaf), or the children's reduced right-hand sides
+// (the skeleton rows of their Y).
+__global__ __launch_bounds__(256) void k_ulv_rhs_in(const UlvMove* __restrict__ tasks, int32_t nrhs) {
+  const UlvMove& t = tasks[blockIdx.x];
+  const int m = t.m;
+  const int64_t tot = (int64_t)m * nrhs;
+  for (int64_t e = threadIdx.x + (int64_t)blockIdx.y * 256; e < tot; e += (int64_t)256 * gridDim.y) {
+    const int i = (int)(e % m), c = (int)(e / m);
+    const int a = rs_index(t.J, i, t.k, t.r);
+    double v;
+    if (t.ext) v = t.ext[(t.lo + a) + (int64_t)c * t.ldext];
+    else if (a < t.rl) v = t.Yl[(t.kl + a) + (int64_t)c * t.ml];
+    else v = t.Yr[(t.kr + a - t.rl) + (int64_t)c * t.mr];
+    t.Y[i + (int64_t)c * m] = v;
+  }
+}
+
+// The node's solution (Y in [R; S] column order) to its local column order:
+// into the output rows (leaf) or the children's skeleton rows.
+__global__ __launch_bounds__(256) void k_ulv_x_out(const UlvMove* __restrict__ tasks, int32_t nrhs) {
+  const UlvMove& t = tasks[blockIdx.x];
+  const int m = t.m;
+  const int64_t tot = (int64_t)m * nrhs;
+  for (int64_t e = threadIdx.x + (int64_t)blockIdx.y * 256; e < tot; e += (int64_t)256 * gridDim.y) {
+    const int i = (int)(e % m), c = (int)(e / m);
+    const int a = rs_index(t.J, i, t.k, t.r);
+    const double v = t.Y[i + (int64_t)c * m];
+    if (t.ext) t.ext[(t.lo + a) + (int64_t)c * t.ldext] = v;
+    else if (a < t.rl) t.Yl[(t.kl + a) + (int64_t)c * t.ml] = v;
+    else t.Yr[(t.kr + a - t.rl) + (int64_t)c * t.mr] = v;
+  }
+}
+
+void launch_ulv_build(const UlvBuild* t, int32_t count, int64_t maxelems, hipStream_t s) {
+  if (count <= 0) return;
+  const unsigned gy = (unsigned)std::max<int64_t>(1, std::min<int64_t>(64, (maxelems + 4095) / 4096));
+  hipLaunchKernelGGL(k_ulv_build, dim3(count, gy), dim3(256), 0, s, t);
+}
+void launch_ulv_panel(const UlvPanel* t, int32_t count, int32_t* flag, hipStream_t s) {
+  if (count > 0) hipLaunchKernelGGL(k_ulv_panel, dim3(count), dim3(UPT), 0, s, t, flag);
+}
+void launch_ulv_swap(const UlvSwap* t, int32_t count, int64_t maxcols, hipStream_t s) {
+  if (count <= 0 || maxcols <= 0) return;
+  hipLaunchKernelGGL(k_ulv_swap, dim3(count, (unsigned)((maxcols + 255) / 256)), dim3(256), 0, s, t);
+}
+void launch_ulv_rhs_in(const UlvMove* t, int32_t count, int32_t nrhs, int64_t maxelems, hipStream_t s) {
+  if (count <= 0) return;
+  const unsigned gy = (unsigned)std::max<int64_t>(1, std::min<int64_t>(64, (maxelems * nrhs + 4095) / 4096));
+  hipLaunchKernelGGL(k_ulv_rhs_in, dim3(count, gy), dim3(256), 0, s, t, nrhs);
+}
+void launch_ulv_x_out(const UlvMove* t, int32_t count, int32_t nrhs, int64_t maxelems, hipStream_t s) {
+  if (count <= 0) return;
+  const unsigned gy = (unsigned)std::max<int64_t>(1, std::min<int64_t>(64, (maxelems * nrhs + 4095) / 4096));
+  hipLaunchKernelGGL(k_ulv_x_out, dim3(count, gy), dim3(256), 0, s, t, nrhs);
+}
+
+}  // namespace hss

@@ -133,7 +133,7 @@ EXPORTS = ["hss_tree_build", "hss_tree_free", "hss_compress", "hss_compress_batc
            "hss_sample", "hss_extract", "hss_interpolative_batched", "hss_last_error", "hss_version",
            "hss_get_kernel_stats", "hss_release_cache", "hss_mlp_num_params", "hss_mlp_forward", "hss_mlp_gradient",
            "hss_mlp_adam", "hss_mlp_train", "hss_random_normal", "hss_random_words", "hss_matvec_noalloc",
-           "hss_default_tunables", "hss_load_tunables", "hss_lookup_tunables"]
+           "hss_default_tunables", "hss_load_tunables", "hss_lookup_tunables", "hss_factor", "hss_solve"]
 
 MLP_MAX_LAYERS = 6
 
@@ -177,6 +177,8 @@ def lib():
     L.hss_destroy.restype = None
     L.hss_matvec.argtypes = [vp, i32, vp, i64, vp, i64, vp]
     L.hss_matvec_noalloc.argtypes = [vp, i32, vp, i64, vp, i64, vp]
+    L.hss_factor.argtypes = [vp]
+    L.hss_solve.argtypes = [vp, i32, vp, i64, vp, i64, vp]
     L.hss_rel_error.argtypes = [vp, C.POINTER(_Gen), C.POINTER(dbl)]
     L.hss_get_info.argtypes = [vp, C.POINTER(_Info)]
     L.hss_get_node_info.argtypes = [vp, i32, C.POINTER(_NodeInfo)]
@@ -467,6 +469,21 @@ class HSSMatrix:
         _check(lib().hss_matvec(self._h, Xc.shape[1], _ptr(Xc), _colmajor(Xc, "X"), _ptr(Y),
                                 _colmajor(Y, "Y"), _stream()))
         return Y[:, 0] if vec else Y
+
+    def factor(self):
+        """hss_factor: the direct factorization for solve() (kept with the matrix)."""
+        _check(lib().hss_factor(self._h))
+        return self
+
+    def solve(self, B):
+        """X = H^{-1} B (original ordering, hss_solve); B: (n,) or (n, k) float64 CUDA tensor."""
+        import torch
+        vec = B.dim() == 1
+        Bc = colmajor(B[:, None] if vec else B)
+        X = colmajor(torch.empty_like(Bc))
+        _check(lib().hss_solve(self._h, Bc.shape[1], _ptr(Bc), _colmajor(Bc, "B"), _ptr(X),
+                               _colmajor(X, "X"), _stream()))
+        return X[:, 0] if vec else X
 
     def matvec_noalloc(self, X, Y):
         """Y = H X through hss_matvec_noalloc (no device allocation in the call):
