@@ -568,6 +568,54 @@ def learned_leg(args, name, log):
             "rank_pred_mae_log2": round(float(np.mean(np.abs(np.log2(1 + lr_pred) - np.log2(1 + act[1:])))), 4)}
 
 
+def ulv_leg(H, T, args, log):
+    """The direct factorization and solve of the bench's compressed matrix
+    (hss_factor, hss_solve): time of one factorization, of solves with 1 and
+    64 right-hand sides, algorithmic flops against the FP64 peak, and the
+    residual through H.  Per node (m = leaf size or children's ranks, r its
+    rank, k = m - r; the root r = 0): the basis transforms 4 r k (r + k)
+    flops, the LU of the first k columns 2/3 (m^3 - (m - k)^3); a solve
+    about 4 m k + 4 r k flops per right-hand side."""
+    import torch
+
+    from paper_1810_04125_amd import hss, inputs
+    n = T.n
+    ranks = [H.node_info(t)["rank_r"] if T.parent[t] >= 0 else 0 for t in range(T.num_nodes)]
+    fflops = sflops = fbytes = 0.0
+    for t in range(T.num_nodes):
+        m = float(T.hi[t] - T.lo[t] if T.left[t] < 0 else ranks[T.left[t]] + ranks[T.right[t]])
+        r = float(ranks[t])
+        k = m - r
+        fflops += 4.0 * r * k * (r + k) + 2.0 / 3.0 * (m ** 3 - (m - k) ** 3)
+        sflops += 4.0 * m * k + 4.0 * r * k
+        fbytes += 8.0 * m * m
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    H.factor()
+    torch.cuda.synchronize()
+    fsec = time.perf_counter() - t0
+    out = {"factor_ms": round(1e3 * fsec, 2), "factor_alg_gflop": round(fflops / 1e9, 2),
+           "factor_tflops": round(fflops / fsec / 1e12, 3),
+           "factor_frac_fp64_peak": round(fflops / fsec / 1e12 / PEAK_FP64_TFLOPS, 4),
+           "factor_gbytes": round(fbytes / 1e9, 3)}
+    for nrhs in (1, 64):
+        B = hss.colmajor(torch.from_numpy(inputs.gaussian_matrix(n, nrhs, 17)).cuda())
+        X = H.solve(B)   # warm-up
+        torch.cuda.synchronize()
+        reps = 5
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            X = H.solve(B)
+        torch.cuda.synchronize()
+        ssec = (time.perf_counter() - t0) / reps
+        res = float(torch.linalg.norm(H.matvec(X) - B) / torch.linalg.norm(B))
+        out["solve_ms_nrhs%d" % nrhs] = round(1e3 * ssec, 3)
+        out["solve_tflops_nrhs%d" % nrhs] = round(sflops * nrhs / ssec / 1e12, 4)
+        out["residual_through_H_nrhs%d" % nrhs] = res
+    log("bench: ulv %s" % json.dumps(out))
+    return out
+
+
 def id_roofline(stats):
     """The per-level ID (rows a6-a8 of the method): its algorithmic work as the
     method defines it (class ID: 4 d m r flops, 8 d m + 8 r (m - r) bytes per
@@ -599,7 +647,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-legs", action="store_true",
-                    help="skip the mixed-precision and learned-d0 legs of the default line")
+                    help="skip the factorization, mixed-precision and learned-d0 legs of the default line")
+    ap.add_argument("--legs", default="all", choices=["all", "ulv", "none"],
+                    help="legs of the default line: all, only the factorization and solve, or none")
     ap.add_argument("--leg-steps", type=int, default=3)
     ap.add_argument("--tunables", default=TUNE_FILE,
                     help="launch-shape table written by the autotuner ('none': the built-in shapes)")
@@ -623,6 +673,8 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.no_legs:
+        args.legs = "none"
     W = WORKLOADS[args.workload]
     log = lambda m: print(m, file=sys.stderr, flush=True)
     tune_file = None
@@ -648,6 +700,9 @@ def main():
     log("bench: timed %d steps in %.3f s; info %s" % (args.steps, el, info))
     err, kind = probe_error(gen, T, H, n)
     log("bench: rel err %.3e (%s)" % (err, kind))
+    ulv = None
+    if args.legs in ("all", "ulv") and args.precision == "fp64" and args.workload == "laplace-sphere-32768":
+        ulv = ulv_leg(H, T, args, log)
     del H
 
     rl = None
@@ -676,7 +731,7 @@ def main():
         del Hp
 
     legs = {}
-    if not args.no_legs and args.workload == "laplace-sphere-32768" and args.precision == "fp64":
+    if args.legs == "all" and args.workload == "laplace-sphere-32768" and args.precision == "fp64":
         legs["mixed"] = mixed_leg(args, log)
         legs["learned"] = [learned_leg(args, nm, log) for nm in ("learned-laplace-sphere-65536",
                                                                  "learned-toeplitz-131072")]
@@ -703,6 +758,8 @@ def main():
         "rounds": info["rounds"], "d_final": info["d_final"], "hss_rank": info["hss_rank"],
         "roofline": rl, "cpu_baseline": cpu,
     }
+    if ulv:
+        out["ulv"] = ulv
     out.update(legs)
     print(json.dumps(out), flush=True)
 

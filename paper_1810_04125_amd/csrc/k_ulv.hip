@@ -41,7 +41,7 @@
 namespace hss {
 
 constexpr int UNB = 32;   // panel width: the GEMM's K tile
-constexpr int UPT = 256;  // threads of the panel kernel
+constexpr int UPT = 1024; // threads of the panel kernel
 
 // Local index i of F's [R; S] order -> the node's local row (column): R =
 // J[r..m), S = J[0..r); the root has no basis (identity).
@@ -75,63 +75,122 @@ __global__ __launch_bounds__(256) void k_ulv_build(const UlvBuild* __restrict__ 
 
 // ---------------------------------------------------------------- panel
 // LU with partial pivoting of F(jb:m, jb:jb+nb), pivots among rows [jb, k);
-// the panel's row swaps stay in its own columns.  Then Linv and Uinv, the
-// inverses of the panel's diagonal block's unit-lower and upper parts
-// (UNB x UNB, column-major, zero outside nb x nb).
+// the panel's row swaps stay in its own columns.  The panel is factored in
+// sub-panels of USB columns: column by column inside a sub-panel (pivot,
+// swap across the whole panel, multipliers, update of the sub-panel's
+// later columns), then one blocked update of the panel's columns right of
+// it (U12 = L11^{-1} A12 on its rows, A22 -= L21 U12 below), so each entry
+// is read and written about USB + nb / USB times instead of nb.  Then Linv
+// and Uinv, the inverses of the panel's diagonal block's unit-lower and
+// upper parts (UNB x UNB, column-major, zero outside nb x nb).
+constexpr int USB = 8;
+static_assert(UNB % USB == 0, "whole sub-panels");
 __global__ __launch_bounds__(UPT) void k_ulv_panel(const UlvPanel* __restrict__ tasks, int32_t* __restrict__ flag) {
   const UlvPanel& t = tasks[blockIdx.x];
   const int nb = t.nb;
   if (nb <= 0) return;
   const int m = t.m, k = t.k, jb = t.jb, tid = threadIdx.x;
   HSS_GLOBAL double* F = gview_w(t.F);
+  HSS_GLOBAL double* P = F + (int64_t)jb * m;   // P(i, c) = F(i, jb + c), i absolute
   __shared__ double prow[UNB];
+  __shared__ double U12[USB][UNB];
   __shared__ double rv[UPT / 64];
   __shared__ int ri[UPT / 64];
   __shared__ int prow_i;
-  for (int c = 0; c < nb; ++c) {
-    const int j = jb + c;
-    const HSS_GLOBAL double* col = F + (int64_t)j * m;
-    // the pivot: largest |F(i, j)| over i in [j, k), the lowest i on ties
-    double bv = -1.0;
-    int bi = 0x7fffffff;
-    for (int i = j + tid; i < k; i += UPT) {
-      const double v = fabs(col[i]);
-      if (v > bv) { bv = v; bi = i; }
-    }
-    for (int off = 32; off > 0; off >>= 1) {
-      const double ov = __shfl_down(bv, off);
-      const int oi = __shfl_down(bi, off);
-      if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
-    }
-    if ((tid & 63) == 0) { rv[tid >> 6] = bv; ri[tid >> 6] = bi; }
-    __syncthreads();
-    if (tid == 0) {
-      for (int w = 1; w < UPT / 64; ++w)
-        if (rv[w] > rv[0] || (rv[w] == rv[0] && ri[w] < ri[0])) { rv[0] = rv[w]; ri[0] = ri[w]; }
-      if (!(rv[0] > 0.0)) {   // a zero (or non-finite) column: the block is singular
-        atomicOr(flag, 1);
-        ri[0] = j;
+  for (int c0 = 0; c0 < nb; c0 += USB) {
+    const int ce = min(c0 + USB, nb);
+    for (int c = c0; c < ce; ++c) {
+      const int j = jb + c;
+      // the pivot: largest |P(i, c)| over i in [j, k), the lowest i on ties
+      double bv = -1.0;
+      int bi = 0x7fffffff;
+      for (int i = j + tid; i < k; i += UPT) {
+        const double v = fabs(P[i + (int64_t)c * m]);
+        if (v > bv) { bv = v; bi = i; }
       }
-      prow_i = ri[0];
-      t.piv[j] = ri[0];
+      for (int off = 32; off > 0; off >>= 1) {
+        const double ov = __shfl_down(bv, off);
+        const int oi = __shfl_down(bi, off);
+        if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+      }
+      if ((tid & 63) == 0) { rv[tid >> 6] = bv; ri[tid >> 6] = bi; }
+      __syncthreads();
+      if (tid == 0) {
+        for (int w = 1; w < UPT / 64; ++w)
+          if (rv[w] > rv[0] || (rv[w] == rv[0] && ri[w] < ri[0])) { rv[0] = rv[w]; ri[0] = ri[w]; }
+        if (!(rv[0] > 0.0)) {   // a zero (or non-finite) column: the block is singular
+          atomicOr(flag, 1);
+          ri[0] = j;
+        }
+        prow_i = ri[0];
+        t.piv[j] = ri[0];
+      }
+      __syncthreads();
+      const int p = prow_i;
+      if (tid < nb) {   // the swap across the whole panel; the pivot row's sub-panel part to LDS
+        HSS_GLOBAL double* a = P + j + (int64_t)tid * m;
+        HSS_GLOBAL double* b = P + p + (int64_t)tid * m;
+        const double x = *a, y = *b;
+        if (p != j) { *a = y; *b = x; }
+        prow[tid] = p != j ? y : x;
+      }
+      __syncthreads();
+      const double d = prow[c];
+      const double rinv = d != 0.0 ? 1.0 / d : 0.0;
+      for (int i = j + 1 + tid; i < m; i += UPT) {
+        HSS_GLOBAL double* pi = P + i;
+        double v[USB];
+#pragma unroll
+        for (int q = 0; q < USB; ++q) v[q] = c0 + q > c && c0 + q < ce ? pi[(int64_t)(c0 + q) * m] : 0.0;
+        const double l = pi[(int64_t)c * m] * rinv;
+        pi[(int64_t)c * m] = l;
+#pragma unroll
+        for (int q = 0; q < USB; ++q)
+          if (c0 + q > c && c0 + q < ce) pi[(int64_t)(c0 + q) * m] = v[q] - l * prow[c0 + q];
+      }
+      __syncthreads();
+    }
+    if (ce >= nb) break;
+    // U12 = L11^{-1} A12 on the sub-panel's rows (one thread per column right
+    // of it, the unit-lower L11 from the sub-panel's rows), into LDS and F
+    const int w = nb - ce;
+    if (tid < w) {
+      const int cc = ce + tid;
+      double u[USB];
+#pragma unroll
+      for (int q = 0; q < USB; ++q) u[q] = c0 + q < ce ? P[(jb + c0 + q) + (int64_t)cc * m] : 0.0;
+#pragma unroll
+      for (int q = 1; q < USB; ++q) {
+        if (c0 + q >= ce) break;
+        double s = u[q];
+#pragma unroll
+        for (int q2 = 0; q2 < q; ++q2) s -= P[(jb + c0 + q) + (int64_t)(c0 + q2) * m] * u[q2];
+        u[q] = s;
+      }
+#pragma unroll
+      for (int q = 0; q < USB; ++q) {
+        U12[q][tid] = u[q];
+        if (c0 + q < ce) P[(jb + c0 + q) + (int64_t)cc * m] = u[q];
+      }
     }
     __syncthreads();
-    const int p = prow_i;
-    if (tid < nb) {
-      HSS_GLOBAL double* a = F + j + (int64_t)(jb + tid) * m;
-      HSS_GLOBAL double* b = F + p + (int64_t)(jb + tid) * m;
-      const double x = *a, y = *b;
-      if (p != j) { *a = y; *b = x; }
-      prow[tid] = p != j ? y : x;   // the pivot row after the swap
-    }
-    __syncthreads();
-    const double d = prow[c];
-    const double rinv = d != 0.0 ? 1.0 / d : 0.0;
-    for (int i = j + 1 + tid; i < m; i += UPT) {
-      HSS_GLOBAL double* fi = F + i;
-      const double l = fi[(int64_t)j * m] * rinv;
-      fi[(int64_t)j * m] = l;
-      for (int cc = c + 1; cc < nb; ++cc) fi[(int64_t)(jb + cc) * m] -= l * prow[cc];
+    // A22 -= L21 U12 for the rows below the sub-panel
+    for (int i = jb + ce + tid; i < m; i += UPT) {
+      HSS_GLOBAL double* pi = P + i;
+      double l[USB];
+#pragma unroll
+      for (int q = 0; q < USB; ++q) l[q] = c0 + q < ce ? pi[(int64_t)(c0 + q) * m] : 0.0;
+      double a[UNB - USB];
+#pragma unroll
+      for (int x = 0; x < UNB - USB; ++x) a[x] = x < w ? pi[(int64_t)(ce + x) * m] : 0.0;
+#pragma unroll
+      for (int x = 0; x < UNB - USB; ++x) {
+        if (x >= w) break;
+        double s = a[x];
+#pragma unroll
+        for (int q = 0; q < USB; ++q) s -= l[q] * U12[q][x];
+        pi[(int64_t)(ce + x) * m] = s;
+      }
     }
     __syncthreads();
   }
