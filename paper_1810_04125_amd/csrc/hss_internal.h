@@ -454,6 +454,15 @@ struct UlvMove {   // right-hand sides into / solutions out of a node's Y
   int64_t ldext;
   int32_t m, k, r, lo, rl, kl, ml, kr, mr;
 };
+struct UlvSubst {   // a node's whole forward or backward block substitution
+  double* Y;                    // m x nrhs, ld m
+  const double* F;
+  const double* inv;            // the node's diagonal-block inverses
+  const int32_t* piv;
+  int32_t m, k;
+};
+constexpr int UST_MAXR = 16;    // right-hand sides up to which the fused substitutions run
+void launch_ulv_subst(const UlvSubst* t, int32_t count, int32_t nrhs, int32_t backward, hipStream_t s);
 void launch_ulv_build(const UlvBuild* t, int32_t count, int64_t maxelems, hipStream_t s);
 void launch_ulv_panel(const UlvPanel* t, int32_t count, int32_t* flag, hipStream_t s);
 void launch_ulv_swap(const UlvSwap* t, int32_t count, int64_t maxcols, hipStream_t s);

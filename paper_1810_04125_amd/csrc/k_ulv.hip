@@ -276,6 +276,72 @@ __global__ __launch_bounds__(256) void k_ulv_x_out(const UlvMove* __restrict__ t
   }
 }
 
+// ---------------------------------------------------------------- fused solves
+// For few right-hand sides the block steps of a level's substitutions are
+// too small for one launch each: one workgroup per node runs them all.
+// Forward (after the row transform): for each 32-row block of the first k
+// rows, its row swaps, y_j = Linv y_j, and Y(rows below, :) -= L(rows
+// below, block) y_j (the skeleton rows included).  Backward (after
+// y_R -= U_RS x_S): from the last block up, x_j = Uinv y_j and
+// Y(rows above, :) -= U(rows above, block) x_j.
+constexpr int UST = 1024;  // threads of the fused substitutions
+__global__ __launch_bounds__(UST) void k_ulv_subst(const UlvSubst* __restrict__ tasks, int32_t nrhs, int32_t backward) {
+  const UlvSubst& t = tasks[blockIdx.x];
+  const int m = t.m, k = t.k, tid = threadIdx.x;
+  if (k <= 0) return;
+  HSS_GLOBAL double* Y = gview_w(t.Y);
+  const HSS_GLOBAL double* F = gview(t.F);
+  __shared__ double yj[UNB * UST_MAXR];
+  const int nblk = (k + UNB - 1) / UNB;
+  for (int s0 = 0; s0 < nblk; ++s0) {
+    const int st = backward ? nblk - 1 - s0 : s0;
+    const int jb = st * UNB, nb = min(UNB, k - jb);
+    const HSS_GLOBAL double* inv = gview(t.inv + (int64_t)st * 2 * UNB * UNB + (backward ? UNB * UNB : 0));
+    if (!backward && tid < nrhs) {   // the block's row swaps, in order, one column per thread
+      HSS_GLOBAL double* y = Y + (int64_t)tid * m;
+      for (int q = 0; q < nb; ++q) {
+        const int j = jb + q, p = t.piv[j];
+        if (p != j) {
+          const double a = y[j], b = y[p];
+          y[j] = b;
+          y[p] = a;
+        }
+      }
+    }
+    __syncthreads();
+    // y_j = inv y_j (inv: lower for the forward pass, upper for the backward)
+    for (int e = tid; e < nb * nrhs; e += UST) {
+      const int r = e % nb, c = e / nb;
+      double acc = 0.0;
+#pragma unroll 8
+      for (int q = 0; q < nb; ++q) acc += inv[r + q * UNB] * Y[(jb + q) + (int64_t)c * m];
+      yj[r + UNB * c] = acc;
+    }
+    __syncthreads();
+    for (int e = tid; e < nb * nrhs; e += UST) {
+      const int r = e % nb, c = e / nb;
+      Y[(jb + r) + (int64_t)c * m] = yj[r + UNB * c];
+    }
+    // the other rows: below the block (forward) or above it (backward)
+    const int lo = backward ? 0 : jb + nb, hi = backward ? jb : m;
+    for (int64_t e = tid; e < (int64_t)(hi - lo) * nrhs; e += UST) {
+      const int i = lo + (int)(e % (hi - lo)), c = (int)(e / (hi - lo));
+      double f[UNB];   // the row's block entries, loaded together
+#pragma unroll
+      for (int q = 0; q < UNB; ++q) f[q] = q < nb ? F[i + (int64_t)(jb + q) * m] : 0.0;
+      double acc = Y[i + (int64_t)c * m];
+#pragma unroll
+      for (int q = 0; q < UNB; ++q) acc -= f[q] * yj[q + UNB * c];
+      Y[i + (int64_t)c * m] = acc;
+    }
+    __syncthreads();
+  }
+}
+
+void launch_ulv_subst(const UlvSubst* t, int32_t count, int32_t nrhs, int32_t backward, hipStream_t s) {
+  if (count > 0) hipLaunchKernelGGL(k_ulv_subst, dim3(count), dim3(UST), 0, s, t, nrhs, backward);
+}
+
 void launch_ulv_build(const UlvBuild* t, int32_t count, int64_t maxelems, hipStream_t s) {
   if (count <= 0) return;
   const unsigned gy = (unsigned)std::max<int64_t>(1, std::min<int64_t>(64, (maxelems + 4095) / 4096));

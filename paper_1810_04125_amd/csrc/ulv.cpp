@@ -28,7 +28,7 @@ GemmTask gemm(const double* A, int64_t a_rs, int64_t a_cs, const double* B, int6
 
 // One launch of the replayed sequence: `count` tasks of one kind from
 // offset `off` of that kind's array; a, b: the launch's size caps.
-enum Kind { kBuild, kGemm, kPanel, kSwap, kIn, kOut };
+enum Kind { kBuild, kGemm, kPanel, kSwap, kIn, kOut, kSubstF, kSubstB };
 struct Launch {
   Kind kind;
   int64_t off;
@@ -43,6 +43,7 @@ struct Program {
   std::vector<UlvPanel> panels;
   std::vector<UlvSwap> swaps;
   std::vector<UlvMove> moves;
+  std::vector<UlvSubst> substs;
   void gemm_launch(const std::vector<GemmTask>& ts) {
     if (ts.empty()) return;
     int64_t M = 1, N = 1;
@@ -53,7 +54,7 @@ struct Program {
   template <class T>
   static size_t bytes(const std::vector<T>& v) { return ((sizeof(T) * v.size() + 255) / 256) * 256; }
   size_t device_bytes() const {
-    return bytes(gemms) + bytes(builds) + bytes(panels) + bytes(swaps) + bytes(moves) + 256;
+    return bytes(gemms) + bytes(builds) + bytes(panels) + bytes(swaps) + bytes(moves) + bytes(substs) + 256;
   }
   // uploads the task arrays into dev (device_bytes() bytes) and launches the sequence on s
   void run(char* dev, int32_t nrhs, int32_t* flag, hipStream_t s) const {
@@ -66,6 +67,7 @@ struct Program {
       return at;
     };
     const size_t og = place(gemms), ob = place(builds), op = place(panels), os = place(swaps), om = place(moves);
+    const size_t osb = place(substs);
     HSS_HIP_CHECK(hipMemcpyAsync(dev, host.data(), host.size(), hipMemcpyHostToDevice, s));
     HSS_HIP_CHECK(hipStreamSynchronize(s));   // the staging copy is complete before `host` goes
     const GemmTask* g = (const GemmTask*)(dev + og);
@@ -73,6 +75,7 @@ struct Program {
     const UlvPanel* p = (const UlvPanel*)(dev + op);
     const UlvSwap* w = (const UlvSwap*)(dev + os);
     const UlvMove* mv = (const UlvMove*)(dev + om);
+    const UlvSubst* sb = (const UlvSubst*)(dev + osb);
     for (const Launch& L : seq) {
       switch (L.kind) {
         case kBuild: launch_ulv_build(b + L.off, L.count, L.a, s); break;
@@ -81,6 +84,8 @@ struct Program {
         case kSwap: launch_ulv_swap(w + L.off, L.count, L.a, s); break;
         case kIn: launch_ulv_rhs_in(mv + L.off, L.count, nrhs, L.a, s); break;
         case kOut: launch_ulv_x_out(mv + L.off, L.count, nrhs, L.a, s); break;
+        case kSubstF: launch_ulv_subst(sb + L.off, L.count, nrhs, 0, s); break;
+        case kSubstB: launch_ulv_subst(sb + L.off, L.count, nrhs, 1, s); break;
       }
     }
     HSS_HIP_CHECK(hipGetLastError());
@@ -274,6 +279,8 @@ Program solve_program(const UlvFactor& f, int32_t nrhs, const double* Bp, double
   Program prog;
   const auto levels = by_level(f);
   auto Yof = [&](const UlvFactor::Node& q) { return Y + q.Y * nrhs; };
+  // few right-hand sides: one fused substitution launch per level and pass
+  const bool fused = nrhs <= UST_MAXR;
   // forward, deepest level first
   for (int lev = f.maxlevel; lev >= 0; --lev) {
     const std::vector<int32_t>& L = levels[lev];
@@ -305,6 +312,14 @@ Program solve_program(const UlvFactor& f, int32_t nrhs, const double* Bp, double
     }
     prog.seq.push_back(Launch{kIn, m0, (int32_t)L.size(), maxe, 0});
     prog.gemm_launch(tr);
+    if (fused) {
+      prog.seq.push_back(Launch{kSubstF, (int64_t)prog.substs.size(), (int32_t)L.size(), 0, 0});
+      for (int32_t v : L) {
+        const UlvFactor::Node& q = f.nodes[v];
+        prog.substs.push_back(UlvSubst{Yof(q), f.fpool + q.F, f.ipool + q.inv, f.ppool + q.piv, q.m, q.k});
+      }
+      continue;
+    }
     int32_t nsteps = 0;
     for (int32_t v : L) nsteps = std::max(nsteps, nblocks(f.nodes[v].k));
     for (int32_t st = 0; st < nsteps; ++st) {
@@ -344,6 +359,14 @@ Program solve_program(const UlvFactor& f, int32_t nrhs, const double* Bp, double
                            nrhs, q.r, -1.0, 1.0));
     }
     prog.gemm_launch(urs);
+    if (fused) {
+      prog.seq.push_back(Launch{kSubstB, (int64_t)prog.substs.size(), (int32_t)L.size(), 0, 0});
+      for (int32_t v : L) {
+        const UlvFactor::Node& q = f.nodes[v];
+        prog.substs.push_back(UlvSubst{Yof(q), f.fpool + q.F, f.ipool + q.inv, f.ppool + q.piv, q.m, q.k});
+      }
+      nsteps = 0;
+    }
     for (int32_t st = nsteps - 1; st >= 0; --st) {
       const int32_t jb = st * UNB;
       std::vector<GemmTask> di, ab;

@@ -1,5 +1,8 @@
 """HSS factorization and solve on the GPU (hss_factor / hss_solve).
 
+Up to 16 right-hand sides the solve runs fused per-level substitutions,
+above that one launch per block step; both paths are checked.
+
 The expected solutions come from the oracle's side only: a dense solve of
 the operator's entries (oracle/operators.py), which the solve of the
 compressed matrix must match within kappa(A) times the compression
@@ -47,6 +50,14 @@ def test_solve_matches_dense_solve(family, n, leaf):
     rel = np.linalg.norm(Xh - Xd) / np.linalg.norm(Xd)
     _log("  kappa %.2e  rel %.2e" % (kappa, rel))
     assert rel <= max(1e-12, 20.0 * kappa * rtol)
+    # more right-hand sides than the fused substitutions take: the block-step
+    # GEMM path, the same solution column by column
+    B20 = inputs.gaussian_matrix(n, 20, 12)
+    B20[:, :3] = B
+    X20 = H.solve(dev_colmajor(B20))
+    R20 = (H.matvec(X20) - dev_colmajor(B20)).cpu().numpy()
+    assert np.linalg.norm(R20) <= 1e-10 * np.linalg.norm(B20)
+    assert np.allclose(X20.cpu().numpy()[:, :3], Xh, rtol=0, atol=1e-11 * np.abs(Xh).max())
 
 
 def test_root_leaf_single_rhs_and_call_order():
