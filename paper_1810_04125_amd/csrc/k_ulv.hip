@@ -94,9 +94,9 @@ __global__ __launch_bounds__(UPT) void k_ulv_panel(const UlvPanel* __restrict__ 
   HSS_GLOBAL double* P = F + (int64_t)jb * m;   // P(i, c) = F(i, jb + c), i absolute
   __shared__ double prow[UNB];
   __shared__ double U12[USB][UNB];
-  __shared__ double rv[UPT / 64];
-  __shared__ int ri[UPT / 64];
-  __shared__ int prow_i;
+  __shared__ double rv[2 * 16];
+  __shared__ int ri[2 * 16];
+  static_assert(UPT / 64 <= 16, "wave partials");
   for (int c0 = 0; c0 < nb; c0 += USB) {
     const int ce = min(c0 + USB, nb);
     for (int c = c0; c < ce; ++c) {
@@ -104,6 +104,7 @@ __global__ __launch_bounds__(UPT) void k_ulv_panel(const UlvPanel* __restrict__ 
       // the pivot: largest |P(i, c)| over i in [j, k), the lowest i on ties
       double bv = -1.0;
       int bi = 0x7fffffff;
+#pragma unroll 4
       for (int i = j + tid; i < k; i += UPT) {
         const double v = fabs(P[i + (int64_t)c * m]);
         if (v > bv) { bv = v; bi = i; }
@@ -113,20 +114,22 @@ __global__ __launch_bounds__(UPT) void k_ulv_panel(const UlvPanel* __restrict__ 
         const int oi = __shfl_down(bi, off);
         if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
       }
-      if ((tid & 63) == 0) { rv[tid >> 6] = bv; ri[tid >> 6] = bi; }
+      if ((tid & 63) == 0) { rv[(c & 1) * 16 + (tid >> 6)] = bv; ri[(c & 1) * 16 + (tid >> 6)] = bi; }
       __syncthreads();
-      if (tid == 0) {
-        for (int w = 1; w < UPT / 64; ++w)
-          if (rv[w] > rv[0] || (rv[w] == rv[0] && ri[w] < ri[0])) { rv[0] = rv[w]; ri[0] = ri[w]; }
-        if (!(rv[0] > 0.0)) {   // a zero (or non-finite) column: the block is singular
-          atomicOr(flag, 1);
-          ri[0] = j;
-        }
-        prow_i = ri[0];
-        t.piv[j] = ri[0];
+      // every thread combines the waves' candidates (double-buffered by
+      // column parity, so the next column's partials cannot overwrite them)
+      double pv = rv[(c & 1) * 16];
+      int p = ri[(c & 1) * 16];
+      for (int w = 1; w < UPT / 64; ++w) {
+        const double ov = rv[(c & 1) * 16 + w];
+        const int oi = ri[(c & 1) * 16 + w];
+        if (ov > pv || (ov == pv && oi < p)) { pv = ov; p = oi; }
       }
-      __syncthreads();
-      const int p = prow_i;
+      if (!(pv > 0.0)) p = j;   // a zero (or non-finite) column: the block is singular
+      if (tid == 0) {
+        if (!(pv > 0.0)) atomicOr(flag, 1);
+        t.piv[j] = p;
+      }
       if (tid < nb) {   // the swap across the whole panel; the pivot row's sub-panel part to LDS
         HSS_GLOBAL double* a = P + j + (int64_t)tid * m;
         HSS_GLOBAL double* b = P + p + (int64_t)tid * m;
