@@ -13,7 +13,9 @@ from what is known before sampling, so d0 can start close to it:
     level; log2 of the mean node size at that level; -log10 rtol
   targets (2, masked):
     level >= 1 rows: log2(1 + largest node rank at that level);
-    level 0 (root) row: log2(d_final) of an incrementing run with d0 = delta_d
+    level 0 (root) row: log2(d_final) of an incrementing run started at
+    d0 = 128, the start of the workloads it serves (a run's end depends on
+    its start: a wider first block can pass where a narrower one grows)
   network: 8 -> 128 -> 128 -> 128 -> 2, ReLU, FP32 (hss_mlp_* kernels)
 
 The compression's stopping tests still decide every node: a low
@@ -95,10 +97,11 @@ def rows_of(spec, tree, level_rank, d_final):
     return X, T, M
 
 
-def generate(count, seed, chunk=48, delta_d=64, eta=0.05, d_max=4096, log=print, n_lo=1024, n_hi=32768):
-    """Compress `count` random problems on the GPU (incrementing strategy,
-    d0 = delta_d, R drawn by the library from the seed) and return the
-    training set as a dict of arrays."""
+def generate(count, seed, chunk=48, delta_d=64, eta=0.05, d_max=4096, log=print, n_lo=1024, n_hi=32768,
+             d0=128):
+    """Compress `count` random problems on the GPU (incrementing strategy
+    from `d0` in steps of delta_d, R drawn by the library from the seed) and
+    return the training set as a dict of arrays."""
     specs = inputs.learned_problems(count, seed, n_lo, n_hi)
     X, T, M = [], [], []
     dropped = 0
@@ -109,7 +112,7 @@ def generate(count, seed, chunk=48, delta_d=64, eta=0.05, d_max=4096, log=print,
         probs = [make_problem(s) for s in part]
         Hs, _ = hss.compress_batched([p[0] for p in probs], [p[1] for p in probs], None,
                                      rtol=[s["rtol"] for s in part], atol=1e-12, eta=eta,
-                                     strategy="inc_fnorm", d0=delta_d, delta_d=delta_d,
+                                     strategy="inc_fnorm", d0=d0, delta_d=delta_d,
                                      d_max=[min(d_max, s["n"]) for s in part], seed=seed + 1)
         for s, (gen, tree), H in zip(part, probs, Hs):
             info = H.info()
@@ -135,6 +138,7 @@ def generate(count, seed, chunk=48, delta_d=64, eta=0.05, d_max=4096, log=print,
     out = {"X": np.array(X, np.float32), "T": np.array(T, np.float32), "M": np.array(M, np.float32)}
     out.update({"p_" + k: np.array(v) for k, v in meta.items()})
     out["p_eta"] = np.array([eta])
+    out["p_d0"] = np.array([d0])
     return out
 
 
@@ -155,9 +159,13 @@ def merge(a, b, every):
     src, grp = (a, b), (ga, gb)
     out = {k: np.concatenate([src[w][k][grp[w][i][0]:grp[w][i][1]] for w, i in order]) for k in ("X", "T", "M")}
     for k in a:
-        if k.startswith("p_") and k != "p_eta" and k in b:
+        if k.startswith("p_") and k not in ("p_eta", "p_d0") and k in b:
             out[k] = np.array([src[w][k][i] for w, i in order])
     out["p_eta"] = a.get("p_eta", np.array([0.05]))
+    if "p_d0" in a:
+        if "p_d0" in b and int(b["p_d0"][0]) != int(a["p_d0"][0]):
+            raise ValueError("the two sets were labelled from different starts d0")
+        out["p_d0"] = a["p_d0"]
     return out
 
 
@@ -246,6 +254,7 @@ def _main():
     g.add_argument("--n-lo", type=int, default=1024)
     g.add_argument("--n-hi", type=int, default=32768)
     g.add_argument("--d-max", type=int, default=4096)
+    g.add_argument("--d0", type=int, default=128, help="start of the labelling runs")
     g.add_argument("--merge-into", default=None,
                    help="an existing set: write it with the new problems interleaved (one after every k-th)")
     g.add_argument("--every", type=int, default=4)
@@ -267,7 +276,7 @@ def _main():
     log = lambda m: print(m, flush=True)
     if a.cmd == "generate":
         d = generate(a.count, a.seed, chunk=a.chunk, eta=a.eta, log=log, n_lo=a.n_lo, n_hi=a.n_hi,
-                     d_max=a.d_max)
+                     d_max=a.d_max, d0=a.d0)
         if a.merge_into:
             with np.load(a.merge_into, allow_pickle=False) as z:
                 d = merge({k: z[k] for k in z.files}, d, a.every)
