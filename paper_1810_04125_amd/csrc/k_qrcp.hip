@@ -663,7 +663,10 @@ void run_qrcp(QrcpTask* tasks, int32_t ntasks, const QrcpWork& wk, const int2* w
     hipLaunchKernelGGL(k_qrcp_plan, dim3(1), dim3(QB), 0, s, tasks, ntasks, target, wk.chunks, wk.meta);
     hipLaunchKernelGGL(k_qrcp_init, dim3(nwg), dim3(QB), 0, s, tasks, wk.chunks, wk.meta, wk.kbuf);
     prof_end(HSS_K_QRCP_OTHER, s);
-    if (solve_e && dmax >= 128) run_qr_first(tasks, ntasks, dmax, ncols_max, sc, gtasks, gws, s, kcnt);
+    // QR first shortens the one-pivot steps of tall panels; the blocked ID
+    // factors them directly (its per-block work is GEMMs over the panel,
+    // while the reduction's 32-column panels run on one workgroup each)
+    if (solve_e && dmax >= 128 && !blocks) run_qr_first(tasks, ntasks, dmax, ncols_max, sc, gtasks, gws, s, kcnt);
   }
   // pivot steps: launched back to back in segments of 32 after liveness
   // polls (none before the first segment when a panel is known to be
