@@ -628,7 +628,7 @@ def id_roofline(stats):
     tf = idc["flops"] / sec / 1e12
     gb = idc["bytes"] / sec / 1e9
     return {"kernels": "k_idb_* + block GEMMs, k_qrcp_wg/step (small or very wide panels), "
-                       "k_qrcp_plan/init/alive/fin, k_qrfirst*, k_trsm_diag",
+                       "k_qrcp_plan/init/alive/fin/count, k_trsm_diag",
             "id_calls": idc["launches"], "ms": round(ms, 2), "alg_tflop": round(idc["flops"] / 1e12, 4),
             "alg_gb": round(idc["bytes"] / 1e9, 3), "achieved_tflops": round(tf, 3),
             "frac_fp64_peak": round(tf / PEAK_FP64_TFLOPS, 5), "achieved_GBps": round(gb, 1),

@@ -157,10 +157,6 @@ struct QrcpTask {
   double hmt_mn;     // > 0: HMT factor with sqrt(hmt_mn); 0: plain threshold
   int32_t m, d, mcap, active;
   int32_t nopivot;   // 1: plain Householder QR (column k is the k-th pivot)
-  double* qrf = nullptr;     // workspace of the QR-first reduction of a tall panel (k_qrfirst.hip)
-  int64_t qrf_elems = 0;
-  int32_t d_orig = 0;        // samples of the local sample (d before a QR-first reduction); 0: d
-  int32_t pad2 = 0;
 };
 
 // Explicit Q of a Householder QR done by run_qrcp in nopivot mode:
@@ -265,7 +261,7 @@ struct IdBlockWork {
   int32_t max_tasks = 0;
 };
 // The block pivot steps of one factorization call, after the panels and
-// their norms are in place (k_qrcp_init, QR first); hw_dev / hw: a mapped
+// their norms are in place (k_qrcp_init); hw_dev / hw: a mapped
 // host word for the liveness polls.
 void run_id_blocks(QrcpTask* tasks, int32_t ntasks, const IdBlockWork& bw, int32_t dmax, int32_t mmax,
                    int32_t* hw_dev, const int32_t* hw, double* gws, hipStream_t s, unsigned long long* kcnt);
@@ -278,22 +274,8 @@ void run_qrcp(QrcpTask* tasks, int32_t ntasks, const QrcpWork& wk, const int2* w
               int32_t kmax, int32_t dmax, int32_t ncols_max, int32_t* flag, GemmTask* gtasks, int32_t mcap_max,
               hipStream_t s, unsigned long long* kcnt = nullptr, bool solve_e = true, double* gws = nullptr,
               const IdBlockWork* bw = nullptr);
-// Reduce tall ID panels (d >= 2 m) to their m x m triangle before the
-// pivoted steps (k_qrfirst.hip), when the rows this takes out of every
-// pivot step, summed over the tall panels, reach kQrFirstMinCells: below
-// that the steps are bound by launch latency rather than by their
-// traffic, and the reduction's own launches would not pay.
-constexpr int64_t kQrFirstMinCells = int64_t(2) << 20;
-// Host-synchronous scan of the panels of a factorization call: the largest
-// m and the summed (d - m) m of the tall ones, and the number of active ones.
-struct QrfScan {
-  int32_t mtall = 0;
-  int64_t cells = 0;
-  int32_t nact = 0;
-};
-QrfScan qrf_scan(const QrcpTask* tasks, int32_t ntasks, hipStream_t s);
-void run_qr_first(QrcpTask* tasks, int32_t ntasks, int32_t dmax, int32_t mcap_max, const QrfScan& sc,
-                  GemmTask* gtasks, double* gws, hipStream_t s, unsigned long long* kcnt);
+// Host-synchronous count of the active panels of a factorization call.
+int32_t count_active_panels(const QrcpTask* tasks, int32_t ntasks, hipStream_t s);
 void run_qform(QformTask* tasks, int32_t count, const int2* wg, int32_t nwg, int32_t cpw, int32_t ncmax,
                int32_t mmax, GemmTask* gt, double* gws, hipStream_t s, unsigned long long* kcnt);
 

@@ -848,7 +848,6 @@ __global__ void k_hmt_reo_qr(LevelArgs a, int side, QrcpTask* __restrict__ qt) {
   q.er = 0.0; q.ea = 0.0; q.hmt_mn = 0.0;
   q.m = st.bnc; q.d = st.m[side]; q.mcap = st.bnc; q.active = 1;
   q.nopivot = 1;
-  q.qrf = nullptr; q.qrf_elems = 0;
   qt[t] = q;
 }
 
@@ -978,14 +977,8 @@ __global__ void k_build_qrcp(LevelArgs a, int side, int hmt, QrcpTask* __restric
   q.hmt_mn = hmt ? (double)min(size, P.n - size) : 0.0;
   q.m = st.m[side];
   q.d = P.d;
-  q.d_orig = P.d;
   q.mcap = nd.mcap;
   q.nopivot = 0;
-  // QR-first workspace: the rest of the node's wsB slot after the scratch
-  const int64_t slot = max((int64_t)nd.qcap * P.dcap, 16 + 2 * ((int64_t)nd.mcap + P.dcap));
-  const int64_t off = (16 + 3 * (int64_t)nd.mcap + 7) / 8 * 8;
-  q.qrf = slot > off ? q.scr + off : nullptr;
-  q.qrf_elems = slot > off ? slot - off : 0;
   out[t] = q;
 }
 

@@ -472,6 +472,33 @@ static int32_t* host_words(int32_t** dev) {
   return p;
 }
 
+// Active panels of a factorization call, written to out[0] (mapped host
+// memory).  One workgroup.
+__global__ __launch_bounds__(QAL) void k_qrcp_count(const QrcpTask* __restrict__ tasks, int ntasks,
+                                                   int32_t* __restrict__ out) {
+  __shared__ int sa[QAL / 64];
+  int act = 0;
+  for (int i = threadIdx.x; i < ntasks; i += QAL) act += tasks[i].active ? 1 : 0;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) act += __shfl_xor(act, o, 64);
+  if ((threadIdx.x & 63) == 0) sa[threadIdx.x >> 6] = act;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int a = 0;
+    for (int w = 0; w < QAL / 64; ++w) a += sa[w];
+    out[0] = a;
+  }
+}
+
+int32_t count_active_panels(const QrcpTask* tasks, int32_t ntasks, hipStream_t s) {
+  if (ntasks <= 0) return 0;
+  int32_t* hw_dev = nullptr;
+  int32_t* hw = host_words(&hw_dev);
+  hipLaunchKernelGGL(k_qrcp_count, dim3(1), dim3(QAL), 0, s, tasks, ntasks, hw_dev + 2);
+  HSS_HIP_CHECK(hipStreamSynchronize(s));
+  return hw[2];
+}
+
 // rank, the ascending rest of J, max rank of the batch
 __global__ __launch_bounds__(QB) void k_qrcp_fin(const QrcpTask* __restrict__ tasks, int32_t* maxrank,
                                                  unsigned long long* __restrict__ kcnt) {
@@ -510,8 +537,7 @@ __global__ __launch_bounds__(QB) void k_qrcp_fin(const QrcpTask* __restrict__ ta
     if (maxrank) atomicMax(maxrank, r);
     // the ID's algorithmic work: the d x m panel read once, E written, and
     // 4 d m r flops of a QR with column pivoting to rank r
-    const double d0 = (double)max(d, t.d_orig);
-    if (!t.nopivot) kcount(kcnt, HSS_K_ID, 8.0 * d0 * m + 8.0 * (double)r * (m - r), 4.0 * d0 * m * r);
+    if (!t.nopivot) kcount(kcnt, HSS_K_ID, 8.0 * (double)d * m + 8.0 * (double)r * (m - r), 4.0 * (double)d * m * r);
   }
 }
 
@@ -632,12 +658,12 @@ void run_qrcp(QrcpTask* tasks, int32_t ntasks, const QrcpWork& wk, const int2* w
   const int target = tune().qrcp_wg;   // kQrcpTarget by default
   const int nwg = 2 * target + ntasks;
   const size_t lds = (size_t)std::max(dmax, 1) * sizeof(double);
-  // The ID first counts its active panels (and finds the tall ones): with
-  // none it is done, and the count picks the factorization kernel.
-  QrfScan sc;
+  // The ID first counts its active panels: with none it is done, and the
+  // count picks the factorization kernel.
+  int32_t nact = 0;
   if (solve_e) {
-    sc = qrf_scan(tasks, ntasks, s);
-    if (sc.nact == 0) return;
+    nact = count_active_panels(tasks, ntasks, s);
+    if (nact == 0) return;
   }
   const bool known_active = solve_e;   // some panel is known to be active
   const int64_t cells = (int64_t)std::max(dmax, 1) * std::max(ncols_max, 1);
@@ -650,7 +676,7 @@ void run_qrcp(QrcpTask* tasks, int32_t ntasks, const QrcpWork& wk, const int2* w
     // ID about 10 us on the sphere-Laplace levels (a block of 12 launches
     // per 19 pivots on average), so small panels stay on one workgroup.
     const double t_wg = 5.0 + 2.2 * std::ceil(ncols_max / 16.0);
-    const double t_step = std::max(7.0, 2.35e-6 * (double)sc.nact * (double)cells);
+    const double t_step = std::max(7.0, 2.35e-6 * (double)nact * (double)cells);
     one_wg = t_wg < t_step;
   }
   const bool blocks = !one_wg && solve_e && bw && bw->blk && ncols_max <= kIdbMaxM;
@@ -663,10 +689,6 @@ void run_qrcp(QrcpTask* tasks, int32_t ntasks, const QrcpWork& wk, const int2* w
     hipLaunchKernelGGL(k_qrcp_plan, dim3(1), dim3(QB), 0, s, tasks, ntasks, target, wk.chunks, wk.meta);
     hipLaunchKernelGGL(k_qrcp_init, dim3(nwg), dim3(QB), 0, s, tasks, wk.chunks, wk.meta, wk.kbuf);
     prof_end(HSS_K_QRCP_OTHER, s);
-    // QR first shortens the one-pivot steps of tall panels; the blocked ID
-    // factors them directly (its per-block work is GEMMs over the panel,
-    // while the reduction's 32-column panels run on one workgroup each)
-    if (solve_e && dmax >= 128 && !blocks) run_qr_first(tasks, ntasks, dmax, ncols_max, sc, gtasks, gws, s, kcnt);
   }
   // pivot steps: launched back to back in segments of 32 after liveness
   // polls (none before the first segment when a panel is known to be

@@ -309,9 +309,8 @@ def test_release_cache_between_compressions():
 @pytest.mark.parametrize("strategy", ["inc_fnorm", "dbl_fnorm"])
 def test_compress_large_first_block_tall_panels(strategy):
     """A first block of 1024 columns: the IDs of the lower levels factor
-    tall panels (d >= 2 m), which are reduced to their m x m triangle by a
-    blocked Householder QR before the pivoted steps; ranks, rounds and the
-    error must match the oracle's direct QRCP."""
+    tall panels (d >= 2 m) with the block-pivoted ID; ranks, rounds and the
+    error must match the oracle's QRCP."""
     _log("compress laplace 4096 d0=1024 " + strategy)
     n = 4096
     gen, T, ot, op = problem("laplace", n, 128, seed=3)
