@@ -70,6 +70,15 @@ struct GenHolder {
       double* t = (double*)alloc(sizeof(double) * gen.n);
       launch_toeplitz_table(t, gen.n, gen.h, s);
       g.tcol = t;
+      std::vector<int64_t> hp((size_t)gen.n);
+      HSS_HIP_CHECK(hipMemcpyAsync(hp.data(), perm, sizeof(int64_t) * gen.n, hipMemcpyDeviceToHost, s));
+      HSS_HIP_CHECK(hipStreamSynchronize(s));
+      g.perm_id = 1;
+      for (int64_t i = 0; i < gen.n; ++i)
+        if (hp[i] != i) {
+          g.perm_id = 0;
+          break;
+        }
     } else if (gen.family == HSS_FAM_DENSE) {
       if (!gen.dense || gen.ld < gen.n) throw Error(HSS_ERR_INVALID_ARG, "dense needs dense, ld >= n");
       g.dense = gen.dense;

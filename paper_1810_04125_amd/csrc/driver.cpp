@@ -670,6 +670,12 @@ void Job::setup(int32_t count, const hss_generator* gens, const hss_tree* const*
       double* t = (double*)dalloc(sizeof(double) * P.n);
       launch_toeplitz_table(t, P.n, P.gen.h, stream);
       g.tcol = t;
+      g.perm_id = 1;   // index bisection keeps the order: entries from the sampling window
+      for (int64_t i = 0; i < P.n; ++i)
+        if (P.perm[i] != i) {
+          g.perm_id = 0;
+          break;
+        }
     }
     if (P.gen.family == HSS_FAM_LAPLACE || P.gen.family == HSS_FAM_GAUSS) {
       double* pts = (double*)dalloc(sizeof(double) * 3 * P.n);

@@ -35,7 +35,7 @@ struct GenDev {
   const int32_t* leaf_lo;  // per permuted index: range of its leaf (reduced-precision
   const int32_t* leaf_hi;  // sampling skips these diagonal blocks when offdiag = 1)
   int32_t offdiag;
-  int32_t pad;
+  int32_t perm_id;    // 1: perm is the identity (Toeplitz entries from an LDS window)
 };
 
 // The generated families are symmetric; dense and caller operators say

@@ -72,6 +72,10 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
   return fma(y * e, fma(0.375, e, 0.5), y);
 }
 
+// Kernel variant of HSS_FAM_TOEPLITZ for the identity permutation (index
+// bisection): entries from an LDS window of t(|i - j|) per tile pair.
+constexpr int kFamToeplitzWindow = 16;
+
 template <int FAM>
 __device__ __forceinline__ double entry_t(const GenDev& g, int64_t i, int64_t j) {
   if constexpr (FAM == HSS_FAM_TOEPLITZ) return toeplitz_entry(g, i, j);
@@ -93,10 +97,13 @@ __global__ __launch_bounds__(SM_T, 2) void k_sample_f64(GenDev g, const double* 
                                                      int64_t lds, int32_t ncols, int64_t kchunk,
                                                      int32_t nsplit) {
   constexpr bool PTS = FAM == HSS_FAM_LAPLACE || FAM == HSS_FAM_GAUSS;
+  constexpr bool TOEP = FAM == kFamToeplitzWindow;
   constexpr int COLS = 16 * NCB;
   constexpr int ROWS = 64 * NH;
+  constexpr int TW = ROWS + SM_BK - 1;   // Toeplitz window: t(|i - j|) over one tile pair
   __shared__ double Rs[SM_BK][COLS + 2];
   __shared__ double Ps[PTS ? SM_BK : 1][3];   // points of the K rows of the tile
+  __shared__ double Tw[TOEP ? TW : 1];
   const int64_t n = g.n;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -132,10 +139,15 @@ __global__ __launch_bounds__(SM_T, 2) void k_sample_f64(GenDev g, const double* 
     for (int c = 0; c < NCB; ++c) acc[h][c] = dbl4{0.0, 0.0, 0.0, 0.0};
 
   // R(kt:kt+BK, col0:col0+COLS) and the tile's points are loaded into
-  // registers one tile ahead, then stored to LDS (Rs[k][c], Ps[k][xyz])
+  // registers one tile ahead, then stored to LDS (Rs[k][c], Ps[k][xyz]).
+  // With the identity permutation a Toeplitz entry t(|i - j|) of the tile
+  // pair (rows rb0.., K rows kt..) is Tw[i - j - (rb0 - kt - BK + 1)]: the
+  // window of its ROWS + BK - 1 distinct values is staged the same way.
   constexpr int RPT = SM_BK * COLS / SM_T;
+  static_assert(TW <= SM_T, "one window value per thread");
+  const int64_t rb0 = (int64_t)blockIdx.x * ROWS, rb1 = rb0 + ROWS;   // rows of the workgroup
   double rr[RPT];
-  double pp = 0.0;
+  double pp = 0.0, tw = 0.0;
   auto load_tile = [&](int64_t kt) {
 #pragma unroll
     for (int e = 0; e < RPT; ++e) {
@@ -151,9 +163,15 @@ __global__ __launch_bounds__(SM_T, 2) void k_sample_f64(GenDev g, const double* 
         pp = gk < ke ? g.pts[3 * kt + threadIdx.x] : 0.0;
       }
     }
+    if constexpr (TOEP) {
+      if (threadIdx.x < TW) {
+        int64_t o = rb0 - kt - (SM_BK - 1) + threadIdx.x;
+        o = o < 0 ? -o : o;
+        tw = o < n ? g.tcol[o] : 0.0;   // beyond n only for rows or K rows outside the matrix
+      }
+    }
   };
   if (kb < ke) load_tile(kb);
-  const int64_t rb0 = (int64_t)blockIdx.x * ROWS, rb1 = rb0 + ROWS;   // rows of the workgroup
   for (int64_t kt = kb; kt < ke; kt += SM_BK) {
 #pragma unroll
     for (int e = 0; e < RPT; ++e) {
@@ -163,11 +181,39 @@ __global__ __launch_bounds__(SM_T, 2) void k_sample_f64(GenDev g, const double* 
     if constexpr (PTS) {
       if (threadIdx.x < SM_BK * 3) Ps[threadIdx.x / 3][threadIdx.x % 3] = pp;
     }
+    if constexpr (TOEP) {
+      if (threadIdx.x < TW) Tw[threadIdx.x] = tw;
+    }
     __syncthreads();
     if (kt + SM_BK < ke) load_tile(kt + SM_BK);
     // A tile inside the matrix and off its diagonal needs neither the
     // bounds nor the diagonal selects: the kernel families take a short
     // path there (all but the few tiles that meet the diagonal or an edge).
+    if constexpr (TOEP) {
+      // entries from the LDS window (the diagonal's t(0) included); rows
+      // and K rows outside the matrix are masked on the edge tiles only
+      const bool inner = rb1 <= n && kt + SM_BK <= ke;
+      const int wb = wave * 16 * NH + (lane & 15) - kq + SM_BK - 1;
+#pragma unroll 2
+      for (int kk = 0; kk < SM_BK; kk += 4) {
+        const bool k_ok = kt + kk + kq < ke;
+        double a[NH];
+#pragma unroll
+        for (int h = 0; h < NH; ++h) {
+          a[h] = Tw[wb + 16 * h - kk];
+          if (!inner) a[h] = (row_ok[h] && k_ok) ? a[h] : 0.0;
+        }
+#pragma unroll
+        for (int c = 0; c < NCB; ++c) {
+          const double b = Rs[kk + kq][c * 16 + (lane & 15)];
+#pragma unroll
+          for (int h = 0; h < NH; ++h)
+            acc[h][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[h], b, acc[h][c], 0, 0, 0);
+        }
+      }
+      __syncthreads();
+      continue;
+    }
     bool fast = false;
     if constexpr (PTS) fast = rb1 <= n && kt + SM_BK <= ke && (kt + SM_BK <= rb0 || kt >= rb1);
     if (fast) {
@@ -341,6 +387,14 @@ static void launch_fam(const GenDev& g, int transpose, const double* R, int64_t 
                        int64_t lds, int32_t ncols, int64_t kchunk, int nsplit, dim3 grid,
                        SampleTile t, hipStream_t s) {
   if constexpr (FAM == HSS_FAM_TOEPLITZ) {
+    // the entries are symmetric: the transposed product is the same one
+    if (g.perm_id) {
+      if (t.cols == SM_COLS_W)
+        launch_fam<kFamToeplitzWindow, 2, 8>(g, 0, R, ldr, out, lds, ncols, kchunk, nsplit, grid, s);
+      else
+        launch_fam<kFamToeplitzWindow, 2, 4>(g, 0, R, ldr, out, lds, ncols, kchunk, nsplit, grid, s);
+      return;
+    }
     if (t.cols == SM_COLS_W) {
       launch_fam<FAM, 2, 8>(g, transpose, R, ldr, out, lds, ncols, kchunk, nsplit, grid, s);
       return;

@@ -4,6 +4,7 @@ import pytest
 
 from oracle.hss import compress as ocompress, interpolative
 from oracle.matvec import hss_matvec as omatvec, rel_error as orel
+from oracle.operators import PermutedOperator, Toeplitz
 from paper_1810_04125_amd import hss, inputs
 from tests.gpu_util import dev, dev_colmajor, problem
 
@@ -25,6 +26,23 @@ def test_sampling_matches_dense_product(family, n, leaf, ncols):
     ref = op.dense() @ R
     err = np.linalg.norm(S - ref, axis=0) / np.linalg.norm(ref, axis=0)
     assert err.max() <= 1e-12
+
+
+@pytest.mark.parametrize("n,ncols", [(1000, 70), (3000, 128)])
+def test_sampling_toeplitz_any_permutation(n, ncols):
+    """Toeplitz sampling under the index-bisection tree takes its entries
+    from an LDS window of t(|i - j|), which needs the identity permutation;
+    under any other permutation the kernel reads the table by permuted
+    index.  Both must give the oracle's product (a random permutation, and
+    the identity again, on the same inputs)."""
+    _log("sample toeplitz perms n=%d ncols=%d" % (n, ncols))
+    gen = hss.toeplitz(n, 0.1)
+    R = inputs.gaussian_matrix(n, ncols, 5)
+    for perm in (np.random.default_rng(11).permutation(n).astype(np.int64), np.arange(n, dtype=np.int64)):
+        ref = PermutedOperator(Toeplitz(n, 0.1), perm).dense() @ R
+        S = hss.sample(gen, dev(perm), dev_colmajor(R)).cpu().numpy()
+        err = np.linalg.norm(S - ref, axis=0) / np.linalg.norm(ref, axis=0)
+        assert err.max() <= 1e-12
 
 
 @pytest.mark.parametrize("family,n,leaf", [("toeplitz", 80000, 128), ("gauss", 40000, 256)])
