@@ -101,8 +101,8 @@ WORKLOADS = {
 TRAFFIC = {
     ("laplace-sphere-32768", "SAMPLE"): {
         "source": "paper_1810_04125_amd/csrc/k_sample.hip",
-        "sha256": "74ad7940505467123688df4a495769f4cd6d2282639d319bdc8a988a1d6d43e0",
-        "fetch_kib": 71868.0, "write_kib": 131072.0,               # k_sample_f64, 44 dispatches
+        "sha256": "aed9b951c64de8d3ef7a6981b256ef75861c7a2a900365e930d5300e75827d8b",
+        "fetch_kib": 71851.3, "write_kib": 131072.0,               # k_sample_f64, 44 dispatches
         "fetch_scale": 1048576.0 / 524302.0, "write_scale": 1.0,   # 1 GiB copy: FETCH 524302 KiB, WRITE 1048576 KiB
     },
 }
@@ -114,9 +114,9 @@ TRAFFIC = {
 # SQ_INSTS_VALU_MFMA_MOPS_F64 (512 flops per MOP).
 SAMPLE_COUNTERS = {
     ("laplace-sphere-32768", "fp64"): {
-        "source_sha256": "74ad7940505467123688df4a495769f4cd6d2282639d319bdc8a988a1d6d43e0",
-        "mfma_busy_frac": round(4.39258e9 / (4 * 1.67236e9), 4),
-        "valu_active_frac": round(4.39561e8 / (4 * 1.67236e9), 4),
+        "source_sha256": "aed9b951c64de8d3ef7a6981b256ef75861c7a2a900365e930d5300e75827d8b",
+        "mfma_busy_frac": round(4.39258e9 / (4 * 1.67249e9), 4),
+        "valu_active_frac": round(4.39561e8 / (4 * 1.67249e9), 4),
         "mfma_valu_coexec_cycles": 0,
         "mfma_flops_per_dispatch": 2.74536e8 * 512,
         "valu_fp64_flops_per_dispatch": 3.08853e8,
