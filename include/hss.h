@@ -183,6 +183,12 @@ void hss_tree_free(hss_tree* tree);
  * sample count 2^y (output 1 of the root row) rounded to the nearest
  * multiple of delta_d, within [delta_d, min(d_max, n)].  The stopping tests still
  * decide every node: a low prediction costs rounds, a high one samples.
+ * The prediction also sizes the compression's sample capacity (its
+ * device memory grows with it): twice the predicted count rounded up to a
+ * multiple of delta_d, at least d0 + 4 delta_d, at most d_max.  A run
+ * that reaches that capacity with its root still open is restarted from
+ * scratch with options.d_max, starting from the capacity it reached (its
+ * statistics are those of the restarted run).
  * Only for HSS_FAM_TOEPLITZ, HSS_FAM_LAPLACE and HSS_FAM_GAUSS with the
  * incrementing strategies; options.d0 is then ignored. */
 #define HSS_MLP_MAX_LAYERS 6

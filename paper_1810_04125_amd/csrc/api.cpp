@@ -318,58 +318,101 @@ hss_status hss_compress_batched(int32_t count, const hss_generator* gens, const 
       if (!trees[k]) throw Error(HSS_ERR_INVALID_ARG, "NULL tree");
     // every argument is checked on the host before the first HIP call
     for (int32_t k = 0; k < count; ++k) Job::validate(gens[k], trees[k], opts[k], k);
-    // learned starts: the predictor's d0 replaces options.d0
+    // learned starts: the predictor's d0 replaces options.d0, and its
+    // predicted final count sizes the compression's sample capacity (the
+    // transient buffers grow with d_max): twice the prediction, at least
+    // four rounds past d0, at most the caller's d_max.  A run that reaches
+    // that capacity before its root compresses is restarted from scratch
+    // with the caller's d_max, starting from the capacity it reached.
     std::vector<hss_options> op(opts, opts + count);
     std::vector<double> dpred(count, 0.0);
-    for (int32_t k = 0; k < count; ++k)
-      if (op[k].predictor) op[k].d0 = predict_d0(gens[k], trees[k], op[k], (hipStream_t)op[k].stream, &dpred[k]);
-    opts = op.data();
+    std::vector<int32_t> cap_dmax(count, 0);
+    for (int32_t k = 0; k < count; ++k) {
+      if (!op[k].predictor) continue;
+      op[k].d0 = predict_d0(gens[k], trees[k], op[k], (hipStream_t)op[k].stream, &dpred[k]);
+      const int64_t dd = op[k].delta_d;
+      const int64_t want = std::max<int64_t>((int64_t)op[k].d0 + 4 * dd,
+                                             dd * (int64_t)std::ceil(2.0 * dpred[k] / (double)dd));
+      if (want < op[k].d_max) {
+        cap_dmax[k] = op[k].d_max;   // the caller's, for a restart
+        op[k].d_max = (int32_t)want;
+      }
+    }
+    std::vector<std::unique_ptr<hss_matrix>> res(count);
+    hss_status worst = HSS_OK;
     // Problems are taken in order into groups whose estimated device memory
     // fits the free HBM at the time the group starts (earlier groups keep only
     // their generators); every group is one level-batched job.
-    std::vector<std::unique_ptr<hss_matrix>> res(count);
-    hss_status worst = HSS_OK;
-    int32_t g0 = 0;
-    while (g0 < count) {
-      size_t free_b = 0, total_b = 0;
-      HSS_HIP_CHECK(hipMemGetInfo(&free_b, &total_b));
-      free_b += arena_idle_bytes();   // the cached transient block is reusable
-      const size_t budget = std::min<size_t>((size_t)(0.6 * (double)free_b), (size_t)80 << 30);
-      size_t acc = 0, shared = 0;
-      int32_t g1 = g0;
-      while (g1 < count) {
-        size_t sh = 0;
-        const size_t b = Job::estimate_bytes(gens[g1], trees[g1], opts[g1], &sh);
-        if (g1 > g0 && acc + b + std::max(shared, sh) > budget) break;
-        acc += b;
-        shared = std::max(shared, sh);
-        ++g1;
+    auto run_groups = [&](const std::vector<int32_t>& idx) {
+      std::vector<hss_generator> gv;
+      std::vector<const hss_tree*> tv;
+      std::vector<hss_options> ov;
+      for (int32_t k : idx) {
+        gv.push_back(gens[k]);
+        tv.push_back(trees[k]);
+        ov.push_back(op[k]);
       }
-      acc += shared;
-      auto job = std::make_shared<Job>();
-      // launch shapes from the tunables table (the group's first problem)
-      const hss_tunables tv = tunables_for(gens[g0].family, opts[g0].sample_precision, gens[g0].n);
-      TuneScope scope(tv);
-      const auto t0 = std::chrono::steady_clock::now();
-      job->setup(g1 - g0, gens + g0, trees + g0, opts + g0);
-      const auto t1 = std::chrono::steady_clock::now();
-      job->compress();
-      if (std::getenv("HSS_TRACE")) {
-        const auto t2 = std::chrono::steady_clock::now();
-        std::fprintf(stderr,
-                     "[hss] group %d..%d: est %.1f GB (free %.1f GB), setup %.1f ms (alloc %.1f ms), compress "
-                     "%.1f ms, sample %.1f ms\n",
-                     g0, g1, acc / 1e9, free_b / 1e9, std::chrono::duration<double, std::milli>(t1 - t0).count(),
-                     job->alloc_ms, std::chrono::duration<double, std::milli>(t2 - t1).count(), job->sample_ms);
+      const int32_t cnt = (int32_t)idx.size();
+      int32_t g0 = 0;
+      while (g0 < cnt) {
+        size_t free_b = 0, total_b = 0;
+        HSS_HIP_CHECK(hipMemGetInfo(&free_b, &total_b));
+        free_b += arena_idle_bytes();   // the cached transient block is reusable
+        const size_t budget = std::min<size_t>((size_t)(0.6 * (double)free_b), (size_t)80 << 30);
+        size_t acc = 0, shared = 0;
+        int32_t g1 = g0;
+        while (g1 < cnt) {
+          size_t sh = 0;
+          const size_t b = Job::estimate_bytes(gv[g1], tv[g1], ov[g1], &sh);
+          if (g1 > g0 && acc + b + std::max(shared, sh) > budget) break;
+          acc += b;
+          shared = std::max(shared, sh);
+          ++g1;
+        }
+        acc += shared;
+        auto job = std::make_shared<Job>();
+        // launch shapes from the tunables table (the group's first problem)
+        const hss_tunables tu = tunables_for(gv[g0].family, ov[g0].sample_precision, gv[g0].n);
+        TuneScope scope(tu);
+        const auto t0 = std::chrono::steady_clock::now();
+        job->setup(g1 - g0, gv.data() + g0, tv.data() + g0, ov.data() + g0);
+        const auto t1 = std::chrono::steady_clock::now();
+        job->compress();
+        if (std::getenv("HSS_TRACE")) {
+          const auto t2 = std::chrono::steady_clock::now();
+          std::fprintf(stderr,
+                       "[hss] group %d..%d: est %.1f GB (free %.1f GB), setup %.1f ms (alloc %.1f ms), compress "
+                       "%.1f ms, sample %.1f ms\n",
+                       g0, g1, acc / 1e9, free_b / 1e9, std::chrono::duration<double, std::milli>(t1 - t0).count(),
+                       job->alloc_ms, std::chrono::duration<double, std::milli>(t2 - t1).count(), job->sample_ms);
+        }
+        for (int32_t q = g0; q < g1; ++q) {
+          const int32_t k = idx[q];
+          job->probs[q - g0].d_pred = dpred[k];
+          res[k].reset(new hss_matrix);
+          res[k]->job = job;
+          res[k]->k = q - g0;
+        }
+        g0 = g1;
       }
-      for (int32_t k = g0; k < g1; ++k) {
-        job->probs[k - g0].d_pred = dpred[k];
-        if (job->probs[k - g0].status > worst) worst = job->probs[k - g0].status;
-        res[k].reset(new hss_matrix);
-        res[k]->job = job;
-        res[k]->k = k - g0;
-      }
-      g0 = g1;
+    };
+    std::vector<int32_t> all(count);
+    for (int32_t k = 0; k < count; ++k) all[k] = k;
+    run_groups(all);
+    // hard restarts of the learned starts that outgrew their capacity
+    std::vector<int32_t> again;
+    for (int32_t k = 0; k < count; ++k) {
+      // (force: d reached the capacity with the root open, whatever the status)
+      if (!cap_dmax[k] || !res[k]->job->probs[res[k]->k].force) continue;
+      op[k].d0 = op[k].d_max;
+      op[k].d_max = cap_dmax[k];
+      res[k].reset();
+      again.push_back(k);
+    }
+    if (!again.empty()) run_groups(again);
+    for (int32_t k = 0; k < count; ++k) {
+      const hss_status st = res[k]->job->probs[res[k]->k].status;
+      if (st > worst) worst = st;
     }
     for (int32_t k = 0; k < count; ++k) out[k] = res[k].release();
     if (worst == HSS_NOT_CONVERGED) g_last_error = "d reached d_max before the root compressed";

@@ -88,3 +88,28 @@ def test_low_prediction_falls_back_to_the_adaptive_rounds():
     kw = dict(rtol=1e-6, atol=1e-12, eta=0.1, strategy="inc_fnorm", delta_d=64, d_max=2048)
     H, st = hss.compress(gen, T, R, d0=64, **kw)
     assert st == hss.OK and H.rel_error() <= 1e-6 and H.info()["rounds"] > 3
+
+
+def test_low_prediction_outgrows_its_capacity_and_restarts():
+    """A network that always predicts 64 final samples: the compression
+    starts at d0 = 64 with a capacity of d0 + 4 delta_d = 320 columns, which
+    a sphere-Laplace problem of n = 4096 outgrows; it is then restarted from
+    320 with the caller's d_max and must reach the accuracy of the adaptive
+    run (the stopping tests decide every node)."""
+    import torch
+    n = 4096
+    gen, T = _laplace(n, 5)
+    P = np.zeros(hss.mlp_num_params(learned.SIZES), np.float32)
+    P[-1] = 6.0                                   # output 1 of the last layer: log2 d_final = 6
+    pred = hss.Predictor(learned.SIZES, torch.from_numpy(P).cuda())
+    kw = dict(rtol=1e-6, atol=1e-12, eta=0.1, strategy="inc_fnorm", delta_d=64, d_max=2048)
+    H, st = hss.compress(gen, T, None, predictor=pred, **kw)
+    info = H.info()
+    print("restarted", info, flush=True)
+    assert st == hss.OK
+    assert info["d_predicted"] == pytest.approx(64.0)
+    assert info["d0"] == 320 and info["d_final"] > 320
+    Hb, stb = hss.compress(gen, T, None, d0=128, **kw)
+    assert stb == hss.OK
+    e, eb = H.rel_error(), Hb.rel_error()
+    assert e <= 1e-6 and e <= 2.0 * eb
