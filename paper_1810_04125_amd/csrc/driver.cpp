@@ -921,10 +921,19 @@ void Job::run_level(int lev, int32_t ncap) {
         L.test_ncap = nb_all;
       }
       TestScratch ts{qtasks_d, qform_d, chol_d, L.wg_test, L.ntest, kTestCpw, flags_d + 3, tasks_d, qwork};
-      for (int it = 0; it < nblk; ++it)
+      // A replay's first iteration may test a schedule's first block (d0
+      // wide); the later ones test the blocks sampled after it, at most the
+      // widest of those, so their launches are sized for that
+      int32_t later = 0;
+      for (const Problem& P : probs)
+        if (!P.done)
+          for (size_t i = 1; i < P.sched.size(); ++i) later = std::max(later, P.sched[i] - P.sched[i - 1]);
+      for (int it = 0; it < nblk; ++it) {
+        const int32_t nb_it = (it > 0 && later > 0) ? std::min(nb, later) : nb;
         for (int s = 0; s < nsides; ++s)
-          launch_fnorm_test(a, s, it, lv_m, std::max(1, std::min(L.qcap, lv_m)), nb, ts, stream,
+          launch_fnorm_test(a, s, it, lv_m, std::max(1, std::min(L.qcap, lv_m)), nb_it, ts, stream,
                             strategy == HSS_INC_HMT);
+      }
     }
     // A node passes only through a test of this round (a side that passed
     // earlier passed with the other, and the node compressed then) or when

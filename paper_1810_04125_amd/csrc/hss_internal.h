@@ -368,7 +368,7 @@ void launch_local_samples(const LevelArgs& a, int side, int32_t mcap_max, int32_
 // Cholesky QR (two passes) of a projected block S_hat (m x nc, nc <=
 // kCholMaxB): Q1 = S_hat R1^{-1}, Q = Q1 R2^{-1}, Rbar = R2 R1, used to
 // decide a clearly failing stopping test without the Householder QR.
-constexpr int kCholMaxB = 64;
+constexpr int kCholMaxB = 128;
 struct CholTask {
   const double* S;   // S_hat, column-major, leading dimension lds
   int64_t lds;

@@ -593,16 +593,22 @@ __global__ __launch_bounds__(NBN) void k_fn_norms(LevelArgs a, int side, QrcpTas
 // of the block is skipped.  Anything else is left to the Householder path.
 //
 // 16 waves per node: thread (row group ib, column j) updates the rows ib,
-// ib + 16, ... of column j, at most CRW of them per step, unrolled so that
-// their LDS reads are in flight together.
+// ib + CRG, ... of column j, at most CRW of them per step, unrolled so that
+// their LDS reads are in flight together.  NB is the widest block the
+// instance takes (64, or 128 for the first blocks of a replay, d0 wide);
+// the NB x NB factor lives in dynamic LDS (about 130 KB at 128).
 constexpr int CHT = 1024;               // threads of the Cholesky kernel
-constexpr int CRG = CHT / 64;           // row groups
-constexpr int CRW = kCholMaxB / CRG;    // rows per thread and step
 
-template <int PASS>
+template <int NB>
+constexpr size_t cq_lds_bytes() { return sizeof(double) * (size_t)NB * (NB + 1); }
+
+template <int PASS, int NB>
 __global__ __launch_bounds__(CHT) void k_cq_chol(LevelArgs a, int side, CholTask* __restrict__ ct,
                                                  QrcpTask* __restrict__ qt) {
-  __shared__ double A[kCholMaxB][kCholMaxB + 1];
+  constexpr int CRG = CHT / NB;   // row groups
+  constexpr int CRW = NB / CRG;   // rows per thread and step
+  extern __shared__ double cq_lds[];
+  double (*A)[NB + 1] = reinterpret_cast<double (*)[NB + 1]>(cq_lds);
   const int t = blockIdx.x;
   GemmTask* T0 = a.tasks + t;
   GemmTask* T1 = a.tasks + a.count + t;
@@ -613,7 +619,8 @@ __global__ __launch_bounds__(CHT) void k_cq_chol(LevelArgs a, int side, CholTask
   CholTask& c = ct[t];
   if (!c.active) return;
   const int nc = c.nc;
-  const int j = threadIdx.x & 63, ib = threadIdx.x >> 6;
+  if (nc > NB) return;   // cannot happen: the launch takes the widest block
+  const int j = threadIdx.x % NB, ib = threadIdx.x / NB;
   {
     const HSS_GLOBAL double* G = gview(c.G);
     double gv[CRW];
@@ -638,7 +645,7 @@ __global__ __launch_bounds__(CHT) void k_cq_chol(LevelArgs a, int side, CholTask
 #pragma unroll
       for (int u = 0; u < CRW; ++u) {
         const int i = k + 1 + ib + CRG * u;
-        const int ic = min(i, kCholMaxB - 1);
+        const int ic = min(i, NB - 1);
         const double v = A[ic][j] - A[k][ic] * akj;
         if (i <= j) A[ic][j] = v;
       }
@@ -650,7 +657,7 @@ __global__ __launch_bounds__(CHT) void k_cq_chol(LevelArgs a, int side, CholTask
     return;
   }
   // R(i, j) = A(i, j) / sqrt(A(i, i)); diag(R) kept apart for the inversion
-  __shared__ double dR[kCholMaxB];
+  __shared__ double dR[NB];
   for (int i = threadIdx.x; i < nc; i += CHT) dR[i] = sqrt(A[i][i]);
   __syncthreads();
   if (j < nc)
@@ -663,7 +670,7 @@ __global__ __launch_bounds__(CHT) void k_cq_chol(LevelArgs a, int side, CholTask
   // B(k, q) / R(k, k) (B(k, k) = 1), write it out and update the rows
   // p < k of their column, so a step reads and writes disjoint entries and
   // needs one barrier.
-  __shared__ double rinv[kCholMaxB];
+  __shared__ double rinv[NB];
   for (int i = threadIdx.x; i < nc; i += CHT) rinv[i] = 1.0 / dR[i];
   if (j < nc)
     for (int i = ib; i < j; i += CRG) A[j][i] = 0.0;
@@ -704,7 +711,7 @@ __global__ __launch_bounds__(CHT) void k_cq_chol(LevelArgs a, int side, CholTask
     }
   } else {
     // diag(R1) of the first pass, loaded by all threads at once
-    __shared__ double d1[kCholMaxB];
+    __shared__ double d1[NB];
     for (int i = threadIdx.x; i < nc; i += CHT) d1[i] = gview(c.d1)[i];
     __syncthreads();
     if (threadIdx.x != 0) return;
@@ -893,14 +900,31 @@ void launch_fnorm_test(const LevelArgs& a, int side, int32_t iter, int32_t mcap_
   prof_end(HSS_K_TEST_NORMS, s);
   // Cholesky QR of the narrow blocks: decides the clearly failing tests
   const int32_t nb = std::min(ncap, kCholMaxB);
+  static thread_local bool cq_attr = false;   // dynamic LDS above 64 KB
+  if (!cq_attr) {
+    HSS_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(k_cq_chol<1, 128>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)cq_lds_bytes<128>()));
+    HSS_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(k_cq_chol<2, 128>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)cq_lds_bytes<128>()));
+    cq_attr = true;
+  }
+  auto cq = [&](int pass) {
+    if (nb <= 64) {
+      if (pass == 1) hipLaunchKernelGGL((k_cq_chol<1, 64>), dim3(a.count), dim3(CHT), cq_lds_bytes<64>(), s, a, side, ts.ct, ts.qt);
+      else hipLaunchKernelGGL((k_cq_chol<2, 64>), dim3(a.count), dim3(CHT), cq_lds_bytes<64>(), s, a, side, ts.ct, ts.qt);
+    } else {
+      if (pass == 1) hipLaunchKernelGGL((k_cq_chol<1, 128>), dim3(a.count), dim3(CHT), cq_lds_bytes<128>(), s, a, side, ts.ct, ts.qt);
+      else hipLaunchKernelGGL((k_cq_chol<2, 128>), dim3(a.count), dim3(CHT), cq_lds_bytes<128>(), s, a, side, ts.ct, ts.qt);
+    }
+  };
   launch_gemm(a.tasks, a.count, nb, nb, s, a.kcnt, mcap_max, a.gws, kGemmSplitElems);
   prof_begin(s);
-  hipLaunchKernelGGL(k_cq_chol<1>, dim3(a.count), dim3(CHT), 0, s, a, side, ts.ct, ts.qt);
+  cq(1);
   prof_end(HSS_K_TEST_NORMS, s);
   launch_gemm(a.tasks, a.count, mcap_max, nb, s, a.kcnt);
   launch_gemm(a.tasks + a.count, a.count, nb, nb, s, a.kcnt, mcap_max, a.gws, kGemmSplitElems);
   prof_begin(s);
-  hipLaunchKernelGGL(k_cq_chol<2>, dim3(a.count), dim3(CHT), 0, s, a, side, ts.ct, ts.qt);
+  cq(2);
   prof_end(HSS_K_TEST_NORMS, s);
   launch_gemm(a.tasks, a.count, mcap_max, nb, s, a.kcnt);
   run_qrcp(ts.qt, a.count, ts.wk, nullptr, 0, ncap, mcap_max, ncap, ts.flag, ts.gt, mcap_max, s, a.kcnt, false);
