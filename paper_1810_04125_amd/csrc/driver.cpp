@@ -930,9 +930,20 @@ void Job::run_level(int lev, int32_t ncap) {
           for (size_t i = 1; i < P.sched.size(); ++i) later = std::max(later, P.sched[i] - P.sched[i - 1]);
       for (int it = 0; it < nblk; ++it) {
         const int32_t nb_it = (it > 0 && later > 0) ? std::min(nb, later) : nb;
+        // The basis a tested block is projected against holds at most the
+        // columns sampled before the block: d - b for a node tested before
+        // (its newest block, iteration 0), sched[it - 1] for one replaying
+        // its blocks; the projections are sized for that, not for the
+        // basis capacity.
+        int32_t qb = 1;
+        for (const Problem& P : probs) {
+          if (P.done) continue;
+          if (it == 0) qb = std::max(qb, P.d - P.b);
+          else if ((size_t)it <= P.sched.size()) qb = std::max(qb, P.sched[it - 1]);
+        }
+        const int32_t q_it = std::max(1, std::min(std::min(L.qcap, lv_m), qb));
         for (int s = 0; s < nsides; ++s)
-          launch_fnorm_test(a, s, it, lv_m, std::max(1, std::min(L.qcap, lv_m)), nb_it, ts, stream,
-                            strategy == HSS_INC_HMT);
+          launch_fnorm_test(a, s, it, lv_m, q_it, nb_it, ts, stream, strategy == HSS_INC_HMT);
       }
     }
     // A node passes only through a test of this round (a side that passed
