@@ -1061,15 +1061,58 @@ __global__ __launch_bounds__(NB) void k_red_gather(LevelArgs a, int side) {
     X1 = ctp(a, a.desc[nd.left].RR[side]);
     X2 = ctp(a, a.desc[nd.right].RR[side]);
   }
-  const HSS_GLOBAL int32_t* gJ = gview(J);
-  copy_elems(m * nc, [&](int idx) {
-    const int c = idx % nc, i = idx / nc;
-    const int row = gJ[i];
-    const double* src = nd.leaf ? P.R + (int64_t)(c0 + c) * P.ldr + nd.lo + row
-                                : (row < r1 ? X1 + (int64_t)row * dcap : X2 + (int64_t)(row - r1) * dcap) + c0 + c;
-    double* dst = i < r ? RR + (int64_t)i * dcap + c0 + c : Xr + (int64_t)c * nd.mcap + (i - r);
-    return CopyAt{gview(src), gview_w(dst)};
-  });
+  // Rows J of the random block, m x nc, through 32 x 32 LDS tiles: a
+  // leaf's source is R (column-major: loaded along the rows), a parent's
+  // its children's reduced blocks (row-major: loaded along the columns);
+  // rows below r go to RR (row-major: stored along the columns), the rest
+  // to Xr (column-major: stored along the rows).
+  {
+    __shared__ double tile[32][33];
+    const HSS_GLOBAL int32_t* gJ = gview(J);
+    const HSS_GLOBAL double* gR = gview(P.R);
+    const HSS_GLOBAL double* gX1 = gview(X1);
+    const HSS_GLOBAL double* gX2 = gview(X2);
+    HSS_GLOBAL double* gRR = gview_w(RR);
+    HSS_GLOBAL double* gXr = gview_w(Xr);
+    const int tr = (m + 31) / 32, tcn = (nc + 31) / 32;
+    const int lx = threadIdx.x & 31, ly = threadIdx.x >> 5;   // NB = 256: 32 x 8
+    for (int tt = blockIdx.y; tt < tr * tcn; tt += gridDim.y) {
+      const int r0 = (tt % tr) * 32, k0 = (tt / tr) * 32;
+      double v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int b = ly + 8 * u;
+        const int ti = nd.leaf ? lx : b, tc = nd.leaf ? b : lx;
+        const int i = r0 + ti, c = k0 + tc;
+        const int row = gJ[min(i, m - 1)];
+        const int64_t cc = c0 + min(c, nc - 1);
+        double x;
+        if (nd.leaf) x = gR[cc * P.ldr + nd.lo + row];
+        else x = row < r1 ? gX1[(int64_t)row * dcap + cc] : gX2[(int64_t)(row - r1) * dcap + cc];
+        v[u] = x;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int b = ly + 8 * u;
+        if (nd.leaf) tile[lx][b] = v[u];
+        else tile[b][lx] = v[u];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int b = ly + 8 * u;
+        {   // rows of RR, along the columns
+          const int i = r0 + b, c = k0 + lx;
+          if (i < r && c < nc) gRR[(int64_t)i * dcap + c0 + c] = tile[b][lx];
+        }
+        {   // rows of Xr, along the rows
+          const int i = r0 + lx, c = k0 + b;
+          if (i >= r && i < m && c < nc) gXr[(int64_t)c * nd.mcap + (i - r)] = tile[lx][b];
+        }
+      }
+      __syncthreads();
+    }
+  }
   if (st.go && blockIdx.y == 0) {
     int64_t* I = a.lpool + nd.I[side];
     const int64_t* I1 = nd.leaf ? nullptr : a.lpool + a.desc[nd.left].I[side];
