@@ -58,3 +58,29 @@ def test_committed_training_set_is_consistent():
     assert np.all(M[root] == [0, 1]) and np.all(M[~root] == [1, 0])
     assert np.allclose(2.0 ** T[root, 1], d_final)
     assert np.all(d_final % 64 == 0)
+
+
+def _fake_set(nprob, d0, seed):
+    """A training set of `nprob` problems with two rows each (root first)."""
+    rng = np.random.default_rng(seed)
+    X = rng.random((2 * nprob, 8)).astype(np.float32)
+    X[0::2, 5] = 0.0   # root rows: level 0
+    X[1::2, 5] = 0.125
+    T = rng.random((2 * nprob, 2)).astype(np.float32)
+    M = np.tile(np.array([[0, 1], [1, 0]], np.float32), (nprob, 1))
+    return {"X": X, "T": T, "M": M, "p_n": np.arange(nprob) + 1000 * seed, "p_eta": np.array([0.05]),
+            "p_d0": np.array([d0])}
+
+
+def test_merge_interleaves_whole_problems_and_keeps_the_start():
+    a, b = _fake_set(6, 128, 1), _fake_set(2, 128, 2)
+    m = learned.merge(a, b, every=3)
+    assert list(m["p_n"]) == [1000, 1001, 1002, 2000, 1003, 1004, 1005, 2001]
+    assert len(m["X"]) == 16 and np.all(m["X"][0::2, 5] == 0.0)
+    assert np.array_equal(m["X"][6:8], b["X"][0:2])   # b's first problem after a's third
+    assert int(m["p_d0"][0]) == 128
+
+
+def test_merge_refuses_sets_labelled_from_different_starts():
+    with pytest.raises(ValueError):
+        learned.merge(_fake_set(4, 128, 1), _fake_set(2, 64, 2), every=2)
